@@ -1,0 +1,201 @@
+"""The filter solve (oracle, FP64, test-only).
+
+Eq. 1 with the discrete operators of Sect. 2.1.1 (Eq. 4 / Eq. 5 forms):
+``S = M + gamma * k^(-2n) * K_n``, ``S phi_bar = M phi``, with ``k = 1/l``
+and ``gamma = 1/2`` (Sect. 2.1). ``S`` is symmetric positive definite
+(Sect. 2.1.1), so ``phi_bar = S^-1 M phi`` is unique; the oracle computes it
+
+* by dense Cholesky for small systems, and
+* by Jacobi-preconditioned conjugate gradients started from ``x0 = phi``
+  (the residual form of Sect. 2.2.2: the product ``S phi`` is subtracted
+  from the right-hand side and CG solves for the correction), to a tight
+  tolerance, followed by iterative refinement whose residual is formed in
+  extended (x87 80-bit) precision.
+"""
+from __future__ import annotations
+
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+
+def system_matrix(op, k: float, gamma: float = 0.5):
+    """``S = M + c K_n`` with ``c = gamma / k^(2n)`` (Eq. 1, Eq. 4/5)."""
+    c = gamma / (k ** (2 * op.n))
+    return (sp.diags(op.A) + c * op.Kn).tocsr()
+
+
+def to_dofs(op, field: np.ndarray) -> np.ndarray:
+    """Caller's numbering (vertices or cells) -> dof vector."""
+    if hasattr(op, "verts"):
+        return np.asarray(field, dtype=np.float64)[op.verts]
+    f = np.asarray(field, dtype=np.float64).reshape(-1, 2)
+    return f[op.cells].reshape(-1)
+
+
+def from_dofs(op, x: np.ndarray) -> np.ndarray:
+    """dof vector -> caller's numbering, zeros at dry vertices / cells."""
+    if hasattr(op, "verts"):
+        out = np.zeros(op.n_vertices)
+        out[op.verts] = x
+        return out
+    out = np.zeros((op.n_cells_total, 2))
+    out[op.cells] = x.reshape(-1, 2)
+    return out.reshape(-1)
+
+
+def filter_dense(S, b) -> np.ndarray:
+    """Dense Cholesky solve of the SPD system (small meshes only)."""
+    Sd = S.toarray() if sp.issparse(S) else np.asarray(S)
+    cf = sla.cho_factor(Sd, lower=True)
+    return sla.cho_solve(cf, b)
+
+
+def pcg_jacobi(S, b, x0, rtol: float = 1e-14, max_iter: int = 100000, replace_every: int = 50):
+    """Jacobi-preconditioned CG on ``S x = b`` from ``x0``, FP64.
+
+    Stops when the true residual satisfies ``||b - S x|| <= rtol ||b||``
+    (the recursive residual is replaced by the true one every
+    ``replace_every`` iterations) or when it stops decreasing.
+    Returns ``(x, iterations, true_relative_residual)``.
+    """
+    S = S.tocsr()
+    d = S.diagonal()
+    x = np.array(x0, dtype=np.float64, copy=True)
+    r = b - S @ x
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return np.zeros_like(x), 0, 0.0
+    z = r / d
+    p = z.copy()
+    rho = float(r @ z)
+    best = np.linalg.norm(r)
+    stall = 0
+    it = 0
+    while it < max_iter:
+        if np.linalg.norm(r) <= rtol * bn:
+            break
+        q = S @ p
+        alpha = rho / float(p @ q)
+        x += alpha * p
+        r -= alpha * q
+        it += 1
+        if it % replace_every == 0:
+            r = b - S @ x
+            rn = np.linalg.norm(r)
+            if rn < 0.5 * best:
+                best = rn
+                stall = 0
+            else:
+                stall += 1
+                if stall >= 3:
+                    break
+        z = r / d
+        rho_new = float(r @ z)
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    res = np.linalg.norm(b - S @ x) / bn
+    return x, it, res
+
+
+def refine_solve(S, b, x0, steps: int = 3, rtol: float = 1e-14):
+    """CG from ``x0`` followed by ``steps`` rounds of iterative refinement
+    with an extended-precision residual. Returns ``(x, total_iterations)``."""
+    x, it, _ = pcg_jacobi(S, b, x0, rtol=rtol)
+    xl = x.astype(np.longdouble)
+    bn = float(np.linalg.norm(b))
+    for _ in range(steps):
+        r = _residual_ld(S, b, xl)
+        r64 = r.astype(np.float64)
+        rn = float(np.linalg.norm(r64))
+        if rn <= 1e-17 * bn:
+            break
+        d, it2, _ = pcg_jacobi(S, r64, np.zeros_like(r64), rtol=rtol)
+        it += it2
+        xl = xl + d.astype(np.longdouble)
+    return xl.astype(np.float64), it
+
+
+def _residual_ld(S, b, xl):
+    """``b - S x`` with products and sums in x87 extended precision
+    (``xl`` is already extended)."""
+    ld = np.longdouble
+    prod = S.data.astype(ld) * xl[S.indices]
+    nnz_row = np.diff(S.indptr)
+    sx = np.zeros(S.shape[0], dtype=ld)
+    nz = nnz_row > 0
+    sx[nz] = np.add.reduceat(prod, S.indptr[:-1][nz])
+    return b.astype(ld) - sx
+
+
+def _solve(op, phi_dofs, k, gamma, method):
+    S = system_matrix(op, k, gamma)
+    b = op.A * phi_dofs
+    n = b.size
+    if method == "auto":
+        method = "dense" if n <= 4096 else "cg"
+    if method == "dense":
+        return filter_dense(S, b), {"method": "dense", "iterations": 0}
+    x, it = refine_solve(S, b, phi_dofs)
+    return x, {"method": "cg", "iterations": it}
+
+
+def filter_scalar(op, field, ks, gamma: float = 0.5, method: str = "auto", return_info: bool = False):
+    """Filter a vertex field at each wavenumber in ``ks``.
+
+    ``field``: (V,) in vertex numbering. Returns (len(ks), V) with zeros at
+    vertices that are not dofs (dry or orphaned).
+    """
+    phi = to_dofs(op, field)
+    out = np.zeros((len(ks), op.n_vertices))
+    infos = []
+    for j, k in enumerate(ks):
+        x, info = _solve(op, phi, float(k), gamma, method)
+        out[j] = from_dofs(op, x)
+        infos.append(info)
+    return (out, infos) if return_info else out
+
+
+def filter_vector(op, field, ks, gamma: float = 0.5, method: str = "auto", return_info: bool = False):
+    """Filter a cell vector field ``(F, 2)`` (east, north) at each ``k``.
+    Returns (len(ks), F, 2) with zeros on inactive cells."""
+    phi = to_dofs(op, field)
+    out = np.zeros((len(ks), op.n_cells_total, 2))
+    infos = []
+    for j, k in enumerate(ks):
+        x, info = _solve(op, phi, float(k), gamma, method)
+        out[j] = from_dofs(op, x).reshape(-1, 2)
+        infos.append(info)
+    return (out, infos) if return_info else out
+
+
+def residual_bound(S, A, b, x) -> float:
+    """Certified bound on the relative error of ``x``: since ``K_n`` is
+    positive semidefinite, ``S >= M`` and ``||S^-1|| <= 1/min(A)``, so
+    ``||x - x*|| / ||x|| <= ||b - S x|| / (min(A) ||x||)``; the residual is
+    formed in extended precision so that its own rounding does not hide
+    the bound."""
+    r = _residual_ld(S.tocsr(), np.asarray(b, dtype=np.float64), np.asarray(x).astype(np.longdouble))
+    return float(np.linalg.norm(r.astype(np.float64)) / (np.min(A) * np.linalg.norm(x)))
+
+
+def relative_l2(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+__all__ = [
+    "system_matrix",
+    "to_dofs",
+    "from_dofs",
+    "filter_dense",
+    "pcg_jacobi",
+    "refine_solve",
+    "filter_scalar",
+    "filter_vector",
+    "residual_bound",
+    "relative_l2",
+]

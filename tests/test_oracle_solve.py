@@ -1,0 +1,140 @@
+"""Pins of the oracle's filter solve (CPU only): the closed-form Fourier
+multiplier on a uniform periodic mesh, filter invariants, and the CG path
+against dense Cholesky / LAPACK."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle.solve import relative_l2, residual_bound
+
+
+def _fourier_filter(phi_grid, k, gamma, n):
+    """Closed form on the unjittered periodic split-square lattice (h = 1):
+    K is the 5-point Laplacian with symbol lam(q) = 4 sin^2(qx/2) +
+    4 sin^2(qy/2), M = I, and K_n has symbol lam^n, so each Fourier mode
+    is multiplied by 1 / (1 + gamma (lam / k^2)^n)."""
+    ny, nx = phi_grid.shape
+    qx = 2 * np.pi * np.fft.fftfreq(nx)
+    qy = 2 * np.pi * np.fft.fftfreq(ny)
+    QX, QY = np.meshgrid(qx, qy)
+    lam = 4 * np.sin(QX / 2) ** 2 + 4 * np.sin(QY / 2) ** 2
+    mult = 1.0 / (1.0 + gamma * (lam / k ** 2) ** n)
+    return np.real(np.fft.ifft2(np.fft.fft2(phi_grid) * mult))
+
+
+@pytest.mark.parametrize("n", [1, 2])
+@pytest.mark.parametrize("gamma", [0.5, 1.0])
+def test_closed_form_fourier_multiplier(n, gamma):
+    N = 32
+    m = W.split_square(N, jitter=0.0)
+    op = O.scalar_operator(m, n)
+    phi = W.planar_k3_field(m, 1000)
+    ks = W.log_scales(1.0, 5)
+    for method in ("dense", "cg"):
+        out = O.filter_scalar(op, phi, ks, gamma=gamma, method=method)
+        for j, k in enumerate(ks):
+            ref = _fourier_filter(phi.reshape(N, N), k, gamma, n).ravel()
+            assert relative_l2(out[j], ref) < 1e-12, (method, j)
+
+
+def test_cg_matches_dense_and_lapack_c1():
+    """Plain FP64 configuration: 64x64 periodic split square, jitter 0.2,
+    n = 1, eight scales from 32 to 2 cells: CG (from x0 = phi) equals the
+    dense Cholesky solve and LAPACK's general solve."""
+    m = W.split_square(64, jitter=0.2)
+    op = O.scalar_operator(m, 1)
+    phi = W.planar_k3_field(m, 1000)
+    ks = W.log_scales(1.0, 8)
+    dense = O.filter_scalar(op, phi, ks, method="dense")
+    cg = O.filter_scalar(op, phi, ks, method="cg")
+    for j, k in enumerate(ks):
+        assert relative_l2(cg[j], dense[j]) < 1e-12
+    S = O.system_matrix(op, ks[0])
+    lap = np.linalg.solve(S.toarray(), op.A * phi)
+    assert relative_l2(dense[0], lap) < 1e-12
+
+
+def test_residual_form_start_is_equivalent():
+    """Sect. 2.2.2: subtracting S phi from the right-hand side and solving
+    for the correction is the same as starting CG from x0 = phi."""
+    s = W.icosphere(4, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    op = O.scalar_operator(s, 1)
+    phi = O.to_dofs(op, W.sphere_k3_field(s, 1000, n_waves=256))
+    k = W.log_scales(s.h, 3)[0]
+    S = O.system_matrix(op, k)
+    b = op.A * phi
+    x1, _, _ = O.pcg_jacobi(S, b, phi, rtol=1e-15)
+    d, _, _ = O.pcg_jacobi(S, b - S @ phi, np.zeros_like(phi), rtol=1e-15)
+    x0, _, _ = O.pcg_jacobi(S, b, np.zeros_like(phi), rtol=1e-15)
+    assert relative_l2(x1, phi + d) < 1e-13
+    assert relative_l2(x1, x0) < 1e-13
+    assert residual_bound(S, op.A, b, x1) < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_filter_invariants_masked_sphere(n):
+    s = W.icosphere(4, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    op = O.scalar_operator(s, n)
+    phi = W.sphere_k3_field(s, 1001, n_waves=256)
+    ks = W.log_scales(s.h, 4)
+    out = O.filter_scalar(op, phi, ks)
+    pd = O.to_dofs(op, phi)
+    # constant in -> constant out (K 1 = 0)
+    c = np.where(s.wet.astype(bool), 3.7, 0.0)
+    cst = O.filter_scalar(op, c, ks[:2])
+    for j in range(2):
+        # K_n 1 vanishes up to rounding; S^-1 <= 1/min(A) bounds what that
+        # rounding can do to the constant: ||u - 3.7|| <= 3.7 c ||K_n 1|| / min A
+        cfac = 0.5 / ks[j] ** (2 * n)
+        bound = 3.7 * cfac * np.linalg.norm(op.Kn @ np.ones(op.A.size)) / op.A.min()
+        err = np.linalg.norm(O.to_dofs(op, cst[j]) - 3.7)
+        assert err <= max(1e-13, 10 * bound), (err, bound)
+        assert np.max(np.abs(O.to_dofs(op, cst[j]) - 3.7)) <= 1e-11 * 3.7
+    prev = None
+    for j in range(len(ks)):
+        u = O.to_dofs(op, out[j])
+        # area-weighted mean conserved: 1^T K = 0
+        assert abs(op.A @ u - op.A @ pd) < 1e-12 * (op.A @ np.abs(pd))
+        # M-norm contraction, and monotone in k (eigenvalues 1/(1+c lam))
+        eu = op.A @ (u * u)
+        assert eu <= op.A @ (pd * pd) * (1 + 1e-14)
+        if prev is not None:
+            assert eu >= prev * (1 - 1e-14)
+        prev = eu
+        # dry vertices are returned as zero
+        assert np.all(out[j][s.wet == 0] == 0.0)
+
+
+def test_filter_limits():
+    """k -> infinity: the filter is the identity; k -> 0: it returns the
+    area-weighted mean (on a connected mesh)."""
+    m = W.split_square(32, jitter=0.2)
+    op = O.scalar_operator(m, 1)
+    phi = W.planar_k3_field(m, 1002)
+    hi = O.filter_scalar(op, phi, [1e6])[0]
+    assert relative_l2(hi, phi) < 1e-11
+    lo = O.filter_scalar(op, phi, [1e-5])[0]
+    mean = (op.A @ phi) / op.A.sum()
+    assert np.max(np.abs(lo - mean)) < 1e-6 * np.max(np.abs(phi))
+
+
+def test_cg_certificate_larger_mesh():
+    """On a mesh too large for Cholesky the CG + extended-precision
+    refinement result carries a certified error bound below 1e-11 (the
+    bound itself cannot go below about cond(S) * eps, since storing x in
+    FP64 already leaves a residual of ||S|| eps ||x||)."""
+    s = W.icosphere(5, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    op = O.scalar_operator(s, 2)
+    phi = W.sphere_k3_field(s, 1003, n_waves=256)
+    k = W.log_scales(s.h, 5)[0]
+    S = O.system_matrix(op, k)
+    pd = O.to_dofs(op, phi)
+    x, it = O.refine_solve(S, op.A * pd, pd)
+    assert residual_bound(S, op.A, op.A * pd, x) < 1e-11
+    assert it > 10
