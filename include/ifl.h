@@ -1,0 +1,276 @@
+/*
+ * ifl.h -- C ABI of the implicit-filter library (MI355X / gfx950).
+ *
+ * The library solves the implicit filter of Nowak, Danilov, Mueller & Liu,
+ * "Implementation of implicit filter for spatial spectra extraction":
+ *
+ *     (1 + gamma (-l^2 Lap)^n) phi_bar = phi            (Eq. 1, Eq. 2)
+ *
+ * discretised on an unstructured triangle mesh as the SPD system
+ *
+ *     S phi_bar = M phi,   S = M + (gamma / k^(2n)) K_n,   k = 1/l,
+ *
+ * with M the lumped median-dual (vertex) or triangle (cell) areas and K_n
+ * the order-n Laplacian (Sect. 2.1.1 and Eq. 4/5 for vertex scalars,
+ * Eq. 7 for cell vectors). The work is split into a mesh-only prepare
+ * phase, run once, and a per-scale solve (Sect. 2.2): Jacobi-preconditioned
+ * conjugate gradients started from x0 = phi, i.e. on the residual form
+ * where S phi is subtracted from the right-hand side (Sect. 2.2.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every call returns IFL_OK (0) or a negative ifl_status. On an error
+ *    other than IFL_ENOTCONV the outputs are left untouched; the message of
+ *    the last error of the calling thread is returned by ifl_last_error().
+ *  - Field pointers ("fields", "field", "out") may be host memory or device
+ *    memory of the handle's device; the library tells them apart with
+ *    hipPointerGetAttributes. Everything else (mesh arrays, k lists, stats,
+ *    energies) is host memory.
+ *  - The caller owns all buffers it passes. Except for ifl_submit, no call
+ *    keeps a caller pointer after it returns.
+ *  - Calls on one handle are synchronous with respect to the host and are
+ *    serialised by a per-handle lock; different handles may be used from
+ *    different threads.
+ *  - Wavenumbers k are in radians per unit of the mesh coordinates
+ *    (k = 2 pi / wavelength), must be finite and > 0.
+ */
+#ifndef IFL_H
+#define IFL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef int32_t ifl_status;
+#define IFL_OK 0
+#define IFL_EINVAL (-1)       /* null / NaN / Inf input, k <= 0, bad index or size */
+#define IFL_EDEGENERATE (-2)  /* zero-area triangle, or no active triangle at all */
+#define IFL_ENOMEM (-3)       /* host or device allocation failed */
+#define IFL_ENOTCONV (-4)     /* max_iter reached or CG breakdown; out holds the last iterate */
+#define IFL_EDEVICE (-5)      /* HIP runtime error, or no usable gfx950 device */
+#define IFL_EUNSUPPORTED (-6) /* placement / order / option not implemented */
+#define IFL_EIO (-7)          /* save / load failure or bad file */
+
+/* ------------------------------------------------------------------ mesh */
+#define IFL_GEOM_PLANAR 0   /* coords V x 2 (x, y) */
+#define IFL_GEOM_PERIODIC 1 /* coords V x 2, doubly periodic with period[0], period[1] */
+#define IFL_GEOM_SPHERE 2   /* coords V x 3 (x, y, z) on a sphere; flat facets */
+
+typedef struct ifl_mesh {
+  int64_t n_vertices;       /* V >= 3 */
+  int64_t n_triangles;      /* F >= 1 */
+  const double* coords;     /* host, V x 2 or V x 3, row-major */
+  const int32_t* triangles; /* host, F x 3 vertex ids, 0-based; any orientation */
+  int32_t geometry;         /* IFL_GEOM_* */
+  int32_t reserved0;
+  double period[2];         /* IFL_GEOM_PERIODIC only */
+  const uint8_t* wet;       /* host, V entries, 1 = wet (ocean), 0 = dry; NULL = all wet */
+} ifl_mesh;
+
+/* Data placement (Sect. 2.1, Fig. 1). */
+#define IFL_VERTEX_SCALAR 0       /* scalars on vertices, median-dual CVs, P1 FE (Sect. 2.1.1) */
+#define IFL_CELL_VECTOR 1         /* (east, north) vectors on triangles, Eq. 7 (Sect. 2.1.2) */
+#define IFL_VORONOI_SCALAR 2      /* Eq. 3-5: reserved, IFL_EUNSUPPORTED */
+#define IFL_CIRCUMCENTER_SCALAR 3 /* Eq. 6: reserved, IFL_EUNSUPPORTED */
+#define IFL_VERTEX_VECTOR 4       /* vertex FE vector Laplacian: reserved, IFL_EUNSUPPORTED */
+
+/* Arithmetic of the solve. */
+#define IFL_FP64 0  /* all vectors, matrix values, SpMV and reductions in FP64 */
+#define IFL_MIXED 1 /* FP32 matrix values / vectors / SpMV, FP64 reductions, FP64 residual
+                       replacement ("reliable updates") and FP64 solution accumulation */
+
+typedef struct ifl_options {
+  double gamma;      /* filter parameter (Sect. 2.1: 1/2); default 0.5 */
+  double rtol;       /* stop when ||M phi - S x||_2 <= rtol * ||M phi||_2; default 1e-12 */
+  int32_t max_iter;  /* CG iteration cap per solve; default 20000 */
+  int32_t precision; /* IFL_FP64 (default) or IFL_MIXED */
+  double cell_A;     /* stencil constant A of Eq. 7; default sqrt(3) */
+  int32_t device;    /* HIP device ordinal; default 0. -1 = host-only handle: prepare,
+                        export and save work, solves return IFL_EDEVICE */
+  int32_t batch;     /* columns per multi-RHS tile for ifl_filter: 0 = auto (default),
+                        1 = one solve at a time, 2..64 = fixed tile */
+  void* stream;      /* hipStream_t to run on; NULL = the handle's own stream */
+  int32_t reorder;   /* 1 = reverse Cuthill-McKee locality ordering (default), 0 = none */
+  int32_t profile;   /* 1 = time the SpMV launches with HIP events (ifl_profile_read) */
+} ifl_options;
+
+/* Per-solve statistics (one per field x scale). */
+typedef struct ifl_solve_stats {
+  int32_t iterations;   /* CG iterations */
+  int32_t refinements;  /* FP64 residual replacements (IFL_MIXED) */
+  int32_t status;       /* IFL_OK or IFL_ENOTCONV */
+  int32_t reserved;
+  double rel_residual;  /* final ||M phi - S x|| / ||M phi||, FP64 on the GPU */
+  double seconds;       /* wall time of the solve (of its tile when batched) */
+} ifl_solve_stats;
+
+typedef struct ifl_handle ifl_handle;
+
+/* Fill *opt with the defaults listed above. */
+void ifl_default_options(ifl_options* opt);
+
+/*
+ * Mesh-only preparation (Sect. 2.2.1), run once per mesh and order.
+ *
+ * Builds, on the host, the active triangles (all three vertices wet), the
+ * dofs (vertices of an active triangle for IFL_VERTEX_SCALAR; active
+ * triangles for IFL_CELL_VECTOR), flat-facet geometry, the lumped mass
+ * and the stiffness K (P1 Galerkin form of Sect. 2.1.1, or Eq. 7 with the
+ * change of local unit vectors between neighbouring cells), the order-n
+ * operator K_n = K (M^-1 K)^(n-1), a locality ordering of the dofs, and
+ * uploads the matrix to device memory owned by the handle.
+ *
+ * mesh      : host arrays, read only during the call.
+ * placement : IFL_VERTEX_SCALAR or IFL_CELL_VECTOR.
+ * n         : filter order, 1 or 2 (others: IFL_EUNSUPPORTED).
+ * opt       : NULL for defaults; copied into the handle.
+ * out       : receives the handle; release with ifl_destroy.
+ * Errors    : IFL_EINVAL (bad sizes, ids out of range, non-finite coords),
+ *             IFL_EDEGENERATE (zero-area active triangle, no active
+ *             triangle), IFL_EUNSUPPORTED, IFL_ENOMEM, IFL_EDEVICE.
+ */
+ifl_status ifl_prepare(const ifl_mesh* mesh, int32_t placement, int32_t n,
+                       const ifl_options* opt, ifl_handle** out);
+
+/* Release the handle and all its host and device memory. NULL is a no-op. */
+void ifl_destroy(ifl_handle* h);
+
+/* Number of unknowns of the solve (dofs, times 2 for vectors). */
+int64_t ifl_num_dofs(const ifl_handle* h);
+
+/* Length of one field in the caller's numbering: V for vertex scalars,
+ * 2F for cell vectors (interleaved east, north per triangle). */
+int64_t ifl_field_length(const ifl_handle* h);
+
+/* Replace the solver options of a prepared handle (gamma, rtol, max_iter,
+ * precision, batch, stream, profile). Mesh-dependent fields (cell_A,
+ * device, reorder) must equal the prepare-time values, else IFL_EINVAL. */
+ifl_status ifl_set_options(ifl_handle* h, const ifl_options* opt);
+
+/*
+ * Filter n_fields fields at n_scales wavenumbers (Eq. 1 discretised as
+ * above; solve of Sect. 2.2.2).
+ *
+ * fields : n_fields x L doubles, L = ifl_field_length(h), row-major; entries
+ *          at dry vertices / inactive cells are ignored. Host or device.
+ * k      : host, n_scales wavenumbers (> 0, finite).
+ * out    : n_fields x n_scales x L doubles; out[f][s] is field f filtered at
+ *          k[s]; dry entries are written as 0. Host or device.
+ * stats  : host, n_fields x n_scales entries, or NULL.
+ * Errors : IFL_EINVAL (NaN/Inf in a wet entry of a field, bad k, bad sizes),
+ *          IFL_ENOTCONV (some column hit max_iter or broke down: out holds
+ *          the last iterates and stats say which), IFL_EDEVICE, IFL_ENOMEM.
+ * n_fields == 0 or n_scales == 0 is a valid no-op.
+ */
+ifl_status ifl_filter(ifl_handle* h, int32_t n_fields, const double* fields,
+                      int32_t n_scales, const double* k, double* out,
+                      ifl_solve_stats* stats);
+
+/*
+ * Coarse-graining spectrum of one field (Sect. 2.1, Sect. 4): the filtered
+ * energy E(k_j) = (1/2) sum_i M_i phi_bar_i(k_j)^2 / sum_i M_i at each k_j
+ * (for vectors phi_bar^2 = u_bar^2 + v_bar^2), and its finite-difference
+ * density (E_{j+1} - E_j) / (k_{j+1} - k_j) at k_mid = sqrt(k_j k_{j+1}).
+ *
+ * field   : L doubles, host or device.
+ * k       : host, n_scales > 0 wavenumbers, strictly ascending.
+ * energy  : host, n_scales doubles.
+ * density : host, n_scales - 1 doubles, or NULL.
+ * k_mid   : host, n_scales - 1 doubles, or NULL.
+ * Errors  : as ifl_filter; IFL_EINVAL if k is not strictly ascending.
+ */
+ifl_status ifl_spectrum(ifl_handle* h, const double* field, int32_t n_scales,
+                        const double* k, double* energy, double* density,
+                        double* k_mid);
+
+/*
+ * y = S(k) x in the caller's numbering (the operator of the solve, for
+ * checks and for callers that want the residual themselves).
+ * x, y : L doubles each, host or device; dry entries of y are 0.
+ */
+ifl_status ifl_apply(ifl_handle* h, double k, const double* x, double* y);
+
+/*
+ * Export the prepared operator to host memory (checks, debugging).
+ * Rows are the dofs in the library's internal order. With nnz = the value
+ * returned by ifl_operator_nnz:
+ *   row_ptr[N+1], col[nnz] (internal dof ids), val[nnz] : K_n in CSR, FP64,
+ *   including its diagonal;
+ *   mass[N] : lumped mass;
+ *   entity[N] : caller-numbering index of each dof (vertex id, or
+ *               2*triangle + component for cell vectors).
+ * Any pointer may be NULL to skip that array.
+ */
+int64_t ifl_operator_nnz(const ifl_handle* h);
+ifl_status ifl_export_operator(const ifl_handle* h, int64_t* row_ptr, int32_t* col,
+                               double* val, double* mass, int64_t* entity);
+
+/* Save / load a prepared handle (Sect. 2.2.1: the precomputed arrays can be
+ * saved to disk and reused). Versioned little-endian binary. ifl_load
+ * uploads to opt->device (NULL opt: defaults). Errors: IFL_EIO. */
+ifl_status ifl_save(const ifl_handle* h, const char* path);
+ifl_status ifl_load(const char* path, const ifl_options* opt, ifl_handle** out);
+
+/* Thread-local message of the last error ("" if none). */
+const char* ifl_last_error(void);
+
+/*
+ * SpMV launch timing, for roofline reports (requires opt.profile = 1).
+ * Returns the number of timed SpMV launches since the last reset, their
+ * summed duration in milliseconds (HIP events on the launch stream), and
+ * the algorithmic bytes one launch moves (matrix stream + vector reads and
+ * writes, without cache effects). reset != 0 clears the counters.
+ */
+ifl_status ifl_profile_read(ifl_handle* h, int64_t* launches, double* total_ms,
+                            double* bytes_per_launch, int32_t reset);
+
+/* ----------------------------------------------------------- serving API */
+typedef struct ifl_server ifl_server;
+typedef struct ifl_ticket ifl_ticket;
+
+/*
+ * Continuous-batching server over prepared handles (one device).
+ * hbm_budget_bytes : device memory the server may use for in-flight work
+ *                    (vectors of admitted solves); requests wait until
+ *                    their footprint fits.
+ * slots            : maximum columns in flight per mesh (tile width), 1..64.
+ */
+ifl_status ifl_server_create(size_t hbm_budget_bytes, int32_t slots, ifl_server** out);
+
+/* Register a handle (borrowed: it must outlive the server). Handles of the
+ * same mesh prepared for n = 1 and n = 2 are separate entries. */
+ifl_status ifl_server_add(ifl_server* s, ifl_handle* h, int32_t* mesh_id);
+
+/*
+ * Queue one request: field (host, L doubles) filtered at n_scales
+ * wavenumbers into out (host, n_scales x L). Returns at once; the field is
+ * copied, out must stay valid until ifl_wait returns for the ticket.
+ * Solves are admitted into the mesh's running tile as slots and memory
+ * free up; each result is the same as a standalone ifl_filter within the
+ * handle's tolerance.
+ */
+ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field,
+                      int32_t n_scales, const double* k, double* out, ifl_ticket** ticket);
+
+/* Block until the request is done; fills stats[n_scales] (may be NULL) and
+ * frees the ticket. Returns the request's status. */
+ifl_status ifl_wait(ifl_ticket* t, ifl_solve_stats* stats);
+
+/* 1 if done, 0 if not yet (non-blocking). */
+int32_t ifl_poll(const ifl_ticket* t);
+
+/* Latency of a finished request (seconds from submit to completion). */
+double ifl_ticket_latency(const ifl_ticket* t);
+
+/* Drain outstanding work and destroy the server. */
+void ifl_server_destroy(ifl_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IFL_H */

@@ -1,0 +1,874 @@
+// Device side of the implicit filter on gfx950: matrix upload, the
+// Jacobi-preconditioned CG kernels and the per-column solve driver.
+//
+// The solve of Sect. 2.2.2 is CG on S x = M phi from x0 = phi (the residual
+// form: r0 = M phi - S phi = -c K_n phi), with S = diag(M) + c K_n and the
+// Jacobi preconditioner diag(S)^-1. Everything is bandwidth bound, so the
+// kernels are organised around HBM traffic:
+//
+//  * K_n's off-diagonal entries are streamed in sliced-ELL form (slices of
+//    64 rows = one wavefront, column-major inside a slice) so that column
+//    indices and values are read with fully coalesced 256 / 512 B wavefront
+//    loads; the diagonal of S = M + c diag(K_n) is formed once per solve and
+//    doubles as the Jacobi preconditioner.
+//  * One CG iteration is two kernels: (1) p = z + beta p fused into the SpMV
+//    q = S p together with the block partials of (p, q); (2) x += alpha p,
+//    r -= alpha q, z = r / diag(S) with the partials of (r, z) and (r, r).
+//  * Reductions are deterministic two-level sums: every block writes one
+//    partial per quantity; the next kernel's blocks each finish the sum in
+//    the same fixed order, so all blocks agree bitwise on alpha / beta and
+//    on the stopping test without atomics or cross-XCD fences.
+//  * Logical blocks own contiguous row ranges and are mapped so that the
+//    blocks of one XCD (hardware dispatches workgroups round-robin over the
+//    8 XCDs) hold neighbouring ranges: neighbouring rows' gathers then hit
+//    the same XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace ifl {
+
+#define IFL_HIP(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(IFL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+constexpr int kWave = 64;
+constexpr int kBlock = 512;                 // 8 wavefronts
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxBlocks = 1024;            // logical blocks (partials per quantity)
+constexpr int kXcd = 8;
+
+// Per-column device scalars. Written by block 0 of a kernel, read by the
+// following kernels (kernel boundaries order them).
+struct Scalars {
+  double tol2;      // rtol^2 ||M phi||^2
+  double rr_ref;    // mixed: ||r||^2 at the last FP64 residual replacement
+  double c;         // gamma / k^(2n)
+  double rr_last;   // ||r||^2 seen by the last stopping test
+  double res2;      // final true ||b - S x||^2 (FP64)
+  double bb;        // ||b||^2
+  double energy2;   // sum M x^2
+  double pad0;
+  int32_t iters;    // CG iterations performed
+  int32_t done;     // 0 running, 1 converged, 2 breakdown
+  int32_t rr_true;  // mixed: the current residual norm is an FP64 true residual
+  int32_t updates;  // mixed: residual replacements
+  int32_t update_now;
+  int32_t pad1[3];
+};
+
+struct DevMatrix {
+  int64_t n = 0, n_slices = 0, n_pad = 0;
+  int64_t nnz_stored = 0;   // padded sliced-ELL entries
+  int64_t offdiag = 0;      // true off-diagonal entries
+  int64_t* sptr = nullptr;
+  int32_t* col = nullptr;
+  double* val64 = nullptr;
+  float* val32 = nullptr;
+  double* kdiag64 = nullptr;
+  float* kdiag32 = nullptr;
+  double* mass64 = nullptr;
+  int64_t* entity = nullptr;
+  double mass_sum = 0.0;
+};
+
+struct ColWork {
+  // FP64 path vectors
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *d = nullptr;
+  // mixed path vectors
+  float *r32 = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *d32 = nullptr,
+        *xacc = nullptr;
+  double* phi = nullptr;   // field in internal order
+  double* part = nullptr;  // partials, see offsets below
+  Scalars* sc = nullptr;
+  Scalars* sc_host = nullptr;  // pinned, 2 slots
+  int* flag = nullptr;         // device: non-finite input detected
+  double* stage_in = nullptr;  // field staging (caller numbering)
+  double* stage_out = nullptr;
+  int64_t stage_len = 0;
+};
+
+struct DeviceState {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  DevMatrix m;
+  ColWork w;
+  int G = 1;          // logical blocks
+  int spb = 1;        // slices per logical block
+  // profiling
+  std::vector<hipEvent_t> ev;
+  int64_t prof_launches = 0;
+  double prof_ms = 0.0;
+};
+
+// partial-array offsets (in units of G)
+enum { P_PQ = 0, P_RZ0 = 1, P_RZ1 = 2, P_RR0 = 3, P_RR1 = 4, P_BB = 5, P_RES = 6, P_EN = 7, P_COUNT = 8 };
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ int logical_block(int G) {
+  const int b = blockIdx.x;
+  if (G % kXcd) return b;
+  return (b % kXcd) * (G / kXcd) + b / kXcd;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Block-wide sum of NV values, fixed order; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[kWavesPerBlock]) {
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = wave_sum(v[i]);
+    if (lane == 0) lds[i][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < kWavesPerBlock; ++w) s += lds[i][w];
+      v[i] = s;
+    }
+  }
+}
+
+// Sum of a partial array a[0..G) by the whole block, fixed order; every
+// thread returns the same value.
+__device__ __forceinline__ double reduce_partials(const double* a, int G, double* lds_w, double* lds_out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < G; i += kBlock) s += a[i];
+  s = wave_sum(s);
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  if (lane == 0) lds_w[wid] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kWavesPerBlock; ++w) t += lds_w[w];
+    *lds_out = t;
+  }
+  __syncthreads();
+  return *lds_out;
+}
+
+template <typename T>
+struct Vecs {
+  T* r;
+  T* z;
+  T* p0;
+  T* p1;
+  T* q;
+  T* d;
+};
+
+struct Mat {
+  int64_t n, n_slices;
+  const int64_t* sptr;
+  const int32_t* col;
+  const double* val64;
+  const float* val32;
+  const double* kdiag64;
+  const float* kdiag32;
+  const double* mass64;
+};
+
+template <typename T>
+__device__ __forceinline__ const T* mval(const Mat& m);
+template <>
+__device__ __forceinline__ const double* mval<double>(const Mat& m) { return m.val64; }
+template <>
+__device__ __forceinline__ const float* mval<float>(const Mat& m) { return m.val32; }
+
+// Stopping test shared by the iteration kernels; identical inputs in every
+// block give identical decisions.
+template <bool MIXED>
+__device__ __forceinline__ int stop_state(const Scalars* sc, double rr) {
+  // 0 = iterate, 1 = stop (converged / finished), 2 = idle (mixed: waiting
+  // for an FP64 residual to confirm convergence)
+  if (sc->done) return 1;
+  if (rr <= sc->tol2) {
+    if (!MIXED || sc->rr_true) return 1;
+    return 2;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------- kernels
+// Start of a solve: x0 = phi, r0 = M phi - S phi = -c K_n phi (FP64 values),
+// diag(S), z0, p = 0, and the partials of (r, z), (r, r), (b, b).
+template <typename T, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_init(Mat m, Vecs<T> v, double* x, float* xacc, const double* phi,
+                                                  double* part, Scalars* sc, double c, int G, int spb) {
+  __shared__ double lds[3][kWavesPerBlock];
+  const int lb = logical_block(G);
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  double acc3[3] = {0.0, 0.0, 0.0};
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+    const int64_t row = s * kWave + lane;
+    if (row >= m.n) continue;
+    const int64_t base = m.sptr[s];
+    const int w = (int)((m.sptr[s + 1] - base) / kWave);
+    double a = 0.0;
+    for (int k = 0; k < w; ++k) {
+      const int64_t e = base + (int64_t)k * kWave + lane;
+      a += m.val64[e] * phi[m.col[e]];
+    }
+    const double ph = phi[row];
+    const double kd = m.kdiag64[row];
+    const double r64 = -c * (kd * ph + a);
+    const double d64 = m.mass64[row] + c * kd;
+    const T rt = (T)r64, dt = (T)d64;
+    const T zt = rt / dt;
+    x[row] = ph;
+    if (MIXED) xacc[row] = 0.0f;
+    v.r[row] = rt;
+    v.z[row] = zt;
+    v.d[row] = dt;
+    v.p0[row] = (T)0;
+    acc3[0] += (double)rt * (double)zt;
+    acc3[1] += r64 * r64;
+    const double b = m.mass64[row] * ph;
+    acc3[2] += b * b;
+  }
+  block_sum<3>(acc3, lds);
+  if (threadIdx.x == 0) {
+    part[P_RZ0 * G + lb] = acc3[0];
+    part[P_RR0 * G + lb] = acc3[1];
+    part[P_BB * G + lb] = acc3[2];
+    // rho_{-1} = +inf makes beta_0 = 0
+    part[P_RZ1 * G + lb] = lb == 0 ? INFINITY : 0.0;
+    if (lb == 0) {
+      sc->c = c;
+      sc->iters = 0;
+      sc->done = 0;
+      sc->rr_true = 1;
+      sc->updates = 0;
+      sc->update_now = 0;
+    }
+  }
+}
+
+// One block: tolerance and reference norms from the init partials.
+__global__ __launch_bounds__(kBlock) void k_setup(double* part, Scalars* sc, double rtol, int G) {
+  __shared__ double lw[kWavesPerBlock];
+  __shared__ double lo;
+  const double bb = reduce_partials(part + P_BB * G, G, lw, &lo);
+  const double rr = reduce_partials(part + P_RR0 * G, G, lw, &lo);
+  if (threadIdx.x == 0) {
+    sc->bb = bb;
+    sc->tol2 = rtol * rtol * bb;
+    sc->rr_ref = rr;
+    sc->rr_last = rr;
+  }
+}
+
+// CG step 1: p_new = z + beta p_old (own row and gathered neighbours),
+// q = S p_new = d p_new + c K_off p_new, partial (p_new, q).
+template <typename T, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_dir_spmv(Mat m, Vecs<T> v, double* part, Scalars* sc, int parity,
+                                                      int G, int spb) {
+  __shared__ double lw[kWavesPerBlock];
+  __shared__ double lo;
+  __shared__ double lds[1][kWavesPerBlock];
+  const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
+  const double rz_old = reduce_partials(part + (P_RZ0 + (parity ^ 1)) * G, G, lw, &lo);
+  const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
+  const int st = stop_state<MIXED>(sc, rr);
+  const int lb = logical_block(G);
+  if (st != 0) {
+    if (lb == 0 && threadIdx.x == 0 && st == 1 && sc->done == 0) {
+      sc->done = 1;
+      sc->rr_last = rr;
+    }
+    return;
+  }
+  const T beta = (T)(rz / rz_old);
+  const T c = (T)sc->c;
+  const T* __restrict__ pin = parity ? v.p1 : v.p0;
+  T* __restrict__ pout = parity ? v.p0 : v.p1;
+  const T* __restrict__ z = v.z;
+  const T* __restrict__ val = mval<T>(m);
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  double pq[1] = {0.0};
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+    const int64_t row = s * kWave + lane;
+    if (row >= m.n) continue;
+    const int64_t base = m.sptr[s];
+    const int w = (int)((m.sptr[s + 1] - base) / kWave);
+    T a = (T)0;
+    for (int k = 0; k < w; ++k) {
+      const int64_t e = base + (int64_t)k * kWave + lane;
+      const int32_t j = m.col[e];
+      a += val[e] * (z[j] + beta * pin[j]);
+    }
+    const T pn = z[row] + beta * pin[row];
+    const T qv = v.d[row] * pn + c * a;
+    pout[row] = pn;
+    v.q[row] = qv;
+    pq[0] += (double)pn * (double)qv;
+  }
+  block_sum<1>(pq, lds);
+  if (threadIdx.x == 0) {
+    part[P_PQ * G + lb] = pq[0];
+    if (lb == 0) {
+      sc->iters += 1;
+      sc->rr_last = rr;
+      if (MIXED && sc->rr_true) sc->rr_ref = rr;
+    }
+  }
+}
+
+// CG step 2: alpha = (r, z) / (p, q); x += alpha p; r -= alpha q;
+// z = r / diag(S); partials (r, z) and (r, r) for the next iteration.
+template <typename T, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_update(Mat m, Vecs<T> v, double* x, float* xacc, double* part,
+                                                    Scalars* sc, int parity, int G, int spb) {
+  __shared__ double lw[kWavesPerBlock];
+  __shared__ double lo;
+  __shared__ double lds[2][kWavesPerBlock];
+  const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
+  const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
+  const int st = stop_state<MIXED>(sc, rr);
+  const int lb = logical_block(G);
+  if (st != 0) return;
+  const double pq = reduce_partials(part + P_PQ * G, G, lw, &lo);
+  const double alpha = rz / pq;
+  if (!(pq > 0.0) || !isfinite(alpha)) {
+    if (lb == 0 && threadIdx.x == 0) sc->done = 2;
+    return;
+  }
+  const T at = (T)alpha;
+  const T* __restrict__ p = parity ? v.p0 : v.p1;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  double acc[2] = {0.0, 0.0};
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+    const int64_t row = s * kWave + lane;
+    if (row >= m.n) continue;
+    const T pv = p[row];
+    if (MIXED) xacc[row] += at * pv;
+    else x[row] += alpha * (double)pv;
+    const T rv = v.r[row] - at * v.q[row];
+    const T zv = rv / v.d[row];
+    v.r[row] = rv;
+    v.z[row] = zv;
+    acc[0] += (double)rv * (double)zv;
+    acc[1] += (double)rv * (double)rv;
+  }
+  block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    part[(P_RZ0 + (parity ^ 1)) * G + lb] = acc[0];
+    part[(P_RR0 + (parity ^ 1)) * G + lb] = acc[1];
+    if (MIXED && lb == 0) sc->rr_true = 0;
+  }
+}
+
+// Mixed precision, residual replacement part 1: decide (from the recursive
+// residual) whether to fold the FP32 increments into the FP64 solution now:
+// when the residual fell by a factor delta since the last replacement, or
+// when it meets the tolerance and needs an FP64 confirmation.
+__global__ __launch_bounds__(kBlock) void k_fold(Mat m, double* x, float* xacc, double* part, Scalars* sc,
+                                                 int parity, double delta2, int G, int spb) {
+  __shared__ double lw[kWavesPerBlock];
+  __shared__ double lo;
+  const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
+  const int lb = logical_block(G);
+  const bool trig = !sc->done && !sc->rr_true && (rr <= sc->tol2 || rr <= delta2 * sc->rr_ref);
+  if (lb == 0 && threadIdx.x == 0) sc->update_now = trig ? 1 : 0;
+  if (!trig) return;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+    const int64_t row = s * kWave + lane;
+    if (row >= m.n) continue;
+    x[row] += (double)xacc[row];
+    xacc[row] = 0.0f;
+  }
+}
+
+// Mixed precision, residual replacement part 2: r = M phi - S x in FP64
+// (FP64 values, FP64 x), stored as the FP32 recursive residual; the norm
+// partial is the FP64 one, so the next stopping test sees a true residual.
+__global__ __launch_bounds__(kBlock) void k_replace(Mat m, Vecs<float> v, const double* x, const double* phi,
+                                                    double* part, Scalars* sc, int parity, int G, int spb) {
+  __shared__ double lds[2][kWavesPerBlock];
+  if (!sc->update_now) return;
+  const int lb = logical_block(G);
+  const double c = sc->c;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  double acc[2] = {0.0, 0.0};
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+    const int64_t row = s * kWave + lane;
+    if (row >= m.n) continue;
+    const int64_t base = m.sptr[s];
+    const int w = (int)((m.sptr[s + 1] - base) / kWave);
+    double a = 0.0;
+    for (int k = 0; k < w; ++k) {
+      const int64_t e = base + (int64_t)k * kWave + lane;
+      a += m.val64[e] * x[m.col[e]];
+    }
+    const double xi = x[row];
+    const double r64 = m.mass64[row] * (phi[row] - xi) - c * (m.kdiag64[row] * xi + a);
+    const float rt = (float)r64;
+    const float zt = rt / v.d[row];
+    v.r[row] = rt;
+    v.z[row] = zt;
+    acc[0] += (double)rt * (double)zt;
+    acc[1] += r64 * r64;
+  }
+  block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    part[(P_RZ0 + parity) * G + lb] = acc[0];
+    part[(P_RR0 + parity) * G + lb] = acc[1];
+    if (lb == 0) {
+      sc->rr_true = 1;
+      sc->updates += 1;
+    }
+  }
+}
+
+// End of a solve: x = x (+ FP32 increments), scattered to the caller's
+// numbering; partials of the true FP64 residual and of sum M x^2.
+__global__ __launch_bounds__(kBlock) void k_finish(Mat m, const double* x, const float* xacc, const double* phi,
+                                                   const int64_t* entity, double* out, double* part,
+                                                   Scalars* sc, int G, int spb) {
+  __shared__ double lds[2][kWavesPerBlock];
+  const int lb = logical_block(G);
+  const double c = sc->c;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  double acc[2] = {0.0, 0.0};
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+    const int64_t row = s * kWave + lane;
+    if (row >= m.n) continue;
+    const int64_t base = m.sptr[s];
+    const int w = (int)((m.sptr[s + 1] - base) / kWave);
+    double a = 0.0;
+    for (int k = 0; k < w; ++k) {
+      const int64_t e = base + (int64_t)k * kWave + lane;
+      const int32_t j = m.col[e];
+      const double xj = xacc ? x[j] + (double)xacc[j] : x[j];
+      a += m.val64[e] * xj;
+    }
+    const double xi = xacc ? x[row] + (double)xacc[row] : x[row];
+    const double r64 = m.mass64[row] * (phi[row] - xi) - c * (m.kdiag64[row] * xi + a);
+    if (out) out[entity[row]] = xi;
+    acc[0] += r64 * r64;
+    acc[1] += m.mass64[row] * xi * xi;
+  }
+  block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    part[P_RES * G + lb] = acc[0];
+    part[P_EN * G + lb] = acc[1];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_scalars(double* part, Scalars* sc, int G) {
+  __shared__ double lw[kWavesPerBlock];
+  __shared__ double lo;
+  const double res = reduce_partials(part + P_RES * G, G, lw, &lo);
+  const double en = reduce_partials(part + P_EN * G, G, lw, &lo);
+  if (threadIdx.x == 0) {
+    sc->res2 = res;
+    sc->energy2 = en;
+  }
+}
+
+// Caller numbering -> internal order; flags non-finite wet entries.
+__global__ void k_gather_field(const double* __restrict__ src, const int64_t* __restrict__ entity, int64_t n,
+                               double* __restrict__ dst, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = src[entity[i]];
+  if (!isfinite(v)) atomicOr(flag, 1);
+  dst[i] = v;
+}
+
+// y = S x with FP64 values (internal order), scattered to the caller numbering.
+__global__ __launch_bounds__(kBlock) void k_apply(Mat m, const double* x, double c, const int64_t* entity,
+                                                  double* out) {
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int64_t s = (int64_t)blockIdx.x * kWavesPerBlock + wid;
+  if (s >= m.n_slices) return;
+  const int64_t row = s * kWave + lane;
+  if (row >= m.n) return;
+  const int64_t base = m.sptr[s];
+  const int w = (int)((m.sptr[s + 1] - base) / kWave);
+  double a = 0.0;
+  for (int k = 0; k < w; ++k) {
+    const int64_t e = base + (int64_t)k * kWave + lane;
+    a += m.val64[e] * x[m.col[e]];
+  }
+  out[entity[row]] = (m.mass64[row] + c * m.kdiag64[row]) * x[row] + c * a;
+}
+
+// ------------------------------------------------------------- host driver
+namespace {
+
+template <typename T>
+ifl_status dalloc(T** p, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(IFL_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  return IFL_OK;
+}
+
+template <typename T>
+ifl_status upload(T** p, const std::vector<T>& v) {
+  ifl_status st = dalloc(p, v.size());
+  if (st != IFL_OK) return st;
+  if (!v.empty()) IFL_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return IFL_OK;
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+Mat mat_view(const DevMatrix& m) {
+  return Mat{m.n, m.n_slices, m.sptr, m.col, m.val64, m.val32, m.kdiag64, m.kdiag32, m.mass64};
+}
+
+hipStream_t stream_of(Handle* h) {
+  return h->opt.stream ? (hipStream_t)h->opt.stream : h->dev->own_stream;
+}
+
+}  // namespace
+
+ifl_status device_create(Handle* h) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(IFL_EDEVICE, "no HIP device available");
+  }
+  if (h->opt.device < 0 || h->opt.device >= ndev) return fail(IFL_EDEVICE, "device ordinal out of range");
+  IFL_HIP(hipSetDevice(h->opt.device));
+  hipDeviceProp_t prop;
+  IFL_HIP(hipGetDeviceProperties(&prop, h->opt.device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(IFL_EDEVICE, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
+  DeviceState* d = new DeviceState();
+  h->dev = d;
+  d->device = h->opt.device;
+  IFL_HIP(hipStreamCreateWithFlags(&d->own_stream, hipStreamNonBlocking));
+
+  SellPack sp;
+  pack_sell(h->op, &sp);
+  DevMatrix& m = d->m;
+  m.n = sp.n;
+  m.n_slices = sp.n_slices;
+  m.n_pad = sp.n_slices * kWave;
+  m.nnz_stored = (int64_t)sp.col.size();
+  m.offdiag = sp.stored_offdiag;
+  std::vector<float> v32(sp.val.begin(), sp.val.end());
+  std::vector<float> kd32(sp.diag.begin(), sp.diag.end());
+  ifl_status st;
+  if ((st = upload(&m.sptr, sp.slice_ptr)) || (st = upload(&m.col, sp.col)) || (st = upload(&m.val64, sp.val)) ||
+      (st = upload(&m.val32, v32)) || (st = upload(&m.kdiag64, sp.diag)) || (st = upload(&m.kdiag32, kd32)) ||
+      (st = upload(&m.mass64, sp.mass)) || (st = upload(&m.entity, h->op.entity)))
+    return st;
+  m.mass_sum = 0.0;
+  for (double a : h->op.mass) m.mass_sum += a;
+
+  // launch geometry: logical blocks own contiguous slice ranges
+  const int64_t ns = m.n_slices;
+  int G = (int)std::min<int64_t>(kMaxBlocks, (ns + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (G >= kXcd) G = (G / kXcd) * kXcd;
+  d->G = std::max(1, G);
+  d->spb = (int)((ns + d->G - 1) / d->G);
+
+  ColWork& w = d->w;
+  const size_t np = (size_t)m.n_pad;
+  if ((st = dalloc(&w.x, np)) || (st = dalloc(&w.r, np)) || (st = dalloc(&w.z, np)) || (st = dalloc(&w.p[0], np)) ||
+      (st = dalloc(&w.p[1], np)) || (st = dalloc(&w.q, np)) || (st = dalloc(&w.d, np)) ||
+      (st = dalloc(&w.r32, np)) || (st = dalloc(&w.z32, np)) || (st = dalloc(&w.p32[0], np)) ||
+      (st = dalloc(&w.p32[1], np)) || (st = dalloc(&w.q32, np)) || (st = dalloc(&w.d32, np)) ||
+      (st = dalloc(&w.xacc, np)) || (st = dalloc(&w.phi, np)) || (st = dalloc(&w.part, (size_t)P_COUNT * d->G)) ||
+      (st = dalloc(&w.sc, 1)) || (st = dalloc(&w.flag, 1)))
+    return st;
+  IFL_HIP(hipHostMalloc((void**)&w.sc_host, 2 * sizeof(Scalars), hipHostMallocDefault));
+  IFL_HIP(hipMemset(w.part, 0, sizeof(double) * P_COUNT * d->G));
+  IFL_HIP(hipMemset(w.sc, 0, sizeof(Scalars)));
+  return IFL_OK;
+}
+
+void device_destroy(Handle* h) {
+  DeviceState* d = h->dev;
+  if (!d) return;
+  (void)hipSetDevice(d->device);
+  if (d->own_stream) (void)hipStreamSynchronize(d->own_stream);
+  DevMatrix& m = d->m;
+  void* ptrs[] = {m.sptr, m.col, m.val64, m.val32, m.kdiag64, m.kdiag32, m.mass64, m.entity, d->w.x, d->w.r, d->w.z,
+                  d->w.p[0], d->w.p[1], d->w.q, d->w.d, d->w.r32, d->w.z32, d->w.p32[0], d->w.p32[1], d->w.q32,
+                  d->w.d32, d->w.xacc, d->w.phi, d->w.part, d->w.sc, d->w.flag, d->w.stage_in, d->w.stage_out};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (d->w.sc_host) (void)hipHostFree(d->w.sc_host);
+  for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
+  if (d->own_stream) (void)hipStreamDestroy(d->own_stream);
+  delete d;
+  h->dev = nullptr;
+}
+
+namespace {
+
+ifl_status ensure_stage(DeviceState* d, int64_t len) {
+  if (d->w.stage_len >= len) return IFL_OK;
+  if (d->w.stage_in) (void)hipFree(d->w.stage_in);
+  if (d->w.stage_out) (void)hipFree(d->w.stage_out);
+  d->w.stage_in = d->w.stage_out = nullptr;
+  d->w.stage_len = 0;
+  ifl_status st;
+  if ((st = dalloc(&d->w.stage_in, (size_t)len)) || (st = dalloc(&d->w.stage_out, (size_t)len))) return st;
+  d->w.stage_len = len;
+  return IFL_OK;
+}
+
+ifl_status ensure_events(DeviceState* d, size_t count) {
+  while (d->ev.size() < count) {
+    hipEvent_t e;
+    IFL_HIP(hipEventCreate(&e));
+    d->ev.push_back(e);
+  }
+  return IFL_OK;
+}
+
+// Bring one field (caller numbering, host or device) into w.phi (internal
+// order); IFL_EINVAL on a non-finite wet entry.
+ifl_status load_field(Handle* h, const double* field, bool dev_ptr, hipStream_t s) {
+  DeviceState* d = h->dev;
+  const int64_t L = h->op.field_len;
+  const double* src = field;
+  if (!dev_ptr) {
+    IFL_HIP(hipMemcpyAsync(d->w.stage_in, field, sizeof(double) * L, hipMemcpyHostToDevice, s));
+    src = d->w.stage_in;
+  }
+  IFL_HIP(hipMemsetAsync(d->w.flag, 0, sizeof(int), s));
+  const int64_t n = d->m.n;
+  k_gather_field<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, d->m.entity, n, d->w.phi, d->w.flag);
+  IFL_HIP(hipGetLastError());
+  int flag = 0;
+  IFL_HIP(hipMemcpyAsync(&flag, d->w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  IFL_HIP(hipStreamSynchronize(s));
+  if (flag) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");
+  return IFL_OK;
+}
+
+// Algorithmic bytes of one k_dir_spmv launch: the sliced-ELL stream
+// (index + value per stored entry, slice pointers), the gathered z and p
+// (each read once), own d, and the writes of p and q.
+double spmv_bytes(const DevMatrix& m, size_t vb) {
+  return (double)m.nnz_stored * (4.0 + vb) + 8.0 * (m.n_slices + 1) + (double)m.n * vb * 5.0;
+}
+
+template <typename T, bool MIXED>
+ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* out_dev, double* energy) {
+  DeviceState* d = h->dev;
+  ColWork& w = d->w;
+  const DevMatrix& M = d->m;
+  hipStream_t s = stream_of(h);
+  const Mat m = mat_view(M);
+  Vecs<T> v;
+  if constexpr (MIXED) {
+    v = Vecs<T>{w.r32, w.z32, w.p32[0], w.p32[1], w.q32, w.d32};
+  } else {
+    v = Vecs<T>{w.r, w.z, w.p[0], w.p[1], w.q, w.d};
+  }
+  const int G = d->G, spb = d->spb;
+  const double c = h->opt.gamma / std::pow(k, 2.0 * h->op.order);
+  const auto t0 = std::chrono::steady_clock::now();
+  k_init<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, w.phi, w.part, w.sc, c, G, spb);
+  k_setup<<<1, kBlock, 0, s>>>(w.part, w.sc, h->opt.rtol, G);
+  IFL_HIP(hipGetLastError());
+
+  const int chunk = 8;         // iterations between host checks
+  const int fold_every = 4;    // mixed: residual-replacement checks
+  const double delta2 = 1e-4;  // mixed: replace when ||r|| fell 100x
+  const bool prof = h->opt.profile != 0;
+  const int max_iter = h->opt.max_iter;
+  int launched = 0, chunk_id = 0;
+  bool finished = false;
+  int pending = -1;  // chunk whose scalars are in flight
+  int32_t iters_seen = 0;
+  std::vector<int> prof_pairs;
+  if (prof) {
+    ifl_status e = ensure_events(d, 4 * chunk);
+    if (e != IFL_OK) return e;
+  }
+  hipEvent_t done_ev[2];
+  IFL_HIP(hipEventCreateWithFlags(&done_ev[0], hipEventDisableTiming));
+  IFL_HIP(hipEventCreateWithFlags(&done_ev[1], hipEventDisableTiming));
+  ifl_status result = IFL_OK;
+  while (!finished) {
+    const int slot = chunk_id & 1;
+    int npairs = 0;
+    for (int j = 0; j < chunk && launched < max_iter; ++j) {
+      const int parity = launched & 1;
+      if (prof) IFL_HIP(hipEventRecord(d->ev[2 * npairs + 2 * chunk * slot], s));
+      k_dir_spmv<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.part, w.sc, parity, G, spb);
+      if (prof) IFL_HIP(hipEventRecord(d->ev[2 * npairs + 1 + 2 * chunk * slot], s));
+      ++npairs;
+      k_update<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, w.part, w.sc, parity, G, spb);
+      ++launched;
+      if (MIXED && (launched % fold_every == 0 || launched == max_iter)) {
+        const int par2 = launched & 1;
+        k_fold<<<G, kBlock, 0, s>>>(m, w.x, w.xacc, w.part, w.sc, par2, delta2, G, spb);
+        k_replace<<<G, kBlock, 0, s>>>(m, Vecs<float>{w.r32, w.z32, w.p32[0], w.p32[1], w.q32, w.d32}, w.x, w.phi,
+                                       w.part, w.sc, par2, G, spb);
+      }
+    }
+    IFL_HIP(hipGetLastError());
+    IFL_HIP(hipMemcpyAsync(&w.sc_host[slot], w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    IFL_HIP(hipEventRecord(done_ev[slot], s));
+    prof_pairs.resize(2);
+    prof_pairs[slot] = npairs;
+    const bool capped = launched >= max_iter;
+    // wait for the previous chunk (the current one keeps the GPU busy)
+    int wait_chunk = capped ? chunk_id : pending;
+    if (wait_chunk >= 0) {
+      const int ws = wait_chunk & 1;
+      IFL_HIP(hipEventSynchronize(done_ev[ws]));
+      const Scalars& sh = w.sc_host[ws];
+      if (prof) {
+        // count only launches that iterated (iterations are sequential)
+        const int real = std::max(0, std::min(prof_pairs[ws], sh.iters - iters_seen));
+        for (int p = 0; p < real; ++p) {
+          float ms = 0.f;
+          IFL_HIP(hipEventElapsedTime(&ms, d->ev[2 * p + 2 * chunk * ws], d->ev[2 * p + 1 + 2 * chunk * ws]));
+          d->prof_ms += ms;
+        }
+        d->prof_launches += real;
+      }
+      iters_seen = sh.iters;
+      if (sh.done) finished = true;
+    }
+    if (capped) finished = true;
+    pending = chunk_id;
+    ++chunk_id;
+  }
+  // finish: x to caller numbering, true residual, energy
+  k_finish<<<G, kBlock, 0, s>>>(m, w.x, MIXED ? w.xacc : nullptr, w.phi, M.entity, out_dev, w.part, w.sc, G, spb);
+  k_finish_scalars<<<1, kBlock, 0, s>>>(w.part, w.sc, G);
+  IFL_HIP(hipGetLastError());
+  IFL_HIP(hipMemcpyAsync(&w.sc_host[0], w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  IFL_HIP(hipStreamSynchronize(s));
+  (void)hipEventDestroy(done_ev[0]);
+  (void)hipEventDestroy(done_ev[1]);
+  const Scalars& sh = w.sc_host[0];
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  const double rel = sh.bb > 0 ? std::sqrt(sh.res2 / sh.bb) : std::sqrt(sh.res2);
+  const bool ok = sh.done == 1;
+  if (st_out) {
+    st_out->iterations = sh.iters;
+    st_out->refinements = sh.updates;
+    st_out->status = ok ? IFL_OK : IFL_ENOTCONV;
+    st_out->reserved = 0;
+    st_out->rel_residual = rel;
+    st_out->seconds = secs;
+  }
+  if (energy) *energy = 0.5 * sh.energy2 / M.mass_sum;
+  if (!ok) result = fail(IFL_ENOTCONV, sh.done == 2 ? "CG breakdown ((p, Sp) <= 0 or non-finite)"
+                                                       : "CG reached max_iter before the tolerance");
+  return result;
+}
+
+}  // namespace
+
+ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales, const double* k,
+                         double* out, ifl_solve_stats* stats, double* energy) {
+  DeviceState* d = h->dev;
+  IFL_HIP(hipSetDevice(d->device));
+  hipStream_t s = stream_of(h);
+  const int64_t L = h->op.field_len;
+  const bool fdev = is_device_ptr(fields);
+  const bool odev = out ? is_device_ptr(out) : false;
+  ifl_status st = ensure_stage(d, L);
+  if (st != IFL_OK) return st;
+  ifl_status agg = IFL_OK;
+  for (int32_t f = 0; f < n_fields; ++f) {
+    st = load_field(h, fields + (int64_t)f * L, fdev, s);
+    if (st != IFL_OK) return st;
+    for (int32_t j = 0; j < n_scales; ++j) {
+      double* dst = nullptr;
+      if (out) {
+        dst = odev ? out + ((int64_t)f * n_scales + j) * L : d->w.stage_out;
+        IFL_HIP(hipMemsetAsync(dst, 0, sizeof(double) * L, s));
+      }
+      ifl_solve_stats* so = stats ? &stats[(int64_t)f * n_scales + j] : nullptr;
+      double* eo = energy ? &energy[(int64_t)f * n_scales + j] : nullptr;
+      if (h->opt.precision == IFL_MIXED) st = solve_column<float, true>(h, k[j], so, dst, eo);
+      else st = solve_column<double, false>(h, k[j], so, dst, eo);
+      if (st == IFL_ENOTCONV) agg = st;
+      else if (st != IFL_OK) return st;
+      if (out && !odev) {
+        IFL_HIP(hipMemcpyAsync(out + ((int64_t)f * n_scales + j) * L, d->w.stage_out, sizeof(double) * L,
+                               hipMemcpyDeviceToHost, s));
+        IFL_HIP(hipStreamSynchronize(s));
+      }
+    }
+  }
+  if (agg != IFL_OK) return fail(agg, "at least one column did not converge (see stats)");
+  return IFL_OK;
+}
+
+ifl_status device_apply(Handle* h, double kk, const double* x, double* y) {
+  DeviceState* d = h->dev;
+  IFL_HIP(hipSetDevice(d->device));
+  hipStream_t s = stream_of(h);
+  const int64_t L = h->op.field_len;
+  ifl_status st = ensure_stage(d, L);
+  if (st != IFL_OK) return st;
+  st = load_field(h, x, is_device_ptr(x), s);
+  if (st != IFL_OK) return st;
+  const bool ydev = is_device_ptr(y);
+  double* dst = ydev ? y : d->w.stage_out;
+  IFL_HIP(hipMemsetAsync(dst, 0, sizeof(double) * L, s));
+  const double c = h->opt.gamma / std::pow(kk, 2.0 * h->op.order);
+  const unsigned nb = (unsigned)((d->m.n_slices + kWavesPerBlock - 1) / kWavesPerBlock);
+  k_apply<<<nb, kBlock, 0, s>>>(mat_view(d->m), d->w.phi, c, d->m.entity, dst);
+  IFL_HIP(hipGetLastError());
+  if (!ydev) IFL_HIP(hipMemcpyAsync(y, dst, sizeof(double) * L, hipMemcpyDeviceToHost, s));
+  IFL_HIP(hipStreamSynchronize(s));
+  return IFL_OK;
+}
+
+ifl_status device_profile_read(Handle* h, int64_t* launches, double* total_ms, double* bytes, int32_t reset) {
+  DeviceState* d = h->dev;
+  if (launches) *launches = d->prof_launches;
+  if (total_ms) *total_ms = d->prof_ms;
+  if (bytes) *bytes = spmv_bytes(d->m, h->opt.precision == IFL_MIXED ? 4 : 8);
+  if (reset) {
+    d->prof_launches = 0;
+    d->prof_ms = 0.0;
+  }
+  return IFL_OK;
+}
+
+}  // namespace ifl

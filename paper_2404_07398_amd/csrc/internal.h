@@ -1,0 +1,77 @@
+// Internal declarations of the implicit-filter library (not part of the ABI).
+#pragma once
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ifl.h"
+
+namespace ifl {
+
+// Sets the thread-local error message and returns the status.
+ifl_status fail(ifl_status st, const std::string& msg);
+
+// ----------------------------------------------------------------- host side
+// The prepared operator in host memory, rows in the library's internal
+// (locality) order. K_n is stored in CSR with sorted columns and its
+// diagonal included; the system of a solve is S = diag(mass) + c K_n.
+struct HostOperator {
+  int32_t placement = IFL_VERTEX_SCALAR;
+  int32_t order = 1;
+  int64_t n = 0;                   // rows (unknowns)
+  int64_t field_len = 0;           // length of a field in the caller's numbering
+  std::vector<int64_t> entity;     // caller index of each row
+  std::vector<int64_t> row_ptr;    // n + 1
+  std::vector<int32_t> col;        // nnz
+  std::vector<double> val;         // nnz
+  std::vector<double> mass;        // n
+  int32_t n_components = 1;        // 1 (scalar) or 2 (vector)
+  uint64_t mesh_hash = 0;
+};
+
+// Mesh -> operator (prepare phase). 'reorder' selects the reverse
+// Cuthill-McKee ordering of the dofs.
+ifl_status build_operator(const ifl_mesh& mesh, int32_t placement, int32_t order, double cell_A,
+                          int32_t reorder, HostOperator* out);
+
+// Sliced-ELL packing used by the device kernels: rows in slices of 64
+// (one wavefront); slice s stores its off-diagonal entries column-major,
+// entry k of lane l at slice_ptr[s] + 64 k + l, padded to the widest row
+// of the slice with (col = row, val = 0).
+struct SellPack {
+  int64_t n = 0;
+  int64_t n_slices = 0;
+  std::vector<int64_t> slice_ptr;  // n_slices + 1
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  std::vector<double> diag;        // K_n diagonal, n_slices * 64 (zero padded)
+  std::vector<double> mass;        // n_slices * 64 (pads: 0)
+  int32_t max_width = 0;
+  int64_t stored_offdiag = 0;      // true off-diagonal entries (no padding)
+};
+
+void pack_sell(const HostOperator& op, SellPack* out);
+
+// ---------------------------------------------------------------- device side
+struct DeviceState;  // defined in device.hip
+
+struct Handle {
+  ifl_options opt{};
+  HostOperator op;
+  DeviceState* dev = nullptr;
+  std::mutex mu;
+};
+
+ifl_status device_create(Handle* h);
+void device_destroy(Handle* h);
+
+// Solve n_fields x n_scales columns. fields / out may be host or device.
+ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales,
+                         const double* k, double* out, ifl_solve_stats* stats, double* energy);
+ifl_status device_apply(Handle* h, double k, const double* x, double* y);
+ifl_status device_profile_read(Handle* h, int64_t* launches, double* total_ms, double* bytes,
+                               int32_t reset);
+
+}  // namespace ifl

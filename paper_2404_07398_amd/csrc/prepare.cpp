@@ -1,0 +1,567 @@
+// Mesh-only preparation of the implicit filter (Sect. 2.2.1): active cells,
+// dofs, flat-facet geometry, lumped mass, stiffness, order-n operator and a
+// locality ordering. Host C++, run once per mesh; the result is reused for
+// every field and every scale.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace ifl {
+namespace {
+
+struct V3 {
+  double x, y, z;
+};
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 scale(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+
+// Corner positions of triangle t; periodic edges are unwrapped by the
+// minimum image relative to corner 0. Planar points get z = 0.
+void corners(const ifl_mesh& m, const int32_t* t, V3 p[3]) {
+  if (m.geometry == IFL_GEOM_SPHERE) {
+    for (int i = 0; i < 3; ++i) {
+      const double* c = m.coords + 3 * (int64_t)t[i];
+      p[i] = {c[0], c[1], c[2]};
+    }
+    return;
+  }
+  const double* c0 = m.coords + 2 * (int64_t)t[0];
+  p[0] = {c0[0], c0[1], 0.0};
+  for (int i = 1; i < 3; ++i) {
+    const double* c = m.coords + 2 * (int64_t)t[i];
+    double dx = c[0] - c0[0], dy = c[1] - c0[1];
+    if (m.geometry == IFL_GEOM_PERIODIC) {
+      dx -= m.period[0] * std::nearbyint(dx / m.period[0]);
+      dy -= m.period[1] * std::nearbyint(dy / m.period[1]);
+    }
+    p[i] = {c0[0] + dx, c0[1] + dy, 0.0};
+  }
+}
+
+// COO triplets -> CSR with sorted columns; duplicates are summed in the
+// order they were added, so two rows that receive the same contributions in
+// the same order get bitwise equal entries.
+struct Triplets {
+  std::vector<int64_t> r;
+  std::vector<int32_t> c;
+  std::vector<double> v;
+  void add(int64_t i, int64_t j, double x) {
+    r.push_back(i);
+    c.push_back((int32_t)j);
+    v.push_back(x);
+  }
+};
+
+void to_csr(int64_t n, const Triplets& t, std::vector<int64_t>& row_ptr, std::vector<int32_t>& col,
+            std::vector<double>& val) {
+  const int64_t m = (int64_t)t.r.size();
+  std::vector<int64_t> cnt(n + 1, 0);
+  for (int64_t e = 0; e < m; ++e) cnt[t.r[e] + 1]++;
+  for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  std::vector<int32_t> bc(m);
+  std::vector<double> bv(m);
+  for (int64_t e = 0; e < m; ++e) {
+    int64_t p = pos[t.r[e]]++;
+    bc[p] = t.c[e];
+    bv[p] = t.v[e];
+  }
+  row_ptr.assign(n + 1, 0);
+  col.clear();
+  val.clear();
+  col.reserve(m);
+  val.reserve(m);
+  std::vector<int64_t> idx;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t b = cnt[i], e = cnt[i + 1];
+    idx.resize(e - b);
+    std::iota(idx.begin(), idx.end(), b);
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t q) { return bc[a] < bc[q]; });
+    for (size_t k = 0; k < idx.size();) {
+      const int32_t cc = bc[idx[k]];
+      double s = 0.0;
+      while (k < idx.size() && bc[idx[k]] == cc) s += bv[idx[k++]];
+      col.push_back(cc);
+      val.push_back(s);
+    }
+    row_ptr[i + 1] = (int64_t)col.size();
+  }
+}
+
+// C = A diag(1/m) B for CSR A, B with sorted columns. Entry (i, j) sums
+// (A_ik B_kj) / m_k over k ascending; with A = B symmetric this makes C
+// bitwise symmetric.
+void spgemm_scaled(int64_t n, const std::vector<int64_t>& ap, const std::vector<int32_t>& ac,
+                   const std::vector<double>& av, const std::vector<int64_t>& bp,
+                   const std::vector<int32_t>& bc, const std::vector<double>& bv,
+                   const std::vector<double>& m, std::vector<int64_t>& cp, std::vector<int32_t>& cc,
+                   std::vector<double>& cv) {
+  std::vector<double> acc(n, 0.0);
+  std::vector<int64_t> mark(n, -1);
+  std::vector<int32_t> touched;
+  cp.assign(n + 1, 0);
+  cc.clear();
+  cv.clear();
+  for (int64_t i = 0; i < n; ++i) {
+    touched.clear();
+    for (int64_t a = ap[i]; a < ap[i + 1]; ++a) {
+      const int32_t k = ac[a];
+      const double aik = av[a];
+      for (int64_t b = bp[k]; b < bp[k + 1]; ++b) {
+        const int32_t j = bc[b];
+        const double t = (aik * bv[b]) / m[k];
+        if (mark[j] != i) {
+          mark[j] = i;
+          acc[j] = t;
+          touched.push_back(j);
+        } else {
+          acc[j] += t;
+        }
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int32_t j : touched) {
+      cc.push_back(j);
+      cv.push_back(acc[j]);
+    }
+    cp[i + 1] = (int64_t)cc.size();
+  }
+}
+
+// Reverse Cuthill-McKee ordering of a graph given by CSR adjacency (self
+// loops ignored). Each connected component starts from a pseudo-peripheral
+// node; neighbours are visited by increasing degree. Returns order[new] = old.
+std::vector<int64_t> rcm(int64_t n, const std::vector<int64_t>& ptr, const std::vector<int32_t>& adj) {
+  std::vector<int32_t> deg(n);
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t d = 0;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) d += (adj[e] != i);
+    deg[i] = d;
+  }
+  std::vector<int64_t> order;
+  order.reserve(n);
+  std::vector<char> seen(n, 0);
+  std::vector<int64_t> level(n, -1);
+  std::vector<int64_t> queue;
+  std::vector<int64_t> nb;
+  auto bfs_last = [&](int64_t s, int64_t* depth) {
+    // returns a minimum-degree node of the last BFS level from s
+    queue.clear();
+    queue.push_back(s);
+    level[s] = 0;
+    std::vector<int64_t> touched{s};
+    size_t h = 0;
+    int64_t maxl = 0;
+    while (h < queue.size()) {
+      int64_t u = queue[h++];
+      for (int64_t e = ptr[u]; e < ptr[u + 1]; ++e) {
+        int64_t w = adj[e];
+        if (w == u || level[w] >= 0) continue;
+        level[w] = level[u] + 1;
+        maxl = std::max(maxl, level[w]);
+        queue.push_back(w);
+        touched.push_back(w);
+      }
+    }
+    int64_t best = s;
+    for (int64_t u : touched)
+      if (level[u] == maxl && (best == s || deg[u] < deg[best])) best = u;
+    for (int64_t u : touched) level[u] = -1;
+    *depth = maxl;
+    return best;
+  };
+  for (int64_t s0 = 0; s0 < n; ++s0) {
+    if (seen[s0]) continue;
+    int64_t start = s0, depth = 0, d2 = 0;
+    int64_t cand = bfs_last(start, &depth);
+    for (int it = 0; it < 4; ++it) {
+      int64_t c2 = bfs_last(cand, &d2);
+      if (d2 <= depth) break;
+      start = cand;
+      depth = d2;
+      cand = c2;
+    }
+    // Cuthill-McKee BFS from start
+    size_t head = order.size();
+    order.push_back(start);
+    seen[start] = 1;
+    while (head < order.size()) {
+      int64_t u = order[head++];
+      nb.clear();
+      for (int64_t e = ptr[u]; e < ptr[u + 1]; ++e) {
+        int64_t w = adj[e];
+        if (w != u && !seen[w]) {
+          seen[w] = 1;
+          nb.push_back(w);
+        }
+      }
+      std::stable_sort(nb.begin(), nb.end(), [&](int64_t a, int64_t b) { return deg[a] < deg[b]; });
+      for (int64_t w : nb) order.push_back(w);
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+ifl_status validate(const ifl_mesh& m) {
+  if (m.n_vertices < 3 || m.n_triangles < 1) return fail(IFL_EINVAL, "mesh needs >= 3 vertices and >= 1 triangle");
+  if (m.n_vertices > INT32_MAX || m.n_triangles > INT32_MAX / 2)
+    return fail(IFL_EINVAL, "mesh too large for 32-bit indices");
+  if (!m.coords || !m.triangles) return fail(IFL_EINVAL, "mesh coords / triangles are NULL");
+  if (m.geometry < IFL_GEOM_PLANAR || m.geometry > IFL_GEOM_SPHERE) return fail(IFL_EINVAL, "unknown geometry");
+  const int dim = m.geometry == IFL_GEOM_SPHERE ? 3 : 2;
+  for (int64_t i = 0; i < m.n_vertices * dim; ++i)
+    if (!std::isfinite(m.coords[i])) return fail(IFL_EINVAL, "non-finite vertex coordinate");
+  if (m.geometry == IFL_GEOM_PERIODIC &&
+      !(m.period[0] > 0 && m.period[1] > 0 && std::isfinite(m.period[0]) && std::isfinite(m.period[1])))
+    return fail(IFL_EINVAL, "periodic mesh needs positive finite periods");
+  for (int64_t i = 0; i < 3 * m.n_triangles; ++i)
+    if (m.triangles[i] < 0 || m.triangles[i] >= m.n_vertices) return fail(IFL_EINVAL, "triangle vertex id out of range");
+  return IFL_OK;
+}
+
+std::vector<char> active_triangles(const ifl_mesh& m) {
+  std::vector<char> act(m.n_triangles, 1);
+  if (m.wet) {
+    for (int64_t t = 0; t < m.n_triangles; ++t) {
+      const int32_t* v = m.triangles + 3 * t;
+      act[t] = (m.wet[v[0]] != 0) && (m.wet[v[1]] != 0) && (m.wet[v[2]] != 0);
+    }
+  }
+  return act;
+}
+
+// Renumber rows/cols of a CSR by order[new] = old; columns re-sorted.
+void permute_csr(int64_t n, const std::vector<int64_t>& order, const std::vector<int64_t>& p,
+                 const std::vector<int32_t>& c, const std::vector<double>& v, std::vector<int64_t>& np,
+                 std::vector<int32_t>& nc, std::vector<double>& nv) {
+  std::vector<int64_t> inv(n);
+  for (int64_t i = 0; i < n; ++i) inv[order[i]] = i;
+  np.assign(n + 1, 0);
+  nc.resize(c.size());
+  nv.resize(v.size());
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t r = 0; r < n; ++r) {
+    const int64_t o = order[r];
+    row.clear();
+    for (int64_t e = p[o]; e < p[o + 1]; ++e) row.push_back({(int32_t)inv[c[e]], v[e]});
+    std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    int64_t base = np[r];
+    for (size_t k = 0; k < row.size(); ++k) {
+      nc[base + k] = row[k].first;
+      nv[base + k] = row[k].second;
+    }
+    np[r + 1] = base + (int64_t)row.size();
+  }
+}
+
+ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder, HostOperator* out) {
+  const std::vector<char> act = active_triangles(m);
+  std::vector<int64_t> dof_of(m.n_vertices, -1);
+  for (int64_t t = 0; t < m.n_triangles; ++t)
+    if (act[t])
+      for (int k = 0; k < 3; ++k) dof_of[m.triangles[3 * t + k]] = 0;
+  std::vector<int64_t> vert_of;
+  for (int64_t v = 0; v < m.n_vertices; ++v)
+    if (dof_of[v] == 0) {
+      dof_of[v] = (int64_t)vert_of.size();
+      vert_of.push_back(v);
+    }
+  const int64_t n = (int64_t)vert_of.size();
+  if (n == 0) return fail(IFL_EDEGENERATE, "no active triangle (all triangles touch a dry vertex)");
+
+  Triplets tr;
+  tr.r.reserve(9 * (size_t)m.n_triangles);
+  tr.c.reserve(9 * (size_t)m.n_triangles);
+  tr.v.reserve(9 * (size_t)m.n_triangles);
+  std::vector<double> mass(n, 0.0);
+  for (int64_t t = 0; t < m.n_triangles; ++t) {
+    if (!act[t]) continue;
+    const int32_t* tv = m.triangles + 3 * t;
+    V3 p[3];
+    corners(m, tv, p);
+    // e[i] is the edge opposite corner i; grad N_i = (normal x e_i) / (2 area),
+    // so A_T grad N_i . grad N_j = e_i . e_j / (4 A_T).
+    const V3 e[3] = {sub(p[2], p[1]), sub(p[0], p[2]), sub(p[1], p[0])};
+    const double twoA = norm(cross(e[2], scale(e[1], -1.0)));
+    const double ee = dot(e[0], e[0]) + dot(e[1], e[1]) + dot(e[2], e[2]);
+    if (!(twoA > 1e-14 * ee)) return fail(IFL_EDEGENERATE, "zero-area active triangle " + std::to_string(t));
+    const double inv = 1.0 / (2.0 * twoA);
+    int64_t d[3] = {dof_of[tv[0]], dof_of[tv[1]], dof_of[tv[2]]};
+    for (int i = 0; i < 3; ++i) {
+      tr.add(d[i], d[i], dot(e[i], e[i]) * inv);
+      for (int j = i + 1; j < 3; ++j) {
+        const double kij = dot(e[i], e[j]) * inv;
+        tr.add(d[i], d[j], kij);
+        tr.add(d[j], d[i], kij);
+      }
+      mass[d[i]] += twoA / 6.0;
+    }
+  }
+  std::vector<int64_t> kp;
+  std::vector<int32_t> kc;
+  std::vector<double> kv;
+  to_csr(n, tr, kp, kc, kv);
+  tr = Triplets();
+
+  std::vector<int64_t> np = kp;
+  std::vector<int32_t> nc = kc;
+  std::vector<double> nv = kv;
+  for (int32_t r = 1; r < order; ++r) {
+    std::vector<int64_t> tp;
+    std::vector<int32_t> tc;
+    std::vector<double> tvv;
+    spgemm_scaled(n, np, nc, nv, kp, kc, kv, mass, tp, tc, tvv);
+    np.swap(tp);
+    nc.swap(tc);
+    nv.swap(tvv);
+  }
+  std::vector<int64_t> ord(n);
+  if (reorder) ord = rcm(n, kp, kc);
+  else std::iota(ord.begin(), ord.end(), 0);
+
+  out->placement = IFL_VERTEX_SCALAR;
+  out->order = order;
+  out->n = n;
+  out->n_components = 1;
+  out->field_len = m.n_vertices;
+  permute_csr(n, ord, np, nc, nv, out->row_ptr, out->col, out->val);
+  out->mass.resize(n);
+  out->entity.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    out->mass[i] = mass[ord[i]];
+    out->entity[i] = vert_of[ord[i]];
+  }
+  return IFL_OK;
+}
+
+ifl_status build_cell_vector(const ifl_mesh& m, int32_t order, double A, int32_t reorder, HostOperator* out) {
+  const std::vector<char> act = active_triangles(m);
+  std::vector<int64_t> cell_of(m.n_triangles, -1), tri_of;
+  for (int64_t t = 0; t < m.n_triangles; ++t)
+    if (act[t]) {
+      cell_of[t] = (int64_t)tri_of.size();
+      tri_of.push_back(t);
+    }
+  const int64_t nc = (int64_t)tri_of.size();
+  if (nc == 0) return fail(IFL_EDEGENERATE, "no active triangle (all triangles touch a dry vertex)");
+  std::vector<double> area(nc);
+  std::vector<V3> eE(nc), eN(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int32_t* tv = m.triangles + 3 * tri_of[c];
+    V3 p[3];
+    corners(m, tv, p);
+    const V3 a = sub(p[1], p[0]), b = sub(p[2], p[0]);
+    const double twoA = norm(cross(a, b));
+    const double ee = dot(a, a) + dot(b, b) + dot(sub(p[2], p[1]), sub(p[2], p[1]));
+    if (!(twoA > 1e-14 * ee)) return fail(IFL_EDEGENERATE, "zero-area active triangle " + std::to_string(tri_of[c]));
+    area[c] = 0.5 * twoA;
+    if (m.geometry == IFL_GEOM_SPHERE) {
+      V3 cd = add(add(p[0], p[1]), p[2]);
+      cd = scale(cd, 1.0 / norm(cd));
+      V3 e = cross(V3{0.0, 0.0, 1.0}, cd);
+      const double ne = norm(e);
+      e = ne > 1e-300 ? scale(e, 1.0 / ne) : V3{1.0, 0.0, 0.0};
+      eE[c] = e;
+      eN[c] = cross(cd, e);
+    } else {
+      eE[c] = {1.0, 0.0, 0.0};
+      eN[c] = {0.0, 1.0, 0.0};
+    }
+  }
+  // edges of active cells, grouped by vertex pair
+  struct EC {
+    int64_t key;
+    int64_t cell;
+  };
+  std::vector<EC> ec;
+  ec.reserve(3 * nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int32_t* tv = m.triangles + 3 * tri_of[c];
+    for (int k = 0; k < 3; ++k) {
+      int64_t a = tv[k], b = tv[(k + 1) % 3];
+      ec.push_back({std::min(a, b) * m.n_vertices + std::max(a, b), c});
+    }
+  }
+  std::stable_sort(ec.begin(), ec.end(), [](const EC& x, const EC& y) { return x.key < y.key; });
+  Triplets tr;
+  std::vector<double> deg(nc, 0.0);
+  std::vector<int64_t> gp(nc + 1, 0);  // cell graph for the ordering
+  std::vector<std::pair<int64_t, int64_t>> pairs;
+  for (size_t i = 0; i < ec.size();) {
+    size_t j = i;
+    while (j < ec.size() && ec[j].key == ec[i].key) ++j;
+    if (j - i > 2) return fail(IFL_EINVAL, "edge shared by more than two active triangles");
+    if (j - i == 2) pairs.push_back({ec[i].cell, ec[i + 1].cell});
+    i = j;
+  }
+  for (const auto& pr : pairs) {
+    const int64_t c1 = pr.first, c2 = pr.second;
+    // P maps components at c2 into the (east, north) frame at c1
+    const V3 f1[2] = {eE[c1], eN[c1]}, f2[2] = {eE[c2], eN[c2]};
+    for (int r = 0; r < 2; ++r)
+      for (int s = 0; s < 2; ++s) {
+        const double w = -A * dot(f1[r], f2[s]);
+        tr.add(2 * c1 + r, 2 * c2 + s, w);
+        tr.add(2 * c2 + s, 2 * c1 + r, w);
+      }
+    deg[c1] += 1.0;
+    deg[c2] += 1.0;
+    gp[c1 + 1]++;
+    gp[c2 + 1]++;
+  }
+  for (int64_t c = 0; c < nc; ++c)
+    for (int r = 0; r < 2; ++r) tr.add(2 * c + r, 2 * c + r, A * deg[c]);
+  const int64_t n = 2 * nc;
+  std::vector<double> mass(n);
+  for (int64_t c = 0; c < nc; ++c) mass[2 * c] = mass[2 * c + 1] = area[c];
+  std::vector<int64_t> kp;
+  std::vector<int32_t> kc;
+  std::vector<double> kv;
+  to_csr(n, tr, kp, kc, kv);
+  tr = Triplets();
+  std::vector<int64_t> np = kp;
+  std::vector<int32_t> ncol = kc;
+  std::vector<double> nv = kv;
+  for (int32_t r = 1; r < order; ++r) {
+    std::vector<int64_t> tp;
+    std::vector<int32_t> tc;
+    std::vector<double> tvv;
+    spgemm_scaled(n, np, ncol, nv, kp, kc, kv, mass, tp, tc, tvv);
+    np.swap(tp);
+    ncol.swap(tc);
+    nv.swap(tvv);
+  }
+  // locality ordering of cells; both components of a cell stay adjacent
+  std::vector<int64_t> cord(nc);
+  if (reorder) {
+    for (int64_t c = 0; c < nc; ++c) gp[c + 1] += gp[c];
+    std::vector<int32_t> adj(gp[nc]);
+    std::vector<int64_t> fill(gp.begin(), gp.end() - 1);
+    for (const auto& pr : pairs) {
+      adj[fill[pr.first]++] = (int32_t)pr.second;
+      adj[fill[pr.second]++] = (int32_t)pr.first;
+    }
+    cord = rcm(nc, gp, adj);
+  } else {
+    std::iota(cord.begin(), cord.end(), 0);
+  }
+  std::vector<int64_t> ord(n);
+  for (int64_t c = 0; c < nc; ++c) {
+    ord[2 * c] = 2 * cord[c];
+    ord[2 * c + 1] = 2 * cord[c] + 1;
+  }
+  out->placement = IFL_CELL_VECTOR;
+  out->order = order;
+  out->n = n;
+  out->n_components = 2;
+  out->field_len = 2 * m.n_triangles;
+  permute_csr(n, ord, np, ncol, nv, out->row_ptr, out->col, out->val);
+  out->mass.resize(n);
+  out->entity.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    out->mass[i] = mass[ord[i]];
+    const int64_t c = ord[i] / 2, comp = ord[i] % 2;
+    out->entity[i] = 2 * tri_of[c] + comp;
+  }
+  return IFL_OK;
+}
+
+}  // namespace
+
+ifl_status build_operator(const ifl_mesh& mesh, int32_t placement, int32_t order, double cell_A,
+                          int32_t reorder, HostOperator* out) {
+  ifl_status st = validate(mesh);
+  if (st != IFL_OK) return st;
+  if (order < 1 || order > 2) return fail(IFL_EUNSUPPORTED, "filter order n must be 1 or 2");
+  if (placement == IFL_VERTEX_SCALAR) {
+    st = build_vertex_scalar(mesh, order, reorder, out);
+  } else if (placement == IFL_CELL_VECTOR) {
+    if (!(cell_A > 0) || !std::isfinite(cell_A)) return fail(IFL_EINVAL, "cell_A must be positive and finite");
+    st = build_cell_vector(mesh, order, cell_A, reorder, out);
+  } else if (placement >= IFL_VORONOI_SCALAR && placement <= IFL_VERTEX_VECTOR) {
+    return fail(IFL_EUNSUPPORTED, "placement not implemented (vertex scalars and cell vectors are)");
+  } else {
+    return fail(IFL_EINVAL, "unknown placement");
+  }
+  if (st != IFL_OK) return st;
+  uint64_t h = 1469598103934665603ull;
+  const int dim = mesh.geometry == IFL_GEOM_SPHERE ? 3 : 2;
+  h = fnv1a(h, mesh.coords, sizeof(double) * dim * mesh.n_vertices);
+  h = fnv1a(h, mesh.triangles, sizeof(int32_t) * 3 * mesh.n_triangles);
+  if (mesh.wet) h = fnv1a(h, mesh.wet, (size_t)mesh.n_vertices);
+  h = fnv1a(h, &placement, sizeof placement);
+  h = fnv1a(h, &order, sizeof order);
+  out->mesh_hash = h;
+  return IFL_OK;
+}
+
+void pack_sell(const HostOperator& op, SellPack* out) {
+  const int64_t n = op.n;
+  const int64_t ns = (n + 63) / 64;
+  out->n = n;
+  out->n_slices = ns;
+  out->slice_ptr.assign(ns + 1, 0);
+  out->diag.assign(ns * 64, 0.0);
+  out->mass.assign(ns * 64, 0.0);
+  out->max_width = 0;
+  out->stored_offdiag = 0;
+  std::vector<int32_t> width(ns, 0);
+  for (int64_t s = 0; s < ns; ++s) {
+    int32_t w = 0;
+    for (int64_t r = s * 64; r < std::min(n, s * 64 + 64); ++r) {
+      int32_t len = 0;
+      for (int64_t e = op.row_ptr[r]; e < op.row_ptr[r + 1]; ++e) len += (op.col[e] != r);
+      w = std::max(w, len);
+      out->stored_offdiag += len;
+    }
+    width[s] = w;
+    out->max_width = std::max(out->max_width, w);
+    out->slice_ptr[s + 1] = out->slice_ptr[s] + 64 * (int64_t)w;
+  }
+  out->col.assign(out->slice_ptr[ns], 0);
+  out->val.assign(out->slice_ptr[ns], 0.0);
+  for (int64_t s = 0; s < ns; ++s) {
+    for (int64_t l = 0; l < 64; ++l) {
+      const int64_t r = s * 64 + l;
+      const int32_t self = (int32_t)std::min(r, n - 1);
+      int32_t k = 0;
+      if (r < n) {
+        out->mass[r] = op.mass[r];
+        for (int64_t e = op.row_ptr[r]; e < op.row_ptr[r + 1]; ++e) {
+          if (op.col[e] == r) {
+            out->diag[r] = op.val[e];
+          } else {
+            out->col[out->slice_ptr[s] + 64 * k + l] = op.col[e];
+            out->val[out->slice_ptr[s] + 64 * k + l] = op.val[e];
+            ++k;
+          }
+        }
+      }
+      for (; k < width[s]; ++k) {
+        out->col[out->slice_ptr[s] + 64 * k + l] = self;
+        out->val[out->slice_ptr[s] + 64 * k + l] = 0.0;
+      }
+    }
+  }
+}
+
+}  // namespace ifl

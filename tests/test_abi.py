@@ -1,0 +1,187 @@
+"""C-ABI and host-side prepare checks (CPU only: no device work).
+
+The library is loaded and every entry point that ``include/ifl.h``
+declares must be exported. Host-only handles (``device = -1``) run the
+host prepare code, whose operator is compared with the oracle's."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+ifl = pytest.importorskip("paper_2404_07398_amd")
+
+
+def _lib_or_skip():
+    if not os.path.exists(ifl.LIB_PATH):
+        pytest.skip("libifl.so not built")
+    return ifl.lib()
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "ifl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(ifl_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_symbols_exported():
+    L = _lib_or_skip()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in ifl.h but not exported"
+    assert set(names) == set(ifl.EXPORTED)
+
+
+def test_default_options():
+    _lib_or_skip()
+    o = ifl.default_options()
+    assert o.gamma == 0.5 and o.rtol == 1e-12 and o.precision == ifl.IFL_FP64
+    assert abs(o.cell_A - np.sqrt(3)) < 1e-15 and o.reorder == 1 and o.device == 0
+
+
+def _host_handle(mesh, placement=ifl.IFL_VERTEX_SCALAR, n=1, **kw):
+    return ifl.prepare_mesh(mesh, placement, n, device=-1, **kw)
+
+
+def _to_oracle_numbering(h, op_or):
+    """Library CSR (internal order) -> scipy matrix in the oracle's dof order."""
+    rp, col, val, mass, ent = h.export_operator()
+    n = rp.size - 1
+    if hasattr(op_or, "verts"):
+        dof = op_or.dof_of[ent]
+    else:
+        cell_dof = np.full(op_or.n_cells_total, -1)
+        cell_dof[op_or.cells] = np.arange(op_or.cells.size)
+        dof = 2 * cell_dof[ent // 2] + ent % 2
+    assert np.all(dof >= 0)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    K = sp.coo_matrix((val, (dof[rows], dof[col])), shape=(n, n)).tocsr()
+    M = np.zeros(n)
+    M[dof] = mass
+    return K, M, rp, col, val
+
+
+def _meshes():
+    yield "periodic64", W.split_square(64, jitter=0.2)
+    s = W.icosphere(4, jitter=0.1)
+    yield "sphere-L4-mask", s.with_mask(W.land_mask(s, 0.3))
+    yield "planar-patch", W.split_square(10, jitter=0.2, periodic=False, seed=3)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("name,mesh", list(_meshes()))
+def test_prepare_matches_oracle_vertex(name, mesh, order):
+    _lib_or_skip()
+    h = _host_handle(mesh, n=order)
+    op = O.scalar_operator(mesh, order)
+    K, M, rp, col, val = _to_oracle_numbering(h, op)
+    assert h.num_dofs == op.A.size and h.field_length == mesh.n_vertices
+    assert abs(K - op.Kn).max() <= 1e-13 * abs(op.Kn).max()
+    assert np.max(np.abs(M - op.A) / op.A) < 1e-14
+    # bitwise symmetric in the library's own storage
+    n = rp.size - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    Kl = sp.coo_matrix((val, (rows, col)), shape=(n, n)).tocsr()
+    assert (Kl != Kl.T).nnz == 0
+    h.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_prepare_matches_oracle_cell_vector(order):
+    _lib_or_skip()
+    s = W.icosphere(3, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    h = _host_handle(s, ifl.IFL_CELL_VECTOR, order)
+    vo = O.vector_operator(s, order)
+    K, M, *_ = _to_oracle_numbering(h, vo)
+    assert h.field_length == 2 * s.n_triangles
+    assert abs(K - vo.Kn).max() <= 1e-13 * abs(vo.Kn).max()
+    assert np.max(np.abs(M - vo.A) / vo.A) < 1e-14
+    h.close()
+
+
+def test_ordering_is_a_permutation_and_local():
+    _lib_or_skip()
+    s = W.icosphere(5, jitter=0.1)
+    h = _host_handle(s)
+    rp, col, val, mass, ent = h.export_operator()
+    assert np.array_equal(np.sort(ent), np.arange(s.n_vertices))
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    bw_rcm = np.max(np.abs(col - rows))
+    h0 = _host_handle(s, reorder=0)
+    rp0, col0, *_ = h0.export_operator()
+    rows0 = np.repeat(np.arange(rp0.size - 1), np.diff(rp0))
+    assert bw_rcm < np.max(np.abs(col0 - rows0)) / 4
+    h.close()
+    h0.close()
+
+
+def test_prepare_errors():
+    _lib_or_skip()
+    m = W.split_square(8, jitter=0.1)
+    bad = m.tris.copy()
+    bad[3, 1] = m.n_vertices + 5
+    with pytest.raises(ifl.IflError) as e:
+        ifl.ifl_prepare(m.coords, bad, m.geometry, period=m.period, device=-1)
+    assert e.value.status == ifl.IFL_EINVAL
+    deg = m.tris.copy()
+    deg[0, 1] = deg[0, 0]
+    with pytest.raises(ifl.IflError) as e:
+        ifl.ifl_prepare(m.coords, deg, m.geometry, period=m.period, device=-1)
+    assert e.value.status == ifl.IFL_EDEGENERATE
+    c = m.coords.copy()
+    c[2, 0] = np.nan
+    with pytest.raises(ifl.IflError) as e:
+        ifl.ifl_prepare(c, m.tris, m.geometry, period=m.period, device=-1)
+    assert e.value.status == ifl.IFL_EINVAL
+    for placement in (ifl.IFL_VORONOI_SCALAR, ifl.IFL_CIRCUMCENTER_SCALAR, ifl.IFL_VERTEX_VECTOR):
+        with pytest.raises(ifl.IflError) as e:
+            ifl.prepare_mesh(m, placement, 1, device=-1)
+        assert e.value.status == ifl.IFL_EUNSUPPORTED
+    with pytest.raises(ifl.IflError) as e:
+        ifl.prepare_mesh(m, ifl.IFL_VERTEX_SCALAR, 3, device=-1)
+    assert e.value.status == ifl.IFL_EUNSUPPORTED
+    dry = m.with_mask(np.zeros(m.n_vertices, np.uint8))
+    with pytest.raises(ifl.IflError) as e:
+        ifl.prepare_mesh(dry, ifl.IFL_VERTEX_SCALAR, 1, device=-1)
+    assert e.value.status == ifl.IFL_EDEGENERATE
+
+
+def test_host_only_handle_refuses_solves():
+    _lib_or_skip()
+    m = W.split_square(8, jitter=0.1)
+    h = _host_handle(m)
+    with pytest.raises(ifl.IflError) as e:
+        h.filter(np.zeros(m.n_vertices), [1.0])
+    assert e.value.status == ifl.IFL_EDEVICE
+    with pytest.raises(ifl.IflError) as e:
+        h.filter(np.zeros(m.n_vertices), [-1.0])
+    assert e.value.status == ifl.IFL_EINVAL
+    h.close()
+
+
+def test_save_load_roundtrip(tmp_path):
+    _lib_or_skip()
+    s = W.icosphere(3, jitter=0.1)
+    h = _host_handle(s, n=2)
+    p = str(tmp_path / "h.ifl")
+    h.save(p)
+    h2 = ifl.ifl_load(p, device=-1)
+    a = h.export_operator()
+    b = h2.export_operator()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    open(p, "r+b").truncate(100)
+    with pytest.raises(ifl.IflError) as e:
+        ifl.ifl_load(p, device=-1)
+    assert e.value.status == ifl.IFL_EIO
+    h.close()
+    h2.close()
