@@ -114,7 +114,14 @@ struct DeviceState {
 };
 
 // partial-array offsets (in units of G)
-enum { P_PQ = 0, P_RZ0 = 1, P_RZ1 = 2, P_RR0 = 3, P_RR1 = 4, P_BB = 5, P_RES = 6, P_EN = 7, P_COUNT = 8 };
+enum { P_PQ = 0, P_RZ0 = 1, P_RZ1 = 2, P_RR0 = 3, P_RR1 = 4, P_BB = 5, P_RES = 6, P_EN = 7, P_FL = 8, P_COUNT = 9 };
+
+// Attainable accuracy of an FP64 residual r = b - S x: its rounding error is
+// bounded by a small multiple of u ||(|b| + |S| |x|)||, u = 2^-53. A true
+// residual at or below kFloorUnits * u times that norm cannot be reduced
+// further in FP64 and counts as converged.
+constexpr double kUnitRoundoff = 1.1102230246251565e-16;
+constexpr double kFloorUnits = 8.0;
 
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int logical_block(int G) {
@@ -196,16 +203,17 @@ template <>
 __device__ __forceinline__ const float* mval<float>(const Mat& m) { return m.val32; }
 
 // Stopping test shared by the iteration kernels; identical inputs in every
-// block give identical decisions.
+// block give identical decisions. 0 = iterate, 1 = stop. In mixed precision
+// only an FP64 true residual may stop the solve: a recursive FP32 residual
+// below the tolerance keeps iterating until the next residual replacement
+// (k_fold / k_replace) confirms it. Every iterating launch writes the
+// partials of the next parity, so the partials a kernel reads are never
+// stale.
 template <bool MIXED>
-__device__ __forceinline__ int stop_state(const Scalars* sc, double rr) {
-  // 0 = iterate, 1 = stop (converged / finished), 2 = idle (mixed: waiting
-  // for an FP64 residual to confirm convergence)
+__device__ __forceinline__ int stop_state(const Scalars* sc, double rr, double floor2) {
   if (sc->done) return 1;
-  if (rr <= sc->tol2) {
-    if (!MIXED || sc->rr_true) return 1;
-    return 2;
-  }
+  if (!MIXED) return rr <= sc->tol2 ? 1 : 0;
+  if (sc->rr_true && rr <= fmax(sc->tol2, floor2)) return 1;
   return 0;
 }
 
@@ -252,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Mat m, Vecs<T> v, double* x, fl
     part[P_RZ0 * G + lb] = acc3[0];
     part[P_RR0 * G + lb] = acc3[1];
     part[P_BB * G + lb] = acc3[2];
+    part[P_FL * G + lb] = 0.0;
     // rho_{-1} = +inf makes beta_0 = 0
     part[P_RZ1 * G + lb] = lb == 0 ? INFINITY : 0.0;
     if (lb == 0) {
@@ -290,10 +299,15 @@ __global__ __launch_bounds__(kBlock) void k_dir_spmv(Mat m, Vecs<T> v, double* p
   const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
   const double rz_old = reduce_partials(part + (P_RZ0 + (parity ^ 1)) * G, G, lw, &lo);
   const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
-  const int st = stop_state<MIXED>(sc, rr);
+  double floor2 = 0.0;
+  if (MIXED && sc->rr_true) {
+    const double f = reduce_partials(part + P_FL * G, G, lw, &lo);
+    floor2 = f * (kFloorUnits * kUnitRoundoff) * (kFloorUnits * kUnitRoundoff);
+  }
+  const int st = stop_state<MIXED>(sc, rr, floor2);
   const int lb = logical_block(G);
   if (st != 0) {
-    if (lb == 0 && threadIdx.x == 0 && st == 1 && sc->done == 0) {
+    if (lb == 0 && threadIdx.x == 0 && sc->done == 0) {
       sc->done = 1;
       sc->rr_last = rr;
     }
@@ -344,11 +358,10 @@ __global__ __launch_bounds__(kBlock) void k_update(Mat m, Vecs<T> v, double* x, 
   __shared__ double lw[kWavesPerBlock];
   __shared__ double lo;
   __shared__ double lds[2][kWavesPerBlock];
+  // k_dir_spmv of this iteration took the stopping decision (and set done)
+  if (sc->done) return;
   const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
-  const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
-  const int st = stop_state<MIXED>(sc, rr);
   const int lb = logical_block(G);
-  if (st != 0) return;
   const double pq = reduce_partials(part + P_PQ * G, G, lw, &lo);
   const double alpha = rz / pq;
   if (!(pq > 0.0) || !isfinite(alpha)) {
@@ -409,36 +422,42 @@ __global__ __launch_bounds__(kBlock) void k_fold(Mat m, double* x, float* xacc, 
 // partial is the FP64 one, so the next stopping test sees a true residual.
 __global__ __launch_bounds__(kBlock) void k_replace(Mat m, Vecs<float> v, const double* x, const double* phi,
                                                     double* part, Scalars* sc, int parity, int G, int spb) {
-  __shared__ double lds[2][kWavesPerBlock];
+  __shared__ double lds[3][kWavesPerBlock];
   if (!sc->update_now) return;
   const int lb = logical_block(G);
   const double c = sc->c;
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  double acc[2] = {0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
   const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
   for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
     const int64_t row = s * kWave + lane;
     if (row >= m.n) continue;
     const int64_t base = m.sptr[s];
     const int w = (int)((m.sptr[s + 1] - base) / kWave);
-    double a = 0.0;
+    double a = 0.0, aa = 0.0;
     for (int k = 0; k < w; ++k) {
       const int64_t e = base + (int64_t)k * kWave + lane;
-      a += m.val64[e] * x[m.col[e]];
+      const double t = m.val64[e] * x[m.col[e]];
+      a += t;
+      aa += fabs(t);
     }
     const double xi = x[row];
-    const double r64 = m.mass64[row] * (phi[row] - xi) - c * (m.kdiag64[row] * xi + a);
+    const double mi = m.mass64[row], kd = m.kdiag64[row];
+    const double r64 = mi * (phi[row] - xi) - c * (kd * xi + a);
+    const double mag = fabs(mi * phi[row]) + fabs(mi * xi) + c * (fabs(kd * xi) + aa);
     const float rt = (float)r64;
     const float zt = rt / v.d[row];
     v.r[row] = rt;
     v.z[row] = zt;
     acc[0] += (double)rt * (double)zt;
     acc[1] += r64 * r64;
+    acc[2] += mag * mag;
   }
-  block_sum<2>(acc, lds);
+  block_sum<3>(acc, lds);
   if (threadIdx.x == 0) {
     part[(P_RZ0 + parity) * G + lb] = acc[0];
     part[(P_RR0 + parity) * G + lb] = acc[1];
+    part[P_FL * G + lb] = acc[2];
     if (lb == 0) {
       sc->rr_true = 1;
       sc->updates += 1;
