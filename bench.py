@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--mask", type=float, default=0.4)
     ap.add_argument("--fields", type=int, default=64)
     ap.add_argument("--scales", type=int, default=30)
+    ap.add_argument("--field-block", type=int, default=16, help="fields per ifl_filter call")
+    ap.add_argument("--plain-fields", type=int, default=4,
+                    help="fields for the plain FP64 single-column comparison (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
@@ -118,14 +121,16 @@ def main():
     h = ifl.prepare_mesh(mesh, ifl.IFL_VERTEX_SCALAR, 1, precision=precision, batch=args.batch, device=0)
     log(f"prepare {time.time() - t0:.1f}s, dofs={h.num_dofs}")
     fields = torch.from_numpy(fields_h).to(dev)
-    out = torch.zeros((1, ks.size, h.field_length), dtype=torch.float64, device=dev)
+    fb = max(1, min(args.fields, args.field_block))
+    out = torch.zeros((fb, ks.size, h.field_length), dtype=torch.float64, device=dev)
     n_solves = args.fields * ks.size
 
-    def step(profile: bool):
-        h.set_options(precision=precision, batch=args.batch, profile=int(profile))
+    def step(profile: bool, batch: int = args.batch, prec: int = precision, n_fields: int = args.fields):
+        h.set_options(precision=prec, batch=batch, profile=int(profile))
         iters = 0
-        for f in range(args.fields):
-            _, st = h.filter(fields[f], ks, out=out)
+        for f0 in range(0, n_fields, fb):
+            nf = min(fb, n_fields - f0)
+            _, st = h.filter(fields[f0:f0 + nf], ks, out=out[:nf])
             iters += sum(s.iterations for s in st)
         return iters
 
@@ -167,6 +172,7 @@ def main():
             "dofs": h.num_dofs,
             "solves_per_step": n_solves,
             "precision": args.precision,
+            "batch": args.batch if args.batch else "auto (32)",
             "rtol": 1e-12,
             "mean_cg_iterations": round(total_it / (n_solves * args.steps), 2),
         },
@@ -177,12 +183,26 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "kernel": "k_dir_spmv",
+            "kernel": "kb_dir_spmv" if args.batch != 1 else "k_dir_spmv",
             "launches": launches,
             "mean_launch_us": round(mean_s * 1e6, 3),
             "bytes_per_launch": bytes_per,
         },
     }
+    if args.plain_fields > 0:
+        # the plain FP64 path, one column at a time, on a subset of the fields
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        it = step(False, batch=1, prec=ifl.IFL_FP64, n_fields=args.plain_fields)
+        torch.cuda.synchronize()
+        el_p = time.perf_counter() - t
+        res["plain_fp64_single_column"] = {
+            "value": round(args.plain_fields * ks.size / el_p, 3),
+            "unit": "solves/s",
+            "sample": f"{args.plain_fields} fields x {ks.size} scales, FP64, one column per solve",
+            "mean_cg_iterations": round(it / (args.plain_fields * ks.size), 2),
+        }
+        res["speedup_vs_plain_fp64"] = round(value / res["plain_fp64_single_column"]["value"], 3)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(mesh, fields_h, ks, args.cpu_budget)

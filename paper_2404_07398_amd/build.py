@@ -19,7 +19,7 @@ INC = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libifl.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["prepare.cpp", "api.cpp", "server.cpp", "device.hip"]
+SOURCES = ["prepare.cpp", "api.cpp", "server.cpp", "device.hip", "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 

@@ -1,0 +1,97 @@
+// Multi-RHS batched solver: shared declarations (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace ifl {
+
+// Per-column CG state of one slot (device memory; mirrored to pinned host
+// memory by batch_read_slots).
+struct BSlot {
+  double c;         // gamma / k^(2n)
+  double alpha, beta, rho, rho_prev;
+  double rr;        // current ||r||^2 (recursive, or FP64 true after a replacement)
+  double tol2;      // rtol^2 ||M phi||^2
+  double bb;        // ||M phi||^2
+  double rr_ref;    // mixed: ||r||^2 at the last replacement
+  double res2;      // final true ||M phi - S x||^2
+  double energy2;   // final sum M x^2
+  double pad0;
+  int32_t active;   // slot holds a column
+  int32_t done;     // 0 running, 1 converged, 2 breakdown, 3 max_iter
+  int32_t iters;    // CG iterations of this column
+  int32_t updates;  // mixed: FP64 residual replacements
+  int32_t rr_true;  // mixed: rr is an FP64 true residual
+  int32_t fold;     // mixed: fold + replace this iteration
+  int32_t pad1, pad2;
+};
+
+// The handle's matrix as the batched kernels see it (device pointers).
+struct BatchMatrix {
+  int64_t n = 0, n_slices = 0, n_pad = 0;
+  const int64_t* sptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val64 = nullptr;
+  const float* val32 = nullptr;
+  const double* kdiag = nullptr;
+  const double* mass = nullptr;
+  const int64_t* entity = nullptr;
+  int G = 1;  // logical blocks of the row kernels
+};
+
+struct BatchParams {
+  int max_iter = 20000;
+  int fold_every = 4;     // mixed: check for a residual replacement every k iterations
+  double delta2 = 1e-4;   // mixed: replace when ||r||^2 fell by this factor
+  hipEvent_t ev_begin = nullptr;  // if set: recorded around the first SpMV launch
+  hipEvent_t ev_end = nullptr;
+};
+
+// Algorithmic bytes of one batched SpMV launch with 'live' active columns:
+// the sliced-ELL stream, mass and diagonal, and per live column the reads of
+// z and p (each once) and the writes of p and q.
+double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, int live);
+
+// Device work space of one tile of R slots (vectors rows x R).
+struct BatchWork {
+  int R = 0;
+  bool mixed = false;
+  float *r32 = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *xacc = nullptr;
+  double *r64 = nullptr, *z64 = nullptr, *p64[2] = {nullptr, nullptr}, *q64 = nullptr;
+  double* x = nullptr;    // FP64 solution, rows x R
+  double* phi = nullptr;  // FP64 fields, rows x R
+  double* part = nullptr; // per-(quantity, column, block) partial sums
+  BSlot* slots = nullptr;
+  BSlot* slots_host = nullptr;  // pinned
+  int* flag = nullptr;
+};
+
+// Scale factors c_j of the slots being initialised (kernel argument).
+struct SlotScales {
+  double c[64];
+};
+
+size_t batch_bytes(int64_t n_pad, int R, bool mixed);
+ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed);
+void batch_free(BatchWork* w);
+
+ifl_status batch_clear_flag(BatchWork& w, hipStream_t s);
+// Gather one field (caller numbering, device) into column 'slot' of phi;
+// non-finite entries raise the device flag (read with batch_check_flag).
+ifl_status batch_load_column(const BatchMatrix& bm, BatchWork& w, int slot, const double* field_dev, hipStream_t s);
+ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad);
+// Start the columns in 'mask' (their phi columns loaded) at scales cs.
+ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const SlotScales& cs, double rtol,
+                      hipStream_t s);
+ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s);
+// Write x of the columns in 'mask' to out[slot] (caller numbering; dry
+// entries untouched) and compute their true residual and energy.
+ifl_status batch_finish(const BatchMatrix& bm, BatchWork& w, uint64_t mask, double* const* out, hipStream_t s);
+ifl_status batch_read_slots(BatchWork& w, hipStream_t s);
+ifl_status batch_release(BatchWork& w, uint64_t mask, hipStream_t s);
+
+}  // namespace ifl

@@ -28,11 +28,13 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "internal.h"
 
 namespace ifl {
@@ -111,6 +113,13 @@ struct DeviceState {
   std::vector<hipEvent_t> ev;
   int64_t prof_launches = 0;
   double prof_ms = 0.0;
+  double prof_bytes = 0.0;  // summed algorithmic bytes of the timed launches
+  // batched engine work space (allocated on first use)
+  BatchWork bw;
+  double* field_stage = nullptr;  // device copy of host fields
+  int64_t field_stage_len = 0;
+  double* col_stage = nullptr;    // per-slot outputs for host destinations
+  int64_t col_stage_len = 0;
 };
 
 // partial-array offsets (in units of G)
@@ -296,6 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_dir_spmv(Mat m, Vecs<T> v, double* p
   __shared__ double lw[kWavesPerBlock];
   __shared__ double lo;
   __shared__ double lds[1][kWavesPerBlock];
+  if (sc->done) return;  // finished solves cost one scalar load per launch
   const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
   const double rz_old = reduce_partials(part + (P_RZ0 + (parity ^ 1)) * G, G, lw, &lo);
   const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
@@ -402,9 +412,13 @@ __global__ __launch_bounds__(kBlock) void k_fold(Mat m, double* x, float* xacc, 
                                                  int parity, double delta2, int G, int spb) {
   __shared__ double lw[kWavesPerBlock];
   __shared__ double lo;
-  const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
   const int lb = logical_block(G);
-  const bool trig = !sc->done && !sc->rr_true && (rr <= sc->tol2 || rr <= delta2 * sc->rr_ref);
+  if (sc->done || sc->rr_true) {
+    if (lb == 0 && threadIdx.x == 0) sc->update_now = 0;
+    return;
+  }
+  const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
+  const bool trig = rr <= sc->tol2 || rr <= delta2 * sc->rr_ref;
   if (lb == 0 && threadIdx.x == 0) sc->update_now = trig ? 1 : 0;
   if (!trig) return;
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
@@ -618,7 +632,9 @@ ifl_status device_create(Handle* h) {
 
   // launch geometry: logical blocks own contiguous slice ranges
   const int64_t ns = m.n_slices;
-  int G = (int)std::min<int64_t>(kMaxBlocks, (ns + kWavesPerBlock - 1) / kWavesPerBlock);
+  int max_blocks = kMaxBlocks;
+  if (const char* e = std::getenv("IFL_MAX_BLOCKS")) max_blocks = std::max(8, std::min(4096, std::atoi(e)));
+  int G = (int)std::min<int64_t>(max_blocks, (ns + kWavesPerBlock - 1) / kWavesPerBlock);
   if (G >= kXcd) G = (G / kXcd) * kXcd;
   d->G = std::max(1, G);
   d->spb = (int)((ns + d->G - 1) / d->G);
@@ -650,6 +666,9 @@ void device_destroy(Handle* h) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (d->w.sc_host) (void)hipHostFree(d->w.sc_host);
+  batch_free(&d->bw);
+  if (d->field_stage) (void)hipFree(d->field_stage);
+  if (d->col_stage) (void)hipFree(d->col_stage);
   for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
   if (d->own_stream) (void)hipStreamDestroy(d->own_stream);
   delete d;
@@ -736,9 +755,9 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
   bool finished = false;
   int pending = -1;  // chunk whose scalars are in flight
   int32_t iters_seen = 0;
-  std::vector<int> prof_pairs;
+  int prof_pos[2] = {-1, -1};
   if (prof) {
-    ifl_status e = ensure_events(d, 4 * chunk);
+    ifl_status e = ensure_events(d, 4);
     if (e != IFL_OK) return e;
   }
   hipEvent_t done_ev[2];
@@ -747,13 +766,19 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
   ifl_status result = IFL_OK;
   while (!finished) {
     const int slot = chunk_id & 1;
-    int npairs = 0;
+    // profiling samples one SpMV launch per chunk (bracketing every launch
+    // with events would itself slow the loop down)
+    const int pos = chunk_id % chunk;
+    prof_pos[slot] = -1;
     for (int j = 0; j < chunk && launched < max_iter; ++j) {
       const int parity = launched & 1;
-      if (prof) IFL_HIP(hipEventRecord(d->ev[2 * npairs + 2 * chunk * slot], s));
+      const bool sample = prof && j == pos;
+      if (sample) IFL_HIP(hipEventRecord(d->ev[2 * slot], s));
       k_dir_spmv<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.part, w.sc, parity, G, spb);
-      if (prof) IFL_HIP(hipEventRecord(d->ev[2 * npairs + 1 + 2 * chunk * slot], s));
-      ++npairs;
+      if (sample) {
+        IFL_HIP(hipEventRecord(d->ev[2 * slot + 1], s));
+        prof_pos[slot] = j;
+      }
       k_update<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, w.part, w.sc, parity, G, spb);
       ++launched;
       if (MIXED && (launched % fold_every == 0 || launched == max_iter)) {
@@ -766,8 +791,6 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
     IFL_HIP(hipGetLastError());
     IFL_HIP(hipMemcpyAsync(&w.sc_host[slot], w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     IFL_HIP(hipEventRecord(done_ev[slot], s));
-    prof_pairs.resize(2);
-    prof_pairs[slot] = npairs;
     const bool capped = launched >= max_iter;
     // wait for the previous chunk (the current one keeps the GPU busy)
     int wait_chunk = capped ? chunk_id : pending;
@@ -775,15 +798,14 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
       const int ws = wait_chunk & 1;
       IFL_HIP(hipEventSynchronize(done_ev[ws]));
       const Scalars& sh = w.sc_host[ws];
-      if (prof) {
-        // count only launches that iterated (iterations are sequential)
-        const int real = std::max(0, std::min(prof_pairs[ws], sh.iters - iters_seen));
-        for (int p = 0; p < real; ++p) {
-          float ms = 0.f;
-          IFL_HIP(hipEventElapsedTime(&ms, d->ev[2 * p + 2 * chunk * ws], d->ev[2 * p + 1 + 2 * chunk * ws]));
-          d->prof_ms += ms;
-        }
-        d->prof_launches += real;
+      // count the sample only if that launch iterated (iterations within a
+      // chunk come first, finished launches after)
+      if (prof && prof_pos[ws] >= 0 && prof_pos[ws] < sh.iters - iters_seen) {
+        float ms = 0.f;
+        IFL_HIP(hipEventElapsedTime(&ms, d->ev[2 * ws], d->ev[2 * ws + 1]));
+        d->prof_ms += ms;
+        d->prof_launches += 1;
+        d->prof_bytes += spmv_bytes(M, sizeof(T));
       }
       iters_seen = sh.iters;
       if (sh.done) finished = true;
@@ -820,10 +842,12 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
 
 }  // namespace
 
-ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales, const double* k,
+namespace {
+
+// One column at a time (the plain path, and single solves).
+ifl_status filter_single(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales, const double* k,
                          double* out, ifl_solve_stats* stats, double* energy) {
   DeviceState* d = h->dev;
-  IFL_HIP(hipSetDevice(d->device));
   hipStream_t s = stream_of(h);
   const int64_t L = h->op.field_len;
   const bool fdev = is_device_ptr(fields);
@@ -857,6 +881,188 @@ ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int3
   return IFL_OK;
 }
 
+BatchMatrix batch_matrix(DeviceState* d, int R) {
+  BatchMatrix bm;
+  const DevMatrix& m = d->m;
+  bm.n = m.n;
+  bm.n_slices = m.n_slices;
+  bm.n_pad = m.n_pad;
+  bm.sptr = m.sptr;
+  bm.col = m.col;
+  bm.val64 = m.val64;
+  bm.val32 = m.val32;
+  bm.kdiag = m.kdiag64;
+  bm.mass = m.mass64;
+  bm.entity = m.entity;
+  const int64_t tasks = m.n_slices * (kWave / R);
+  int G = (int)std::min<int64_t>(kMaxBlocks, (tasks + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (G >= kXcd) G = (G / kXcd) * kXcd;
+  bm.G = std::max(1, G);
+  return bm;
+}
+
+ifl_status ensure_batch(DeviceState* d, int R, bool mixed) {
+  if (d->bw.R == R && d->bw.mixed == mixed && d->bw.slots) return IFL_OK;
+  batch_free(&d->bw);
+  return batch_alloc(&d->bw, batch_matrix(d, R), R, mixed);
+}
+
+// Many columns at once: slots of a tile of R columns are filled from the
+// (field, scale) list, iterated together, and refilled as columns finish.
+ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fields, int32_t n_scales,
+                          const double* k, double* out, ifl_solve_stats* stats, double* energy) {
+  DeviceState* d = h->dev;
+  hipStream_t s = stream_of(h);
+  const int64_t L = h->op.field_len;
+  const bool mixed = h->opt.precision == IFL_MIXED;
+  ifl_status st = ensure_batch(d, R, mixed);
+  if (st != IFL_OK) return st;
+  BatchWork& w = d->bw;
+  const BatchMatrix bm = batch_matrix(d, R);
+  // fields on the device
+  const double* fdev = fields;
+  if (!is_device_ptr(fields)) {
+    const int64_t need = (int64_t)n_fields * L;
+    if (d->field_stage_len < need) {
+      if (d->field_stage) (void)hipFree(d->field_stage);
+      d->field_stage = nullptr;
+      d->field_stage_len = 0;
+      if ((st = dalloc(&d->field_stage, (size_t)need)) != IFL_OK) return st;
+      d->field_stage_len = need;
+    }
+    IFL_HIP(hipMemcpyAsync(d->field_stage, fields, sizeof(double) * need, hipMemcpyHostToDevice, s));
+    fdev = d->field_stage;
+  }
+  const bool odev = out ? is_device_ptr(out) : false;
+  if (out && !odev && d->col_stage_len < (int64_t)R * L) {
+    if (d->col_stage) (void)hipFree(d->col_stage);
+    d->col_stage = nullptr;
+    d->col_stage_len = 0;
+    if ((st = dalloc(&d->col_stage, (size_t)R * L)) != IFL_OK) return st;
+    d->col_stage_len = (int64_t)R * L;
+  }
+  // columns: larger scales (more iterations) first, fields in order
+  const int64_t ncols = (int64_t)n_fields * n_scales;
+  std::vector<int64_t> order(ncols);
+  for (int64_t i = 0; i < ncols; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return k[a % n_scales] < k[b % n_scales]; });
+  BatchParams prm;
+  prm.max_iter = h->opt.max_iter;
+  std::vector<int64_t> slot_col(R, -1);
+  std::vector<std::chrono::steady_clock::time_point> t_in(R);
+  int64_t next = 0, finished = 0;
+  bool any_notconv = false;
+  const int chunk = 4;
+  while (finished < ncols) {
+    // fill free slots
+    uint64_t mask = 0;
+    SlotScales cs{};
+    if (next < ncols && (st = batch_clear_flag(w, s)) != IFL_OK) return st;
+    for (int j = 0; j < R && next < ncols; ++j) {
+      if (slot_col[j] >= 0) continue;
+      const int64_t col = order[next++];
+      const int64_t f = col / n_scales, sc = col % n_scales;
+      if ((st = batch_load_column(bm, w, j, fdev + f * L, s)) != IFL_OK) return st;
+      cs.c[j] = h->opt.gamma / std::pow(k[sc], 2.0 * h->op.order);
+      slot_col[j] = col;
+      t_in[j] = std::chrono::steady_clock::now();
+      mask |= 1ull << j;
+    }
+    if (mask) {
+      bool bad = false;
+      if ((st = batch_check_flag(w, s, &bad)) != IFL_OK) return st;
+      if (bad) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");
+      if ((st = batch_init(bm, w, mask, cs, h->opt.rtol, s)) != IFL_OK) return st;
+    }
+    BatchParams p = prm;
+    int live = 0;
+    if (h->opt.profile) {
+      if ((st = ensure_events(d, 2)) != IFL_OK) return st;
+      p.ev_begin = d->ev[0];
+      p.ev_end = d->ev[1];
+      for (int j = 0; j < R; ++j)
+        live += slot_col[j] >= 0 && (((mask >> j) & 1ull) || w.slots_host[j].done == 0);
+    }
+    if ((st = batch_iterate(bm, w, chunk, p, s)) != IFL_OK) return st;
+    if ((st = batch_read_slots(w, s)) != IFL_OK) return st;
+    if (h->opt.profile && live > 0) {
+      float ms = 0.f;
+      IFL_HIP(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
+      d->prof_ms += ms;
+      d->prof_launches += 1;
+      d->prof_bytes += batch_spmv_bytes(bm, d->m.nnz_stored, mixed, live);
+    }
+    uint64_t fin = 0;
+    std::vector<double*> dst(R, nullptr);
+    for (int j = 0; j < R; ++j) {
+      if (slot_col[j] < 0 || w.slots_host[j].done == 0) continue;
+      fin |= 1ull << j;
+      if (out) {
+        dst[j] = odev ? out + slot_col[j] * L : d->col_stage + (int64_t)j * L;
+        IFL_HIP(hipMemsetAsync(dst[j], 0, sizeof(double) * L, s));
+      }
+    }
+    if (!fin) continue;
+    if ((st = batch_finish(bm, w, fin, dst.data(), s)) != IFL_OK) return st;
+    if ((st = batch_read_slots(w, s)) != IFL_OK) return st;
+    const auto now = std::chrono::steady_clock::now();
+    for (int j = 0; j < R; ++j) {
+      if (!((fin >> j) & 1ull)) continue;
+      const BSlot& sl = w.slots_host[j];
+      const int64_t col = slot_col[j];
+      const bool ok = sl.done == 1;
+      any_notconv |= !ok;
+      if (stats) {
+        ifl_solve_stats& so = stats[col];
+        so.iterations = sl.iters;
+        so.refinements = sl.updates;
+        so.status = ok ? IFL_OK : IFL_ENOTCONV;
+        so.reserved = 0;
+        so.rel_residual = sl.bb > 0 ? std::sqrt(sl.res2 / sl.bb) : std::sqrt(sl.res2);
+        so.seconds = std::chrono::duration<double>(now - t_in[j]).count();
+      }
+      if (energy) energy[col] = 0.5 * sl.energy2 / d->m.mass_sum;
+      if (out && !odev)
+        IFL_HIP(hipMemcpyAsync(out + col * L, dst[j], sizeof(double) * L, hipMemcpyDeviceToHost, s));
+      slot_col[j] = -1;
+      ++finished;
+    }
+    if ((st = batch_release(w, fin, s)) != IFL_OK) return st;
+  }
+  IFL_HIP(hipStreamSynchronize(s));
+  if (any_notconv) return fail(IFL_ENOTCONV, "at least one column did not converge (see stats)");
+  return IFL_OK;
+}
+
+// Tile width: opt.batch >= 2 fixes R (rounded down to a power of two);
+// auto (0) uses 32 columns, fewer when there are fewer columns, and the
+// single-column path for one column.
+int pick_tile(const Handle* h, int64_t ncols) {
+  const int want = h->opt.batch;
+  if (want == 1) return 1;
+  int R = 1;
+  if (want >= 2) {
+    while (R * 2 <= want && R < 64) R *= 2;
+    return R;
+  }
+  if (ncols <= 1) return 1;
+  R = 32;
+  while (R > 2 && R / 2 >= ncols) R /= 2;
+  return R;
+}
+
+}  // namespace
+
+ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales, const double* k,
+                         double* out, ifl_solve_stats* stats, double* energy) {
+  DeviceState* d = h->dev;
+  IFL_HIP(hipSetDevice(d->device));
+  const int R = pick_tile(h, (int64_t)n_fields * n_scales);
+  if (R <= 1) return filter_single(h, n_fields, fields, n_scales, k, out, stats, energy);
+  return filter_batched(h, R, n_fields, fields, n_scales, k, out, stats, energy);
+}
+
 ifl_status device_apply(Handle* h, double kk, const double* x, double* y) {
   DeviceState* d = h->dev;
   IFL_HIP(hipSetDevice(d->device));
@@ -882,10 +1088,11 @@ ifl_status device_profile_read(Handle* h, int64_t* launches, double* total_ms, d
   DeviceState* d = h->dev;
   if (launches) *launches = d->prof_launches;
   if (total_ms) *total_ms = d->prof_ms;
-  if (bytes) *bytes = spmv_bytes(d->m, h->opt.precision == IFL_MIXED ? 4 : 8);
+  if (bytes) *bytes = d->prof_launches ? d->prof_bytes / d->prof_launches : 0.0;
   if (reset) {
     d->prof_launches = 0;
     d->prof_ms = 0.0;
+    d->prof_bytes = 0.0;
   }
   return IFL_OK;
 }

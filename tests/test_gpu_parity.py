@@ -49,7 +49,7 @@ def test_c1_plain_config(ifl, precision):
     m, phi, ks = _c1()
     op = O.scalar_operator(m, 1)
     ref = O.filter_scalar(op, phi, ks, method="dense")
-    h = _prep(ifl, m, precision=precision)
+    h = _prep(ifl, m, precision=precision, batch=1)
     out, stats = h.filter(phi, ks)
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j in range(len(ks)):
@@ -76,7 +76,7 @@ def test_sphere_masked(ifl, n, precision):
     ks = W.log_scales(s.h, 5)
     op = O.scalar_operator(s, n)
     ref = O.filter_scalar(op, phi, ks)
-    h = _prep(ifl, s, n=n, precision=precision)
+    h = _prep(ifl, s, n=n, precision=precision, batch=1)
     out, stats = h.filter(phi, ks)
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j in range(len(ks)):
@@ -96,7 +96,7 @@ def test_cell_vector(ifl, precision):
     ks = W.log_scales(s.h, 4)
     vo = O.vector_operator(s, 1)
     ref = O.filter_vector(vo, u, ks)
-    h = _prep(ifl, s, placement=1, n=1, precision=precision)
+    h = _prep(ifl, s, placement=1, n=1, precision=precision, batch=1)
     out, stats = h.filter(u, ks)
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j in range(len(ks)):
@@ -138,7 +138,7 @@ def test_device_pointers_and_determinism(ifl):
 
     s, phi = _sphere(5, 0.3)
     ks = W.log_scales(s.h, 3)
-    h = _prep(ifl, s)
+    h = _prep(ifl, s, batch=1)
     host, _ = h.filter(phi, ks)
     host2, _ = h.filter(phi, ks)
     assert np.array_equal(host, host2)
@@ -155,7 +155,7 @@ def test_edge_cases(ifl):
     op = O.scalar_operator(m, 1)
     phi = np.random.default_rng(0).normal(size=m.n_vertices)
     ks = np.array([0.5, 2.0])
-    h = _prep(ifl, m)
+    h = _prep(ifl, m, batch=1)
     out, _ = h.filter(phi, ks)
     ref = O.filter_scalar(op, phi, ks, method="dense")
     assert relative_l2(out[0], ref) < TOL_FP64
@@ -184,7 +184,7 @@ def test_edge_cases(ifl):
     h.close()
     # max_iter reached -> ENOTCONV with the last iterate and stats
     m, phi, ks = _c1()
-    h = _prep(ifl, m, max_iter=3)
+    h = _prep(ifl, m, max_iter=3, batch=1)
     out, st = h.filter(phi, ks[:1], raise_on_notconv=False)
     assert st[0].status == ifl.IFL_ENOTCONV and st[0].iterations == 3
     assert np.all(np.isfinite(out))
@@ -208,23 +208,121 @@ def _oracle_certificate(op, phi, k, x):
     return O.solve.residual_bound(S, op.A, op.A * pd, O.to_dofs(op, x))
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_full_size_level9_certified(ifl, precision):
-    """Level-9 icosphere (2,621,442 vertices), 40% land mask, n = 1: the
-    oracle's own matrix certifies ||x - x*|| / ||x|| for sampled columns."""
-    import torch
-
+@pytest.mark.parametrize("precision,batch", [(0, 1), (1, 1), (1, 32)])
+def test_full_size_level9_certified(ifl, precision, batch):
+    """Level-9 icosphere (2,621,442 vertices), 40% land mask, n = 1, in the
+    launch configuration of the benchmark: the oracle's own matrix
+    certifies ||x - x*|| / ||x|| for sampled columns."""
     s = W.icosphere(9, jitter=0.1)
     s = s.with_mask(W.land_mask(s, 0.4))
     phi = W.sphere_k3_field(s, 1000, n_waves=512, device="cuda")
     ks = W.log_scales(s.h, 30)[[0, 15, 29]]
     op = O.scalar_operator(s, 1)
-    h = _prep(ifl, s, precision=precision)
+    h = _prep(ifl, s, precision=precision, batch=batch)
     out, stats = h.filter(phi, ks)
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j, k in enumerate(ks):
         cert = _oracle_certificate(op, phi, k, out[0, j])
-        print(f"L9 precision={precision} k={k:.3e} certified_err<={cert:.2e} it={stats[j].iterations} "
+        print(f"L9 precision={precision} batch={batch} k={k:.3e} certified_err<={cert:.2e} it={stats[j].iterations} "
               f"upd={stats[j].refinements} t={stats[j].seconds:.3f}s")
         assert cert <= tol
+    h.close()
+
+
+# ------------------------------------------------------------------ batched
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("R", [4, 16, 64])
+def test_batched_c1(ifl, precision, R):
+    """Multi-RHS tiles: 2 fields x 8 scales; R = 4 exercises slot refill,
+    R = 64 leaves most slots empty."""
+    m, phi, ks = _c1()
+    phi2 = W.planar_k3_field(m, 1001)
+    op = O.scalar_operator(m, 1)
+    refs = [O.filter_scalar(op, f, ks, method="dense") for f in (phi, phi2)]
+    h = _prep(ifl, m, precision=precision, batch=R)
+    out, stats = h.filter(np.stack([phi, phi2]), ks)
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    for f in range(2):
+        for j in range(len(ks)):
+            err = relative_l2(out[f, j], refs[f][j])
+            st = stats[f * len(ks) + j]
+            print(f"batched C1 R={R} precision={precision} f={f} j={j} err={err:.2e} it={st.iterations} "
+                  f"upd={st.refinements}")
+            assert err <= tol and st.status == 0
+    h.close()
+
+
+@pytest.mark.parametrize("n", [1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_sphere(ifl, n, precision):
+    s, phi = _sphere(5, 0.3)
+    phi2 = W.sphere_k3_field(s, 1001, n_waves=256)
+    ks = W.log_scales(s.h, 5)
+    op = O.scalar_operator(s, n)
+    refs = [O.filter_scalar(op, f, ks) for f in (phi, phi2)]
+    h = _prep(ifl, s, n=n, precision=precision, batch=8)
+    out, stats = h.filter(np.stack([phi, phi2]), ks)
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    for f in range(2):
+        for j in range(len(ks)):
+            err = relative_l2(out[f, j], refs[f][j])
+            print(f"batched sphere n={n} precision={precision} f={f} j={j} err={err:.2e} "
+                  f"it={stats[f * len(ks) + j].iterations}")
+            assert err <= tol
+            assert np.all(out[f, j][s.wet == 0] == 0.0)
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_cell_vector(ifl, precision):
+    s = W.icosphere(4, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    u = W.sphere_k3_velocity(s, 31, 32, n_waves=256).reshape(-1)
+    ks = W.log_scales(s.h, 4)
+    ref = O.filter_vector(O.vector_operator(s, 1), u, ks)
+    h = _prep(ifl, s, placement=1, n=1, precision=precision, batch=4)
+    out, _ = h.filter(u, ks)
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    for j in range(len(ks)):
+        assert relative_l2(out[0, j], ref[j].reshape(-1)) <= tol
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_alone_equals_in_mix(ifl, precision):
+    """A column's arithmetic does not depend on the other columns of its
+    tile, its slot, or when it entered: bitwise equal results."""
+    s, phi = _sphere(5, 0.3)
+    others = [W.sphere_k3_field(s, 2000 + i, n_waves=128) for i in range(3)]
+    ks = W.log_scales(s.h, 6)
+    h = _prep(ifl, s, n=1, precision=precision, batch=8)
+    alone, st_a = h.filter(phi, ks[2:3])
+    mix, st_m = h.filter(np.stack(others + [phi]), ks)  # phi enters late, after refills
+    assert np.array_equal(alone[0, 0], mix[3, 2])
+    assert st_a[0].iterations == st_m[3 * len(ks) + 2].iterations
+    h.close()
+
+
+def test_batched_edge_cases(ifl):
+    import torch
+
+    m, phi, ks = _c1()
+    h = _prep(ifl, m, precision=1, batch=8)
+    fields = np.stack([phi, np.zeros_like(phi), np.full_like(phi, 1.5)])
+    out, st = h.filter(fields, ks)
+    assert np.all(out[1] == 0.0) and all(st[len(ks) + j].iterations == 0 for j in range(len(ks)))
+    assert np.max(np.abs(out[2] - 1.5)) < 1e-12
+    dout = torch.zeros((3, ks.size, phi.size), dtype=torch.float64, device="cuda")
+    h.filter(torch.from_numpy(fields).cuda(), ks, out=dout)
+    assert np.array_equal(dout.cpu().numpy(), out)
+    bad = fields.copy()
+    bad[2, 7] = np.inf
+    with pytest.raises(ifl.IflError) as e:
+        h.filter(bad, ks)
+    assert e.value.status == ifl.IFL_EINVAL
+    h.close()
+    h = _prep(ifl, m, precision=0, batch=4, max_iter=5)
+    out, st = h.filter(np.stack([phi, phi]), ks[:3], raise_on_notconv=False)
+    assert st[0].status == ifl.IFL_ENOTCONV and st[0].iterations == 5
+    assert np.all(np.isfinite(out))
     h.close()
