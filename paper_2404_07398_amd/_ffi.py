@@ -132,6 +132,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                               "(python -m paper_2404_07398_amd.build)")
+        # PyTorch ships its own HIP runtime under the same soname; loading it
+        # first makes the library bind to that one runtime instead of a second
+        # copy from /opt/rocm (two runtimes in one process break GPU init).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _PROTOS.items():
             f = getattr(L, name)

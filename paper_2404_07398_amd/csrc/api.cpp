@@ -41,8 +41,6 @@ static ifl_status check_k(int32_t n_scales, const double* k, bool ascending) {
 
 using namespace ifl;
 
-struct ifl_handle : ifl::Handle {};
-
 extern "C" {
 
 void ifl_default_options(ifl_options* opt) {

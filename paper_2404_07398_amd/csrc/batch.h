@@ -94,4 +94,9 @@ ifl_status batch_finish(const BatchMatrix& bm, BatchWork& w, uint64_t mask, doub
 ifl_status batch_read_slots(BatchWork& w, hipStream_t s);
 ifl_status batch_release(BatchWork& w, uint64_t mask, hipStream_t s);
 
+// The handle's matrix for tiles of R columns, and the sum of its mass
+// (both need a device handle; defined with the device state).
+BatchMatrix handle_batch_matrix(Handle* h, int R);
+double handle_mass_sum(const Handle* h);
+
 }  // namespace ifl

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, BSlot* slot
   T* __restrict__ pout = par ? v.p0 : v.p1;
   const T* __restrict__ z = v.z;
   const T* __restrict__ val = bval<T>(m);
-  const int64_t ntasks = m.n_slices * RPW;
+  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
   const Range rg = task_range(ntasks, G);
   double acc[1] = {0.0};
   if (on) {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, BSlot* slots,
   const double c64 = sl.c;
   const int par = sl.iters & 1;
   const T* __restrict__ p = par ? v.p0 : v.p1;  // written by kb_dir_spmv this iteration
-  const int64_t ntasks = m.n_slices * RPW;
+  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
   const Range rg = task_range(ntasks, G);
   double acc[2] = {0.0, 0.0};
   if (on) {
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kB) void kb_fold(BMat m, BVec<float> v, const BSlot
   const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
   const int j = lane % R, rsub = lane / R;
   if (!slots[j].fold) return;
-  const int64_t ntasks = m.n_slices * RPW;
+  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
   const Range rg = task_range(ntasks, G);
   for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
     const int64_t row = t * RPW + rsub;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
   const BSlot& sl = slots[j];
   const bool on = MODE == 0 ? (sl.fold != 0) : ((mask >> j) & 1ull) != 0;
   const double c = MODE == 0 ? sl.c : cs.c[j];
-  const int64_t ntasks = m.n_slices * RPW;
+  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
   const Range rg = task_range(ntasks, G);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // rz, rr, floor (mode 0) or bb (mode 1)
   if (on) {
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<float> vf, BVec<dou
   const float* __restrict__ xacc = mixed ? vf.xacc : nullptr;
   const double* __restrict__ phi = mixed ? vf.phi : vd.phi;
   double* __restrict__ o = out.p[j];
-  const int64_t ntasks = m.n_slices * RPW;
+  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
   const Range rg = task_range(ntasks, G);
   double acc[2] = {0.0, 0.0};
   if (on) {

@@ -881,6 +881,8 @@ ifl_status filter_single(Handle* h, int32_t n_fields, const double* fields, int3
   return IFL_OK;
 }
 
+}  // namespace
+
 BatchMatrix batch_matrix(DeviceState* d, int R) {
   BatchMatrix bm;
   const DevMatrix& m = d->m;
@@ -894,12 +896,17 @@ BatchMatrix batch_matrix(DeviceState* d, int R) {
   bm.kdiag = m.kdiag64;
   bm.mass = m.mass64;
   bm.entity = m.entity;
-  const int64_t tasks = m.n_slices * (kWave / R);
+  const int64_t tasks = m.n_slices * R;  // tasks of 64/R rows
   int G = (int)std::min<int64_t>(kMaxBlocks, (tasks + kWavesPerBlock - 1) / kWavesPerBlock);
   if (G >= kXcd) G = (G / kXcd) * kXcd;
   bm.G = std::max(1, G);
   return bm;
 }
+
+BatchMatrix handle_batch_matrix(Handle* h, int R) { return batch_matrix(h->dev, R); }
+double handle_mass_sum(const Handle* h) { return h->dev->m.mass_sum; }
+
+namespace {
 
 ifl_status ensure_batch(DeviceState* d, int R, bool mixed) {
   if (d->bw.R == R && d->bw.mixed == mixed && d->bw.slots) return IFL_OK;

@@ -75,3 +75,6 @@ ifl_status device_profile_read(Handle* h, int64_t* launches, double* total_ms, d
                                int32_t reset);
 
 }  // namespace ifl
+
+// The ABI's opaque handle is the library's Handle.
+struct ifl_handle : ifl::Handle {};

@@ -1,21 +1,400 @@
-// Serving entry points (continuous batching); filled in by the batched engine.
+// Serving: continuous batching of filter requests over prepared handles.
+//
+// Each registered handle gets a worker thread, its own HIP stream and its
+// own tile of R slots of the batched CG engine, so solves on different
+// meshes run concurrently on the device. A request (one field, several
+// scales) becomes one column per scale. Columns enter the tile between CG
+// iterations as slots free up, and leave it as they converge; a request is
+// admitted when its device footprint fits the server's memory budget. A
+// column's arithmetic does not depend on its tile neighbours, its slot or
+// its start time, so a result is the same alone and in any mix.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "batch.h"
 #include "internal.h"
 
 using namespace ifl;
+using Clock = std::chrono::steady_clock;
+
+struct ifl_ticket {
+  std::mutex mu;
+  std::condition_variable cv;
+  bool done = false;
+  ifl_status status = IFL_OK;
+  std::string error;
+  int32_t mesh_id = 0;
+  int32_t n_scales = 0;
+  std::vector<double> k;
+  std::vector<double> field;  // host copy
+  double* out = nullptr;      // caller's host buffer, n_scales x L
+  std::vector<ifl_solve_stats> stats;
+  int remaining = 0;
+  size_t footprint = 0;
+  double* dev_field = nullptr;
+  Clock::time_point t_submit, t_done;
+};
+
+namespace {
+
+struct Column {
+  ifl_ticket* t;
+  int scale;
+};
+
+struct Worker {
+  ifl_server* srv = nullptr;
+  Handle* h = nullptr;
+  int id = 0;
+  int R = 0;
+  hipStream_t stream = nullptr;
+  BatchWork w;
+  BatchMatrix bm;
+  double* col_out = nullptr;  // R x L device staging of finished columns
+  int64_t L = 0;
+  std::deque<ifl_ticket*> queue;  // submitted, not yet admitted (guarded by srv->mu)
+  std::deque<Column> pending;     // admitted columns waiting for a slot (worker only)
+  std::vector<Column> slot;       // column in each slot
+  std::vector<Clock::time_point> t_in;
+  std::vector<double*> field_pool;  // device field buffers for reuse (worker only)
+  std::thread th;
+  ifl_status init_status = IFL_OK;
+};
+
+}  // namespace
+
+struct ifl_server {
+  size_t budget = 0;
+  size_t tiles = 0;  // work space of the registered tiles (guarded by mu)
+  size_t used = 0;   // device memory of admitted requests (guarded by mu)
+  int slots = 32;
+  int device = 0;
+  std::vector<std::unique_ptr<Worker>> workers;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool stop = false;
+};
+
+namespace {
+
+void finish_ticket(ifl_ticket* t, ifl_status st, const std::string& msg) {
+  std::lock_guard<std::mutex> lk(t->mu);
+  if (st != IFL_OK && t->status == IFL_OK) {
+    t->status = st;
+    t->error = msg;
+  }
+  t->done = true;
+  t->t_done = Clock::now();
+  t->cv.notify_all();
+}
+
+// Admit queued requests of this worker whose footprint fits the budget
+// (oldest first; a request that does not fit blocks the ones behind it so
+// that large requests are not starved).
+void admit(Worker* wk, std::vector<ifl_ticket*>* admitted) {
+  ifl_server* s = wk->srv;
+  std::lock_guard<std::mutex> lk(s->mu);
+  while (!wk->queue.empty()) {
+    ifl_ticket* t = wk->queue.front();
+    // one request is always admitted when none is in flight, so a request
+    // larger than the budget still runs (alone)
+    if (s->tiles + s->used + t->footprint > s->budget && s->used > 0) break;
+    s->used += t->footprint;
+    wk->queue.pop_front();
+    admitted->push_back(t);
+  }
+}
+
+// Device field buffers are pooled per worker: hipFree would synchronise the
+// whole device and stall the other meshes' streams.
+void release_ticket(Worker* wk, ifl_ticket* t) {
+  if (t->dev_field) wk->field_pool.push_back(t->dev_field);
+  t->dev_field = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(wk->srv->mu);
+    wk->srv->used -= t->footprint;
+  }
+  wk->srv->cv.notify_all();
+}
+
+ifl_status run_worker(Worker* wk) {
+  Handle* h = wk->h;
+  const int R = wk->R;
+  const double rtol = h->opt.rtol;
+  BatchParams prm;
+  prm.max_iter = h->opt.max_iter;
+  const int chunk = 4;
+  int active = 0;
+  for (;;) {
+    // 1. admit and stage new requests
+    std::vector<ifl_ticket*> adm;
+    admit(wk, &adm);
+    for (ifl_ticket* t : adm) {
+      if (!wk->field_pool.empty()) {
+        t->dev_field = wk->field_pool.back();
+        wk->field_pool.pop_back();
+      } else if (hipMalloc((void**)&t->dev_field, sizeof(double) * wk->L) != hipSuccess) {
+        t->dev_field = nullptr;
+      }
+      if (!t->dev_field ||
+          hipMemcpyAsync(t->dev_field, t->field.data(), sizeof(double) * wk->L, hipMemcpyHostToDevice,
+                         wk->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        release_ticket(wk, t);
+        finish_ticket(t, IFL_ENOMEM, "device allocation for the request failed");
+        continue;
+      }
+      for (int j = 0; j < t->n_scales; ++j) wk->pending.push_back({t, j});
+    }
+    // 2. fill free slots
+    uint64_t mask = 0;
+    SlotScales cs{};
+    for (int j = 0; j < R && !wk->pending.empty(); ++j) {
+      if (wk->slot[j].t) continue;
+      const Column col = wk->pending.front();
+      wk->pending.pop_front();
+      ifl_status st = batch_load_column(wk->bm, wk->w, j, col.t->dev_field, wk->stream);
+      if (st != IFL_OK) return st;
+      cs.c[j] = h->opt.gamma / std::pow(col.t->k[col.scale], 2.0 * h->op.order);
+      wk->slot[j] = col;
+      wk->t_in[j] = Clock::now();
+      mask |= 1ull << j;
+      ++active;
+    }
+    if (mask) {
+      ifl_status st = batch_init(wk->bm, wk->w, mask, cs, rtol, wk->stream);
+      if (st != IFL_OK) return st;
+    }
+    if (active == 0) {
+      std::unique_lock<std::mutex> lk(wk->srv->mu);
+      if (wk->srv->stop && wk->queue.empty()) return IFL_OK;
+      if (wk->queue.empty()) wk->srv->cv.wait_for(lk, std::chrono::milliseconds(50));
+      continue;
+    }
+    // 3. iterate
+    ifl_status st = batch_iterate(wk->bm, wk->w, chunk, prm, wk->stream);
+    if (st != IFL_OK) return st;
+    if ((st = batch_read_slots(wk->w, wk->stream)) != IFL_OK) return st;
+    // 4. retire finished columns
+    uint64_t fin = 0;
+    std::vector<double*> dst(R, nullptr);
+    for (int j = 0; j < R; ++j) {
+      if (!wk->slot[j].t || wk->w.slots_host[j].done == 0) continue;
+      fin |= 1ull << j;
+      dst[j] = wk->col_out + (int64_t)j * wk->L;
+      if (hipMemsetAsync(dst[j], 0, sizeof(double) * wk->L, wk->stream) != hipSuccess)
+        return fail(IFL_EDEVICE, "hipMemsetAsync failed");
+    }
+    if (!fin) continue;
+    if ((st = batch_finish(wk->bm, wk->w, fin, dst.data(), wk->stream)) != IFL_OK) return st;
+    if ((st = batch_read_slots(wk->w, wk->stream)) != IFL_OK) return st;
+    const auto now = Clock::now();
+    for (int j = 0; j < R; ++j) {
+      if (!((fin >> j) & 1ull)) continue;
+      const Column col = wk->slot[j];
+      ifl_ticket* t = col.t;
+      const BSlot& sl = wk->w.slots_host[j];
+      if (hipMemcpyAsync(t->out + (int64_t)col.scale * wk->L, dst[j], sizeof(double) * wk->L,
+                         hipMemcpyDeviceToHost, wk->stream) != hipSuccess ||
+          hipStreamSynchronize(wk->stream) != hipSuccess)
+        return fail(IFL_EDEVICE, "copy of a finished column failed");
+      ifl_solve_stats& so = t->stats[col.scale];
+      so.iterations = sl.iters;
+      so.refinements = sl.updates;
+      so.status = sl.done == 1 ? IFL_OK : IFL_ENOTCONV;
+      so.reserved = 0;
+      so.rel_residual = sl.bb > 0 ? std::sqrt(sl.res2 / sl.bb) : std::sqrt(sl.res2);
+      so.seconds = std::chrono::duration<double>(now - wk->t_in[j]).count();
+      wk->slot[j] = Column{nullptr, 0};
+      --active;
+      if (--t->remaining == 0) {
+        bool all_ok = true;
+        for (const auto& x : t->stats) all_ok &= x.status == IFL_OK;
+        release_ticket(wk, t);
+        finish_ticket(t, all_ok ? IFL_OK : IFL_ENOTCONV, all_ok ? "" : "a column did not converge");
+      }
+    }
+    if ((st = batch_release(wk->w, fin, wk->stream)) != IFL_OK) return st;
+  }
+}
+
+void worker_main(Worker* wk) {
+  (void)hipSetDevice(wk->srv->device);
+  ifl_status st = run_worker(wk);
+  if (st != IFL_OK) {
+    // fail everything this worker still holds, so no waiter blocks forever
+    const std::string msg = std::string("serving worker failed: ") + ifl_last_error();
+    for (int j = 0; j < wk->R; ++j)
+      if (wk->slot[j].t) {
+        ifl_ticket* t = wk->slot[j].t;
+        wk->slot[j] = Column{nullptr, 0};
+        if (--t->remaining == 0) finish_ticket(t, st, msg);
+      }
+    for (const Column& c : wk->pending)
+      if (--c.t->remaining == 0) finish_ticket(c.t, st, msg);
+    wk->pending.clear();
+    std::lock_guard<std::mutex> lk(wk->srv->mu);
+    for (ifl_ticket* t : wk->queue) finish_ticket(t, st, msg);
+    wk->queue.clear();
+    wk->init_status = st;
+  }
+}
+
+}  // namespace
 
 extern "C" {
 
-ifl_status ifl_server_create(size_t, int32_t, ifl_server** out) {
-  if (out) *out = nullptr;
-  return fail(IFL_EUNSUPPORTED, "serving is not built yet");
+ifl_status ifl_server_create(size_t hbm_budget_bytes, int32_t slots, ifl_server** out) {
+  if (!out) return fail(IFL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (slots < 1 || slots > 64) return fail(IFL_EINVAL, "slots must be in 1..64");
+  if (hbm_budget_bytes == 0) return fail(IFL_EINVAL, "memory budget must be > 0");
+  ifl_server* s = new ifl_server();
+  s->budget = hbm_budget_bytes;
+  int R = 1;
+  while (R * 2 <= slots) R *= 2;
+  s->slots = R;
+  *out = s;
+  return IFL_OK;
 }
-ifl_status ifl_server_add(ifl_server*, ifl_handle*, int32_t*) { return fail(IFL_EUNSUPPORTED, "serving is not built yet"); }
-ifl_status ifl_submit(ifl_server*, int32_t, const double*, int32_t, const double*, double*, ifl_ticket**) {
-  return fail(IFL_EUNSUPPORTED, "serving is not built yet");
-}
-ifl_status ifl_wait(ifl_ticket*, ifl_solve_stats*) { return fail(IFL_EUNSUPPORTED, "serving is not built yet"); }
-int32_t ifl_poll(const ifl_ticket*) { return 0; }
-double ifl_ticket_latency(const ifl_ticket*) { return 0.0; }
-void ifl_server_destroy(ifl_server*) {}
 
+ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
+  if (!s || !hh || !mesh_id) return fail(IFL_EINVAL, "server / handle / mesh_id is NULL");
+  Handle* h = static_cast<Handle*>(hh);
+  if (!h->dev) return fail(IFL_EDEVICE, "host-only handle (device = -1)");
+  std::unique_ptr<Worker> wk(new Worker());
+  wk->srv = s;
+  wk->h = h;
+  wk->R = s->slots;
+  wk->L = h->op.field_len;
+  s->device = h->opt.device;
+  if (hipSetDevice(h->opt.device) != hipSuccess) return fail(IFL_EDEVICE, "hipSetDevice failed");
+  wk->bm = handle_batch_matrix(h, wk->R);
+  const size_t tile = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED) +
+                      sizeof(double) * (size_t)wk->R * wk->L;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->tiles + s->used + tile > s->budget)
+      return fail(IFL_ENOMEM, "tile work space exceeds the server's memory budget");
+    s->tiles += tile;
+  }
+  ifl_status st = batch_alloc(&wk->w, wk->bm, wk->R, h->opt.precision == IFL_MIXED);
+  if (st == IFL_OK && hipMalloc((void**)&wk->col_out, sizeof(double) * (size_t)wk->R * wk->L) != hipSuccess)
+    st = fail(IFL_ENOMEM, "hipMalloc of the output staging failed");
+  if (st == IFL_OK && hipStreamCreateWithFlags(&wk->stream, hipStreamNonBlocking) != hipSuccess)
+    st = fail(IFL_EDEVICE, "hipStreamCreate failed");
+  if (st != IFL_OK) {
+    batch_free(&wk->w);
+    if (wk->col_out) (void)hipFree(wk->col_out);
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->tiles -= tile;
+    return st;
+  }
+  wk->slot.assign(wk->R, Column{nullptr, 0});
+  wk->t_in.resize(wk->R);
+  std::lock_guard<std::mutex> lk(s->mu);
+  wk->id = (int)s->workers.size();
+  *mesh_id = wk->id;
+  Worker* raw = wk.get();
+  s->workers.push_back(std::move(wk));
+  raw->th = std::thread(worker_main, raw);
+  return IFL_OK;
 }
+
+ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field, int32_t n_scales, const double* k,
+                      double* out, ifl_ticket** ticket) {
+  if (!s || !field || !k || !out || !ticket) return fail(IFL_EINVAL, "NULL argument");
+  *ticket = nullptr;
+  Worker* wk = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (mesh_id < 0 || mesh_id >= (int)s->workers.size()) return fail(IFL_EINVAL, "unknown mesh id");
+    wk = s->workers[mesh_id].get();
+    if (s->stop) return fail(IFL_EINVAL, "server is shutting down");
+  }
+  if (n_scales < 1) return fail(IFL_EINVAL, "n_scales must be >= 1");
+  for (int32_t j = 0; j < n_scales; ++j)
+    if (!(k[j] > 0) || !std::isfinite(k[j])) return fail(IFL_EINVAL, "wavenumbers must be finite and > 0");
+  const HostOperator& op = wk->h->op;
+  for (int64_t i = 0; i < op.n; ++i)
+    if (!std::isfinite(field[op.entity[i]])) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");
+  ifl_ticket* t = new ifl_ticket();
+  t->mesh_id = mesh_id;
+  t->n_scales = n_scales;
+  t->k.assign(k, k + n_scales);
+  t->field.assign(field, field + op.field_len);
+  for (int64_t i = 0; i < (int64_t)n_scales * op.field_len; ++i) out[i] = 0.0;
+  t->out = out;
+  t->stats.assign(n_scales, ifl_solve_stats{});
+  t->remaining = n_scales;
+  t->footprint = sizeof(double) * (size_t)op.field_len;
+  t->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    wk->queue.push_back(t);
+  }
+  s->cv.notify_all();
+  *ticket = t;
+  return IFL_OK;
+}
+
+int32_t ifl_poll(const ifl_ticket* t) {
+  if (!t) return 0;
+  std::lock_guard<std::mutex> lk(const_cast<ifl_ticket*>(t)->mu);
+  return t->done ? 1 : 0;
+}
+
+double ifl_ticket_latency(const ifl_ticket* t) {
+  if (!t) return 0.0;
+  std::lock_guard<std::mutex> lk(const_cast<ifl_ticket*>(t)->mu);
+  if (!t->done) return std::chrono::duration<double>(Clock::now() - t->t_submit).count();
+  return std::chrono::duration<double>(t->t_done - t->t_submit).count();
+}
+
+ifl_status ifl_wait(ifl_ticket* t, ifl_solve_stats* stats) {
+  if (!t) return fail(IFL_EINVAL, "ticket is NULL");
+  ifl_status st;
+  std::string msg;
+  {
+    std::unique_lock<std::mutex> lk(t->mu);
+    t->cv.wait(lk, [&] { return t->done; });
+    if (stats)
+      for (int32_t j = 0; j < t->n_scales; ++j) stats[j] = t->stats[j];
+    st = t->status;
+    msg = t->error;
+  }
+  delete t;
+  if (st != IFL_OK) return fail(st, msg);
+  return IFL_OK;
+}
+
+void ifl_server_destroy(ifl_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  for (auto& wk : s->workers) {
+    if (wk->th.joinable()) wk->th.join();
+    (void)hipSetDevice(s->device);
+    if (wk->stream) (void)hipStreamSynchronize(wk->stream);
+    batch_free(&wk->w);
+    if (wk->col_out) (void)hipFree(wk->col_out);
+    for (double* f : wk->field_pool) (void)hipFree(f);
+    if (wk->stream) (void)hipStreamDestroy(wk->stream);
+  }
+  delete s;
+}
+
+}  // extern "C"

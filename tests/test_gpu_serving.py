@@ -1,0 +1,113 @@
+"""GPU tests of the continuous-batching server (needs MI355X).
+
+Requests over two prepared meshes arrive while others are on the GPU; each
+result must match the FP64 oracle within the mixed-precision bar and be the
+same (bitwise) as the same request served alone."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle.solve import relative_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ifl():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2404_07398_amd as m
+
+    assert os.path.exists(m.LIB_PATH), "libifl.so must be built before the GPU tests"
+    return m
+
+
+def _meshes():
+    s = W.icosphere(5, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    m = W.split_square(64, jitter=0.2)
+    return [(s, 1), (s, 2), (m, 1)]
+
+
+def _requests(meshes, n_req, seed=7):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for r in range(n_req):
+        mi = int(rng.integers(len(meshes)))
+        mesh, n = meshes[mi]
+        ns = int(rng.integers(1, 7))
+        ks = np.sort(rng.uniform(np.log(2 * np.pi / (16 * mesh.h)), np.log(2 * np.pi / (2 * mesh.h)), ns))
+        ks = np.exp(ks)
+        if mesh.geometry == W.GEOM_SPHERE:
+            field = W.sphere_k3_field(mesh, 5000 + r, n_waves=128)
+        else:
+            field = W.planar_k3_field(mesh, 5000 + r)
+        reqs.append((mi, field, ks))
+    return reqs
+
+
+def test_served_results_match_oracle_and_alone(ifl):
+    meshes = _meshes()
+    handles = [ifl.prepare_mesh(mesh, 0, n, precision=ifl.IFL_MIXED) for mesh, n in meshes]
+    reqs = _requests(meshes, 24)
+    srv = ifl.Server(4 << 30, slots=8)
+    ids = [srv.add(h) for h in handles]
+    t0 = time.time()
+    tickets = [srv.submit(ids[mi], field, ks) for (mi, field, ks) in reqs]
+    results = []
+    for (t, out), (mi, field, ks) in zip(tickets, reqs):
+        st, stats, o, lat = srv.wait(t, len(ks))
+        assert st == 0, st
+        assert all(s.status == 0 for s in stats)
+        results.append(o.copy())
+    print(f"served {len(reqs)} requests in {time.time() - t0:.2f}s")
+    # oracle parity (mixed-precision bar)
+    ops = {}
+    for (mi, field, ks), o in zip(reqs, results):
+        mesh, n = meshes[mi]
+        if mi not in ops:
+            ops[mi] = O.scalar_operator(mesh, n)
+        ref = O.filter_scalar(ops[mi], field, ks)
+        for j in range(len(ks)):
+            assert relative_l2(o[j], ref[j]) <= 1e-9
+    # the same requests one at a time give bitwise the same fields
+    for idx in (0, 5, 11, 23):
+        mi, field, ks = reqs[idx]
+        t, out = srv.submit(ids[mi], field, ks)
+        st, stats, o, lat = srv.wait(t, len(ks))
+        assert st == 0
+        assert np.array_equal(o, results[idx]), idx
+    srv.close()
+    for h in handles:
+        h.close()
+
+
+def test_server_errors(ifl):
+    m = W.split_square(16, jitter=0.1)
+    h = ifl.prepare_mesh(m, 0, 1, precision=ifl.IFL_MIXED)
+    srv = ifl.Server(1 << 30, slots=4)
+    mid = srv.add(h)
+    f = W.planar_k3_field(m, 1)
+    bad = f.copy()
+    bad[3] = np.nan
+    with pytest.raises(ifl.IflError) as e:
+        srv.submit(mid, bad, [0.5])
+    assert e.value.status == ifl.IFL_EINVAL
+    with pytest.raises(ifl.IflError) as e:
+        srv.submit(mid + 5, f, [0.5])
+    assert e.value.status == ifl.IFL_EINVAL
+    with pytest.raises(ifl.IflError) as e:
+        srv.submit(mid, f, [-1.0])
+    assert e.value.status == ifl.IFL_EINVAL
+    # tiny budget: requests queue and still all complete
+    t_list = [srv.submit(mid, f * (i + 1), [0.3, 1.0]) for i in range(6)]
+    for t, _ in t_list:
+        st, stats, o, lat = srv.wait(t, 2)
+        assert st == 0 and lat > 0
+    srv.close()
+    h.close()
