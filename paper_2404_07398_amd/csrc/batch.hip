@@ -46,6 +46,7 @@ constexpr int kW = 64;            // wavefront
 constexpr int kB = 512;           // threads per block
 constexpr int kWpb = kB / kW;     // waves per block
 constexpr int kFinThreads = 256;  // per-column finalize workgroup
+constexpr int kUnroll = 8;        // sliced-ELL entries loaded together per row
 constexpr double kU = 1.1102230246251565e-16;
 constexpr double kFloor = 8.0;
 
@@ -155,11 +156,33 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, BSlot* slot
       const int64_t s = row / kW, l = row % kW;
       const int64_t base = m.sptr[s];
       const int w = (int)((m.sptr[s + 1] - base) / kW);
+      // Entries are taken kUnroll at a time: all index / value loads, then
+      // all gathers, then the FMAs in entry order (the summation order is
+      // that of the plain loop; the unrolling only raises the number of
+      // loads in flight per wavefront).
       T a = (T)0;
-      for (int k = 0; k < w; ++k) {
-        const int64_t e = base + (int64_t)k * kW + l;
-        const int64_t cj = (int64_t)m.col[e] * R + j;
-        a = fma(val[e], fma(beta, pin[cj], z[cj]), a);
+      for (int k0 = 0; k0 < w; k0 += kUnroll) {
+        int32_t cu[kUnroll];
+        T vu[kUnroll], zu[kUnroll], pu[kUnroll];
+        // loads past the row's end stay in bounds (next slice or the zero
+        // tail of the arrays); their values are replaced by 0
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int64_t e = base + (int64_t)(k0 + u) * kW + l;
+          cu[u] = m.col[e];
+          const T vv = val[e];
+          vu[u] = k0 + u < w ? vv : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int64_t cj = (int64_t)cu[u] * R + j;
+          zu[u] = z[cj];
+          pu[u] = pin[cj];
+        }
+        // entries past the row's end have value 0 and gather row 0 (finite):
+        // their FMA leaves a unchanged, so no branch keeps the gathers apart
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) a = fma(vu[u], fma(beta, pu[u], zu[u]), a);
       }
       const int64_t idx = row * R + j;
       const T pn = fma(beta, pin[idx], z[idx]);

@@ -51,6 +51,7 @@ constexpr int kBlock = 512;                 // 8 wavefronts
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxBlocks = 1024;            // logical blocks (partials per quantity)
 constexpr int kXcd = 8;
+constexpr int kUnroll = 8;                  // sliced-ELL entries loaded together per row
 
 // Per-column device scalars. Written by block 0 of a kernel, read by the
 // following kernels (kernel boundaries order them).
@@ -337,11 +338,30 @@ __global__ __launch_bounds__(kBlock) void k_dir_spmv(Mat m, Vecs<T> v, double* p
     if (row >= m.n) continue;
     const int64_t base = m.sptr[s];
     const int w = (int)((m.sptr[s + 1] - base) / kWave);
+    // entries kUnroll at a time: index / value loads, then the gathers, then
+    // the FMAs in entry order (more loads in flight per wavefront)
     T a = (T)0;
-    for (int k = 0; k < w; ++k) {
-      const int64_t e = base + (int64_t)k * kWave + lane;
-      const int32_t j = m.col[e];
-      a += val[e] * (z[j] + beta * pin[j]);
+    for (int k0 = 0; k0 < w; k0 += kUnroll) {
+      int32_t cu[kUnroll];
+      T vu[kUnroll], zu[kUnroll], pu[kUnroll];
+      // loads past the row's end stay in bounds (next slice or the zero
+      // tail of the arrays); their values are replaced by 0
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t e = base + (int64_t)(k0 + u) * kWave + lane;
+        cu[u] = m.col[e];
+        const T vv = val[e];
+        vu[u] = k0 + u < w ? vv : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        zu[u] = z[cu[u]];
+        pu[u] = pin[cu[u]];
+      }
+      // entries past the row's end have value 0 and gather row 0 (finite):
+      // their FMA leaves a unchanged, so no branch keeps the gathers apart
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) a = fma(vu[u], fma(beta, pu[u], zu[u]), a);
     }
     const T pn = z[row] + beta * pin[row];
     const T qv = v.d[row] * pn + c * a;
@@ -618,7 +638,7 @@ ifl_status device_create(Handle* h) {
   m.n = sp.n;
   m.n_slices = sp.n_slices;
   m.n_pad = sp.n_slices * kWave;
-  m.nnz_stored = (int64_t)sp.col.size();
+  m.nnz_stored = sp.slice_ptr.back();  // without the zero tail
   m.offdiag = sp.stored_offdiag;
   std::vector<float> v32(sp.val.begin(), sp.val.end());
   std::vector<float> kd32(sp.diag.begin(), sp.diag.end());

@@ -54,6 +54,9 @@ struct SellPack {
 
 void pack_sell(const HostOperator& op, SellPack* out);
 
+// Zero entries appended after the last slice (8 entries x 64 lanes).
+constexpr int64_t kSellTail = 8 * 64;
+
 // ---------------------------------------------------------------- device side
 struct DeviceState;  // defined in device.hip
 

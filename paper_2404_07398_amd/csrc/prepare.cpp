@@ -537,8 +537,10 @@ void pack_sell(const HostOperator& op, SellPack* out) {
     out->max_width = std::max(out->max_width, w);
     out->slice_ptr[s + 1] = out->slice_ptr[s] + 64 * (int64_t)w;
   }
-  out->col.assign(out->slice_ptr[ns], 0);
-  out->val.assign(out->slice_ptr[ns], 0.0);
+  // kSellTail zero entries (column 0, value 0) follow the last slice, so that
+  // kernels may load a fixed number of entries per row without bounds checks
+  out->col.assign(out->slice_ptr[ns] + kSellTail, 0);
+  out->val.assign(out->slice_ptr[ns] + kSellTail, 0.0);
   for (int64_t s = 0; s < ns; ++s) {
     for (int64_t l = 0; l < 64; ++l) {
       const int64_t r = s * 64 + l;
