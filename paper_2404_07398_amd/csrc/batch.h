@@ -9,6 +9,11 @@
 
 namespace ifl {
 
+// Tile iterations between FP64 residual-replacement checks of mixed tiles.
+// Columns enter a tile only at multiples of it, and the host advances a tile
+// by multiples of it.
+constexpr int kFoldEvery = 4;
+
 // Per-column CG state of one slot (device memory; mirrored to pinned host
 // memory by batch_read_slots).
 struct BSlot {
@@ -68,6 +73,7 @@ struct BatchWork {
   BSlot* slots = nullptr;
   BSlot* slots_host = nullptr;  // pinned
   int* flag = nullptr;
+  int64_t iter = 0;       // tile iterations so far (parity of the p ping-pong)
 };
 
 // Scale factors c_j of the slots being initialised (kernel argument).
@@ -76,6 +82,9 @@ struct SlotScales {
 };
 
 size_t batch_bytes(int64_t n_pad, int R, bool mixed);
+// Lanes that share one row in a tile of R columns (each lane owns 16 bytes of
+// columns: 4 FP32 or 2 FP64).
+int batch_lanes_per_row(int R, bool mixed);
 ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed);
 void batch_free(BatchWork* w);
 
@@ -96,7 +105,7 @@ ifl_status batch_release(BatchWork& w, uint64_t mask, hipStream_t s);
 
 // The handle's matrix for tiles of R columns, and the sum of its mass
 // (both need a device handle; defined with the device state).
-BatchMatrix handle_batch_matrix(Handle* h, int R);
+BatchMatrix handle_batch_matrix(Handle* h, int R, bool mixed);
 double handle_mass_sum(const Handle* h);
 
 }  // namespace ifl

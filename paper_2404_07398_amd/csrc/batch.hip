@@ -3,22 +3,24 @@
 //
 // Every column is an independent Jacobi-PCG solve of S_j x = M phi_j with
 // S_j = M + c_j K_n (Sect. 2.2.2, residual form x0 = phi_j). A tile holds R
-// slots; vectors are stored rows x R with the R columns of a row contiguous,
-// and a wavefront covers 64/R consecutive rows x R columns, lane = column.
-// Each sliced-ELL entry (index, value) is then loaded once per row for all R
-// columns (identical addresses within a row's lanes are served by one
-// request), and the gather of a neighbour's R values is one contiguous
-// segment. HBM traffic per column-iteration is the vector traffic plus
-// 1/R of the matrix stream.
+// slots; vectors are stored rows x R with the R columns of a row contiguous.
+// A lane owns C consecutive columns of one row (C x 4 B = 16 B for FP32,
+// C x 8 B = 16 B for FP64), so vector traffic moves in 16-byte loads and
+// stores and each lane carries C independent FMA chains; the R / C lanes of
+// a row share the row's sliced-ELL entries (same address within the group),
+// and a gather of a neighbour's R values is one contiguous segment. HBM
+// traffic per column-iteration is the vector traffic plus 1/R of the matrix
+// stream.
 //
 // Per-column state (alpha, beta, rho, stopping, residual replacement) lives
 // in device memory; after each reduction phase a small kernel with one
-// workgroup per column finishes that column's sum in a fixed order. A
-// column's arithmetic and reduction order do not depend on the other
-// columns, on its slot index or on when it entered the tile, so a solve
-// gives bitwise the same result alone or in a full tile. Finished columns
-// leave the tile and new ones take their slots between iterations
-// (continuous batching).
+// workgroup per column finishes that column's sum in a fixed order. Columns
+// enter a tile only at tile iterations that are multiples of kFoldEvery, so
+// all live columns share the parity of the p ping-pong and the iterations at
+// which FP64 residual replacements are considered: one replacement pass
+// serves every column that needs it. A column's arithmetic and reduction
+// order depend neither on the other columns, nor on its slot, nor on when it
+// entered, so a solve gives bitwise the same result alone or in a full tile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,6 +53,28 @@ constexpr double kU = 1.1102230246251565e-16;
 constexpr double kFloor = 8.0;
 
 enum { Q_PQ = 0, Q_RZ, Q_RR, Q_BB, Q_FL, Q_RES, Q_EN, Q_COUNT };
+
+// Lane geometry of a tile of R columns of type T.
+template <typename T, int R>
+struct Geo {
+  static constexpr int C = (int)(16 / sizeof(T)) < R ? (int)(16 / sizeof(T)) : R;  // columns per lane
+  static constexpr int LPR = R / C;                                              // lanes per row
+  static constexpr int RPW = kW / LPR;                                           // rows per wavefront
+};
+
+template <typename T, int C>
+struct alignas(sizeof(T) * C) Pack {
+  T v[C];
+};
+
+template <typename T, int C>
+__device__ __forceinline__ Pack<T, C> vload(const T* p) {
+  return *reinterpret_cast<const Pack<T, C>*>(p);
+}
+template <typename T, int C>
+__device__ __forceinline__ void vstore(T* p, const Pack<T, C>& x) {
+  *reinterpret_cast<Pack<T, C>*>(p) = x;
+}
 
 struct BMat {
   int64_t n, n_slices;
@@ -92,17 +116,21 @@ __device__ __forceinline__ int lblock(int G) {
   return (b % 8) * (G / 8) + b / 8;
 }
 
-// Per-column block sums: lane l carries column l % R. Result for column t
-// in thread t (t < R), fixed order.
-template <int R, int NV>
-__device__ __forceinline__ void col_sum(double (&v)[NV], double* lds /* NV*kWpb*R */) {
+// Per-column block sums. Lane l carries columns (l % LPR) * C + c; the
+// result for column t is returned in thread t (t < R), fixed order.
+template <int R, int C, int NV>
+__device__ __forceinline__ void col_sum(double (&v)[NV][C], double* lds /* NV * kWpb * R */, double (&out)[NV]) {
+  constexpr int LPR = R / C;
   const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    double s = v[i];
 #pragma unroll
-    for (int off = 32; off >= R; off >>= 1) s += __shfl_xor(s, off, kW);
-    if (lane < R) lds[(i * kWpb + wid) * R + lane] = s;
+    for (int c = 0; c < C; ++c) {
+      double s = v[i][c];
+#pragma unroll
+      for (int off = 32; off >= LPR; off >>= 1) s += __shfl_xor(s, off, kW);
+      if (lane < LPR) lds[(i * kWpb + wid) * R + lane * C + c] = s;
+    }
   }
   __syncthreads();
   if (threadIdx.x < R) {
@@ -110,7 +138,7 @@ __device__ __forceinline__ void col_sum(double (&v)[NV], double* lds /* NV*kWpb*
     for (int i = 0; i < NV; ++i) {
       double s = 0.0;
       for (int w = 0; w < kWpb; ++w) s += lds[(i * kWpb + w) * R + threadIdx.x];
-      v[i] = s;
+      out[i] = s;
     }
   }
 }
@@ -119,7 +147,7 @@ struct Range {
   int64_t begin, end;
 };
 
-// contiguous task range of this logical block; a task is 64/R rows
+// contiguous task range of this logical block; a task is RPW rows
 __device__ __forceinline__ Range task_range(int64_t ntasks, int G) {
   const int lb = lblock(G);
   const int64_t per = (ntasks + G - 1) / G;
@@ -129,247 +157,365 @@ __device__ __forceinline__ Range task_range(int64_t ntasks, int G) {
 
 __device__ __forceinline__ bool live(const BSlot& s) { return s.active && s.done == 0; }
 
+// Sliced-ELL row product: a[c] += sum_k val_k * comb(c, x0[k], x1[k]) (or
+// |val_k| * comb when ABS) over
+// the row's entries in order, kUnroll entries at a time (index and value
+// loads, then the 16-byte gathers of the operands, then the FMAs). Loads
+// past the row's end stay in bounds (the next slice, or the zero tail after
+// the last slice) and their value is replaced by 0, so they leave a
+// unchanged.
+template <typename V, typename T, int R, int C, bool TWO, bool ABS, typename Comb>
+__device__ __forceinline__ void row_product(const BMat& m, const V* __restrict__ val, int64_t base, int w,
+                                            int64_t l, int j0, const T* __restrict__ x0,
+                                            const T* __restrict__ x1, Comb comb, T (&a)[C]) {
+  for (int k0 = 0; k0 < w; k0 += kUnroll) {
+    int32_t cu[kUnroll];
+    V vu[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t e = base + (int64_t)(k0 + u) * kW + l;
+      cu[u] = m.col[e];
+      const V vv = val[e];
+      vu[u] = k0 + u < w ? (ABS ? (V)fabs(vv) : vv) : (V)0;
+    }
+    Pack<T, C> g0[kUnroll], g1[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t off = (int64_t)cu[u] * R + j0;
+      g0[u] = vload<T, C>(x0 + off);
+      if constexpr (TWO) g1[u] = vload<T, C>(x1 + off);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+      for (int c = 0; c < C; ++c) a[c] = fma((T)vu[u], comb(c, g0[u].v[c], TWO ? g1[u].v[c] : (T)0), a[c]);
+  }
+}
+
 // ------------------------------------------------------------ iteration
+// p_new = z + beta p (own row and gathered neighbours), q = S p_new,
+// partial (p_new, q) per column.
 template <typename T, int R>
-__global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, BSlot* slots, double* part, int G) {
+__global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+                                                  int par) {
+  using Gm = Geo<T, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[1 * kWpb * R];
-  constexpr int RPW = kW / R;
   const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
-  const int j = lane % R, rsub = lane / R;
-  const BSlot& sl = slots[j];
-  const bool on = live(sl);
-  const T beta = (T)sl.beta;
-  const T c = (T)sl.c;
-  const double c64 = sl.c;
-  const int par = sl.iters & 1;
+  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
+  T beta[C], cc[C];
+  double c64[C];
+  bool on[C];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const BSlot& sl = slots[j0 + c];
+    on[c] = live(sl);
+    beta[c] = on[c] ? (T)sl.beta : (T)0;
+    cc[c] = (T)sl.c;
+    c64[c] = sl.c;
+    any |= on[c];
+  }
   const T* __restrict__ pin = par ? v.p1 : v.p0;
   T* __restrict__ pout = par ? v.p0 : v.p1;
   const T* __restrict__ z = v.z;
-  const T* __restrict__ val = bval<T>(m);
-  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
-  const Range rg = task_range(ntasks, G);
-  double acc[1] = {0.0};
-  if (on) {
+  double acc[1][C] = {};
+  if (any) {
+    const Range rg = task_range(m.n_slices * LPR, G);
     for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
       const int64_t row = t * RPW + rsub;
       if (row >= m.n) continue;
       const int64_t s = row / kW, l = row % kW;
       const int64_t base = m.sptr[s];
       const int w = (int)((m.sptr[s + 1] - base) / kW);
-      // Entries are taken kUnroll at a time: all index / value loads, then
-      // all gathers, then the FMAs in entry order (the summation order is
-      // that of the plain loop; the unrolling only raises the number of
-      // loads in flight per wavefront).
-      T a = (T)0;
-      for (int k0 = 0; k0 < w; k0 += kUnroll) {
-        int32_t cu[kUnroll];
-        T vu[kUnroll], zu[kUnroll], pu[kUnroll];
-        // loads past the row's end stay in bounds (next slice or the zero
-        // tail of the arrays); their values are replaced by 0
+      T a[C] = {};
+      row_product<T, T, R, C, true, false>(m, bval<T>(m), base, w, l, j0, z, pin,
+                                    [&](int c, T zz, T pp) { return fma(beta[c], pp, zz); }, a);
+      const int64_t idx = row * R + j0;
+      const Pack<T, C> zi = vload<T, C>(z + idx), pi = vload<T, C>(pin + idx);
+      const double mi = m.mass[row], kd = m.kdiag[row];
+      Pack<T, C> pn, qv;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int64_t e = base + (int64_t)(k0 + u) * kW + l;
-          cu[u] = m.col[e];
-          const T vv = val[e];
-          vu[u] = k0 + u < w ? vv : (T)0;
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int64_t cj = (int64_t)cu[u] * R + j;
-          zu[u] = z[cj];
-          pu[u] = pin[cj];
-        }
-        // entries past the row's end have value 0 and gather row 0 (finite):
-        // their FMA leaves a unchanged, so no branch keeps the gathers apart
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) a = fma(vu[u], fma(beta, pu[u], zu[u]), a);
+      for (int c = 0; c < C; ++c) {
+        pn.v[c] = fma(beta[c], pi.v[c], zi.v[c]);
+        const T d = (T)(mi + c64[c] * kd);
+        qv.v[c] = fma(d, pn.v[c], cc[c] * a[c]);
+        if (on[c]) acc[0][c] += (double)pn.v[c] * (double)qv.v[c];
       }
-      const int64_t idx = row * R + j;
-      const T pn = fma(beta, pin[idx], z[idx]);
-      const T d = (T)(m.mass[row] + c64 * m.kdiag[row]);
-      const T qv = fma(d, pn, c * a);
-      pout[idx] = pn;
-      v.q[idx] = qv;
-      acc[0] += (double)pn * (double)qv;
+      vstore<T, C>(pout + idx, pn);
+      vstore<T, C>(v.q + idx, qv);
     }
   }
-  col_sum<R, 1>(acc, lds);
-  if (threadIdx.x < R) part[(Q_PQ * R + threadIdx.x) * G + lblock(G)] = acc[0];
+  double tot[1];
+  col_sum<R, C, 1>(acc, lds, tot);
+  if (threadIdx.x < R) part[(Q_PQ * R + threadIdx.x) * G + lblock(G)] = tot[0];
 }
 
+// x += alpha p (FP64, or FP32 increments when mixed), r -= alpha q,
+// z = r / diag(S); partials (r, z), (r, r) per column. x of columns that are
+// not iterating is left unchanged.
 template <typename T, bool MIXED, int R>
-__global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, BSlot* slots, double* part, int G) {
+__global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+                                                int par) {
+  using Gm = Geo<T, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[2 * kWpb * R];
-  constexpr int RPW = kW / R;
   const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
-  const int j = lane % R, rsub = lane / R;
-  const BSlot& sl = slots[j];
-  const bool on = live(sl);
-  const double a64 = sl.alpha;
-  const T alpha = (T)a64;
-  const double c64 = sl.c;
-  const int par = sl.iters & 1;
+  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
+  T alpha[C];
+  double a64[C], c64[C];
+  bool on[C];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const BSlot& sl = slots[j0 + c];
+    on[c] = live(sl);
+    a64[c] = on[c] ? sl.alpha : 0.0;
+    alpha[c] = (T)a64[c];
+    c64[c] = sl.c;
+    any |= on[c];
+  }
   const T* __restrict__ p = par ? v.p0 : v.p1;  // written by kb_dir_spmv this iteration
-  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
-  const Range rg = task_range(ntasks, G);
-  double acc[2] = {0.0, 0.0};
-  if (on) {
+  double acc[2][C] = {};
+  if (any) {
+    const Range rg = task_range(m.n_slices * LPR, G);
     for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
       const int64_t row = t * RPW + rsub;
       if (row >= m.n) continue;
-      const int64_t idx = row * R + j;
-      const T pv = p[idx];
-      if (MIXED) v.xacc[idx] = fma(alpha, pv, v.xacc[idx]);
-      else v.x[idx] = fma(a64, (double)pv, v.x[idx]);
-      const T rv = fma(-alpha, v.q[idx], v.r[idx]);
-      const T d = (T)(m.mass[row] + c64 * m.kdiag[row]);
-      const T zv = rv / d;
-      v.r[idx] = rv;
-      v.z[idx] = zv;
-      acc[0] += (double)rv * (double)zv;
-      acc[1] += (double)rv * (double)rv;
+      const int64_t idx = row * R + j0;
+      const Pack<T, C> pv = vload<T, C>(p + idx), qv = vload<T, C>(v.q + idx);
+      Pack<T, C> rv = vload<T, C>(v.r + idx), zv;
+      if constexpr (MIXED) {
+        Pack<float, C> xa = vload<float, C>(v.xacc + idx);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          if (on[c]) xa.v[c] = fma(alpha[c], pv.v[c], xa.v[c]);
+        vstore<float, C>(v.xacc + idx, xa);
+      } else {
+        Pack<double, C> xv = vload<double, C>(v.x + idx);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          if (on[c]) xv.v[c] = fma(a64[c], (double)pv.v[c], xv.v[c]);
+        vstore<double, C>(v.x + idx, xv);
+      }
+      const double mi = m.mass[row], kd = m.kdiag[row];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        rv.v[c] = fma(-alpha[c], qv.v[c], rv.v[c]);
+        const T d = (T)(mi + c64[c] * kd);
+        zv.v[c] = rv.v[c] / d;
+        if (on[c]) {
+          acc[0][c] += (double)rv.v[c] * (double)zv.v[c];
+          acc[1][c] += (double)rv.v[c] * (double)rv.v[c];
+        }
+      }
+      vstore<T, C>(v.r + idx, rv);
+      vstore<T, C>(v.z + idx, zv);
     }
   }
-  col_sum<R, 2>(acc, lds);
+  double tot[2];
+  col_sum<R, C, 2>(acc, lds, tot);
   if (threadIdx.x < R) {
     const int lb = lblock(G);
-    part[(Q_RZ * R + threadIdx.x) * G + lb] = acc[0];
-    part[(Q_RR * R + threadIdx.x) * G + lb] = acc[1];
+    part[(Q_RZ * R + threadIdx.x) * G + lb] = tot[0];
+    part[(Q_RR * R + threadIdx.x) * G + lb] = tot[1];
   }
 }
 
 // mixed: fold the FP32 increments into the FP64 solution for flagged columns
 template <int R>
 __global__ __launch_bounds__(kB) void kb_fold(BMat m, BVec<float> v, const BSlot* slots, int G) {
-  constexpr int RPW = kW / R;
+  using Gm = Geo<float, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
-  const int j = lane % R, rsub = lane / R;
-  if (!slots[j].fold) return;
-  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
-  const Range rg = task_range(ntasks, G);
+  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
+  bool f[C];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    f[c] = slots[j0 + c].active && slots[j0 + c].fold;
+    any |= f[c];
+  }
+  if (!any) return;
+  const Range rg = task_range(m.n_slices * LPR, G);
   for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
     const int64_t row = t * RPW + rsub;
     if (row >= m.n) continue;
-    const int64_t idx = row * R + j;
-    v.x[idx] += (double)v.xacc[idx];
-    v.xacc[idx] = 0.0f;
+    const int64_t idx = row * R + j0;
+    Pack<double, C> xv = vload<double, C>(v.x + idx);
+    Pack<float, C> xa = vload<float, C>(v.xacc + idx);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (f[c]) {
+        xv.v[c] += (double)xa.v[c];
+        xa.v[c] = 0.0f;
+      }
+    vstore<double, C>(v.x + idx, xv);
+    vstore<float, C>(v.xacc + idx, xa);
   }
 }
 
 // FP64 residual r = M phi - S x (FP64 values and x) for flagged columns
-// (mode 0: residual replacement of a mixed solve) or for the columns being
-// initialised (mode 1: x = phi first, r0 = -c K_n phi).
+// (MODE 0: residual replacement of a mixed solve; partials rz, rr and the
+// attainable-accuracy norm) or for the columns being started (MODE 1:
+// x = phi, p = 0, r0 = -c K_n phi; partials rz, rr and ||M phi||^2). Other
+// columns' vectors are left unchanged.
 template <typename T, int R, int MODE>
 __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
                                                   uint64_t mask, SlotScales cs) {
-  __shared__ double lds[4 * kWpb * R];
-  constexpr int RPW = kW / R;
+  using Gm = Geo<T, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
+  __shared__ double lds[3 * kWpb * R];
   const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
-  const int j = lane % R, rsub = lane / R;
-  const BSlot& sl = slots[j];
-  const bool on = MODE == 0 ? (sl.fold != 0) : ((mask >> j) & 1ull) != 0;
-  const double c = MODE == 0 ? sl.c : cs.c[j];
-  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
-  const Range rg = task_range(ntasks, G);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // rz, rr, floor (mode 0) or bb (mode 1)
-  if (on) {
+  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
+  bool on[C];
+  double cc[C];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int j = j0 + c;
+    const BSlot& sl = slots[j];
+    on[c] = MODE == 0 ? (sl.active && sl.fold) : ((mask >> j) & 1ull) != 0;
+    cc[c] = MODE == 0 ? sl.c : cs.c[j];
+    any |= on[c];
+  }
+  double acc[3][C] = {};  // rz, rr, floor norm (MODE 0) or ||M phi||^2 (MODE 1)
+  if (any) {
     const double* __restrict__ src = MODE == 0 ? v.x : v.phi;
+    const Range rg = task_range(m.n_slices * LPR, G);
     for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
       const int64_t row = t * RPW + rsub;
       if (row >= m.n) continue;
       const int64_t s = row / kW, l = row % kW;
       const int64_t base = m.sptr[s];
       const int w = (int)((m.sptr[s + 1] - base) / kW);
-      double a = 0.0, aa = 0.0;
-      for (int k = 0; k < w; ++k) {
-        const int64_t e = base + (int64_t)k * kW + l;
-        const double tv = m.val64[e] * src[(int64_t)m.col[e] * R + j];
-        a += tv;
-        aa += fabs(tv);
-      }
-      const int64_t idx = row * R + j;
+      double a[C] = {}, aa[C] = {};
+      row_product<double, double, R, C, false, false>(m, m.val64, base, w, l, j0, src, nullptr,
+                                                      [&](int, double xx, double) { return xx; }, a);
+      if (MODE == 0)
+        row_product<double, double, R, C, false, true>(m, m.val64, base, w, l, j0, src, nullptr,
+                                                       [&](int, double xx, double) { return fabs(xx); }, aa);
+      const int64_t idx = row * R + j0;
       const double mi = m.mass[row], kd = m.kdiag[row];
-      const double ph = v.phi[idx];
-      const double xi = MODE == 0 ? v.x[idx] : ph;
-      double r64;
-      if (MODE == 0) {
-        r64 = mi * (ph - xi) - c * (kd * xi + a);
-        const double mag = fabs(mi * ph) + fabs(mi * xi) + c * (fabs(kd * xi) + aa);
-        acc[2] += mag * mag;
-      } else {
-        r64 = -c * (kd * ph + a);
-        v.x[idx] = ph;
-        if (v.xacc) v.xacc[idx] = 0.0f;
-        v.p0[idx] = (T)0;
-        v.p1[idx] = (T)0;
-        acc[3] += (mi * ph) * (mi * ph);
+      const Pack<double, C> ph = vload<double, C>(v.phi + idx);
+      Pack<double, C> xv = vload<double, C>(v.x + idx);
+      Pack<T, C> rv = vload<T, C>(v.r + idx), zv = vload<T, C>(v.z + idx);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (!on[c]) continue;
+        double r64;
+        if (MODE == 0) {
+          const double xi = xv.v[c];
+          r64 = mi * (ph.v[c] - xi) - cc[c] * (kd * xi + a[c]);
+          // componentwise magnitude of (|b| + |S||x|)_i; aa = sum_k |val_k| |x_k|
+          const double mag = fabs(mi * ph.v[c]) + fabs(mi * xi) + cc[c] * (fabs(kd * xi) + aa[c]);
+          acc[2][c] += mag * mag;
+        } else {
+          r64 = -cc[c] * (kd * ph.v[c] + a[c]);
+          xv.v[c] = ph.v[c];
+          acc[2][c] += (mi * ph.v[c]) * (mi * ph.v[c]);
+        }
+        const T rt = (T)r64;
+        const T d = (T)(mi + cc[c] * kd);
+        rv.v[c] = rt;
+        zv.v[c] = rt / d;
+        acc[0][c] += (double)rt * (double)zv.v[c];
+        acc[1][c] += r64 * r64;
       }
-      const T rt = (T)r64;
-      const T d = (T)(mi + c * kd);
-      const T zt = rt / d;
-      v.r[idx] = rt;
-      v.z[idx] = zt;
-      acc[0] += (double)rt * (double)zt;
-      acc[1] += r64 * r64;
+      vstore<T, C>(v.r + idx, rv);
+      vstore<T, C>(v.z + idx, zv);
+      if (MODE == 1) {
+        vstore<double, C>(v.x + idx, xv);
+        Pack<T, C> p0 = vload<T, C>(v.p0 + idx), p1 = vload<T, C>(v.p1 + idx);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          if (on[c]) p0.v[c] = p1.v[c] = (T)0;
+        vstore<T, C>(v.p0 + idx, p0);
+        vstore<T, C>(v.p1 + idx, p1);
+        if (v.xacc) {
+          Pack<float, C> xa = vload<float, C>(v.xacc + idx);
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            if (on[c]) xa.v[c] = 0.0f;
+          vstore<float, C>(v.xacc + idx, xa);
+        }
+      }
     }
   }
-  col_sum<R, 4>(acc, lds);
+  double tot[3];
+  col_sum<R, C, 3>(acc, lds, tot);
   if (threadIdx.x < R) {
     const int lb = lblock(G);
-    part[(Q_RZ * R + threadIdx.x) * G + lb] = acc[0];
-    part[(Q_RR * R + threadIdx.x) * G + lb] = acc[1];
-    part[(Q_FL * R + threadIdx.x) * G + lb] = acc[2];
-    part[(Q_BB * R + threadIdx.x) * G + lb] = acc[3];
+    part[(Q_RZ * R + threadIdx.x) * G + lb] = tot[0];
+    part[(Q_RR * R + threadIdx.x) * G + lb] = tot[1];
+    part[((MODE == 0 ? Q_FL : Q_BB) * R + threadIdx.x) * G + lb] = tot[2];
   }
 }
 
 // End of a column: x (+ increments) to the caller's numbering, partials of
 // the true residual and of sum M x^2.
-template <int R>
-__global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<float> vf, BVec<double> vd, bool mixed,
-                                                const BSlot* slots, double* part, int G, uint64_t mask,
-                                                OutPtrs out) {
+template <typename T, int R>
+__global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+                                                uint64_t mask, OutPtrs out) {
+  using Gm = Geo<T, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[2 * kWpb * R];
-  constexpr int RPW = kW / R;
   const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
-  const int j = lane % R, rsub = lane / R;
-  const bool on = ((mask >> j) & 1ull) != 0;
-  const double c = slots[j].c;
-  const double* __restrict__ x = mixed ? vf.x : vd.x;
-  const float* __restrict__ xacc = mixed ? vf.xacc : nullptr;
-  const double* __restrict__ phi = mixed ? vf.phi : vd.phi;
-  double* __restrict__ o = out.p[j];
-  const int64_t ntasks = m.n_slices * R;  // tasks of 64/R rows
-  const Range rg = task_range(ntasks, G);
-  double acc[2] = {0.0, 0.0};
-  if (on) {
+  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
+  bool on[C];
+  double cc[C];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    on[c] = ((mask >> (j0 + c)) & 1ull) != 0;
+    cc[c] = slots[j0 + c].c;
+    any |= on[c];
+  }
+  const bool mixed = v.xacc != nullptr;
+  double acc[2][C] = {};
+  if (any) {
+    const Range rg = task_range(m.n_slices * LPR, G);
     for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
       const int64_t row = t * RPW + rsub;
       if (row >= m.n) continue;
       const int64_t s = row / kW, l = row % kW;
       const int64_t base = m.sptr[s];
       const int w = (int)((m.sptr[s + 1] - base) / kW);
-      double a = 0.0;
+      double a[C] = {};
+      // x = x64 + increments, gathered for the FP64 residual
       for (int k = 0; k < w; ++k) {
         const int64_t e = base + (int64_t)k * kW + l;
-        const int64_t cj = (int64_t)m.col[e] * R + j;
-        const double xj = xacc ? x[cj] + (double)xacc[cj] : x[cj];
-        a += m.val64[e] * xj;
+        const int64_t off = (int64_t)m.col[e] * R + j0;
+        const double vv = m.val64[e];
+        const Pack<double, C> xj = vload<double, C>(v.x + off);
+        Pack<float, C> xaj = {};
+        if (mixed) xaj = vload<float, C>(v.xacc + off);
+#pragma unroll
+        for (int c = 0; c < C; ++c) a[c] += vv * (mixed ? xj.v[c] + (double)xaj.v[c] : xj.v[c]);
       }
-      const int64_t idx = row * R + j;
-      const double xi = xacc ? x[idx] + (double)xacc[idx] : x[idx];
-      const double mi = m.mass[row];
-      const double r64 = mi * (phi[idx] - xi) - c * (m.kdiag[row] * xi + a);
-      if (o) o[m.entity[row]] = xi;
-      acc[0] += r64 * r64;
-      acc[1] += mi * xi * xi;
+      const int64_t idx = row * R + j0;
+      const Pack<double, C> xv = vload<double, C>(v.x + idx), ph = vload<double, C>(v.phi + idx);
+      Pack<float, C> xa = {};
+      if (mixed) xa = vload<float, C>(v.xacc + idx);
+      const double mi = m.mass[row], kd = m.kdiag[row];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (!on[c]) continue;
+        const double xi = mixed ? xv.v[c] + (double)xa.v[c] : xv.v[c];
+        const double r64 = mi * (ph.v[c] - xi) - cc[c] * (kd * xi + a[c]);
+        double* o = out.p[j0 + c];
+        if (o) o[m.entity[row]] = xi;
+        acc[0][c] += r64 * r64;
+        acc[1][c] += mi * xi * xi;
+      }
     }
   }
-  col_sum<R, 2>(acc, lds);
+  double tot[2];
+  col_sum<R, C, 2>(acc, lds, tot);
   if (threadIdx.x < R) {
     const int lb = lblock(G);
-    part[(Q_RES * R + threadIdx.x) * G + lb] = acc[0];
-    part[(Q_EN * R + threadIdx.x) * G + lb] = acc[1];
+    part[(Q_RES * R + threadIdx.x) * G + lb] = tot[0];
+    part[(Q_EN * R + threadIdx.x) * G + lb] = tot[1];
   }
 }
 
@@ -412,7 +558,9 @@ __global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const doub
   }
 }
 
-// phase 2 (after kb_update): rho, beta, stopping test / fold decision
+// phase 2 (after kb_update): rho, beta, stopping test (FP64) or the
+// residual-replacement decision (mixed; considered at the column's own
+// iterations that are multiples of fold_every)
 __global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const double* part, int G, int R, int mixed,
                                                         int max_iter, int fold_every, double delta2) {
   __shared__ double lds[kFinThreads / kW];
@@ -429,13 +577,11 @@ __global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const doubl
     s.iters += 1;
     if (!mixed) {
       if (rr <= s.tol2) s.done = 1;
+      else if (s.iters >= max_iter) s.done = 3;
     } else {
       s.rr_true = 0;
-      s.fold = (rr <= s.tol2 || (s.iters % fold_every == 0 && rr <= delta2 * s.rr_ref)) ? 1 : 0;
-    }
-    if (s.done == 0 && s.iters >= max_iter) {
-      if (mixed) s.fold = 1;  // finish with an FP64 residual; done = 3 set after it
-      else s.done = 3;
+      if (s.iters % fold_every == 0 && (rr <= s.tol2 || rr <= delta2 * s.rr_ref || s.iters >= max_iter))
+        s.fold = 1;
     }
   }
 }
@@ -539,35 +685,37 @@ ifl_status dalloc_b(T** p, size_t count) {
 // ----------------------------------------------------------- launchers
 template <int R>
 struct Launch {
-  static void iterate(const BMat& m, BatchWork& w, bool mixed, int G, hipStream_t s, const BatchParams& prm) {
+  // one CG iteration of the tile; fold kernels only at replacement checks
+  static void iterate(const BMat& m, BatchWork& w, int G, hipStream_t s, const BatchParams& prm, int par,
+                      bool check) {
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
-    if (mixed) kb_dir_spmv<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G);
-    else kb_dir_spmv<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G);
+    if (w.mixed) kb_dir_spmv<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, par);
+    else kb_dir_spmv<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, par);
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
-    if (mixed) {
+    kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R);
+    if (w.mixed) {
       BVec<float> v = bvec<float>(w);
-      kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R);
-      kb_update<float, true, R><<<G, kB, 0, s>>>(m, v, w.slots, w.part, G);
-      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 1, prm.max_iter, prm.fold_every, prm.delta2);
-      kb_fold<R><<<G, kB, 0, s>>>(m, v, w.slots, G);
-      kb_residual<float, R, 0><<<G, kB, 0, s>>>(m, v, w.slots, w.part, G, 0ull, SlotScales{});
-      kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, prm.max_iter);
+      kb_update<float, true, R><<<G, kB, 0, s>>>(m, v, w.slots, w.part, G, par);
+      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 1, prm.max_iter, kFoldEvery, prm.delta2);
+      if (check) {
+        kb_fold<R><<<G, kB, 0, s>>>(m, v, w.slots, G);
+        kb_residual<float, R, 0><<<G, kB, 0, s>>>(m, v, w.slots, w.part, G, 0ull, SlotScales{});
+        kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, prm.max_iter);
+      }
     } else {
-      BVec<double> v = bvec<double>(w);
-      kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R);
-      kb_update<double, false, R><<<G, kB, 0, s>>>(m, v, w.slots, w.part, G);
-      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 0, prm.max_iter, prm.fold_every, prm.delta2);
+      kb_update<double, false, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, par);
+      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 0, prm.max_iter, kFoldEvery, prm.delta2);
     }
   }
-  static void init(const BMat& m, BatchWork& w, bool mixed, int G, hipStream_t s, uint64_t mask,
-                   const SlotScales& cs, double rtol) {
-    if (mixed) kb_residual<float, R, 1><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, mask, cs);
+  static void init(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const SlotScales& cs,
+                   double rtol) {
+    if (w.mixed) kb_residual<float, R, 1><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, mask, cs);
     else kb_residual<double, R, 1><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, mask, cs);
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, mask, rtol, cs);
   }
-  static void finish(const BMat& m, BatchWork& w, bool mixed, int G, hipStream_t s, uint64_t mask,
-                     const OutPtrs& out) {
-    kb_finish<R><<<G, kB, 0, s>>>(m, bvec<float>(w), bvec<double>(w), mixed, w.slots, w.part, G, mask, out);
+  static void finish(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const OutPtrs& out) {
+    if (w.mixed) kb_finish<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, mask, out);
+    else kb_finish<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, mask, out);
     kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, mask);
   }
 };
@@ -587,27 +735,32 @@ void dispatch_R(int R, A&&... a) {
 
 template <int R>
 struct DoIterate {
-  static void run(const BMat& m, BatchWork& w, bool mixed, int G, hipStream_t s, const BatchParams& p) {
-    Launch<R>::iterate(m, w, mixed, G, s, p);
+  static void run(const BMat& m, BatchWork& w, int G, hipStream_t s, const BatchParams& p, int par, bool check) {
+    Launch<R>::iterate(m, w, G, s, p, par, check);
   }
 };
 template <int R>
 struct DoInit {
-  static void run(const BMat& m, BatchWork& w, bool mixed, int G, hipStream_t s, uint64_t mask,
-                  const SlotScales& cs, double rtol) {
-    Launch<R>::init(m, w, mixed, G, s, mask, cs, rtol);
+  static void run(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const SlotScales& cs,
+                  double rtol) {
+    Launch<R>::init(m, w, G, s, mask, cs, rtol);
   }
 };
 template <int R>
 struct DoFinish {
-  static void run(const BMat& m, BatchWork& w, bool mixed, int G, hipStream_t s, uint64_t mask, const OutPtrs& o) {
-    Launch<R>::finish(m, w, mixed, G, s, mask, o);
+  static void run(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const OutPtrs& o) {
+    Launch<R>::finish(m, w, G, s, mask, o);
   }
 };
 
 }  // namespace
 
 // ----------------------------------------------------------------- host
+int batch_lanes_per_row(int R, bool mixed) {
+  const int C = std::min(mixed ? 4 : 2, R);
+  return R / C;
+}
+
 ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   const size_t nr = (size_t)bm.n_pad * R;
   ifl_status st;
@@ -628,8 +781,16 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   IFL_HIPB(hipMemset(w->slots, 0, sizeof(BSlot) * R));
   IFL_HIPB(hipMemset(w->x, 0, sizeof(double) * nr));
   IFL_HIPB(hipMemset(w->phi, 0, sizeof(double) * nr));
+  if (mixed) {
+    float* f32[] = {w->xacc, w->r32, w->z32, w->p32[0], w->p32[1], w->q32};
+    for (float* p : f32) IFL_HIPB(hipMemset(p, 0, sizeof(float) * nr));
+  } else {
+    double* f64[] = {w->r64, w->z64, w->p64[0], w->p64[1], w->q64};
+    for (double* p : f64) IFL_HIPB(hipMemset(p, 0, sizeof(double) * nr));
+  }
   w->R = R;
   w->mixed = mixed;
+  w->iter = 0;
   return IFL_OK;
 }
 
@@ -672,7 +833,9 @@ ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad) {
 
 ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const SlotScales& cs, double rtol,
                       hipStream_t s) {
-  dispatch_R<DoInit>(w.R, bmat(bm), w, w.mixed, bm.G, s, mask, cs, rtol);
+  if (w.iter % kFoldEvery != 0)
+    return fail(IFL_EINVAL, "columns may only enter a tile at iterations that are multiples of kFoldEvery");
+  dispatch_R<DoInit>(w.R, bmat(bm), w, bm.G, s, mask, cs, rtol);
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
 }
@@ -683,10 +846,16 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
 }
 
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s) {
+  if (n_iter % kFoldEvery != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of kFoldEvery");
   const BMat m = bmat(bm);
   BatchParams rest = prm;
   rest.ev_begin = rest.ev_end = nullptr;
-  for (int i = 0; i < n_iter; ++i) dispatch_R<DoIterate>(w.R, m, w, w.mixed, bm.G, s, i == 0 ? prm : rest);
+  for (int i = 0; i < n_iter; ++i) {
+    const int par = (int)(w.iter & 1);
+    const bool check = (w.iter + 1) % kFoldEvery == 0;
+    dispatch_R<DoIterate>(w.R, m, w, bm.G, s, i == 0 ? prm : rest, par, check);
+    ++w.iter;
+  }
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
 }
@@ -694,7 +863,7 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
 ifl_status batch_finish(const BatchMatrix& bm, BatchWork& w, uint64_t mask, double* const* out, hipStream_t s) {
   OutPtrs o;
   for (int j = 0; j < 64; ++j) o.p[j] = (j < w.R && out) ? out[j] : nullptr;
-  dispatch_R<DoFinish>(w.R, bmat(bm), w, w.mixed, bm.G, s, mask, o);
+  dispatch_R<DoFinish>(w.R, bmat(bm), w, bm.G, s, mask, o);
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
 }

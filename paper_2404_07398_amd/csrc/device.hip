@@ -903,7 +903,7 @@ ifl_status filter_single(Handle* h, int32_t n_fields, const double* fields, int3
 
 }  // namespace
 
-BatchMatrix batch_matrix(DeviceState* d, int R) {
+BatchMatrix batch_matrix(DeviceState* d, int R, bool mixed) {
   BatchMatrix bm;
   const DevMatrix& m = d->m;
   bm.n = m.n;
@@ -916,14 +916,15 @@ BatchMatrix batch_matrix(DeviceState* d, int R) {
   bm.kdiag = m.kdiag64;
   bm.mass = m.mass64;
   bm.entity = m.entity;
-  const int64_t tasks = m.n_slices * R;  // tasks of 64/R rows
+  // a task is one wavefront's rows: 64 / lanes-per-row consecutive rows
+  const int64_t tasks = m.n_slices * batch_lanes_per_row(R, mixed);
   int G = (int)std::min<int64_t>(kMaxBlocks, (tasks + kWavesPerBlock - 1) / kWavesPerBlock);
   if (G >= kXcd) G = (G / kXcd) * kXcd;
   bm.G = std::max(1, G);
   return bm;
 }
 
-BatchMatrix handle_batch_matrix(Handle* h, int R) { return batch_matrix(h->dev, R); }
+BatchMatrix handle_batch_matrix(Handle* h, int R, bool mixed) { return batch_matrix(h->dev, R, mixed); }
 double handle_mass_sum(const Handle* h) { return h->dev->m.mass_sum; }
 
 namespace {
@@ -931,7 +932,7 @@ namespace {
 ifl_status ensure_batch(DeviceState* d, int R, bool mixed) {
   if (d->bw.R == R && d->bw.mixed == mixed && d->bw.slots) return IFL_OK;
   batch_free(&d->bw);
-  return batch_alloc(&d->bw, batch_matrix(d, R), R, mixed);
+  return batch_alloc(&d->bw, batch_matrix(d, R, mixed), R, mixed);
 }
 
 // Many columns at once: slots of a tile of R columns are filled from the
@@ -945,7 +946,9 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
   ifl_status st = ensure_batch(d, R, mixed);
   if (st != IFL_OK) return st;
   BatchWork& w = d->bw;
-  const BatchMatrix bm = batch_matrix(d, R);
+  const BatchMatrix bm = batch_matrix(d, R, mixed);
+  // slots left active by an earlier call that stopped on an error
+  if ((st = batch_release(w, ~0ull, s)) != IFL_OK) return st;
   // fields on the device
   const double* fdev = fields;
   if (!is_device_ptr(fields)) {

@@ -279,7 +279,7 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
   wk->L = h->op.field_len;
   s->device = h->opt.device;
   if (hipSetDevice(h->opt.device) != hipSuccess) return fail(IFL_EDEVICE, "hipSetDevice failed");
-  wk->bm = handle_batch_matrix(h, wk->R);
+  wk->bm = handle_batch_matrix(h, wk->R, h->opt.precision == IFL_MIXED);
   const size_t tile = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED) +
                       sizeof(double) * (size_t)wk->R * wk->L;
   {
