@@ -28,6 +28,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# rocprofv3 summary of the default workload: per-launch HBM bytes of the
+# batched SpMV kernel from FETCH_SIZE / WRITE_SIZE counters, scaled by the
+# counters of a plain device copy of known size
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "kb_dir_spmv_f32_R32_icosphere-L9-mask40_64x30_n1.txt")
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` as counted in the committed profile,
+    or None if there is none or the kernel source changed since."""
+    import hashlib
+
+    try:
+        kv = {}
+        for line in open(TRAFFIC_PROFILE):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        src = os.path.join(ROOT, "paper_2404_07398_amd", "csrc", "batch.hip")
+        if kv.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        if kv.get("traffic_kernel") != kernel:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -86,6 +111,87 @@ def cpu_baseline(mesh, fields, ks, budget_s: float = 20.0):
     }
 
 
+def serve_leg(args, ifl):
+    """Continuous-batching server on resident prepared meshes, fed by a
+    Poisson arrival stream; returns latency percentiles and solves/s."""
+    import torch
+
+    import workloads as W
+
+    levels = [int(x) for x in args.serve_levels.split(",") if x]
+    rng = np.random.default_rng(11)
+    handles, meshes, pools = [], [], []
+    t0 = time.time()
+    for L in levels:
+        s = W.icosphere(L, jitter=0.1, seed=1)
+        s = s.with_mask(W.land_mask(s, 0.3, n_blobs=40, seed=2))
+        pool = [np.asarray(W.sphere_k3_field(s, 3000 + 10 * L + i, n_waves=256, device="cuda:0"))
+                for i in range(4)]
+        for n in (1, 2):
+            handles.append(ifl.prepare_mesh(s, ifl.IFL_VERTEX_SCALAR, n, precision=ifl.IFL_MIXED, device=0))
+            meshes.append((L, n, s.h))
+            pools.append(pool)
+    log(f"serving: {len(handles)} resident handles prepared in {time.time() - t0:.1f}s")
+    srv = ifl.Server(64 << 30, slots=args.serve_slots)
+    ids = [srv.add(h) for h in handles]
+    # warm every worker once
+    for i, (L, n, h) in enumerate(meshes):
+        t, _ = srv.submit(ids[i], pools[i][0], np.array([2 * math.pi / (4 * h)]))
+        srv.wait(t, 1)
+    # the stream: uniform mesh and order, 1-32 log-spaced scales in [2h, 32h] wavelengths
+    N = args.serve_requests
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, N))
+    reqs = []
+    for r in range(N):
+        i = int(rng.integers(len(handles)))
+        L, n, h = meshes[i]
+        ns = int(rng.integers(1, 33))
+        ks = np.sort(np.exp(rng.uniform(math.log(2 * math.pi / (32 * h)), math.log(2 * math.pi / (2 * h)), ns)))
+        reqs.append((i, int(rng.integers(4)), ks))
+    torch.cuda.synchronize()
+    tickets = []
+    t_start = time.perf_counter()
+    for r, (i, f, ks) in enumerate(reqs):
+        delay = arrivals[r] - (time.perf_counter() - t_start)
+        if delay > 0:
+            time.sleep(delay)
+        t, out = srv.submit(ids[i], pools[i][f], ks)
+        tickets.append((t, ks.size, i))
+    lat, solves, iters, bad = [], 0, 0, 0
+    per = {}
+    for t, ns, i in tickets:
+        st, stats, out, l = srv.wait(t, ns)
+        del out
+        bad += st != 0
+        lat.append(l)
+        solves += ns
+        iters += sum(x.iterations for x in stats)
+        per.setdefault(meshes[i][:2], []).append(l)
+    el = time.perf_counter() - t_start
+    srv.close()
+    for h in handles:
+        h.close()
+    lat = np.array(lat)
+    return {
+        "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+        "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+        "solves_per_s": round(solves / el, 2),
+        "requests": N,
+        "failed": int(bad),
+        "offered_rate_req_s": args.serve_rate,
+        "completed_rate_req_s": round(N / el, 2),
+        "arrival_window_s": round(float(arrivals[-1]), 3),
+        "drain_s": round(el, 3),
+        "solves": int(solves),
+        "mean_cg_iterations": round(iters / max(1, solves), 1),
+        "p50_latency_ms_by_mesh": {f"L{L}-n{n}": round(float(np.percentile(v, 50)) * 1e3, 1)
+                                   for (L, n), v in sorted(per.items())},
+        "workload": f"Poisson arrivals, {N} requests at {args.serve_rate:g}/s over icosphere levels "
+                    f"{args.serve_levels} (30% land mask) x n in {{1,2}}, 1-32 scales each, mixed precision, "
+                    f"{args.serve_slots} slots per mesh",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,10 +208,19 @@ def main():
                     help="fields for the plain FP64 single-column comparison (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-levels", default="6,7,8,9",
+                    help="icosphere levels of the resident meshes (each prepared for n = 1 and n = 2)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="mean Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-requests", type=int, default=300, help="requests in the arrival stream")
+    ap.add_argument("--serve-slots", type=int, default=8, help="column slots per resident mesh")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device copy of this size (a known-traffic kernel for "
+                         "calibrating HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the filter's independent "
-              "solves would be dealt out per GPU with no communication, which this build does not do.",
+              "solves would be dealt out per GPU with no communication; the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -115,6 +230,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 x {args.copy_probe_mib} MiB device copies")
+        del a, b
     mesh, fields_h, ks = make_workload(args.level, args.mask, args.fields, args.scales, dev)
     precision = ifl.IFL_MIXED if args.precision == "mixed" else ifl.IFL_FP64
     t0 = time.time()
@@ -151,6 +275,13 @@ def main():
     launches, ms, bytes_per = h.profile_read(reset=True)
     mean_s = ms / 1e3 / max(1, launches)
     achieved = bytes_per / mean_s / 1e9 if launches else 0.0
+    if args.batch == 1:
+        kernel = "k_dir_spmv<double, false>" if precision == ifl.IFL_FP64 else "k_dir_spmv<float, true>"
+    else:
+        R = args.batch if args.batch else 32
+        kernel = f"kb_dir_spmv<{'float' if precision == ifl.IFL_MIXED else 'double'}, {R}>"
+    default_workload = (args.level, args.mask, args.fields, args.scales) == (9, 0.4, 64, 30)
+    traffic = recorded_traffic(kernel) if default_workload else None
     value = n_solves * args.steps / el
     res = {
         "metric": "filter solves/s + SpMV HBM GB/s at 2.6M verts; served p50/p99 latency",
@@ -182,8 +313,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "kernel": "kb_dir_spmv" if args.batch != 1 else "k_dir_spmv",
+            "traffic": round(traffic) if traffic else None,
+            "kernel": kernel,
             "launches": launches,
             "mean_launch_us": round(mean_s * 1e6, 3),
             "bytes_per_launch": bytes_per,
@@ -203,10 +334,14 @@ def main():
             "mean_cg_iterations": round(it / (args.plain_fields * ks.size), 2),
         }
         res["speedup_vs_plain_fp64"] = round(value / res["plain_fp64_single_column"]["value"], 3)
+    h.close()
+    if not args.no_serve:
+        log("serving leg ...")
+        res["serving"] = serve_leg(args, ifl)
+        log(f"serving: {res['serving']}")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(mesh, fields_h, ks, args.cpu_budget)
-    h.close()
     print(json.dumps(res), flush=True)
 
 

@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes as C
 import math
 import os
+import time
 
 import numpy as np
 
@@ -386,7 +387,11 @@ class Server:
         return float(lib().ifl_ticket_latency(ticket))
 
     def wait(self, ticket, n_scales: int):
+        """Block until the request is done; returns (status, stats, out,
+        latency in seconds from submit to completion, server clock)."""
         stats = (ifl_solve_stats * max(1, n_scales))()
+        while not self.poll(ticket):  # the latency is final once the ticket is done
+            time.sleep(0.0005)
         lat = float(lib().ifl_ticket_latency(ticket))
         st = lib().ifl_wait(ticket, stats)
         keep = self._keep.pop(ticket.value, None)

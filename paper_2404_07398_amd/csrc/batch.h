@@ -22,7 +22,6 @@ struct BSlot {
   double rr;        // current ||r||^2 (recursive, or FP64 true after a replacement)
   double tol2;      // rtol^2 ||M phi||^2
   double bb;        // ||M phi||^2
-  double rr_ref;    // mixed: ||r||^2 at the last replacement
   double res2;      // final true ||M phi - S x||^2
   double energy2;   // final sum M x^2
   double pad0;
@@ -31,8 +30,7 @@ struct BSlot {
   int32_t iters;    // CG iterations of this column
   int32_t updates;  // mixed: FP64 residual replacements
   int32_t rr_true;  // mixed: rr is an FP64 true residual
-  int32_t fold;     // mixed: fold + replace this iteration
-  int32_t pad1, pad2;
+  int32_t pad1;
 };
 
 // The handle's matrix as the batched kernels see it (device pointers).
@@ -50,8 +48,6 @@ struct BatchMatrix {
 
 struct BatchParams {
   int max_iter = 20000;
-  int fold_every = 4;     // mixed: check for a residual replacement every k iterations
-  double delta2 = 1e-4;   // mixed: replace when ||r||^2 fell by this factor
   hipEvent_t ev_begin = nullptr;  // if set: recorded around the first SpMV launch
   hipEvent_t ev_end = nullptr;
 };
@@ -64,16 +60,19 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
 // Device work space of one tile of R slots (vectors rows x R).
 struct BatchWork {
   int R = 0;
+  int G = 0;  // blocks the partial-sum array was sized for
   bool mixed = false;
   float *r32 = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *xacc = nullptr;
   double *r64 = nullptr, *z64 = nullptr, *p64[2] = {nullptr, nullptr}, *q64 = nullptr;
-  double* x = nullptr;    // FP64 solution, rows x R
+  double* x = nullptr;    // FP64 solution, rows x R (mixed: without the FP32 increments)
+  double* xn = nullptr;   // mixed: second FP64 solution buffer (swapped with x at each fold)
   double* phi = nullptr;  // FP64 fields, rows x R
   double* part = nullptr; // per-(quantity, column, block) partial sums
   BSlot* slots = nullptr;
   BSlot* slots_host = nullptr;  // pinned
   int* flag = nullptr;
   int64_t iter = 0;       // tile iterations so far (parity of the p ping-pong)
+  bool fresh = true;      // mixed: the increments were just folded (read as zero)
 };
 
 // Scale factors c_j of the slots being initialised (kernel argument).
@@ -85,6 +84,8 @@ size_t batch_bytes(int64_t n_pad, int R, bool mixed);
 // Lanes that share one row in a tile of R columns (each lane owns 16 bytes of
 // columns: 4 FP32 or 2 FP64).
 int batch_lanes_per_row(int R, bool mixed);
+// Blocks of the batched SpMV kernel that are resident on the device at once.
+int batch_resident_blocks(int R, bool mixed, int device);
 ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed);
 void batch_free(BatchWork* w);
 

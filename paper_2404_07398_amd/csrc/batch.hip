@@ -16,11 +16,13 @@
 // in device memory; after each reduction phase a small kernel with one
 // workgroup per column finishes that column's sum in a fixed order. Columns
 // enter a tile only at tile iterations that are multiples of kFoldEvery, so
-// all live columns share the parity of the p ping-pong and the iterations at
-// which FP64 residual replacements are considered: one replacement pass
-// serves every column that needs it. A column's arithmetic and reduction
-// order depend neither on the other columns, nor on its slot, nor on when it
-// entered, so a solve gives bitwise the same result alone or in a full tile.
+// all live columns share the parity of the p ping-pong. Mixed tiles fold the
+// FP32 increments of x into FP64 and replace every running column's
+// residual by its FP64 true residual at every kFoldEvery-th iteration, in
+// one pass for the whole tile; a column stops only on such a replaced
+// residual. A column's arithmetic and reduction order depend neither on the
+// other columns, nor on its slot, nor on when it entered, so a solve gives
+// bitwise the same result alone or in a full tile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -95,7 +97,8 @@ struct BVec {
   T* p1;
   T* q;
   float* xacc;   // mixed: FP32 increments since the last fold
-  double* x;     // FP64 solution
+  double* x;     // FP64 solution (mixed: without the increments in xacc)
+  double* xn;    // mixed: the other FP64 solution buffer (target of a fold)
   double* phi;   // FP64 field per column
 };
 
@@ -110,11 +113,8 @@ __device__ __forceinline__ const double* bval<double>(const BMat& m) { return m.
 template <>
 __device__ __forceinline__ const float* bval<float>(const BMat& m) { return m.val32; }
 
-__device__ __forceinline__ int lblock(int G) {
-  const int b = blockIdx.x;
-  if (G % 8) return b;
-  return (b % 8) * (G / 8) + b / 8;
-}
+// partial-sum slot of this block
+__device__ __forceinline__ int lblock(int) { return blockIdx.x; }
 
 // Per-column block sums. Lane l carries columns (l % LPR) * C + c; the
 // result for column t is returned in thread t (t < R), fixed order.
@@ -143,16 +143,24 @@ __device__ __forceinline__ void col_sum(double (&v)[NV][C], double* lds /* NV * 
   }
 }
 
-struct Range {
-  int64_t begin, end;
+// Task walk of this block and wavefront (a task is RPW consecutive rows).
+// XCD x (hardware dispatches workgroups round-robin over the 8 XCDs, so
+// block b runs on XCD b % 8) owns a contiguous eighth of the tasks; inside
+// it, the XCD's blocks and wavefronts take consecutive tasks in turn. With G
+// no larger than the resident block count, the rows in flight on one XCD
+// form a narrow band that advances through its eighth, so the rows that a
+// band's gathers reach (the RCM neighbours before and after it) were touched
+// shortly before or are touched shortly after, in the same XCD's L2.
+struct Walk {
+  int64_t t, end, stride;
 };
 
-// contiguous task range of this logical block; a task is RPW rows
-__device__ __forceinline__ Range task_range(int64_t ntasks, int G) {
-  const int lb = lblock(G);
-  const int64_t per = (ntasks + G - 1) / G;
-  const int64_t b = (int64_t)lb * per;
-  return {b, min(b + per, ntasks)};
+__device__ __forceinline__ Walk task_walk(int64_t ntasks, int G) {
+  const int b = blockIdx.x, wid = threadIdx.x / kW;
+  if (G % 8) return {(int64_t)b * kWpb + wid, ntasks, (int64_t)G * kWpb};
+  const int64_t per = (ntasks + 7) / 8;
+  const int64_t begin = (int64_t)(b % 8) * per;
+  return {begin + (int64_t)(b / 8) * kWpb + wid, min(begin + per, ntasks), (int64_t)(G / 8) * kWpb};
 }
 
 __device__ __forceinline__ bool live(const BSlot& s) { return s.active && s.done == 0; }
@@ -164,44 +172,63 @@ __device__ __forceinline__ bool live(const BSlot& s) { return s.active && s.done
 // past the row's end stay in bounds (the next slice, or the zero tail after
 // the last slice) and their value is replaced by 0, so they leave a
 // unchanged.
-template <typename V, typename T, int R, int C, bool TWO, bool ABS, typename Comb>
+template <typename V, typename T, int R, int C, bool TWO, bool ABS, typename Comb, int U = kUnroll>
 __device__ __forceinline__ void row_product(const BMat& m, const V* __restrict__ val, int64_t base, int w,
                                             int64_t l, int j0, const T* __restrict__ x0,
-                                            const T* __restrict__ x1, Comb comb, T (&a)[C]) {
-  for (int k0 = 0; k0 < w; k0 += kUnroll) {
-    int32_t cu[kUnroll];
-    V vu[kUnroll];
+                                            const T* __restrict__ x1, Comb comb, T (&a)[C], int k_begin = 0) {
+  for (int k0 = k_begin; k0 < w; k0 += U) {
+    int32_t cu[U];
+    V vu[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int64_t e = base + (int64_t)(k0 + u) * kW + l;
       cu[u] = m.col[e];
       const V vv = val[e];
       vu[u] = k0 + u < w ? (ABS ? (V)fabs(vv) : vv) : (V)0;
     }
-    Pack<T, C> g0[kUnroll], g1[kUnroll];
+    Pack<T, C> g0[U], g1[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int64_t off = (int64_t)cu[u] * R + j0;
       g0[u] = vload<T, C>(x0 + off);
       if constexpr (TWO) g1[u] = vload<T, C>(x1 + off);
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int c = 0; c < C; ++c) a[c] = fma((T)vu[u], comb(c, g0[u].v[c], TWO ? g1[u].v[c] : (T)0), a[c]);
   }
 }
 
 // ------------------------------------------------------------ iteration
+constexpr int kHead = 6;  // off-diagonal entries per row gathered in the pipelined head
+
+__device__ __forceinline__ int64_t wave_uniform(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // p_new = z + beta p (own row and gathered neighbours), q = S p_new,
 // partial (p_new, q) per column.
+//
+// The loop over a wavefront's tasks is software-pipelined so that a task
+// costs about one memory round trip instead of three. While the gathers of
+// task i are in flight, the slice bounds of task i + 2 and the column
+// indices of task i + 1 are loaded; after task i's row is computed, the
+// values and own-row operands of task i + 1 are loaded, and they arrive
+// under the gathers of task i + 1. Vector memory operations complete in
+// issue order, so waiting for a batch of loads never waits for the loads
+// issued after it. Rows with more than kHead off-diagonal entries finish
+// the rest unpipelined (the biharmonic operator); the first-order operator
+// on triangle meshes has at most six.
 template <typename T, int R>
 __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
                                                   int par) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[1 * kWpb * R];
-  const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
+  const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
   T beta[C], cc[C];
   double c64[C];
@@ -219,31 +246,101 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
   const T* __restrict__ pin = par ? v.p1 : v.p0;
   T* __restrict__ pout = par ? v.p0 : v.p1;
   const T* __restrict__ z = v.z;
+  const T* __restrict__ val = bval<T>(m);
+  const auto dir = [&](int c, T zz, T pp) { return fma(beta[c], pp, zz); };
   double acc[1][C] = {};
   if (any) {
-    const Range rg = task_range(m.n_slices * LPR, G);
-    for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
-      const int64_t row = t * RPW + rsub;
-      if (row >= m.n) continue;
-      const int64_t s = row / kW, l = row % kW;
-      const int64_t base = m.sptr[s];
-      const int w = (int)((m.sptr[s + 1] - base) / kW);
-      T a[C] = {};
-      row_product<T, T, R, C, true, false>(m, bval<T>(m), base, w, l, j0, z, pin,
-                                    [&](int c, T zz, T pp) { return fma(beta[c], pp, zz); }, a);
+    const Walk wk = task_walk(m.n_slices * LPR, G);
+    const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
+    const int64_t last_slice = m.n_slices - 1;
+    // a task's rows lie in one slice; out-of-range tasks are clamped so that
+    // every load of the loop body is issued unconditionally (a fixed count
+    // of memory operations per iteration keeps the compiler's wait counts
+    // exact), and their results are discarded
+    auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
+    int32_t cu[kHead];
+    T vu[kHead];
+    Pack<T, C> zi, pi;
+    double mi, kd;
+    int64_t base, nb, ne;  // this task's slice base; next task's raw slice bounds
+    int w;
+    auto fetch_idx = [&](int64_t t, int64_t sb) {
+      const int64_t l = (t * RPW + rsub) % kW;
+#pragma unroll
+      for (int u = 0; u < kHead; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
+    };
+    // values are loaded raw (entries past the width are masked where they
+    // are used, so that no instruction consumes the loads early)
+    auto fetch_rest = [&](int64_t t, int64_t sb) {
+      const int64_t row = min(t * RPW + rsub, m.n_slices * kW - 1), l = row % kW;
+#pragma unroll
+      for (int u = 0; u < kHead; ++u) vu[u] = val[sb + (int64_t)u * kW + l];
       const int64_t idx = row * R + j0;
-      const Pack<T, C> zi = vload<T, C>(z + idx), pi = vload<T, C>(pin + idx);
-      const double mi = m.mass[row], kd = m.kdiag[row];
+      zi = vload<T, C>(z + idx);
+      pi = vload<T, C>(pin + idx);
+      mi = m.mass[row];
+      kd = m.kdiag[row];
+    };
+    {
+      const int64_t s0 = slice_of(first);
+      base = wave_uniform(m.sptr[s0]);
+      w = (int)((wave_uniform(m.sptr[s0 + 1]) - base) / kW);
+      fetch_idx(first, base);
+      fetch_rest(first, base);
+      const int64_t s1 = slice_of(first + stride);
+      nb = m.sptr[s1];
+      ne = m.sptr[s1 + 1];
+    }
+    for (int64_t t = first; t < end; t += stride) {
+      const int64_t row = t * RPW + rsub;
+      const int32_t self = (int32_t)min(row, m.n - 1);
+      // (a) gathers of this task; entries past the row's width (padding of
+      // value 0) gather the row itself, a line that is loaded anyway
+      Pack<T, C> g0[kHead], g1[kHead];
+#pragma unroll
+      for (int u = 0; u < kHead; ++u) {
+        const int64_t off = (int64_t)(u < w ? cu[u] : self) * R + j0;
+        g0[u] = vload<T, C>(z + off);
+        g1[u] = vload<T, C>(pin + off);
+      }
+      const int64_t cbase = base;
+      const int cw = w;
+      // (b) slice bounds two tasks ahead, (c) indices of the next task
+      const int64_t tn = t + stride < end ? t + stride : t;
+      const int64_t s2 = slice_of(t + 2 * stride);
+      const int64_t nb2 = m.sptr[s2], ne2 = m.sptr[s2 + 1];
+      base = wave_uniform(nb);
+      w = (int)((wave_uniform(ne) - base) / kW);
+      fetch_idx(tn, base);
+      nb = nb2;
+      ne = ne2;
+      // (d) this task's row (rows past the last dof are padding: zero mass,
+      // diagonal and entries; their p and q stay zero and are never read)
+      T a[C] = {};
+#pragma unroll
+      for (int u = 0; u < kHead; ++u) {
+        const T vm = u < cw ? vu[u] : (T)0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) a[c] = fma(vm, dir(c, g0[u].v[c], g1[u].v[c]), a[c]);
+      }
+      if (cw > kHead)
+        row_product<T, T, R, C, true, false, decltype(dir), kHead>(m, val, cbase, cw, row % kW, j0, z, pin, dir, a,
+                                                                    kHead);
+      const bool real = row < m.n;
+      const int64_t idx = row * R + j0;
       Pack<T, C> pn, qv;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         pn.v[c] = fma(beta[c], pi.v[c], zi.v[c]);
         const T d = (T)(mi + c64[c] * kd);
         qv.v[c] = fma(d, pn.v[c], cc[c] * a[c]);
-        if (on[c]) acc[0][c] += (double)pn.v[c] * (double)qv.v[c];
+        const double pq = (double)pn.v[c] * (double)qv.v[c];
+        acc[0][c] += (on[c] && real) ? pq : 0.0;
       }
       vstore<T, C>(pout + idx, pn);
       vstore<T, C>(v.q + idx, qv);
+      // (e) values and own row of the next task
+      fetch_rest(tn, base);
     }
   }
   double tot[1];
@@ -254,13 +351,15 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
 // x += alpha p (FP64, or FP32 increments when mixed), r -= alpha q,
 // z = r / diag(S); partials (r, z), (r, r) per column. x of columns that are
 // not iterating is left unchanged.
+// Mixed tiles keep x as an FP64 part plus FP32 increments; 'fresh' means
+// the increments were just folded, so they restart from zero.
 template <typename T, bool MIXED, int R>
 __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
-                                                int par) {
+                                                int par, int fresh) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[2 * kWpb * R];
-  const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
+  const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
   T alpha[C];
   double a64[C], c64[C];
@@ -278,15 +377,16 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
   const T* __restrict__ p = par ? v.p0 : v.p1;  // written by kb_dir_spmv this iteration
   double acc[2][C] = {};
   if (any) {
-    const Range rg = task_range(m.n_slices * LPR, G);
-    for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
+    for (Walk k = task_walk(m.n_slices * LPR, G); k.t < k.end; k.t += k.stride) {
+      const int64_t t = k.t;
       const int64_t row = t * RPW + rsub;
       if (row >= m.n) continue;
       const int64_t idx = row * R + j0;
       const Pack<T, C> pv = vload<T, C>(p + idx), qv = vload<T, C>(v.q + idx);
       Pack<T, C> rv = vload<T, C>(v.r + idx), zv;
       if constexpr (MIXED) {
-        Pack<float, C> xa = vload<float, C>(v.xacc + idx);
+        Pack<float, C> xa = {};
+        if (!fresh) xa = vload<float, C>(v.xacc + idx);
 #pragma unroll
         for (int c = 0; c < C; ++c)
           if (on[c]) xa.v[c] = fma(alpha[c], pv.v[c], xa.v[c]);
@@ -322,123 +422,164 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
   }
 }
 
-// mixed: fold the FP32 increments into the FP64 solution for flagged columns
+// Mixed tiles, every kFoldEvery iterations: the FP32 increments of every
+// column are folded into the FP64 solution (written to the other x buffer,
+// since other blocks still gather this one), and every running column's
+// residual is replaced by the FP64 true residual r = M phi - S x (FP64
+// values, x = x64 + increments), with the partials of (r, z), (r, r) and of
+// the attainable-accuracy norm || |M phi| + |M x| + c |K_n| |x| ||^2.
+// r and z of columns that are not running are overwritten with values
+// nothing reads (a column that enters is started from scratch).
+constexpr int kUnrollX = 4;  // entries per batch of the FP64 + FP32 gathers
+
 template <int R>
-__global__ __launch_bounds__(kB) void kb_fold(BMat m, BVec<float> v, const BSlot* slots, int G) {
+__global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BSlot* slots, double* part, int G) {
   using Gm = Geo<float, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
-  const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
+  __shared__ double lds[3 * kWpb * R];
+  const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
-  bool f[C];
-  bool any = false;
+  bool on[C];
+  double cc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    f[c] = slots[j0 + c].active && slots[j0 + c].fold;
-    any |= f[c];
+    on[c] = live(slots[j0 + c]);
+    cc[c] = slots[j0 + c].c;
   }
-  if (!any) return;
-  const Range rg = task_range(m.n_slices * LPR, G);
-  for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
-    const int64_t row = t * RPW + rsub;
+  double acc[3][C] = {};
+  for (Walk k = task_walk(m.n_slices * LPR, G); k.t < k.end; k.t += k.stride) {
+    const int64_t row = k.t * RPW + rsub;
     if (row >= m.n) continue;
-    const int64_t idx = row * R + j0;
-    Pack<double, C> xv = vload<double, C>(v.x + idx);
-    Pack<float, C> xa = vload<float, C>(v.xacc + idx);
+    const int64_t s = row / kW, l = row % kW;
+    const int64_t base = m.sptr[s];
+    const int w = (int)((m.sptr[s + 1] - base) / kW);
+    double a[C] = {}, aa[C] = {};  // sum val x, sum |val| |x|
+    for (int k0 = 0; k0 < w; k0 += kUnrollX) {
+      int32_t cu[kUnrollX];
+      double vu[kUnrollX];
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      if (f[c]) {
-        xv.v[c] += (double)xa.v[c];
-        xa.v[c] = 0.0f;
+      for (int u = 0; u < kUnrollX; ++u) {
+        const int64_t e = base + (int64_t)(k0 + u) * kW + l;
+        cu[u] = m.col[e];
+        const double vv = m.val64[e];
+        vu[u] = k0 + u < w ? vv : 0.0;
       }
-    vstore<double, C>(v.x + idx, xv);
-    vstore<float, C>(v.xacc + idx, xa);
+      Pack<double, C> gx[kUnrollX];
+      Pack<float, C> ga[kUnrollX];
+#pragma unroll
+      for (int u = 0; u < kUnrollX; ++u) {
+        const int64_t off = (int64_t)cu[u] * R + j0;
+        gx[u] = vload<double, C>(v.x + off);
+        ga[u] = vload<float, C>(v.xacc + off);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnrollX; ++u)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const double xf = gx[u].v[c] + (double)ga[u].v[c];
+          a[c] = fma(vu[u], xf, a[c]);
+          aa[c] = fma(fabs(vu[u]), fabs(xf), aa[c]);
+        }
+    }
+    const int64_t idx = row * R + j0;
+    const double mi = m.mass[row], kd = m.kdiag[row];
+    const Pack<double, C> ph = vload<double, C>(v.phi + idx), xv = vload<double, C>(v.x + idx);
+    const Pack<float, C> xa = vload<float, C>(v.xacc + idx);
+    Pack<double, C> xn;
+    Pack<float, C> rv, zv;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const double xf = xv.v[c] + (double)xa.v[c];
+      xn.v[c] = xf;
+      const double r64 = mi * (ph.v[c] - xf) - cc[c] * (kd * xf + a[c]);
+      const float rt = (float)r64;
+      const float d = (float)(mi + cc[c] * kd);
+      rv.v[c] = rt;
+      zv.v[c] = rt / d;
+      if (on[c]) {
+        const double mag = fabs(mi * ph.v[c]) + fabs(mi * xf) + cc[c] * (fabs(kd * xf) + aa[c]);
+        acc[0][c] += (double)rt * (double)zv.v[c];
+        acc[1][c] += r64 * r64;
+        acc[2][c] += mag * mag;
+      }
+    }
+    vstore<double, C>(v.xn + idx, xn);
+    vstore<float, C>(v.r + idx, rv);
+    vstore<float, C>(v.z + idx, zv);
+  }
+  double tot[3];
+  col_sum<R, C, 3>(acc, lds, tot);
+  if (threadIdx.x < R) {
+    const int lb = lblock(G);
+    part[(Q_RZ * R + threadIdx.x) * G + lb] = tot[0];
+    part[(Q_RR * R + threadIdx.x) * G + lb] = tot[1];
+    part[(Q_FL * R + threadIdx.x) * G + lb] = tot[2];
   }
 }
 
-// FP64 residual r = M phi - S x (FP64 values and x) for flagged columns
-// (MODE 0: residual replacement of a mixed solve; partials rz, rr and the
-// attainable-accuracy norm) or for the columns being started (MODE 1:
-// x = phi, p = 0, r0 = -c K_n phi; partials rz, rr and ||M phi||^2). Other
-// columns' vectors are left unchanged.
-template <typename T, int R, int MODE>
-__global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
-                                                  uint64_t mask, SlotScales cs) {
+// Start of the columns in 'mask': x = phi, p = 0, increments 0 and the
+// FP64 residual of the residual form, r0 = M phi - S phi = -c K_n phi, with
+// the partials of (r, z), (r, r) and ||M phi||^2. Other columns' vectors are
+// left unchanged.
+template <typename T, int R>
+__global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, int G, uint64_t mask,
+                                               SlotScales cs) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[3 * kWpb * R];
-  const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
+  const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
   bool on[C];
   double cc[C];
   bool any = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const int j = j0 + c;
-    const BSlot& sl = slots[j];
-    on[c] = MODE == 0 ? (sl.active && sl.fold) : ((mask >> j) & 1ull) != 0;
-    cc[c] = MODE == 0 ? sl.c : cs.c[j];
+    on[c] = ((mask >> (j0 + c)) & 1ull) != 0;
+    cc[c] = cs.c[j0 + c];
     any |= on[c];
   }
-  double acc[3][C] = {};  // rz, rr, floor norm (MODE 0) or ||M phi||^2 (MODE 1)
+  double acc[3][C] = {};  // rz, rr, ||M phi||^2
   if (any) {
-    const double* __restrict__ src = MODE == 0 ? v.x : v.phi;
-    const Range rg = task_range(m.n_slices * LPR, G);
-    for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
-      const int64_t row = t * RPW + rsub;
+    for (Walk k = task_walk(m.n_slices * LPR, G); k.t < k.end; k.t += k.stride) {
+      const int64_t row = k.t * RPW + rsub;
       if (row >= m.n) continue;
       const int64_t s = row / kW, l = row % kW;
       const int64_t base = m.sptr[s];
       const int w = (int)((m.sptr[s + 1] - base) / kW);
-      double a[C] = {}, aa[C] = {};
-      row_product<double, double, R, C, false, false>(m, m.val64, base, w, l, j0, src, nullptr,
+      double a[C] = {};
+      row_product<double, double, R, C, false, false>(m, m.val64, base, w, l, j0, v.phi, nullptr,
                                                       [&](int, double xx, double) { return xx; }, a);
-      if (MODE == 0)
-        row_product<double, double, R, C, false, true>(m, m.val64, base, w, l, j0, src, nullptr,
-                                                       [&](int, double xx, double) { return fabs(xx); }, aa);
       const int64_t idx = row * R + j0;
       const double mi = m.mass[row], kd = m.kdiag[row];
       const Pack<double, C> ph = vload<double, C>(v.phi + idx);
       Pack<double, C> xv = vload<double, C>(v.x + idx);
       Pack<T, C> rv = vload<T, C>(v.r + idx), zv = vload<T, C>(v.z + idx);
+      Pack<T, C> p0 = vload<T, C>(v.p0 + idx), p1 = vload<T, C>(v.p1 + idx);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         if (!on[c]) continue;
-        double r64;
-        if (MODE == 0) {
-          const double xi = xv.v[c];
-          r64 = mi * (ph.v[c] - xi) - cc[c] * (kd * xi + a[c]);
-          // componentwise magnitude of (|b| + |S||x|)_i; aa = sum_k |val_k| |x_k|
-          const double mag = fabs(mi * ph.v[c]) + fabs(mi * xi) + cc[c] * (fabs(kd * xi) + aa[c]);
-          acc[2][c] += mag * mag;
-        } else {
-          r64 = -cc[c] * (kd * ph.v[c] + a[c]);
-          xv.v[c] = ph.v[c];
-          acc[2][c] += (mi * ph.v[c]) * (mi * ph.v[c]);
-        }
+        const double r64 = -cc[c] * (kd * ph.v[c] + a[c]);
         const T rt = (T)r64;
         const T d = (T)(mi + cc[c] * kd);
+        xv.v[c] = ph.v[c];
         rv.v[c] = rt;
         zv.v[c] = rt / d;
+        p0.v[c] = p1.v[c] = (T)0;
         acc[0][c] += (double)rt * (double)zv.v[c];
         acc[1][c] += r64 * r64;
+        acc[2][c] += (mi * ph.v[c]) * (mi * ph.v[c]);
       }
+      vstore<double, C>(v.x + idx, xv);
       vstore<T, C>(v.r + idx, rv);
       vstore<T, C>(v.z + idx, zv);
-      if (MODE == 1) {
-        vstore<double, C>(v.x + idx, xv);
-        Pack<T, C> p0 = vload<T, C>(v.p0 + idx), p1 = vload<T, C>(v.p1 + idx);
+      vstore<T, C>(v.p0 + idx, p0);
+      vstore<T, C>(v.p1 + idx, p1);
+      if (v.xacc) {
+        Pack<float, C> xa = vload<float, C>(v.xacc + idx);
 #pragma unroll
         for (int c = 0; c < C; ++c)
-          if (on[c]) p0.v[c] = p1.v[c] = (T)0;
-        vstore<T, C>(v.p0 + idx, p0);
-        vstore<T, C>(v.p1 + idx, p1);
-        if (v.xacc) {
-          Pack<float, C> xa = vload<float, C>(v.xacc + idx);
-#pragma unroll
-          for (int c = 0; c < C; ++c)
-            if (on[c]) xa.v[c] = 0.0f;
-          vstore<float, C>(v.xacc + idx, xa);
-        }
+          if (on[c]) xa.v[c] = 0.0f;
+        vstore<float, C>(v.xacc + idx, xa);
       }
     }
   }
@@ -448,7 +589,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
     const int lb = lblock(G);
     part[(Q_RZ * R + threadIdx.x) * G + lb] = tot[0];
     part[(Q_RR * R + threadIdx.x) * G + lb] = tot[1];
-    part[((MODE == 0 ? Q_FL : Q_BB) * R + threadIdx.x) * G + lb] = tot[2];
+    part[(Q_BB * R + threadIdx.x) * G + lb] = tot[2];
   }
 }
 
@@ -456,11 +597,11 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
 // the true residual and of sum M x^2.
 template <typename T, int R>
 __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
-                                                uint64_t mask, OutPtrs out) {
+                                                uint64_t mask, OutPtrs out, int fresh) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[2 * kWpb * R];
-  const int lane = threadIdx.x % kW, wid = threadIdx.x / kW;
+  const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
   bool on[C];
   double cc[C];
@@ -471,11 +612,11 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
     cc[c] = slots[j0 + c].c;
     any |= on[c];
   }
-  const bool mixed = v.xacc != nullptr;
+  const bool mixed = v.xacc != nullptr && !fresh;  // increments to add
   double acc[2][C] = {};
   if (any) {
-    const Range rg = task_range(m.n_slices * LPR, G);
-    for (int64_t t = rg.begin + wid; t < rg.end; t += kWpb) {
+    for (Walk k = task_walk(m.n_slices * LPR, G); k.t < k.end; k.t += k.stride) {
+      const int64_t t = k.t;
       const int64_t row = t * RPW + rsub;
       if (row >= m.n) continue;
       const int64_t s = row / kW, l = row % kW;
@@ -558,11 +699,10 @@ __global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const doub
   }
 }
 
-// phase 2 (after kb_update): rho, beta, stopping test (FP64) or the
-// residual-replacement decision (mixed; considered at the column's own
-// iterations that are multiples of fold_every)
+// phase 2 (after kb_update): rho, beta and (FP64) the stopping test; a
+// mixed column is tested on its replaced FP64 residual only
 __global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const double* part, int G, int R, int mixed,
-                                                        int max_iter, int fold_every, double delta2) {
+                                                        int max_iter) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
@@ -580,19 +720,17 @@ __global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const doubl
       else if (s.iters >= max_iter) s.done = 3;
     } else {
       s.rr_true = 0;
-      if (s.iters % fold_every == 0 && (rr <= s.tol2 || rr <= delta2 * s.rr_ref || s.iters >= max_iter))
-        s.fold = 1;
     }
   }
 }
 
-// phase 3 (mixed, after kb_residual mode 0): replaced residual
+// phase 3 (mixed, after kb_replace): replaced residual and stopping test
 __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const double* part, int G, int R,
                                                            int max_iter) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
-  if (!s.active || !s.fold) return;
+  if (!live(s)) return;
   const double rz = fin_sum(part + (Q_RZ * R + j) * G, G, lds);
   const double rr = fin_sum(part + (Q_RR * R + j) * G, G, lds);
   const double fl = fin_sum(part + (Q_FL * R + j) * G, G, lds);
@@ -600,17 +738,15 @@ __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const do
     s.rho = rz;
     s.beta = rz / s.rho_prev;
     s.rr = rr;
-    s.rr_ref = rr;
     s.rr_true = 1;
     s.updates += 1;
-    s.fold = 0;
     const double floor2 = fl * (kFloor * kU) * (kFloor * kU);
     if (rr <= fmax(s.tol2, floor2)) s.done = 1;
     else if (s.iters >= max_iter) s.done = 3;
   }
 }
 
-// start of a column (after kb_residual mode 1)
+// start of a column (after kb_start)
 __global__ __launch_bounds__(kFinThreads) void kf_init(BSlot* slots, const double* part, int G, int R, uint64_t mask,
                                                         double rtol, SlotScales cs) {
   __shared__ double lds[kFinThreads / kW];
@@ -629,11 +765,9 @@ __global__ __launch_bounds__(kFinThreads) void kf_init(BSlot* slots, const doubl
     s.rr = rr;
     s.bb = bb;
     s.tol2 = rtol * rtol * bb;
-    s.rr_ref = rr;
     s.iters = 0;
     s.updates = 0;
     s.rr_true = 1;
-    s.fold = 0;
     s.active = 1;
     s.done = rr <= s.tol2 ? 1 : 0;
   }
@@ -644,7 +778,6 @@ __global__ void kf_release(BSlot* slots, int R, uint64_t mask) {
   if (j < R && ((mask >> j) & 1ull)) {
     slots[j].active = 0;
     slots[j].done = 0;
-    slots[j].fold = 0;
   }
 }
 
@@ -665,9 +798,9 @@ __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const dou
 template <typename T>
 BVec<T> bvec(BatchWork& w) {
   if constexpr (sizeof(T) == 4) {
-    return BVec<T>{w.r32, w.z32, w.p32[0], w.p32[1], w.q32, w.xacc, w.x, w.phi};
+    return BVec<T>{w.r32, w.z32, w.p32[0], w.p32[1], w.q32, w.xacc, w.x, w.xn, w.phi};
   } else {
-    return BVec<T>{w.r64, w.z64, w.p64[0], w.p64[1], w.q64, nullptr, w.x, w.phi};
+    return BVec<T>{w.r64, w.z64, w.p64[0], w.p64[1], w.q64, nullptr, w.x, nullptr, w.phi};
   }
 }
 
@@ -685,37 +818,41 @@ ifl_status dalloc_b(T** p, size_t count) {
 // ----------------------------------------------------------- launchers
 template <int R>
 struct Launch {
-  // one CG iteration of the tile; fold kernels only at replacement checks
+  // one CG iteration of the tile; on a check iteration of a mixed tile also
+  // the fold and residual replacement of every running column
   static void iterate(const BMat& m, BatchWork& w, int G, hipStream_t s, const BatchParams& prm, int par,
                       bool check) {
+    const int fresh = w.fresh ? 1 : 0;
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
     if (w.mixed) kb_dir_spmv<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, par);
     else kb_dir_spmv<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, par);
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
     kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R);
     if (w.mixed) {
-      BVec<float> v = bvec<float>(w);
-      kb_update<float, true, R><<<G, kB, 0, s>>>(m, v, w.slots, w.part, G, par);
-      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 1, prm.max_iter, kFoldEvery, prm.delta2);
+      kb_update<float, true, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, par, fresh);
+      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 1, prm.max_iter);
+      w.fresh = false;
       if (check) {
-        kb_fold<R><<<G, kB, 0, s>>>(m, v, w.slots, G);
-        kb_residual<float, R, 0><<<G, kB, 0, s>>>(m, v, w.slots, w.part, G, 0ull, SlotScales{});
+        kb_replace<R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G);
         kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, prm.max_iter);
+        std::swap(w.x, w.xn);
+        w.fresh = true;
       }
     } else {
-      kb_update<double, false, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, par);
-      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 0, prm.max_iter, kFoldEvery, prm.delta2);
+      kb_update<double, false, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, par, 0);
+      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 0, prm.max_iter);
     }
   }
   static void init(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const SlotScales& cs,
                    double rtol) {
-    if (w.mixed) kb_residual<float, R, 1><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, mask, cs);
-    else kb_residual<double, R, 1><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, mask, cs);
+    if (w.mixed) kb_start<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.part, G, mask, cs);
+    else kb_start<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.part, G, mask, cs);
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, mask, rtol, cs);
   }
   static void finish(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const OutPtrs& out) {
-    if (w.mixed) kb_finish<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, mask, out);
-    else kb_finish<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, mask, out);
+    const int fresh = w.fresh ? 1 : 0;
+    if (w.mixed) kb_finish<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, mask, out, fresh);
+    else kb_finish<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, mask, out, 0);
     kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, mask);
   }
 };
@@ -753,9 +890,33 @@ struct DoFinish {
   }
 };
 
+template <typename T>
+int occupancy_of(int R) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (R) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 1>, kB, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 2>, kB, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 4>, kB, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 8>, kB, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 16>, kB, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 32>, kB, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 64>, kB, 0); break;
+  }
+  return e == hipSuccess ? nb : 0;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- host
+int batch_resident_blocks(int R, bool mixed, int device) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0) cus = 256;
+  int per = mixed ? occupancy_of<float>(R) : occupancy_of<double>(R);
+  if (per <= 0) per = 1;
+  return per * cus;
+}
+
 int batch_lanes_per_row(int R, bool mixed) {
   const int C = std::min(mixed ? 4 : 2, R);
   return R / C;
@@ -766,7 +927,8 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   ifl_status st;
   if (mixed) {
     if ((st = dalloc_b(&w->r32, nr)) || (st = dalloc_b(&w->z32, nr)) || (st = dalloc_b(&w->p32[0], nr)) ||
-        (st = dalloc_b(&w->p32[1], nr)) || (st = dalloc_b(&w->q32, nr)) || (st = dalloc_b(&w->xacc, nr)))
+        (st = dalloc_b(&w->p32[1], nr)) || (st = dalloc_b(&w->q32, nr)) || (st = dalloc_b(&w->xacc, nr)) ||
+        (st = dalloc_b(&w->xn, nr)))
       return st;
   } else {
     if ((st = dalloc_b(&w->r64, nr)) || (st = dalloc_b(&w->z64, nr)) || (st = dalloc_b(&w->p64[0], nr)) ||
@@ -784,19 +946,22 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   if (mixed) {
     float* f32[] = {w->xacc, w->r32, w->z32, w->p32[0], w->p32[1], w->q32};
     for (float* p : f32) IFL_HIPB(hipMemset(p, 0, sizeof(float) * nr));
+    IFL_HIPB(hipMemset(w->xn, 0, sizeof(double) * nr));
   } else {
     double* f64[] = {w->r64, w->z64, w->p64[0], w->p64[1], w->q64};
     for (double* p : f64) IFL_HIPB(hipMemset(p, 0, sizeof(double) * nr));
   }
   w->R = R;
+  w->G = bm.G;
   w->mixed = mixed;
   w->iter = 0;
+  w->fresh = true;
   return IFL_OK;
 }
 
 void batch_free(BatchWork* w) {
   void* ptrs[] = {w->r32, w->z32, w->p32[0], w->p32[1], w->q32, w->xacc, w->r64, w->z64, w->p64[0], w->p64[1],
-                  w->q64, w->x, w->phi, w->part, w->slots, w->flag};
+                  w->q64, w->x, w->xn, w->phi, w->part, w->slots, w->flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w->slots_host) (void)hipHostFree(w->slots_host);
@@ -804,7 +969,7 @@ void batch_free(BatchWork* w) {
 }
 
 size_t batch_bytes(int64_t n_pad, int R, bool mixed) {
-  const size_t per = mixed ? (5 * 4 + 4 + 8 + 8) : (5 * 8 + 8 + 8);
+  const size_t per = mixed ? (5 * 4 + 4 + 8 + 8 + 8) : (5 * 8 + 8 + 8);
   return (size_t)n_pad * R * per;
 }
 
@@ -833,6 +998,7 @@ ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad) {
 
 ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const SlotScales& cs, double rtol,
                       hipStream_t s) {
+  if (bm.G != w.G) return fail(IFL_EINVAL, "tile work space was sized for another block count");
   if (w.iter % kFoldEvery != 0)
     return fail(IFL_EINVAL, "columns may only enter a tile at iterations that are multiples of kFoldEvery");
   dispatch_R<DoInit>(w.R, bmat(bm), w, bm.G, s, mask, cs, rtol);
@@ -846,6 +1012,7 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
 }
 
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s) {
+  if (bm.G != w.G) return fail(IFL_EINVAL, "tile work space was sized for another block count");
   if (n_iter % kFoldEvery != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of kFoldEvery");
   const BMat m = bmat(bm);
   BatchParams rest = prm;
@@ -861,6 +1028,7 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
 }
 
 ifl_status batch_finish(const BatchMatrix& bm, BatchWork& w, uint64_t mask, double* const* out, hipStream_t s) {
+  if (bm.G != w.G) return fail(IFL_EINVAL, "tile work space was sized for another block count");
   OutPtrs o;
   for (int j = 0; j < 64; ++j) o.p[j] = (j < w.R && out) ? out[j] : nullptr;
   dispatch_R<DoFinish>(w.R, bmat(bm), w, bm.G, s, mask, o);

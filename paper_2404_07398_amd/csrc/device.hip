@@ -916,9 +916,12 @@ BatchMatrix batch_matrix(DeviceState* d, int R, bool mixed) {
   bm.kdiag = m.kdiag64;
   bm.mass = m.mass64;
   bm.entity = m.entity;
-  // a task is one wavefront's rows: 64 / lanes-per-row consecutive rows
+  // a task is one wavefront's rows: 64 / lanes-per-row consecutive rows;
+  // one block per resident slot, so that every XCD's rows advance as one band
   const int64_t tasks = m.n_slices * batch_lanes_per_row(R, mixed);
-  int G = (int)std::min<int64_t>(kMaxBlocks, (tasks + kWavesPerBlock - 1) / kWavesPerBlock);
+  int G = (int)std::min<int64_t>(batch_resident_blocks(R, mixed, d->device),
+                                 (tasks + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (const char* e = std::getenv("IFL_BATCH_BLOCKS")) G = std::max(8, std::min(G, std::atoi(e)));
   if (G >= kXcd) G = (G / kXcd) * kXcd;
   bm.G = std::max(1, G);
   return bm;
@@ -930,9 +933,10 @@ double handle_mass_sum(const Handle* h) { return h->dev->m.mass_sum; }
 namespace {
 
 ifl_status ensure_batch(DeviceState* d, int R, bool mixed) {
-  if (d->bw.R == R && d->bw.mixed == mixed && d->bw.slots) return IFL_OK;
+  const BatchMatrix bm = batch_matrix(d, R, mixed);
+  if (d->bw.R == R && d->bw.mixed == mixed && d->bw.G == bm.G && d->bw.slots) return IFL_OK;
   batch_free(&d->bw);
-  return batch_alloc(&d->bw, batch_matrix(d, R, mixed), R, mixed);
+  return batch_alloc(&d->bw, bm, R, mixed);
 }
 
 // Many columns at once: slots of a tile of R columns are filled from the

@@ -212,6 +212,67 @@ std::vector<int64_t> rcm(int64_t n, const std::vector<int64_t>& ptr, const std::
   return order;
 }
 
+// Morton (Z-order) key of a point quantised to 21 bits per axis.
+uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+// Locality ordering for the GPU kernels. Small graphs: reverse Cuthill-McKee.
+// Larger ones: the nodes are cut into kParts parts of equal size along the
+// Morton curve of their positions (one part per XCD of the device: a
+// kernel's blocks on one XCD walk one contiguous eighth of the rows), and
+// each part is ordered by RCM on its induced subgraph. A part is compact,
+// so its RCM levels are short and a row's neighbours are a few hundred rows
+// away instead of a great circle's worth; the few edges between parts are
+// far apart in the numbering.
+constexpr int kParts = 8;
+constexpr int64_t kPartMin = 32768;  // below this, plain RCM
+
+std::vector<int64_t> locality_order(int64_t n, const std::vector<int64_t>& ptr, const std::vector<int32_t>& adj,
+                                    const std::vector<V3>& pts) {
+  if (n < kPartMin) return rcm(n, ptr, adj);
+  V3 lo = pts[0], hi = pts[0];
+  for (const V3& q : pts) {
+    lo = V3{std::min(lo.x, q.x), std::min(lo.y, q.y), std::min(lo.z, q.z)};
+    hi = V3{std::max(hi.x, q.x), std::max(hi.y, q.y), std::max(hi.z, q.z)};
+  }
+  const double ext = std::max({hi.x - lo.x, hi.y - lo.y, hi.z - lo.z, 1e-300});
+  const double qs = 2097151.0 / ext;
+  std::vector<std::pair<uint64_t, int64_t>> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t ix = (uint64_t)((pts[i].x - lo.x) * qs), iy = (uint64_t)((pts[i].y - lo.y) * qs),
+                   iz = (uint64_t)((pts[i].z - lo.z) * qs);
+    key[i] = {spread3(ix) | (spread3(iy) << 1) | (spread3(iz) << 2), i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int64_t> order;
+  order.reserve(n);
+  std::vector<int64_t> loc(n, -1);
+  for (int p = 0; p < kParts; ++p) {
+    const int64_t b = n * p / kParts, e = n * (p + 1) / kParts;
+    const int64_t m = e - b;
+    for (int64_t i = 0; i < m; ++i) loc[key[b + i].second] = i;
+    std::vector<int64_t> sp(m + 1, 0);
+    std::vector<int32_t> sa;
+    for (int64_t i = 0; i < m; ++i) {
+      const int64_t u = key[b + i].second;
+      for (int64_t k = ptr[u]; k < ptr[u + 1]; ++k)
+        if (loc[adj[k]] >= 0) sa.push_back((int32_t)loc[adj[k]]);
+      sp[i + 1] = (int64_t)sa.size();
+    }
+    const std::vector<int64_t> r = rcm(m, sp, sa);
+    for (int64_t i = 0; i < m; ++i) order.push_back(key[b + r[i]].second);
+    for (int64_t i = 0; i < m; ++i) loc[key[b + i].second] = -1;
+  }
+  return order;
+}
+
 uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
   const unsigned char* b = (const unsigned char*)p;
   for (size_t i = 0; i < n; ++i) {
@@ -335,8 +396,17 @@ ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder
     nv.swap(tvv);
   }
   std::vector<int64_t> ord(n);
-  if (reorder) ord = rcm(n, kp, kc);
-  else std::iota(ord.begin(), ord.end(), 0);
+  if (reorder) {
+    const int dim = m.geometry == IFL_GEOM_SPHERE ? 3 : 2;
+    std::vector<V3> pts(n);
+    for (int64_t i = 0; i < n; ++i) {
+      const double* c = m.coords + dim * vert_of[i];
+      pts[i] = V3{c[0], c[1], dim == 3 ? c[2] : 0.0};
+    }
+    ord = locality_order(n, kp, kc, pts);
+  } else {
+    std::iota(ord.begin(), ord.end(), 0);
+  }
 
   out->placement = IFL_VERTEX_SCALAR;
   out->order = order;
@@ -460,7 +530,13 @@ ifl_status build_cell_vector(const ifl_mesh& m, int32_t order, double A, int32_t
       adj[fill[pr.first]++] = (int32_t)pr.second;
       adj[fill[pr.second]++] = (int32_t)pr.first;
     }
-    cord = rcm(nc, gp, adj);
+    std::vector<V3> pts(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+      V3 p[3];
+      corners(m, m.triangles + 3 * tri_of[c], p);
+      pts[c] = scale(add(add(p[0], p[1]), p[2]), 1.0 / 3.0);
+    }
+    cord = locality_order(nc, gp, adj, pts);
   } else {
     std::iota(cord.begin(), cord.end(), 0);
   }

@@ -124,6 +124,40 @@ def test_ordering_is_a_permutation_and_local():
     h0.close()
 
 
+def test_partitioned_ordering_is_a_permutation_and_local():
+    """Meshes of >= 32768 dofs are ordered by RCM inside 8 Morton-curve
+    parts: almost every edge stays within a short distance, the rest cross
+    parts. The operator is the same up to the permutation."""
+    _lib_or_skip()
+    s = W.icosphere(7, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    h = _host_handle(s)
+    rp, col, val, mass, ent = h.export_operator()
+    n = rp.size - 1
+    assert n >= 32768
+    wet_dofs = np.sort(ent)
+    assert np.unique(wet_dofs).size == n
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    d = np.abs(col - rows)
+    part = np.minimum(np.arange(n) * 8 // n, 7)
+    cross = part[rows] != part[col]
+    # RCM of the whole sphere has level width ~ a great circle (~440 rows
+    # at this level); inside a part the levels are shorter
+    assert np.percentile(d[~cross], 99) < 300
+    # edges between parts: a small share
+    assert np.mean(cross) < 0.03
+    h0 = _host_handle(s, reorder=0)
+    rp0, col0, val0, mass0, ent0 = h0.export_operator()
+    # same operator up to the permutation: compare in mesh numbering
+    import scipy.sparse as sp
+    K = sp.csr_matrix((val, col, rp), shape=(n, n))
+    K0 = sp.csr_matrix((val0, col0, rp0), shape=(n, n))
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), np.searchsorted(ent0, ent))), shape=(n, n))
+    assert abs(P @ K0 @ P.T - K).max() <= 1e-13 * abs(K0).max()
+    h.close()
+    h0.close()
+
+
 def test_prepare_errors():
     _lib_or_skip()
     m = W.split_square(8, jitter=0.1)
