@@ -208,6 +208,7 @@ def main():
                     help="fields for the plain FP64 single-column comparison (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-autotune", action="store_true", help="skip ifl_autotune (default tile and grids)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-levels", default="6,7,8,9",
                     help="icosphere levels of the resident meshes (each prepared for n = 1 and n = 2)")
@@ -244,6 +245,11 @@ def main():
     t0 = time.time()
     h = ifl.prepare_mesh(mesh, ifl.IFL_VERTEX_SCALAR, 1, precision=precision, batch=args.batch, device=0)
     log(f"prepare {time.time() - t0:.1f}s, dofs={h.num_dofs}")
+    tune = None
+    if not args.no_autotune and args.batch != 1:
+        t0 = time.time()
+        tune = h.autotune()
+        log(f"autotune {time.time() - t0:.2f}s: {tune}")
     fields = torch.from_numpy(fields_h).to(dev)
     fb = max(1, min(args.fields, args.field_block))
     out = torch.zeros((fb, ks.size, h.field_length), dtype=torch.float64, device=dev)
@@ -278,7 +284,7 @@ def main():
     if args.batch == 1:
         kernel = "k_dir_spmv<double, false>" if precision == ifl.IFL_FP64 else "k_dir_spmv<float, true>"
     else:
-        R = args.batch if args.batch else 32
+        R = args.batch if args.batch else (tune["batch"] if tune else 32)
         kernel = f"kb_dir_spmv<{'float' if precision == ifl.IFL_MIXED else 'double'}, {R}>"
     default_workload = (args.level, args.mask, args.fields, args.scales) == (9, 0.4, 64, 30)
     traffic = recorded_traffic(kernel) if default_workload else None
@@ -303,7 +309,8 @@ def main():
             "dofs": h.num_dofs,
             "solves_per_step": n_solves,
             "precision": args.precision,
-            "batch": args.batch if args.batch else "auto (32)",
+            "batch": args.batch if args.batch else (f"autotuned ({tune['batch']})" if tune else "auto (32)"),
+            "autotune": tune,
             "rtol": 1e-12,
             "mean_cg_iterations": round(total_it / (n_solves * args.steps), 2),
         },

@@ -229,6 +229,30 @@ const char* ifl_last_error(void);
 ifl_status ifl_profile_read(ifl_handle* h, int64_t* launches, double* total_ms,
                             double* bytes_per_launch, int32_t reset);
 
+/*
+ * Autotuner of the batched engine (the multi-column CG of Sect. 2.2.2 run as
+ * one SpMM-like pass per iteration). Times full tiles of pseudo-random
+ * columns for tile sizes 16, 32 and 64 and several grid sizes of the
+ * gathering and streaming kernels on this handle's matrix in the handle's
+ * current precision, and keeps the fastest per column-iteration: the grid
+ * sizes per tile size, and the tile size used by ifl_filter when
+ * options.batch = 0. Results computed afterwards may differ from untuned
+ * ones in the last bits (another reduction order); runs with the same
+ * tuning are bitwise reproducible. Takes ~0.1-1 s; needs device memory for
+ * one tile of 64 columns. out may be NULL.
+ * Errors: IFL_EINVAL (NULL handle), IFL_EDEVICE (host-only handle or a HIP
+ * failure), IFL_ENOMEM.
+ */
+typedef struct ifl_tune {
+  int32_t batch;                   /* fastest tile size (columns per tile) */
+  int32_t blocks_gather;           /* its blocks of the SpMV / replacement / start / finish kernels */
+  int32_t blocks_update;           /* its blocks of the streaming update kernel */
+  int32_t candidates;              /* configurations timed */
+  double us_per_column_iteration;  /* measured cost of the fastest configuration */
+} ifl_tune;
+
+ifl_status ifl_autotune(ifl_handle* h, ifl_tune* out);
+
 /* ----------------------------------------------------------- serving API */
 typedef struct ifl_server ifl_server;
 typedef struct ifl_ticket ifl_ticket;

@@ -85,6 +85,16 @@ class ifl_solve_stats(C.Structure):
     ]
 
 
+class ifl_tune(C.Structure):
+    _fields_ = [
+        ("batch", C.c_int32),
+        ("blocks_gather", C.c_int32),
+        ("blocks_update", C.c_int32),
+        ("candidates", C.c_int32),
+        ("us_per_column_iteration", C.c_double),
+    ]
+
+
 class IflError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -113,6 +123,7 @@ _PROTOS = {
     "ifl_last_error": (C.c_char_p, []),
     "ifl_profile_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_int32]),
+    "ifl_autotune": (C.c_int32, [C.c_void_p, C.POINTER(ifl_tune)]),
     "ifl_server_create": (C.c_int32, [C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]),
     "ifl_server_add": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "ifl_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p,
@@ -308,6 +319,14 @@ class Handle:
         b = C.c_double()
         _check(lib().ifl_profile_read(self._h, C.byref(n), C.byref(ms), C.byref(b), int(reset)))
         return int(n.value), float(ms.value), float(b.value)
+
+    def autotune(self) -> dict:
+        """Time tile and grid sizes of the batched engine on this handle
+        (``ifl_autotune``); returns the fastest configuration."""
+        t = ifl_tune()
+        _check(lib().ifl_autotune(self._h, C.byref(t)))
+        return {"batch": t.batch, "blocks_gather": t.blocks_gather, "blocks_update": t.blocks_update,
+                "candidates": t.candidates, "us_per_column_iteration": t.us_per_column_iteration}
 
 
 def ifl_prepare(coords, tris, geometry, placement=IFL_VERTEX_SCALAR, n=1, period=None, wet=None, **opts) -> Handle:

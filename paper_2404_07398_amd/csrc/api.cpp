@@ -270,4 +270,11 @@ ifl_status ifl_profile_read(ifl_handle* h, int64_t* launches, double* total_ms, 
   return device_profile_read(h, launches, total_ms, bytes_per_launch, reset);
 }
 
+ifl_status ifl_autotune(ifl_handle* h, ifl_tune* out) {
+  if (!h) return fail(IFL_EINVAL, "handle is NULL");
+  if (!h->dev) return fail(IFL_EDEVICE, "host-only handle (device = -1)");
+  std::lock_guard<std::mutex> lk(h->mu);
+  return device_autotune(h, out);
+}
+
 }  // extern "C"

@@ -43,7 +43,8 @@ struct BatchMatrix {
   const double* kdiag = nullptr;
   const double* mass = nullptr;
   const int64_t* entity = nullptr;
-  int G = 1;  // logical blocks of the row kernels
+  int G = 1;   // blocks of the kernels that gather (SpMV, replacement, start, finish)
+  int Gu = 1;  // blocks of the streaming update kernel
 };
 
 struct BatchParams {
@@ -60,7 +61,7 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
 // Device work space of one tile of R slots (vectors rows x R).
 struct BatchWork {
   int R = 0;
-  int G = 0;  // blocks the partial-sum array was sized for
+  int G = 0, Gu = 0;  // grid sizes the work space (partial-sum array) was made for
   bool mixed = false;
   float *r32 = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *xacc = nullptr;
   double *r64 = nullptr, *z64 = nullptr, *p64[2] = {nullptr, nullptr}, *q64 = nullptr;
@@ -94,6 +95,8 @@ ifl_status batch_clear_flag(BatchWork& w, hipStream_t s);
 // non-finite entries raise the device flag (read with batch_check_flag).
 ifl_status batch_load_column(const BatchMatrix& bm, BatchWork& w, int slot, const double* field_dev, hipStream_t s);
 ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad);
+// A pseudo-random column (for timing trials) into column 'slot' of phi.
+ifl_status batch_load_synthetic(const BatchMatrix& bm, BatchWork& w, int slot, uint64_t seed, hipStream_t s);
 // Start the columns in 'mask' (their phi columns loaded) at scales cs.
 ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const SlotScales& cs, double rtol,
                       hipStream_t s);

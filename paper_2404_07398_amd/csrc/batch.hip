@@ -223,7 +223,7 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 // the rest unpipelined (the biharmonic operator); the first-order operator
 // on triangle meshes has at most six.
 template <typename T, int R>
-__global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+__global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
                                                   int par) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
   }
   double tot[1];
   col_sum<R, C, 1>(acc, lds, tot);
-  if (threadIdx.x < R) part[(Q_PQ * R + threadIdx.x) * G + lblock(G)] = tot[0];
+  if (threadIdx.x < R) part[(Q_PQ * R + threadIdx.x) * Gp + lblock(G)] = tot[0];
 }
 
 // x += alpha p (FP64, or FP32 increments when mixed), r -= alpha q,
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
 // Mixed tiles keep x as an FP64 part plus FP32 increments; 'fresh' means
 // the increments were just folded, so they restart from zero.
 template <typename T, bool MIXED, int R>
-__global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+__global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
                                                 int par, int fresh) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
@@ -417,8 +417,8 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
   col_sum<R, C, 2>(acc, lds, tot);
   if (threadIdx.x < R) {
     const int lb = lblock(G);
-    part[(Q_RZ * R + threadIdx.x) * G + lb] = tot[0];
-    part[(Q_RR * R + threadIdx.x) * G + lb] = tot[1];
+    part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
+    part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
   }
 }
 
@@ -433,7 +433,8 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
 constexpr int kUnrollX = 4;  // entries per batch of the FP64 + FP32 gathers
 
 template <int R>
-__global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BSlot* slots, double* part, int G) {
+__global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BSlot* slots, double* part, int G,
+                                                 int Gp) {
   using Gm = Geo<float, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[3 * kWpb * R];
@@ -511,9 +512,9 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
   col_sum<R, C, 3>(acc, lds, tot);
   if (threadIdx.x < R) {
     const int lb = lblock(G);
-    part[(Q_RZ * R + threadIdx.x) * G + lb] = tot[0];
-    part[(Q_RR * R + threadIdx.x) * G + lb] = tot[1];
-    part[(Q_FL * R + threadIdx.x) * G + lb] = tot[2];
+    part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
+    part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
+    part[(Q_FL * R + threadIdx.x) * Gp + lb] = tot[2];
   }
 }
 
@@ -522,7 +523,7 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
 // the partials of (r, z), (r, r) and ||M phi||^2. Other columns' vectors are
 // left unchanged.
 template <typename T, int R>
-__global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, int G, uint64_t mask,
+__global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, int G, int Gp, uint64_t mask,
                                                SlotScales cs) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
@@ -587,16 +588,16 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
   col_sum<R, C, 3>(acc, lds, tot);
   if (threadIdx.x < R) {
     const int lb = lblock(G);
-    part[(Q_RZ * R + threadIdx.x) * G + lb] = tot[0];
-    part[(Q_RR * R + threadIdx.x) * G + lb] = tot[1];
-    part[(Q_BB * R + threadIdx.x) * G + lb] = tot[2];
+    part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
+    part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
+    part[(Q_BB * R + threadIdx.x) * Gp + lb] = tot[2];
   }
 }
 
 // End of a column: x (+ increments) to the caller's numbering, partials of
 // the true residual and of sum M x^2.
 template <typename T, int R>
-__global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+__global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
                                                 uint64_t mask, OutPtrs out, int fresh) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
@@ -655,8 +656,8 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
   col_sum<R, C, 2>(acc, lds, tot);
   if (threadIdx.x < R) {
     const int lb = lblock(G);
-    part[(Q_RES * R + threadIdx.x) * G + lb] = tot[0];
-    part[(Q_EN * R + threadIdx.x) * G + lb] = tot[1];
+    part[(Q_RES * R + threadIdx.x) * Gp + lb] = tot[0];
+    part[(Q_EN * R + threadIdx.x) * Gp + lb] = tot[1];
   }
 }
 
@@ -668,6 +669,18 @@ __global__ void kb_gather(const double* __restrict__ src, const int64_t* __restr
   const double v = src[entity[i]];
   if (!isfinite(v)) atomicOr(flag, 1);
   phi[i * R + j] = v;
+}
+
+// Pseudo-random column in [-1, 1) for timing trials: splitmix64 (Vigna) of
+// the row index and a seed.
+__global__ void kb_synth(int64_t n, int R, int j, uint64_t seed, double* __restrict__ phi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t x = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  phi[i * R + j] = (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
 // ------------------------------------------------------------ finalizers
@@ -686,12 +699,12 @@ __device__ __forceinline__ double fin_sum(const double* a, int G, double* lds) {
 }
 
 // phase 1 (after kb_dir_spmv): alpha = rho / (p, q)
-__global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const double* part, int G, int R) {
+__global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const double* part, int G, int Gp, int R) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
   if (!live(s)) return;
-  const double pq = fin_sum(part + (Q_PQ * R + j) * G, G, lds);
+  const double pq = fin_sum(part + (Q_PQ * R + j) * Gp, G, lds);
   if (threadIdx.x == 0) {
     const double a = s.rho / pq;
     if (!(pq > 0.0) || !isfinite(a)) s.done = 2;
@@ -701,14 +714,14 @@ __global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const doub
 
 // phase 2 (after kb_update): rho, beta and (FP64) the stopping test; a
 // mixed column is tested on its replaced FP64 residual only
-__global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const double* part, int G, int R, int mixed,
+__global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const double* part, int G, int Gp, int R, int mixed,
                                                         int max_iter) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
   if (!live(s)) return;
-  const double rz = fin_sum(part + (Q_RZ * R + j) * G, G, lds);
-  const double rr = fin_sum(part + (Q_RR * R + j) * G, G, lds);
+  const double rz = fin_sum(part + (Q_RZ * R + j) * Gp, G, lds);
+  const double rr = fin_sum(part + (Q_RR * R + j) * Gp, G, lds);
   if (threadIdx.x == 0) {
     s.rho_prev = s.rho;
     s.rho = rz;
@@ -725,15 +738,15 @@ __global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const doubl
 }
 
 // phase 3 (mixed, after kb_replace): replaced residual and stopping test
-__global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const double* part, int G, int R,
+__global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const double* part, int G, int Gp, int R,
                                                            int max_iter) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
   if (!live(s)) return;
-  const double rz = fin_sum(part + (Q_RZ * R + j) * G, G, lds);
-  const double rr = fin_sum(part + (Q_RR * R + j) * G, G, lds);
-  const double fl = fin_sum(part + (Q_FL * R + j) * G, G, lds);
+  const double rz = fin_sum(part + (Q_RZ * R + j) * Gp, G, lds);
+  const double rr = fin_sum(part + (Q_RR * R + j) * Gp, G, lds);
+  const double fl = fin_sum(part + (Q_FL * R + j) * Gp, G, lds);
   if (threadIdx.x == 0) {
     s.rho = rz;
     s.beta = rz / s.rho_prev;
@@ -747,15 +760,15 @@ __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const do
 }
 
 // start of a column (after kb_start)
-__global__ __launch_bounds__(kFinThreads) void kf_init(BSlot* slots, const double* part, int G, int R, uint64_t mask,
+__global__ __launch_bounds__(kFinThreads) void kf_init(BSlot* slots, const double* part, int G, int Gp, int R, uint64_t mask,
                                                         double rtol, SlotScales cs) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   if (!((mask >> j) & 1ull)) return;
   BSlot& s = slots[j];
-  const double rz = fin_sum(part + (Q_RZ * R + j) * G, G, lds);
-  const double rr = fin_sum(part + (Q_RR * R + j) * G, G, lds);
-  const double bb = fin_sum(part + (Q_BB * R + j) * G, G, lds);
+  const double rz = fin_sum(part + (Q_RZ * R + j) * Gp, G, lds);
+  const double rr = fin_sum(part + (Q_RR * R + j) * Gp, G, lds);
+  const double bb = fin_sum(part + (Q_BB * R + j) * Gp, G, lds);
   if (threadIdx.x == 0) {
     s.c = cs.c[j];
     s.rho = rz;
@@ -781,14 +794,14 @@ __global__ void kf_release(BSlot* slots, int R, uint64_t mask) {
   }
 }
 
-__global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const double* part, int G, int R,
+__global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const double* part, int G, int Gp, int R,
                                                           uint64_t mask) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   if (!((mask >> j) & 1ull)) return;
   BSlot& s = slots[j];
-  const double res = fin_sum(part + (Q_RES * R + j) * G, G, lds);
-  const double en = fin_sum(part + (Q_EN * R + j) * G, G, lds);
+  const double res = fin_sum(part + (Q_RES * R + j) * Gp, G, lds);
+  const double en = fin_sum(part + (Q_EN * R + j) * Gp, G, lds);
   if (threadIdx.x == 0) {
     s.res2 = res;
     s.energy2 = en;
@@ -816,44 +829,52 @@ ifl_status dalloc_b(T** p, size_t count) {
 }
 
 // ----------------------------------------------------------- launchers
+// Grid sizes of a tile: G for the kernels that gather (SpMV, replacement,
+// start, finish), Gu for the streaming update, Gp >= both the stride of the
+// partial-sum array.
+struct Grids {
+  int G, Gu, Gp;
+};
+
 template <int R>
 struct Launch {
   // one CG iteration of the tile; on a check iteration of a mixed tile also
   // the fold and residual replacement of every running column
-  static void iterate(const BMat& m, BatchWork& w, int G, hipStream_t s, const BatchParams& prm, int par,
+  static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int par,
                       bool check) {
     const int fresh = w.fresh ? 1 : 0;
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
-    if (w.mixed) kb_dir_spmv<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, par);
-    else kb_dir_spmv<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, par);
+    if (w.mixed) kb_dir_spmv<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, par);
+    else kb_dir_spmv<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, par);
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
-    kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R);
+    kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R);
     if (w.mixed) {
-      kb_update<float, true, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, par, fresh);
-      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 1, prm.max_iter);
+      kb_update<float, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, par, fresh);
+      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R, 1, prm.max_iter);
       w.fresh = false;
       if (check) {
-        kb_replace<R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G);
-        kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, prm.max_iter);
+        kb_replace<R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp);
+        kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
         std::swap(w.x, w.xn);
         w.fresh = true;
       }
     } else {
-      kb_update<double, false, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, par, 0);
-      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, 0, prm.max_iter);
+      kb_update<double, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.Gu, g.Gp, par, 0);
+      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R, 0, prm.max_iter);
     }
   }
-  static void init(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const SlotScales& cs,
+  static void init(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs,
                    double rtol) {
-    if (w.mixed) kb_start<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.part, G, mask, cs);
-    else kb_start<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.part, G, mask, cs);
-    kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, mask, rtol, cs);
+    if (w.mixed) kb_start<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.part, g.G, g.Gp, mask, cs);
+    else kb_start<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.part, g.G, g.Gp, mask, cs);
+    kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
   }
-  static void finish(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const OutPtrs& out) {
+  static void finish(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const OutPtrs& out) {
     const int fresh = w.fresh ? 1 : 0;
-    if (w.mixed) kb_finish<float, R><<<G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, G, mask, out, fresh);
-    else kb_finish<double, R><<<G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, G, mask, out, 0);
-    kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, G, R, mask);
+    if (w.mixed)
+      kb_finish<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask, out, fresh);
+    else kb_finish<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask, out, 0);
+    kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask);
   }
 };
 
@@ -872,21 +893,21 @@ void dispatch_R(int R, A&&... a) {
 
 template <int R>
 struct DoIterate {
-  static void run(const BMat& m, BatchWork& w, int G, hipStream_t s, const BatchParams& p, int par, bool check) {
-    Launch<R>::iterate(m, w, G, s, p, par, check);
+  static void run(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& p, int par, bool check) {
+    Launch<R>::iterate(m, w, g, s, p, par, check);
   }
 };
 template <int R>
 struct DoInit {
-  static void run(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const SlotScales& cs,
+  static void run(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs,
                   double rtol) {
-    Launch<R>::init(m, w, G, s, mask, cs, rtol);
+    Launch<R>::init(m, w, g, s, mask, cs, rtol);
   }
 };
 template <int R>
 struct DoFinish {
-  static void run(const BMat& m, BatchWork& w, int G, hipStream_t s, uint64_t mask, const OutPtrs& o) {
-    Launch<R>::finish(m, w, G, s, mask, o);
+  static void run(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const OutPtrs& o) {
+    Launch<R>::finish(m, w, g, s, mask, o);
   }
 };
 
@@ -936,7 +957,7 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
       return st;
   }
   if ((st = dalloc_b(&w->x, nr)) || (st = dalloc_b(&w->phi, nr)) ||
-      (st = dalloc_b(&w->part, (size_t)Q_COUNT * R * bm.G)) || (st = dalloc_b(&w->slots, (size_t)R)) ||
+      (st = dalloc_b(&w->part, (size_t)Q_COUNT * R * std::max(bm.G, bm.Gu))) || (st = dalloc_b(&w->slots, (size_t)R)) ||
       (st = dalloc_b(&w->flag, 1)))
     return st;
   IFL_HIPB(hipHostMalloc((void**)&w->slots_host, sizeof(BSlot) * R, hipHostMallocDefault));
@@ -953,6 +974,7 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   }
   w->R = R;
   w->G = bm.G;
+  w->Gu = bm.Gu;
   w->mixed = mixed;
   w->iter = 0;
   w->fresh = true;
@@ -973,6 +995,10 @@ size_t batch_bytes(int64_t n_pad, int R, bool mixed) {
   return (size_t)n_pad * R * per;
 }
 
+static Grids grids(const BatchMatrix& bm) { return Grids{bm.G, bm.Gu, std::max(bm.G, bm.Gu)}; }
+
+static bool same_grids(const BatchMatrix& bm, const BatchWork& w) { return bm.G == w.G && bm.Gu == w.Gu; }
+
 static BMat bmat(const BatchMatrix& bm) {
   return BMat{bm.n, bm.n_slices, bm.sptr, bm.col, bm.val64, bm.val32, bm.kdiag, bm.mass, bm.entity};
 }
@@ -988,6 +1014,13 @@ ifl_status batch_load_column(const BatchMatrix& bm, BatchWork& w, int slot, cons
   return IFL_OK;
 }
 
+ifl_status batch_load_synthetic(const BatchMatrix& bm, BatchWork& w, int slot, uint64_t seed, hipStream_t s) {
+  if (slot < 0 || slot >= w.R) return fail(IFL_EINVAL, "slot out of range");
+  kb_synth<<<(unsigned)((bm.n + 255) / 256), 256, 0, s>>>(bm.n, w.R, slot, seed, w.phi);
+  IFL_HIPB(hipGetLastError());
+  return IFL_OK;
+}
+
 ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad) {
   int flag = 0;
   IFL_HIPB(hipMemcpyAsync(&flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -998,10 +1031,10 @@ ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad) {
 
 ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const SlotScales& cs, double rtol,
                       hipStream_t s) {
-  if (bm.G != w.G) return fail(IFL_EINVAL, "tile work space was sized for another block count");
+  if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
   if (w.iter % kFoldEvery != 0)
     return fail(IFL_EINVAL, "columns may only enter a tile at iterations that are multiples of kFoldEvery");
-  dispatch_R<DoInit>(w.R, bmat(bm), w, bm.G, s, mask, cs, rtol);
+  dispatch_R<DoInit>(w.R, bmat(bm), w, grids(bm), s, mask, cs, rtol);
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
 }
@@ -1012,7 +1045,7 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
 }
 
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s) {
-  if (bm.G != w.G) return fail(IFL_EINVAL, "tile work space was sized for another block count");
+  if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
   if (n_iter % kFoldEvery != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of kFoldEvery");
   const BMat m = bmat(bm);
   BatchParams rest = prm;
@@ -1020,7 +1053,7 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
   for (int i = 0; i < n_iter; ++i) {
     const int par = (int)(w.iter & 1);
     const bool check = (w.iter + 1) % kFoldEvery == 0;
-    dispatch_R<DoIterate>(w.R, m, w, bm.G, s, i == 0 ? prm : rest, par, check);
+    dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, i == 0 ? prm : rest, par, check);
     ++w.iter;
   }
   IFL_HIPB(hipGetLastError());
@@ -1028,10 +1061,10 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
 }
 
 ifl_status batch_finish(const BatchMatrix& bm, BatchWork& w, uint64_t mask, double* const* out, hipStream_t s) {
-  if (bm.G != w.G) return fail(IFL_EINVAL, "tile work space was sized for another block count");
+  if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
   OutPtrs o;
   for (int j = 0; j < 64; ++j) o.p[j] = (j < w.R && out) ? out[j] : nullptr;
-  dispatch_R<DoFinish>(w.R, bmat(bm), w, bm.G, s, mask, o);
+  dispatch_R<DoFinish>(w.R, bmat(bm), w, grids(bm), s, mask, o);
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
 }

@@ -117,6 +117,15 @@ struct DeviceState {
   double prof_bytes = 0.0;  // summed algorithmic bytes of the timed launches
   // batched engine work space (allocated on first use)
   BatchWork bw;
+  // grid sizes picked by the autotuner, per (tile size, precision), and the
+  // tile size it found best per precision (0 = not tuned)
+  struct TunedGrid {
+    int R;
+    bool mixed;
+    int G, Gu;
+  };
+  std::vector<TunedGrid> tuned;
+  int tuned_R[2] = {0, 0};
   double* field_stage = nullptr;  // device copy of host fields
   int64_t field_stage_len = 0;
   double* col_stage = nullptr;    // per-slot outputs for host destinations
@@ -903,6 +912,21 @@ ifl_status filter_single(Handle* h, int32_t n_fields, const double* fields, int3
 
 }  // namespace
 
+// Clamp a grid size to the tile's task count and round it to the XCDs.
+static int fit_grid(const DeviceState* d, int R, bool mixed, int g) {
+  const int64_t tasks = d->m.n_slices * batch_lanes_per_row(R, mixed);
+  const int64_t most = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
+  g = (int)std::min<int64_t>(g, most);
+  if (g >= kXcd) g = (g / kXcd) * kXcd;
+  return std::max(1, g);
+}
+
+static int device_cus(int device) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0) cus = 256;
+  return cus;
+}
+
 BatchMatrix batch_matrix(DeviceState* d, int R, bool mixed) {
   BatchMatrix bm;
   const DevMatrix& m = d->m;
@@ -916,13 +940,19 @@ BatchMatrix batch_matrix(DeviceState* d, int R, bool mixed) {
   bm.kdiag = m.kdiag64;
   bm.mass = m.mass64;
   bm.entity = m.entity;
-  // a task is one wavefront's rows: 64 / lanes-per-row consecutive rows;
-  // one block per resident slot, so that every XCD's rows advance as one band
-  const int64_t tasks = m.n_slices * batch_lanes_per_row(R, mixed);
-  int G = (int)std::min<int64_t>(batch_resident_blocks(R, mixed, d->device),
-                                 (tasks + kWavesPerBlock - 1) / kWavesPerBlock);
-  if (const char* e = std::getenv("IFL_BATCH_BLOCKS")) G = std::max(8, std::min(G, std::atoi(e)));
-  if (G >= kXcd) G = (G / kXcd) * kXcd;
+  // a task is one wavefront's rows: 64 / lanes-per-row consecutive rows.
+  // Defaults: the gathering kernels run one block per CU, so that the rows
+  // in flight on an XCD form a band narrow enough for its L2 to keep the
+  // gathered neighbours; the streaming update runs all resident blocks. The
+  // autotuner may have picked others for this tile size.
+  int G = device_cus(d->device), Gu = batch_resident_blocks(R, mixed, d->device);
+  for (const auto& t : d->tuned)
+    if (t.R == R && t.mixed == mixed) {
+      G = t.G;
+      Gu = t.Gu;
+    }
+  G = fit_grid(d, R, mixed, G);
+  bm.Gu = fit_grid(d, R, mixed, Gu);
   bm.G = std::max(1, G);
   return bm;
 }
@@ -934,7 +964,7 @@ namespace {
 
 ifl_status ensure_batch(DeviceState* d, int R, bool mixed) {
   const BatchMatrix bm = batch_matrix(d, R, mixed);
-  if (d->bw.R == R && d->bw.mixed == mixed && d->bw.G == bm.G && d->bw.slots) return IFL_OK;
+  if (d->bw.R == R && d->bw.mixed == mixed && d->bw.G == bm.G && d->bw.Gu == bm.Gu && d->bw.slots) return IFL_OK;
   batch_free(&d->bw);
   return batch_alloc(&d->bw, bm, R, mixed);
 }
@@ -1081,7 +1111,8 @@ int pick_tile(const Handle* h, int64_t ncols) {
     return R;
   }
   if (ncols <= 1) return 1;
-  R = 32;
+  const int tuned = h->dev->tuned_R[h->opt.precision == IFL_MIXED ? 1 : 0];
+  R = tuned > 0 ? tuned : 32;
   while (R > 2 && R / 2 >= ncols) R /= 2;
   return R;
 }
@@ -1095,6 +1126,96 @@ ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int3
   const int R = pick_tile(h, (int64_t)n_fields * n_scales);
   if (R <= 1) return filter_single(h, n_fields, fields, n_scales, k, out, stats, energy);
   return filter_batched(h, R, n_fields, fields, n_scales, k, out, stats, energy);
+}
+
+// Autotuner of the batched engine: times 8 iterations (two replacement
+// periods) of full tiles of pseudo-random columns for every tile size in
+// {16, 32, 64} and grid sizes of the gathering kernels in {1/2, 1, 2} blocks
+// per CU and of the update in {1, 2} blocks per CU, at a scale where the
+// stiffness term dominates (the columns keep iterating), and keeps the
+// fastest per column-iteration: per tile size for its grid sizes, overall
+// for the default tile size of ifl_filter.
+ifl_status device_autotune(Handle* h, ifl_tune* out) {
+  DeviceState* d = h->dev;
+  IFL_HIP(hipSetDevice(d->device));
+  hipStream_t s = stream_of(h);
+  const bool mixed = h->opt.precision == IFL_MIXED;
+  ifl_status st = ensure_events(d, 2);
+  if (st != IFL_OK) return st;
+  double kd_sum = 0.0;
+  for (int64_t r = 0; r < h->op.n; ++r)
+    for (int64_t e = h->op.row_ptr[r]; e < h->op.row_ptr[r + 1]; ++e)
+      if (h->op.col[e] == r) kd_sum += std::fabs(h->op.val[e]);
+  const double c = 1e4 * d->m.mass_sum / std::max(kd_sum, 1e-300);
+  const int cus = device_cus(d->device);
+  batch_free(&d->bw);  // room for the trial tiles; the cached tile is rebuilt on demand
+  struct Best {
+    int R = 0, G = 0, Gu = 0;
+    double us = 1e300;
+  };
+  Best overall;
+  std::vector<Best> per_R;
+  int tried = 0;
+  for (int R : {16, 32, 64}) {
+    Best b;
+    std::vector<std::pair<int, int>> seen;
+    for (int gm : {1, 2, 4})
+      for (int gu : {2, 4}) {
+        const int G = fit_grid(d, R, mixed, cus * gm / 2), Gu = fit_grid(d, R, mixed, cus * gu / 2);
+        if (std::find(seen.begin(), seen.end(), std::make_pair(G, Gu)) != seen.end()) continue;
+        seen.emplace_back(G, Gu);
+        BatchMatrix bm = batch_matrix(d, R, mixed);
+        bm.G = G;
+        bm.Gu = Gu;
+        BatchWork w;
+        st = batch_alloc(&w, bm, R, mixed);
+        SlotScales cs{};
+        uint64_t mask = 0;
+        for (int j = 0; j < R && st == IFL_OK; ++j) {
+          st = batch_load_synthetic(bm, w, j, 0x5eed0000ull + (uint64_t)j, s);
+          cs.c[j] = c;
+          mask |= 1ull << j;
+        }
+        BatchParams prm;
+        prm.max_iter = 1 << 30;
+        if (st == IFL_OK) st = batch_init(bm, w, mask, cs, 1e-300, s);
+        if (st == IFL_OK) st = batch_iterate(bm, w, kFoldEvery, prm, s);  // warm-up
+        float ms = 0.f;
+        if (st == IFL_OK) {
+          (void)hipEventRecord(d->ev[0], s);
+          st = batch_iterate(bm, w, 2 * kFoldEvery, prm, s);
+          (void)hipEventRecord(d->ev[1], s);
+          if (hipEventSynchronize(d->ev[1]) != hipSuccess || hipEventElapsedTime(&ms, d->ev[0], d->ev[1]) != hipSuccess)
+            st = fail(IFL_EDEVICE, "timing the autotuner trial failed");
+        }
+        batch_free(&w);
+        if (st != IFL_OK) return st;
+        ++tried;
+        const double us = ms * 1e3 / (2.0 * kFoldEvery * R);
+        if (us < b.us) b = Best{R, G, Gu, us};
+      }
+    per_R.push_back(b);
+    if (b.us < overall.us) overall = b;
+  }
+  for (const Best& b : per_R) {
+    bool found = false;
+    for (auto& t : d->tuned)
+      if (t.R == b.R && t.mixed == mixed) {
+        t.G = b.G;
+        t.Gu = b.Gu;
+        found = true;
+      }
+    if (!found) d->tuned.push_back(DeviceState::TunedGrid{b.R, mixed, b.G, b.Gu});
+  }
+  d->tuned_R[mixed ? 1 : 0] = overall.R;
+  if (out) {
+    out->batch = overall.R;
+    out->blocks_gather = overall.G;
+    out->blocks_update = overall.Gu;
+    out->candidates = tried;
+    out->us_per_column_iteration = overall.us;
+  }
+  return IFL_OK;
 }
 
 ifl_status device_apply(Handle* h, double kk, const double* x, double* y) {

@@ -199,6 +199,9 @@ def test_host_only_handle_refuses_solves():
     with pytest.raises(ifl.IflError) as e:
         h.filter(np.zeros(m.n_vertices), [-1.0])
     assert e.value.status == ifl.IFL_EINVAL
+    with pytest.raises(ifl.IflError) as e:
+        h.autotune()
+    assert e.value.status == ifl.IFL_EDEVICE
     h.close()
 
 

@@ -274,6 +274,30 @@ def test_batched_sphere(ifl, n, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_autotuned_batched_sphere(ifl, precision):
+    """After ifl_autotune the default (batch = 0) path runs the tuned tile
+    and grid sizes: still within the bar, and bitwise reproducible."""
+    s, phi = _sphere(5, 0.3)
+    ks = W.log_scales(s.h, 6)
+    fields = np.stack([phi, W.sphere_k3_field(s, 1002, n_waves=256), W.sphere_k3_field(s, 1003, n_waves=256)])
+    op = O.scalar_operator(s, 1)
+    h = _prep(ifl, s, n=1, precision=precision, batch=0)
+    t = h.autotune()
+    print("autotune", t)
+    assert t["batch"] in (16, 32, 64) and t["candidates"] >= 3 and t["us_per_column_iteration"] > 0
+    out, stats = h.filter(fields, ks)
+    out2, _ = h.filter(fields, ks)
+    assert np.array_equal(out, out2)
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    for f in range(fields.shape[0]):
+        ref = O.filter_scalar(op, fields[f], ks)
+        for j in range(len(ks)):
+            err = relative_l2(out[f, j], ref[j])
+            assert err <= tol, (f, j, err)
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_batched_cell_vector(ifl, precision):
     s = W.icosphere(4, jitter=0.1)
     s = s.with_mask(W.land_mask(s, 0.3))
