@@ -63,8 +63,8 @@ struct BatchWork {
   int R = 0;
   int G = 0, Gu = 0;  // grid sizes the work space (partial-sum array) was made for
   bool mixed = false;
-  float *r32 = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *xacc = nullptr;
-  double *r64 = nullptr, *z64 = nullptr, *p64[2] = {nullptr, nullptr}, *q64 = nullptr;
+  float *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *xacc = nullptr;
+  double *z64 = nullptr, *p64[2] = {nullptr, nullptr}, *q64 = nullptr;
   double* x = nullptr;    // FP64 solution, rows x R (mixed: without the FP32 increments)
   double* xn = nullptr;   // mixed: second FP64 solution buffer (swapped with x at each fold)
   double* phi = nullptr;  // FP64 fields, rows x R

@@ -91,8 +91,7 @@ struct BMat {
 
 template <typename T>
 struct BVec {
-  T* r;
-  T* z;
+  T* z;  // preconditioned residual diag(S)^-1 r
   T* p0;
   T* p1;
   T* q;
@@ -348,9 +347,11 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
   if (threadIdx.x < R) part[(Q_PQ * R + threadIdx.x) * Gp + lblock(G)] = tot[0];
 }
 
-// x += alpha p (FP64, or FP32 increments when mixed), r -= alpha q,
-// z = r / diag(S); partials (r, z), (r, r) per column. x of columns that are
-// not iterating is left unchanged.
+// x += alpha p (FP64, or FP32 increments when mixed), z -= alpha q / diag(S)
+// (the preconditioned residual is the stored state; r = diag(S) z is formed
+// where it is needed, so r is neither read nor written); partials (r, z),
+// (r, r) per column. x and z of columns that are not iterating are left
+// unchanged.
 // Mixed tiles keep x as an FP64 part plus FP32 increments; 'fresh' means
 // the increments were just folded, so they restart from zero.
 template <typename T, bool MIXED, int R>
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
       if (row >= m.n) continue;
       const int64_t idx = row * R + j0;
       const Pack<T, C> pv = vload<T, C>(p + idx), qv = vload<T, C>(v.q + idx);
-      Pack<T, C> rv = vload<T, C>(v.r + idx), zv;
+      Pack<T, C> zv = vload<T, C>(v.z + idx);
       if constexpr (MIXED) {
         Pack<float, C> xa = {};
         if (!fresh) xa = vload<float, C>(v.xacc + idx);
@@ -401,15 +402,15 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
       const double mi = m.mass[row], kd = m.kdiag[row];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        rv.v[c] = fma(-alpha[c], qv.v[c], rv.v[c]);
         const T d = (T)(mi + c64[c] * kd);
-        zv.v[c] = rv.v[c] / d;
+        const T zn = fma(-alpha[c], qv.v[c] / d, zv.v[c]);
+        zv.v[c] = on[c] ? zn : zv.v[c];
+        const T rr = d * zv.v[c];  // the residual r = diag(S) z
         if (on[c]) {
-          acc[0][c] += (double)rv.v[c] * (double)zv.v[c];
-          acc[1][c] += (double)rv.v[c] * (double)rv.v[c];
+          acc[0][c] += (double)rr * (double)zv.v[c];
+          acc[1][c] += (double)rr * (double)rr;
         }
       }
-      vstore<T, C>(v.r + idx, rv);
       vstore<T, C>(v.z + idx, zv);
     }
   }
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
 // residual is replaced by the FP64 true residual r = M phi - S x (FP64
 // values, x = x64 + increments), with the partials of (r, z), (r, r) and of
 // the attainable-accuracy norm || |M phi| + |M x| + c |K_n| |x| ||^2.
-// r and z of columns that are not running are overwritten with values
+// z of columns that are not running is overwritten with values
 // nothing reads (a column that enters is started from scratch).
 constexpr int kUnrollX = 4;  // entries per batch of the FP64 + FP32 gathers
 
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
     const Pack<double, C> ph = vload<double, C>(v.phi + idx), xv = vload<double, C>(v.x + idx);
     const Pack<float, C> xa = vload<float, C>(v.xacc + idx);
     Pack<double, C> xn;
-    Pack<float, C> rv, zv;
+    Pack<float, C> zv;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const double xf = xv.v[c] + (double)xa.v[c];
@@ -495,7 +496,6 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
       const double r64 = mi * (ph.v[c] - xf) - cc[c] * (kd * xf + a[c]);
       const float rt = (float)r64;
       const float d = (float)(mi + cc[c] * kd);
-      rv.v[c] = rt;
       zv.v[c] = rt / d;
       if (on[c]) {
         const double mag = fabs(mi * ph.v[c]) + fabs(mi * xf) + cc[c] * (fabs(kd * xf) + aa[c]);
@@ -505,7 +505,6 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
       }
     }
     vstore<double, C>(v.xn + idx, xn);
-    vstore<float, C>(v.r + idx, rv);
     vstore<float, C>(v.z + idx, zv);
   }
   double tot[3];
@@ -554,7 +553,7 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
       const double mi = m.mass[row], kd = m.kdiag[row];
       const Pack<double, C> ph = vload<double, C>(v.phi + idx);
       Pack<double, C> xv = vload<double, C>(v.x + idx);
-      Pack<T, C> rv = vload<T, C>(v.r + idx), zv = vload<T, C>(v.z + idx);
+      Pack<T, C> zv = vload<T, C>(v.z + idx);
       Pack<T, C> p0 = vload<T, C>(v.p0 + idx), p1 = vload<T, C>(v.p1 + idx);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -563,7 +562,6 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
         const T rt = (T)r64;
         const T d = (T)(mi + cc[c] * kd);
         xv.v[c] = ph.v[c];
-        rv.v[c] = rt;
         zv.v[c] = rt / d;
         p0.v[c] = p1.v[c] = (T)0;
         acc[0][c] += (double)rt * (double)zv.v[c];
@@ -571,7 +569,6 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
         acc[2][c] += (mi * ph.v[c]) * (mi * ph.v[c]);
       }
       vstore<double, C>(v.x + idx, xv);
-      vstore<T, C>(v.r + idx, rv);
       vstore<T, C>(v.z + idx, zv);
       vstore<T, C>(v.p0 + idx, p0);
       vstore<T, C>(v.p1 + idx, p1);
@@ -811,9 +808,9 @@ __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const dou
 template <typename T>
 BVec<T> bvec(BatchWork& w) {
   if constexpr (sizeof(T) == 4) {
-    return BVec<T>{w.r32, w.z32, w.p32[0], w.p32[1], w.q32, w.xacc, w.x, w.xn, w.phi};
+    return BVec<T>{w.z32, w.p32[0], w.p32[1], w.q32, w.xacc, w.x, w.xn, w.phi};
   } else {
-    return BVec<T>{w.r64, w.z64, w.p64[0], w.p64[1], w.q64, nullptr, w.x, nullptr, w.phi};
+    return BVec<T>{w.z64, w.p64[0], w.p64[1], w.q64, nullptr, w.x, nullptr, w.phi};
   }
 }
 
@@ -947,12 +944,12 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   const size_t nr = (size_t)bm.n_pad * R;
   ifl_status st;
   if (mixed) {
-    if ((st = dalloc_b(&w->r32, nr)) || (st = dalloc_b(&w->z32, nr)) || (st = dalloc_b(&w->p32[0], nr)) ||
+    if ((st = dalloc_b(&w->z32, nr)) || (st = dalloc_b(&w->p32[0], nr)) ||
         (st = dalloc_b(&w->p32[1], nr)) || (st = dalloc_b(&w->q32, nr)) || (st = dalloc_b(&w->xacc, nr)) ||
         (st = dalloc_b(&w->xn, nr)))
       return st;
   } else {
-    if ((st = dalloc_b(&w->r64, nr)) || (st = dalloc_b(&w->z64, nr)) || (st = dalloc_b(&w->p64[0], nr)) ||
+    if ((st = dalloc_b(&w->z64, nr)) || (st = dalloc_b(&w->p64[0], nr)) ||
         (st = dalloc_b(&w->p64[1], nr)) || (st = dalloc_b(&w->q64, nr)))
       return st;
   }
@@ -965,11 +962,11 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   IFL_HIPB(hipMemset(w->x, 0, sizeof(double) * nr));
   IFL_HIPB(hipMemset(w->phi, 0, sizeof(double) * nr));
   if (mixed) {
-    float* f32[] = {w->xacc, w->r32, w->z32, w->p32[0], w->p32[1], w->q32};
+    float* f32[] = {w->xacc, w->z32, w->p32[0], w->p32[1], w->q32};
     for (float* p : f32) IFL_HIPB(hipMemset(p, 0, sizeof(float) * nr));
     IFL_HIPB(hipMemset(w->xn, 0, sizeof(double) * nr));
   } else {
-    double* f64[] = {w->r64, w->z64, w->p64[0], w->p64[1], w->q64};
+    double* f64[] = {w->z64, w->p64[0], w->p64[1], w->q64};
     for (double* p : f64) IFL_HIPB(hipMemset(p, 0, sizeof(double) * nr));
   }
   w->R = R;
@@ -982,7 +979,7 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
 }
 
 void batch_free(BatchWork* w) {
-  void* ptrs[] = {w->r32, w->z32, w->p32[0], w->p32[1], w->q32, w->xacc, w->r64, w->z64, w->p64[0], w->p64[1],
+  void* ptrs[] = {w->z32, w->p32[0], w->p32[1], w->q32, w->xacc, w->z64, w->p64[0], w->p64[1],
                   w->q64, w->x, w->xn, w->phi, w->part, w->slots, w->flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -991,7 +988,7 @@ void batch_free(BatchWork* w) {
 }
 
 size_t batch_bytes(int64_t n_pad, int R, bool mixed) {
-  const size_t per = mixed ? (5 * 4 + 4 + 8 + 8 + 8) : (5 * 8 + 8 + 8);
+  const size_t per = mixed ? (4 * 4 + 4 + 8 + 8 + 8) : (4 * 8 + 8 + 8);
   return (size_t)n_pad * R * per;
 }
 
