@@ -25,6 +25,7 @@ struct BSlot {
   double res2;      // final true ||M phi - S x||^2
   double energy2;   // final sum M x^2
   double pad0;
+  double alpha_hist[kFoldEvery];  // alpha of each iteration of the current chunk (0 if not iterating)
   int32_t active;   // slot holds a column
   int32_t done;     // 0 running, 1 converged, 2 breakdown, 3 max_iter
   int32_t iters;    // CG iterations of this column
@@ -63,8 +64,10 @@ struct BatchWork {
   int R = 0;
   int G = 0, Gu = 0;  // grid sizes the work space (partial-sum array) was made for
   bool mixed = false;
-  float *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *xacc = nullptr;
-  double *z64 = nullptr, *p64[2] = {nullptr, nullptr}, *q64 = nullptr;
+  // p cycles through kFoldEvery buffers, so that the directions of a whole
+  // chunk are still there when x is updated at its last iteration
+  float *z32 = nullptr, *p32[kFoldEvery] = {}, *q32 = nullptr, *xacc = nullptr;
+  double *z64 = nullptr, *p64[kFoldEvery] = {}, *q64 = nullptr;
   double* x = nullptr;    // FP64 solution, rows x R (mixed: without the FP32 increments)
   double* xn = nullptr;   // mixed: second FP64 solution buffer (swapped with x at each fold)
   double* phi = nullptr;  // FP64 fields, rows x R
@@ -73,7 +76,6 @@ struct BatchWork {
   BSlot* slots_host = nullptr;  // pinned
   int* flag = nullptr;
   int64_t iter = 0;       // tile iterations so far (parity of the p ping-pong)
-  bool fresh = true;      // mixed: the increments were just folded (read as zero)
 };
 
 // Scale factors c_j of the slots being initialised (kernel argument).

@@ -14,15 +14,18 @@
 //
 // Per-column state (alpha, beta, rho, stopping, residual replacement) lives
 // in device memory; after each reduction phase a small kernel with one
-// workgroup per column finishes that column's sum in a fixed order. Columns
-// enter a tile only at tile iterations that are multiples of kFoldEvery, so
-// all live columns share the parity of the p ping-pong. Mixed tiles fold the
-// FP32 increments of x into FP64 and replace every running column's
-// residual by its FP64 true residual at every kFoldEvery-th iteration, in
-// one pass for the whole tile; a column stops only on such a replaced
-// residual. A column's arithmetic and reduction order depend neither on the
-// other columns, nor on its slot, nor on when it entered, so a solve gives
-// bitwise the same result alone or in a full tile.
+// workgroup per column finishes that column's sum in a fixed order. A tile
+// advances in chunks of kFoldEvery iterations and columns enter only at
+// chunk boundaries, so all live columns share the chunk position. Inside a
+// chunk only z (the preconditioned residual) and p change; the directions
+// of the chunk are kept in kFoldEvery buffers and x is updated once, at the
+// chunk's last iteration, from them and each column's alpha history. Mixed
+// tiles then fold that FP32 update into FP64 and replace every running
+// column's residual by its FP64 true residual, in one pass for the whole
+// tile; a mixed column stops only on such a replaced residual. A column's
+// arithmetic and reduction order depend neither on the other columns, nor
+// on its slot, nor on when it entered, so a solve gives bitwise the same
+// result alone or in a full tile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,9 +94,8 @@ struct BMat {
 
 template <typename T>
 struct BVec {
-  T* z;  // preconditioned residual diag(S)^-1 r
-  T* p0;
-  T* p1;
+  T* z;              // preconditioned residual diag(S)^-1 r
+  T* p[kFoldEvery];  // directions of the chunk's iterations (p of iteration k in p[k])
   T* q;
   float* xacc;   // mixed: FP32 increments since the last fold
   double* x;     // FP64 solution (mixed: without the increments in xacc)
@@ -223,7 +225,7 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 // on triangle meshes has at most six.
 template <typename T, int R>
 __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                                  int par) {
+                                                  int k) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[1 * kWpb * R];
@@ -242,8 +244,8 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
     c64[c] = sl.c;
     any |= on[c];
   }
-  const T* __restrict__ pin = par ? v.p1 : v.p0;
-  T* __restrict__ pout = par ? v.p0 : v.p1;
+  const T* __restrict__ pin = v.p[(k + kFoldEvery - 1) % kFoldEvery];  // previous iteration's p
+  T* __restrict__ pout = v.p[k];
   const T* __restrict__ z = v.z;
   const T* __restrict__ val = bval<T>(m);
   const auto dir = [&](int c, T zz, T pp) { return fma(beta[c], pp, zz); };
@@ -347,57 +349,70 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
   if (threadIdx.x < R) part[(Q_PQ * R + threadIdx.x) * Gp + lblock(G)] = tot[0];
 }
 
-// x += alpha p (FP64, or FP32 increments when mixed), z -= alpha q / diag(S)
-// (the preconditioned residual is the stored state; r = diag(S) z is formed
-// where it is needed, so r is neither read nor written); partials (r, z),
-// (r, r) per column. x and z of columns that are not iterating are left
-// unchanged.
-// Mixed tiles keep x as an FP64 part plus FP32 increments; 'fresh' means
-// the increments were just folded, so they restart from zero.
-template <typename T, bool MIXED, int R>
+// z -= alpha q / diag(S) (the preconditioned residual is the stored state;
+// r = diag(S) z is formed where it is needed, so r is neither read nor
+// written); partials (r, z), (r, r) per column. At the last iteration of a
+// chunk (XUP) the chunk's x update is applied at once from the directions
+// kept in p[0..3] and each column's alpha history: x += sum_k alpha_k p_k
+// (FP64), or for mixed tiles the FP32 increments xacc = sum_k alpha_k p_k,
+// which the replacement pass that follows folds into x. z of columns that
+// are not iterating is left unchanged.
+template <typename T, bool MIXED, bool XUP, int R>
 __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                                int par, int fresh) {
+                                                int k) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[2 * kWpb * R];
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
   T alpha[C];
-  double a64[C], c64[C];
+  double c64[C];
+  double ah[kFoldEvery][C];  // alpha history (XUP)
   bool on[C];
   bool any = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const BSlot& sl = slots[j0 + c];
     on[c] = live(sl);
-    a64[c] = on[c] ? sl.alpha : 0.0;
-    alpha[c] = (T)a64[c];
+    alpha[c] = on[c] ? (T)sl.alpha : (T)0;
     c64[c] = sl.c;
     any |= on[c];
+#pragma unroll
+    for (int i = 0; i < kFoldEvery; ++i) {
+      ah[i][c] = XUP ? sl.alpha_hist[i] : 0.0;
+      any |= XUP && ah[i][c] != 0.0;
+    }
   }
-  const T* __restrict__ p = par ? v.p0 : v.p1;  // written by kb_dir_spmv this iteration
   double acc[2][C] = {};
   if (any) {
-    for (Walk k = task_walk(m.n_slices * LPR, G); k.t < k.end; k.t += k.stride) {
-      const int64_t t = k.t;
-      const int64_t row = t * RPW + rsub;
+    for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
+      const int64_t row = wk.t * RPW + rsub;
       if (row >= m.n) continue;
       const int64_t idx = row * R + j0;
-      const Pack<T, C> pv = vload<T, C>(p + idx), qv = vload<T, C>(v.q + idx);
+      const Pack<T, C> qv = vload<T, C>(v.q + idx);
       Pack<T, C> zv = vload<T, C>(v.z + idx);
-      if constexpr (MIXED) {
-        Pack<float, C> xa = {};
-        if (!fresh) xa = vload<float, C>(v.xacc + idx);
+      if constexpr (XUP) {
+        Pack<T, C> pk[kFoldEvery];
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-          if (on[c]) xa.v[c] = fma(alpha[c], pv.v[c], xa.v[c]);
-        vstore<float, C>(v.xacc + idx, xa);
-      } else {
-        Pack<double, C> xv = vload<double, C>(v.x + idx);
+        for (int i = 0; i < kFoldEvery; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
+        if constexpr (MIXED) {
+          Pack<float, C> xa;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-          if (on[c]) xv.v[c] = fma(a64[c], (double)pv.v[c], xv.v[c]);
-        vstore<double, C>(v.x + idx, xv);
+          for (int c = 0; c < C; ++c) {
+            float s = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kFoldEvery; ++i) s = fma((float)ah[i][c], (float)pk[i].v[c], s);
+            xa.v[c] = s;
+          }
+          vstore<float, C>(v.xacc + idx, xa);
+        } else {
+          Pack<double, C> xv = vload<double, C>(v.x + idx);
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i = 0; i < kFoldEvery; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
+          vstore<double, C>(v.x + idx, xv);
+        }
       }
       const double mi = m.mass[row], kd = m.kdiag[row];
 #pragma unroll
@@ -554,7 +569,8 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
       const Pack<double, C> ph = vload<double, C>(v.phi + idx);
       Pack<double, C> xv = vload<double, C>(v.x + idx);
       Pack<T, C> zv = vload<T, C>(v.z + idx);
-      Pack<T, C> p0 = vload<T, C>(v.p0 + idx), p1 = vload<T, C>(v.p1 + idx);
+      T* pprev = v.p[kFoldEvery - 1];  // read as the previous direction at the chunk's first iteration
+      Pack<T, C> p0 = vload<T, C>(pprev + idx);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         if (!on[c]) continue;
@@ -563,22 +579,14 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
         const T d = (T)(mi + cc[c] * kd);
         xv.v[c] = ph.v[c];
         zv.v[c] = rt / d;
-        p0.v[c] = p1.v[c] = (T)0;
+        p0.v[c] = (T)0;
         acc[0][c] += (double)rt * (double)zv.v[c];
         acc[1][c] += r64 * r64;
         acc[2][c] += (mi * ph.v[c]) * (mi * ph.v[c]);
       }
       vstore<double, C>(v.x + idx, xv);
       vstore<T, C>(v.z + idx, zv);
-      vstore<T, C>(v.p0 + idx, p0);
-      vstore<T, C>(v.p1 + idx, p1);
-      if (v.xacc) {
-        Pack<float, C> xa = vload<float, C>(v.xacc + idx);
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-          if (on[c]) xa.v[c] = 0.0f;
-        vstore<float, C>(v.xacc + idx, xa);
-      }
+      vstore<T, C>(pprev + idx, p0);
     }
   }
   double tot[3];
@@ -591,11 +599,11 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
   }
 }
 
-// End of a column: x (+ increments) to the caller's numbering, partials of
-// the true residual and of sum M x^2.
+// End of a column: x to the caller's numbering, partials of the true
+// residual and of sum M x^2.
 template <typename T, int R>
 __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                                uint64_t mask, OutPtrs out, int fresh) {
+                                                uint64_t mask, OutPtrs out) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[2 * kWpb * R];
@@ -610,37 +618,32 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
     cc[c] = slots[j0 + c].c;
     any |= on[c];
   }
-  const bool mixed = v.xacc != nullptr && !fresh;  // increments to add
+  // at a chunk boundary x holds the whole solution (the chunk's update and,
+  // for mixed tiles, the fold have run)
   double acc[2][C] = {};
   if (any) {
-    for (Walk k = task_walk(m.n_slices * LPR, G); k.t < k.end; k.t += k.stride) {
-      const int64_t t = k.t;
-      const int64_t row = t * RPW + rsub;
+    for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
+      const int64_t row = wk.t * RPW + rsub;
       if (row >= m.n) continue;
       const int64_t s = row / kW, l = row % kW;
       const int64_t base = m.sptr[s];
       const int w = (int)((m.sptr[s + 1] - base) / kW);
       double a[C] = {};
-      // x = x64 + increments, gathered for the FP64 residual
       for (int k = 0; k < w; ++k) {
         const int64_t e = base + (int64_t)k * kW + l;
         const int64_t off = (int64_t)m.col[e] * R + j0;
         const double vv = m.val64[e];
         const Pack<double, C> xj = vload<double, C>(v.x + off);
-        Pack<float, C> xaj = {};
-        if (mixed) xaj = vload<float, C>(v.xacc + off);
 #pragma unroll
-        for (int c = 0; c < C; ++c) a[c] += vv * (mixed ? xj.v[c] + (double)xaj.v[c] : xj.v[c]);
+        for (int c = 0; c < C; ++c) a[c] += vv * xj.v[c];
       }
       const int64_t idx = row * R + j0;
       const Pack<double, C> xv = vload<double, C>(v.x + idx), ph = vload<double, C>(v.phi + idx);
-      Pack<float, C> xa = {};
-      if (mixed) xa = vload<float, C>(v.xacc + idx);
       const double mi = m.mass[row], kd = m.kdiag[row];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         if (!on[c]) continue;
-        const double xi = mixed ? xv.v[c] + (double)xa.v[c] : xv.v[c];
+        const double xi = xv.v[c];
         const double r64 = mi * (ph.v[c] - xi) - cc[c] * (kd * xi + a[c]);
         double* o = out.p[j0 + c];
         if (o) o[m.entity[row]] = xi;
@@ -695,17 +698,27 @@ __device__ __forceinline__ double fin_sum(const double* a, int G, double* lds) {
   return t;
 }
 
-// phase 1 (after kb_dir_spmv): alpha = rho / (p, q)
-__global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const double* part, int G, int Gp, int R) {
+// phase 1 (after kb_dir_spmv): alpha = rho / (p, q), kept in the column's
+// alpha history at the chunk position k (0 for columns not iterating)
+__global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const double* part, int G, int Gp, int R,
+                                                         int k) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
-  if (!live(s)) return;
+  if (!live(s)) {
+    if (threadIdx.x == 0) s.alpha_hist[k] = 0.0;
+    return;
+  }
   const double pq = fin_sum(part + (Q_PQ * R + j) * Gp, G, lds);
   if (threadIdx.x == 0) {
     const double a = s.rho / pq;
-    if (!(pq > 0.0) || !isfinite(a)) s.done = 2;
-    else s.alpha = a;
+    if (!(pq > 0.0) || !isfinite(a)) {
+      s.done = 2;
+      s.alpha_hist[k] = 0.0;
+    } else {
+      s.alpha = a;
+      s.alpha_hist[k] = a;
+    }
   }
 }
 
@@ -808,9 +821,9 @@ __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const dou
 template <typename T>
 BVec<T> bvec(BatchWork& w) {
   if constexpr (sizeof(T) == 4) {
-    return BVec<T>{w.z32, w.p32[0], w.p32[1], w.q32, w.xacc, w.x, w.xn, w.phi};
+    return BVec<T>{w.z32, {w.p32[0], w.p32[1], w.p32[2], w.p32[3]}, w.q32, w.xacc, w.x, w.xn, w.phi};
   } else {
-    return BVec<T>{w.z64, w.p64[0], w.p64[1], w.q64, nullptr, w.x, nullptr, w.phi};
+    return BVec<T>{w.z64, {w.p64[0], w.p64[1], w.p64[2], w.p64[3]}, w.q64, nullptr, w.x, nullptr, w.phi};
   }
 }
 
@@ -835,28 +848,30 @@ struct Grids {
 
 template <int R>
 struct Launch {
-  // one CG iteration of the tile; on a check iteration of a mixed tile also
-  // the fold and residual replacement of every running column
-  static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int par,
-                      bool check) {
-    const int fresh = w.fresh ? 1 : 0;
+  // iteration k (0..kFoldEvery-1) of a chunk; the last one applies the
+  // chunk's x update and, for mixed tiles, the fold and residual
+  // replacement of every running column
+  static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k) {
+    const bool last = k == kFoldEvery - 1;
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
-    if (w.mixed) kb_dir_spmv<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, par);
-    else kb_dir_spmv<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, par);
+    if (w.mixed) kb_dir_spmv<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, k);
+    else kb_dir_spmv<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, k);
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
-    kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R);
+    kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
     if (w.mixed) {
-      kb_update<float, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, par, fresh);
+      if (last) kb_update<float, true, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, k);
+      else kb_update<float, true, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, k);
       kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R, 1, prm.max_iter);
-      w.fresh = false;
-      if (check) {
+      if (last) {
         kb_replace<R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp);
         kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
         std::swap(w.x, w.xn);
-        w.fresh = true;
       }
     } else {
-      kb_update<double, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.Gu, g.Gp, par, 0);
+      if (last)
+        kb_update<double, false, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.Gu, g.Gp, k);
+      else
+        kb_update<double, false, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.Gu, g.Gp, k);
       kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R, 0, prm.max_iter);
     }
   }
@@ -867,10 +882,8 @@ struct Launch {
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
   }
   static void finish(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const OutPtrs& out) {
-    const int fresh = w.fresh ? 1 : 0;
-    if (w.mixed)
-      kb_finish<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask, out, fresh);
-    else kb_finish<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask, out, 0);
+    if (w.mixed) kb_finish<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask, out);
+    else kb_finish<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask, out);
     kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask);
   }
 };
@@ -890,8 +903,8 @@ void dispatch_R(int R, A&&... a) {
 
 template <int R>
 struct DoIterate {
-  static void run(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& p, int par, bool check) {
-    Launch<R>::iterate(m, w, g, s, p, par, check);
+  static void run(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& p, int k) {
+    Launch<R>::iterate(m, w, g, s, p, k);
   }
 };
 template <int R>
@@ -944,14 +957,15 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   const size_t nr = (size_t)bm.n_pad * R;
   ifl_status st;
   if (mixed) {
-    if ((st = dalloc_b(&w->z32, nr)) || (st = dalloc_b(&w->p32[0], nr)) ||
-        (st = dalloc_b(&w->p32[1], nr)) || (st = dalloc_b(&w->q32, nr)) || (st = dalloc_b(&w->xacc, nr)) ||
+    if ((st = dalloc_b(&w->z32, nr)) || (st = dalloc_b(&w->q32, nr)) || (st = dalloc_b(&w->xacc, nr)) ||
         (st = dalloc_b(&w->xn, nr)))
       return st;
+    for (float*& p : w->p32)
+      if ((st = dalloc_b(&p, nr))) return st;
   } else {
-    if ((st = dalloc_b(&w->z64, nr)) || (st = dalloc_b(&w->p64[0], nr)) ||
-        (st = dalloc_b(&w->p64[1], nr)) || (st = dalloc_b(&w->q64, nr)))
-      return st;
+    if ((st = dalloc_b(&w->z64, nr)) || (st = dalloc_b(&w->q64, nr))) return st;
+    for (double*& p : w->p64)
+      if ((st = dalloc_b(&p, nr))) return st;
   }
   if ((st = dalloc_b(&w->x, nr)) || (st = dalloc_b(&w->phi, nr)) ||
       (st = dalloc_b(&w->part, (size_t)Q_COUNT * R * std::max(bm.G, bm.Gu))) || (st = dalloc_b(&w->slots, (size_t)R)) ||
@@ -962,11 +976,11 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   IFL_HIPB(hipMemset(w->x, 0, sizeof(double) * nr));
   IFL_HIPB(hipMemset(w->phi, 0, sizeof(double) * nr));
   if (mixed) {
-    float* f32[] = {w->xacc, w->z32, w->p32[0], w->p32[1], w->q32};
+    float* f32[] = {w->xacc, w->z32, w->p32[0], w->p32[1], w->p32[2], w->p32[3], w->q32};
     for (float* p : f32) IFL_HIPB(hipMemset(p, 0, sizeof(float) * nr));
     IFL_HIPB(hipMemset(w->xn, 0, sizeof(double) * nr));
   } else {
-    double* f64[] = {w->z64, w->p64[0], w->p64[1], w->q64};
+    double* f64[] = {w->z64, w->p64[0], w->p64[1], w->p64[2], w->p64[3], w->q64};
     for (double* p : f64) IFL_HIPB(hipMemset(p, 0, sizeof(double) * nr));
   }
   w->R = R;
@@ -974,13 +988,13 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   w->Gu = bm.Gu;
   w->mixed = mixed;
   w->iter = 0;
-  w->fresh = true;
   return IFL_OK;
 }
 
 void batch_free(BatchWork* w) {
-  void* ptrs[] = {w->z32, w->p32[0], w->p32[1], w->q32, w->xacc, w->z64, w->p64[0], w->p64[1],
-                  w->q64, w->x, w->xn, w->phi, w->part, w->slots, w->flag};
+  void* ptrs[] = {w->z32,    w->p32[0], w->p32[1], w->p32[2], w->p32[3], w->q32, w->xacc,
+                  w->z64,    w->p64[0], w->p64[1], w->p64[2], w->p64[3], w->q64, w->x,
+                  w->xn,     w->phi,    w->part,   w->slots,  w->flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w->slots_host) (void)hipHostFree(w->slots_host);
@@ -988,7 +1002,7 @@ void batch_free(BatchWork* w) {
 }
 
 size_t batch_bytes(int64_t n_pad, int R, bool mixed) {
-  const size_t per = mixed ? (4 * 4 + 4 + 8 + 8 + 8) : (4 * 8 + 8 + 8);
+  const size_t per = mixed ? (6 * 4 + 4 + 8 + 8 + 8) : (6 * 8 + 8 + 8);
   return (size_t)n_pad * R * per;
 }
 
@@ -1048,9 +1062,8 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
   BatchParams rest = prm;
   rest.ev_begin = rest.ev_end = nullptr;
   for (int i = 0; i < n_iter; ++i) {
-    const int par = (int)(w.iter & 1);
-    const bool check = (w.iter + 1) % kFoldEvery == 0;
-    dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, i == 0 ? prm : rest, par, check);
+    const int k = (int)(w.iter % kFoldEvery);
+    dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, i == 0 ? prm : rest, k);
     ++w.iter;
   }
   IFL_HIPB(hipGetLastError());
