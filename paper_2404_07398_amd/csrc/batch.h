@@ -22,7 +22,7 @@ struct BSlot {
   double rr;        // current ||r||^2 (recursive, or FP64 true after a replacement)
   double tol2;      // rtol^2 ||M phi||^2
   double bb;        // ||M phi||^2
-  double res2;      // final true ||M phi - S x||^2
+  double res2;      // final true ||M phi - S x||^2 (mixed: of the last replacement)
   double energy2;   // final sum M x^2
   double pad0;
   double alpha_hist[kFoldEvery];  // alpha of each iteration of the current chunk (0 if not iterating)
@@ -96,6 +96,10 @@ ifl_status batch_clear_flag(BatchWork& w, hipStream_t s);
 // Gather one field (caller numbering, device) into column 'slot' of phi;
 // non-finite entries raise the device flag (read with batch_check_flag).
 ifl_status batch_load_column(const BatchMatrix& bm, BatchWork& w, int slot, const double* field_dev, hipStream_t s);
+// Gather several fields at once: fields_dev[j] (caller numbering, device)
+// into column j of phi for every slot j in 'mask'.
+ifl_status batch_load_columns(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const double* const* fields_dev,
+                              hipStream_t s);
 ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad);
 // A pseudo-random column (for timing trials) into column 'slot' of phi.
 ifl_status batch_load_synthetic(const BatchMatrix& bm, BatchWork& w, int slot, uint64_t seed, hipStream_t s);

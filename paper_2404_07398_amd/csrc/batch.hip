@@ -107,6 +107,10 @@ struct OutPtrs {
   double* p[64];
 };
 
+struct FieldPtrs {
+  const double* p[64];
+};
+
 template <typename T>
 __device__ __forceinline__ const T* bval(const BMat& m);
 template <>
@@ -599,9 +603,11 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
   }
 }
 
-// End of a column: x to the caller's numbering, partials of the true
-// residual and of sum M x^2.
-template <typename T, int R>
+// End of a column: x to the caller's numbering, partials of sum M x^2 and
+// (RESID) of the true residual ||M phi - S x||^2. Mixed tiles skip the
+// residual: their columns stop right after a replacement, whose FP64 true
+// residual is that of this very x.
+template <typename T, int R, bool RESID>
 __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
                                                 uint64_t mask, OutPtrs out) {
   using Gm = Geo<T, R>;
@@ -629,14 +635,15 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
       const int64_t base = m.sptr[s];
       const int w = (int)((m.sptr[s + 1] - base) / kW);
       double a[C] = {};
-      for (int k = 0; k < w; ++k) {
-        const int64_t e = base + (int64_t)k * kW + l;
-        const int64_t off = (int64_t)m.col[e] * R + j0;
-        const double vv = m.val64[e];
-        const Pack<double, C> xj = vload<double, C>(v.x + off);
+      if constexpr (RESID)
+        for (int k = 0; k < w; ++k) {
+          const int64_t e = base + (int64_t)k * kW + l;
+          const int64_t off = (int64_t)m.col[e] * R + j0;
+          const double vv = m.val64[e];
+          const Pack<double, C> xj = vload<double, C>(v.x + off);
 #pragma unroll
-        for (int c = 0; c < C; ++c) a[c] += vv * xj.v[c];
-      }
+          for (int c = 0; c < C; ++c) a[c] += vv * xj.v[c];
+        }
       const int64_t idx = row * R + j0;
       const Pack<double, C> xv = vload<double, C>(v.x + idx), ph = vload<double, C>(v.phi + idx);
       const double mi = m.mass[row], kd = m.kdiag[row];
@@ -644,10 +651,12 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
       for (int c = 0; c < C; ++c) {
         if (!on[c]) continue;
         const double xi = xv.v[c];
-        const double r64 = mi * (ph.v[c] - xi) - cc[c] * (kd * xi + a[c]);
         double* o = out.p[j0 + c];
         if (o) o[m.entity[row]] = xi;
-        acc[0][c] += r64 * r64;
+        if constexpr (RESID) {
+          const double r64 = mi * (ph.v[c] - xi) - cc[c] * (kd * xi + a[c]);
+          acc[0][c] += r64 * r64;
+        }
         acc[1][c] += mi * xi * xi;
       }
     }
@@ -659,6 +668,23 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
     part[(Q_RES * R + threadIdx.x) * Gp + lb] = tot[0];
     part[(Q_EN * R + threadIdx.x) * Gp + lb] = tot[1];
   }
+}
+
+// caller numbering -> the columns in 'mask' of the rows x R field array, one
+// row per thread (the new columns of a row are written together)
+__global__ void kb_gather_cols(FieldPtrs src, uint64_t mask, const int64_t* __restrict__ entity, int64_t n, int R,
+                               double* __restrict__ phi, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t e = entity[i];
+  bool bad = false;
+  for (int j = 0; j < R; ++j) {
+    if (!((mask >> j) & 1ull)) continue;
+    const double v = src.p[j][e];
+    bad |= !isfinite(v);
+    phi[i * R + j] = v;
+  }
+  if (bad) atomicOr(flag, 1);
 }
 
 // caller numbering -> column j of the rows x R field array
@@ -805,7 +831,7 @@ __global__ void kf_release(BSlot* slots, int R, uint64_t mask) {
 }
 
 __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const double* part, int G, int Gp, int R,
-                                                          uint64_t mask) {
+                                                          uint64_t mask, int mixed) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   if (!((mask >> j) & 1ull)) return;
@@ -813,7 +839,7 @@ __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const dou
   const double res = fin_sum(part + (Q_RES * R + j) * Gp, G, lds);
   const double en = fin_sum(part + (Q_EN * R + j) * Gp, G, lds);
   if (threadIdx.x == 0) {
-    s.res2 = res;
+    s.res2 = mixed ? s.rr : res;  // mixed: the FP64 true residual of the last replacement
     s.energy2 = en;
   }
 }
@@ -882,9 +908,10 @@ struct Launch {
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
   }
   static void finish(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const OutPtrs& out) {
-    if (w.mixed) kb_finish<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask, out);
-    else kb_finish<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask, out);
-    kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask);
+    if (w.mixed)
+      kb_finish<float, R, false><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask, out);
+    else kb_finish<double, R, true><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask, out);
+    kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, w.mixed ? 1 : 0);
   }
 };
 
@@ -1028,6 +1055,20 @@ ifl_status batch_load_column(const BatchMatrix& bm, BatchWork& w, int slot, cons
 ifl_status batch_load_synthetic(const BatchMatrix& bm, BatchWork& w, int slot, uint64_t seed, hipStream_t s) {
   if (slot < 0 || slot >= w.R) return fail(IFL_EINVAL, "slot out of range");
   kb_synth<<<(unsigned)((bm.n + 255) / 256), 256, 0, s>>>(bm.n, w.R, slot, seed, w.phi);
+  IFL_HIPB(hipGetLastError());
+  return IFL_OK;
+}
+
+ifl_status batch_load_columns(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const double* const* fields_dev,
+                              hipStream_t s) {
+  FieldPtrs f{};
+  for (int j = 0; j < w.R; ++j) {
+    if (!((mask >> j) & 1ull)) continue;
+    if (!fields_dev[j]) return fail(IFL_EINVAL, "field pointer of a loaded slot is NULL");
+    f.p[j] = fields_dev[j];
+  }
+  if (w.R < 64 && (mask >> w.R)) return fail(IFL_EINVAL, "slot mask beyond the tile");
+  kb_gather_cols<<<(unsigned)((bm.n + 255) / 256), 256, 0, s>>>(f, mask, bm.entity, bm.n, w.R, w.phi, w.flag);
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
 }

@@ -1022,18 +1022,20 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
     // fill free slots
     uint64_t mask = 0;
     SlotScales cs{};
-    if (next < ncols && (st = batch_clear_flag(w, s)) != IFL_OK) return st;
+    const double* src[64] = {};
     for (int j = 0; j < R && next < ncols; ++j) {
       if (slot_col[j] >= 0) continue;
       const int64_t col = order[next++];
       const int64_t f = col / n_scales, sc = col % n_scales;
-      if ((st = batch_load_column(bm, w, j, fdev + f * L, s)) != IFL_OK) return st;
+      src[j] = fdev + f * L;
       cs.c[j] = h->opt.gamma / std::pow(k[sc], 2.0 * h->op.order);
       slot_col[j] = col;
       t_in[j] = std::chrono::steady_clock::now();
       mask |= 1ull << j;
     }
     if (mask) {
+      if ((st = batch_clear_flag(w, s)) != IFL_OK) return st;
+      if ((st = batch_load_columns(bm, w, mask, src, s)) != IFL_OK) return st;
       bool bad = false;
       if ((st = batch_check_flag(w, s, &bad)) != IFL_OK) return st;
       if (bad) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");

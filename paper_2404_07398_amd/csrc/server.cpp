@@ -159,12 +159,12 @@ ifl_status run_worker(Worker* wk) {
     // 2. fill free slots
     uint64_t mask = 0;
     SlotScales cs{};
+    const double* src[64] = {};
     for (int j = 0; j < R && !wk->pending.empty(); ++j) {
       if (wk->slot[j].t) continue;
       const Column col = wk->pending.front();
       wk->pending.pop_front();
-      ifl_status st = batch_load_column(wk->bm, wk->w, j, col.t->dev_field, wk->stream);
-      if (st != IFL_OK) return st;
+      src[j] = col.t->dev_field;
       cs.c[j] = h->opt.gamma / std::pow(col.t->k[col.scale], 2.0 * h->op.order);
       wk->slot[j] = col;
       wk->t_in[j] = Clock::now();
@@ -172,7 +172,8 @@ ifl_status run_worker(Worker* wk) {
       ++active;
     }
     if (mask) {
-      ifl_status st = batch_init(wk->bm, wk->w, mask, cs, rtol, wk->stream);
+      ifl_status st = batch_load_columns(wk->bm, wk->w, mask, src, wk->stream);
+      if (st == IFL_OK) st = batch_init(wk->bm, wk->w, mask, cs, rtol, wk->stream);
       if (st != IFL_OK) return st;
     }
     if (active == 0) {
