@@ -9,10 +9,11 @@
 
 namespace ifl {
 
-// Tile iterations between FP64 residual-replacement checks of mixed tiles.
-// Columns enter a tile only at multiples of it, and the host advances a tile
-// by multiples of it.
-constexpr int kFoldEvery = 4;
+// A batched tile advances in chunks of kChunk CG iterations: x is updated
+// and (mixed tiles) the FP64 residual replaced at the end of each chunk,
+// columns enter only at chunk boundaries, and the host advances a tile by
+// whole chunks.
+constexpr int kChunk = 4;
 
 // Per-column CG state of one slot (device memory; mirrored to pinned host
 // memory by batch_read_slots).
@@ -25,7 +26,7 @@ struct BSlot {
   double res2;      // final true ||M phi - S x||^2 (mixed: of the last replacement)
   double energy2;   // final sum M x^2
   double pad0;
-  double alpha_hist[kFoldEvery];  // alpha of each iteration of the current chunk (0 if not iterating)
+  double alpha_hist[kChunk];  // alpha of each iteration of the current chunk (0 if not iterating)
   int32_t active;   // slot holds a column
   int32_t done;     // 0 running, 1 converged, 2 breakdown, 3 max_iter
   int32_t iters;    // CG iterations of this column
@@ -64,12 +65,11 @@ struct BatchWork {
   int R = 0;
   int G = 0, Gu = 0;  // grid sizes the work space (partial-sum array) was made for
   bool mixed = false;
-  // p cycles through kFoldEvery buffers, so that the directions of a whole
+  // p cycles through kChunk buffers, so that the directions of a whole
   // chunk are still there when x is updated at its last iteration
-  float *z32 = nullptr, *p32[kFoldEvery] = {}, *q32 = nullptr, *xacc = nullptr;
-  double *z64 = nullptr, *p64[kFoldEvery] = {}, *q64 = nullptr;
-  double* x = nullptr;    // FP64 solution, rows x R (mixed: without the FP32 increments)
-  double* xn = nullptr;   // mixed: second FP64 solution buffer (swapped with x at each fold)
+  float *z32 = nullptr, *p32[kChunk] = {}, *q32 = nullptr;
+  double *z64 = nullptr, *p64[kChunk] = {}, *q64 = nullptr;
+  double* x = nullptr;    // FP64 solution, rows x R (updated once per chunk)
   double* phi = nullptr;  // FP64 fields, rows x R
   double* part = nullptr; // per-(quantity, column, block) partial sums
   BSlot* slots = nullptr;

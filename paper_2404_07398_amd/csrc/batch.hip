@@ -15,14 +15,14 @@
 // Per-column state (alpha, beta, rho, stopping, residual replacement) lives
 // in device memory; after each reduction phase a small kernel with one
 // workgroup per column finishes that column's sum in a fixed order. A tile
-// advances in chunks of kFoldEvery iterations and columns enter only at
+// advances in chunks of kChunk iterations and columns enter only at
 // chunk boundaries, so all live columns share the chunk position. Inside a
 // chunk only z (the preconditioned residual) and p change; the directions
-// of the chunk are kept in kFoldEvery buffers and x is updated once, at the
-// chunk's last iteration, from them and each column's alpha history. Mixed
-// tiles then fold that FP32 update into FP64 and replace every running
-// column's residual by its FP64 true residual, in one pass for the whole
-// tile; a mixed column stops only on such a replaced residual. A column's
+// of the chunk are kept in kChunk buffers and x is updated once, at the
+// chunk's last iteration (in FP64, in every precision), from them and each
+// column's alpha history. Mixed tiles then replace every running column's
+// residual by its FP64 true residual, in one pass for the whole tile; a
+// mixed column stops only on such a replaced residual. A column's
 // arithmetic and reduction order depend neither on the other columns, nor
 // on its slot, nor on when it entered, so a solve gives bitwise the same
 // result alone or in a full tile.
@@ -95,11 +95,9 @@ struct BMat {
 template <typename T>
 struct BVec {
   T* z;              // preconditioned residual diag(S)^-1 r
-  T* p[kFoldEvery];  // directions of the chunk's iterations (p of iteration k in p[k])
+  T* p[kChunk];  // directions of the chunk's iterations (p of iteration k in p[k])
   T* q;
-  float* xacc;   // mixed: FP32 increments since the last fold
-  double* x;     // FP64 solution (mixed: without the increments in xacc)
-  double* xn;    // mixed: the other FP64 solution buffer (target of a fold)
+  double* x;     // FP64 solution
   double* phi;   // FP64 field per column
 };
 
@@ -205,6 +203,14 @@ __device__ __forceinline__ void row_product(const BMat& m, const V* __restrict__
   }
 }
 
+// combiners of row_product for a single gathered operand
+struct Ident {
+  __device__ double operator()(int, double xx, double) const { return xx; }
+};
+struct AbsVal {
+  __device__ double operator()(int, double xx, double) const { return fabs(xx); }
+};
+
 // ------------------------------------------------------------ iteration
 constexpr int kHead = 6;  // off-diagonal entries per row gathered in the pipelined head
 
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
     c64[c] = sl.c;
     any |= on[c];
   }
-  const T* __restrict__ pin = v.p[(k + kFoldEvery - 1) % kFoldEvery];  // previous iteration's p
+  const T* __restrict__ pin = v.p[(k + kChunk - 1) % kChunk];  // previous iteration's p
   T* __restrict__ pout = v.p[k];
   const T* __restrict__ z = v.z;
   const T* __restrict__ val = bval<T>(m);
@@ -356,11 +362,10 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
 // z -= alpha q / diag(S) (the preconditioned residual is the stored state;
 // r = diag(S) z is formed where it is needed, so r is neither read nor
 // written); partials (r, z), (r, r) per column. At the last iteration of a
-// chunk (XUP) the chunk's x update is applied at once from the directions
-// kept in p[0..3] and each column's alpha history: x += sum_k alpha_k p_k
-// (FP64), or for mixed tiles the FP32 increments xacc = sum_k alpha_k p_k,
-// which the replacement pass that follows folds into x. z of columns that
-// are not iterating is left unchanged.
+// chunk (XUP) the chunk's x update is applied at once, in FP64 in every
+// precision, from the directions kept in p[0..3] and each column's alpha
+// history: x += sum_k alpha_k p_k. z of columns that are not iterating is
+// left unchanged.
 template <typename T, bool MIXED, bool XUP, int R>
 __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
                                                 int k) {
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
   T alpha[C];
   double c64[C];
-  double ah[kFoldEvery][C];  // alpha history (XUP)
+  double ah[kChunk][C];  // alpha history (XUP)
   bool on[C];
   bool any = false;
 #pragma unroll
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
     c64[c] = sl.c;
     any |= on[c];
 #pragma unroll
-    for (int i = 0; i < kFoldEvery; ++i) {
+    for (int i = 0; i < kChunk; ++i) {
       ah[i][c] = XUP ? sl.alpha_hist[i] : 0.0;
       any |= XUP && ah[i][c] != 0.0;
     }
@@ -396,27 +401,15 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
       const Pack<T, C> qv = vload<T, C>(v.q + idx);
       Pack<T, C> zv = vload<T, C>(v.z + idx);
       if constexpr (XUP) {
-        Pack<T, C> pk[kFoldEvery];
+        Pack<T, C> pk[kChunk];
 #pragma unroll
-        for (int i = 0; i < kFoldEvery; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
-        if constexpr (MIXED) {
-          Pack<float, C> xa;
+        for (int i = 0; i < kChunk; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
+        Pack<double, C> xv = vload<double, C>(v.x + idx);
 #pragma unroll
-          for (int c = 0; c < C; ++c) {
-            float s = 0.0f;
+        for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int i = 0; i < kFoldEvery; ++i) s = fma((float)ah[i][c], (float)pk[i].v[c], s);
-            xa.v[c] = s;
-          }
-          vstore<float, C>(v.xacc + idx, xa);
-        } else {
-          Pack<double, C> xv = vload<double, C>(v.x + idx);
-#pragma unroll
-          for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int i = 0; i < kFoldEvery; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
-          vstore<double, C>(v.x + idx, xv);
-        }
+          for (int i = 0; i < kChunk; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
+        vstore<double, C>(v.x + idx, xv);
       }
       const double mi = m.mass[row], kd = m.kdiag[row];
 #pragma unroll
@@ -442,16 +435,13 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
   }
 }
 
-// Mixed tiles, every kFoldEvery iterations: the FP32 increments of every
-// column are folded into the FP64 solution (written to the other x buffer,
-// since other blocks still gather this one), and every running column's
-// residual is replaced by the FP64 true residual r = M phi - S x (FP64
-// values, x = x64 + increments), with the partials of (r, z), (r, r) and of
-// the attainable-accuracy norm || |M phi| + |M x| + c |K_n| |x| ||^2.
-// z of columns that are not running is overwritten with values
-// nothing reads (a column that enters is started from scratch).
-constexpr int kUnrollX = 4;  // entries per batch of the FP64 + FP32 gathers
-
+// Mixed tiles, at the end of every chunk (after the chunk's x update):
+// every running column's residual is replaced by the FP64 true residual
+// r = M phi - S x (FP64 values and x), z = r / diag(S), with the partials of
+// (r, z), (r, r) and of the attainable-accuracy norm
+// || |M phi| + |M x| + c |K_n| |x| ||^2. z of columns that are not running is
+// overwritten with values nothing reads (a column that enters is started
+// from scratch). The slice loop is software-pipelined like kb_dir_spmv.
 template <int R>
 __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BSlot* slots, double* part, int G,
                                                  int Gp) {
@@ -462,69 +452,104 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
   bool on[C];
   double cc[C];
+  bool any = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     on[c] = live(slots[j0 + c]);
     cc[c] = slots[j0 + c].c;
+    any |= on[c];
   }
+  const double* __restrict__ x = v.x;
+  const Ident ident;
+  const AbsVal absval;
   double acc[3][C] = {};
-  for (Walk k = task_walk(m.n_slices * LPR, G); k.t < k.end; k.t += k.stride) {
-    const int64_t row = k.t * RPW + rsub;
-    if (row >= m.n) continue;
-    const int64_t s = row / kW, l = row % kW;
-    const int64_t base = m.sptr[s];
-    const int w = (int)((m.sptr[s + 1] - base) / kW);
-    double a[C] = {}, aa[C] = {};  // sum val x, sum |val| |x|
-    for (int k0 = 0; k0 < w; k0 += kUnrollX) {
-      int32_t cu[kUnrollX];
-      double vu[kUnrollX];
+  if (any) {
+    const Walk wk = task_walk(m.n_slices * LPR, G);
+    const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
+    const int64_t last_slice = m.n_slices - 1;
+    auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
+    int32_t cu[kHead];
+    double vu[kHead];
+    Pack<double, C> ph, xv;
+    double mi, kd;
+    int64_t base, nb, ne;
+    int w;
+    auto fetch_idx = [&](int64_t t, int64_t sb) {
+      const int64_t l = (t * RPW + rsub) % kW;
 #pragma unroll
-      for (int u = 0; u < kUnrollX; ++u) {
-        const int64_t e = base + (int64_t)(k0 + u) * kW + l;
-        cu[u] = m.col[e];
-        const double vv = m.val64[e];
-        vu[u] = k0 + u < w ? vv : 0.0;
-      }
-      Pack<double, C> gx[kUnrollX];
-      Pack<float, C> ga[kUnrollX];
+      for (int u = 0; u < kHead; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
+    };
+    auto fetch_rest = [&](int64_t t, int64_t sb) {
+      const int64_t row = min(t * RPW + rsub, m.n_slices * kW - 1), l = row % kW;
 #pragma unroll
-      for (int u = 0; u < kUnrollX; ++u) {
-        const int64_t off = (int64_t)cu[u] * R + j0;
-        gx[u] = vload<double, C>(v.x + off);
-        ga[u] = vload<float, C>(v.xacc + off);
-      }
+      for (int u = 0; u < kHead; ++u) vu[u] = m.val64[sb + (int64_t)u * kW + l];
+      const int64_t idx = row * R + j0;
+      ph = vload<double, C>(v.phi + idx);
+      xv = vload<double, C>(x + idx);
+      mi = m.mass[row];
+      kd = m.kdiag[row];
+    };
+    {
+      const int64_t s0 = slice_of(first);
+      base = wave_uniform(m.sptr[s0]);
+      w = (int)((wave_uniform(m.sptr[s0 + 1]) - base) / kW);
+      fetch_idx(first, base);
+      fetch_rest(first, base);
+      const int64_t s1 = slice_of(first + stride);
+      nb = m.sptr[s1];
+      ne = m.sptr[s1 + 1];
+    }
+    for (int64_t t = first; t < end; t += stride) {
+      const int64_t row = t * RPW + rsub;
+      const int32_t self = (int32_t)min(row, m.n - 1);
+      Pack<double, C> gx[kHead];
 #pragma unroll
-      for (int u = 0; u < kUnrollX; ++u)
+      for (int u = 0; u < kHead; ++u) gx[u] = vload<double, C>(x + (int64_t)(u < w ? cu[u] : self) * R + j0);
+      const int64_t cbase = base;
+      const int cw = w;
+      const int64_t tn = t + stride < end ? t + stride : t;
+      const int64_t s2 = slice_of(t + 2 * stride);
+      const int64_t nb2 = m.sptr[s2], ne2 = m.sptr[s2 + 1];
+      base = wave_uniform(nb);
+      w = (int)((wave_uniform(ne) - base) / kW);
+      fetch_idx(tn, base);
+      nb = nb2;
+      ne = ne2;
+      double a[C] = {}, aa[C] = {};  // sum val x, sum |val| |x|
+#pragma unroll
+      for (int u = 0; u < kHead; ++u) {
+        const double vm = u < cw ? vu[u] : 0.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const double xf = gx[u].v[c] + (double)ga[u].v[c];
-          a[c] = fma(vu[u], xf, a[c]);
-          aa[c] = fma(fabs(vu[u]), fabs(xf), aa[c]);
+          a[c] = fma(vm, gx[u].v[c], a[c]);
+          aa[c] = fma(fabs(vm), fabs(gx[u].v[c]), aa[c]);
         }
-    }
-    const int64_t idx = row * R + j0;
-    const double mi = m.mass[row], kd = m.kdiag[row];
-    const Pack<double, C> ph = vload<double, C>(v.phi + idx), xv = vload<double, C>(v.x + idx);
-    const Pack<float, C> xa = vload<float, C>(v.xacc + idx);
-    Pack<double, C> xn;
-    Pack<float, C> zv;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const double xf = xv.v[c] + (double)xa.v[c];
-      xn.v[c] = xf;
-      const double r64 = mi * (ph.v[c] - xf) - cc[c] * (kd * xf + a[c]);
-      const float rt = (float)r64;
-      const float d = (float)(mi + cc[c] * kd);
-      zv.v[c] = rt / d;
-      if (on[c]) {
-        const double mag = fabs(mi * ph.v[c]) + fabs(mi * xf) + cc[c] * (fabs(kd * xf) + aa[c]);
-        acc[0][c] += (double)rt * (double)zv.v[c];
-        acc[1][c] += r64 * r64;
-        acc[2][c] += mag * mag;
       }
+      if (cw > kHead) {
+        row_product<double, double, R, C, false, false, decltype(ident), kHead>(
+            m, m.val64, cbase, cw, row % kW, j0, x, nullptr, ident, a, kHead);
+        row_product<double, double, R, C, false, true, decltype(absval), kHead>(
+            m, m.val64, cbase, cw, row % kW, j0, x, nullptr, absval, aa, kHead);
+      }
+      const bool real = row < m.n;
+      Pack<float, C> zv;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const double xf = xv.v[c];
+        const double r64 = mi * (ph.v[c] - xf) - cc[c] * (kd * xf + a[c]);
+        const float rt = (float)r64;
+        const float d = (float)(mi + cc[c] * kd);
+        zv.v[c] = rt / d;
+        if (on[c] && real) {
+          const double mag = fabs(mi * ph.v[c]) + fabs(mi * xf) + cc[c] * (fabs(kd * xf) + aa[c]);
+          acc[0][c] += (double)rt * (double)zv.v[c];
+          acc[1][c] += r64 * r64;
+          acc[2][c] += mag * mag;
+        }
+      }
+      if (real) vstore<float, C>(v.z + row * R + j0, zv);
+      fetch_rest(tn, base);
     }
-    vstore<double, C>(v.xn + idx, xn);
-    vstore<float, C>(v.z + idx, zv);
   }
   double tot[3];
   col_sum<R, C, 3>(acc, lds, tot);
@@ -536,7 +561,7 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
   }
 }
 
-// Start of the columns in 'mask': x = phi, p = 0, increments 0 and the
+// Start of the columns in 'mask': x = phi, p = 0 and the
 // FP64 residual of the residual form, r0 = M phi - S phi = -c K_n phi, with
 // the partials of (r, z), (r, r) and ||M phi||^2. Other columns' vectors are
 // left unchanged.
@@ -573,7 +598,7 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
       const Pack<double, C> ph = vload<double, C>(v.phi + idx);
       Pack<double, C> xv = vload<double, C>(v.x + idx);
       Pack<T, C> zv = vload<T, C>(v.z + idx);
-      T* pprev = v.p[kFoldEvery - 1];  // read as the previous direction at the chunk's first iteration
+      T* pprev = v.p[kChunk - 1];  // read as the previous direction at the chunk's first iteration
       Pack<T, C> p0 = vload<T, C>(pprev + idx);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -624,8 +649,8 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
     cc[c] = slots[j0 + c].c;
     any |= on[c];
   }
-  // at a chunk boundary x holds the whole solution (the chunk's update and,
-  // for mixed tiles, the fold have run)
+  // at a chunk boundary x holds the whole solution (the chunk's x update
+  // has run)
   double acc[2][C] = {};
   if (any) {
     for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
@@ -847,9 +872,9 @@ __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const dou
 template <typename T>
 BVec<T> bvec(BatchWork& w) {
   if constexpr (sizeof(T) == 4) {
-    return BVec<T>{w.z32, {w.p32[0], w.p32[1], w.p32[2], w.p32[3]}, w.q32, w.xacc, w.x, w.xn, w.phi};
+    return BVec<T>{w.z32, {w.p32[0], w.p32[1], w.p32[2], w.p32[3]}, w.q32, w.x, w.phi};
   } else {
-    return BVec<T>{w.z64, {w.p64[0], w.p64[1], w.p64[2], w.p64[3]}, w.q64, nullptr, w.x, nullptr, w.phi};
+    return BVec<T>{w.z64, {w.p64[0], w.p64[1], w.p64[2], w.p64[3]}, w.q64, w.x, w.phi};
   }
 }
 
@@ -874,11 +899,11 @@ struct Grids {
 
 template <int R>
 struct Launch {
-  // iteration k (0..kFoldEvery-1) of a chunk; the last one applies the
-  // chunk's x update and, for mixed tiles, the fold and residual
+  // iteration k (0..kChunk-1) of a chunk; the last one applies the
+  // chunk's x update and, for mixed tiles, the residual
   // replacement of every running column
   static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k) {
-    const bool last = k == kFoldEvery - 1;
+    const bool last = k == kChunk - 1;
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
     if (w.mixed) kb_dir_spmv<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, k);
     else kb_dir_spmv<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, k);
@@ -891,7 +916,6 @@ struct Launch {
       if (last) {
         kb_replace<R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp);
         kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
-        std::swap(w.x, w.xn);
       }
     } else {
       if (last)
@@ -984,9 +1008,7 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   const size_t nr = (size_t)bm.n_pad * R;
   ifl_status st;
   if (mixed) {
-    if ((st = dalloc_b(&w->z32, nr)) || (st = dalloc_b(&w->q32, nr)) || (st = dalloc_b(&w->xacc, nr)) ||
-        (st = dalloc_b(&w->xn, nr)))
-      return st;
+    if ((st = dalloc_b(&w->z32, nr)) || (st = dalloc_b(&w->q32, nr))) return st;
     for (float*& p : w->p32)
       if ((st = dalloc_b(&p, nr))) return st;
   } else {
@@ -1003,9 +1025,8 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   IFL_HIPB(hipMemset(w->x, 0, sizeof(double) * nr));
   IFL_HIPB(hipMemset(w->phi, 0, sizeof(double) * nr));
   if (mixed) {
-    float* f32[] = {w->xacc, w->z32, w->p32[0], w->p32[1], w->p32[2], w->p32[3], w->q32};
+    float* f32[] = {w->z32, w->p32[0], w->p32[1], w->p32[2], w->p32[3], w->q32};
     for (float* p : f32) IFL_HIPB(hipMemset(p, 0, sizeof(float) * nr));
-    IFL_HIPB(hipMemset(w->xn, 0, sizeof(double) * nr));
   } else {
     double* f64[] = {w->z64, w->p64[0], w->p64[1], w->p64[2], w->p64[3], w->q64};
     for (double* p : f64) IFL_HIPB(hipMemset(p, 0, sizeof(double) * nr));
@@ -1019,9 +1040,8 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
 }
 
 void batch_free(BatchWork* w) {
-  void* ptrs[] = {w->z32,    w->p32[0], w->p32[1], w->p32[2], w->p32[3], w->q32, w->xacc,
-                  w->z64,    w->p64[0], w->p64[1], w->p64[2], w->p64[3], w->q64, w->x,
-                  w->xn,     w->phi,    w->part,   w->slots,  w->flag};
+  void* ptrs[] = {w->z32, w->p32[0], w->p32[1], w->p32[2], w->p32[3], w->q32, w->z64,  w->p64[0],
+                  w->p64[1], w->p64[2], w->p64[3], w->q64, w->x,     w->phi,    w->part, w->slots, w->flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w->slots_host) (void)hipHostFree(w->slots_host);
@@ -1029,7 +1049,7 @@ void batch_free(BatchWork* w) {
 }
 
 size_t batch_bytes(int64_t n_pad, int R, bool mixed) {
-  const size_t per = mixed ? (6 * 4 + 4 + 8 + 8 + 8) : (6 * 8 + 8 + 8);
+  const size_t per = mixed ? (6 * 4 + 8 + 8) : (6 * 8 + 8 + 8);
   return (size_t)n_pad * R * per;
 }
 
@@ -1084,8 +1104,8 @@ ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad) {
 ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const SlotScales& cs, double rtol,
                       hipStream_t s) {
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
-  if (w.iter % kFoldEvery != 0)
-    return fail(IFL_EINVAL, "columns may only enter a tile at iterations that are multiples of kFoldEvery");
+  if (w.iter % kChunk != 0)
+    return fail(IFL_EINVAL, "columns may only enter a tile at iterations that are multiples of kChunk");
   dispatch_R<DoInit>(w.R, bmat(bm), w, grids(bm), s, mask, cs, rtol);
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
@@ -1098,12 +1118,12 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
 
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s) {
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
-  if (n_iter % kFoldEvery != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of kFoldEvery");
+  if (n_iter % kChunk != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of kChunk");
   const BMat m = bmat(bm);
   BatchParams rest = prm;
   rest.ev_begin = rest.ev_end = nullptr;
   for (int i = 0; i < n_iter; ++i) {
-    const int k = (int)(w.iter % kFoldEvery);
+    const int k = (int)(w.iter % kChunk);
     dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, i == 0 ? prm : rest, k);
     ++w.iter;
   }

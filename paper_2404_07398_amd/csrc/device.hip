@@ -1181,11 +1181,11 @@ ifl_status device_autotune(Handle* h, ifl_tune* out) {
         BatchParams prm;
         prm.max_iter = 1 << 30;
         if (st == IFL_OK) st = batch_init(bm, w, mask, cs, 1e-300, s);
-        if (st == IFL_OK) st = batch_iterate(bm, w, kFoldEvery, prm, s);  // warm-up
+        if (st == IFL_OK) st = batch_iterate(bm, w, kChunk, prm, s);  // warm-up
         float ms = 0.f;
         if (st == IFL_OK) {
           (void)hipEventRecord(d->ev[0], s);
-          st = batch_iterate(bm, w, 2 * kFoldEvery, prm, s);
+          st = batch_iterate(bm, w, 2 * kChunk, prm, s);
           (void)hipEventRecord(d->ev[1], s);
           if (hipEventSynchronize(d->ev[1]) != hipSuccess || hipEventElapsedTime(&ms, d->ev[0], d->ev[1]) != hipSuccess)
             st = fail(IFL_EDEVICE, "timing the autotuner trial failed");
@@ -1193,7 +1193,7 @@ ifl_status device_autotune(Handle* h, ifl_tune* out) {
         batch_free(&w);
         if (st != IFL_OK) return st;
         ++tried;
-        const double us = ms * 1e3 / (2.0 * kFoldEvery * R);
+        const double us = ms * 1e3 / (2.0 * kChunk * R);
         if (us < b.us) b = Best{R, G, Gu, us};
       }
     per_R.push_back(b);
