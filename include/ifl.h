@@ -152,6 +152,10 @@ int64_t ifl_field_length(const ifl_handle* h);
  * device, reorder) must equal the prepare-time values, else IFL_EINVAL. */
 ifl_status ifl_set_options(ifl_handle* h, const ifl_options* opt);
 
+/* Copy the handle's current options into *out (to change some of them with
+ * ifl_set_options). IFL_EINVAL on NULL arguments. */
+ifl_status ifl_get_options(const ifl_handle* h, ifl_options* out);
+
 /*
  * Filter n_fields fields at n_scales wavenumbers (Eq. 1 discretised as
  * above; solve of Sect. 2.2.2).

@@ -110,6 +110,7 @@ _PROTOS = {
     "ifl_num_dofs": (C.c_int64, [C.c_void_p]),
     "ifl_field_length": (C.c_int64, [C.c_void_p]),
     "ifl_set_options": (C.c_int32, [C.c_void_p, C.POINTER(ifl_options)]),
+    "ifl_get_options": (C.c_int32, [C.c_void_p, C.POINTER(ifl_options)]),
     "ifl_filter": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p,
                                C.POINTER(ifl_solve_stats)]),
     "ifl_spectrum": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -255,8 +256,18 @@ class Handle:
     def field_length(self) -> int:
         return int(lib().ifl_field_length(self._h))
 
+    def options(self) -> ifl_options:
+        o = ifl_options()
+        _check(lib().ifl_get_options(self._h, C.byref(o)))
+        return o
+
     def set_options(self, **kw):
-        o = default_options(**kw)
+        """Change some solver options; the others keep their current values."""
+        o = self.options()
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown option {k}")
+            setattr(o, k, v)
         _check(lib().ifl_set_options(self._h, C.byref(o)))
 
     def filter(self, fields, ks, out=None, raise_on_notconv: bool = True):

@@ -112,6 +112,13 @@ ifl_status ifl_set_options(ifl_handle* h, const ifl_options* opt) {
   return IFL_OK;
 }
 
+ifl_status ifl_get_options(const ifl_handle* h, ifl_options* out) {
+  if (!h || !out) return fail(IFL_EINVAL, "handle / out NULL");
+  std::lock_guard<std::mutex> lk(const_cast<ifl_handle*>(h)->mu);
+  *out = h->opt;
+  return IFL_OK;
+}
+
 ifl_status ifl_filter(ifl_handle* h, int32_t n_fields, const double* fields, int32_t n_scales, const double* k,
                       double* out, ifl_solve_stats* stats) {
   g_last_error.clear();

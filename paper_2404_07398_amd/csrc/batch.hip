@@ -1031,6 +1031,9 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
     double* f64[] = {w->z64, w->p64[0], w->p64[1], w->p64[2], w->p64[3], w->q64};
     for (double* p : f64) IFL_HIPB(hipMemset(p, 0, sizeof(double) * nr));
   }
+  // hipMemset of device memory may return before it completes, and the
+  // tile's kernels run on streams that do not wait for the null stream
+  IFL_HIPB(hipDeviceSynchronize());
   w->R = R;
   w->G = bm.G;
   w->Gu = bm.Gu;

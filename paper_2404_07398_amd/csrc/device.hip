@@ -680,6 +680,9 @@ ifl_status device_create(Handle* h) {
   IFL_HIP(hipHostMalloc((void**)&w.sc_host, 2 * sizeof(Scalars), hipHostMallocDefault));
   IFL_HIP(hipMemset(w.part, 0, sizeof(double) * P_COUNT * d->G));
   IFL_HIP(hipMemset(w.sc, 0, sizeof(Scalars)));
+  // hipMemset of device memory may return before it completes, and the
+  // solves run on streams that do not wait for the null stream
+  IFL_HIP(hipDeviceSynchronize());
   return IFL_OK;
 }
 

@@ -158,6 +158,21 @@ def test_partitioned_ordering_is_a_permutation_and_local():
     h0.close()
 
 
+def test_set_options_keeps_the_others():
+    _lib_or_skip()
+    m = W.split_square(8, jitter=0.1)
+    h = _host_handle(m, precision=ifl.IFL_MIXED, rtol=1e-10)
+    o = h.options()
+    assert o.precision == ifl.IFL_MIXED and o.rtol == 1e-10 and o.device == -1
+    h.set_options(batch=16)
+    o = h.options()
+    assert o.batch == 16 and o.precision == ifl.IFL_MIXED and o.rtol == 1e-10 and o.device == -1
+    with pytest.raises(ifl.IflError) as e:
+        h.set_options(reorder=0)
+    assert e.value.status == ifl.IFL_EINVAL
+    h.close()
+
+
 def test_prepare_errors():
     _lib_or_skip()
     m = W.split_square(8, jitter=0.1)
