@@ -96,10 +96,14 @@ ifl_status batch_clear_flag(BatchWork& w, hipStream_t s);
 // Gather one field (caller numbering, device) into column 'slot' of phi;
 // non-finite entries raise the device flag (read with batch_check_flag).
 ifl_status batch_load_column(const BatchMatrix& bm, BatchWork& w, int slot, const double* field_dev, hipStream_t s);
-// Gather several fields at once: fields_dev[j] (caller numbering, device)
-// into column j of phi for every slot j in 'mask'.
+// Gather several fields at once: fields_dev[j] (device; caller numbering, or
+// row order when 'internal') into column j of phi for every slot j in 'mask'.
 ifl_status batch_load_columns(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const double* const* fields_dev,
-                              hipStream_t s);
+                              bool internal, hipStream_t s);
+// n_fields device fields in the caller's numbering (stride L) -> row order
+// (stride n_pad) in dst; non-finite wet entries set *flag (device int).
+ifl_status batch_permute_fields(const BatchMatrix& bm, const double* src, int64_t L, int n_fields, double* dst,
+                                int* flag, hipStream_t s);
 ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad);
 // A pseudo-random column (for timing trials) into column 'slot' of phi.
 ifl_status batch_load_synthetic(const BatchMatrix& bm, BatchWork& w, int slot, uint64_t seed, hipStream_t s);

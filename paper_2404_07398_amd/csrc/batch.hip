@@ -695,13 +695,15 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
   }
 }
 
-// caller numbering -> the columns in 'mask' of the rows x R field array, one
-// row per thread (the new columns of a row are written together)
+// fields -> the columns in 'mask' of the rows x R field array, one row per
+// thread (the new columns of a row are written together). The fields are in
+// the caller's numbering (read through entity) or, 'internal', already in
+// row order (contiguous reads).
 __global__ void kb_gather_cols(FieldPtrs src, uint64_t mask, const int64_t* __restrict__ entity, int64_t n, int R,
-                               double* __restrict__ phi, int* flag) {
+                               int internal, double* __restrict__ phi, int* flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t e = entity[i];
+  const int64_t e = internal ? i : entity[i];
   bool bad = false;
   for (int j = 0; j < R; ++j) {
     if (!((mask >> j) & 1ull)) continue;
@@ -710,6 +712,18 @@ __global__ void kb_gather_cols(FieldPtrs src, uint64_t mask, const int64_t* __re
     phi[i * R + j] = v;
   }
   if (bad) atomicOr(flag, 1);
+}
+
+// n_fields fields in the caller's numbering (stride L) -> row order (stride
+// n_pad), one field per grid row; non-finite wet entries raise the flag
+__global__ void kb_permute(const double* __restrict__ src, int64_t L, const int64_t* __restrict__ entity, int64_t n,
+                           int64_t n_pad, double* __restrict__ dst, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t f = blockIdx.y;
+  const double v = src[f * L + entity[i]];
+  if (!isfinite(v)) atomicOr(flag, 1);
+  dst[f * n_pad + i] = v;
 }
 
 // caller numbering -> column j of the rows x R field array
@@ -1083,7 +1097,7 @@ ifl_status batch_load_synthetic(const BatchMatrix& bm, BatchWork& w, int slot, u
 }
 
 ifl_status batch_load_columns(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const double* const* fields_dev,
-                              hipStream_t s) {
+                              bool internal, hipStream_t s) {
   FieldPtrs f{};
   for (int j = 0; j < w.R; ++j) {
     if (!((mask >> j) & 1ull)) continue;
@@ -1091,7 +1105,18 @@ ifl_status batch_load_columns(const BatchMatrix& bm, BatchWork& w, uint64_t mask
     f.p[j] = fields_dev[j];
   }
   if (w.R < 64 && (mask >> w.R)) return fail(IFL_EINVAL, "slot mask beyond the tile");
-  kb_gather_cols<<<(unsigned)((bm.n + 255) / 256), 256, 0, s>>>(f, mask, bm.entity, bm.n, w.R, w.phi, w.flag);
+  kb_gather_cols<<<(unsigned)((bm.n + 255) / 256), 256, 0, s>>>(f, mask, bm.entity, bm.n, w.R, internal ? 1 : 0,
+                                                                w.phi, w.flag);
+  IFL_HIPB(hipGetLastError());
+  return IFL_OK;
+}
+
+ifl_status batch_permute_fields(const BatchMatrix& bm, const double* src, int64_t L, int n_fields, double* dst,
+                                int* flag, hipStream_t s) {
+  if (n_fields <= 0) return IFL_OK;
+  if (n_fields > 65535) return fail(IFL_EINVAL, "too many fields in one call (max 65535)");
+  const dim3 grid((unsigned)((bm.n + 255) / 256), (unsigned)n_fields);
+  kb_permute<<<grid, 256, 0, s>>>(src, L, bm.entity, bm.n, bm.n_pad, dst, flag);
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
 }

@@ -128,6 +128,8 @@ struct DeviceState {
   int tuned_R[2] = {0, 0};
   double* field_stage = nullptr;  // device copy of host fields
   int64_t field_stage_len = 0;
+  double* field_rows = nullptr;   // the call's fields in row order (n_fields x n_pad)
+  int64_t field_rows_len = 0;
   double* col_stage = nullptr;    // per-slot outputs for host destinations
   int64_t col_stage_len = 0;
 };
@@ -700,6 +702,7 @@ void device_destroy(Handle* h) {
   if (d->w.sc_host) (void)hipHostFree(d->w.sc_host);
   batch_free(&d->bw);
   if (d->field_stage) (void)hipFree(d->field_stage);
+  if (d->field_rows) (void)hipFree(d->field_rows);
   if (d->col_stage) (void)hipFree(d->col_stage);
   for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
   if (d->own_stream) (void)hipStreamDestroy(d->own_stream);
@@ -1008,6 +1011,23 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
     if ((st = dalloc(&d->col_stage, (size_t)R * L)) != IFL_OK) return st;
     d->col_stage_len = (int64_t)R * L;
   }
+  // the fields in row order, once per call (each is loaded once per scale),
+  // with the non-finite check of every wet entry
+  {
+    const int64_t need = (int64_t)n_fields * bm.n_pad;
+    if (d->field_rows_len < need) {
+      if (d->field_rows) (void)hipFree(d->field_rows);
+      d->field_rows = nullptr;
+      d->field_rows_len = 0;
+      if ((st = dalloc(&d->field_rows, (size_t)need)) != IFL_OK) return st;
+      d->field_rows_len = need;
+    }
+    bool bad = false;
+    if ((st = batch_clear_flag(w, s)) != IFL_OK) return st;
+    if ((st = batch_permute_fields(bm, fdev, L, n_fields, d->field_rows, w.flag, s)) != IFL_OK) return st;
+    if ((st = batch_check_flag(w, s, &bad)) != IFL_OK) return st;
+    if (bad) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");
+  }
   // columns: larger scales (more iterations) first, fields in order
   const int64_t ncols = (int64_t)n_fields * n_scales;
   std::vector<int64_t> order(ncols);
@@ -1030,18 +1050,14 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
       if (slot_col[j] >= 0) continue;
       const int64_t col = order[next++];
       const int64_t f = col / n_scales, sc = col % n_scales;
-      src[j] = fdev + f * L;
+      src[j] = d->field_rows + f * bm.n_pad;
       cs.c[j] = h->opt.gamma / std::pow(k[sc], 2.0 * h->op.order);
       slot_col[j] = col;
       t_in[j] = std::chrono::steady_clock::now();
       mask |= 1ull << j;
     }
     if (mask) {
-      if ((st = batch_clear_flag(w, s)) != IFL_OK) return st;
-      if ((st = batch_load_columns(bm, w, mask, src, s)) != IFL_OK) return st;
-      bool bad = false;
-      if ((st = batch_check_flag(w, s, &bad)) != IFL_OK) return st;
-      if (bad) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");
+      if ((st = batch_load_columns(bm, w, mask, src, true, s)) != IFL_OK) return st;
       if ((st = batch_init(bm, w, mask, cs, h->opt.rtol, s)) != IFL_OK) return st;
     }
     BatchParams p = prm;
@@ -1200,8 +1216,11 @@ ifl_status device_autotune(Handle* h, ifl_tune* out) {
         if (us < b.us) b = Best{R, G, Gu, us};
       }
     per_R.push_back(b);
-    if (b.us < overall.us) overall = b;
   }
+  // the fastest tile size, preferring the smaller one within 3% (a smaller
+  // tile wastes fewer slots when columns run out and needs less memory)
+  for (const Best& b : per_R)
+    if (b.us < overall.us * 0.97 || overall.R == 0) overall = b;
   for (const Best& b : per_R) {
     bool found = false;
     for (auto& t : d->tuned)

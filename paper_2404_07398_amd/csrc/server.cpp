@@ -61,12 +61,13 @@ struct Worker {
   BatchWork w;
   BatchMatrix bm;
   double* col_out = nullptr;  // R x L device staging of finished columns
+  double* stage = nullptr;    // L doubles: a request's field on its way to row order
   int64_t L = 0;
   std::deque<ifl_ticket*> queue;  // submitted, not yet admitted (guarded by srv->mu)
   std::deque<Column> pending;     // admitted columns waiting for a slot (worker only)
   std::vector<Column> slot;       // column in each slot
   std::vector<Clock::time_point> t_in;
-  std::vector<double*> field_pool;  // device field buffers for reuse (worker only)
+  std::vector<double*> field_pool;  // device field buffers (row order, n_pad) for reuse (worker only)
   std::thread th;
   ifl_status init_status = IFL_OK;
 };
@@ -143,12 +144,15 @@ ifl_status run_worker(Worker* wk) {
       if (!wk->field_pool.empty()) {
         t->dev_field = wk->field_pool.back();
         wk->field_pool.pop_back();
-      } else if (hipMalloc((void**)&t->dev_field, sizeof(double) * wk->L) != hipSuccess) {
+      } else if (hipMalloc((void**)&t->dev_field, sizeof(double) * wk->bm.n_pad) != hipSuccess) {
         t->dev_field = nullptr;
       }
+      // the field goes through the staging buffer into row order (stream order
+      // keeps the staging buffer's reuse safe)
       if (!t->dev_field ||
-          hipMemcpyAsync(t->dev_field, t->field.data(), sizeof(double) * wk->L, hipMemcpyHostToDevice,
-                         wk->stream) != hipSuccess) {
+          hipMemcpyAsync(wk->stage, t->field.data(), sizeof(double) * wk->L, hipMemcpyHostToDevice, wk->stream) !=
+              hipSuccess ||
+          batch_permute_fields(wk->bm, wk->stage, wk->L, 1, t->dev_field, wk->w.flag, wk->stream) != IFL_OK) {
         (void)hipGetLastError();
         release_ticket(wk, t);
         finish_ticket(t, IFL_ENOMEM, "device allocation for the request failed");
@@ -172,7 +176,7 @@ ifl_status run_worker(Worker* wk) {
       ++active;
     }
     if (mask) {
-      ifl_status st = batch_load_columns(wk->bm, wk->w, mask, src, wk->stream);
+      ifl_status st = batch_load_columns(wk->bm, wk->w, mask, src, true, wk->stream);
       if (st == IFL_OK) st = batch_init(wk->bm, wk->w, mask, cs, rtol, wk->stream);
       if (st != IFL_OK) return st;
     }
@@ -282,7 +286,7 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
   if (hipSetDevice(h->opt.device) != hipSuccess) return fail(IFL_EDEVICE, "hipSetDevice failed");
   wk->bm = handle_batch_matrix(h, wk->R, h->opt.precision == IFL_MIXED);
   const size_t tile = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED) +
-                      sizeof(double) * (size_t)wk->R * wk->L;
+                      sizeof(double) * (size_t)(wk->R + 1) * wk->L;  // + output and field staging
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->tiles + s->used + tile > s->budget)
@@ -290,6 +294,8 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
     s->tiles += tile;
   }
   ifl_status st = batch_alloc(&wk->w, wk->bm, wk->R, h->opt.precision == IFL_MIXED);
+  if (st == IFL_OK && hipMalloc((void**)&wk->stage, sizeof(double) * (size_t)wk->L) != hipSuccess)
+    st = fail(IFL_ENOMEM, "hipMalloc of the field staging failed");
   if (st == IFL_OK && hipMalloc((void**)&wk->col_out, sizeof(double) * (size_t)wk->R * wk->L) != hipSuccess)
     st = fail(IFL_ENOMEM, "hipMalloc of the output staging failed");
   if (st == IFL_OK && hipStreamCreateWithFlags(&wk->stream, hipStreamNonBlocking) != hipSuccess)
@@ -297,6 +303,7 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
   if (st != IFL_OK) {
     batch_free(&wk->w);
     if (wk->col_out) (void)hipFree(wk->col_out);
+    if (wk->stage) (void)hipFree(wk->stage);
     std::lock_guard<std::mutex> lk(s->mu);
     s->tiles -= tile;
     return st;
@@ -338,7 +345,8 @@ ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field, int32
   t->out = out;
   t->stats.assign(n_scales, ifl_solve_stats{});
   t->remaining = n_scales;
-  t->footprint = sizeof(double) * (size_t)op.field_len;
+  // the request's device field, in row order (padded to whole slices)
+  t->footprint = sizeof(double) * (size_t)((op.n + 63) / 64 * 64);
   t->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -392,6 +400,7 @@ void ifl_server_destroy(ifl_server* s) {
     if (wk->stream) (void)hipStreamSynchronize(wk->stream);
     batch_free(&wk->w);
     if (wk->col_out) (void)hipFree(wk->col_out);
+    if (wk->stage) (void)hipFree(wk->stage);
     for (double* f : wk->field_pool) (void)hipFree(f);
     if (wk->stream) (void)hipStreamDestroy(wk->stream);
   }
