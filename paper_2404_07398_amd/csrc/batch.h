@@ -45,6 +45,8 @@ struct BatchMatrix {
   const double* kdiag = nullptr;
   const double* mass = nullptr;
   const int64_t* entity = nullptr;
+  const int32_t* row_of = nullptr;  // caller index -> row (-1: no dof), field_len entries
+  int64_t field_len = 0;
   int G = 1;   // blocks of the kernels that gather (SpMV, replacement, start, finish)
   int Gu = 1;  // blocks of the streaming update kernel
 };
@@ -111,8 +113,9 @@ ifl_status batch_load_synthetic(const BatchMatrix& bm, BatchWork& w, int slot, u
 ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const SlotScales& cs, double rtol,
                       hipStream_t s);
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s);
-// Write x of the columns in 'mask' to out[slot] (caller numbering; dry
-// entries untouched) and compute their true residual and energy.
+// Write x of the columns in 'mask' to out[slot] (caller numbering, every
+// entry: 0 where there is no dof) and compute their energy (and, FP64 tiles,
+// true residual) into the slot state.
 ifl_status batch_finish(const BatchMatrix& bm, BatchWork& w, uint64_t mask, double* const* out, hipStream_t s);
 ifl_status batch_read_slots(BatchWork& w, hipStream_t s);
 ifl_status batch_release(BatchWork& w, uint64_t mask, hipStream_t s);

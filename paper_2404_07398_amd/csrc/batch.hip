@@ -83,6 +83,8 @@ __device__ __forceinline__ void vstore(T* p, const Pack<T, C>& x) {
 
 struct BMat {
   int64_t n, n_slices;
+  const int32_t* row_of;  // caller index -> row (-1: no dof)
+  int64_t field_len;
   const int64_t* sptr;
   const int32_t* col;
   const double* val64;
@@ -628,13 +630,13 @@ __global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, 
   }
 }
 
-// End of a column: x to the caller's numbering, partials of sum M x^2 and
-// (RESID) of the true residual ||M phi - S x||^2. Mixed tiles skip the
-// residual: their columns stop right after a replacement, whose FP64 true
-// residual is that of this very x.
+// End of a column: partials of sum M x^2 and (RESID) of the true residual
+// ||M phi - S x||^2 (kb_out writes x out). Mixed tiles skip the residual:
+// their columns stop right after a replacement, whose FP64 true residual is
+// that of this very x.
 template <typename T, int R, bool RESID>
 __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                                uint64_t mask, OutPtrs out) {
+                                                uint64_t mask) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[2 * kWpb * R];
@@ -676,8 +678,6 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
       for (int c = 0; c < C; ++c) {
         if (!on[c]) continue;
         const double xi = xv.v[c];
-        double* o = out.p[j0 + c];
-        if (o) o[m.entity[row]] = xi;
         if constexpr (RESID) {
           const double r64 = mi * (ph.v[c] - xi) - cc[c] * (kd * xi + a[c]);
           acc[0][c] += r64 * r64;
@@ -695,6 +695,28 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
   }
 }
 
+// x of the columns in 'mask' to the caller's numbering, one caller entry per
+// thread: coalesced writes (0 where there is no dof), each thread reading
+// its row's columns together.
+__global__ void kb_out(const double* __restrict__ x, int R, OutPtrs out, uint64_t mask, const int32_t* __restrict__ row_of,
+                       int64_t L) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= L) return;
+  const int64_t i = row_of[v];
+  if (R == 1) {
+    if (mask & 1ull) out.p[0][v] = i >= 0 ? x[i] : 0.0;
+    return;
+  }
+  for (int j = 0; j < R; j += 2) {
+    const uint64_t bits = (mask >> j) & 3ull;
+    if (!bits) continue;
+    Pack<double, 2> xv = {};
+    if (i >= 0) xv = vload<double, 2>(x + i * R + j);
+    if (bits & 1ull) out.p[j][v] = xv.v[0];
+    if (bits & 2ull) out.p[j + 1][v] = xv.v[1];
+  }
+}
+
 // fields -> the columns in 'mask' of the rows x R field array, one row per
 // thread (the new columns of a row are written together). The fields are in
 // the caller's numbering (read through entity) or, 'internal', already in
@@ -705,11 +727,29 @@ __global__ void kb_gather_cols(FieldPtrs src, uint64_t mask, const int64_t* __re
   if (i >= n) return;
   const int64_t e = internal ? i : entity[i];
   bool bad = false;
-  for (int j = 0; j < R; ++j) {
-    if (!((mask >> j) & 1ull)) continue;
-    const double v = src.p[j][e];
-    bad |= !isfinite(v);
-    phi[i * R + j] = v;
+  if (R == 1) {
+    if (mask & 1ull) {
+      const double v = src.p[0][e];
+      bad = !isfinite(v);
+      phi[i] = v;
+    }
+  } else {
+    for (int j = 0; j < R; j += 2) {
+      const uint64_t bits = (mask >> j) & 3ull;
+      if (!bits) continue;
+      Pack<double, 2> pv;
+      if (bits == 3ull) {
+        pv.v[0] = src.p[j][e];
+        pv.v[1] = src.p[j + 1][e];
+        bad |= !isfinite(pv.v[0]) || !isfinite(pv.v[1]);
+        vstore<double, 2>(phi + i * R + j, pv);
+      } else {
+        const int jj = bits == 1ull ? j : j + 1;
+        const double vv = src.p[jj][e];
+        bad |= !isfinite(vv);
+        phi[i * R + jj] = vv;
+      }
+    }
   }
   if (bad) atomicOr(flag, 1);
 }
@@ -946,9 +986,16 @@ struct Launch {
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
   }
   static void finish(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const OutPtrs& out) {
-    if (w.mixed)
-      kb_finish<float, R, false><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask, out);
-    else kb_finish<double, R, true><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask, out);
+    if (w.mixed) kb_finish<float, R, false><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask);
+    else kb_finish<double, R, true><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask);
+    bool any_out = false;
+    for (int j = 0; j < R; ++j) any_out |= ((mask >> j) & 1ull) && out.p[j];
+    if (any_out) {
+      uint64_t omask = 0;
+      for (int j = 0; j < R; ++j)
+        if (((mask >> j) & 1ull) && out.p[j]) omask |= 1ull << j;
+      kb_out<<<(unsigned)((m.field_len + 255) / 256), 256, 0, s>>>(w.x, R, out, omask, m.row_of, m.field_len);
+    }
     kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, w.mixed ? 1 : 0);
   }
 };
@@ -1075,7 +1122,8 @@ static Grids grids(const BatchMatrix& bm) { return Grids{bm.G, bm.Gu, std::max(b
 static bool same_grids(const BatchMatrix& bm, const BatchWork& w) { return bm.G == w.G && bm.Gu == w.Gu; }
 
 static BMat bmat(const BatchMatrix& bm) {
-  return BMat{bm.n, bm.n_slices, bm.sptr, bm.col, bm.val64, bm.val32, bm.kdiag, bm.mass, bm.entity};
+  return BMat{bm.n, bm.n_slices, bm.row_of, bm.field_len, bm.sptr, bm.col, bm.val64, bm.val32, bm.kdiag, bm.mass,
+              bm.entity};
 }
 
 ifl_status batch_clear_flag(BatchWork& w, hipStream_t s) {

@@ -84,6 +84,8 @@ struct DevMatrix {
   float* kdiag32 = nullptr;
   double* mass64 = nullptr;
   int64_t* entity = nullptr;
+  int32_t* row_of = nullptr;  // caller index -> row, -1 for entries without a dof (field_len)
+  int64_t field_len = 0;
   double mass_sum = 0.0;
 };
 
@@ -658,6 +660,12 @@ ifl_status device_create(Handle* h) {
       (st = upload(&m.val32, v32)) || (st = upload(&m.kdiag64, sp.diag)) || (st = upload(&m.kdiag32, kd32)) ||
       (st = upload(&m.mass64, sp.mass)) || (st = upload(&m.entity, h->op.entity)))
     return st;
+  {
+    std::vector<int32_t> row_of((size_t)h->op.field_len, -1);
+    for (int64_t i = 0; i < (int64_t)h->op.entity.size(); ++i) row_of[(size_t)h->op.entity[i]] = (int32_t)i;
+    m.field_len = h->op.field_len;
+    if ((st = upload(&m.row_of, row_of))) return st;
+  }
   m.mass_sum = 0.0;
   for (double a : h->op.mass) m.mass_sum += a;
 
@@ -694,7 +702,7 @@ void device_destroy(Handle* h) {
   (void)hipSetDevice(d->device);
   if (d->own_stream) (void)hipStreamSynchronize(d->own_stream);
   DevMatrix& m = d->m;
-  void* ptrs[] = {m.sptr, m.col, m.val64, m.val32, m.kdiag64, m.kdiag32, m.mass64, m.entity, d->w.x, d->w.r, d->w.z,
+  void* ptrs[] = {m.sptr, m.col, m.val64, m.val32, m.kdiag64, m.kdiag32, m.mass64, m.entity, m.row_of, d->w.x, d->w.r, d->w.z,
                   d->w.p[0], d->w.p[1], d->w.q, d->w.d, d->w.r32, d->w.z32, d->w.p32[0], d->w.p32[1], d->w.q32,
                   d->w.d32, d->w.xacc, d->w.phi, d->w.part, d->w.sc, d->w.flag, d->w.stage_in, d->w.stage_out};
   for (void* p : ptrs)
@@ -946,6 +954,8 @@ BatchMatrix batch_matrix(DeviceState* d, int R, bool mixed) {
   bm.kdiag = m.kdiag64;
   bm.mass = m.mass64;
   bm.entity = m.entity;
+  bm.row_of = m.row_of;
+  bm.field_len = m.field_len;
   // a task is one wavefront's rows: 64 / lanes-per-row consecutive rows.
   // Defaults: the gathering kernels run one block per CU, so that the rows
   // in flight on an XCD form a band narrow enough for its L2 to keep the
@@ -1083,10 +1093,7 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
     for (int j = 0; j < R; ++j) {
       if (slot_col[j] < 0 || w.slots_host[j].done == 0) continue;
       fin |= 1ull << j;
-      if (out) {
-        dst[j] = odev ? out + slot_col[j] * L : d->col_stage + (int64_t)j * L;
-        IFL_HIP(hipMemsetAsync(dst[j], 0, sizeof(double) * L, s));
-      }
+      if (out) dst[j] = odev ? out + slot_col[j] * L : d->col_stage + (int64_t)j * L;
     }
     if (!fin) continue;
     if ((st = batch_finish(bm, w, fin, dst.data(), s)) != IFL_OK) return st;

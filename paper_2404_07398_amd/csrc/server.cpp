@@ -197,8 +197,6 @@ ifl_status run_worker(Worker* wk) {
       if (!wk->slot[j].t || wk->w.slots_host[j].done == 0) continue;
       fin |= 1ull << j;
       dst[j] = wk->col_out + (int64_t)j * wk->L;
-      if (hipMemsetAsync(dst[j], 0, sizeof(double) * wk->L, wk->stream) != hipSuccess)
-        return fail(IFL_EDEVICE, "hipMemsetAsync failed");
     }
     if (!fin) continue;
     if ((st = batch_finish(wk->bm, wk->w, fin, dst.data(), wk->stream)) != IFL_OK) return st;
