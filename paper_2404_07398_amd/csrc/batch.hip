@@ -437,31 +437,46 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
   }
 }
 
-// Mixed tiles, at the end of every chunk (after the chunk's x update):
-// every running column's residual is replaced by the FP64 true residual
+// FP64 residual passes, software-pipelined like kb_dir_spmv (the gathered
+// operand is FP64: 16 B per lane and entry for FP64 tiles, 32 B for mixed).
+//
+// START (the columns in 'mask', scales cs): x = phi, p = 0 and the residual
+// of the residual form r0 = M phi - S phi = -c K_n phi, z = r0 / diag(S), with
+// the partials of (r, z), (r, r) and ||M phi||^2. Other columns' vectors are
+// left unchanged.
+//
+// REPLACE (mixed tiles, at the end of every chunk, after its x update): the
+// residual of every running column is replaced by its FP64 true residual
 // r = M phi - S x (FP64 values and x), z = r / diag(S), with the partials of
 // (r, z), (r, r) and of the attainable-accuracy norm
 // || |M phi| + |M x| + c |K_n| |x| ||^2. z of columns that are not running is
 // overwritten with values nothing reads (a column that enters is started
-// from scratch). The slice loop is software-pipelined like kb_dir_spmv.
-template <int R>
-__global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BSlot* slots, double* part, int G,
-                                                 int Gp) {
-  using Gm = Geo<float, R>;
+// from scratch).
+template <typename T, int R, bool START>
+__global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+                                                  int Gp, uint64_t mask, SlotScales cs) {
+  using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[3 * kWpb * R];
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
   bool on[C];
   double cc[C];
-  bool any = false;
+  bool any = false, all = true;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    on[c] = live(slots[j0 + c]);
-    cc[c] = slots[j0 + c].c;
+    if constexpr (START) {
+      on[c] = ((mask >> (j0 + c)) & 1ull) != 0;
+      cc[c] = cs.c[j0 + c];
+    } else {
+      on[c] = live(slots[j0 + c]);
+      cc[c] = slots[j0 + c].c;
+    }
     any |= on[c];
+    all &= on[c];
   }
-  const double* __restrict__ x = v.x;
+  const double* __restrict__ src = START ? v.phi : v.x;  // the gathered operand
+  T* __restrict__ pprev = v.p[kChunk - 1];             // the chunk's first iteration reads it as p
   const Ident ident;
   const AbsVal absval;
   double acc[3][C] = {};
@@ -487,7 +502,7 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
       for (int u = 0; u < kHead; ++u) vu[u] = m.val64[sb + (int64_t)u * kW + l];
       const int64_t idx = row * R + j0;
       ph = vload<double, C>(v.phi + idx);
-      xv = vload<double, C>(x + idx);
+      if constexpr (!START) xv = vload<double, C>(v.x + idx);
       mi = m.mass[row];
       kd = m.kdiag[row];
     };
@@ -506,7 +521,7 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
       const int32_t self = (int32_t)min(row, m.n - 1);
       Pack<double, C> gx[kHead];
 #pragma unroll
-      for (int u = 0; u < kHead; ++u) gx[u] = vload<double, C>(x + (int64_t)(u < w ? cu[u] : self) * R + j0);
+      for (int u = 0; u < kHead; ++u) gx[u] = vload<double, C>(src + (int64_t)(u < w ? cu[u] : self) * R + j0);
       const int64_t cbase = base;
       const int cw = w;
       const int64_t tn = t + stride < end ? t + stride : t;
@@ -517,39 +532,70 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
       fetch_idx(tn, base);
       nb = nb2;
       ne = ne2;
-      double a[C] = {}, aa[C] = {};  // sum val x, sum |val| |x|
+      double a[C] = {}, aa[C] = {};  // sum val x, sum |val| |x| (REPLACE)
 #pragma unroll
       for (int u = 0; u < kHead; ++u) {
         const double vm = u < cw ? vu[u] : 0.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           a[c] = fma(vm, gx[u].v[c], a[c]);
-          aa[c] = fma(fabs(vm), fabs(gx[u].v[c]), aa[c]);
+          if constexpr (!START) aa[c] = fma(fabs(vm), fabs(gx[u].v[c]), aa[c]);
         }
       }
       if (cw > kHead) {
         row_product<double, double, R, C, false, false, decltype(ident), kHead>(
-            m, m.val64, cbase, cw, row % kW, j0, x, nullptr, ident, a, kHead);
-        row_product<double, double, R, C, false, true, decltype(absval), kHead>(
-            m, m.val64, cbase, cw, row % kW, j0, x, nullptr, absval, aa, kHead);
+            m, m.val64, cbase, cw, row % kW, j0, src, nullptr, ident, a, kHead);
+        if constexpr (!START)
+          row_product<double, double, R, C, false, true, decltype(absval), kHead>(
+              m, m.val64, cbase, cw, row % kW, j0, src, nullptr, absval, aa, kHead);
       }
       const bool real = row < m.n;
-      Pack<float, C> zv;
+      const int64_t idx = row * R + j0;
+      if constexpr (START) {
+        if (real) {
+          // columns of this lane that do not start keep their state
+          Pack<double, C> xo = ph;
+          Pack<T, C> zo, po = {};
+          if (!all) {
+            xo = vload<double, C>(v.x + idx);
+            zo = vload<T, C>(v.z + idx);
+            po = vload<T, C>(pprev + idx);
+          }
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const double xf = xv.v[c];
-        const double r64 = mi * (ph.v[c] - xf) - cc[c] * (kd * xf + a[c]);
-        const float rt = (float)r64;
-        const float d = (float)(mi + cc[c] * kd);
-        zv.v[c] = rt / d;
-        if (on[c] && real) {
-          const double mag = fabs(mi * ph.v[c]) + fabs(mi * xf) + cc[c] * (fabs(kd * xf) + aa[c]);
-          acc[0][c] += (double)rt * (double)zv.v[c];
-          acc[1][c] += r64 * r64;
-          acc[2][c] += mag * mag;
+          for (int c = 0; c < C; ++c) {
+            if (!on[c]) continue;
+            const double r64 = -cc[c] * (kd * ph.v[c] + a[c]);
+            const T rt = (T)r64;
+            const T d = (T)(mi + cc[c] * kd);
+            xo.v[c] = ph.v[c];
+            zo.v[c] = rt / d;
+            po.v[c] = (T)0;
+            acc[0][c] += (double)rt * (double)zo.v[c];
+            acc[1][c] += r64 * r64;
+            acc[2][c] += (mi * ph.v[c]) * (mi * ph.v[c]);
+          }
+          vstore<double, C>(v.x + idx, xo);
+          vstore<T, C>(v.z + idx, zo);
+          vstore<T, C>(pprev + idx, po);
         }
+      } else {
+        Pack<T, C> zv;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const double xf = xv.v[c];
+          const double r64 = mi * (ph.v[c] - xf) - cc[c] * (kd * xf + a[c]);
+          const T rt = (T)r64;
+          const T d = (T)(mi + cc[c] * kd);
+          zv.v[c] = rt / d;
+          if (on[c] && real) {
+            const double mag = fabs(mi * ph.v[c]) + fabs(mi * xf) + cc[c] * (fabs(kd * xf) + aa[c]);
+            acc[0][c] += (double)rt * (double)zv.v[c];
+            acc[1][c] += r64 * r64;
+            acc[2][c] += mag * mag;
+          }
+        }
+        if (real) vstore<T, C>(v.z + idx, zv);
       }
-      if (real) vstore<float, C>(v.z + row * R + j0, zv);
       fetch_rest(tn, base);
     }
   }
@@ -559,74 +605,7 @@ __global__ __launch_bounds__(kB) void kb_replace(BMat m, BVec<float> v, const BS
     const int lb = lblock(G);
     part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
     part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
-    part[(Q_FL * R + threadIdx.x) * Gp + lb] = tot[2];
-  }
-}
-
-// Start of the columns in 'mask': x = phi, p = 0 and the
-// FP64 residual of the residual form, r0 = M phi - S phi = -c K_n phi, with
-// the partials of (r, z), (r, r) and ||M phi||^2. Other columns' vectors are
-// left unchanged.
-template <typename T, int R>
-__global__ __launch_bounds__(kB) void kb_start(BMat m, BVec<T> v, double* part, int G, int Gp, uint64_t mask,
-                                               SlotScales cs) {
-  using Gm = Geo<T, R>;
-  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
-  __shared__ double lds[3 * kWpb * R];
-  const int lane = threadIdx.x % kW;
-  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
-  bool on[C];
-  double cc[C];
-  bool any = false;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    on[c] = ((mask >> (j0 + c)) & 1ull) != 0;
-    cc[c] = cs.c[j0 + c];
-    any |= on[c];
-  }
-  double acc[3][C] = {};  // rz, rr, ||M phi||^2
-  if (any) {
-    for (Walk k = task_walk(m.n_slices * LPR, G); k.t < k.end; k.t += k.stride) {
-      const int64_t row = k.t * RPW + rsub;
-      if (row >= m.n) continue;
-      const int64_t s = row / kW, l = row % kW;
-      const int64_t base = m.sptr[s];
-      const int w = (int)((m.sptr[s + 1] - base) / kW);
-      double a[C] = {};
-      row_product<double, double, R, C, false, false>(m, m.val64, base, w, l, j0, v.phi, nullptr,
-                                                      [&](int, double xx, double) { return xx; }, a);
-      const int64_t idx = row * R + j0;
-      const double mi = m.mass[row], kd = m.kdiag[row];
-      const Pack<double, C> ph = vload<double, C>(v.phi + idx);
-      Pack<double, C> xv = vload<double, C>(v.x + idx);
-      Pack<T, C> zv = vload<T, C>(v.z + idx);
-      T* pprev = v.p[kChunk - 1];  // read as the previous direction at the chunk's first iteration
-      Pack<T, C> p0 = vload<T, C>(pprev + idx);
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        if (!on[c]) continue;
-        const double r64 = -cc[c] * (kd * ph.v[c] + a[c]);
-        const T rt = (T)r64;
-        const T d = (T)(mi + cc[c] * kd);
-        xv.v[c] = ph.v[c];
-        zv.v[c] = rt / d;
-        p0.v[c] = (T)0;
-        acc[0][c] += (double)rt * (double)zv.v[c];
-        acc[1][c] += r64 * r64;
-        acc[2][c] += (mi * ph.v[c]) * (mi * ph.v[c]);
-      }
-      vstore<double, C>(v.x + idx, xv);
-      vstore<T, C>(v.z + idx, zv);
-      vstore<T, C>(pprev + idx, p0);
-    }
-  }
-  double tot[3];
-  col_sum<R, C, 3>(acc, lds, tot);
-  if (threadIdx.x < R) {
-    const int lb = lblock(G);
-    part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
-    part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
-    part[(Q_BB * R + threadIdx.x) * Gp + lb] = tot[2];
+    part[((START ? Q_BB : Q_FL) * R + threadIdx.x) * Gp + lb] = tot[2];
   }
 }
 
@@ -852,7 +831,7 @@ __global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const doubl
   }
 }
 
-// phase 3 (mixed, after kb_replace): replaced residual and stopping test
+// phase 3 (mixed, after the replacement pass): replaced residual and stopping test
 __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const double* part, int G, int Gp, int R,
                                                            int max_iter) {
   __shared__ double lds[kFinThreads / kW];
@@ -874,7 +853,7 @@ __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const do
   }
 }
 
-// start of a column (after kb_start)
+// start of a column (after the start pass)
 __global__ __launch_bounds__(kFinThreads) void kf_init(BSlot* slots, const double* part, int G, int Gp, int R, uint64_t mask,
                                                         double rtol, SlotScales cs) {
   __shared__ double lds[kFinThreads / kW];
@@ -968,7 +947,8 @@ struct Launch {
       else kb_update<float, true, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, k);
       kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R, 1, prm.max_iter);
       if (last) {
-        kb_replace<R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp);
+        kb_residual<float, R, false><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, 0ull,
+                                                        SlotScales{});
         kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
       }
     } else {
@@ -981,8 +961,9 @@ struct Launch {
   }
   static void init(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs,
                    double rtol) {
-    if (w.mixed) kb_start<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.part, g.G, g.Gp, mask, cs);
-    else kb_start<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.part, g.G, g.Gp, mask, cs);
+    if (w.mixed)
+      kb_residual<float, R, true><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask, cs);
+    else kb_residual<double, R, true><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask, cs);
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
   }
   static void finish(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const OutPtrs& out) {
