@@ -128,7 +128,8 @@ def serve_leg(args, ifl):
         pool = [np.asarray(W.sphere_k3_field(s, 3000 + 10 * L + i, n_waves=256, device="cuda:0"))
                 for i in range(4)]
         for n in (1, 2):
-            handles.append(ifl.prepare_mesh(s, ifl.IFL_VERTEX_SCALAR, n, precision=ifl.IFL_MIXED, device=0))
+            handles.append(ifl.prepare_mesh(s, ifl.IFL_VERTEX_SCALAR, n, precision=ifl.IFL_MIXED, device=0,
+                                            graphs=0 if args.no_graphs else 1))
             meshes.append((L, n, s.h))
             pools.append(pool)
     log(f"serving: {len(handles)} resident handles prepared in {time.time() - t0:.1f}s")
@@ -210,6 +211,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true", help="skip ifl_autotune (default tile and grids)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every kernel directly instead of replaying captured chunks")
     ap.add_argument("--serve-levels", default="6,7,8,9",
                     help="icosphere levels of the resident meshes (each prepared for n = 1 and n = 2)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean Poisson arrival rate, requests/s")
@@ -243,7 +246,8 @@ def main():
     mesh, fields_h, ks = make_workload(args.level, args.mask, args.fields, args.scales, dev)
     precision = ifl.IFL_MIXED if args.precision == "mixed" else ifl.IFL_FP64
     t0 = time.time()
-    h = ifl.prepare_mesh(mesh, ifl.IFL_VERTEX_SCALAR, 1, precision=precision, batch=args.batch, device=0)
+    h = ifl.prepare_mesh(mesh, ifl.IFL_VERTEX_SCALAR, 1, precision=precision, batch=args.batch, device=0,
+                         graphs=0 if args.no_graphs else 1)
     log(f"prepare {time.time() - t0:.1f}s, dofs={h.num_dofs}")
     tune = None
     if not args.no_autotune and args.batch != 1:
@@ -311,6 +315,7 @@ def main():
             "precision": args.precision,
             "batch": args.batch if args.batch else (f"autotuned ({tune['batch']})" if tune else "auto (32)"),
             "autotune": tune,
+            "graphs": not args.no_graphs,
             "rtol": 1e-12,
             "mean_cg_iterations": round(total_it / (n_solves * args.steps), 2),
         },

@@ -97,6 +97,8 @@ typedef struct ifl_options {
   int32_t reorder;   /* 1 = locality ordering of the rows (default): reverse Cuthill-McKee, on meshes of
                         >= 32768 dofs inside 8 Morton-curve parts; 0 = mesh order */
   int32_t profile;   /* 1 = time the SpMV launches with HIP events (ifl_profile_read) */
+  int32_t graphs;    /* 1 = the batched engine replays each 4-iteration chunk of a tile as one captured
+                        HIP graph (default), 0 = launches every kernel; results are bitwise equal */
 } ifl_options;
 
 /* Per-solve statistics (one per field x scale). */

@@ -71,6 +71,7 @@ class ifl_options(C.Structure):
         ("stream", C.c_void_p),
         ("reorder", C.c_int32),
         ("profile", C.c_int32),
+        ("graphs", C.c_int32),
     ]
 
 

@@ -24,6 +24,7 @@ static ifl_status check_options(const ifl_options& o) {
   if (o.max_iter < 1) return fail(IFL_EINVAL, "max_iter must be >= 1");
   if (o.precision != IFL_FP64 && o.precision != IFL_MIXED) return fail(IFL_EINVAL, "unknown precision");
   if (o.batch < 0 || o.batch > 64) return fail(IFL_EINVAL, "batch must be in 0..64");
+  if (o.graphs != 0 && o.graphs != 1) return fail(IFL_EINVAL, "graphs must be 0 or 1");
   return IFL_OK;
 }
 
@@ -56,6 +57,7 @@ void ifl_default_options(ifl_options* opt) {
   opt->stream = nullptr;
   opt->reorder = 1;
   opt->profile = 0;
+  opt->graphs = 1;
 }
 
 const char* ifl_last_error(void) { return g_last_error.c_str(); }

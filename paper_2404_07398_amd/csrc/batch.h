@@ -55,6 +55,7 @@ struct BatchParams {
   int max_iter = 20000;
   hipEvent_t ev_begin = nullptr;  // if set: recorded around the first SpMV launch
   hipEvent_t ev_end = nullptr;
+  bool graphs = true;             // replay whole chunks as captured HIP graphs
 };
 
 // Algorithmic bytes of one batched SpMV launch with 'live' active columns:
@@ -77,7 +78,11 @@ struct BatchWork {
   BSlot* slots = nullptr;
   BSlot* slots_host = nullptr;  // pinned
   int* flag = nullptr;
-  int64_t iter = 0;       // tile iterations so far (parity of the p ping-pong)
+  int64_t iter = 0;       // tile iterations so far (position in the chunk)
+  // one captured chunk (kChunk iterations), rebuilt when max_iter changes
+  hipGraphExec_t chunk_exec = nullptr;
+  int chunk_max_iter = 0;
+  bool graphs_broken = false;  // capture failed once: launch directly
 };
 
 // Scale factors c_j of the slots being initialised (kernel argument).

@@ -1085,6 +1085,7 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
 }
 
 void batch_free(BatchWork* w) {
+  if (w->chunk_exec) (void)hipGraphExecDestroy(w->chunk_exec);
   void* ptrs[] = {w->z32, w->p32[0], w->p32[1], w->p32[2], w->p32[3], w->q32, w->z64,  w->p64[0],
                   w->p64[1], w->p64[2], w->p64[3], w->q64, w->x,     w->phi,    w->part, w->slots, w->flag};
   for (void* p : ptrs)
@@ -1173,16 +1174,62 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
   return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 4.0 * vb * bm.n * live;
 }
 
+// Capture one chunk (kChunk iterations, no timing events) into w.chunk_exec.
+// The kernel arguments of a tile do not change from one chunk to the next, so
+// the one graph serves every chunk until max_iter changes.
+static ifl_status capture_chunk(const BMat& m, const BatchMatrix& bm, BatchWork& w, const BatchParams& prm,
+                                hipStream_t s) {
+  if (w.chunk_exec) {
+    (void)hipGraphExecDestroy(w.chunk_exec);
+    w.chunk_exec = nullptr;
+  }
+  BatchParams p = prm;
+  p.ev_begin = p.ev_end = nullptr;
+  IFL_HIPB(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < kChunk; ++k) dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, p, k);
+  hipGraph_t g = nullptr;
+  const hipError_t e1 = hipStreamEndCapture(s, &g);
+  const hipError_t e2 = hipGetLastError();
+  if (e1 != hipSuccess || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(IFL_EDEVICE, std::string("capturing a chunk failed: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  }
+  const hipError_t e3 = hipGraphInstantiate(&w.chunk_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) {
+    w.chunk_exec = nullptr;
+    return fail(IFL_EDEVICE, std::string("instantiating a chunk graph failed: ") + hipGetErrorString(e3));
+  }
+  w.chunk_max_iter = prm.max_iter;
+  return IFL_OK;
+}
+
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s) {
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
   if (n_iter % kChunk != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of kChunk");
   const BMat m = bmat(bm);
   BatchParams rest = prm;
   rest.ev_begin = rest.ev_end = nullptr;
-  for (int i = 0; i < n_iter; ++i) {
+  for (int i = 0; i < n_iter;) {
+    const bool timed = i == 0 && (prm.ev_begin || prm.ev_end);
+    if (!timed && prm.graphs && !w.graphs_broken && w.iter % kChunk == 0 && n_iter - i >= kChunk) {
+      if (!w.chunk_exec || w.chunk_max_iter != prm.max_iter) {
+        if (capture_chunk(m, bm, w, prm, s) != IFL_OK) {
+          // launch directly from now on; the stream is out of capture mode
+          w.graphs_broken = true;
+          (void)hipGetLastError();
+          continue;
+        }
+      }
+      IFL_HIPB(hipGraphLaunch(w.chunk_exec, s));
+      w.iter += kChunk;
+      i += kChunk;
+      continue;
+    }
     const int k = (int)(w.iter % kChunk);
-    dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, i == 0 ? prm : rest, k);
+    dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, timed ? prm : rest, k);
     ++w.iter;
+    ++i;
   }
   IFL_HIPB(hipGetLastError());
   return IFL_OK;

@@ -1046,6 +1046,7 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
                    [&](int64_t a, int64_t b) { return k[a % n_scales] < k[b % n_scales]; });
   BatchParams prm;
   prm.max_iter = h->opt.max_iter;
+  prm.graphs = h->opt.graphs != 0;
   std::vector<int64_t> slot_col(R, -1);
   std::vector<std::chrono::steady_clock::time_point> t_in(R);
   int64_t next = 0, finished = 0;
@@ -1206,6 +1207,7 @@ ifl_status device_autotune(Handle* h, ifl_tune* out) {
         }
         BatchParams prm;
         prm.max_iter = 1 << 30;
+        prm.graphs = h->opt.graphs != 0;
         if (st == IFL_OK) st = batch_init(bm, w, mask, cs, 1e-300, s);
         if (st == IFL_OK) st = batch_iterate(bm, w, kChunk, prm, s);  // warm-up
         float ms = 0.f;

@@ -134,6 +134,7 @@ ifl_status run_worker(Worker* wk) {
   const double rtol = h->opt.rtol;
   BatchParams prm;
   prm.max_iter = h->opt.max_iter;
+  prm.graphs = h->opt.graphs != 0;
   const int chunk = 4;
   int active = 0;
   for (;;) {

@@ -170,6 +170,12 @@ def test_set_options_keeps_the_others():
     with pytest.raises(ifl.IflError) as e:
         h.set_options(reorder=0)
     assert e.value.status == ifl.IFL_EINVAL
+    assert h.options().graphs == 1  # captured chunks are the default
+    h.set_options(graphs=0)
+    assert h.options().graphs == 0 and h.options().batch == 16
+    with pytest.raises(ifl.IflError) as e:
+        h.set_options(graphs=2)
+    assert e.value.status == ifl.IFL_EINVAL
     h.close()
 
 

@@ -375,6 +375,40 @@ def test_batched_alone_equals_in_mix(ifl, precision):
     h.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_equals_direct_launches(ifl, precision):
+    """Chunks replayed from a captured HIP graph give bitwise the results of
+    the same kernels launched one by one, call after call (the graph is
+    replayed many times, with other GPU work and host syncs in between, and
+    captured again after max_iter changes)."""
+    import torch
+
+    s, phi = _sphere(5, 0.3)
+    fields = np.stack([phi] + [W.sphere_k3_field(s, 3000 + i, n_waves=128) for i in range(4)])
+    ks = W.log_scales(s.h, 5)
+    direct = _prep(ifl, s, n=2, precision=precision, batch=8, graphs=0)
+    ref, st_ref = direct.filter(fields, ks)
+    direct.close()
+    h = _prep(ifl, s, n=2, precision=precision, batch=8)
+    assert h.options().graphs == 1
+    a = torch.randn(512, 512, device="cuda:0")
+    for rep in range(3):
+        if rep == 2:
+            h.set_options(max_iter=h.options().max_iter + 1)
+        out, st = h.filter(fields, ks)
+        b = (a @ a).sum().item()  # eager work on torch's stream between calls
+        torch.cuda.synchronize()
+        assert math.isfinite(b)
+        assert np.array_equal(out, ref), rep
+        assert [x.iterations for x in st] == [x.iterations for x in st_ref]
+    op = O.scalar_operator(s, 2)
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    r0 = O.filter_scalar(op, fields[0], ks)
+    for j in range(len(ks)):
+        assert relative_l2(ref[0, j], r0[j]) <= tol
+    h.close()
+
+
 def test_batched_edge_cases(ifl):
     import torch
 

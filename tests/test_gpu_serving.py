@@ -85,6 +85,19 @@ def test_served_results_match_oracle_and_alone(ifl):
     srv.close()
     for h in handles:
         h.close()
+    # a server whose handles launch every kernel directly (no captured
+    # chunks) gives bitwise the same fields
+    handles = [ifl.prepare_mesh(mesh, 0, n, precision=ifl.IFL_MIXED, graphs=0) for mesh, n in meshes]
+    srv = ifl.Server(4 << 30, slots=8)
+    ids = [srv.add(h) for h in handles]
+    tickets = [(idx, srv.submit(ids[reqs[idx][0]], reqs[idx][1], reqs[idx][2])) for idx in (1, 6, 12, 22)]
+    for idx, (t, out) in tickets:
+        st, stats, o, lat = srv.wait(t, len(reqs[idx][2]))
+        assert st == 0
+        assert np.array_equal(o, results[idx]), idx
+    srv.close()
+    for h in handles:
+        h.close()
 
 
 def test_server_errors(ifl):
