@@ -367,12 +367,15 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
 // chunk (XUP) the chunk's x update is applied at once, in FP64 in every
 // precision, from the directions kept in p[0..3] and each column's alpha
 // history: x += sum_k alpha_k p_k. z of columns that are not iterating is
-// left unchanged.
+// left unchanged. A mixed tile replaces every running column's residual right
+// after its chunk's x update, so there the last iteration updates x only (no
+// z, no partials).
 template <typename T, bool MIXED, bool XUP, int R>
 __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
                                                 int k) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
+  constexpr bool ZUP = !(MIXED && XUP);
   __shared__ double lds[2 * kWpb * R];
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
@@ -400,8 +403,6 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
       const int64_t row = wk.t * RPW + rsub;
       if (row >= m.n) continue;
       const int64_t idx = row * R + j0;
-      const Pack<T, C> qv = vload<T, C>(v.q + idx);
-      Pack<T, C> zv = vload<T, C>(v.z + idx);
       if constexpr (XUP) {
         Pack<T, C> pk[kChunk];
 #pragma unroll
@@ -413,6 +414,9 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
           for (int i = 0; i < kChunk; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
         vstore<double, C>(v.x + idx, xv);
       }
+      if constexpr (!ZUP) continue;
+      const Pack<T, C> qv = vload<T, C>(v.q + idx);
+      Pack<T, C> zv = vload<T, C>(v.z + idx);
       const double mi = m.mass[row], kd = m.kdiag[row];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -428,12 +432,14 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
       vstore<T, C>(v.z + idx, zv);
     }
   }
-  double tot[2];
-  col_sum<R, C, 2>(acc, lds, tot);
-  if (threadIdx.x < R) {
-    const int lb = lblock(G);
-    part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
-    part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
+  if constexpr (ZUP) {
+    double tot[2];
+    col_sum<R, C, 2>(acc, lds, tot);
+    if (threadIdx.x < R) {
+      const int lb = lblock(G);
+      part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
+      part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
+    }
   }
 }
 
@@ -831,7 +837,8 @@ __global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const doubl
   }
 }
 
-// phase 3 (mixed, after the replacement pass): replaced residual and stopping test
+// phase 2 of a mixed tile's last iteration in a chunk (after the x update and
+// the replacement pass): rho, beta from the replaced residual and the test
 __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const double* part, int G, int Gp, int R,
                                                            int max_iter) {
   __shared__ double lds[kFinThreads / kW];
@@ -842,9 +849,11 @@ __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const do
   const double rr = fin_sum(part + (Q_RR * R + j) * Gp, G, lds);
   const double fl = fin_sum(part + (Q_FL * R + j) * Gp, G, lds);
   if (threadIdx.x == 0) {
+    s.rho_prev = s.rho;
     s.rho = rz;
     s.beta = rz / s.rho_prev;
     s.rr = rr;
+    s.iters += 1;
     s.rr_true = 1;
     s.updates += 1;
     const double floor2 = fl * (kFloor * kU) * (kFloor * kU);
@@ -943,13 +952,14 @@ struct Launch {
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
     kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
     if (w.mixed) {
-      if (last) kb_update<float, true, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, k);
-      else kb_update<float, true, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, k);
-      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R, 1, prm.max_iter);
       if (last) {
+        kb_update<float, true, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, k);
         kb_residual<float, R, false><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, 0ull,
                                                         SlotScales{});
         kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
+      } else {
+        kb_update<float, true, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, k);
+        kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R, 1, prm.max_iter);
       }
     } else {
       if (last)
