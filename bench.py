@@ -28,31 +28,32 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# rocprofv3 summary of the default workload: per-launch HBM bytes of the
-# batched SpMV kernel from FETCH_SIZE / WRITE_SIZE counters, scaled by the
-# counters of a plain device copy of known size
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "kb_dir_spmv_f32_R32_icosphere-L9-mask40_64x30_n1.txt")
+# rocprofv3 summaries of the default workload (profiles/*.txt): per-launch
+# HBM bytes of the batched SpMV kernel from FETCH_SIZE / WRITE_SIZE counters,
+# scaled by the counters of a plain device copy of known size
+PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
 def recorded_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` as counted in the committed profile,
+    """HBM bytes per launch of `kernel` as counted in a committed profile,
     or None if there is none or the kernel source changed since."""
+    import glob
     import hashlib
 
-    try:
-        kv = {}
-        for line in open(TRAFFIC_PROFILE):
-            if ":" in line:
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-        src = os.path.join(ROOT, "paper_2404_07398_amd", "csrc", "batch.hip")
-        if kv.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
-            return None
-        if kv.get("traffic_kernel") != kernel:
-            return None
-        return float(kv["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+    src = os.path.join(ROOT, "paper_2404_07398_amd", "csrc", "batch.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(PROFILE_DIR, "*.txt"))):
+        try:
+            kv = {}
+            for line in open(path):
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+            if kv.get("kernel_source_sha256") == sha and kv.get("traffic_kernel") == kernel:
+                return float(kv["traffic_bytes_per_launch"])
+        except (OSError, KeyError, ValueError):
+            continue
+    return None
 
 
 def log(*a):
@@ -285,11 +286,7 @@ def main():
     launches, ms, bytes_per = h.profile_read(reset=True)
     mean_s = ms / 1e3 / max(1, launches)
     achieved = bytes_per / mean_s / 1e9 if launches else 0.0
-    if args.batch == 1:
-        kernel = "k_dir_spmv<double, false>" if precision == ifl.IFL_FP64 else "k_dir_spmv<float, true>"
-    else:
-        R = args.batch if args.batch else (tune["batch"] if tune else 32)
-        kernel = f"kb_dir_spmv<{'float' if precision == ifl.IFL_MIXED else 'double'}, {R}>"
+    kernel = h.profile_kernel()
     default_workload = (args.level, args.mask, args.fields, args.scales) == (9, 0.4, 64, 30)
     traffic = recorded_traffic(kernel) if default_workload else None
     value = n_solves * args.steps / el

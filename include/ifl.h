@@ -236,6 +236,14 @@ ifl_status ifl_profile_read(ifl_handle* h, int64_t* launches, double* total_ms,
                             double* bytes_per_launch, int32_t reset);
 
 /*
+ * Name of the SpMV kernel of the last timed launch, as a profiler lists it
+ * (e.g. "kb_dir_spmv<float, 32>"), NUL-terminated in buf (len bytes, the
+ * name truncated to fit); "" before the first timed launch. IFL_EINVAL for
+ * a NULL handle or buffer, IFL_EDEVICE for a host-only handle.
+ */
+ifl_status ifl_profile_kernel(ifl_handle* h, char* buf, int32_t len);
+
+/*
  * Autotuner of the batched engine (the multi-column CG of Sect. 2.2.2 run as
  * one SpMM-like pass per iteration). Times full tiles of pseudo-random
  * columns for tile sizes 16, 32 and 64 and several grid sizes of the

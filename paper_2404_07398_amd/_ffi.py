@@ -125,6 +125,7 @@ _PROTOS = {
     "ifl_last_error": (C.c_char_p, []),
     "ifl_profile_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_int32]),
+    "ifl_profile_kernel": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32]),
     "ifl_autotune": (C.c_int32, [C.c_void_p, C.POINTER(ifl_tune)]),
     "ifl_server_create": (C.c_int32, [C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]),
     "ifl_server_add": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -331,6 +332,12 @@ class Handle:
         b = C.c_double()
         _check(lib().ifl_profile_read(self._h, C.byref(n), C.byref(ms), C.byref(b), int(reset)))
         return int(n.value), float(ms.value), float(b.value)
+
+    def profile_kernel(self) -> str:
+        """Name of the SpMV kernel of the last timed launch (``ifl_profile_kernel``)."""
+        buf = C.create_string_buffer(128)
+        _check(lib().ifl_profile_kernel(self._h, buf, len(buf)))
+        return buf.value.decode()
 
     def autotune(self) -> dict:
         """Time tile and grid sizes of the batched engine on this handle

@@ -1,5 +1,6 @@
 // C ABI of the implicit-filter library: argument checks, handle lifetime,
 // save / load, and dispatch to the prepare and device layers.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -277,6 +278,18 @@ ifl_status ifl_profile_read(ifl_handle* h, int64_t* launches, double* total_ms, 
   if (!h->dev) return fail(IFL_EDEVICE, "host-only handle (device = -1)");
   std::lock_guard<std::mutex> lk(h->mu);
   return device_profile_read(h, launches, total_ms, bytes_per_launch, reset);
+}
+
+ifl_status ifl_profile_kernel(ifl_handle* h, char* buf, int32_t len) {
+  if (!h) return fail(IFL_EINVAL, "handle is NULL");
+  if (!buf || len < 1) return fail(IFL_EINVAL, "buffer is NULL or empty");
+  if (!h->dev) return fail(IFL_EDEVICE, "host-only handle (device = -1)");
+  std::lock_guard<std::mutex> lk(h->mu);
+  const std::string name = device_profile_kernel(h);
+  const size_t n = std::min(name.size(), (size_t)len - 1);
+  std::memcpy(buf, name.data(), n);
+  buf[n] = '\0';
+  return IFL_OK;
 }
 
 ifl_status ifl_autotune(ifl_handle* h, ifl_tune* out) {

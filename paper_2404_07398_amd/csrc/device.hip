@@ -117,6 +117,7 @@ struct DeviceState {
   int64_t prof_launches = 0;
   double prof_ms = 0.0;
   double prof_bytes = 0.0;  // summed algorithmic bytes of the timed launches
+  std::string prof_kernel;  // the kernel those launches ran
   // batched engine work space (allocated on first use)
   BatchWork bw;
   // grid sizes picked by the autotuner, per (tile size, precision), and the
@@ -849,6 +850,7 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
         d->prof_ms += ms;
         d->prof_launches += 1;
         d->prof_bytes += spmv_bytes(M, sizeof(T));
+        d->prof_kernel = MIXED ? "k_dir_spmv<float, true>" : "k_dir_spmv<double, false>";
       }
       iters_seen = sh.iters;
       if (sh.done) finished = true;
@@ -1088,6 +1090,7 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
       d->prof_ms += ms;
       d->prof_launches += 1;
       d->prof_bytes += batch_spmv_bytes(bm, d->m.nnz_stored, mixed, live);
+      d->prof_kernel = std::string("kb_dir_spmv<") + (mixed ? "float, " : "double, ") + std::to_string(R) + ">";
     }
     uint64_t fin = 0;
     std::vector<double*> dst(R, nullptr);
@@ -1271,6 +1274,8 @@ ifl_status device_apply(Handle* h, double kk, const double* x, double* y) {
   IFL_HIP(hipStreamSynchronize(s));
   return IFL_OK;
 }
+
+std::string device_profile_kernel(Handle* h) { return h->dev->prof_kernel; }
 
 ifl_status device_profile_read(Handle* h, int64_t* launches, double* total_ms, double* bytes, int32_t reset) {
   DeviceState* d = h->dev;

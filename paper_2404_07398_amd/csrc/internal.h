@@ -76,6 +76,7 @@ ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int3
 ifl_status device_apply(Handle* h, double k, const double* x, double* y);
 ifl_status device_profile_read(Handle* h, int64_t* launches, double* total_ms, double* bytes,
                                int32_t reset);
+std::string device_profile_kernel(Handle* h);
 ifl_status device_autotune(Handle* h, ifl_tune* out);
 
 }  // namespace ifl

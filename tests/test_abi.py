@@ -176,6 +176,9 @@ def test_set_options_keeps_the_others():
     with pytest.raises(ifl.IflError) as e:
         h.set_options(graphs=2)
     assert e.value.status == ifl.IFL_EINVAL
+    with pytest.raises(ifl.IflError) as e:
+        h.profile_kernel()  # host-only handle
+    assert e.value.status == ifl.IFL_EDEVICE
     h.close()
 
 

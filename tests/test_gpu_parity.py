@@ -218,8 +218,10 @@ def test_full_size_level9_certified(ifl, precision, batch):
     phi = W.sphere_k3_field(s, 1000, n_waves=512, device="cuda")
     ks = W.log_scales(s.h, 30)[[0, 15, 29]]
     op = O.scalar_operator(s, 1)
-    h = _prep(ifl, s, precision=precision, batch=batch)
+    h = _prep(ifl, s, precision=precision, batch=batch, profile=1)
     out, stats = h.filter(phi, ks)
+    t = "float" if precision else "double"
+    assert h.profile_kernel() == (f"kb_dir_spmv<{t}, {batch}>" if batch > 1 else f"k_dir_spmv<{t}, {str(bool(precision)).lower()}>")
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j, k in enumerate(ks):
         cert = _oracle_certificate(op, phi, k, out[0, j])
