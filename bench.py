@@ -140,58 +140,64 @@ def serve_leg(args, ifl):
     for i, (L, n, h) in enumerate(meshes):
         t, _ = srv.submit(ids[i], pools[i][0], np.array([2 * math.pi / (4 * h)]))
         srv.wait(t, 1)
-    # the stream: uniform mesh and order, 1-32 log-spaced scales in [2h, 32h] wavelengths
-    N = args.serve_requests
-    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, N))
-    reqs = []
-    for r in range(N):
-        i = int(rng.integers(len(handles)))
-        L, n, h = meshes[i]
-        ns = int(rng.integers(1, 33))
-        ks = np.sort(np.exp(rng.uniform(math.log(2 * math.pi / (32 * h)), math.log(2 * math.pi / (2 * h)), ns)))
-        reqs.append((i, int(rng.integers(4)), ks))
-    torch.cuda.synchronize()
-    tickets = []
-    t_start = time.perf_counter()
-    for r, (i, f, ks) in enumerate(reqs):
-        delay = arrivals[r] - (time.perf_counter() - t_start)
-        if delay > 0:
-            time.sleep(delay)
-        t, out = srv.submit(ids[i], pools[i][f], ks)
-        tickets.append((t, ks.size, i))
-    lat, solves, iters, bad = [], 0, 0, 0
-    per = {}
-    for t, ns, i in tickets:
-        st, stats, out, l = srv.wait(t, ns)
-        del out
-        bad += st != 0
-        lat.append(l)
-        solves += ns
-        iters += sum(x.iterations for x in stats)
-        per.setdefault(meshes[i][:2], []).append(l)
-    el = time.perf_counter() - t_start
+    def stream(rate, N):
+        # uniform mesh and order, 1-32 log-spaced scales in [2h, 32h] wavelengths
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, N))
+        reqs = []
+        for r in range(N):
+            i = int(rng.integers(len(handles)))
+            L, n, h = meshes[i]
+            ns = int(rng.integers(1, 33))
+            ks = np.sort(np.exp(rng.uniform(math.log(2 * math.pi / (32 * h)), math.log(2 * math.pi / (2 * h)), ns)))
+            reqs.append((i, int(rng.integers(4)), ks))
+        torch.cuda.synchronize()
+        tickets = []
+        t_start = time.perf_counter()
+        for r, (i, f, ks) in enumerate(reqs):
+            delay = arrivals[r] - (time.perf_counter() - t_start)
+            if delay > 0:
+                time.sleep(delay)
+            t, out = srv.submit(ids[i], pools[i][f], ks)
+            tickets.append((t, ks.size, i))
+        lat, solves, iters, bad = [], 0, 0, 0
+        per = {}
+        for t, ns, i in tickets:
+            st, stats, out, lt = srv.wait(t, ns)
+            del out
+            bad += st != 0
+            lat.append(lt)
+            solves += ns
+            iters += sum(x.iterations for x in stats)
+            per.setdefault(meshes[i][:2], []).append(lt)
+        el = time.perf_counter() - t_start
+        lat = np.array(lat)
+        return {
+            "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "solves_per_s": round(solves / el, 2),
+            "requests": N,
+            "failed": int(bad),
+            "offered_rate_req_s": rate,
+            "completed_rate_req_s": round(N / el, 2),
+            "arrival_window_s": round(float(arrivals[-1]), 3),
+            "drain_s": round(el, 3),
+            "solves": int(solves),
+            "mean_cg_iterations": round(iters / max(1, solves), 1),
+            "p50_latency_ms_by_mesh": {f"L{L}-n{n}": round(float(np.percentile(v, 50)) * 1e3, 1)
+                                       for (L, n), v in sorted(per.items())},
+            "workload": f"Poisson arrivals, {N} requests at {rate:g}/s over icosphere levels "
+                        f"{args.serve_levels} (30% land mask) x n in {{1,2}}, 1-32 scales each, mixed precision, "
+                        f"{args.serve_slots} slots per mesh",
+        }
+
+    res = stream(args.serve_rate, args.serve_requests)
+    log(f"serving at {args.serve_rate:g}/s: {res}")
+    if args.serve_sustained_rate > 0 and args.serve_sustained_requests > 0:
+        res["sustained"] = stream(args.serve_sustained_rate, args.serve_sustained_requests)
     srv.close()
     for h in handles:
         h.close()
-    lat = np.array(lat)
-    return {
-        "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-        "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-        "solves_per_s": round(solves / el, 2),
-        "requests": N,
-        "failed": int(bad),
-        "offered_rate_req_s": args.serve_rate,
-        "completed_rate_req_s": round(N / el, 2),
-        "arrival_window_s": round(float(arrivals[-1]), 3),
-        "drain_s": round(el, 3),
-        "solves": int(solves),
-        "mean_cg_iterations": round(iters / max(1, solves), 1),
-        "p50_latency_ms_by_mesh": {f"L{L}-n{n}": round(float(np.percentile(v, 50)) * 1e3, 1)
-                                   for (L, n), v in sorted(per.items())},
-        "workload": f"Poisson arrivals, {N} requests at {args.serve_rate:g}/s over icosphere levels "
-                    f"{args.serve_levels} (30% land mask) x n in {{1,2}}, 1-32 scales each, mixed precision, "
-                    f"{args.serve_slots} slots per mesh",
-    }
+    return res
 
 
 def main():
@@ -219,6 +225,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean Poisson arrival rate, requests/s")
     ap.add_argument("--serve-requests", type=int, default=300, help="requests in the arrival stream")
     ap.add_argument("--serve-slots", type=int, default=8, help="column slots per resident mesh")
+    ap.add_argument("--serve-sustained-rate", type=float, default=15.0,
+                    help="second arrival stream, below the server's capacity (requests/s; 0 = skip)")
+    ap.add_argument("--serve-sustained-requests", type=int, default=150)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this size (a known-traffic kernel for "
                          "calibrating HBM byte counters)")

@@ -681,24 +681,32 @@ __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* 
 }
 
 // x of the columns in 'mask' to the caller's numbering, one caller entry per
-// thread: coalesced writes (0 where there is no dof), each thread reading
-// its row's columns together.
-__global__ void kb_out(const double* __restrict__ x, int R, OutPtrs out, uint64_t mask, const int32_t* __restrict__ row_of,
+// thread: coalesced writes (0 where there is no dof). Each thread loads all
+// of its row's wanted columns before it stores any: as far as the compiler
+// knows a store could change x, so interleaved loads would each wait for
+// the store before them, and the row's lines would be fetched again.
+template <int R>
+__global__ void kb_out(const double* __restrict__ x, OutPtrs out, uint64_t mask, const int32_t* __restrict__ row_of,
                        int64_t L) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= L) return;
   const int64_t i = row_of[v];
-  if (R == 1) {
+  if constexpr (R == 1) {
     if (mask & 1ull) out.p[0][v] = i >= 0 ? x[i] : 0.0;
-    return;
-  }
-  for (int j = 0; j < R; j += 2) {
-    const uint64_t bits = (mask >> j) & 3ull;
-    if (!bits) continue;
-    Pack<double, 2> xv = {};
-    if (i >= 0) xv = vload<double, 2>(x + i * R + j);
-    if (bits & 1ull) out.p[j][v] = xv.v[0];
-    if (bits & 2ull) out.p[j + 1][v] = xv.v[1];
+  } else {
+    constexpr int NP = R / 2;
+    Pack<double, 2> xv[NP];
+#pragma unroll
+    for (int jp = 0; jp < NP; ++jp) {
+      xv[jp] = {};
+      if (i >= 0 && ((mask >> (2 * jp)) & 3ull)) xv[jp] = vload<double, 2>(x + i * R + 2 * jp);
+    }
+#pragma unroll
+    for (int jp = 0; jp < NP; ++jp) {
+      const uint64_t bits = (mask >> (2 * jp)) & 3ull;
+      if (bits & 1ull) out.p[2 * jp][v] = xv[jp].v[0];
+      if (bits & 2ull) out.p[2 * jp + 1][v] = xv[jp].v[1];
+    }
   }
 }
 
@@ -985,7 +993,7 @@ struct Launch {
       uint64_t omask = 0;
       for (int j = 0; j < R; ++j)
         if (((mask >> j) & 1ull) && out.p[j]) omask |= 1ull << j;
-      kb_out<<<(unsigned)((m.field_len + 255) / 256), 256, 0, s>>>(w.x, R, out, omask, m.row_of, m.field_len);
+      kb_out<R><<<(unsigned)((m.field_len + 255) / 256), 256, 0, s>>>(w.x, out, omask, m.row_of, m.field_len);
     }
     kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, w.mixed ? 1 : 0);
   }
