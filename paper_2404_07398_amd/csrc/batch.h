@@ -53,14 +53,16 @@ struct BatchMatrix {
 
 struct BatchParams {
   int max_iter = 20000;
-  hipEvent_t ev_begin = nullptr;  // if set: recorded around the first SpMV launch
+  hipEvent_t ev_begin = nullptr;  // if set: recorded around the second SpMV launch
   hipEvent_t ev_end = nullptr;
   bool graphs = true;             // replay whole chunks as captured HIP graphs
 };
 
-// Algorithmic bytes of one batched SpMV launch with 'live' active columns:
-// the sliced-ELL stream, mass and diagonal, and per live column the reads of
-// z and p (each once) and the writes of p and q.
+// Algorithmic bytes of one batched SpMV launch of the recurrence form (the
+// second to fourth iteration of a chunk, the one batch_iterate times) with
+// 'live' active columns: the sliced-ELL stream, mass and diagonal, and per
+// live column the reads of z, p and the previous q (each once) and the
+// writes of p and q.
 double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, int live);
 
 // Device work space of one tile of R slots (vectors rows x R).

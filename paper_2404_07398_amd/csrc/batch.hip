@@ -225,6 +225,13 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 // p_new = z + beta p (own row and gathered neighbours), q = S p_new,
 // partial (p_new, q) per column.
 //
+// REC (iterations 1..3 of a chunk): q = S z + beta q_prev instead, which is
+// S p_new as well (S p_new = S z + beta S p and q_prev = S p), so only z is
+// gathered and q_prev is read on the row itself. The first iteration of
+// every chunk forms S p_new directly, so the rounding of the recurrence
+// never spans more than three iterations, and the FP64 residual
+// replacement of mixed tiles does not depend on it.
+//
 // The loop over a wavefront's tasks is software-pipelined so that a task
 // costs about one memory round trip instead of three. While the gathers of
 // task i are in flight, the slice bounds of task i + 2 and the column
@@ -235,7 +242,7 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 // issued after it. Rows with more than kHead off-diagonal entries finish
 // the rest unpipelined (the biharmonic operator); the first-order operator
 // on triangle meshes has at most six.
-template <typename T, int R>
+template <typename T, int R, bool REC>
 __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
                                                   int k) {
   using Gm = Geo<T, R>;
@@ -261,6 +268,7 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
   const T* __restrict__ z = v.z;
   const T* __restrict__ val = bval<T>(m);
   const auto dir = [&](int c, T zz, T pp) { return fma(beta[c], pp, zz); };
+  const auto zonly = [&](int, T zz, T) { return zz; };
   double acc[1][C] = {};
   if (any) {
     const Walk wk = task_walk(m.n_slices * LPR, G);
@@ -273,7 +281,7 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
     auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
     int32_t cu[kHead];
     T vu[kHead];
-    Pack<T, C> zi, pi;
+    Pack<T, C> zi, pi, qi;
     double mi, kd;
     int64_t base, nb, ne;  // this task's slice base; next task's raw slice bounds
     int w;
@@ -291,6 +299,7 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
       const int64_t idx = row * R + j0;
       zi = vload<T, C>(z + idx);
       pi = vload<T, C>(pin + idx);
+      if constexpr (REC) qi = vload<T, C>(v.q + idx);
       mi = m.mass[row];
       kd = m.kdiag[row];
     };
@@ -314,7 +323,7 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
       for (int u = 0; u < kHead; ++u) {
         const int64_t off = (int64_t)(u < w ? cu[u] : self) * R + j0;
         g0[u] = vload<T, C>(z + off);
-        g1[u] = vload<T, C>(pin + off);
+        if constexpr (!REC) g1[u] = vload<T, C>(pin + off);
       }
       const int64_t cbase = base;
       const int cw = w;
@@ -334,11 +343,16 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
       for (int u = 0; u < kHead; ++u) {
         const T vm = u < cw ? vu[u] : (T)0;
 #pragma unroll
-        for (int c = 0; c < C; ++c) a[c] = fma(vm, dir(c, g0[u].v[c], g1[u].v[c]), a[c]);
+        for (int c = 0; c < C; ++c) a[c] = fma(vm, REC ? g0[u].v[c] : dir(c, g0[u].v[c], g1[u].v[c]), a[c]);
       }
-      if (cw > kHead)
-        row_product<T, T, R, C, true, false, decltype(dir), kHead>(m, val, cbase, cw, row % kW, j0, z, pin, dir, a,
-                                                                    kHead);
+      if (cw > kHead) {
+        if constexpr (REC)
+          row_product<T, T, R, C, false, false, decltype(zonly), kHead>(m, val, cbase, cw, row % kW, j0, z, z, zonly,
+                                                                          a, kHead);
+        else
+          row_product<T, T, R, C, true, false, decltype(dir), kHead>(m, val, cbase, cw, row % kW, j0, z, pin, dir, a,
+                                                                      kHead);
+      }
       const bool real = row < m.n;
       const int64_t idx = row * R + j0;
       Pack<T, C> pn, qv;
@@ -346,7 +360,8 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
       for (int c = 0; c < C; ++c) {
         pn.v[c] = fma(beta[c], pi.v[c], zi.v[c]);
         const T d = (T)(mi + c64[c] * kd);
-        qv.v[c] = fma(d, pn.v[c], cc[c] * a[c]);
+        if constexpr (REC) qv.v[c] = fma(beta[c], qi.v[c], fma(d, zi.v[c], cc[c] * a[c]));
+        else qv.v[c] = fma(d, pn.v[c], cc[c] * a[c]);
         const double pq = (double)pn.v[c] * (double)qv.v[c];
         acc[0][c] += (on[c] && real) ? pq : 0.0;
       }
@@ -949,14 +964,19 @@ struct Grids {
 
 template <int R>
 struct Launch {
+  template <typename T>
+  static void dir_spmv(const BMat& m, BatchWork& w, Grids g, hipStream_t s, int k) {
+    if (k == 0) kb_dir_spmv<T, R, false><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k);
+    else kb_dir_spmv<T, R, true><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k);
+  }
   // iteration k (0..kChunk-1) of a chunk; the last one applies the
   // chunk's x update and, for mixed tiles, the residual
   // replacement of every running column
   static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k) {
     const bool last = k == kChunk - 1;
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
-    if (w.mixed) kb_dir_spmv<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, k);
-    else kb_dir_spmv<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, k);
+    if (w.mixed) dir_spmv<float>(m, w, g, s, k);
+    else dir_spmv<double>(m, w, g, s, k);
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
     kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
     if (w.mixed) {
@@ -1037,13 +1057,13 @@ int occupancy_of(int R) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (R) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 1>, kB, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 2>, kB, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 4>, kB, 0); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 8>, kB, 0); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 16>, kB, 0); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 32>, kB, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 64>, kB, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 1, false>, kB, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 2, false>, kB, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 4, false>, kB, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 8, false>, kB, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 16, false>, kB, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 32, false>, kB, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 64, false>, kB, 0); break;
   }
   return e == hipSuccess ? nb : 0;
 }
@@ -1189,7 +1209,7 @@ ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const 
 
 double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, int live) {
   const double vb = mixed ? 4.0 : 8.0;
-  return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 4.0 * vb * bm.n * live;
+  return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 5.0 * vb * bm.n * live;
 }
 
 // Capture one chunk (kChunk iterations, no timing events) into w.chunk_exec.
@@ -1226,10 +1246,14 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
   if (n_iter % kChunk != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of kChunk");
   const BMat m = bmat(bm);
+  // the timing events (if any) go around the SpMV of the call's second
+  // iteration (the recurrence form that runs three times per chunk); the
+  // chunk holding it is launched directly
   BatchParams rest = prm;
   rest.ev_begin = rest.ev_end = nullptr;
+  const bool events = prm.ev_begin || prm.ev_end;
   for (int i = 0; i < n_iter;) {
-    const bool timed = i == 0 && (prm.ev_begin || prm.ev_end);
+    const bool timed = events && i <= 1;
     if (!timed && prm.graphs && !w.graphs_broken && w.iter % kChunk == 0 && n_iter - i >= kChunk) {
       if (!w.chunk_exec || w.chunk_max_iter != prm.max_iter) {
         if (capture_chunk(m, bm, w, prm, s) != IFL_OK) {
@@ -1245,7 +1269,7 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
       continue;
     }
     const int k = (int)(w.iter % kChunk);
-    dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, timed ? prm : rest, k);
+    dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, i == 1 ? prm : rest, k);
     ++w.iter;
     ++i;
   }

@@ -1090,7 +1090,7 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
       d->prof_ms += ms;
       d->prof_launches += 1;
       d->prof_bytes += batch_spmv_bytes(bm, d->m.nnz_stored, mixed, live);
-      d->prof_kernel = std::string("kb_dir_spmv<") + (mixed ? "float, " : "double, ") + std::to_string(R) + ">";
+      d->prof_kernel = std::string("kb_dir_spmv<") + (mixed ? "float, " : "double, ") + std::to_string(R) + ", true>";
     }
     uint64_t fin = 0;
     std::vector<double*> dst(R, nullptr);
@@ -1229,10 +1229,11 @@ ifl_status device_autotune(Handle* h, ifl_tune* out) {
       }
     per_R.push_back(b);
   }
-  // the fastest tile size, preferring the smaller one within 3% (a smaller
-  // tile wastes fewer slots when columns run out and needs less memory)
+  // the fastest tile size, preferring the smaller one within 5%: a smaller
+  // tile wastes fewer slots when a call's columns run out (the trial tiles
+  // are always full) and needs less memory
   for (const Best& b : per_R)
-    if (b.us < overall.us * 0.97 || overall.R == 0) overall = b;
+    if (b.us < overall.us * 0.95 || overall.R == 0) overall = b;
   for (const Best& b : per_R) {
     bool found = false;
     for (auto& t : d->tuned)

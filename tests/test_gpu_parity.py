@@ -221,7 +221,8 @@ def test_full_size_level9_certified(ifl, precision, batch):
     h = _prep(ifl, s, precision=precision, batch=batch, profile=1)
     out, stats = h.filter(phi, ks)
     t = "float" if precision else "double"
-    assert h.profile_kernel() == (f"kb_dir_spmv<{t}, {batch}>" if batch > 1 else f"k_dir_spmv<{t}, {str(bool(precision)).lower()}>")
+    assert h.profile_kernel() == (f"kb_dir_spmv<{t}, {batch}, true>" if batch > 1
+                                  else f"k_dir_spmv<{t}, {str(bool(precision)).lower()}>")
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j, k in enumerate(ks):
         cert = _oracle_certificate(op, phi, k, out[0, j])
