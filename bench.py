@@ -77,11 +77,14 @@ def make_workload(level: int, mask: float, n_fields: int, n_scales: int, device:
     return s, np.stack(fields), ks
 
 
-def cpu_baseline(mesh, fields, ks, budget_s: float = 20.0):
+def cpu_baseline(mesh, fields, ks, budget_s: float = 20.0, gpu_column=None):
     """The FP64 oracle on a bounded sample: solves of field 0 at scales
     taken alternately from both ends of the k list, until the budget is
-    spent (at least one solve)."""
+    spent (at least one solve). With gpu_column(j) (the GPU's result for
+    field 0 at scale j, caller numbering), also the relative L2 error of the
+    GPU results on that sample (not timed)."""
     import oracle as O
+    from oracle.solve import relative_l2
 
     t0 = time.time()
     op = O.scalar_operator(mesh, 1)
@@ -95,13 +98,20 @@ def cpu_baseline(mesh, fields, ks, budget_s: float = 20.0):
         lo, hi = lo + 1, hi - 1
     done = 0
     t1 = time.time()
+    sols = []
     for j in order:
-        O.filter_scalar(op, fields[0], [ks[j]])
+        sols.append((j, O.filter_scalar(op, fields[0], [ks[j]])[0]))
         done += 1
         if time.time() - t1 > budget_s:
             break
     el = time.time() - t1
-    return {
+    parity = None
+    if gpu_column is not None:
+        errs = [relative_l2(gpu_column(j), x) for j, x in sols]
+        parity = {"max_rel_l2": float(max(errs)), "solves": len(errs), "tol": 1e-9,
+                  "what": "GPU result of the benchmark's launch configuration vs the FP64 oracle on the "
+                          "baseline's sample (field 0)"}
+    return parity, {
         "value": done / el,
         "unit": "solves/s",
         "cores": 1,
@@ -110,6 +120,50 @@ def cpu_baseline(mesh, fields, ks, budget_s: float = 20.0):
                   f"same level-9 masked mesh, NumPy/SciPy FP64 Jacobi-PCG + extended-precision refinement, "
                   f"single-threaded sparse products; oracle prepare {t_prep:.1f}s not counted",
     }
+
+
+def spmv_leg(ifl):
+    """SpMV rates on the unmasked level-9 icosphere (2,621,442 vertices, all
+    of them dofs): the single-column kernels in FP64 and FP32 for n = 1 and
+    n = 2, and the batched kernel (32 mixed columns) for n = 1. Each figure
+    is algorithmic bytes per launch over the HIP-event time of the launch."""
+    import torch
+
+    import workloads as W
+
+    s = W.icosphere(9, jitter=0.1, seed=1)
+    phi = torch.from_numpy(np.asarray(W.sphere_k3_field(s, 1000, n_waves=512, device="cuda:0"))).to("cuda:0")
+    lam = [32, 16, 8, 4]
+    ks = np.array([2 * math.pi / (x * s.h) for x in lam])
+    res = {"vertices": s.n_vertices, "scales": f"wavelengths {lam} h"}
+
+    def timed(h, fields, kk):
+        nf = fields.shape[0] if fields.dim() == 2 else 1
+        dst = torch.empty((nf, len(kk), h.field_length), dtype=torch.float64, device="cuda:0")
+        h.filter(fields, kk[:1], out=torch.empty((nf, 1, h.field_length), dtype=torch.float64, device="cuda:0"))
+        h.profile_read(reset=True)
+        _, st = h.filter(fields, kk, out=dst)
+        n, ms, b = h.profile_read(reset=True)
+        us = ms / max(n, 1) * 1e3
+        return {"kernel": h.profile_kernel(), "mean_launch_us": round(us, 2), "bytes_per_launch": round(b),
+                "GBs": round(b / (us * 1e3), 1) if n else None, "launches": n,
+                "mean_cg_iterations": round(sum(x.iterations for x in st) / len(st), 1)}
+
+    for n in (1, 2):
+        t0 = time.time()
+        h = ifl.prepare_mesh(s, ifl.IFL_VERTEX_SCALAR, n, precision=ifl.IFL_FP64, batch=1, device=0, profile=1)
+        res[f"n{n}_prepare_s"] = round(time.time() - t0, 1)
+        kk = ks if n == 1 else ks[2:]  # n = 2: the smaller scales keep the iteration count modest
+        for prec, name in ((ifl.IFL_FP64, "fp64"), (ifl.IFL_MIXED, "fp32")):
+            h.set_options(precision=prec, batch=1)
+            res[f"n{n}_{name}_single_column"] = timed(h, phi, kk)
+        if n == 1:
+            # 32 copies of the field at one scale: every timed launch has all 32 columns live
+            h.set_options(precision=ifl.IFL_MIXED, batch=32)
+            many = phi.unsqueeze(0).expand(32, -1).contiguous()
+            res["n1_fp32_batched_32"] = timed(h, many, ks[1:2].repeat(2))
+        h.close()
+    return res
 
 
 def serve_leg(args, ifl):
@@ -218,6 +272,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true", help="skip ifl_autotune (default tile and grids)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-spmv-leg", action="store_true", help="skip the SpMV rates on the unmasked level-9 mesh")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured chunks")
     ap.add_argument("--serve-levels", default="6,7,8,9",
@@ -269,6 +324,8 @@ def main():
     out = torch.zeros((fb, ks.size, h.field_length), dtype=torch.float64, device=dev)
     n_solves = args.fields * ks.size
 
+    agg = {"max_it": 0, "refinements": 0, "solves": 0}
+
     def step(profile: bool, batch: int = args.batch, prec: int = precision, n_fields: int = args.fields):
         h.set_options(precision=prec, batch=batch, profile=int(profile))
         iters = 0
@@ -276,6 +333,10 @@ def main():
             nf = min(fb, n_fields - f0)
             _, st = h.filter(fields[f0:f0 + nf], ks, out=out[:nf])
             iters += sum(s.iterations for s in st)
+            if profile:
+                agg["max_it"] = max(agg["max_it"], max(s.iterations for s in st))
+                agg["refinements"] += sum(s.refinements for s in st)
+                agg["solves"] += len(st)
         return iters
 
     for w in range(args.warmup):
@@ -324,6 +385,8 @@ def main():
             "graphs": not args.no_graphs,
             "rtol": 1e-12,
             "mean_cg_iterations": round(total_it / (n_solves * args.steps), 2),
+            "max_cg_iterations": agg["max_it"],
+            "mean_fp64_replacements": round(agg["refinements"] / max(1, agg["solves"]), 2),
         },
         "roofline": {
             "bound": "hbm",
@@ -352,14 +415,41 @@ def main():
             "mean_cg_iterations": round(it / (args.plain_fields * ks.size), 2),
         }
         res["speedup_vs_plain_fp64"] = round(value / res["plain_fp64_single_column"]["value"], 3)
+    # field 0 at every scale in the benchmark's launch configuration, for the
+    # parity check on the CPU baseline's sample (not timed)
+    h.set_options(precision=precision, batch=args.batch, profile=0)
+    h.filter(fields[0:1], ks, out=out[:1])
+    torch.cuda.synchronize()
     h.close()
+    # the practical streaming rate of this GPU: a plain 1 GiB device copy
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    times = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    copy_gbs = 2 * a.numel() * 8 / float(np.median(times)) / 1e9
+    del a, b
+    res["roofline"]["copy_probe_GBs"] = round(copy_gbs, 1)
+    res["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    if not args.no_spmv_leg:
+        log("SpMV leg on the unmasked level-9 mesh ...")
+        res["spmv_2.6M_vertices"] = spmv_leg(ifl)
+        log(f"spmv: {res['spmv_2.6M_vertices']}")
     if not args.no_serve:
         log("serving leg ...")
         res["serving"] = serve_leg(args, ifl)
         log(f"serving: {res['serving']}")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        res["cpu_baseline"] = cpu_baseline(mesh, fields_h, ks, args.cpu_budget)
+        parity, res["cpu_baseline"] = cpu_baseline(mesh, fields_h, ks, args.cpu_budget,
+                                                   gpu_column=lambda j: out[0, j].cpu().numpy())
+        res["parity_sample"] = parity
     print(json.dumps(res), flush=True)
 
 
