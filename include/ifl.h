@@ -91,8 +91,9 @@ typedef struct ifl_options {
   double cell_A;     /* stencil constant A of Eq. 7; default sqrt(3) */
   int32_t device;    /* HIP device ordinal; default 0. -1 = host-only handle: prepare,
                         export and save work, solves return IFL_EDEVICE */
-  int32_t batch;     /* columns per multi-RHS tile for ifl_filter: 0 = auto (default),
-                        1 = one solve at a time, 2..64 = fixed tile */
+  int32_t batch;     /* columns per multi-RHS tile for ifl_filter: 0 = auto (default: the autotuner's
+                        width, else 32, at most a quarter of the call's columns), 1 = one solve at a
+                        time, 2..64 = fixed tile (rounded down to a power of two) */
   void* stream;      /* hipStream_t to run on; NULL = the handle's own stream */
   int32_t reorder;   /* 1 = locality ordering of the rows (default): reverse Cuthill-McKee, on meshes of
                         >= 32768 dofs inside 8 Morton-curve parts; 0 = mesh order */

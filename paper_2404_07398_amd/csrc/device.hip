@@ -1132,8 +1132,11 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
 }
 
 // Tile width: opt.batch >= 2 fixes R (rounded down to a power of two);
-// auto (0) uses 32 columns, fewer when there are fewer columns, and the
-// single-column path for one column.
+// auto (0) uses the autotuner's width (else 32), but at most a quarter of
+// the columns (at least 2), and the single-column path for one column. A
+// tile iterates until its slowest column is done, at the cost of a full
+// tile per iteration; with few columns of very different iteration counts
+// (many scales, n = 2) a narrower tile spends less on slots left idle.
 int pick_tile(const Handle* h, int64_t ncols) {
   const int want = h->opt.batch;
   if (want == 1) return 1;
@@ -1145,7 +1148,7 @@ int pick_tile(const Handle* h, int64_t ncols) {
   if (ncols <= 1) return 1;
   const int tuned = h->dev->tuned_R[h->opt.precision == IFL_MIXED ? 1 : 0];
   R = tuned > 0 ? tuned : 32;
-  while (R > 2 && R / 2 >= ncols) R /= 2;
+  while (R > 2 && (int64_t)R * 4 > ncols) R /= 2;
   return R;
 }
 
