@@ -125,6 +125,11 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
 // true residual) into the slot state.
 ifl_status batch_finish(const BatchMatrix& bm, BatchWork& w, uint64_t mask, double* const* out, hipStream_t s);
 ifl_status batch_read_slots(BatchWork& w, hipStream_t s);
+// Move n running columns (slots from[c] of src -> to[c] of dst, a tile of
+// another width and the same precision) at a chunk boundary; the other
+// slots of dst become idle. Both tiles must be sized for bm's rows.
+ifl_status batch_move_columns(const BatchMatrix& bm, BatchWork& src, BatchWork& dst, const int* from, const int* to,
+                              int n, hipStream_t s);
 ifl_status batch_release(BatchWork& w, uint64_t mask, hipStream_t s);
 
 // The handle's matrix for tiles of R columns, and the sum of its mass

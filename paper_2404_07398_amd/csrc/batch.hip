@@ -725,6 +725,45 @@ __global__ void kb_out(const double* __restrict__ x, OutPtrs out, uint64_t mask,
   }
 }
 
+// Columns of one tile into another of a different width (same precision), at
+// a chunk boundary: z, the chunk's last direction p[kChunk - 1] (the next
+// chunk's first SpMV forms q from it, so q is not carried), x and phi of
+// each mapped column, one row per thread.
+struct ColMap {
+  int n;
+  int src[64], dst[64];
+};
+
+template <typename T>
+__global__ void kb_move_cols(const T* __restrict__ zs, const T* __restrict__ ps, const double* __restrict__ xs,
+                             const double* __restrict__ fs, int RS, T* __restrict__ zd, T* __restrict__ pd,
+                             double* __restrict__ xd, double* __restrict__ fd, int RD, ColMap map, int64_t n_pad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  for (int c = 0; c < map.n; ++c) {
+    const int64_t a = i * RS + map.src[c], b = i * RD + map.dst[c];
+    zd[b] = zs[a];
+    pd[b] = ps[a];
+    xd[b] = xs[a];
+    fd[b] = fs[a];
+  }
+}
+
+// slots of the moved columns; the other slots of the destination are idle
+__global__ void kf_move_slots(const BSlot* __restrict__ src, BSlot* __restrict__ dst, int RD, ColMap map) {
+  const int j = threadIdx.x;
+  if (j >= RD) return;
+  int from = -1;
+  for (int c = 0; c < map.n; ++c)
+    if (map.dst[c] == j) from = map.src[c];
+  if (from >= 0) {
+    dst[j] = src[from];
+  } else {
+    dst[j].active = 0;
+    dst[j].done = 0;
+  }
+}
+
 // fields -> the columns in 'mask' of the rows x R field array, one row per
 // thread (the new columns of a row are written together). The fields are in
 // the caller's numbering (read through entity) or, 'internal', already in
@@ -1289,6 +1328,32 @@ ifl_status batch_finish(const BatchMatrix& bm, BatchWork& w, uint64_t mask, doub
 ifl_status batch_read_slots(BatchWork& w, hipStream_t s) {
   IFL_HIPB(hipMemcpyAsync(w.slots_host, w.slots, sizeof(BSlot) * w.R, hipMemcpyDeviceToHost, s));
   IFL_HIPB(hipStreamSynchronize(s));
+  return IFL_OK;
+}
+
+ifl_status batch_move_columns(const BatchMatrix& bm, BatchWork& src, BatchWork& dst, const int* from, const int* to,
+                              int n, hipStream_t s) {
+  if (src.mixed != dst.mixed) return fail(IFL_EINVAL, "tiles of different precision");
+  if (src.iter % kChunk != 0) return fail(IFL_EINVAL, "columns move only at chunk boundaries");
+  if (n < 0 || n > dst.R || n > src.R) return fail(IFL_EINVAL, "too many columns to move");
+  ColMap map{};
+  map.n = n;
+  for (int c = 0; c < n; ++c) {
+    if (from[c] < 0 || from[c] >= src.R || to[c] < 0 || to[c] >= dst.R)
+      return fail(IFL_EINVAL, "column slot out of range");
+    map.src[c] = from[c];
+    map.dst[c] = to[c];
+  }
+  const unsigned nb = (unsigned)((bm.n_pad + 255) / 256);
+  if (src.mixed)
+    kb_move_cols<float><<<nb, 256, 0, s>>>(src.z32, src.p32[kChunk - 1], src.x, src.phi, src.R, dst.z32,
+                                            dst.p32[kChunk - 1], dst.x, dst.phi, dst.R, map, bm.n_pad);
+  else
+    kb_move_cols<double><<<nb, 256, 0, s>>>(src.z64, src.p64[kChunk - 1], src.x, src.phi, src.R, dst.z64,
+                                             dst.p64[kChunk - 1], dst.x, dst.phi, dst.R, map, bm.n_pad);
+  kf_move_slots<<<1, 64, 0, s>>>(src.slots, dst.slots, dst.R, map);
+  IFL_HIPB(hipGetLastError());
+  dst.iter = 0;
   return IFL_OK;
 }
 

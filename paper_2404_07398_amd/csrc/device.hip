@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <limits>
 #include <string>
 #include <vector>
@@ -118,8 +119,10 @@ struct DeviceState {
   double prof_ms = 0.0;
   double prof_bytes = 0.0;  // summed algorithmic bytes of the timed launches
   std::string prof_kernel;  // the kernel those launches ran
-  // batched engine work space (allocated on first use)
+  // batched engine work space (allocated on first use), and narrower tiles
+  // that the last columns of a call move to
   BatchWork bw;
+  std::deque<BatchWork> spare;  // a deque: adding a tile leaves the others where they are
   // grid sizes picked by the autotuner, per (tile size, precision), and the
   // tile size it found best per precision (0 = not tuned)
   struct TunedGrid {
@@ -710,6 +713,7 @@ void device_destroy(Handle* h) {
     if (p) (void)hipFree(p);
   if (d->w.sc_host) (void)hipHostFree(d->w.sc_host);
   batch_free(&d->bw);
+  for (BatchWork& t : d->spare) batch_free(&t);
   if (d->field_stage) (void)hipFree(d->field_stage);
   if (d->field_rows) (void)hipFree(d->field_rows);
   if (d->col_stage) (void)hipFree(d->col_stage);
@@ -987,6 +991,30 @@ ifl_status ensure_batch(DeviceState* d, int R, bool mixed) {
   return batch_alloc(&d->bw, bm, R, mixed);
 }
 
+// A cached narrower tile of width R (its slots all idle).
+ifl_status spare_tile(DeviceState* d, int R, bool mixed, hipStream_t s, BatchWork** out) {
+  const BatchMatrix bm = batch_matrix(d, R, mixed);
+  for (BatchWork& t : d->spare)
+    if (t.R == R && t.mixed == mixed) {
+      if (t.G != bm.G || t.Gu != bm.Gu) {
+        batch_free(&t);
+        ifl_status st = batch_alloc(&t, bm, R, mixed);
+        if (st != IFL_OK) return st;
+      }
+      *out = &t;
+      return batch_release(t, ~0ull, s);
+    }
+  d->spare.emplace_back();
+  BatchWork& t = d->spare.back();
+  ifl_status st = batch_alloc(&t, bm, R, mixed);
+  if (st != IFL_OK) {
+    d->spare.pop_back();
+    return st;
+  }
+  *out = &t;
+  return batch_release(t, ~0ull, s);
+}
+
 // Many columns at once: slots of a tile of R columns are filled from the
 // (field, scale) list, iterated together, and refilled as columns finish.
 ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fields, int32_t n_scales,
@@ -997,10 +1025,11 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
   const bool mixed = h->opt.precision == IFL_MIXED;
   ifl_status st = ensure_batch(d, R, mixed);
   if (st != IFL_OK) return st;
-  BatchWork& w = d->bw;
-  const BatchMatrix bm = batch_matrix(d, R, mixed);
+  BatchWork* wp = &d->bw;
+  BatchMatrix bm = batch_matrix(d, R, mixed);
+  const int R0 = R;
   // slots left active by an earlier call that stopped on an error
-  if ((st = batch_release(w, ~0ull, s)) != IFL_OK) return st;
+  if ((st = batch_release(*wp, ~0ull, s)) != IFL_OK) return st;
   // fields on the device
   const double* fdev = fields;
   if (!is_device_ptr(fields)) {
@@ -1035,9 +1064,9 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
       d->field_rows_len = need;
     }
     bool bad = false;
-    if ((st = batch_clear_flag(w, s)) != IFL_OK) return st;
-    if ((st = batch_permute_fields(bm, fdev, L, n_fields, d->field_rows, w.flag, s)) != IFL_OK) return st;
-    if ((st = batch_check_flag(w, s, &bad)) != IFL_OK) return st;
+    if ((st = batch_clear_flag(*wp, s)) != IFL_OK) return st;
+    if ((st = batch_permute_fields(bm, fdev, L, n_fields, d->field_rows, wp->flag, s)) != IFL_OK) return st;
+    if ((st = batch_check_flag(*wp, s, &bad)) != IFL_OK) return st;
     if (bad) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");
   }
   // columns: larger scales (more iterations) first, fields in order
@@ -1054,7 +1083,12 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
   int64_t next = 0, finished = 0;
   bool any_notconv = false;
   const int chunk = 4;
+  // with the tile width left to the library, the last columns of the call
+  // move to narrower tiles as the others finish: a tile pays for all of its
+  // slots every iteration
+  const bool shrink = h->opt.batch == 0;
   while (finished < ncols) {
+    BatchWork& w = *wp;
     // fill free slots
     uint64_t mask = 0;
     SlotScales cs{};
@@ -1075,7 +1109,7 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
     }
     BatchParams p = prm;
     int live = 0;
-    if (h->opt.profile) {
+    if (h->opt.profile && R == R0) {  // the timed launches are those of the call's full-width tile
       if ((st = ensure_events(d, 2)) != IFL_OK) return st;
       p.ev_begin = d->ev[0];
       p.ev_end = d->ev[1];
@@ -1084,7 +1118,7 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
     }
     if ((st = batch_iterate(bm, w, chunk, p, s)) != IFL_OK) return st;
     if ((st = batch_read_slots(w, s)) != IFL_OK) return st;
-    if (h->opt.profile && live > 0) {
+    if (h->opt.profile && R == R0 && live > 0) {
       float ms = 0.f;
       IFL_HIP(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
       d->prof_ms += ms;
@@ -1125,6 +1159,37 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
       ++finished;
     }
     if ((st = batch_release(w, fin, s)) != IFL_OK) return st;
+    // no column left to enter and at most a quarter of the slots running:
+    // move the running columns to a tile of the next power of two >= their
+    // count (at least 2); iteration state moves as it is at the boundary
+    int running = 0;
+    for (int j = 0; j < R; ++j) running += slot_col[j] >= 0;
+    if (shrink && next >= ncols && running > 0 && R >= 4 && running * 4 <= R) {
+      int R2 = 2;
+      while (R2 < running) R2 *= 2;
+      BatchWork* nw = nullptr;
+      if ((st = spare_tile(d, R2, mixed, s, &nw)) != IFL_OK) return st;
+      std::vector<int> from, to;
+      std::vector<int64_t> col2(R2, -1);
+      std::vector<std::chrono::steady_clock::time_point> t2(R2);
+      for (int j = 0; j < R; ++j)
+        if (slot_col[j] >= 0) {
+          const int c = (int)from.size();
+          from.push_back(j);
+          to.push_back(c);
+          col2[c] = slot_col[j];
+          t2[c] = t_in[j];
+        }
+      const BatchMatrix bm2 = batch_matrix(d, R2, mixed);
+      if ((st = batch_move_columns(bm2, w, *nw, from.data(), to.data(), running, s)) != IFL_OK) return st;
+      if ((st = batch_release(w, ~0ull, s)) != IFL_OK) return st;
+      if ((st = batch_read_slots(*nw, s)) != IFL_OK) return st;
+      wp = nw;
+      bm = bm2;
+      R = R2;
+      slot_col = col2;
+      t_in = t2;
+    }
   }
   IFL_HIP(hipStreamSynchronize(s));
   if (any_notconv) return fail(IFL_ENOTCONV, "at least one column did not converge (see stats)");
@@ -1183,7 +1248,9 @@ ifl_status device_autotune(Handle* h, ifl_tune* out) {
       if (h->op.col[e] == r) kd_sum += std::fabs(h->op.val[e]);
   const double c = 1e4 * d->m.mass_sum / std::max(kd_sum, 1e-300);
   const int cus = device_cus(d->device);
-  batch_free(&d->bw);  // room for the trial tiles; the cached tile is rebuilt on demand
+  batch_free(&d->bw);  // room for the trial tiles; the cached tiles are rebuilt on demand
+  for (BatchWork& t : d->spare) batch_free(&t);
+  d->spare.clear();
   struct Best {
     int R = 0, G = 0, Gu = 0;
     double us = 1e300;

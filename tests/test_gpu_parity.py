@@ -412,6 +412,39 @@ def test_graph_replay_equals_direct_launches(ifl, precision):
     h.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tail_columns_move_to_narrower_tiles(ifl, precision):
+    """With the tile width left to the library (batch = 0), the last columns
+    of a call move to narrower tiles (128 columns: 32 -> 8 -> 2 slots) in
+    the middle of their solves; n = 2 over 16 scales gives very different
+    iteration counts. Results stay within the bar, equal those of a fixed
+    32-column tile to well within it, and repeat bitwise."""
+    s, _ = _sphere(5, 0.3)
+    fields = np.stack([W.sphere_k3_field(s, 6000 + i, n_waves=128) for i in range(8)])
+    ks = W.log_scales(s.h, 16)
+    h = _prep(ifl, s, n=2, precision=precision, batch=0)
+    out, st = h.filter(fields, ks)
+    out2, _ = h.filter(fields, ks)
+    assert np.array_equal(out, out2)
+    h.set_options(batch=32)
+    fixed, st_f = h.filter(fields, ks)
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    its = [x.iterations for x in st]
+    assert max(its) > 4 * min(its)  # the tail is real
+    for f in range(fields.shape[0]):
+        for j in range(len(ks)):
+            assert relative_l2(out[f, j], fixed[f, j]) <= tol
+    op = O.scalar_operator(s, 2)
+    for f in (0, 7):
+        ref = O.filter_scalar(op, fields[f], ks)
+        for j in range(len(ks)):
+            err = relative_l2(out[f, j], ref[j])
+            print(f"tail precision={precision} f={f} j={j} err={err:.2e} it={st[f * len(ks) + j].iterations} "
+                  f"fixed_it={st_f[f * len(ks) + j].iterations}")
+            assert err <= tol
+    h.close()
+
+
 def test_batched_edge_cases(ifl):
     import torch
 
