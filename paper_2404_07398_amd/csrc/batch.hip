@@ -170,14 +170,13 @@ __device__ __forceinline__ Walk task_walk(int64_t ntasks, int G) {
 
 __device__ __forceinline__ bool live(const BSlot& s) { return s.active && s.done == 0; }
 
-// Sliced-ELL row product: a[c] += sum_k val_k * comb(c, x0[k], x1[k]) (or
-// |val_k| * comb when ABS) over
+// Sliced-ELL row product: a[c] += sum_k val_k * comb(c, x0[k], x1[k]) over
 // the row's entries in order, kUnroll entries at a time (index and value
 // loads, then the 16-byte gathers of the operands, then the FMAs). Loads
 // past the row's end stay in bounds (the next slice, or the zero tail after
 // the last slice) and their value is replaced by 0, so they leave a
 // unchanged.
-template <typename V, typename T, int R, int C, bool TWO, bool ABS, typename Comb, int U = kUnroll>
+template <typename V, typename T, int R, int C, bool TWO, typename Comb, int U = kUnroll>
 __device__ __forceinline__ void row_product(const BMat& m, const V* __restrict__ val, int64_t base, int w,
                                             int64_t l, int j0, const T* __restrict__ x0,
                                             const T* __restrict__ x1, Comb comb, T (&a)[C], int k_begin = 0) {
@@ -189,7 +188,7 @@ __device__ __forceinline__ void row_product(const BMat& m, const V* __restrict__
       const int64_t e = base + (int64_t)(k0 + u) * kW + l;
       cu[u] = m.col[e];
       const V vv = val[e];
-      vu[u] = k0 + u < w ? (ABS ? (V)fabs(vv) : vv) : (V)0;
+      vu[u] = k0 + u < w ? vv : (V)0;
     }
     Pack<T, C> g0[U], g1[U];
 #pragma unroll
@@ -205,12 +204,38 @@ __device__ __forceinline__ void row_product(const BMat& m, const V* __restrict__
   }
 }
 
-// combiners of row_product for a single gathered operand
+// Both sums of the FP64 residual over a row's entries from k_begin on, in
+// one pass over the gathers: a[c] += val_k x[k], aa[c] += |val_k| |x[k]|.
+template <int R, int C, int U = kUnroll>
+__device__ __forceinline__ void row_product_abs2(const BMat& m, int64_t base, int w, int64_t l, int j0,
+                                                 const double* __restrict__ x, double (&a)[C], double (&aa)[C],
+                                                 int k_begin) {
+  for (int k0 = k_begin; k0 < w; k0 += U) {
+    int32_t cu[U];
+    double vu[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = base + (int64_t)(k0 + u) * kW + l;
+      cu[u] = m.col[e];
+      const double vv = m.val64[e];
+      vu[u] = k0 + u < w ? vv : 0.0;
+    }
+    Pack<double, C> g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) g[u] = vload<double, C>(x + (int64_t)cu[u] * R + j0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        a[c] = fma(vu[u], g[u].v[c], a[c]);
+        aa[c] = fma(fabs(vu[u]), fabs(g[u].v[c]), aa[c]);
+      }
+  }
+}
+
+// combiner of row_product for a single gathered operand
 struct Ident {
   __device__ double operator()(int, double xx, double) const { return xx; }
-};
-struct AbsVal {
-  __device__ double operator()(int, double xx, double) const { return fabs(xx); }
 };
 
 // ------------------------------------------------------------ iteration
@@ -347,10 +372,10 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
       }
       if (cw > kHead) {
         if constexpr (REC)
-          row_product<T, T, R, C, false, false, decltype(zonly), kHead>(m, val, cbase, cw, row % kW, j0, z, z, zonly,
+          row_product<T, T, R, C, false, decltype(zonly), kHead>(m, val, cbase, cw, row % kW, j0, z, z, zonly,
                                                                           a, kHead);
         else
-          row_product<T, T, R, C, true, false, decltype(dir), kHead>(m, val, cbase, cw, row % kW, j0, z, pin, dir, a,
+          row_product<T, T, R, C, true, decltype(dir), kHead>(m, val, cbase, cw, row % kW, j0, z, pin, dir, a,
                                                                       kHead);
       }
       const bool real = row < m.n;
@@ -499,7 +524,6 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
   const double* __restrict__ src = START ? v.phi : v.x;  // the gathered operand
   T* __restrict__ pprev = v.p[kChunk - 1];             // the chunk's first iteration reads it as p
   const Ident ident;
-  const AbsVal absval;
   double acc[3][C] = {};
   if (any) {
     const Walk wk = task_walk(m.n_slices * LPR, G);
@@ -564,11 +588,11 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
         }
       }
       if (cw > kHead) {
-        row_product<double, double, R, C, false, false, decltype(ident), kHead>(
-            m, m.val64, cbase, cw, row % kW, j0, src, nullptr, ident, a, kHead);
-        if constexpr (!START)
-          row_product<double, double, R, C, false, true, decltype(absval), kHead>(
-              m, m.val64, cbase, cw, row % kW, j0, src, nullptr, absval, aa, kHead);
+        if constexpr (START)
+          row_product<double, double, R, C, false, decltype(ident), kHead>(
+              m, m.val64, cbase, cw, row % kW, j0, src, nullptr, ident, a, kHead);
+        else
+          row_product_abs2<R, C, kHead>(m, cbase, cw, row % kW, j0, src, a, aa, kHead);
       }
       const bool real = row < m.n;
       const int64_t idx = row * R + j0;
