@@ -7,10 +7,16 @@ z log-spaced 5 m .. 5 km) filtered at 30 wavenumbers (wavelengths
 log-spaced 32h .. 2h), order n = 1: 1,920 solves per step. Inputs are
 synthetic (seeded) and resident in HBM before the timed region.
 
-Prints one JSON line: solves/s of the whole job, the roofline of the
-SpMV kernel (algorithmic bytes per launch / mean launch time from HIP
-events recorded live on the launch stream) and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+Prints one JSON line: solves/s of the whole job (the timed steps), the
+roofline of the dominant SpMV kernel (algorithmic bytes per launch / mean
+launch time from HIP events recorded live on the launch stream; HBM
+traffic from the committed rocprofv3 profile; a plain 1 GiB device copy
+timed in the same run), and, outside the timed steps: the plain FP64
+one-column-at-a-time path on a subset of the fields, SpMV rates on the
+unmasked level-9 mesh (single column FP64 / FP32, n = 1 and 2; 32 batched
+columns), the continuous-batching server under two Poisson streams (200
+requests/s, and 15 requests/s below capacity), and the FP64 CPU oracle on a
+bounded sample of the same workload together with the GPU's error on it.
 """
 from __future__ import annotations
 
