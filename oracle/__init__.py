@@ -46,7 +46,7 @@ from .solve import (
     to_dofs,
     from_dofs,
 )
-from .spectrum import energy, spectrum_density
+from .spectrum import discrete_symbol, energy, fig8_modes, filtered_energy_of_modes, spectrum_density
 
 __all__ = [
     "ScalarOperator",
@@ -68,4 +68,7 @@ __all__ = [
     "from_dofs",
     "energy",
     "spectrum_density",
+    "discrete_symbol",
+    "filtered_energy_of_modes",
+    "fig8_modes",
 ]

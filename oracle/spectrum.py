@@ -9,6 +9,14 @@ prints no formula; the reading used here is
   area-weighted mean; for vectors ``phi_bar^2 = u_bar^2 + v_bar^2``), and
 * spectral density ``dE/dk`` by finite differences between neighbouring
   wavenumbers, placed at their geometric mean.
+
+The theoretical spectra of the "Some comments" section (Fig. 8) filter a
+prescribed Fourier spectrum with the analytic transfer function of the
+implicit filter built on the 1-D discrete Laplacian: a Fourier mode of
+wavenumber q is an eigenvector of the filter on a uniform periodic grid,
+damped by ``G = 1 / (1 + gamma (lam(q) / k^2)^n)`` with the discrete symbol
+``lam(q) = 4 sin^2(q h / 2) / h^2``, so its filtered energy is ``G^2``
+times its energy.
 """
 from __future__ import annotations
 
@@ -32,3 +40,34 @@ def spectrum_density(ks, E):
     dens = (E[1:] - E[:-1]) / (ks[1:] - ks[:-1])
     kmid = np.sqrt(ks[1:] * ks[:-1])
     return dens, kmid
+
+
+def discrete_symbol(q, h: float = 1.0):
+    """Fourier symbol of the 1-D second-difference Laplacian (-D2) on a
+    grid of spacing h: ``4 sin^2(q h / 2) / h^2``."""
+    q = np.asarray(q, dtype=np.float64)
+    return 4.0 * np.sin(0.5 * q * h) ** 2 / (h * h)
+
+
+def filtered_energy_of_modes(q, E_q, ks, n: int, gamma: float = 0.5, h: float = 1.0):
+    """Filtered energy ``E(k) = sum_q E_q / (1 + gamma (lam(q)/k^2)^n)^2``
+    of a field whose Fourier modes q carry energies E_q, at each k."""
+    lam = discrete_symbol(q, h)
+    E_q = np.asarray(E_q, dtype=np.float64)
+    out = []
+    for k in np.asarray(ks, dtype=np.float64):
+        G = 1.0 / (1.0 + gamma * (lam / (k * k)) ** n)
+        out.append(float(np.sum(E_q * G * G)))
+    return np.array(out)
+
+
+def fig8_modes(N: int, h: float = 1.0, k_star_over_kmin: float = 30.0):
+    """The prescribed spectrum of Fig. 8, ``E_q ~ q^-2 / (1 + (q/k*)^2)``
+    with ``k* = 30 k_min``, on the modes q = 2 pi m / (N h), m = 1 .. N/2 - 1
+    of a periodic grid of N points (k_min = 2 pi / (N h), the domain
+    wavenumber; the Nyquist mode is left out). Returns (q, E_q)."""
+    m = np.arange(1, N // 2)
+    q = 2.0 * np.pi * m / (N * h)
+    k_star = k_star_over_kmin * 2.0 * np.pi / (N * h)
+    E_q = q ** -2.0 / (1.0 + (q / k_star) ** 2)
+    return q, E_q

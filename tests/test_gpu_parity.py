@@ -133,6 +133,31 @@ def test_spectrum_matches_oracle(ifl):
     h.close()
 
 
+@pytest.mark.parametrize("n,precision", [(1, 0), (2, 0), (1, 1), (2, 1)])
+def test_fig8_spectrum_closed_form(ifl, n, precision):
+    """The spectrum of the Fig. 8 construction ("Some comments" section):
+    the prescribed spectrum E_q ~ q^-2 / (1 + (q/k*)^2), k* = 30 k_min, as
+    1-D modes on the uniform periodic 64 x 64 split square, where the
+    filter's transfer function is exact in closed form. ifl_spectrum's
+    energies against the closed form; density by the same differences."""
+    N = 64
+    m = W.split_square(N, jitter=0.0)
+    q, E_q = O.fig8_modes(N)
+    rng = np.random.default_rng(5)
+    phi = sum(W.planar_mode_field(m, j, 0, amp=2 * np.sqrt(e), phase=t)
+              for j, e, t in zip(range(1, N // 2), E_q, rng.uniform(0, 2 * np.pi, q.size)))
+    ks = 2 * np.pi / np.geomspace(N / 2, 2.5, 12)
+    E_ref = O.filtered_energy_of_modes(q, E_q, ks, n)
+    d_ref, _ = O.spectrum_density(ks, E_ref)
+    h = _prep(ifl, m, n=n, precision=precision)
+    E, d, km = h.spectrum(phi, ks)
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    print(f"fig8 n={n} precision={precision} max rel energy err {np.max(np.abs(E / E_ref - 1)):.2e}")
+    assert np.max(np.abs(E / E_ref - 1)) <= 10 * tol
+    assert np.max(np.abs(d - d_ref) / np.abs(d_ref)) <= 1e-6
+    h.close()
+
+
 def test_device_pointers_and_determinism(ifl):
     import torch
 

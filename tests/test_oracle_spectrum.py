@@ -55,3 +55,75 @@ def test_density_of_random_field_is_positive():
     assert np.all((kmid > ks[:-1]) & (kmid < ks[1:]))
     # energy at the finest scale approaches the unfiltered energy
     assert E[-1] < O.energy(op.A, O.to_dofs(op, phi))
+
+
+def _fig8_field(mesh, N, seed=5):
+    """The Fig. 8 spectrum as a field of 1-D modes along x on the uniform
+    periodic split square (mode m carries energy E_m = a_m^2 / 4)."""
+    q, E = O.fig8_modes(N)
+    rng = np.random.default_rng(seed)
+    phases = rng.uniform(0, 2 * np.pi, q.size)
+    phi = sum(W.planar_mode_field(mesh, m, 0, amp=2 * np.sqrt(e), phase=t)
+              for m, e, t in zip(range(1, N // 2), E, phases))
+    return phi, q, E
+
+
+@pytest.mark.parametrize("n_order", [1, 2])
+def test_fig8_closed_form_matches_the_assembled_filter(n_order):
+    """"Some comments" section (Fig. 8): the theoretical spectrum is the
+    prescribed one damped by the analytic transfer function of the filter
+    built on the discrete Laplacian symbol. On the uniform periodic split
+    square, modes along x see exactly that symbol (the assembled P1
+    stiffness is the 5-point Laplacian there), so the filtered energy of
+    the assembled filter equals the closed form."""
+    N = 32
+    m = W.split_square(N, jitter=0.0)
+    op = O.scalar_operator(m, n_order)
+    phi, q, E = _fig8_field(m, N)
+    ks = W.log_scales(1.0, 5)
+    out = O.filter_scalar(op, phi, ks, method="dense")
+    got = [O.energy(op.A, O.to_dofs(op, out[j])) for j in range(len(ks))]
+    ref = O.filtered_energy_of_modes(q, E, ks, n_order)
+    assert np.max(np.abs(np.array(got) / ref - 1)) < 1e-11
+    # unfiltered energy: Parseval over the prescribed modes
+    assert abs(O.energy(op.A, O.to_dofs(op, phi)) / E.sum() - 1) < 1e-12
+
+
+def test_fig8_four_harmonic_closed_form_matches_a_dense_filter():
+    """n = 4 (the four-harmonic curve of Fig. 8) from the closed form against
+    the filter applied as a dense matrix power on a 1-D periodic grid."""
+    N = 64
+    q, E = O.fig8_modes(N)
+    x = np.arange(N, dtype=np.float64)
+    rng = np.random.default_rng(9)
+    phi = sum(2 * np.sqrt(e) * np.cos(qq * x + t) for qq, e, t in zip(q, E, rng.uniform(0, 2 * np.pi, q.size)))
+    L = 2 * np.eye(N) - np.roll(np.eye(N), 1, axis=1) - np.roll(np.eye(N), -1, axis=1)
+    # k not too small: the dense solve's condition number is (4 / k^2)^4
+    for k in (0.6, 1.0, 2.0):
+        S = np.eye(N) + 0.5 * np.linalg.matrix_power(L / k ** 2, 4)
+        fbar = np.linalg.solve(S, phi)
+        got = 0.5 * np.mean(fbar ** 2)
+        ref = O.filtered_energy_of_modes(q, E, [k], 4)[0]
+        assert abs(got / ref - 1) < 1e-10
+
+
+def test_fig8_higher_orders_follow_the_steep_slope():
+    """The qualitative content of Fig. 8: where the prescribed spectrum falls
+    as k^-4 (k > k*), the Laplacian filter's spectrum is flatter than k^-3,
+    and the biharmonic and four-harmonic filters come successively closer to
+    the prescribed spectrum."""
+    N = 2048
+    q, E = O.fig8_modes(N)
+    dq = q[1] - q[0]
+    k_star = 30 * 2 * np.pi / N
+    ks = np.exp(np.linspace(np.log(4 * np.pi / N), np.log(0.9 * np.pi), 60))
+    errs, slopes = {}, {}
+    for n in (1, 2, 4):
+        dens, km = O.spectrum_density(ks, O.filtered_energy_of_modes(q, E, ks, n))
+        sel = (km > 4 * k_star) & (km < 0.5 * np.pi)
+        true = np.interp(km[sel], q, E / dq)
+        errs[n] = np.sqrt(np.mean(np.log(dens[sel] / true) ** 2))
+        slopes[n] = np.diff(np.log(dens[sel])) / np.diff(np.log(km[sel]))
+    assert np.all(slopes[1] > -3.0)
+    assert errs[4] < errs[2] < errs[1]
+    assert errs[4] < 0.5
