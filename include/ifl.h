@@ -74,8 +74,8 @@ typedef struct ifl_mesh {
 /* Data placement (Sect. 2.1, Fig. 1). */
 #define IFL_VERTEX_SCALAR 0       /* scalars on vertices, median-dual CVs, P1 FE (Sect. 2.1.1) */
 #define IFL_CELL_VECTOR 1         /* (east, north) vectors on triangles, Eq. 7 (Sect. 2.1.2) */
-#define IFL_VORONOI_SCALAR 2      /* Eq. 3-5: reserved, IFL_EUNSUPPORTED */
-#define IFL_CIRCUMCENTER_SCALAR 3 /* Eq. 6: reserved, IFL_EUNSUPPORTED */
+#define IFL_VORONOI_SCALAR 2      /* scalars on vertices, quasi-hexagonal (Voronoi) CVs, Eq. 3-5 */
+#define IFL_CIRCUMCENTER_SCALAR 3 /* scalars at triangle circumcentres, Eq. 6 */
 #define IFL_VERTEX_VECTOR 4       /* vertex FE vector Laplacian: reserved, IFL_EUNSUPPORTED */
 
 /* Arithmetic of the solve. */
@@ -121,15 +121,29 @@ void ifl_default_options(ifl_options* opt);
  * Mesh-only preparation (Sect. 2.2.1), run once per mesh and order.
  *
  * Builds, on the host, the active triangles (all three vertices wet), the
- * dofs (vertices of an active triangle for IFL_VERTEX_SCALAR; active
- * triangles for IFL_CELL_VECTOR), flat-facet geometry, the lumped mass
- * and the stiffness K (P1 Galerkin form of Sect. 2.1.1, or Eq. 7 with the
- * change of local unit vectors between neighbouring cells), the order-n
- * operator K_n = K (M^-1 K)^(n-1), a locality ordering of the dofs, and
- * uploads the matrix to device memory owned by the handle.
+ * dofs (vertices of an active triangle for the vertex placements; active
+ * triangles for IFL_CELL_VECTOR and IFL_CIRCUMCENTER_SCALAR), flat-facet
+ * geometry, the lumped mass and the stiffness K, the order-n operator
+ * K_n = K (M^-1 K)^(n-1), a locality ordering of the dofs, and uploads the
+ * matrix to device memory owned by the handle. K and M per placement:
+ *   IFL_VERTEX_SCALAR       P1 Galerkin stiffness, median-dual areas (Sect. 2.1.1);
+ *   IFL_VORONOI_SCALAR      Eq. 3 (its l/d weights are the P1 cotangent weights),
+ *                           circumcentric (Voronoi) cell areas; IFL_EDEGENERATE
+ *                           where a cell area is not positive;
+ *   IFL_CIRCUMCENTER_SCALAR Eq. 6 between triangles sharing an edge, triangle
+ *                           areas; the circumcentre distance is measured through
+ *                           the shared edge's midpoint; IFL_EDEGENERATE where it
+ *                           is not positive (e.g. right triangles sharing their
+ *                           hypotenuse);
+ *   IFL_CELL_VECTOR         Eq. 7 with the change of local unit vectors between
+ *                           neighbouring cells, triangle areas.
+ * Fields are per vertex (L = n_vertices) for the vertex placements, per
+ * triangle (L = n_triangles) for IFL_CIRCUMCENTER_SCALAR and (east, north)
+ * per triangle (L = 2 n_triangles) for IFL_CELL_VECTOR.
  *
  * mesh      : host arrays, read only during the call.
- * placement : IFL_VERTEX_SCALAR or IFL_CELL_VECTOR.
+ * placement : IFL_VERTEX_SCALAR, IFL_VORONOI_SCALAR, IFL_CIRCUMCENTER_SCALAR
+ *             or IFL_CELL_VECTOR (IFL_VERTEX_VECTOR: IFL_EUNSUPPORTED).
  * n         : filter order, 1 or 2 (others: IFL_EUNSUPPORTED).
  * opt       : NULL for defaults; copied into the handle.
  * out       : receives the handle; release with ifl_destroy.

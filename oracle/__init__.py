@@ -26,11 +26,14 @@ Every function names the passage it follows. Functions without a pin say
 "parity unpinned" in their docstring.
 """
 from .operators import (
+    CellScalarOperator,
     ScalarOperator,
     VectorOperator,
     active_cells,
+    circumcenter_operator,
     scalar_operator,
     vector_operator,
+    voronoi_operator,
     cot_stiffness,
     fv_stiffness,
     lumped_mass,
@@ -54,6 +57,9 @@ __all__ = [
     "active_cells",
     "scalar_operator",
     "vector_operator",
+    "voronoi_operator",
+    "circumcenter_operator",
+    "CellScalarOperator",
     "cot_stiffness",
     "fv_stiffness",
     "lumped_mass",

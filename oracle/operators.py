@@ -298,3 +298,130 @@ def vector_operator(mesh, n: int = 1, stencil_A: float = np.sqrt(3.0)) -> Vector
     A2 = np.repeat(area, 2)
     Kn = order_n(K, A2, n)
     return VectorOperator(K=K, Kn=Kn, A=A2, n=n, cells=cells, n_cells_total=mesh.n_triangles)
+
+
+# ------------------------------------------------------------ Eq. 3-6
+def _circumcentric_geometry(a, b, c):
+    """Per triangle (corners a, b, c, flat facet, 2-D or 3-D): the corners
+    and circumcentre in 3-D, the unit normal of (b - a) x (c - a) and, for
+    each edge k (opposite corner k), the signed distance from the edge's
+    midpoint to the circumcentre, measured in the facet's plane towards
+    corner k, the edge length and the midpoint. Computed from the
+    circumcentre's coordinates (not from angles)."""
+    if a.shape[1] == 2:
+        z = np.zeros((a.shape[0], 1))
+        a, b, c = np.hstack([a, z]), np.hstack([b, z]), np.hstack([c, z])
+    ab, ac = b - a, c - a
+    nrm = np.cross(ab, ac)
+    n2 = np.sum(nrm * nrm, axis=1, keepdims=True)
+    O = a + (np.sum(ac * ac, 1, keepdims=True) * np.cross(nrm, ab) +
+             np.sum(ab * ab, 1, keepdims=True) * np.cross(ac, nrm)) / (2.0 * n2)
+    P = (a, b, c)
+    unit_n = nrm / np.sqrt(n2)
+    dist, length, mids = [], [], []
+    for k in range(3):
+        i, j = (k + 1) % 3, (k + 2) % 3
+        e = P[j] - P[i]
+        le = np.linalg.norm(e, axis=1)
+        mid = 0.5 * (P[i] + P[j])
+        u = np.cross(unit_n, e) / le[:, None]  # in-plane, perpendicular to the edge
+        u *= np.sign(np.sum(u * (P[k] - mid), axis=1))[:, None]  # towards corner k
+        dist.append(np.sum((O - mid) * u, axis=1))
+        length.append(le)
+        mids.append(mid)
+    return O, P, unit_n, dist, length, mids
+
+
+def voronoi_operator(mesh, n: int = 1) -> ScalarOperator:
+    """Scalars on vertices with quasi-hexagonal (Voronoi) control volumes,
+    Eq. 3-5: ``A_v (D phi)_v = l^2 sum_v' (phi_v - phi_v') l_vv' / d_vv'``
+    with ``d`` the edge length and ``l`` the distance between the
+    circumcentres on both sides of the edge (through the edge midpoint;
+    only the side of an active triangle counts, so boundary edges take one
+    segment), and ``A_v`` the area of the circumcentric cell: over the
+    active triangles at v, the quadrilaterals (v, midpoint, circumcentre,
+    midpoint)."""
+    act = active_cells(mesh)
+    tris = np.asarray(mesh.tris, dtype=np.int64)[act]
+    verts, dof_of = _dof_numbering(mesh.n_vertices, tris)
+    a, b, c = _corner_positions(mesh, tris)
+    O, P, unit_n, dist, length, mids = _circumcentric_geometry(a, b, c)
+    idx = dof_of[tris]
+    nv = verts.size
+    rows, cols, vals = [], [], []
+    diag = np.zeros(nv)
+    for k in range(3):
+        i, j = (k + 1) % 3, (k + 2) % 3
+        w = dist[k] / length[k]
+        rows += [idx[:, i], idx[:, j]]
+        cols += [idx[:, j], idx[:, i]]
+        vals += [-w, -w]
+        np.add.at(diag, idx[:, i], w)
+        np.add.at(diag, idx[:, j], w)
+    rows.append(np.arange(nv))
+    cols.append(np.arange(nv))
+    vals.append(diag)
+    K = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(nv, nv)).tocsr()
+    K.sort_indices()
+    A = np.zeros(nv)
+    for i in range(3):
+        # corners (i, j, k) run the same way round as (a, b, c), and so does
+        # the quadrilateral (corner, midpoint of ij, circumcentre, midpoint
+        # of ik): its area is positive unless the circumcentre lies outside
+        j, k = (i + 1) % 3, (i + 2) % 3
+        m_ij, m_ik, pi = mids[k], mids[j], P[i]
+        quad = 0.5 * (np.sum(np.cross(m_ij - pi, O - pi) * unit_n, 1) + np.sum(np.cross(O - pi, m_ik - pi) * unit_n, 1))
+        np.add.at(A, idx[:, i], quad)
+    Kn = order_n(K, A, n)
+    return ScalarOperator(K=K, Kn=Kn, A=A, n=n, verts=verts, dof_of=dof_of, n_vertices=mesh.n_vertices)
+
+
+@dataclasses.dataclass
+class CellScalarOperator:
+    """Scalars at triangle circumcentres (Eq. 6) over active triangles."""
+
+    K: sp.csr_matrix
+    Kn: sp.csr_matrix
+    A: np.ndarray
+    n: int
+    cells: np.ndarray
+    n_cells_total: int
+
+
+def circumcenter_operator(mesh, n: int = 1) -> CellScalarOperator:
+    """Eq. 6: ``A_c (D phi)_c = l^2 sum_c' (phi_c - phi_c') l_cc' / d_cc'`` over
+    the active triangles c' sharing an edge with c, ``l_cc'`` the length of
+    that edge and ``d_cc'`` the distance between the two circumcentres
+    (through the edge midpoint); ``A_c`` the triangle's area."""
+    act = active_cells(mesh)
+    cells = np.nonzero(act)[0]
+    tris = np.asarray(mesh.tris, dtype=np.int64)[act]
+    a, b, c = _corner_positions(mesh, tris)
+    area = 0.5 * _cross_norm(b - a, c - a)
+    O, P, unit_n, dist, length, mids = _circumcentric_geometry(a, b, c)
+    nc = tris.shape[0]
+    # each edge k of each cell: key, cell, its circumcentre distance and length
+    keys, owner, dd, ll = [], [], [], []
+    for k in range(3):
+        i, j = (k + 1) % 3, (k + 2) % 3
+        keys.append(np.minimum(tris[:, i], tris[:, j]) * mesh.n_vertices + np.maximum(tris[:, i], tris[:, j]))
+        owner.append(np.arange(nc))
+        dd.append(dist[k])
+        ll.append(length[k])
+    keys, owner, dd, ll = map(np.concatenate, (keys, owner, dd, ll))
+    order = np.argsort(keys, kind="stable")
+    ks = keys[order]
+    same = ks[1:] == ks[:-1]
+    c1, c2 = owner[order][:-1][same], owner[order][1:][same]
+    d = dd[order][:-1][same] + dd[order][1:][same]
+    w = ll[order][:-1][same] / d
+    diag = np.zeros(nc)
+    np.add.at(diag, c1, w)
+    np.add.at(diag, c2, w)
+    rows = np.concatenate([c1, c2, np.arange(nc)])
+    cols = np.concatenate([c2, c1, np.arange(nc)])
+    vals = np.concatenate([-w, -w, diag])
+    K = sp.coo_matrix((vals, (rows, cols)), shape=(nc, nc)).tocsr()
+    K.sort_indices()
+    Kn = order_n(K, area, n)
+    return CellScalarOperator(K=K, Kn=Kn, A=area, n=n, cells=cells, n_cells_total=mesh.n_triangles)

@@ -26,10 +26,16 @@ def system_matrix(op, k: float, gamma: float = 0.5):
     return (sp.diags(op.A) + c * op.Kn).tocsr()
 
 
+def _cell_scalar(op) -> bool:
+    return op.A.size == op.cells.size if hasattr(op, "cells") else False
+
+
 def to_dofs(op, field: np.ndarray) -> np.ndarray:
     """Caller's numbering (vertices or cells) -> dof vector."""
     if hasattr(op, "verts"):
         return np.asarray(field, dtype=np.float64)[op.verts]
+    if _cell_scalar(op):
+        return np.asarray(field, dtype=np.float64)[op.cells]
     f = np.asarray(field, dtype=np.float64).reshape(-1, 2)
     return f[op.cells].reshape(-1)
 
@@ -39,6 +45,10 @@ def from_dofs(op, x: np.ndarray) -> np.ndarray:
     if hasattr(op, "verts"):
         out = np.zeros(op.n_vertices)
         out[op.verts] = x
+        return out
+    if _cell_scalar(op):
+        out = np.zeros(op.n_cells_total)
+        out[op.cells] = x
         return out
     out = np.zeros((op.n_cells_total, 2))
     out[op.cells] = x.reshape(-1, 2)
@@ -142,13 +152,14 @@ def _solve(op, phi_dofs, k, gamma, method):
 
 
 def filter_scalar(op, field, ks, gamma: float = 0.5, method: str = "auto", return_info: bool = False):
-    """Filter a vertex field at each wavenumber in ``ks``.
+    """Filter a scalar field at each wavenumber in ``ks``.
 
-    ``field``: (V,) in vertex numbering. Returns (len(ks), V) with zeros at
-    vertices that are not dofs (dry or orphaned).
+    ``field``: (V,) in vertex numbering (vertex placements) or (F,) in
+    triangle numbering (circumcentre placement). Returns (len(ks), V or F)
+    with zeros at entries that are not dofs (dry, orphaned, inactive).
     """
     phi = to_dofs(op, field)
-    out = np.zeros((len(ks), op.n_vertices))
+    out = np.zeros((len(ks), op.n_vertices if hasattr(op, "verts") else op.n_cells_total))
     infos = []
     for j, k in enumerate(ks):
         x, info = _solve(op, phi, float(k), gamma, method)

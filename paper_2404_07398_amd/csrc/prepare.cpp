@@ -334,7 +334,15 @@ void permute_csr(int64_t n, const std::vector<int64_t>& order, const std::vector
   }
 }
 
-ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder, HostOperator* out) {
+// Scalars on vertices. Median-dual control volumes and P1 elements (Sect.
+// 2.1.1), or (voronoi) the quasi-hexagonal control volumes of Eq. 3-5: the
+// flux weight of Eq. 3, l/d (circumcentre distance across the edge over the
+// edge length), is the cotangent weight of the P1 stiffness, triangle by
+// triangle (a triangle's circumcentre lies (d/2) cot(theta) from the edge
+// midpoint, theta the angle opposite the edge), so the two share K and
+// differ in the mass: the circumcentric (Voronoi) cell area. A corner i of a
+// triangle (i, j, k) contributes (|ij|^2 cot(theta_k) + |ik|^2 cot(theta_j)) / 8.
+ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder, bool voronoi, HostOperator* out) {
   const std::vector<char> act = active_triangles(m);
   std::vector<int64_t> dof_of(m.n_vertices, -1);
   for (int64_t t = 0; t < m.n_triangles; ++t)
@@ -374,9 +382,22 @@ ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder
         tr.add(d[i], d[j], kij);
         tr.add(d[j], d[i], kij);
       }
-      mass[d[i]] += twoA / 6.0;
+      if (voronoi) {
+        // corners j, k of i; cot of the angle at corner c is -e_a.e_b / 2A
+        // with a, b the other two corners
+        const int j = (i + 1) % 3, k = (i + 2) % 3;
+        const double cot_k = -dot(e[i], e[j]) / twoA, cot_j = -dot(e[i], e[k]) / twoA;
+        mass[d[i]] += (dot(e[k], e[k]) * cot_k + dot(e[j], e[j]) * cot_j) / 8.0;
+      } else {
+        mass[d[i]] += twoA / 6.0;
+      }
     }
   }
+  if (voronoi)
+    for (int64_t v = 0; v < n; ++v)
+      if (!(mass[v] > 0.0))
+        return fail(IFL_EDEGENERATE, "non-positive Voronoi cell area at vertex " + std::to_string(vert_of[v]) +
+                                         " (the triangulation is not well centred there)");
   std::vector<int64_t> kp;
   std::vector<int32_t> kc;
   std::vector<double> kv;
@@ -408,7 +429,7 @@ ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder
     std::iota(ord.begin(), ord.end(), 0);
   }
 
-  out->placement = IFL_VERTEX_SCALAR;
+  out->placement = voronoi ? IFL_VORONOI_SCALAR : IFL_VERTEX_SCALAR;
   out->order = order;
   out->n = n;
   out->n_components = 1;
@@ -419,6 +440,130 @@ ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder
   for (int64_t i = 0; i < n; ++i) {
     out->mass[i] = mass[ord[i]];
     out->entity[i] = vert_of[ord[i]];
+  }
+  return IFL_OK;
+}
+
+// Scalars at triangle circumcentres (Eq. 6): dofs are the active triangles,
+// mass their (flat-facet) areas, and a pair of active triangles sharing an
+// edge of length l is coupled with weight l / d, d the distance between
+// their circumcentres measured through the edge midpoint: each circumcentre
+// lies (l/2) cot(theta) from it, theta the triangle's angle opposite the
+// edge, so l / d = 2 / (cot(theta_1) + cot(theta_2)). The triangulation must
+// be well centred (d > 0); two right triangles sharing their hypotenuse, for
+// instance, have coincident circumcentres.
+ifl_status build_circumcenter_scalar(const ifl_mesh& m, int32_t order, int32_t reorder, HostOperator* out) {
+  const std::vector<char> act = active_triangles(m);
+  std::vector<int64_t> tri_of;
+  for (int64_t t = 0; t < m.n_triangles; ++t)
+    if (act[t]) tri_of.push_back(t);
+  const int64_t n = (int64_t)tri_of.size();
+  if (n == 0) return fail(IFL_EDEGENERATE, "no active triangle (all triangles touch a dry vertex)");
+  std::vector<double> area(n);
+  // cot of the angle at each corner (the angle opposite edge (k+1, k+2))
+  std::vector<double> cot(3 * n);
+  for (int64_t c = 0; c < n; ++c) {
+    V3 p[3];
+    corners(m, m.triangles + 3 * tri_of[c], p);
+    const V3 e[3] = {sub(p[2], p[1]), sub(p[0], p[2]), sub(p[1], p[0])};
+    const double twoA = norm(cross(e[2], scale(e[1], -1.0)));
+    const double ee = dot(e[0], e[0]) + dot(e[1], e[1]) + dot(e[2], e[2]);
+    if (!(twoA > 1e-14 * ee)) return fail(IFL_EDEGENERATE, "zero-area active triangle " + std::to_string(tri_of[c]));
+    area[c] = 0.5 * twoA;
+    for (int k = 0; k < 3; ++k) cot[3 * c + k] = -dot(e[(k + 1) % 3], e[(k + 2) % 3]) / twoA;
+  }
+  struct EC {
+    int64_t key;
+    int64_t cell;
+    int corner;  // the corner opposite the edge
+  };
+  std::vector<EC> ec;
+  ec.reserve(3 * n);
+  for (int64_t c = 0; c < n; ++c) {
+    const int32_t* tv = m.triangles + 3 * tri_of[c];
+    for (int k = 0; k < 3; ++k) {
+      const int64_t a = tv[(k + 1) % 3], b = tv[(k + 2) % 3];
+      ec.push_back({std::min(a, b) * m.n_vertices + std::max(a, b), c, k});
+    }
+  }
+  std::stable_sort(ec.begin(), ec.end(), [](const EC& x, const EC& y) { return x.key < y.key; });
+  Triplets tr;
+  std::vector<double> diag(n, 0.0);
+  std::vector<int64_t> gp(n + 1, 0);
+  std::vector<std::pair<int64_t, int64_t>> pairs;
+  std::vector<double> wts;
+  for (size_t i = 0; i < ec.size();) {
+    size_t j = i;
+    while (j < ec.size() && ec[j].key == ec[i].key) ++j;
+    if (j - i > 2) return fail(IFL_EINVAL, "edge shared by more than two active triangles");
+    if (j - i == 2) {
+      const int64_t c1 = ec[i].cell, c2 = ec[i + 1].cell;
+      const double cs = cot[3 * c1 + ec[i].corner] + cot[3 * c2 + ec[i + 1].corner];
+      if (!(cs > 1e-12))
+        return fail(IFL_EDEGENERATE, "circumcentres of triangles " + std::to_string(tri_of[c1]) + " and " +
+                                         std::to_string(tri_of[c2]) + " coincide or cross (not well centred)");
+      pairs.push_back({c1, c2});
+      wts.push_back(2.0 / cs);
+    }
+    i = j;
+  }
+  for (size_t q = 0; q < pairs.size(); ++q) {
+    const int64_t c1 = pairs[q].first, c2 = pairs[q].second;
+    tr.add(c1, c2, -wts[q]);
+    tr.add(c2, c1, -wts[q]);
+    diag[c1] += wts[q];
+    diag[c2] += wts[q];
+    gp[c1 + 1]++;
+    gp[c2 + 1]++;
+  }
+  for (int64_t c = 0; c < n; ++c) tr.add(c, c, diag[c]);
+  std::vector<int64_t> kp;
+  std::vector<int32_t> kc;
+  std::vector<double> kv;
+  to_csr(n, tr, kp, kc, kv);
+  tr = Triplets();
+  std::vector<int64_t> np = kp;
+  std::vector<int32_t> ncol = kc;
+  std::vector<double> nv = kv;
+  for (int32_t r = 1; r < order; ++r) {
+    std::vector<int64_t> tp;
+    std::vector<int32_t> tc;
+    std::vector<double> tvv;
+    spgemm_scaled(n, np, ncol, nv, kp, kc, kv, area, tp, tc, tvv);
+    np.swap(tp);
+    ncol.swap(tc);
+    nv.swap(tvv);
+  }
+  std::vector<int64_t> ord(n);
+  if (reorder) {
+    for (int64_t c = 0; c < n; ++c) gp[c + 1] += gp[c];
+    std::vector<int32_t> adj(gp[n]);
+    std::vector<int64_t> fill(gp.begin(), gp.end() - 1);
+    for (const auto& pr : pairs) {
+      adj[fill[pr.first]++] = (int32_t)pr.second;
+      adj[fill[pr.second]++] = (int32_t)pr.first;
+    }
+    std::vector<V3> pts(n);
+    for (int64_t c = 0; c < n; ++c) {
+      V3 p[3];
+      corners(m, m.triangles + 3 * tri_of[c], p);
+      pts[c] = scale(add(add(p[0], p[1]), p[2]), 1.0 / 3.0);
+    }
+    ord = locality_order(n, gp, adj, pts);
+  } else {
+    std::iota(ord.begin(), ord.end(), 0);
+  }
+  out->placement = IFL_CIRCUMCENTER_SCALAR;
+  out->order = order;
+  out->n = n;
+  out->n_components = 1;
+  out->field_len = m.n_triangles;
+  permute_csr(n, ord, np, ncol, nv, out->row_ptr, out->col, out->val);
+  out->mass.resize(n);
+  out->entity.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    out->mass[i] = area[ord[i]];
+    out->entity[i] = tri_of[ord[i]];
   }
   return IFL_OK;
 }
@@ -568,13 +713,15 @@ ifl_status build_operator(const ifl_mesh& mesh, int32_t placement, int32_t order
   ifl_status st = validate(mesh);
   if (st != IFL_OK) return st;
   if (order < 1 || order > 2) return fail(IFL_EUNSUPPORTED, "filter order n must be 1 or 2");
-  if (placement == IFL_VERTEX_SCALAR) {
-    st = build_vertex_scalar(mesh, order, reorder, out);
+  if (placement == IFL_VERTEX_SCALAR || placement == IFL_VORONOI_SCALAR) {
+    st = build_vertex_scalar(mesh, order, reorder, placement == IFL_VORONOI_SCALAR, out);
   } else if (placement == IFL_CELL_VECTOR) {
     if (!(cell_A > 0) || !std::isfinite(cell_A)) return fail(IFL_EINVAL, "cell_A must be positive and finite");
     st = build_cell_vector(mesh, order, cell_A, reorder, out);
-  } else if (placement >= IFL_VORONOI_SCALAR && placement <= IFL_VERTEX_VECTOR) {
-    return fail(IFL_EUNSUPPORTED, "placement not implemented (vertex scalars and cell vectors are)");
+  } else if (placement == IFL_CIRCUMCENTER_SCALAR) {
+    st = build_circumcenter_scalar(mesh, order, reorder, out);
+  } else if (placement == IFL_VERTEX_VECTOR) {
+    return fail(IFL_EUNSUPPORTED, "vertex vectors (the FE vector Laplacian with the metric term T) are not implemented");
   } else {
     return fail(IFL_EINVAL, "unknown placement");
   }

@@ -57,6 +57,10 @@ def _to_oracle_numbering(h, op_or):
     n = rp.size - 1
     if hasattr(op_or, "verts"):
         dof = op_or.dof_of[ent]
+    elif op_or.A.size == op_or.cells.size:  # scalars on cells
+        cell_dof = np.full(op_or.n_cells_total, -1)
+        cell_dof[op_or.cells] = np.arange(op_or.cells.size)
+        dof = cell_dof[ent]
     else:
         cell_dof = np.full(op_or.n_cells_total, -1)
         cell_dof[op_or.cells] = np.arange(op_or.cells.size)
@@ -106,6 +110,55 @@ def test_prepare_matches_oracle_cell_vector(order):
     assert abs(K - vo.Kn).max() <= 1e-13 * abs(vo.Kn).max()
     assert np.max(np.abs(M - vo.A) / vo.A) < 1e-14
     h.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("name", ["sphere-L4-mask", "planar-jitter"])
+def test_prepare_matches_oracle_voronoi(name, order):
+    """Eq. 3-5 (Voronoi control volumes) from the library's angle-based
+    assembly against the oracle's geometric one."""
+    _lib_or_skip()
+    if name == "planar-jitter":
+        mesh = W.split_square(24, jitter=0.12)
+    else:
+        s = W.icosphere(4, jitter=0.1)
+        mesh = s.with_mask(W.land_mask(s, 0.3))
+    h = _host_handle(mesh, ifl.IFL_VORONOI_SCALAR, order)
+    op = O.voronoi_operator(mesh, order)
+    K, M, rp, col, val = _to_oracle_numbering(h, op)
+    assert h.num_dofs == op.A.size and h.field_length == mesh.n_vertices
+    assert abs(K - op.Kn).max() <= 1e-12 * abs(op.Kn).max()
+    assert np.max(np.abs(M - op.A) / op.A) < 1e-12
+    h.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_prepare_matches_oracle_circumcenter(order):
+    """Eq. 6 (scalars at circumcentres) from the library's angle-based
+    weights against the oracle's circumcentre coordinates."""
+    _lib_or_skip()
+    s = W.icosphere(4, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    h = _host_handle(s, ifl.IFL_CIRCUMCENTER_SCALAR, order)
+    op = O.circumcenter_operator(s, order)
+    K, M, rp, col, val = _to_oracle_numbering(h, op)
+    assert h.num_dofs == op.A.size and h.field_length == s.n_triangles
+    assert abs(K - op.Kn).max() <= 1e-12 * abs(op.Kn).max()
+    assert np.max(np.abs(M - op.A) / op.A) < 1e-14
+    n = rp.size - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    Kl = sp.coo_matrix((val, (rows, col)), shape=(n, n)).tocsr()
+    assert (Kl != Kl.T).nnz == 0
+    h.close()
+
+
+def test_circumcenter_rejects_coincident_circumcentres():
+    """Right triangles sharing their hypotenuse (the unjittered split
+    square) have one circumcentre: Eq. 6 has no finite weight there."""
+    _lib_or_skip()
+    with pytest.raises(ifl.IflError) as e:
+        _host_handle(W.split_square(8, jitter=0.0), ifl.IFL_CIRCUMCENTER_SCALAR, 1)
+    assert e.value.status == ifl.IFL_EDEGENERATE
 
 
 def test_ordering_is_a_permutation_and_local():
@@ -200,7 +253,7 @@ def test_prepare_errors():
     with pytest.raises(ifl.IflError) as e:
         ifl.ifl_prepare(c, m.tris, m.geometry, period=m.period, device=-1)
     assert e.value.status == ifl.IFL_EINVAL
-    for placement in (ifl.IFL_VORONOI_SCALAR, ifl.IFL_CIRCUMCENTER_SCALAR, ifl.IFL_VERTEX_VECTOR):
+    for placement in (ifl.IFL_VERTEX_VECTOR,):
         with pytest.raises(ifl.IflError) as e:
             ifl.prepare_mesh(m, placement, 1, device=-1)
         assert e.value.status == ifl.IFL_EUNSUPPORTED

@@ -470,6 +470,31 @@ def test_tail_columns_move_to_narrower_tiles(ifl, precision):
     h.close()
 
 
+@pytest.mark.parametrize("batch", [1, 8])
+@pytest.mark.parametrize("n,precision", [(1, 0), (2, 0), (1, 1), (2, 1)])
+def test_voronoi_and_circumcenter_placements(ifl, n, precision, batch):
+    """Eq. 3-5 (scalars on vertices, Voronoi cells) and Eq. 6 (scalars at
+    circumcentres) through the same solver, one column at a time and in a
+    tile, against the oracle's operators on a masked level-5 sphere."""
+    s, phi = _sphere(5, 0.3)
+    ks = W.log_scales(s.h, 5)
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    fields = {ifl.IFL_VORONOI_SCALAR: (phi, O.voronoi_operator(s, n)),
+              ifl.IFL_CIRCUMCENTER_SCALAR: (phi[s.tris].mean(axis=1), O.circumcenter_operator(s, n))}
+    for placement, (f, op) in fields.items():
+        ref = O.filter_scalar(op, f, ks)
+        h = _prep(ifl, s, placement=placement, n=n, precision=precision, batch=batch)
+        out, st = h.filter(f, ks)
+        for j in range(len(ks)):
+            err = relative_l2(out[0, j], ref[j])
+            print(f"placement={placement} n={n} precision={precision} batch={batch} j={j} err={err:.2e} "
+                  f"it={st[j].iterations}")
+            assert err <= tol
+        inactive = ~O.active_cells(s) if placement == ifl.IFL_CIRCUMCENTER_SCALAR else (s.wet == 0)
+        assert np.all(out[0][:, inactive] == 0.0)
+        h.close()
+
+
 def test_batched_edge_cases(ifl):
     import torch
 
