@@ -282,10 +282,11 @@ def test_host_only_handle_refuses_solves():
     h.close()
 
 
-def test_save_load_roundtrip(tmp_path):
+@pytest.mark.parametrize("placement", [0, 2, 3])
+def test_save_load_roundtrip(tmp_path, placement):
     _lib_or_skip()
     s = W.icosphere(3, jitter=0.1)
-    h = _host_handle(s, n=2)
+    h = _host_handle(s, placement, n=2)
     p = str(tmp_path / "h.ifl")
     h.save(p)
     h2 = ifl.ifl_load(p, device=-1)
@@ -293,6 +294,7 @@ def test_save_load_roundtrip(tmp_path):
     b = h2.export_operator()
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+    assert h2.field_length == h.field_length
     open(p, "r+b").truncate(100)
     with pytest.raises(ifl.IflError) as e:
         ifl.ifl_load(p, device=-1)
