@@ -144,7 +144,12 @@ void ifl_default_options(ifl_options* opt);
  * mesh      : host arrays, read only during the call.
  * placement : IFL_VERTEX_SCALAR, IFL_VORONOI_SCALAR, IFL_CIRCUMCENTER_SCALAR
  *             or IFL_CELL_VECTOR (IFL_VERTEX_VECTOR: IFL_EUNSUPPORTED).
- * n         : filter order, 1 or 2 (others: IFL_EUNSUPPORTED).
+ * n         : filter order, 1 to 4 (others: IFL_EUNSUPPORTED). K_n is assembled
+ *             explicitly: on a triangular mesh its rows hold about 7, 19, 37
+ *             and 61 entries for n = 1..4, and the condition number of S grows
+ *             like gamma (lambda_max / k^2)^n, so orders above 2 converge only
+ *             at scales a few grid steps long (Sect. 4 and the "Some comments"
+ *             section report lost convergence for n = 2 at large scales).
  * opt       : NULL for defaults; copied into the handle.
  * out       : receives the handle; release with ifl_destroy.
  * Errors    : IFL_EINVAL (bad sizes, ids out of range, non-finite coords),

@@ -137,6 +137,50 @@ void spgemm_scaled(int64_t n, const std::vector<int64_t>& ap, const std::vector<
   }
 }
 
+// C = (A + A^T) / 2 for a CSR matrix with a symmetric pattern and sorted
+// columns; the result is bitwise symmetric (each pair is one sum).
+void symmetrize_csr(int64_t n, const std::vector<int64_t>& p, const std::vector<int32_t>& c, std::vector<double>& v) {
+  std::vector<double> out(v.size());
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = p[i]; e < p[i + 1]; ++e) {
+      const int32_t j = c[e];
+      const auto b = c.begin() + p[j], en = c.begin() + p[j + 1];
+      const auto t = std::lower_bound(b, en, (int32_t)i);
+      const double vji = (t != en && *t == i) ? v[t - c.begin()] : 0.0;
+      out[e] = 0.5 * (v[e] + vji);
+    }
+  }
+  v.swap(out);
+}
+
+// Order-n operator K_n = K (M^-1 K)^(n-1), n = 1..4 (Sect. 2.1.1; n = 2 is
+// the biharmonic form of Eq. 5, n = 4 the highest order of Fig. 8). Even
+// orders are squares, K_4 = K_2 M^-1 K_2: a product X M^-1 X of a bitwise
+// symmetric X is bitwise symmetric (entry (i,j) and (j,i) sum the same
+// products in the same order), and n = 3 is symmetrised explicitly.
+void order_n_csr(int64_t n, int32_t order, const std::vector<int64_t>& kp, const std::vector<int32_t>& kc,
+                 const std::vector<double>& kv, const std::vector<double>& m, std::vector<int64_t>& np,
+                 std::vector<int32_t>& nc, std::vector<double>& nv) {
+  np = kp;
+  nc = kc;
+  nv = kv;
+  if (order == 1) return;
+  std::vector<int64_t> p2;
+  std::vector<int32_t> c2;
+  std::vector<double> v2;
+  spgemm_scaled(n, kp, kc, kv, kp, kc, kv, m, p2, c2, v2);
+  if (order == 2) {
+    np.swap(p2);
+    nc.swap(c2);
+    nv.swap(v2);
+  } else if (order == 3) {
+    spgemm_scaled(n, p2, c2, v2, kp, kc, kv, m, np, nc, nv);
+    symmetrize_csr(n, np, nc, nv);
+  } else {
+    spgemm_scaled(n, p2, c2, v2, p2, c2, v2, m, np, nc, nv);
+  }
+}
+
 // Reverse Cuthill-McKee ordering of a graph given by CSR adjacency (self
 // loops ignored). Each connected component starts from a pseudo-peripheral
 // node; neighbours are visited by increasing degree. Returns order[new] = old.
@@ -404,18 +448,10 @@ ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder
   to_csr(n, tr, kp, kc, kv);
   tr = Triplets();
 
-  std::vector<int64_t> np = kp;
-  std::vector<int32_t> nc = kc;
-  std::vector<double> nv = kv;
-  for (int32_t r = 1; r < order; ++r) {
-    std::vector<int64_t> tp;
-    std::vector<int32_t> tc;
-    std::vector<double> tvv;
-    spgemm_scaled(n, np, nc, nv, kp, kc, kv, mass, tp, tc, tvv);
-    np.swap(tp);
-    nc.swap(tc);
-    nv.swap(tvv);
-  }
+  std::vector<int64_t> np;
+  std::vector<int32_t> nc;
+  std::vector<double> nv;
+  order_n_csr(n, order, kp, kc, kv, mass, np, nc, nv);
   std::vector<int64_t> ord(n);
   if (reorder) {
     const int dim = m.geometry == IFL_GEOM_SPHERE ? 3 : 2;
@@ -522,18 +558,10 @@ ifl_status build_circumcenter_scalar(const ifl_mesh& m, int32_t order, int32_t r
   std::vector<double> kv;
   to_csr(n, tr, kp, kc, kv);
   tr = Triplets();
-  std::vector<int64_t> np = kp;
-  std::vector<int32_t> ncol = kc;
-  std::vector<double> nv = kv;
-  for (int32_t r = 1; r < order; ++r) {
-    std::vector<int64_t> tp;
-    std::vector<int32_t> tc;
-    std::vector<double> tvv;
-    spgemm_scaled(n, np, ncol, nv, kp, kc, kv, area, tp, tc, tvv);
-    np.swap(tp);
-    ncol.swap(tc);
-    nv.swap(tvv);
-  }
+  std::vector<int64_t> np;
+  std::vector<int32_t> ncol;
+  std::vector<double> nv;
+  order_n_csr(n, order, kp, kc, kv, area, np, ncol, nv);
   std::vector<int64_t> ord(n);
   if (reorder) {
     for (int64_t c = 0; c < n; ++c) gp[c + 1] += gp[c];
@@ -653,18 +681,10 @@ ifl_status build_cell_vector(const ifl_mesh& m, int32_t order, double A, int32_t
   std::vector<double> kv;
   to_csr(n, tr, kp, kc, kv);
   tr = Triplets();
-  std::vector<int64_t> np = kp;
-  std::vector<int32_t> ncol = kc;
-  std::vector<double> nv = kv;
-  for (int32_t r = 1; r < order; ++r) {
-    std::vector<int64_t> tp;
-    std::vector<int32_t> tc;
-    std::vector<double> tvv;
-    spgemm_scaled(n, np, ncol, nv, kp, kc, kv, mass, tp, tc, tvv);
-    np.swap(tp);
-    ncol.swap(tc);
-    nv.swap(tvv);
-  }
+  std::vector<int64_t> np;
+  std::vector<int32_t> ncol;
+  std::vector<double> nv;
+  order_n_csr(n, order, kp, kc, kv, mass, np, ncol, nv);
   // locality ordering of cells; both components of a cell stay adjacent
   std::vector<int64_t> cord(nc);
   if (reorder) {
@@ -712,7 +732,7 @@ ifl_status build_operator(const ifl_mesh& mesh, int32_t placement, int32_t order
                           int32_t reorder, HostOperator* out) {
   ifl_status st = validate(mesh);
   if (st != IFL_OK) return st;
-  if (order < 1 || order > 2) return fail(IFL_EUNSUPPORTED, "filter order n must be 1 or 2");
+  if (order < 1 || order > 4) return fail(IFL_EUNSUPPORTED, "filter order n must be 1 to 4");
   if (placement == IFL_VERTEX_SCALAR || placement == IFL_VORONOI_SCALAR) {
     st = build_vertex_scalar(mesh, order, reorder, placement == IFL_VORONOI_SCALAR, out);
   } else if (placement == IFL_CELL_VECTOR) {

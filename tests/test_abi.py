@@ -80,7 +80,7 @@ def _meshes():
     yield "planar-patch", W.split_square(10, jitter=0.2, periodic=False, seed=3)
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 @pytest.mark.parametrize("name,mesh", list(_meshes()))
 def test_prepare_matches_oracle_vertex(name, mesh, order):
     _lib_or_skip()
@@ -98,7 +98,7 @@ def test_prepare_matches_oracle_vertex(name, mesh, order):
     h.close()
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4])
 def test_prepare_matches_oracle_cell_vector(order):
     _lib_or_skip()
     s = W.icosphere(3, jitter=0.1)
@@ -112,7 +112,7 @@ def test_prepare_matches_oracle_cell_vector(order):
     h.close()
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4])
 @pytest.mark.parametrize("name", ["sphere-L4-mask", "planar-jitter"])
 def test_prepare_matches_oracle_voronoi(name, order):
     """Eq. 3-5 (Voronoi control volumes) from the library's angle-based
@@ -132,7 +132,7 @@ def test_prepare_matches_oracle_voronoi(name, order):
     h.close()
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4])
 def test_prepare_matches_oracle_circumcenter(order):
     """Eq. 6 (scalars at circumcentres) from the library's angle-based
     weights against the oracle's circumcentre coordinates."""
@@ -258,7 +258,7 @@ def test_prepare_errors():
             ifl.prepare_mesh(m, placement, 1, device=-1)
         assert e.value.status == ifl.IFL_EUNSUPPORTED
     with pytest.raises(ifl.IflError) as e:
-        ifl.prepare_mesh(m, ifl.IFL_VERTEX_SCALAR, 3, device=-1)
+        ifl.prepare_mesh(m, ifl.IFL_VERTEX_SCALAR, 5, device=-1)
     assert e.value.status == ifl.IFL_EUNSUPPORTED
     dry = m.with_mask(np.zeros(m.n_vertices, np.uint8))
     with pytest.raises(ifl.IflError) as e:

@@ -88,6 +88,30 @@ def test_sphere_masked(ifl, n, precision):
     h.close()
 
 
+@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("batch", [1, 0])
+def test_higher_orders(ifl, n, precision, batch):
+    """Orders 3 and 4 (K_n = K (M^-1 K)^(n-1), up to 61 entries a row) on
+    the masked level-5 sphere, one column at a time and in auto-width
+    tiles, at wavelengths of 8 to 2 cells (condition number up to ~1e5 at
+    n = 4), against the oracle's direct solve."""
+    s, phi = _sphere(5, 0.3)
+    ks = W.log_scales(s.h, 4, lam_max_cells=8.0)
+    op = O.scalar_operator(s, n)
+    ref = O.filter_scalar(op, phi, ks)
+    h = _prep(ifl, s, n=n, precision=precision, batch=batch)
+    out, stats = h.filter(phi, ks)
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    for j in range(len(ks)):
+        err = relative_l2(out[0, j], ref[j])
+        print(f"sphere L5 n={n} precision={precision} batch={batch} j={j} err={err:.2e} "
+              f"it={stats[j].iterations} upd={stats[j].refinements}")
+        assert err <= tol
+        assert np.all(out[0, j][s.wet == 0] == 0.0)
+    h.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_cell_vector(ifl, precision):
     s = W.icosphere(4, jitter=0.1)
@@ -133,7 +157,7 @@ def test_spectrum_matches_oracle(ifl):
     h.close()
 
 
-@pytest.mark.parametrize("n,precision", [(1, 0), (2, 0), (1, 1), (2, 1)])
+@pytest.mark.parametrize("n,precision", [(1, 0), (2, 0), (4, 0), (1, 1), (2, 1), (4, 1)])
 def test_fig8_spectrum_closed_form(ifl, n, precision):
     """The spectrum of the Fig. 8 construction ("Some comments" section):
     the prescribed spectrum E_q ~ q^-2 / (1 + (q/k*)^2), k* = 30 k_min, as
@@ -146,7 +170,8 @@ def test_fig8_spectrum_closed_form(ifl, n, precision):
     rng = np.random.default_rng(5)
     phi = sum(W.planar_mode_field(m, j, 0, amp=2 * np.sqrt(e), phase=t)
               for j, e, t in zip(range(1, N // 2), E_q, rng.uniform(0, 2 * np.pi, q.size)))
-    ks = 2 * np.pi / np.geomspace(N / 2, 2.5, 12)
+    # n = 4: wavelengths up to 8 cells (condition number ~1e4; at 32 cells it is ~1e9)
+    ks = 2 * np.pi / (np.geomspace(N / 2, 2.5, 12) if n <= 2 else np.geomspace(8, 2.5, 8))
     E_ref = O.filtered_energy_of_modes(q, E_q, ks, n)
     d_ref, _ = O.spectrum_density(ks, E_ref)
     h = _prep(ifl, m, n=n, precision=precision)

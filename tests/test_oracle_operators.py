@@ -151,6 +151,24 @@ def test_order2_operator():
     assert np.diff(K2.indptr).max() <= 19
 
 
+def test_order4_operator():
+    """K4 = K (M^-1 K)^3 (Sect. 2.1.1 at n = 4): symmetric, annihilates
+    constants, equals four applications of the Laplacian form, and reaches
+    the 4-ring (61 entries a row on a valence-6 mesh)."""
+    s = W.icosphere(3, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    op = O.scalar_operator(s, 4)
+    K4 = op.Kn
+    assert abs(K4 - K4.T).max() <= 1e-14 * abs(K4).max()
+    assert np.max(np.abs(K4 @ np.ones(K4.shape[0]))) <= 1e-13 * abs(K4).max()
+    x = np.random.default_rng(2).normal(size=K4.shape[0])
+    y = x
+    for r in range(4):
+        y = op.K @ y if r == 3 else (op.K @ y) / op.A
+    assert np.linalg.norm(K4 @ x - y) <= 1e-13 * np.linalg.norm(y)
+    assert np.diff(K4.indptr).max() <= 61
+
+
 def test_dofs_exclude_dry_and_orphans():
     s = W.icosphere(3, jitter=0.1)
     wet = W.land_mask(s, 0.4, seed=3)

@@ -40,6 +40,25 @@ def test_closed_form_fourier_multiplier(n, gamma):
             assert relative_l2(out[j], ref) < 1e-12, (method, j)
 
 
+@pytest.mark.parametrize("n", [3, 4])
+def test_closed_form_fourier_multiplier_higher_orders(n):
+    """Orders 3 and 4 (K_n = K (M^-1 K)^(n-1), Sect. 2.1.1; n = 4 is the
+    highest order of Fig. 8): on the uniform periodic split square the
+    filter is the multiplier 1 / (1 + gamma (lambda / k^2)^n). Scales stop at
+    8 cells, where the condition number (~1e4) leaves the direct solves
+    accurate to 1e-12."""
+    N = 32
+    m = W.split_square(N, jitter=0.0)
+    op = O.scalar_operator(m, n)
+    phi = W.planar_k3_field(m, 1000)
+    ks = W.log_scales(1.0, 4, lam_max_cells=8.0)
+    for method in ("dense", "direct"):
+        out = O.filter_scalar(op, phi, ks, method=method)
+        for j, k in enumerate(ks):
+            ref = _fourier_filter(phi.reshape(N, N), k, 0.5, n).ravel()
+            assert relative_l2(out[j], ref) < 1e-12, (method, j)
+
+
 def test_cg_matches_dense_and_lapack_c1():
     """Plain FP64 configuration: 64x64 periodic split square, jitter 0.2,
     n = 1, eight scales from 32 to 2 cells: CG (from x0 = phi) equals the
