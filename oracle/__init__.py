@@ -14,7 +14,8 @@ Contents
 operators : active cells / dofs, flat-facet geometry, cotangent stiffness
             (Galerkin P1 form of Sect. 2.1.1), the finite-volume median-dual
             route (same section), lumped mass, order-n operator (Eq. 5 and
-            the biharmonic FE form), the cell-vector operator (Eq. 7).
+            the biharmonic FE form), the cell-vector operator (Eq. 7), the
+            vertex FE vector Laplacian with metric terms (Sect. 2.1.2).
 solve     : the system ``S = M + gamma/k^(2n) K_n`` (Eq. 1 with Eq. 4/5),
             dense Cholesky for small meshes, Jacobi-PCG from ``x0 = phi``
             (residual form of Sect. 2.2.2) with extended-precision
@@ -29,10 +30,12 @@ from .operators import (
     CellScalarOperator,
     ScalarOperator,
     VectorOperator,
+    VertexVectorOperator,
     active_cells,
     circumcenter_operator,
     scalar_operator,
     vector_operator,
+    vertex_vector_operator,
     voronoi_operator,
     cot_stiffness,
     fv_stiffness,
@@ -43,6 +46,8 @@ from .solve import (
     system_matrix,
     filter_scalar,
     filter_vector,
+    filter_vertex_vector,
+    project_cells_to_vertices,
     filter_dense,
     pcg_jacobi,
     refine_solve,
@@ -54,6 +59,10 @@ from .spectrum import discrete_symbol, energy, fig8_modes, filtered_energy_of_mo
 __all__ = [
     "ScalarOperator",
     "VectorOperator",
+    "VertexVectorOperator",
+    "vertex_vector_operator",
+    "filter_vertex_vector",
+    "project_cells_to_vertices",
     "active_cells",
     "scalar_operator",
     "vector_operator",

@@ -425,3 +425,112 @@ def circumcenter_operator(mesh, n: int = 1) -> CellScalarOperator:
     K.sort_indices()
     Kn = order_n(K, area, n)
     return CellScalarOperator(K=K, Kn=Kn, A=area, n=n, cells=cells, n_cells_total=mesh.n_triangles)
+
+
+# ------------------------------------------------- Sect. 2.1.2, vertex vectors
+@dataclasses.dataclass
+class VertexVectorOperator:
+    """FE vector Laplacian on vertices, unknowns interleaved ``(u_v, v_v)``
+    (east, north) as ``2d, 2d+1``; ``A`` holds the lumped mass per
+    component; ``Rvc`` maps a cell velocity field (caller numbering,
+    interleaved ``2c, 2c+1``) to the right-hand side."""
+
+    K: sp.csr_matrix
+    Kn: sp.csr_matrix
+    A: np.ndarray
+    n: int
+    verts: np.ndarray
+    dof_of: np.ndarray
+    n_vertices: int
+    Rvc: sp.csr_matrix
+    n_cells_total: int
+
+
+def _metric_geometry(mesh, a, b, c):
+    """Per triangle: metric factor ``m = tan(theta) / R_e`` with ``theta``
+    the latitude of the centroid and ``R_e`` the mean corner radius,
+    ``1 / R_e^2``, and the zonal unit vector ``e_E = z x c / |z x c|`` at
+    the centroid direction ``c``. Planar meshes: ``m = 0``, ``1/R_e^2 = 0``,
+    ``e_E = x``."""
+    nf = a.shape[0]
+    if mesh.geometry != GEOM_SPHERE:
+        return np.zeros(nf), np.zeros(nf), np.tile(np.array([1.0, 0.0, 0.0]), (nf, 1))
+    cd = a + b + c
+    cd = cd / np.linalg.norm(cd, axis=1, keepdims=True)
+    Re = (np.linalg.norm(a, axis=1) + np.linalg.norm(b, axis=1) + np.linalg.norm(c, axis=1)) / 3.0
+    coslat = np.hypot(cd[:, 0], cd[:, 1])
+    m = cd[:, 2] / (coslat * Re)
+    ee = np.stack([-cd[:, 1], cd[:, 0], np.zeros(nf)], axis=1) / coslat[:, None]
+    return m, 1.0 / Re ** 2, ee
+
+
+def vertex_vector_operator(mesh, n: int = 1) -> VertexVectorOperator:
+    """The vertex-based FE vector Laplacian of Sect. 2.1.2:
+    ``D_2 = [[D~, T], [-T, D~]]`` (l-free) with, over each active triangle
+    (P1 basis ``N``, metric factor ``m`` constant on the triangle),
+
+    * ``D~_vv' = int grad N_v . grad N_v' + (R_e^-2 + m^2) N_v N_v'``
+      (the scalar stiffness plus a consistent-mass term),
+    * ``T_vv' = int m (-N_v' d_x N_v + N_v d_x N_v')``, with ``d_x`` the
+      derivative along the zonal unit vector at the centroid; as
+      ``d_x N`` is constant on a triangle this is
+      ``m A_t / 3 (d_x N_v' - d_x N_v)``.
+
+    ``M_2 = diag(M, M)`` with the lumped (median-dual) mass, order n by
+    ``K_n = D_2 (M_2^-1 D_2)^(n-1)``, and the right-hand side
+    ``R_vc u_c`` with ``R_vc = int N_v M_c dS = A_c / 3`` for each corner
+    ``v`` of an active cell ``c`` (same component to same component).
+
+    Gradients are those of the flat facet: ``grad N_i = n x (P_{i+2} -
+    P_{i+1}) / (2 A)`` with ``n`` the facet normal of the corner order.
+    """
+    K, area, verts, dof_of, tris = cot_stiffness(mesh)
+    A = lumped_mass(verts.size, dof_of[tris], area)
+    act = active_cells(mesh)
+    cells = np.nonzero(act)[0]
+    a, b, c = _corner_positions(mesh, tris)
+    if a.shape[1] == 2:
+        a, b, c = (np.concatenate([p, np.zeros((p.shape[0], 1))], axis=1) for p in (a, b, c))
+    m, inv_r2, ee = _metric_geometry(mesh, a, b, c)
+    nrm = np.cross(b - a, c - a)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    P = (a, b, c)
+    dx = [np.sum(np.cross(nrm, P[(i + 2) % 3] - P[(i + 1) % 3]) * ee, axis=1) / (2.0 * area)
+          for i in range(3)]
+    idx = dof_of[tris]
+    nd = verts.size
+    rows, cols, vals = [], [], []
+    Kc = K.tocoo()
+    for comp in range(2):
+        rows.append(2 * Kc.row + comp)
+        cols.append(2 * Kc.col + comp)
+        vals.append(Kc.data)
+    w0 = (inv_r2 + m ** 2) * area / 12.0
+    for i in range(3):
+        for j in range(3):
+            mass_ij = w0 * (2.0 if i == j else 1.0)
+            t_ij = m * area / 3.0 * (dx[j] - dx[i])
+            for comp in range(2):
+                rows.append(2 * idx[:, i] + comp)
+                cols.append(2 * idx[:, j] + comp)
+                vals.append(mass_ij)
+            # T couples east (row) with north (column), -T north with east
+            rows += [2 * idx[:, i], 2 * idx[:, i] + 1]
+            cols += [2 * idx[:, j] + 1, 2 * idx[:, j]]
+            vals += [t_ij, -t_ij]
+    D2 = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(2 * nd, 2 * nd)).tocsr()
+    D2.sum_duplicates()
+    D2.sort_indices()
+    A2 = np.repeat(A, 2)
+    Kn = order_n(D2, A2, n)
+    rr, rc, rv = [], [], []
+    for i in range(3):
+        for comp in range(2):
+            rr.append(2 * idx[:, i] + comp)
+            rc.append(2 * cells + comp)
+            rv.append(area / 3.0)
+    Rvc = sp.coo_matrix((np.concatenate(rv), (np.concatenate(rr), np.concatenate(rc))),
+                        shape=(2 * nd, 2 * mesh.n_triangles)).tocsr()
+    return VertexVectorOperator(K=D2, Kn=Kn, A=A2, n=n, verts=verts, dof_of=dof_of, n_vertices=mesh.n_vertices,
+                                Rvc=Rvc, n_cells_total=mesh.n_triangles)

@@ -160,8 +160,13 @@ def direct_refine_solve(S, b, steps: int = 3):
 
 
 def _solve(op, phi_dofs, k, gamma, method):
+    return _solve_rhs(op, op.A * phi_dofs, phi_dofs, k, gamma, method)
+
+
+def _solve_rhs(op, b, x0, k, gamma, method):
+    """Solve ``S x = b``; ``x0`` starts the iterative method."""
     S = system_matrix(op, k, gamma)
-    b = op.A * phi_dofs
+    phi_dofs = x0
     n = b.size
     if method == "auto":
         method = "dense" if n <= 4096 else ("direct" if n <= 300_000 else "cg")
@@ -199,6 +204,31 @@ def filter_vector(op, field, ks, gamma: float = 0.5, method: str = "auto", retur
     for j, k in enumerate(ks):
         x, info = _solve(op, phi, float(k), gamma, method)
         out[j] = from_dofs(op, x).reshape(-1, 2)
+        infos.append(info)
+    return (out, infos) if return_info else out
+
+
+def project_cells_to_vertices(op, cell_field) -> np.ndarray:
+    """Right-hand side of the vertex vector filter (Sect. 2.1.2):
+    ``R_vc u_c`` over active cells, interleaved ``(east, north)`` per dof.
+    ``cell_field``: (F, 2) in triangle numbering."""
+    u = np.asarray(cell_field, dtype=np.float64).reshape(-1)
+    return op.Rvc @ u
+
+
+def filter_vertex_vector(op, cell_field, ks, gamma: float = 0.5, method: str = "auto",
+                         return_info: bool = False):
+    """Filter a cell velocity field ``(F, 2)`` onto vertices at each ``k``:
+    ``S x = R_vc u_c`` with ``S = M_2 + gamma/k^(2n) K_n`` (Sect. 2.1.2).
+    Returns (len(ks), V, 2) (east, north) with zeros at vertices that are
+    not dofs; the iterative method starts from ``M_2^-1 R_vc u_c``."""
+    b = project_cells_to_vertices(op, cell_field)
+    x0 = b / op.A
+    out = np.zeros((len(ks), op.n_vertices, 2))
+    infos = []
+    for j, k in enumerate(ks):
+        x, info = _solve_rhs(op, b, x0, float(k), gamma, method)
+        out[j][op.verts] = x.reshape(-1, 2)
         infos.append(info)
     return (out, infos) if return_info else out
 
