@@ -76,7 +76,7 @@ typedef struct ifl_mesh {
 #define IFL_CELL_VECTOR 1         /* (east, north) vectors on triangles, Eq. 7 (Sect. 2.1.2) */
 #define IFL_VORONOI_SCALAR 2      /* scalars on vertices, quasi-hexagonal (Voronoi) CVs, Eq. 3-5 */
 #define IFL_CIRCUMCENTER_SCALAR 3 /* scalars at triangle circumcentres, Eq. 6 */
-#define IFL_VERTEX_VECTOR 4       /* vertex FE vector Laplacian: reserved, IFL_EUNSUPPORTED */
+#define IFL_VERTEX_VECTOR 4       /* (east, north) vectors on vertices, FE vector Laplacian (Sect. 2.1.2) */
 
 /* Arithmetic of the solve. */
 #define IFL_FP64 0  /* all vectors, matrix values, SpMV and reductions in FP64 */
@@ -136,14 +136,25 @@ void ifl_default_options(ifl_options* opt);
  *                           is not positive (e.g. right triangles sharing their
  *                           hypotenuse);
  *   IFL_CELL_VECTOR         Eq. 7 with the change of local unit vectors between
- *                           neighbouring cells, triangle areas.
- * Fields are per vertex (L = n_vertices) for the vertex placements, per
- * triangle (L = n_triangles) for IFL_CIRCUMCENTER_SCALAR and (east, north)
- * per triangle (L = 2 n_triangles) for IFL_CELL_VECTOR.
+ *                           neighbouring cells, triangle areas;
+ *   IFL_VERTEX_VECTOR       D_2 = [[D~, T], [-T, D~]] of Sect. 2.1.2 on P1 elements:
+ *                           D~ = stiffness + (1/R_e^2 + m^2) consistent mass, T the
+ *                           metric coupling, m = tan(latitude) / R_e constant on a
+ *                           triangle (taken at its centroid, R_e its mean corner
+ *                           radius; m = 0 and 1/R_e^2 = 0 on planar meshes),
+ *                           median-dual areas; IFL_EDEGENERATE if an active
+ *                           triangle's centroid lies on the polar axis. Lon/lat
+ *                           components are singular at the poles: put the poles
+ *                           on land (rotated meshes do) for accurate results.
+ * Fields are per vertex (L = n_vertices) for the vertex scalar placements, per
+ * triangle (L = n_triangles) for IFL_CIRCUMCENTER_SCALAR, (east, north) per
+ * triangle (L = 2 n_triangles) for IFL_CELL_VECTOR and (east, north) per vertex
+ * (L = 2 n_vertices) for IFL_VERTEX_VECTOR, whose fields come from cell
+ * velocities through ifl_project_cells.
  *
  * mesh      : host arrays, read only during the call.
- * placement : IFL_VERTEX_SCALAR, IFL_VORONOI_SCALAR, IFL_CIRCUMCENTER_SCALAR
- *             or IFL_CELL_VECTOR (IFL_VERTEX_VECTOR: IFL_EUNSUPPORTED).
+ * placement : IFL_VERTEX_SCALAR, IFL_VORONOI_SCALAR, IFL_CIRCUMCENTER_SCALAR,
+ *             IFL_CELL_VECTOR or IFL_VERTEX_VECTOR.
  * n         : filter order, 1 to 4 (others: IFL_EUNSUPPORTED). K_n is assembled
  *             explicitly: on a triangular mesh its rows hold about 7, 19, 37
  *             and 61 entries for n = 1..4, and the condition number of S grows
@@ -165,9 +176,14 @@ void ifl_destroy(ifl_handle* h);
 /* Number of unknowns of the solve (dofs, times 2 for vectors). */
 int64_t ifl_num_dofs(const ifl_handle* h);
 
-/* Length of one field in the caller's numbering: V for vertex scalars,
- * 2F for cell vectors (interleaved east, north per triangle). */
+/* Length of one field in the caller's numbering: V for vertex scalars, F
+ * for circumcentre scalars, 2F for cell vectors and 2V for vertex vectors
+ * (interleaved east, north). */
 int64_t ifl_field_length(const ifl_handle* h);
+
+/* IFL_VERTEX_VECTOR handles: the number of triangles F of the mesh (the
+ * cell field of ifl_project_cells has 2F doubles); 0 for other placements. */
+int64_t ifl_num_cells(const ifl_handle* h);
 
 /* Replace the solver options of a prepared handle (gamma, rtol, max_iter,
  * precision, batch, stream, profile). Mesh-dependent fields (cell_A,
@@ -220,6 +236,22 @@ ifl_status ifl_spectrum(ifl_handle* h, const double* field, int32_t n_scales,
  * x, y : L doubles each, host or device; dry entries of y are 0.
  */
 ifl_status ifl_apply(ifl_handle* h, double k, const double* x, double* y);
+
+/*
+ * Right-hand side of the vertex vector filter (Sect. 2.1.2): the paper
+ * projects cell velocities u_c to vertices by R_vc = integral of N_v over
+ * cell c (A_c / 3 for each corner of an active cell, component by
+ * component). This writes the vertex field f = M^-1 R_vc u_c, so that
+ * ifl_filter(f) solves S u_bar = M f = R_vc u_c (and starts from f).
+ * Needs an IFL_VERTEX_VECTOR handle with a device (else IFL_EINVAL /
+ * IFL_EDEVICE).
+ * cells : 2 n_triangles doubles, (east, north) per triangle, host or device;
+ *         entries of inactive triangles are not read; non-finite values
+ *         propagate (ifl_filter then rejects the field).
+ * out   : L = 2 n_vertices doubles, host or device; 0 at vertices that are
+ *         not dofs. Synchronous.
+ */
+ifl_status ifl_project_cells(ifl_handle* h, const double* cells, double* out);
 
 /*
  * Export the prepared operator to host memory (checks, debugging).

@@ -32,6 +32,7 @@ from ._ffi import (  # noqa: F401
     LIB_PATH,
     default_options,
     ifl_apply,
+    ifl_project_cells,
     ifl_destroy,
     ifl_filter,
     ifl_last_error,

@@ -110,6 +110,7 @@ _PROTOS = {
     "ifl_destroy": (None, [C.c_void_p]),
     "ifl_num_dofs": (C.c_int64, [C.c_void_p]),
     "ifl_field_length": (C.c_int64, [C.c_void_p]),
+    "ifl_num_cells": (C.c_int64, [C.c_void_p]),
     "ifl_set_options": (C.c_int32, [C.c_void_p, C.POINTER(ifl_options)]),
     "ifl_get_options": (C.c_int32, [C.c_void_p, C.POINTER(ifl_options)]),
     "ifl_filter": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p,
@@ -117,6 +118,7 @@ _PROTOS = {
     "ifl_spectrum": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ifl_apply": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "ifl_project_cells": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ifl_operator_nnz": (C.c_int64, [C.c_void_p]),
     "ifl_export_operator": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -310,6 +312,23 @@ class Handle:
         _check(lib().ifl_apply(self._h, float(k), fx.ptr, fy.ptr))
         return y
 
+    def project_cells(self, cells, out=None):
+        """Cell velocities (F, 2) -> the vertex field M^-1 R_vc u_c (2V,)
+        that ifl_filter takes on an IFL_VERTEX_VECTOR handle."""
+        nc = int(lib().ifl_num_cells(self._h))
+        if nc == 0:
+            raise ValueError("project_cells needs an IFL_VERTEX_VECTOR handle")
+        if int(np.prod(cells.shape)) != 2 * nc:
+            raise ValueError(f"cell field has {int(np.prod(cells.shape))} entries, expected {2 * nc}")
+        fc = _Field(cells.reshape(-1))
+        if out is None:
+            out = np.zeros(self.field_length)
+        if int(np.prod(out.shape)) != self.field_length:
+            raise ValueError(f"out has {int(np.prod(out.shape))} entries, expected {self.field_length}")
+        fo = _Field(out, writable=True)
+        _check(lib().ifl_project_cells(self._h, fc.ptr, fo.ptr))
+        return out
+
     def export_operator(self):
         n = self.num_dofs
         nnz = int(lib().ifl_operator_nnz(self._h))
@@ -380,6 +399,10 @@ def ifl_spectrum(h: Handle, field, ks):
 
 def ifl_apply(h: Handle, k, x, y=None):
     return h.apply(k, x, y)
+
+
+def ifl_project_cells(h: Handle, cells, out=None):
+    return h.project_cells(cells, out)
 
 
 def ifl_save(h: Handle, path: str):

@@ -103,6 +103,8 @@ int64_t ifl_num_dofs(const ifl_handle* h) { return h ? h->op.n : 0; }
 
 int64_t ifl_field_length(const ifl_handle* h) { return h ? h->op.field_len : 0; }
 
+int64_t ifl_num_cells(const ifl_handle* h) { return h ? h->op.n_cells : 0; }
+
 ifl_status ifl_set_options(ifl_handle* h, const ifl_options* opt) {
   if (!h || !opt) return fail(IFL_EINVAL, "handle / options NULL");
   ifl_status st = check_options(*opt);
@@ -168,6 +170,16 @@ ifl_status ifl_apply(ifl_handle* h, double k, const double* x, double* y) {
   return device_apply(h, k, x, y);
 }
 
+ifl_status ifl_project_cells(ifl_handle* h, const double* cells, double* out) {
+  g_last_error.clear();
+  if (!h || !cells || !out) return fail(IFL_EINVAL, "handle / cells / out is NULL");
+  if (h->op.placement != IFL_VERTEX_VECTOR)
+    return fail(IFL_EINVAL, "ifl_project_cells needs an IFL_VERTEX_VECTOR handle");
+  if (!h->dev) return fail(IFL_EDEVICE, "host-only handle (device = -1)");
+  std::lock_guard<std::mutex> lk(h->mu);
+  return device_project_cells(h, cells, out);
+}
+
 int64_t ifl_operator_nnz(const ifl_handle* h) { return h ? (int64_t)h->op.col.size() : 0; }
 
 ifl_status ifl_export_operator(const ifl_handle* h, int64_t* row_ptr, int32_t* col, double* val, double* mass,
@@ -206,6 +218,14 @@ ifl_status ifl_save(const ifl_handle* h, const char* path) {
   w(op.val.data(), sizeof(double) * op.val.size());
   w(op.mass.data(), sizeof(double) * op.mass.size());
   w(op.entity.data(), sizeof(int64_t) * op.entity.size());
+  if (op.placement == IFL_VERTEX_VECTOR) {
+    const int64_t pn = (int64_t)op.proj_tri.size();
+    w(&op.n_cells, 8);
+    w(&pn, 8);
+    w(op.proj_ptr.data(), sizeof(int64_t) * op.proj_ptr.size());
+    w(op.proj_tri.data(), sizeof(int32_t) * op.proj_tri.size());
+    w(op.proj_w.data(), sizeof(double) * op.proj_w.size());
+  }
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) return fail(IFL_EIO, std::string("write failed: ") + path);
   return IFL_OK;
@@ -249,12 +269,32 @@ ifl_status ifl_load(const char* path, const ifl_options* opt, ifl_handle** out) 
     r(op.mass.data(), sizeof(double) * op.mass.size());
     r(op.entity.data(), sizeof(int64_t) * op.entity.size());
   }
+  if (ok && op.placement == IFL_VERTEX_VECTOR) {
+    int64_t pn = 0;
+    r(&op.n_cells, 8);
+    r(&pn, 8);
+    ok = ok && op.n % 2 == 0 && op.n_cells > 0 && op.n_cells < (1ll << 31) && pn > 0 && pn <= 3 * op.n_cells;
+    if (ok) {
+      op.proj_ptr.resize(op.n / 2 + 1);
+      op.proj_tri.resize(pn);
+      op.proj_w.resize(pn);
+      r(op.proj_ptr.data(), sizeof(int64_t) * op.proj_ptr.size());
+      r(op.proj_tri.data(), sizeof(int32_t) * op.proj_tri.size());
+      r(op.proj_w.data(), sizeof(double) * op.proj_w.size());
+    }
+    ok = ok && op.proj_ptr[0] == 0 && op.proj_ptr[op.n / 2] == pn;
+    for (int64_t i = 0; ok && i < op.n / 2; ++i) ok = op.proj_ptr[i] <= op.proj_ptr[i + 1];
+    for (int64_t e = 0; ok && e < pn; ++e) ok = op.proj_tri[e] >= 0 && op.proj_tri[e] < op.n_cells;
+  }
   std::fclose(f);
   if (ok) {
     ok = op.row_ptr[0] == 0 && op.row_ptr[op.n] == nnz;
     for (int64_t i = 0; ok && i < op.n; ++i) ok = op.row_ptr[i] <= op.row_ptr[i + 1];
     for (int64_t e = 0; ok && e < nnz; ++e) ok = op.col[e] >= 0 && op.col[e] < op.n;
     for (int64_t i = 0; ok && i < op.n; ++i) ok = op.entity[i] >= 0 && op.entity[i] < op.field_len;
+    if (op.placement == IFL_VERTEX_VECTOR)  // the projection writes (east, north) pairs
+      for (int64_t i = 0; ok && i + 1 < op.n; i += 2)
+        ok = op.entity[i] % 2 == 0 && op.entity[i + 1] == op.entity[i] + 1;
   }
   if (!ok) return fail(IFL_EIO, std::string("bad or truncated handle file: ") + path);
   h->opt.reorder = reorder;

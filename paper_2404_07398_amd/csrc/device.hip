@@ -141,6 +141,11 @@ struct DeviceState {
   int64_t field_rows_len = 0;
   double* col_stage = nullptr;    // per-slot outputs for host destinations
   int64_t col_stage_len = 0;
+  // cell -> vertex projection of vertex-vector handles (uploaded on first use)
+  int64_t* proj_ptr = nullptr;
+  int32_t* proj_tri = nullptr;
+  double* proj_w = nullptr;
+  double* proj_in = nullptr;      // device copy of a host cell field
 };
 
 // partial-array offsets (in units of G)
@@ -576,6 +581,25 @@ __global__ void k_gather_field(const double* __restrict__ src, const int64_t* __
   dst[i] = v;
 }
 
+// Cell -> vertex projection (Sect. 2.1.2): one thread per dof d (rows 2d,
+// 2d+1) sums w_e u_c over its incident active triangles, w_e = (A_c / 3) /
+// M_d, and writes (east, north) to the dof's vertex in the caller numbering.
+__global__ __launch_bounds__(kBlock) void k_project_cells(int64_t nd, const int64_t* ptr, const int32_t* tri,
+                                                           const double* w, const int64_t* entity,
+                                                           const double* cells, double* out) {
+  const int64_t d = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (d >= nd) return;
+  double ue = 0.0, un = 0.0;
+  for (int64_t e = ptr[d]; e < ptr[d + 1]; ++e) {
+    const int64_t t = tri[e];
+    ue += w[e] * cells[2 * t];
+    un += w[e] * cells[2 * t + 1];
+  }
+  const int64_t v2 = entity[2 * d];
+  out[v2] = ue;
+  out[v2 + 1] = un;
+}
+
 // y = S x with FP64 values (internal order), scattered to the caller numbering.
 __global__ __launch_bounds__(kBlock) void k_apply(Mat m, const double* x, double c, const int64_t* entity,
                                                   double* out) {
@@ -720,6 +744,9 @@ void device_destroy(Handle* h) {
   if (d->field_stage) (void)hipFree(d->field_stage);
   if (d->field_rows) (void)hipFree(d->field_rows);
   if (d->col_stage) (void)hipFree(d->col_stage);
+  void* proj[] = {d->proj_ptr, d->proj_tri, d->proj_w, d->proj_in};
+  for (void* p : proj)
+    if (p) (void)hipFree(p);
   for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
   if (d->own_stream) (void)hipStreamDestroy(d->own_stream);
   delete d;
@@ -1345,6 +1372,35 @@ ifl_status device_apply(Handle* h, double kk, const double* x, double* y) {
   k_apply<<<nb, kBlock, 0, s>>>(mat_view(d->m), d->w.phi, c, d->m.entity, dst);
   IFL_HIP(hipGetLastError());
   if (!ydev) IFL_HIP(hipMemcpyAsync(y, dst, sizeof(double) * L, hipMemcpyDeviceToHost, s));
+  IFL_HIP(hipStreamSynchronize(s));
+  return IFL_OK;
+}
+
+ifl_status device_project_cells(Handle* h, const double* cells, double* out) {
+  DeviceState* d = h->dev;
+  const HostOperator& op = h->op;
+  IFL_HIP(hipSetDevice(d->device));
+  hipStream_t s = stream_of(h);
+  const int64_t nd = op.n / 2, L = op.field_len, nc2 = 2 * op.n_cells;
+  ifl_status st;
+  if (!d->proj_ptr) {
+    if ((st = upload(&d->proj_ptr, op.proj_ptr)) || (st = upload(&d->proj_tri, op.proj_tri)) ||
+        (st = upload(&d->proj_w, op.proj_w)) || (st = dalloc(&d->proj_in, (size_t)nc2)))
+      return st;
+  }
+  if ((st = ensure_stage(d, L)) != IFL_OK) return st;
+  const double* src = cells;
+  if (!is_device_ptr(cells)) {
+    IFL_HIP(hipMemcpyAsync(d->proj_in, cells, sizeof(double) * nc2, hipMemcpyHostToDevice, s));
+    src = d->proj_in;
+  }
+  const bool odev = is_device_ptr(out);
+  double* dst = odev ? out : d->w.stage_out;
+  IFL_HIP(hipMemsetAsync(dst, 0, sizeof(double) * L, s));
+  const unsigned nb = (unsigned)((nd + kBlock - 1) / kBlock);
+  k_project_cells<<<nb, kBlock, 0, s>>>(nd, d->proj_ptr, d->proj_tri, d->proj_w, d->m.entity, src, dst);
+  IFL_HIP(hipGetLastError());
+  if (!odev) IFL_HIP(hipMemcpyAsync(out, dst, sizeof(double) * L, hipMemcpyDeviceToHost, s));
   IFL_HIP(hipStreamSynchronize(s));
   return IFL_OK;
 }

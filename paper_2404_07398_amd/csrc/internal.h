@@ -29,6 +29,13 @@ struct HostOperator {
   std::vector<double> mass;        // n
   int32_t n_components = 1;        // 1 (scalar) or 2 (vector)
   uint64_t mesh_hash = 0;
+  // IFL_VERTEX_VECTOR only: the cell -> vertex projection R_vc u_c / M_v.
+  // Rows 2d and 2d+1 are dof d; its incident active triangles are
+  // proj_tri[proj_ptr[d] .. proj_ptr[d+1]) with weights (A_c / 3) / M_d.
+  int64_t n_cells = 0;             // triangles of the mesh (cell field: 2 n_cells)
+  std::vector<int64_t> proj_ptr;   // n / 2 + 1
+  std::vector<int32_t> proj_tri;
+  std::vector<double> proj_w;
 };
 
 // Mesh -> operator (prepare phase). 'reorder' selects the reverse
@@ -74,6 +81,9 @@ void device_destroy(Handle* h);
 ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales,
                          const double* k, double* out, ifl_solve_stats* stats, double* energy);
 ifl_status device_apply(Handle* h, double k, const double* x, double* y);
+// Cell velocities (2 n_cells, host or device) -> the projected vertex field
+// R_vc u_c / M (field_len, host or device; 0 where there is no dof).
+ifl_status device_project_cells(Handle* h, const double* cells, double* out);
 ifl_status device_profile_read(Handle* h, int64_t* launches, double* total_ms, double* bytes,
                                int32_t reset);
 std::string device_profile_kernel(Handle* h);

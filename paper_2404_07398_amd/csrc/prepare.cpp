@@ -480,6 +480,160 @@ ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder
   return IFL_OK;
 }
 
+// Velocities on vertices (Sect. 2.1.2): the FE vector Laplacian
+// D_2 = [[D~, T], [-T, D~]] in (east, north) components, unknowns of dof d
+// at rows 2d (east) and 2d+1 (north). Over each active triangle, with P1
+// basis N, flat-facet gradients and m = tan(latitude of the centroid) / R_e
+// (R_e the mean corner radius; planar meshes: m = 0, 1/R_e^2 = 0):
+//   D~_ij += A grad N_i . grad N_j + (1/R_e^2 + m^2) A (1 + [i = j]) / 12,
+//   T_ij  += m A / 3 (d_x N_j - d_x N_i),
+// d_x the derivative along the zonal unit vector at the centroid (constant
+// on the triangle). T is antisymmetric entry by entry, so D_2 is bitwise
+// symmetric. Mass: the median-dual area per component. The right-hand side
+// R_vc u_c (R_vc = A_c / 3 for each corner of an active cell) is kept as a
+// projection onto the rows divided by the mass, so that M times the
+// projected field is R_vc u_c.
+ifl_status build_vertex_vector(const ifl_mesh& m, int32_t order, int32_t reorder, HostOperator* out) {
+  const std::vector<char> act = active_triangles(m);
+  std::vector<int64_t> dof_of(m.n_vertices, -1);
+  for (int64_t t = 0; t < m.n_triangles; ++t)
+    if (act[t])
+      for (int k = 0; k < 3; ++k) dof_of[m.triangles[3 * t + k]] = 0;
+  std::vector<int64_t> vert_of;
+  for (int64_t v = 0; v < m.n_vertices; ++v)
+    if (dof_of[v] == 0) {
+      dof_of[v] = (int64_t)vert_of.size();
+      vert_of.push_back(v);
+    }
+  const int64_t nd = (int64_t)vert_of.size();
+  if (nd == 0) return fail(IFL_EDEGENERATE, "no active triangle (all triangles touch a dry vertex)");
+  const int64_t n = 2 * nd;
+  const bool sphere = m.geometry == IFL_GEOM_SPHERE;
+
+  Triplets tr, pat;
+  std::vector<double> mass(nd, 0.0);
+  std::vector<double> tri_w(m.n_triangles, 0.0);
+  for (int64_t t = 0; t < m.n_triangles; ++t) {
+    if (!act[t]) continue;
+    const int32_t* tv = m.triangles + 3 * t;
+    V3 p[3];
+    corners(m, tv, p);
+    const V3 e[3] = {sub(p[2], p[1]), sub(p[0], p[2]), sub(p[1], p[0])};
+    const V3 nrm_raw = cross(e[2], scale(e[1], -1.0));
+    const double twoA = norm(nrm_raw);
+    const double ee = dot(e[0], e[0]) + dot(e[1], e[1]) + dot(e[2], e[2]);
+    if (!(twoA > 1e-14 * ee)) return fail(IFL_EDEGENERATE, "zero-area active triangle " + std::to_string(t));
+    const double area = 0.5 * twoA;
+    const V3 nrm = scale(nrm_raw, 1.0 / twoA);
+    double mf = 0.0, inv_r2 = 0.0;
+    V3 east{1.0, 0.0, 0.0};
+    if (sphere) {
+      V3 cd = add(add(p[0], p[1]), p[2]);
+      cd = scale(cd, 1.0 / norm(cd));
+      const double re = (norm(p[0]) + norm(p[1]) + norm(p[2])) / 3.0;
+      const double coslat = std::hypot(cd.x, cd.y);
+      if (!(coslat > 1e-12))
+        return fail(IFL_EDEGENERATE, "active triangle " + std::to_string(t) +
+                                         " has its centroid on the polar axis (the metric factor is infinite)");
+      mf = cd.z / (coslat * re);
+      inv_r2 = 1.0 / (re * re);
+      east = V3{-cd.y / coslat, cd.x / coslat, 0.0};
+    }
+    double dx[3];
+    for (int i = 0; i < 3; ++i) dx[i] = dot(cross(nrm, e[i]), east) / twoA;
+    const double inv = 1.0 / (2.0 * twoA);
+    const double w0 = (inv_r2 + mf * mf) * area / 12.0;
+    const double mt = mf * area / 3.0;
+    const int64_t d[3] = {dof_of[tv[0]], dof_of[tv[1]], dof_of[tv[2]]};
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j) {
+        const double dij = dot(e[i], e[j]) * inv + w0 * (i == j ? 2.0 : 1.0);
+        tr.add(2 * d[i], 2 * d[j], dij);
+        tr.add(2 * d[i] + 1, 2 * d[j] + 1, dij);
+        const double tij = mt * (dx[j] - dx[i]);
+        tr.add(2 * d[i], 2 * d[j] + 1, tij);
+        tr.add(2 * d[i] + 1, 2 * d[j], -tij);
+        pat.add(d[i], d[j], 1.0);
+      }
+      mass[d[i]] += twoA / 6.0;
+    }
+    tri_w[t] = area / 3.0;
+  }
+  std::vector<double> mass2(n);
+  for (int64_t i = 0; i < nd; ++i) mass2[2 * i] = mass2[2 * i + 1] = mass[i];
+  std::vector<int64_t> kp;
+  std::vector<int32_t> kc;
+  std::vector<double> kv;
+  to_csr(n, tr, kp, kc, kv);
+  tr = Triplets();
+  std::vector<int64_t> np;
+  std::vector<int32_t> ncol;
+  std::vector<double> nv;
+  order_n_csr(n, order, kp, kc, kv, mass2, np, ncol, nv);
+
+  // locality ordering of the vertices; both components of a dof stay adjacent
+  std::vector<int64_t> vord(nd);
+  if (reorder) {
+    std::vector<int64_t> gp;
+    std::vector<int32_t> gc;
+    std::vector<double> gv;
+    to_csr(nd, pat, gp, gc, gv);
+    const int dim = sphere ? 3 : 2;
+    std::vector<V3> pts(nd);
+    for (int64_t i = 0; i < nd; ++i) {
+      const double* c = m.coords + dim * vert_of[i];
+      pts[i] = V3{c[0], c[1], dim == 3 ? c[2] : 0.0};
+    }
+    vord = locality_order(nd, gp, gc, pts);
+  } else {
+    std::iota(vord.begin(), vord.end(), 0);
+  }
+  pat = Triplets();
+  std::vector<int64_t> ord(n);
+  for (int64_t i = 0; i < nd; ++i) {
+    ord[2 * i] = 2 * vord[i];
+    ord[2 * i + 1] = 2 * vord[i] + 1;
+  }
+  out->placement = IFL_VERTEX_VECTOR;
+  out->order = order;
+  out->n = n;
+  out->n_components = 2;
+  out->field_len = 2 * m.n_vertices;
+  permute_csr(n, ord, np, ncol, nv, out->row_ptr, out->col, out->val);
+  out->mass.resize(n);
+  out->entity.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    out->mass[i] = mass2[ord[i]];
+    out->entity[i] = 2 * vert_of[ord[i] / 2] + ord[i] % 2;
+  }
+  // projection, dofs in row order
+  std::vector<int64_t> cnt(nd + 1, 0);
+  for (int64_t t = 0; t < m.n_triangles; ++t)
+    if (act[t])
+      for (int k = 0; k < 3; ++k) cnt[dof_of[m.triangles[3 * t + k]] + 1]++;
+  for (int64_t i = 0; i < nd; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int32_t> inc(cnt[nd]);
+  {
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t t = 0; t < m.n_triangles; ++t)
+      if (act[t])
+        for (int k = 0; k < 3; ++k) inc[fill[dof_of[m.triangles[3 * t + k]]]++] = (int32_t)t;
+  }
+  out->n_cells = m.n_triangles;
+  out->proj_ptr.assign(nd + 1, 0);
+  out->proj_tri.clear();
+  out->proj_w.clear();
+  for (int64_t i = 0; i < nd; ++i) {
+    const int64_t d = vord[i];
+    for (int64_t e = cnt[d]; e < cnt[d + 1]; ++e) {
+      out->proj_tri.push_back(inc[e]);
+      out->proj_w.push_back(tri_w[inc[e]] / mass[d]);
+    }
+    out->proj_ptr[i + 1] = (int64_t)out->proj_tri.size();
+  }
+  return IFL_OK;
+}
+
 // Scalars at triangle circumcentres (Eq. 6): dofs are the active triangles,
 // mass their (flat-facet) areas, and a pair of active triangles sharing an
 // edge of length l is coupled with weight l / d, d the distance between
@@ -741,7 +895,7 @@ ifl_status build_operator(const ifl_mesh& mesh, int32_t placement, int32_t order
   } else if (placement == IFL_CIRCUMCENTER_SCALAR) {
     st = build_circumcenter_scalar(mesh, order, reorder, out);
   } else if (placement == IFL_VERTEX_VECTOR) {
-    return fail(IFL_EUNSUPPORTED, "vertex vectors (the FE vector Laplacian with the metric term T) are not implemented");
+    st = build_vertex_vector(mesh, order, reorder, out);
   } else {
     return fail(IFL_EINVAL, "unknown placement");
   }

@@ -47,6 +47,10 @@ def test_default_options():
     assert abs(o.cell_A - np.sqrt(3)) < 1e-15 and o.reorder == 1 and o.device == 0
 
 
+def lib_num_cells(h):
+    return int(ifl.lib().ifl_num_cells(h._h))
+
+
 def _host_handle(mesh, placement=ifl.IFL_VERTEX_SCALAR, n=1, **kw):
     return ifl.prepare_mesh(mesh, placement, n, device=-1, **kw)
 
@@ -55,7 +59,9 @@ def _to_oracle_numbering(h, op_or):
     """Library CSR (internal order) -> scipy matrix in the oracle's dof order."""
     rp, col, val, mass, ent = h.export_operator()
     n = rp.size - 1
-    if hasattr(op_or, "verts"):
+    if hasattr(op_or, "Rvc"):  # vectors on vertices, interleaved (east, north)
+        dof = 2 * op_or.dof_of[ent // 2] + ent % 2
+    elif hasattr(op_or, "verts"):
         dof = op_or.dof_of[ent]
     elif op_or.A.size == op_or.cells.size:  # scalars on cells
         cell_dof = np.full(op_or.n_cells_total, -1)
@@ -109,6 +115,25 @@ def test_prepare_matches_oracle_cell_vector(order):
     assert h.field_length == 2 * s.n_triangles
     assert abs(K - vo.Kn).max() <= 1e-13 * abs(vo.Kn).max()
     assert np.max(np.abs(M - vo.A) / vo.A) < 1e-14
+    h.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("name,mesh", list(_meshes()))
+def test_prepare_matches_oracle_vertex_vector(name, mesh, order):
+    """Vertex FE vector Laplacian with metric terms (Sect. 2.1.2): the
+    library's D_2 (order n) and mass equal the oracle's, bitwise symmetric."""
+    _lib_or_skip()
+    h = _host_handle(mesh, ifl.IFL_VERTEX_VECTOR, order)
+    op = O.vertex_vector_operator(mesh, order)
+    K, M, rp, col, val = _to_oracle_numbering(h, op)
+    assert h.num_dofs == op.A.size and h.field_length == 2 * mesh.n_vertices
+    assert abs(K - op.Kn).max() <= 1e-13 * abs(op.Kn).max()
+    assert np.max(np.abs(M - op.A) / op.A) < 1e-14
+    n = rp.size - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    Kl = sp.coo_matrix((val, (rows, col)), shape=(n, n)).tocsr()
+    assert (Kl != Kl.T).nnz == 0
     h.close()
 
 
@@ -253,10 +278,9 @@ def test_prepare_errors():
     with pytest.raises(ifl.IflError) as e:
         ifl.ifl_prepare(c, m.tris, m.geometry, period=m.period, device=-1)
     assert e.value.status == ifl.IFL_EINVAL
-    for placement in (ifl.IFL_VERTEX_VECTOR,):
-        with pytest.raises(ifl.IflError) as e:
-            ifl.prepare_mesh(m, placement, 1, device=-1)
-        assert e.value.status == ifl.IFL_EUNSUPPORTED
+    with pytest.raises(ifl.IflError) as e:
+        ifl.prepare_mesh(m, 7, 1, device=-1)
+    assert e.value.status == ifl.IFL_EINVAL
     with pytest.raises(ifl.IflError) as e:
         ifl.prepare_mesh(m, ifl.IFL_VERTEX_SCALAR, 5, device=-1)
     assert e.value.status == ifl.IFL_EUNSUPPORTED
@@ -282,7 +306,28 @@ def test_host_only_handle_refuses_solves():
     h.close()
 
 
-@pytest.mark.parametrize("placement", [0, 2, 3])
+def test_project_cells_errors():
+    """ifl_project_cells: IFL_EINVAL for a handle of another placement or a
+    NULL pointer, IFL_EDEVICE for a host-only handle (checked before any
+    pointer is read)."""
+    _lib_or_skip()
+    s = W.icosphere(2, jitter=0.1)
+    buf = np.zeros(2 * s.n_triangles)
+    hv = _host_handle(s, ifl.IFL_VERTEX_VECTOR)
+    hs = _host_handle(s)
+    assert lib_num_cells(hv) == s.n_triangles and lib_num_cells(hs) == 0
+    assert hv.field_length == 2 * s.n_vertices
+    L = ifl.lib()
+    assert L.ifl_project_cells(hs._h, buf.ctypes.data, buf.ctypes.data) == ifl.IFL_EINVAL
+    assert L.ifl_project_cells(hv._h, None, buf.ctypes.data) == ifl.IFL_EINVAL
+    assert L.ifl_project_cells(hv._h, buf.ctypes.data, buf.ctypes.data) == ifl.IFL_EDEVICE
+    with pytest.raises(ValueError):
+        hs.project_cells(buf)
+    hv.close()
+    hs.close()
+
+
+@pytest.mark.parametrize("placement", [0, 2, 3, 4])
 def test_save_load_roundtrip(tmp_path, placement):
     _lib_or_skip()
     s = W.icosphere(3, jitter=0.1)
@@ -295,6 +340,13 @@ def test_save_load_roundtrip(tmp_path, placement):
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
     assert h2.field_length == h.field_length
+    assert lib_num_cells(h2) == lib_num_cells(h) == (s.n_triangles if placement == 4 else 0)
+    if placement == 4:  # a file cut inside the projection arrays
+        size = __import__("os").path.getsize(p)
+        open(p, "r+b").truncate(size - 8)
+        with pytest.raises(ifl.IflError) as e:
+            ifl.ifl_load(p, device=-1)
+        assert e.value.status == ifl.IFL_EIO
     open(p, "r+b").truncate(100)
     with pytest.raises(ifl.IflError) as e:
         ifl.ifl_load(p, device=-1)
