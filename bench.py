@@ -14,8 +14,11 @@ traffic from the committed rocprofv3 profile; a plain 1 GiB device copy
 timed in the same run), and, outside the timed steps: the plain FP64
 one-column-at-a-time path on a subset of the fields, SpMV rates on the
 unmasked level-9 mesh (single column FP64 / FP32, n = 1 and 2; 32 batched
-columns), the continuous-batching server under two Poisson streams (200
-requests/s, and 15 requests/s below capacity), and the FP64 CPU oracle on a
+columns), velocity filtering on the level-8 sphere (the vertex FE vector
+Laplacian fed by the cell -> vertex projection, and the cell-vector
+operator of Eq. 7), the continuous-batching server under two Poisson
+streams (200 requests/s, and 15 requests/s below capacity), and the FP64
+CPU oracle on a
 bounded sample of the same workload together with the GPU's error on it.
 """
 from __future__ import annotations
@@ -172,6 +175,62 @@ def spmv_leg(ifl):
     return res
 
 
+def vector_leg(ifl):
+    """Velocity filtering on the level-8 sphere (655,362 vertices,
+    1,310,720 triangles; 30% land and dry polar caps, where lon/lat
+    components are singular): 8 k^-3 velocity fields (rotational + 10%
+    divergent) x 8 scales (wavelengths 32h .. 2h), n = 1, mixed precision,
+    auto-width tiles, one ifl_filter call. Vertex vectors (Sect. 2.1.2) take
+    the cell velocities through ifl_project_cells (timed on its own); cell
+    vectors (Eq. 7) filter them in place. Fields are resident in HBM."""
+    import torch
+
+    import workloads as W
+
+    s = W.icosphere(8, jitter=0.1, seed=1)
+    wet = np.array(W.land_mask(s, 0.3, n_blobs=40, seed=2), dtype=np.uint8)
+    wet[np.abs(s.coords[:, 2] / s.radius) > math.sin(math.radians(80))] = 0
+    s = s.with_mask(wet)
+    nf = 8
+    cells = torch.stack([torch.from_numpy(np.asarray(W.sphere_k3_velocity(s, 100 + i, 200 + i, n_waves=256,
+                                                                          device="cuda:0")).reshape(-1))
+                         for i in range(nf)]).to("cuda:0")
+    ks = W.log_scales(s.h, 8)
+    res = {"vertices": s.n_vertices, "triangles": s.n_triangles, "fields": nf, "scales": int(ks.size)}
+    for placement, name in ((ifl.IFL_VERTEX_VECTOR, "vertex_vector"), (ifl.IFL_CELL_VECTOR, "cell_vector")):
+        t0 = time.time()
+        h = ifl.prepare_mesh(s, placement, 1, precision=ifl.IFL_MIXED, device=0)
+        prep = time.time() - t0
+        L = h.field_length
+        fields = torch.empty((nf, L), dtype=torch.float64, device="cuda:0")
+        proj_ms = None
+        if placement == ifl.IFL_VERTEX_VECTOR:
+            h.project_cells(cells[0], out=fields[0])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for i in range(nf):
+                h.project_cells(cells[i], out=fields[i])
+            torch.cuda.synchronize()
+            proj_ms = (time.perf_counter() - t) / nf * 1e3
+        else:
+            fields.copy_(cells)
+        dst = torch.empty((nf, ks.size, L), dtype=torch.float64, device="cuda:0")
+        h.filter(fields[:1], ks[:1], out=dst[:1, :1])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = h.filter(fields, ks, out=dst)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        res[name] = {"solves_per_s": round(nf * ks.size / el, 2), "unknowns": h.num_dofs,
+                     "mean_cg_iterations": round(sum(x.iterations for x in st) / len(st), 1),
+                     "prepare_s": round(prep, 1)}
+        if proj_ms is not None:
+            res[name]["project_cells_ms"] = round(proj_ms, 3)
+        h.close()
+        del fields, dst
+    return res
+
+
 def serve_leg(args, ifl):
     """Continuous-batching server on resident prepared meshes, fed by a
     Poisson arrival stream; returns latency percentiles and solves/s."""
@@ -279,6 +338,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip ifl_autotune (default tile and grids)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-spmv-leg", action="store_true", help="skip the SpMV rates on the unmasked level-9 mesh")
+    ap.add_argument("--no-vector-leg", action="store_true", help="skip the velocity filtering on the level-8 mesh")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured chunks")
     ap.add_argument("--serve-levels", default="6,7,8,9",
@@ -452,6 +512,13 @@ def main():
         except ifl.IflError as e:
             res["spmv_2.6M_vertices"] = {"error": str(e)}
         log(f"spmv: {res['spmv_2.6M_vertices']}")
+    if not args.no_vector_leg:
+        log("velocity leg on the level-8 mesh ...")
+        try:
+            res["velocity_level8"] = vector_leg(ifl)
+        except ifl.IflError as e:
+            res["velocity_level8"] = {"error": str(e)}
+        log(f"velocity: {res['velocity_level8']}")
     if not args.no_serve:
         log("serving leg ...")
         try:

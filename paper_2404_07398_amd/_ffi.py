@@ -424,17 +424,24 @@ class Server:
         self._s = C.c_void_p()
         _check(lib().ifl_server_create(int(hbm_budget_bytes), int(slots), C.byref(self._s)))
         self._keep = {}
+        self._len = {}
 
     def add(self, h: Handle) -> int:
         mid = C.c_int32()
         _check(lib().ifl_server_add(self._s, h.ptr, C.byref(mid)))
+        self._len[int(mid.value)] = h.field_length
         return int(mid.value)
 
     def submit(self, mesh_id: int, field: np.ndarray, ks, out: np.ndarray | None = None):
         field = np.ascontiguousarray(field, dtype=np.float64)
         ks = np.ascontiguousarray(ks, dtype=np.float64)
+        L = self._len.get(int(mesh_id))
+        if L is not None and field.size != L:
+            raise ValueError(f"field has {field.size} entries, the mesh's fields have {L}")
         if out is None:
             out = np.zeros((ks.size, field.size))
+        elif out.size != ks.size * field.size or out.dtype != np.float64 or not out.flags.c_contiguous:
+            raise ValueError("out must be a C-contiguous float64 array of n_scales x field length")
         t = C.c_void_p()
         _check(lib().ifl_submit(self._s, int(mesh_id), C.c_void_p(field.ctypes.data), ks.size, _dptr(ks),
                                 C.c_void_p(out.ctypes.data), C.byref(t)))

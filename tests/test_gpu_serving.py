@@ -100,6 +100,52 @@ def test_served_results_match_oracle_and_alone(ifl):
         h.close()
 
 
+def test_server_vertex_vectors_and_order4(ifl):
+    """Handles of other placements and orders share one server: vertex
+    velocities (Sect. 2.1.2, fields from ifl_project_cells) on a sphere with
+    dry polar caps, and the order-4 scalar filter at wavelengths <= 8h.
+    Each result matches the oracle within the mixed-precision bar and equals
+    the same request served alone, bitwise."""
+    s = W.icosphere(4, jitter=0.1)
+    wet = np.array(W.land_mask(s, 0.3), dtype=np.uint8)
+    wet[np.abs(s.coords[:, 2] / s.radius) > np.sin(np.radians(80))] = 0
+    s = s.with_mask(wet)
+    hv = ifl.prepare_mesh(s, ifl.IFL_VERTEX_VECTOR, 1, precision=ifl.IFL_MIXED)
+    h4 = ifl.prepare_mesh(s, ifl.IFL_VERTEX_SCALAR, 4, precision=ifl.IFL_MIXED)
+    ov = O.vertex_vector_operator(s, 1)
+    o4 = O.scalar_operator(s, 4)
+    rng = np.random.default_rng(3)
+    reqs = []
+    for r in range(10):
+        vec = r % 2 == 0
+        lam_max = 32.0 if vec else 8.0
+        ks = np.sort(np.exp(rng.uniform(np.log(2 * np.pi / (lam_max * s.h)), np.log(2 * np.pi / (2 * s.h)),
+                                        int(rng.integers(1, 5)))))
+        if vec:
+            u = W.sphere_k3_velocity(s, 600 + r, 700 + r, n_waves=64)
+            reqs.append((0, u, hv.project_cells(u), ks))
+        else:
+            f = W.sphere_k3_field(s, 800 + r, n_waves=64)
+            reqs.append((1, f, f, ks))
+    srv = ifl.Server(2 << 30, slots=8)
+    ids = [srv.add(hv), srv.add(h4)]
+    tickets = [srv.submit(ids[mi], field, ks) for (mi, _, field, ks) in reqs]
+    for r, ((t, _), (mi, src, field, ks)) in enumerate(zip(tickets, reqs)):
+        st, stats, o, lat = srv.wait(t, len(ks))
+        assert st == 0, st
+        ref = (O.filter_vertex_vector(ov, src, ks).reshape(len(ks), -1) if mi == 0
+               else O.filter_scalar(o4, src, ks))
+        for j in range(len(ks)):
+            assert relative_l2(o[j], ref[j]) <= 1e-9, (r, j)
+        if r in (0, 3):
+            t2, _ = srv.submit(ids[mi], field, ks)
+            st2, _, o2, _ = srv.wait(t2, len(ks))
+            assert st2 == 0 and np.array_equal(o2, o), r
+    srv.close()
+    hv.close()
+    h4.close()
+
+
 def test_server_errors(ifl):
     m = W.split_square(16, jitter=0.1)
     h = ifl.prepare_mesh(m, 0, 1, precision=ifl.IFL_MIXED)
@@ -111,6 +157,8 @@ def test_server_errors(ifl):
     with pytest.raises(ifl.IflError) as e:
         srv.submit(mid, bad, [0.5])
     assert e.value.status == ifl.IFL_EINVAL
+    with pytest.raises(ValueError):
+        srv.submit(mid, f[:-1], [0.5])
     with pytest.raises(ifl.IflError) as e:
         srv.submit(mid + 5, f, [0.5])
     assert e.value.status == ifl.IFL_EINVAL
