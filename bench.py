@@ -133,9 +133,10 @@ def cpu_baseline(mesh, fields, ks, budget_s: float = 20.0, gpu_column=None):
 
 def spmv_leg(ifl):
     """SpMV rates on the unmasked level-9 icosphere (2,621,442 vertices, all
-    of them dofs): the single-column kernels in FP64 and FP32 for n = 1 and
-    n = 2, and the batched kernel (32 mixed columns) for n = 1. Each figure
-    is algorithmic bytes per launch over the HIP-event time of the launch."""
+    of them dofs): the single-column kernels in FP64 and FP32 for n = 1, 2
+    and 4 (K_4: up to 61 entries a row), and the batched kernel (32 mixed
+    columns) for n = 1. Each figure is algorithmic bytes per launch over the
+    HIP-event time of the launch."""
     import torch
 
     import workloads as W
@@ -155,14 +156,15 @@ def spmv_leg(ifl):
         n, ms, b = h.profile_read(reset=True)
         us = ms / max(n, 1) * 1e3
         return {"kernel": h.profile_kernel(), "mean_launch_us": round(us, 2), "bytes_per_launch": round(b),
-                "GBs": round(b / (us * 1e3), 1) if n else None, "launches": n,
+                "GBs": round(b / (us * 1e3), 1) if n else None,
+                "frac_of_hbm_peak": round(b / (us * 1e3) / HBM_PEAK_GBS, 4) if n else None, "launches": n,
                 "mean_cg_iterations": round(sum(x.iterations for x in st) / len(st), 1)}
 
-    for n in (1, 2):
+    for n in (1, 2, 4):
         t0 = time.time()
         h = ifl.prepare_mesh(s, ifl.IFL_VERTEX_SCALAR, n, precision=ifl.IFL_FP64, batch=1, device=0, profile=1)
         res[f"n{n}_prepare_s"] = round(time.time() - t0, 1)
-        kk = ks if n == 1 else ks[2:]  # n = 2: the smaller scales keep the iteration count modest
+        kk = ks if n == 1 else ks[2:]  # n = 2, 4: the smaller scales keep the iteration count modest
         for prec, name in ((ifl.IFL_FP64, "fp64"), (ifl.IFL_MIXED, "fp32")):
             h.set_options(precision=prec, batch=1)
             res[f"n{n}_{name}_single_column"] = timed(h, phi, kk)
@@ -201,6 +203,7 @@ def vector_leg(ifl):
         t0 = time.time()
         h = ifl.prepare_mesh(s, placement, 1, precision=ifl.IFL_MIXED, device=0)
         prep = time.time() - t0
+        h.set_options(profile=0)
         L = h.field_length
         fields = torch.empty((nf, L), dtype=torch.float64, device="cuda:0")
         proj_ms = None
@@ -224,6 +227,20 @@ def vector_leg(ifl):
         res[name] = {"solves_per_s": round(nf * ks.size / el, 2), "unknowns": h.num_dofs,
                      "mean_cg_iterations": round(sum(x.iterations for x in st) / len(st), 1),
                      "prepare_s": round(prep, 1)}
+        # the same call again with HIP events around the tile's SpMV launches
+        # (not timed above): algorithmic bytes per launch / mean launch time
+        h.set_options(profile=1)
+        h.profile_read(reset=True)
+        h.filter(fields, ks, out=dst)
+        nl, ms, b = h.profile_read(reset=True)
+        h.set_options(profile=0)
+        if nl:
+            us = ms / nl * 1e3
+            gbs = b / (us * 1e3)
+            res[name]["roofline"] = {"bound": "hbm", "kernel": h.profile_kernel(), "launches": nl,
+                                     "mean_launch_us": round(us, 2), "bytes_per_launch": round(b),
+                                     "achieved_GBs": round(gbs, 1), "peak_GBs": HBM_PEAK_GBS,
+                                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
         if proj_ms is not None:
             res[name]["project_cells_ms"] = round(proj_ms, 3)
         h.close()
@@ -339,6 +356,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-spmv-leg", action="store_true", help="skip the SpMV rates on the unmasked level-9 mesh")
     ap.add_argument("--no-vector-leg", action="store_true", help="skip the velocity filtering on the level-8 mesh")
+    ap.add_argument("--leg", choices=["velocity", "spmv"], default=None,
+                    help="run only this leg and print its JSON (for profiling one leg on its own)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured chunks")
     ap.add_argument("--serve-levels", default="6,7,8,9",
@@ -365,6 +384,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
+    if args.leg is not None:
+        res = vector_leg(ifl) if args.leg == "velocity" else spmv_leg(ifl)
+        print(json.dumps({"leg": args.leg, **res}), flush=True)
+        return
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device=dev)

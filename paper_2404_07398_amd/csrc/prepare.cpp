@@ -550,9 +550,11 @@ ifl_status build_vertex_vector(const ifl_mesh& m, int32_t order, int32_t reorder
         const double dij = dot(e[i], e[j]) * inv + w0 * (i == j ? 2.0 : 1.0);
         tr.add(2 * d[i], 2 * d[j], dij);
         tr.add(2 * d[i] + 1, 2 * d[j] + 1, dij);
-        const double tij = mt * (dx[j] - dx[i]);
-        tr.add(2 * d[i], 2 * d[j] + 1, tij);
-        tr.add(2 * d[i] + 1, 2 * d[j], -tij);
+        if (i != j) {  // T_vv = 0: no east-north entry of a dof with itself
+          const double tij = mt * (dx[j] - dx[i]);
+          tr.add(2 * d[i], 2 * d[j] + 1, tij);
+          tr.add(2 * d[i] + 1, 2 * d[j], -tij);
+        }
         pat.add(d[i], d[j], 1.0);
       }
       mass[d[i]] += twoA / 6.0;
