@@ -169,6 +169,35 @@ def test_vertex_vector(ifl, n, precision, batch):
     h.close()
 
 
+def test_vertex_vector_planar_equals_scalar_and_spectrum(ifl):
+    """On a planar mesh m = 0 and 1/R_e^2 = 0, so the vertex vector filter is
+    the scalar filter of Sect. 2.1.1 applied to each component: checked
+    library against library (FP64, n = 2, periodic 64 x 64 split square).
+    ifl_spectrum on the vertex-vector handle equals the oracle's energies
+    of its filtered velocities."""
+    m = W.split_square(64, jitter=0.2)
+    u = W.planar_k3_velocity(m, 5, 6)
+    ks = W.log_scales(1.0, 6)
+    hv = _prep(ifl, m, placement=ifl.IFL_VERTEX_VECTOR, n=2, precision=0, batch=1)
+    hs = _prep(ifl, m, n=2, precision=0, batch=1)
+    f = hv.project_cells(u)
+    ov, _ = hv.filter(f, ks)
+    osc, _ = hs.filter(np.stack([f[0::2], f[1::2]]), ks)
+    for j in range(len(ks)):
+        for comp in range(2):
+            err = relative_l2(ov[0, j][comp::2], osc[comp, j])
+            print(f"planar vertex-vector vs scalar j={j} comp={comp} diff={err:.2e}")
+            assert err <= TOL_FP64
+    op = O.vertex_vector_operator(m, 2)
+    ref = O.filter_vertex_vector(op, u, ks)
+    E_ref = np.array([O.energy(op.A, ref[j][op.verts].ravel()) for j in range(len(ks))])
+    E, d, km = hv.spectrum(f, ks)
+    print(f"vertex-vector spectrum max rel err {np.max(np.abs(E / E_ref - 1)):.2e}")
+    assert np.max(np.abs(E / E_ref - 1)) <= 10 * TOL_FP64
+    hv.close()
+    hs.close()
+
+
 def test_vertex_vector_projection_device_and_loaded(ifl, tmp_path):
     """ifl_project_cells with device pointers equals the host call bitwise,
     and a saved and loaded handle projects and filters the same."""
