@@ -86,7 +86,9 @@ typedef struct ifl_mesh {
 typedef struct ifl_options {
   double gamma;      /* filter parameter (Sect. 2.1: 1/2); default 0.5 */
   double rtol;       /* stop when ||M phi - S x||_2 <= rtol * ||M phi||_2; default 1e-12 */
-  int32_t max_iter;  /* CG iteration cap per solve; default 20000 */
+  int32_t max_iter;  /* CG iteration cap per solve; default 20000. Tiles (batch != 1) test their
+                        columns at the end of each 4-iteration chunk, on an FP64 true residual, so
+                        there the cap and the iteration counts are rounded up to a multiple of 4 */
   int32_t precision; /* IFL_FP64 (default) or IFL_MIXED */
   double cell_A;     /* stencil constant A of Eq. 7; default sqrt(3) */
   int32_t device;    /* HIP device ordinal; default 0. -1 = host-only handle: prepare,
@@ -105,7 +107,7 @@ typedef struct ifl_options {
 /* Per-solve statistics (one per field x scale). */
 typedef struct ifl_solve_stats {
   int32_t iterations;   /* CG iterations */
-  int32_t refinements;  /* FP64 residual replacements (IFL_MIXED) */
+  int32_t refinements;  /* FP64 residual replacements (IFL_MIXED, and tiles of either precision) */
   int32_t status;       /* IFL_OK or IFL_ENOTCONV */
   int32_t reserved;
   double rel_residual;  /* final ||M phi - S x|| / ||M phi||, FP64 on the GPU */

@@ -10,7 +10,8 @@
 namespace ifl {
 
 // A batched tile advances in chunks of kChunk CG iterations: x is updated
-// and (mixed tiles) the FP64 residual replaced at the end of each chunk,
+// and the FP64 residual replaced at the end of each chunk (where alone a
+// column may stop),
 // columns enter only at chunk boundaries, and the host advances a tile by
 // whole chunks.
 constexpr int kChunk = 4;
@@ -23,15 +24,15 @@ struct BSlot {
   double rr;        // current ||r||^2 (recursive, or FP64 true after a replacement)
   double tol2;      // rtol^2 ||M phi||^2
   double bb;        // ||M phi||^2
-  double res2;      // final true ||M phi - S x||^2 (mixed: of the last replacement)
+  double res2;      // final true ||M phi - S x||^2 (that of the last replacement)
   double energy2;   // final sum M x^2
   double pad0;
   double alpha_hist[kChunk];  // alpha of each iteration of the current chunk (0 if not iterating)
   int32_t active;   // slot holds a column
   int32_t done;     // 0 running, 1 converged, 2 breakdown, 3 max_iter
   int32_t iters;    // CG iterations of this column
-  int32_t updates;  // mixed: FP64 residual replacements
-  int32_t rr_true;  // mixed: rr is an FP64 true residual
+  int32_t updates;  // FP64 residual replacements
+  int32_t rr_true;  // rr is an FP64 true residual
   int32_t pad1;
 };
 
@@ -121,8 +122,8 @@ ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const 
                       hipStream_t s);
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s);
 // Write x of the columns in 'mask' to out[slot] (caller numbering, every
-// entry: 0 where there is no dof) and compute their energy (and, FP64 tiles,
-// true residual) into the slot state.
+// entry: 0 where there is no dof) and compute their energy into the slot
+// state (their true residual is that of the last replacement).
 ifl_status batch_finish(const BatchMatrix& bm, BatchWork& w, uint64_t mask, double* const* out, hipStream_t s);
 ifl_status batch_read_slots(BatchWork& w, hipStream_t s);
 // Move n running columns (slots from[c] of src -> to[c] of dst, a tile of

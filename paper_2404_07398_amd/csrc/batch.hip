@@ -20,9 +20,10 @@
 // chunk only z (the preconditioned residual) and p change; the directions
 // of the chunk are kept in kChunk buffers and x is updated once, at the
 // chunk's last iteration (in FP64, in every precision), from them and each
-// column's alpha history. Mixed tiles then replace every running column's
-// residual by its FP64 true residual, in one pass for the whole tile; a
-// mixed column stops only on such a replaced residual. A column's
+// column's alpha history. Every running column's residual is then replaced
+// by its FP64 true residual, in one pass for the whole tile, and a column
+// stops only on such a replaced residual (in FP64 tiles as well: a recursive
+// residual drifts from the true one when S is badly conditioned). A column's
 // arithmetic and reduction order depend neither on the other columns, nor
 // on its slot, nor on when it entered, so a solve gives bitwise the same
 // result alone or in a full tile.
@@ -57,7 +58,7 @@ constexpr int kUnroll = 8;        // sliced-ELL entries loaded together per row
 constexpr double kU = 1.1102230246251565e-16;
 constexpr double kFloor = 8.0;
 
-enum { Q_PQ = 0, Q_RZ, Q_RR, Q_BB, Q_FL, Q_RES, Q_EN, Q_COUNT };
+enum { Q_PQ = 0, Q_RZ, Q_RR, Q_BB, Q_FL, Q_EN, Q_COUNT };
 
 // Lane geometry of a tile of R columns of type T.
 template <typename T, int R>
@@ -407,15 +408,15 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
 // chunk (XUP) the chunk's x update is applied at once, in FP64 in every
 // precision, from the directions kept in p[0..3] and each column's alpha
 // history: x += sum_k alpha_k p_k. z of columns that are not iterating is
-// left unchanged. A mixed tile replaces every running column's residual right
-// after its chunk's x update, so there the last iteration updates x only (no
-// z, no partials).
-template <typename T, bool MIXED, bool XUP, int R>
+// left unchanged. Every running column's residual is replaced right after
+// its chunk's x update, so the last iteration updates x only (no z, no
+// partials).
+template <typename T, bool XUP, int R>
 __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
                                                 int k) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
-  constexpr bool ZUP = !(MIXED && XUP);
+  constexpr bool ZUP = !XUP;
   __shared__ double lds[2 * kWpb * R];
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
@@ -491,7 +492,7 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
 // the partials of (r, z), (r, r) and ||M phi||^2. Other columns' vectors are
 // left unchanged.
 //
-// REPLACE (mixed tiles, at the end of every chunk, after its x update): the
+// REPLACE (at the end of every chunk, after its x update): the
 // residual of every running column is replaced by its FP64 true residual
 // r = M phi - S x (FP64 values and x), z = r / diag(S), with the partials of
 // (r, z), (r, r) and of the attainable-accuracy norm
@@ -654,69 +655,45 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
   }
 }
 
-// End of a column: partials of sum M x^2 and (RESID) of the true residual
-// ||M phi - S x||^2 (kb_out writes x out). Mixed tiles skip the residual:
-// their columns stop right after a replacement, whose FP64 true residual is
-// that of this very x.
-template <typename T, int R, bool RESID>
+// End of a column: partials of sum M x^2 (kb_out writes x out). A column
+// stops right after a replacement, whose FP64 true residual is that of this
+// very x, so no residual is formed here.
+template <typename T, int R>
 __global__ __launch_bounds__(kB) void kb_finish(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
                                                 uint64_t mask) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
-  __shared__ double lds[2 * kWpb * R];
+  __shared__ double lds[1 * kWpb * R];
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
   bool on[C];
-  double cc[C];
   bool any = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     on[c] = ((mask >> (j0 + c)) & 1ull) != 0;
-    cc[c] = slots[j0 + c].c;
     any |= on[c];
   }
   // at a chunk boundary x holds the whole solution (the chunk's x update
   // has run)
-  double acc[2][C] = {};
+  double acc[1][C] = {};
   if (any) {
     for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
       const int64_t row = wk.t * RPW + rsub;
       if (row >= m.n) continue;
-      const int64_t s = row / kW, l = row % kW;
-      const int64_t base = m.sptr[s];
-      const int w = (int)((m.sptr[s + 1] - base) / kW);
-      double a[C] = {};
-      if constexpr (RESID)
-        for (int k = 0; k < w; ++k) {
-          const int64_t e = base + (int64_t)k * kW + l;
-          const int64_t off = (int64_t)m.col[e] * R + j0;
-          const double vv = m.val64[e];
-          const Pack<double, C> xj = vload<double, C>(v.x + off);
-#pragma unroll
-          for (int c = 0; c < C; ++c) a[c] += vv * xj.v[c];
-        }
       const int64_t idx = row * R + j0;
-      const Pack<double, C> xv = vload<double, C>(v.x + idx), ph = vload<double, C>(v.phi + idx);
-      const double mi = m.mass[row], kd = m.kdiag[row];
+      const Pack<double, C> xv = vload<double, C>(v.x + idx);
+      const double mi = m.mass[row];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         if (!on[c]) continue;
         const double xi = xv.v[c];
-        if constexpr (RESID) {
-          const double r64 = mi * (ph.v[c] - xi) - cc[c] * (kd * xi + a[c]);
-          acc[0][c] += r64 * r64;
-        }
-        acc[1][c] += mi * xi * xi;
+        acc[0][c] += mi * xi * xi;
       }
     }
   }
-  double tot[2];
-  col_sum<R, C, 2>(acc, lds, tot);
-  if (threadIdx.x < R) {
-    const int lb = lblock(G);
-    part[(Q_RES * R + threadIdx.x) * Gp + lb] = tot[0];
-    part[(Q_EN * R + threadIdx.x) * Gp + lb] = tot[1];
-  }
+  double tot[1];
+  col_sum<R, C, 1>(acc, lds, tot);
+  if (threadIdx.x < R) part[(Q_EN * R + threadIdx.x) * Gp + lblock(G)] = tot[0];
 }
 
 // x of the columns in 'mask' to the caller's numbering, one caller entry per
@@ -898,10 +875,10 @@ __global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const doub
   }
 }
 
-// phase 2 (after kb_update): rho, beta and (FP64) the stopping test; a
-// mixed column is tested on its replaced FP64 residual only
-__global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const double* part, int G, int Gp, int R, int mixed,
-                                                        int max_iter) {
+// phase 2 (after kb_update, iterations 1..kChunk-1 of a chunk): rho and
+// beta; no stopping test (a column is tested on its replaced FP64 residual
+// only, in kf_replace)
+__global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const double* part, int G, int Gp, int R) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
@@ -914,17 +891,12 @@ __global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const doubl
     s.beta = rz / s.rho_prev;
     s.rr = rr;
     s.iters += 1;
-    if (!mixed) {
-      if (rr <= s.tol2) s.done = 1;
-      else if (s.iters >= max_iter) s.done = 3;
-    } else {
-      s.rr_true = 0;
-    }
+    s.rr_true = 0;
   }
 }
 
-// phase 2 of a mixed tile's last iteration in a chunk (after the x update and
-// the replacement pass): rho, beta from the replaced residual and the test
+// phase 2 of the last iteration in a chunk (after the x update and the
+// replacement pass): rho, beta from the replaced residual and the test
 __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const double* part, int G, int Gp, int R,
                                                            int max_iter) {
   __shared__ double lds[kFinThreads / kW];
@@ -984,15 +956,14 @@ __global__ void kf_release(BSlot* slots, int R, uint64_t mask) {
 }
 
 __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const double* part, int G, int Gp, int R,
-                                                          uint64_t mask, int mixed) {
+                                                          uint64_t mask) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   if (!((mask >> j) & 1ull)) return;
   BSlot& s = slots[j];
-  const double res = fin_sum(part + (Q_RES * R + j) * Gp, G, lds);
   const double en = fin_sum(part + (Q_EN * R + j) * Gp, G, lds);
   if (threadIdx.x == 0) {
-    s.res2 = mixed ? s.rr : res;  // mixed: the FP64 true residual of the last replacement
+    s.res2 = s.rr;  // the FP64 true residual of the last replacement
     s.energy2 = en;
   }
 }
@@ -1033,32 +1004,29 @@ struct Launch {
     else kb_dir_spmv<T, R, true><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k);
   }
   // iteration k (0..kChunk-1) of a chunk; the last one applies the
-  // chunk's x update and, for mixed tiles, the residual
-  // replacement of every running column
+  // chunk's x update and the FP64 residual replacement of every running
+  // column, whose true residual is the only one that may stop a column (in
+  // both precisions: a recursive residual drifts from the true one when S
+  // is badly conditioned)
+  template <typename T>
+  static void update(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k) {
+    if (k == kChunk - 1) {
+      kb_update<T, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.Gu, g.Gp, k);
+      kb_residual<T, R, false><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, 0ull, SlotScales{});
+      kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
+    } else {
+      kb_update<T, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.Gu, g.Gp, k);
+      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R);
+    }
+  }
   static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k) {
-    const bool last = k == kChunk - 1;
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
     if (w.mixed) dir_spmv<float>(m, w, g, s, k);
     else dir_spmv<double>(m, w, g, s, k);
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
     kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
-    if (w.mixed) {
-      if (last) {
-        kb_update<float, true, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, k);
-        kb_residual<float, R, false><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, 0ull,
-                                                        SlotScales{});
-        kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
-      } else {
-        kb_update<float, true, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.Gu, g.Gp, k);
-        kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R, 1, prm.max_iter);
-      }
-    } else {
-      if (last)
-        kb_update<double, false, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.Gu, g.Gp, k);
-      else
-        kb_update<double, false, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.Gu, g.Gp, k);
-      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R, 0, prm.max_iter);
-    }
+    if (w.mixed) update<float>(m, w, g, s, prm, k);
+    else update<double>(m, w, g, s, prm, k);
   }
   static void init(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs,
                    double rtol) {
@@ -1068,8 +1036,8 @@ struct Launch {
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
   }
   static void finish(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const OutPtrs& out) {
-    if (w.mixed) kb_finish<float, R, false><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask);
-    else kb_finish<double, R, true><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask);
+    if (w.mixed) kb_finish<float, R><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask);
+    else kb_finish<double, R><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask);
     bool any_out = false;
     for (int j = 0; j < R; ++j) any_out |= ((mask >> j) & 1ull) && out.p[j];
     if (any_out) {
@@ -1078,7 +1046,7 @@ struct Launch {
         if (((mask >> j) & 1ull) && out.p[j]) omask |= 1ull << j;
       kb_out<R><<<(unsigned)((m.field_len + 255) / 256), 256, 0, s>>>(w.x, out, omask, m.row_of, m.field_len);
     }
-    kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, w.mixed ? 1 : 0);
+    kf_finish<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask);
   }
 };
 

@@ -637,14 +637,18 @@ def test_voronoi_and_circumcenter_placements(ifl, n, precision, batch):
     tile, against the oracle's operators on a masked level-5 sphere.
     Circumcentres are h / sqrt(3) apart, so at n = 2 the system for a
     wavelength of 32h is ~10x worse conditioned than the vertex one (1.5e6):
-    there the scales stop at 16h, where the FP64 solve's stopping test still
-    certifies the error bar."""
+    there the FP64 single-column solve, which stops on its recursive
+    residual, is run up to 16h only."""
     s, phi = _sphere(5, 0.3)
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     fields = {ifl.IFL_VORONOI_SCALAR: (phi, O.voronoi_operator(s, n)),
               ifl.IFL_CIRCUMCENTER_SCALAR: (phi[s.tris].mean(axis=1), O.circumcenter_operator(s, n))}
     for placement, (f, op) in fields.items():
-        lam_max = 16.0 if (placement == ifl.IFL_CIRCUMCENTER_SCALAR and n == 2) else 32.0
+        # the FP64 single-column solve stops on its recursive residual, which
+        # drifts at this conditioning; tiles and mixed precision stop on FP64
+        # true residuals
+        single64 = batch == 1 and precision == 0
+        lam_max = 16.0 if (placement == ifl.IFL_CIRCUMCENTER_SCALAR and n == 2 and single64) else 32.0
         ks = W.log_scales(s.h, 5, lam_max_cells=lam_max)
         ref = O.filter_scalar(op, f, ks)
         h = _prep(ifl, s, placement=placement, n=n, precision=precision, batch=batch)
@@ -677,8 +681,10 @@ def test_batched_edge_cases(ifl):
         h.filter(bad, ks)
     assert e.value.status == ifl.IFL_EINVAL
     h.close()
+    # tiles test their columns at chunk ends (every 4 iterations): max_iter 5
+    # stops them after the second chunk
     h = _prep(ifl, m, precision=0, batch=4, max_iter=5)
     out, st = h.filter(np.stack([phi, phi]), ks[:3], raise_on_notconv=False)
-    assert st[0].status == ifl.IFL_ENOTCONV and st[0].iterations == 5
+    assert st[0].status == ifl.IFL_ENOTCONV and st[0].iterations == 8
     assert np.all(np.isfinite(out))
     h.close()
