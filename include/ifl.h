@@ -353,6 +353,30 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* h, int32_t* mesh_id);
 ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field,
                       int32_t n_scales, const double* k, double* out, ifl_ticket** ticket);
 
+/*
+ * Memory accounting and request counters of a server (continuous batching
+ * with admission by device-memory footprint). The footprint of a request is
+ * its field copy on the device: 8 bytes per dof row, the dofs rounded up to
+ * a multiple of 64 (its columns run in the mesh's tile, whose work space is
+ * charged once, at ifl_server_add). A request is admitted when
+ * tiles + used + its footprint <= budget, or when nothing is in flight.
+ */
+typedef struct ifl_server_info {
+  size_t budget;          /* hbm_budget_bytes of ifl_server_create */
+  size_t tiles;           /* work space of the registered meshes' tiles */
+  size_t used;            /* footprint of the requests in flight now */
+  size_t peak_used;       /* largest 'used' so far */
+  int64_t submitted;      /* requests accepted by ifl_submit */
+  int64_t admitted;       /* requests that got device memory */
+  int64_t completed;      /* requests finished (any status) */
+  int64_t in_flight;      /* admitted and not finished */
+  int64_t peak_in_flight; /* largest 'in_flight' so far */
+  int64_t queued;         /* submitted, waiting for admission */
+} ifl_server_info;
+
+/* Fill *info (IFL_EINVAL on NULL arguments). Safe while requests run. */
+ifl_status ifl_server_query(ifl_server* s, ifl_server_info* info);
+
 /* Block until the request is done; fills stats[n_scales] (may be NULL) and
  * frees the ticket. Returns the request's status. */
 ifl_status ifl_wait(ifl_ticket* t, ifl_solve_stats* stats);

@@ -96,6 +96,21 @@ class ifl_tune(C.Structure):
     ]
 
 
+class ifl_server_info(C.Structure):
+    _fields_ = [
+        ("budget", C.c_size_t),
+        ("tiles", C.c_size_t),
+        ("used", C.c_size_t),
+        ("peak_used", C.c_size_t),
+        ("submitted", C.c_int64),
+        ("admitted", C.c_int64),
+        ("completed", C.c_int64),
+        ("in_flight", C.c_int64),
+        ("peak_in_flight", C.c_int64),
+        ("queued", C.c_int64),
+    ]
+
+
 class IflError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -137,6 +152,7 @@ _PROTOS = {
     "ifl_poll": (C.c_int32, [C.c_void_p]),
     "ifl_ticket_latency": (C.c_double, [C.c_void_p]),
     "ifl_server_destroy": (None, [C.c_void_p]),
+    "ifl_server_query": (C.c_int32, [C.c_void_p, C.POINTER(ifl_server_info)]),
 }
 
 EXPORTED = tuple(_PROTOS)
@@ -447,6 +463,12 @@ class Server:
                                 C.c_void_p(out.ctypes.data), C.byref(t)))
         self._keep[t.value] = (field, ks, out)
         return t, out
+
+    def query(self) -> dict:
+        """Memory accounting and request counters (``ifl_server_query``)."""
+        info = ifl_server_info()
+        _check(lib().ifl_server_query(self._s, C.byref(info)))
+        return {name: int(getattr(info, name)) for name, _ in ifl_server_info._fields_}
 
     def poll(self, ticket) -> bool:
         return bool(lib().ifl_poll(ticket))

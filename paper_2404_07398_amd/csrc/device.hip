@@ -70,10 +70,15 @@ struct Scalars {
   double pad0;
   int32_t iters;    // CG iterations performed
   int32_t done;     // 0 running, 1 converged, 2 breakdown
-  int32_t rr_true;  // mixed: the current residual norm is an FP64 true residual
-  int32_t updates;  // mixed: residual replacements
+  int32_t rr_true;  // the current residual norm is an FP64 true residual (start, mixed replacement)
+  int32_t updates;  // FP64 residual replacements
   int32_t update_now;
-  int32_t pad1[3];
+  // FP64: index of the last launch of the direction kernel that replaced the
+  // residual instead of iterating (the next launch tests that true residual
+  // and restarts the directions); only ever compared with launch indices, so
+  // no kernel has to clear it
+  int32_t repl_launch;
+  int32_t pad1[2];
 };
 
 struct DevMatrix {
@@ -237,20 +242,13 @@ __device__ __forceinline__ const double* mval<double>(const Mat& m) { return m.v
 template <>
 __device__ __forceinline__ const float* mval<float>(const Mat& m) { return m.val32; }
 
-// Stopping test shared by the iteration kernels; identical inputs in every
-// block give identical decisions. 0 = iterate, 1 = stop. In mixed precision
-// only an FP64 true residual may stop the solve: a recursive FP32 residual
-// below the tolerance keeps iterating until the next residual replacement
-// (k_fold / k_replace) confirms it. Every iterating launch writes the
-// partials of the next parity, so the partials a kernel reads are never
-// stale.
-template <bool MIXED>
-__device__ __forceinline__ int stop_state(const Scalars* sc, double rr, double floor2) {
-  if (sc->done) return 1;
-  if (!MIXED) return rr <= sc->tol2 ? 1 : 0;
-  if (sc->rr_true && rr <= fmax(sc->tol2, floor2)) return 1;
-  return 0;
-}
+// Only an FP64 true residual r = M phi - S x may stop a solve, in both
+// precisions: a recursive residual drifts from the true one when S is badly
+// conditioned (an FP64 solve stopped on it at cond(S) ~ 1e6 was accurate to
+// ~1e-7 only). Mixed precision replaces the residual in k_fold / k_replace;
+// FP64 replaces it in the direction kernel itself (below). Every iterating
+// launch writes the partials of the next parity, so the partials a kernel
+// reads are never stale.
 
 // ---------------------------------------------------------------- kernels
 // Start of a solve: x0 = phi, r0 = M phi - S phi = -c K_n phi (FP64 values),
@@ -305,6 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Mat m, Vecs<T> v, double* x, fl
       sc->rr_true = 1;
       sc->updates = 0;
       sc->update_now = 0;
+      sc->repl_launch = -2;
     }
   }
 }
@@ -325,39 +324,98 @@ __global__ __launch_bounds__(kBlock) void k_setup(double* part, Scalars* sc, dou
 
 // CG step 1: p_new = z + beta p_old (own row and gathered neighbours),
 // q = S p_new = d p_new + c K_off p_new, partial (p_new, q).
+//
+// The prologue finishes the residual sums of the previous step and takes
+// one of three decisions, the same in every block (same partials):
+//  * stop: the residual is an FP64 true one (start of the solve, the launch
+//    after a replacement, or a mixed-precision replacement) and meets
+//    max(tol, attainable-accuracy floor);
+//  * replace (FP64 only): the recursive residual meets the tolerance. x is
+//    complete at a kernel boundary, so this launch forms the true residual
+//    r = M phi - S x with FP64 values instead of iterating, with the
+//    partials of (r, z), (r, r) and the floor norm for the next launch,
+//    which tests it and, if it does not pass, restarts the directions
+//    (beta = 0) from it. The blocks of a replacing launch read only the
+//    partials of the current parity and write only those of the next one;
+//  * iterate.
+// 'launch' is the host's index of this launch (k_update of the same launch
+// does nothing after a replacement).
 template <typename T, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_dir_spmv(Mat m, Vecs<T> v, double* part, Scalars* sc, int parity,
-                                                      int G, int spb) {
+__global__ __launch_bounds__(kBlock) void k_dir_spmv(Mat m, Vecs<T> v, const double* x, const double* phi,
+                                                      double* part, Scalars* sc, int parity, int launch, int G,
+                                                      int spb) {
   __shared__ double lw[kWavesPerBlock];
   __shared__ double lo;
-  __shared__ double lds[1][kWavesPerBlock];
+  __shared__ double lds[3][kWavesPerBlock];
   if (sc->done) return;  // finished solves cost one scalar load per launch
-  const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
-  const double rz_old = reduce_partials(part + (P_RZ0 + (parity ^ 1)) * G, G, lw, &lo);
+  const int lb = logical_block(G);
+  const bool fresh = !MIXED && sc->repl_launch == launch - 1;  // FP64 residual replaced by the last launch
+  const bool is_true = sc->rr_true || fresh;
   const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
   double floor2 = 0.0;
-  if (MIXED && sc->rr_true) {
+  if (is_true) {
     const double f = reduce_partials(part + P_FL * G, G, lw, &lo);
     floor2 = f * (kFloorUnits * kUnitRoundoff) * (kFloorUnits * kUnitRoundoff);
   }
-  const int st = stop_state<MIXED>(sc, rr, floor2);
-  const int lb = logical_block(G);
-  if (st != 0) {
-    if (lb == 0 && threadIdx.x == 0 && sc->done == 0) {
+  if (is_true && rr <= fmax(sc->tol2, floor2)) {
+    if (lb == 0 && threadIdx.x == 0) {
       sc->done = 1;
       sc->rr_last = rr;
     }
     return;
   }
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  if (!MIXED && !is_true && rr <= sc->tol2) {
+    // FP64 residual replacement (x and the FP64 vectors r, z are T = double)
+    const double c = sc->c;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+      const int64_t row = s * kWave + lane;
+      if (row >= m.n) continue;
+      const int64_t base = m.sptr[s];
+      const int w = (int)((m.sptr[s + 1] - base) / kWave);
+      double a = 0.0, aa = 0.0;
+      for (int k = 0; k < w; ++k) {
+        const int64_t e = base + (int64_t)k * kWave + lane;
+        const double t = m.val64[e] * x[m.col[e]];
+        a += t;
+        aa += fabs(t);
+      }
+      const double xi = x[row];
+      const double mi = m.mass64[row], kd = m.kdiag64[row];
+      const double r64 = mi * (phi[row] - xi) - c * (kd * xi + a);
+      const double mag = fabs(mi * phi[row]) + fabs(mi * xi) + c * (fabs(kd * xi) + aa);
+      const double zt = r64 / (double)v.d[row];
+      v.r[row] = (T)r64;
+      v.z[row] = (T)zt;
+      acc[0] += r64 * zt;
+      acc[1] += r64 * r64;
+      acc[2] += mag * mag;
+    }
+    block_sum<3>(acc, lds);
+    if (threadIdx.x == 0) {
+      part[(P_RZ0 + (parity ^ 1)) * G + lb] = acc[0];
+      part[(P_RR0 + (parity ^ 1)) * G + lb] = acc[1];
+      part[P_FL * G + lb] = acc[2];
+      if (lb == 0) {
+        sc->repl_launch = launch;
+        sc->updates += 1;
+        sc->rr_last = rr;
+      }
+    }
+    return;
+  }
+  const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
+  // after a replacement the directions restart (beta = 0)
+  const double rz_old = fresh ? INFINITY : reduce_partials(part + (P_RZ0 + (parity ^ 1)) * G, G, lw, &lo);
   const T beta = (T)(rz / rz_old);
   const T c = (T)sc->c;
   const T* __restrict__ pin = parity ? v.p1 : v.p0;
   T* __restrict__ pout = parity ? v.p0 : v.p1;
   const T* __restrict__ z = v.z;
   const T* __restrict__ val = mval<T>(m);
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   double pq[1] = {0.0};
-  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
   for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
     const int64_t row = s * kWave + lane;
     if (row >= m.n) continue;
@@ -409,12 +467,13 @@ __global__ __launch_bounds__(kBlock) void k_dir_spmv(Mat m, Vecs<T> v, double* p
 // z = r / diag(S); partials (r, z) and (r, r) for the next iteration.
 template <typename T, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_update(Mat m, Vecs<T> v, double* x, float* xacc, double* part,
-                                                    Scalars* sc, int parity, int G, int spb) {
+                                                    Scalars* sc, int parity, int launch, int G, int spb) {
   __shared__ double lw[kWavesPerBlock];
   __shared__ double lo;
   __shared__ double lds[2][kWavesPerBlock];
-  // k_dir_spmv of this iteration took the stopping decision (and set done)
-  if (sc->done) return;
+  // k_dir_spmv of this launch took the stopping decision (and set done), or
+  // replaced the residual instead of iterating
+  if (sc->done || sc->repl_launch == launch) return;
   const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
   const int lb = logical_block(G);
   const double pq = reduce_partials(part + P_PQ * G, G, lw, &lo);
@@ -445,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Mat m, Vecs<T> v, double* x, 
   if (threadIdx.x == 0) {
     part[(P_RZ0 + (parity ^ 1)) * G + lb] = acc[0];
     part[(P_RR0 + (parity ^ 1)) * G + lb] = acc[1];
-    if (MIXED && lb == 0) sc->rr_true = 0;
+    if (lb == 0) sc->rr_true = 0;
   }
 }
 
@@ -832,7 +891,7 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
   int launched = 0, chunk_id = 0;
   bool finished = false;
   int pending = -1;  // chunk whose scalars are in flight
-  int32_t iters_seen = 0;
+  int32_t iters_seen = 0, updates_seen = 0;
   int prof_pos[2] = {-1, -1};
   if (prof) {
     ifl_status e = ensure_events(d, 4);
@@ -852,12 +911,12 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
       const int parity = launched & 1;
       const bool sample = prof && j == pos;
       if (sample) IFL_HIP(hipEventRecord(d->ev[2 * slot], s));
-      k_dir_spmv<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.part, w.sc, parity, G, spb);
+      k_dir_spmv<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.phi, w.part, w.sc, parity, launched, G, spb);
       if (sample) {
         IFL_HIP(hipEventRecord(d->ev[2 * slot + 1], s));
         prof_pos[slot] = j;
       }
-      k_update<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, w.part, w.sc, parity, G, spb);
+      k_update<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, w.part, w.sc, parity, launched, G, spb);
       ++launched;
       if (MIXED && (launched % fold_every == 0 || launched == max_iter)) {
         const int par2 = launched & 1;
@@ -877,8 +936,10 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
       IFL_HIP(hipEventSynchronize(done_ev[ws]));
       const Scalars& sh = w.sc_host[ws];
       // count the sample only if that launch iterated (iterations within a
-      // chunk come first, finished launches after)
-      if (prof && prof_pos[ws] >= 0 && prof_pos[ws] < sh.iters - iters_seen) {
+      // chunk come first, finished launches after; an FP64 chunk that
+      // replaced its residual in a direction launch is not sampled)
+      const bool replaced = !MIXED && sh.updates != updates_seen;
+      if (prof && !replaced && prof_pos[ws] >= 0 && prof_pos[ws] < sh.iters - iters_seen) {
         float ms = 0.f;
         IFL_HIP(hipEventElapsedTime(&ms, d->ev[2 * ws], d->ev[2 * ws + 1]));
         d->prof_ms += ms;
@@ -887,6 +948,7 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
         d->prof_kernel = MIXED ? "k_dir_spmv<float, true>" : "k_dir_spmv<double, false>";
       }
       iters_seen = sh.iters;
+      updates_seen = sh.updates;
       if (sh.done) finished = true;
     }
     if (capped) finished = true;

@@ -10,6 +10,7 @@
 // its start time, so a result is the same alone and in any mix.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -69,7 +70,11 @@ struct Worker {
   std::vector<Clock::time_point> t_in;
   std::vector<double*> field_pool;  // device field buffers (row order, n_pad) for reuse (worker only)
   std::thread th;
-  ifl_status init_status = IFL_OK;
+  // set (under srv->mu) when the worker stopped on an error: submits to its
+  // mesh then fail with this status instead of queueing to nobody
+  bool dead = false;
+  ifl_status exit_status = IFL_OK;
+  std::string exit_msg;
 };
 
 }  // namespace
@@ -78,6 +83,10 @@ struct ifl_server {
   size_t budget = 0;
   size_t tiles = 0;  // work space of the registered tiles (guarded by mu)
   size_t used = 0;   // device memory of admitted requests (guarded by mu)
+  // counters for ifl_server_query (guarded by mu)
+  size_t peak_used = 0;
+  int64_t in_flight = 0, peak_in_flight = 0;
+  int64_t submitted = 0, admitted = 0, completed = 0;
   int slots = 32;
   int device = 0;
   std::vector<std::unique_ptr<Worker>> workers;
@@ -111,6 +120,10 @@ void admit(Worker* wk, std::vector<ifl_ticket*>* admitted) {
     // larger than the budget still runs (alone)
     if (s->tiles + s->used + t->footprint > s->budget && s->used > 0) break;
     s->used += t->footprint;
+    s->peak_used = std::max(s->peak_used, s->used);
+    s->admitted += 1;
+    s->in_flight += 1;
+    s->peak_in_flight = std::max(s->peak_in_flight, s->in_flight);
     wk->queue.pop_front();
     admitted->push_back(t);
   }
@@ -124,6 +137,8 @@ void release_ticket(Worker* wk, ifl_ticket* t) {
   {
     std::lock_guard<std::mutex> lk(wk->srv->mu);
     wk->srv->used -= t->footprint;
+    wk->srv->in_flight -= 1;
+    wk->srv->completed += 1;
   }
   wk->srv->cv.notify_all();
 }
@@ -236,8 +251,17 @@ void worker_main(Worker* wk) {
   (void)hipSetDevice(wk->srv->device);
   ifl_status st = run_worker(wk);
   if (st != IFL_OK) {
-    // fail everything this worker still holds, so no waiter blocks forever
+    // fail everything this worker still holds, so no waiter blocks forever;
+    // admitted requests (in a slot or waiting for one) give their memory
+    // back first, so that other meshes' requests are not held up by it
     const std::string msg = std::string("serving worker failed: ") + ifl_last_error();
+    std::vector<ifl_ticket*> held;
+    for (int j = 0; j < wk->R; ++j)
+      if (wk->slot[j].t) held.push_back(wk->slot[j].t);
+    for (const Column& c : wk->pending) held.push_back(c.t);
+    std::sort(held.begin(), held.end());
+    held.erase(std::unique(held.begin(), held.end()), held.end());
+    for (ifl_ticket* t : held) release_ticket(wk, t);
     for (int j = 0; j < wk->R; ++j)
       if (wk->slot[j].t) {
         ifl_ticket* t = wk->slot[j].t;
@@ -250,7 +274,9 @@ void worker_main(Worker* wk) {
     std::lock_guard<std::mutex> lk(wk->srv->mu);
     for (ifl_ticket* t : wk->queue) finish_ticket(t, st, msg);
     wk->queue.clear();
-    wk->init_status = st;
+    wk->exit_status = st;
+    wk->exit_msg = msg;
+    wk->dead = true;
   }
 }
 
@@ -349,10 +375,33 @@ ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field, int32
   t->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    if (wk->dead) {
+      delete t;
+      return fail(wk->exit_status, wk->exit_msg);
+    }
     wk->queue.push_back(t);
+    s->submitted += 1;
   }
   s->cv.notify_all();
   *ticket = t;
+  return IFL_OK;
+}
+
+ifl_status ifl_server_query(ifl_server* s, ifl_server_info* info) {
+  if (!s || !info) return fail(IFL_EINVAL, "server / info is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  info->budget = s->budget;
+  info->tiles = s->tiles;
+  info->used = s->used;
+  info->peak_used = s->peak_used;
+  info->submitted = s->submitted;
+  info->admitted = s->admitted;
+  info->completed = s->completed;
+  info->in_flight = s->in_flight;
+  info->peak_in_flight = s->peak_in_flight;
+  int64_t queued = 0;
+  for (const auto& wk : s->workers) queued += (int64_t)wk->queue.size();
+  info->queued = queued;
   return IFL_OK;
 }
 

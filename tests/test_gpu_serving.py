@@ -172,3 +172,48 @@ def test_server_errors(ifl):
         assert st == 0 and lat > 0
     srv.close()
     h.close()
+
+
+def test_server_admission_by_footprint(ifl):
+    """A budget that holds the mesh's tile and exactly one request's field:
+    requests submitted together are admitted one at a time (the next only
+    when the previous has released its memory), complete in submission
+    order, and each result equals, bitwise, the same request served by a
+    server with room for all of them."""
+    s = W.icosphere(5, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    h = ifl.prepare_mesh(s, 0, 1, precision=ifl.IFL_MIXED)
+    fields = [W.sphere_k3_field(s, 900 + i, n_waves=64) for i in range(6)]
+    ks = W.log_scales(s.h, 3)
+    footprint = 8 * ((h.num_dofs + 63) // 64 * 64)
+    # reference: everything admitted at once
+    srv = ifl.Server(4 << 30, slots=8)
+    mid = srv.add(h)
+    tiles = srv.query()["tiles"]
+    ref = []
+    tl = [srv.submit(mid, f, ks) for f in fields]
+    for t, _ in tl:
+        st, stats, o, lat = srv.wait(t, len(ks))
+        assert st == 0
+        ref.append(o.copy())
+    q = srv.query()
+    assert q["peak_in_flight"] >= 2, q
+    srv.close()
+    # one request at a time
+    srv = ifl.Server(tiles + footprint + footprint // 2, slots=8)
+    mid = srv.add(h)
+    tl = [srv.submit(mid, f, ks) for f in fields]
+    lats = []
+    for i, (t, _) in enumerate(tl):
+        st, stats, o, lat = srv.wait(t, len(ks))
+        assert st == 0 and all(x.status == 0 for x in stats)
+        assert np.array_equal(o, ref[i]), i
+        lats.append(lat)
+    q = srv.query()
+    print(f"admission: tiles={tiles} footprint={footprint} info={q} latencies={lats}")
+    assert q["peak_in_flight"] == 1 and q["peak_used"] == footprint, q
+    assert q["admitted"] == len(fields) and q["completed"] == len(fields) and q["used"] == 0, q
+    # submitted together, served one after another
+    assert all(a < b for a, b in zip(lats, lats[1:])), lats
+    srv.close()
+    h.close()

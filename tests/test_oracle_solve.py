@@ -157,3 +157,78 @@ def test_cg_certificate_larger_mesh():
     x, it = O.refine_solve(S, op.A * pd, pd)
     assert residual_bound(S, op.A, op.A * pd, x) < 1e-11
     assert it > 10
+
+
+def _bound_pins(bound, S, A, b, xs, lam_max):
+    """The properties a certificate of ||x - x*|| / ||x|| must have, checked
+    around the exact solution xs of S x = b (S = M + c K_n, K_n PSD with
+    K_n 1 = 0). Returns the list of failed checks (empty = all hold).
+
+    * x = xs: the bound is at the level of rounding (~ eps cond(S)), at
+      least 1000 times below the perturbations used next (1e-6 relative);
+    * x = xs + eps 1 (S 1 = M 1, the direction the bound is tight for): it
+      bounds the true error and is within RMS(A) / min(A) of it;
+    * x = xs + random delta: it bounds the true error and is within
+      lam_max(S) / min(A) of it."""
+    failed = []
+    if not bound(S, A, b, xs) <= 1e-9:
+        failed.append("exact solution")
+    n = xs.size
+    eps = 1e-6 * np.linalg.norm(xs) / np.sqrt(n)
+    rng = np.random.default_rng(11)
+    for name, d, factor in (
+        ("constant", np.full(n, eps), np.sqrt(np.mean(A * A)) / A.min()),
+        ("random", eps * rng.standard_normal(n), lam_max / A.min()),
+    ):
+        x = xs + d
+        true = np.linalg.norm(d) / np.linalg.norm(x)
+        got = bound(S, A, b, x)
+        if not (got >= true * (1 - 1e-6) and got <= factor * true * (1 + 1e-6)):
+            failed.append(name)
+    return failed
+
+
+def _mutant_max_area(S, A, b, x):
+    """residual_bound with max(A) where min(A) belongs (a planted mistake)."""
+    return residual_bound(S, np.full_like(A, A.max()), b, x)
+
+
+def _mutant_no_mass(S, A, b, x):
+    """residual_bound on c K_n alone, the mass term dropped (a planted mistake)."""
+    import scipy.sparse as sp
+
+    return residual_bound((S - sp.diags(A)).tocsr(), A, b, x)
+
+
+@pytest.mark.parametrize("case", ["c1", "sphere5_n2_32h"])
+def test_residual_bound_certifies_known_errors(case):
+    """The certificate that the full-size GPU tests rely on
+    (||x - x*|| / ||x|| <= ||b - S x|| / (min(A) ||x||), since S >= M) checked
+    against perturbations of known size around a direct solution: C1, and
+    the ill-conditioned biharmonic case (masked level-5 sphere, n = 2, 32h,
+    cond(S) ~ 1e5). The same checks reject the oracle with a planted mistake
+    (max(A) in place of min(A), or the mass term dropped from the residual)."""
+    import scipy.sparse.linalg as spla
+
+    if case == "c1":
+        m = W.split_square(64, jitter=0.2)
+        op = O.scalar_operator(m, 1)
+        phi = W.planar_k3_field(m, 1000)
+        k = W.log_scales(1.0, 8)[0]
+        method = "dense"
+    else:
+        m = W.icosphere(5, jitter=0.1)
+        m = m.with_mask(W.land_mask(m, 0.3))
+        op = O.scalar_operator(m, 2)
+        phi = W.sphere_k3_field(m, 1003, n_waves=256)
+        k = W.log_scales(m.h, 5)[0]
+        method = "direct"
+    S = O.system_matrix(op, k)
+    pd = O.to_dofs(op, phi)
+    b = op.A * pd
+    xs = O.filter_scalar(op, phi, [k], method=method)[0]
+    xs = O.to_dofs(op, xs)
+    lam_max = float(spla.eigsh(S, k=1, which="LA", return_eigenvectors=False)[0]) * 1.001
+    assert _bound_pins(residual_bound, S, op.A, b, xs, lam_max) == []
+    assert "constant" in _bound_pins(_mutant_max_area, S, op.A, b, xs, lam_max)
+    assert "exact solution" in _bound_pins(_mutant_no_mass, S, op.A, b, xs, lam_max)

@@ -127,3 +127,94 @@ def test_fig8_higher_orders_follow_the_steep_slope():
     assert np.all(slopes[1] > -3.0)
     assert errs[4] < errs[2] < errs[1]
     assert errs[4] < 0.5
+
+
+def _dE_dk(q, E_q, ks, n, gamma=0.5):
+    """Analytic k-derivative of filtered_energy_of_modes: with
+    G = 1 / (1 + gamma (lam/k^2)^n), dG/dk = G^2 2 n gamma (lam/k^2)^n / k,
+    so dE/dk = sum_q E_q 4 n gamma (lam/k^2)^n G^3 / k."""
+    lam = O.discrete_symbol(q)
+    out = []
+    for k in ks:
+        t = gamma * (lam / (k * k)) ** n
+        G = 1.0 / (1.0 + t)
+        out.append(float(np.sum(E_q * 4.0 * n * t * G ** 3 / k)))
+    return np.array(out)
+
+
+def _density_pins(density, n_order):
+    """The checks of test_density_is_the_k_derivative_of_the_fig8_energy on
+    a density function; returns the names of the failed ones."""
+    N = 2048
+    q, E = O.fig8_modes(N)
+    ks = np.exp(np.arange(np.log(4 * np.pi / N), np.log(0.5 * np.pi), np.log1p(1e-3)))[::37]
+    fine = np.exp(np.log(ks)[:, None] + np.array([0.0, np.log1p(1e-3)])[None, :]).ravel()
+    Ef = O.filtered_energy_of_modes(q, E, fine, n_order)
+    dens, km = density(fine, Ef)
+    dens, km = dens[::2], km[::2]  # the pairs (k, k (1 + 1e-3))
+    ref = _dE_dk(q, E, km, n_order)
+    sel = ref > 1e-12 * ref.max()
+    failed = []
+    if not np.max(np.abs(dens[sel] / ref[sel] - 1)) < 1e-4:
+        failed.append("derivative")
+    kc = np.exp(np.linspace(np.log(4 * np.pi / N), np.log(0.9 * np.pi), 25))
+    Ec = O.filtered_energy_of_modes(q, E, kc, n_order)
+    dc, kmc = density(kc, Ec)
+    if not abs(np.sum(dc * np.diff(kc)) / (Ec[-1] - Ec[0]) - 1) < 1e-12:
+        failed.append("telescoping")
+    if not np.allclose(kmc * kmc, kc[:-1] * kc[1:], rtol=1e-14, atol=0):
+        failed.append("midpoint")
+    return failed
+
+
+def _mutant_arithmetic_mid(ks, E):
+    d, _ = O.spectrum_density(ks, E)
+    return d, 0.5 * (ks[1:] + ks[:-1])
+
+
+def _mutant_step(ks, E):
+    d, km = O.spectrum_density(ks, E)
+    return d / 1.6, km
+
+
+def _mutant_left_point(ks, E):
+    d, _ = O.spectrum_density(ks, E)
+    return d, np.asarray(ks)[:-1]
+
+
+@pytest.mark.parametrize("n_order", [1, 2, 4])
+def test_density_pins_reject_planted_mistakes(n_order):
+    """The density pins hold for the oracle and fail for the oracle with a
+    planted mistake: the arithmetic instead of the geometric midpoint, a
+    step scaled by 1.6, or the difference placed at the left wavenumber."""
+    assert _density_pins(O.spectrum_density, n_order) == []
+    assert "midpoint" in _density_pins(_mutant_arithmetic_mid, n_order)
+    assert _density_pins(_mutant_step, n_order)
+    assert "derivative" in _density_pins(_mutant_left_point, n_order)
+
+
+@pytest.mark.parametrize("n_order", [1, 2, 4])
+def test_density_is_the_k_derivative_of_the_fig8_energy(n_order):
+    """spectrum_density on the Fig. 8 construction ("Some comments"
+    section) at fine, log-spaced k (ratio 1 + 1e-3 between neighbours) is
+    the analytic derivative dE/dk at k_mid: a central difference, so the
+    error is O((dk/k)^2) ~ 1e-6, where a difference off by one index or a
+    step scaled wrongly is off by ~1e-3 or more. Summed over the steps the
+    density gives back the energy difference (telescoping), and k_mid is the
+    geometric mean of the two wavenumbers."""
+    N = 2048
+    q, E = O.fig8_modes(N)
+    ks = np.exp(np.arange(np.log(4 * np.pi / N), np.log(0.5 * np.pi), np.log1p(1e-3)))[::37]
+    fine = np.exp(np.log(ks)[:, None] + np.array([0.0, np.log1p(1e-3)])[None, :]).ravel()
+    Ef = O.filtered_energy_of_modes(q, E, fine, n_order)
+    dens, km = O.spectrum_density(fine, Ef)
+    dens, km = dens[::2], km[::2]  # the pairs (k, k (1 + 1e-3))
+    ref = _dE_dk(q, E, km, n_order)
+    sel = ref > 1e-12 * ref.max()
+    assert np.max(np.abs(dens[sel] / ref[sel] - 1)) < 1e-4
+    # telescoping over a coarse list and the geometric midpoint
+    kc = np.exp(np.linspace(np.log(4 * np.pi / N), np.log(0.9 * np.pi), 25))
+    Ec = O.filtered_energy_of_modes(q, E, kc, n_order)
+    dc, kmc = O.spectrum_density(kc, Ec)
+    assert abs(np.sum(dc * np.diff(kc)) / (Ec[-1] - Ec[0]) - 1) < 1e-12
+    assert np.allclose(kmc * kmc, kc[:-1] * kc[1:], rtol=1e-14, atol=0)
