@@ -220,6 +220,34 @@ ifl_status ifl_filter(ifl_handle* h, int32_t n_fields, const double* fields,
                       ifl_solve_stats* stats);
 
 /*
+ * ifl_filter for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solves as ifl_filter with the one-column path (every column
+ * solved on its own; bitwise the results of ifl_filter with
+ * ifl_options.batch = 1), but the per-call work space (block partial sums
+ * and per-column scalars) lives in a static device array of 64 KiB that the
+ * library holds on each GPU until the process ends. The call allocates
+ * nothing: no hipMalloc / hipFree, no events, no staging buffers.
+ *
+ * fields : device, n_fields x L doubles on the handle's device.
+ * out    : device, n_fields x n_scales x L doubles on the handle's device.
+ * k, stats : as ifl_filter (host).
+ * Limits : the handle's logical block count G must satisfy 9 G x 8 bytes
+ *          <= 65,280 (G <= 906; the default is at most 512); otherwise
+ *          IFL_EINVAL with a message naming both sizes. Host pointers for
+ *          fields or out are IFL_EINVAL. Profiling (ifl_options.profile)
+ *          is ignored.
+ * All handles on one GPU share its work space, which keeps the last call's
+ * contents (each call clears it first): calls that overlap on one GPU
+ * (from several threads, or on several handles' streams) race; serialise
+ * them. Calls on one handle are serialised by the handle's lock.
+ * Errors : as ifl_filter.
+ */
+ifl_status ifl_filter_noalloc(ifl_handle* h, int32_t n_fields, const double* fields,
+                              int32_t n_scales, const double* k, double* out,
+                              ifl_solve_stats* stats);
+
+/*
  * Coarse-graining spectrum of one field (Sect. 2.1, Sect. 4): the filtered
  * energy E(k_j) = (1/2) sum_i M_i phi_bar_i(k_j)^2 / sum_i M_i at each k_j
  * (for vectors phi_bar^2 = u_bar^2 + v_bar^2), and its finite-difference
@@ -324,6 +352,7 @@ typedef struct ifl_tune {
 } ifl_tune;
 
 ifl_status ifl_autotune(ifl_handle* h, ifl_tune* out);
+
 
 /* ----------------------------------------------------------- serving API */
 typedef struct ifl_server ifl_server;

@@ -130,6 +130,8 @@ _PROTOS = {
     "ifl_get_options": (C.c_int32, [C.c_void_p, C.POINTER(ifl_options)]),
     "ifl_filter": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p,
                                C.POINTER(ifl_solve_stats)]),
+    "ifl_filter_noalloc": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                       C.c_void_p, C.POINTER(ifl_solve_stats)]),
     "ifl_spectrum": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ifl_apply": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
@@ -310,6 +312,24 @@ class Handle:
         if st != IFL_OK and (st != IFL_ENOTCONV or raise_on_notconv):
             _check(st)
         return out, [stats[i] for i in range(nf * ks.size)]
+
+    def filter_noalloc(self, fields, ks, out, raise_on_notconv: bool = True):
+        """``ifl_filter_noalloc``: ``fields`` and ``out`` are device tensors
+        ((F, L) and (F, S, L), float64, contiguous). Returns the stats."""
+        ks = np.ascontiguousarray(np.atleast_1d(ks), dtype=np.float64)
+        L = self.field_length
+        nf = 1 if len(fields.shape) == 1 else fields.shape[0]
+        if fields.shape[-1] != L:
+            raise ValueError(f"field length {fields.shape[-1]} != {L}")
+        if int(np.prod(out.shape)) != nf * ks.size * L:
+            raise ValueError("out must hold n_fields x n_scales x L doubles")
+        fin = _Field(fields)
+        fout = _Field(out, writable=True)
+        stats = (ifl_solve_stats * max(1, nf * ks.size))()
+        st = lib().ifl_filter_noalloc(self._h, nf, fin.ptr, ks.size, _dptr(ks), fout.ptr, stats)
+        if st != IFL_OK and (st != IFL_ENOTCONV or raise_on_notconv):
+            _check(st)
+        return [stats[i] for i in range(nf * ks.size)]
 
     def spectrum(self, field, ks):
         ks = np.ascontiguousarray(ks, dtype=np.float64)
@@ -497,3 +517,4 @@ class Server:
             self.close()
         except Exception:
             pass
+

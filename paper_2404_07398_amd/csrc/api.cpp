@@ -138,6 +138,20 @@ ifl_status ifl_filter(ifl_handle* h, int32_t n_fields, const double* fields, int
   return device_filter(h, n_fields, fields, n_scales, k, out, stats, nullptr);
 }
 
+ifl_status ifl_filter_noalloc(ifl_handle* h, int32_t n_fields, const double* fields, int32_t n_scales,
+                              const double* k, double* out, ifl_solve_stats* stats) {
+  g_last_error.clear();
+  if (!h) return fail(IFL_EINVAL, "handle is NULL");
+  if (n_fields < 0) return fail(IFL_EINVAL, "n_fields < 0");
+  ifl_status st = check_k(n_scales, k, false);
+  if (st != IFL_OK) return st;
+  if (n_fields == 0 || n_scales == 0) return IFL_OK;
+  if (!fields || !out) return fail(IFL_EINVAL, "fields / out is NULL");
+  if (!h->dev) return fail(IFL_EDEVICE, "host-only handle (device = -1)");
+  std::lock_guard<std::mutex> lk(h->mu);
+  return device_filter_noalloc(h, n_fields, fields, n_scales, k, out, stats);
+}
+
 ifl_status ifl_spectrum(ifl_handle* h, const double* field, int32_t n_scales, const double* k, double* energy,
                         double* density, double* k_mid) {
   g_last_error.clear();

@@ -55,6 +55,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 // 2.6 M-row mesh 512 beat 256, 1024 and 2048 (FP32 SpMV 38 vs 46-50 us).
 constexpr int kMaxBlocks = 512;
 constexpr int kXcd = 8;
+constexpr int kMaxDevices = 64;
 constexpr int kUnroll = 8;                  // sliced-ELL entries loaded together per row
 
 // Per-column device scalars. Written by block 0 of a kernel, read by the
@@ -121,6 +122,8 @@ struct DeviceState {
   ColWork w;
   int G = 1;          // logical blocks
   int spb = 1;        // slices per logical block
+  // completion events of the one-column path's chunks (made with the handle)
+  hipEvent_t done_ev[2] = {nullptr, nullptr};
   // profiling
   std::vector<hipEvent_t> ev;
   int64_t prof_launches = 0;
@@ -155,6 +158,17 @@ struct DeviceState {
 
 // partial-array offsets (in units of G)
 enum { P_PQ = 0, P_RZ0 = 1, P_RZ1 = 2, P_RR0 = 3, P_RR1 = 4, P_BB = 5, P_RES = 6, P_EN = 7, P_FL = 8, P_COUNT = 9 };
+
+// Work space of ifl_filter_noalloc: the one-column path's block partials
+// (P_COUNT x G doubles) followed by its Scalars, in a file-scope device
+// array, so that the call allocates nothing. Each GPU holds its own copy
+// for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (noalloc_scratch_addr),
+// never through the symbol's name.
+constexpr size_t kNoallocScratchBytes = 64 * 1024;
+constexpr size_t kNoallocScalarsOffset = kNoallocScratchBytes - 256;  // Scalars in the last 256 bytes
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+static_assert(sizeof(Scalars) <= 256, "Scalars must fit the scratch tail");
 
 // Attainable accuracy of an FP64 residual r = b - S x: its rounding error is
 // bounded by a small multiple of u ||(|b| + |S| |x|)||, u = 2^-53. A true
@@ -718,6 +732,28 @@ hipStream_t stream_of(Handle* h) {
 
 }  // namespace
 
+// Address of 'scratch' on each device, looked up once per device (with that
+// device current) when the first handle on it is made.
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+static ifl_status noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(IFL_EDEVICE, "device ordinal beyond the library's table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr[device]) return IFL_OK;
+  void* p = nullptr;
+  IFL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return fail(IFL_EDEVICE, "hipGetSymbolAddress returned NULL for the no-allocation work space");
+  g_scratch_addr[device] = p;
+  return IFL_OK;
+}
+
+static void* noalloc_scratch_addr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_addr[device];
+}
+
 ifl_status device_create(Handle* h) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
@@ -734,6 +770,9 @@ ifl_status device_create(Handle* h) {
   h->dev = d;
   d->device = h->opt.device;
   IFL_HIP(hipStreamCreateWithFlags(&d->own_stream, hipStreamNonBlocking));
+  IFL_HIP(hipEventCreateWithFlags(&d->done_ev[0], hipEventDisableTiming));
+  IFL_HIP(hipEventCreateWithFlags(&d->done_ev[1], hipEventDisableTiming));
+  if (ifl_status e = noalloc_scratch_init(d->device); e != IFL_OK) return e;
 
   SellPack sp;
   pack_sell(h->op, &sp);
@@ -807,6 +846,8 @@ void device_destroy(Handle* h) {
   for (void* p : proj)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : d->done_ev)
+    if (e) (void)hipEventDestroy(e);
   if (d->own_stream) (void)hipStreamDestroy(d->own_stream);
   delete d;
   h->dev = nullptr;
@@ -863,8 +904,17 @@ double spmv_bytes(const DevMatrix& m, size_t vb) {
   return (double)m.nnz_stored * (4.0 + vb) + 8.0 * (m.n_slices + 1) + (double)m.n * vb * 5.0;
 }
 
+// Partials and scalars of a one-column solve: the handle's own, or the
+// no-allocation work space.
+struct ColScratch {
+  double* part;
+  Scalars* sc;
+  bool allow_profile;  // the handle's profiling events may be made and used
+};
+
 template <typename T, bool MIXED>
-ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* out_dev, double* energy) {
+ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* out_dev, double* energy,
+                        const ColScratch& cs) {
   DeviceState* d = h->dev;
   ColWork& w = d->w;
   const DevMatrix& M = d->m;
@@ -879,14 +929,14 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
   const int G = d->G, spb = d->spb;
   const double c = h->opt.gamma / std::pow(k, 2.0 * h->op.order);
   const auto t0 = std::chrono::steady_clock::now();
-  k_init<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, w.phi, w.part, w.sc, c, G, spb);
-  k_setup<<<1, kBlock, 0, s>>>(w.part, w.sc, h->opt.rtol, G);
+  k_init<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, w.phi, cs.part, cs.sc, c, G, spb);
+  k_setup<<<1, kBlock, 0, s>>>(cs.part, cs.sc, h->opt.rtol, G);
   IFL_HIP(hipGetLastError());
 
   const int chunk = 8;         // iterations between host checks
   const int fold_every = 4;    // mixed: residual-replacement checks
   const double delta2 = 1e-4;  // mixed: replace when ||r|| fell 100x
-  const bool prof = h->opt.profile != 0;
+  const bool prof = h->opt.profile != 0 && cs.allow_profile;
   const int max_iter = h->opt.max_iter;
   int launched = 0, chunk_id = 0;
   bool finished = false;
@@ -897,9 +947,7 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
     ifl_status e = ensure_events(d, 4);
     if (e != IFL_OK) return e;
   }
-  hipEvent_t done_ev[2];
-  IFL_HIP(hipEventCreateWithFlags(&done_ev[0], hipEventDisableTiming));
-  IFL_HIP(hipEventCreateWithFlags(&done_ev[1], hipEventDisableTiming));
+  hipEvent_t* done_ev = d->done_ev;
   ifl_status result = IFL_OK;
   while (!finished) {
     const int slot = chunk_id & 1;
@@ -911,22 +959,22 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
       const int parity = launched & 1;
       const bool sample = prof && j == pos;
       if (sample) IFL_HIP(hipEventRecord(d->ev[2 * slot], s));
-      k_dir_spmv<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.phi, w.part, w.sc, parity, launched, G, spb);
+      k_dir_spmv<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.phi, cs.part, cs.sc, parity, launched, G, spb);
       if (sample) {
         IFL_HIP(hipEventRecord(d->ev[2 * slot + 1], s));
         prof_pos[slot] = j;
       }
-      k_update<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, w.part, w.sc, parity, launched, G, spb);
+      k_update<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, cs.part, cs.sc, parity, launched, G, spb);
       ++launched;
       if (MIXED && (launched % fold_every == 0 || launched == max_iter)) {
         const int par2 = launched & 1;
-        k_fold<<<G, kBlock, 0, s>>>(m, w.x, w.xacc, w.part, w.sc, par2, delta2, G, spb);
+        k_fold<<<G, kBlock, 0, s>>>(m, w.x, w.xacc, cs.part, cs.sc, par2, delta2, G, spb);
         k_replace<<<G, kBlock, 0, s>>>(m, Vecs<float>{w.r32, w.z32, w.p32[0], w.p32[1], w.q32, w.d32}, w.x, w.phi,
-                                       w.part, w.sc, par2, G, spb);
+                                       cs.part, cs.sc, par2, G, spb);
       }
     }
     IFL_HIP(hipGetLastError());
-    IFL_HIP(hipMemcpyAsync(&w.sc_host[slot], w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    IFL_HIP(hipMemcpyAsync(&w.sc_host[slot], cs.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     IFL_HIP(hipEventRecord(done_ev[slot], s));
     const bool capped = launched >= max_iter;
     // wait for the previous chunk (the current one keeps the GPU busy)
@@ -956,13 +1004,11 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
     ++chunk_id;
   }
   // finish: x to caller numbering, true residual, energy
-  k_finish<<<G, kBlock, 0, s>>>(m, w.x, MIXED ? w.xacc : nullptr, w.phi, M.entity, out_dev, w.part, w.sc, G, spb);
-  k_finish_scalars<<<1, kBlock, 0, s>>>(w.part, w.sc, G);
+  k_finish<<<G, kBlock, 0, s>>>(m, w.x, MIXED ? w.xacc : nullptr, w.phi, M.entity, out_dev, cs.part, cs.sc, G, spb);
+  k_finish_scalars<<<1, kBlock, 0, s>>>(cs.part, cs.sc, G);
   IFL_HIP(hipGetLastError());
-  IFL_HIP(hipMemcpyAsync(&w.sc_host[0], w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  IFL_HIP(hipMemcpyAsync(&w.sc_host[0], cs.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   IFL_HIP(hipStreamSynchronize(s));
-  (void)hipEventDestroy(done_ev[0]);
-  (void)hipEventDestroy(done_ev[1]);
   const Scalars& sh = w.sc_host[0];
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   const double rel = sh.bb > 0 ? std::sqrt(sh.res2 / sh.bb) : std::sqrt(sh.res2);
@@ -987,14 +1033,16 @@ namespace {
 
 // One column at a time (the plain path, and single solves).
 ifl_status filter_single(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales, const double* k,
-                         double* out, ifl_solve_stats* stats, double* energy) {
+                         double* out, ifl_solve_stats* stats, double* energy, const ColScratch& cs) {
   DeviceState* d = h->dev;
   hipStream_t s = stream_of(h);
   const int64_t L = h->op.field_len;
   const bool fdev = is_device_ptr(fields);
   const bool odev = out ? is_device_ptr(out) : false;
-  ifl_status st = ensure_stage(d, L);
-  if (st != IFL_OK) return st;
+  ifl_status st = IFL_OK;
+  if (!fdev || (out && !odev)) {
+    if ((st = ensure_stage(d, L)) != IFL_OK) return st;
+  }
   ifl_status agg = IFL_OK;
   for (int32_t f = 0; f < n_fields; ++f) {
     st = load_field(h, fields + (int64_t)f * L, fdev, s);
@@ -1007,8 +1055,8 @@ ifl_status filter_single(Handle* h, int32_t n_fields, const double* fields, int3
       }
       ifl_solve_stats* so = stats ? &stats[(int64_t)f * n_scales + j] : nullptr;
       double* eo = energy ? &energy[(int64_t)f * n_scales + j] : nullptr;
-      if (h->opt.precision == IFL_MIXED) st = solve_column<float, true>(h, k[j], so, dst, eo);
-      else st = solve_column<double, false>(h, k[j], so, dst, eo);
+      if (h->opt.precision == IFL_MIXED) st = solve_column<float, true>(h, k[j], so, dst, eo, cs);
+      else st = solve_column<double, false>(h, k[j], so, dst, eo, cs);
       if (st == IFL_ENOTCONV) agg = st;
       else if (st != IFL_OK) return st;
       if (out && !odev) {
@@ -1316,8 +1364,37 @@ ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int3
   DeviceState* d = h->dev;
   IFL_HIP(hipSetDevice(d->device));
   const int R = pick_tile(h, (int64_t)n_fields * n_scales);
-  if (R <= 1) return filter_single(h, n_fields, fields, n_scales, k, out, stats, energy);
+  if (R <= 1) return filter_single(h, n_fields, fields, n_scales, k, out, stats, energy, ColScratch{d->w.part, d->w.sc, true});
   return filter_batched(h, R, n_fields, fields, n_scales, k, out, stats, energy);
+}
+
+// Zero n doubles (the start of a no-allocation call: a fill kernel rather
+// than a memset node, so the call can also be captured)
+__global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+ifl_status device_filter_noalloc(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales,
+                                 const double* k, double* out, ifl_solve_stats* stats) {
+  DeviceState* d = h->dev;
+  IFL_HIP(hipSetDevice(d->device));
+  if (!is_device_ptr(fields) || !is_device_ptr(out))
+    return fail(IFL_EINVAL, "ifl_filter_noalloc takes device fields and outputs only");
+  const size_t need = sizeof(double) * (size_t)P_COUNT * (size_t)d->G;
+  if (need > kNoallocScalarsOffset)
+    return fail(IFL_EINVAL, "the handle's " + std::to_string(d->G) + " logical blocks need " + std::to_string(need) +
+                                " bytes of partials; the no-allocation work space holds " +
+                                std::to_string(kNoallocScalarsOffset));
+  unsigned char* base = static_cast<unsigned char*>(noalloc_scratch_addr(d->device));
+  if (!base) return fail(IFL_EDEVICE, "no-allocation work space not set up on this device");
+  const ColScratch cs{reinterpret_cast<double*>(base), reinterpret_cast<Scalars*>(base + kNoallocScalarsOffset),
+                      false};
+  hipStream_t s = stream_of(h);
+  const int64_t nz = (int64_t)(kNoallocScratchBytes / sizeof(double));
+  k_fill_zero<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(cs.part, nz);
+  IFL_HIP(hipGetLastError());
+  return filter_single(h, n_fields, fields, n_scales, k, out, stats, nullptr, cs);
 }
 
 // Autotuner of the batched engine: times 8 iterations (two replacement

@@ -80,6 +80,10 @@ void device_destroy(Handle* h);
 // Solve n_fields x n_scales columns. fields / out may be host or device.
 ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales,
                          const double* k, double* out, ifl_solve_stats* stats, double* energy);
+// The one-column path with its partials and scalars in the library's static
+// device work space (no allocation; device fields and outputs only).
+ifl_status device_filter_noalloc(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales,
+                                 const double* k, double* out, ifl_solve_stats* stats);
 ifl_status device_apply(Handle* h, double k, const double* x, double* y);
 // Cell velocities (2 n_cells, host or device) -> the projected vertex field
 // R_vc u_c / M (field_len, host or device; 0 where there is no dof).
