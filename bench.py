@@ -8,18 +8,21 @@ log-spaced 32h .. 2h), order n = 1: 1,920 solves per step. Inputs are
 synthetic (seeded) and resident in HBM before the timed region.
 
 Prints one JSON line: solves/s of the whole job (the timed steps), the
-roofline of the dominant SpMV kernel (algorithmic bytes per launch / mean
-launch time from HIP events recorded live on the launch stream; HBM
-traffic from the committed rocprofv3 profile; a plain 1 GiB device copy
+roofline of the dominant kernel (algorithmic bytes per launch / mean launch
+time from HIP events recorded live on the launch stream; HBM traffic from
+the committed rocprofv3 profile; the library's own 4 GiB device copy probe
 timed in the same run), and, outside the timed steps: the plain FP64
 one-column-at-a-time path on a subset of the fields, SpMV rates on the
-unmasked level-9 mesh (single column FP64 / FP32, n = 1 and 2; 32 batched
-columns), velocity filtering on the level-8 sphere (the vertex FE vector
-Laplacian fed by the cell -> vertex projection, and the cell-vector
-operator of Eq. 7), the continuous-batching server under two Poisson
-streams (200 requests/s, and 15 requests/s below capacity), and the FP64
-CPU oracle on a
-bounded sample of the same workload together with the GPU's error on it.
+unmasked level-9 mesh (single column FP64 / FP32, n = 1, 2 and 4; 32
+batched columns), C1 (64 x 64 planar, plain FP64, latency-bound) and C2
+(level-8 sphere, n = 2, mixed batched vs plain FP64), velocity filtering on
+the level-8 sphere (the vertex FE vector Laplacian fed by the cell -> vertex
+projection, and the cell-vector operator of Eq. 7), the continuous-batching
+server on resident level 6-10 meshes (200 warm-up + 2,000 measured requests
+at 200 req/s, a stream below capacity, a like-for-like comparison with the
+plain FP64 path, and the SpMV rates on the level-10 mesh), and the FP64 CPU
+oracle on a bounded sample of the same workload (one thread, and one
+process per core) together with the GPU's error on it.
 """
 from __future__ import annotations
 
@@ -248,15 +251,100 @@ def vector_leg(ifl):
     return res
 
 
+def c1_leg(ifl):
+    """C1, the latency-bound configuration: 64 x 64 periodic split-square
+    mesh (4,096 vertices, jitter +-0.2 cell), one k^-3 field, n = 1, 8
+    scales (wavelengths 32 .. 2 cells), the plain FP64 path one column at a
+    time. One SpMV moves ~0.5 MB, so the rate is set by launch and reduction
+    latency, not bandwidth. Field and outputs resident on the device."""
+    import torch
+
+    import workloads as W
+
+    m = W.split_square(64, jitter=0.2, seed=1)
+    phi = torch.from_numpy(W.planar_k3_field(m, 1000)).to("cuda:0")
+    ks = W.log_scales(1.0, 8)
+    res = {"workload": "64x64 periodic split square (4,096 vertices, jitter 0.2), 1 k^-3 field x 8 scales "
+                       "(wavelengths 32..2 cells), n=1"}
+    for prec, batch, name in ((ifl.IFL_FP64, 1, "fp64_single_column"), (ifl.IFL_MIXED, 0, "mixed_batched")):
+        h = ifl.prepare_mesh(m, ifl.IFL_VERTEX_SCALAR, 1, precision=prec, batch=batch, device=0)
+        out = torch.empty((1, ks.size, h.field_length), dtype=torch.float64, device="cuda:0")
+        h.filter(phi, ks, out=out)
+        torch.cuda.synchronize()
+        reps = 20
+        t = time.perf_counter()
+        iters = 0
+        for _ in range(reps):
+            _, st = h.filter(phi, ks, out=out)
+            iters += sum(x.iterations for x in st)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        res[name] = {"solves_per_s": round(reps * ks.size / el, 1),
+                     "ms_per_solve": round(el / (reps * ks.size) * 1e3, 3),
+                     "mean_cg_iterations": round(iters / (reps * ks.size), 1),
+                     "us_per_iteration": round(el / max(1, iters) * 1e6, 2)}
+        h.close()
+    return res
+
+
+def c2_leg(ifl):
+    """C2: level-8 icosphere (655,362 vertices), 10% jitter, 30% land mask
+    (40 caps), one k^-3 field, n = 2 (biharmonic), 20 scales (wavelengths
+    32h .. 2h): the batched mixed-precision form (auto tile width) against
+    the plain FP64 path one column at a time, same GPU, same call. The
+    matrix of K_2 (~8.5 M entries) and the vectors largely fit the 256 MB
+    Infinity Cache, so rates are not HBM rates."""
+    import torch
+
+    import workloads as W
+
+    s = W.icosphere(8, jitter=0.1, seed=1)
+    s = s.with_mask(W.land_mask(s, 0.3, n_blobs=40, seed=2))
+    phi = torch.from_numpy(np.asarray(W.sphere_k3_field(s, 1000, n_waves=512, device="cuda:0"))).to("cuda:0")
+    ks = W.log_scales(s.h, 20)
+    h = ifl.prepare_mesh(s, ifl.IFL_VERTEX_SCALAR, 2, precision=ifl.IFL_MIXED, device=0)
+    res = {"workload": f"icosphere-L8 {s.n_vertices} vertices, 30% land mask ({h.num_dofs} dofs), n=2, "
+                       f"1 k^-3 field x 20 scales (wavelengths 32h..2h)"}
+    out = torch.empty((1, ks.size, h.field_length), dtype=torch.float64, device="cuda:0")
+    for prec, batch, name in ((ifl.IFL_MIXED, 0, "mixed_batched"), (ifl.IFL_FP64, 1, "fp64_single_column")):
+        h.set_options(precision=prec, batch=batch)
+        h.filter(phi, ks[:2], out=out[:, :2])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = h.filter(phi, ks, out=out)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        res[name] = {"solves_per_s": round(ks.size / el, 2),
+                     "mean_cg_iterations": round(sum(x.iterations for x in st) / len(st), 1),
+                     "max_cg_iterations": int(max(x.iterations for x in st)),
+                     "fp64_replacements": int(sum(x.refinements for x in st))}
+    res["speedup_mixed_batched_vs_plain_fp64"] = round(res["mixed_batched"]["solves_per_s"] /
+                                                       res["fp64_single_column"]["solves_per_s"], 3)
+    h.close()
+    return res
+
+
 def serve_leg(args, ifl):
-    """Continuous-batching server on resident prepared meshes, fed by a
-    Poisson arrival stream; returns latency percentiles and solves/s."""
+    """Continuous-batching server (C5): resident prepared meshes (icosphere
+    levels 6..10, 30% land, each prepared for n = 1 and n = 2, mixed
+    precision, 8 column slots per mesh), a memory budget for admission, and
+    Poisson arrival streams. Each request: a uniform mesh handle, 1-32
+    log-uniform scales in [2h, 32h] wavelengths, a field from a pool of 4 per
+    mesh. Streams: (1) the stated one, 200 warm-up + 2,000 measured requests
+    at 200 req/s, spectrum-only (the energies of the filtered fields, so that
+    an overloaded queue does not hold up to 32 x 84 MB of outputs per
+    level-10 request); (2) a stream below capacity with the filtered fields
+    returned. Then a like-for-like comparison on one request sample (served,
+    fields returned, vs the plain FP64 path one column at a time), and the
+    out-of-cache SpMV rates on the level-10 mesh."""
+    import threading
+
     import torch
 
     import workloads as W
 
     levels = [int(x) for x in args.serve_levels.split(",") if x]
-    rng = np.random.default_rng(11)
+    rng = np.random.default_rng(7)
     handles, meshes, pools = [], [], []
     t0 = time.time()
     for L in levels:
@@ -269,71 +357,200 @@ def serve_leg(args, ifl):
                                             graphs=0 if args.no_graphs else 1))
             meshes.append((L, n, s.h))
             pools.append(pool)
-    log(f"serving: {len(handles)} resident handles prepared in {time.time() - t0:.1f}s")
-    srv = ifl.Server(64 << 30, slots=args.serve_slots)
+        log(f"serving: level {L} prepared ({time.time() - t0:.1f}s)")
+    prep_s = time.time() - t0
+    srv = ifl.Server(int(args.serve_budget_gib * (1 << 30)), slots=args.serve_slots)
     ids = [srv.add(h) for h in handles]
-    # warm every worker once
-    for i, (L, n, h) in enumerate(meshes):
+    for i, (L, n, h) in enumerate(meshes):  # warm every worker once
         t, _ = srv.submit(ids[i], pools[i][0], np.array([2 * math.pi / (4 * h)]))
         srv.wait(t, 1)
-    def stream(rate, N):
-        # uniform mesh and order, 1-32 log-spaced scales in [2h, 32h] wavelengths
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, N))
+
+    def draw(N):
         reqs = []
-        for r in range(N):
+        for _ in range(N):
             i = int(rng.integers(len(handles)))
             L, n, h = meshes[i]
             ns = int(rng.integers(1, 33))
             ks = np.sort(np.exp(rng.uniform(math.log(2 * math.pi / (32 * h)), math.log(2 * math.pi / (2 * h)), ns)))
             reqs.append((i, int(rng.integers(4)), ks))
+        return reqs
+
+    def stream(rate, reqs, warmup, spectrum_only):
+        # a waiter thread takes the tickets in submission order while the
+        # arrivals go on, so finished outputs are dropped at once
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+        box = []
+        cv = threading.Condition()
+        done = {}
+
+        def waiter():
+            k = 0
+            while k < len(reqs):
+                with cv:
+                    while len(box) <= k:
+                        cv.wait()
+                    t, ns, i, t_sub = box[k]
+                st, stats, out, lat = srv.wait(t, ns)
+                done[k] = (st, ns, i, lat, sum(x.iterations for x in stats), t_sub + lat)
+                del out
+                k += 1
+
+        th = threading.Thread(target=waiter)
+        th.start()
         torch.cuda.synchronize()
-        tickets = []
         t_start = time.perf_counter()
+        lag = 0.0
         for r, (i, f, ks) in enumerate(reqs):
             delay = arrivals[r] - (time.perf_counter() - t_start)
             if delay > 0:
                 time.sleep(delay)
-            t, out = srv.submit(ids[i], pools[i][f], ks)
-            tickets.append((t, ks.size, i))
-        lat, solves, iters, bad = [], 0, 0, 0
+            else:
+                lag = max(lag, -delay)
+            t_sub = time.perf_counter() - t_start
+            t, _ = srv.submit(ids[i], pools[i][f], ks, spectrum_only=spectrum_only)
+            with cv:
+                box.append((t, ks.size, i, t_sub))
+                cv.notify()
+        th.join()
+        meas = [done[k] for k in range(warmup, len(reqs))]
+        t_first = float(arrivals[warmup])
+        t_last = max(x[5] for x in meas)
+        span = t_last - t_first
+        lat = np.array([x[3] for x in meas])
         per = {}
-        for t, ns, i in tickets:
-            st, stats, out, lt = srv.wait(t, ns)
-            del out
-            bad += st != 0
-            lat.append(lt)
-            solves += ns
-            iters += sum(x.iterations for x in stats)
-            per.setdefault(meshes[i][:2], []).append(lt)
-        el = time.perf_counter() - t_start
-        lat = np.array(lat)
+        for x in meas:
+            per.setdefault(meshes[x[2]][:2], []).append(x[3])
+        solves = sum(x[1] for x in meas)
         return {
             "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
             "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-            "solves_per_s": round(solves / el, 2),
-            "requests": N,
-            "failed": int(bad),
+            "solves_per_s": round(solves / span, 2),
+            "requests": len(meas),
+            "warmup_requests": warmup,
+            "failed": int(sum(x[0] != 0 for x in meas)),
             "offered_rate_req_s": rate,
-            "completed_rate_req_s": round(N / el, 2),
-            "arrival_window_s": round(float(arrivals[-1]), 3),
-            "drain_s": round(el, 3),
+            "achieved_rate_req_s": round(len(meas) / span, 2),
+            "arrival_window_s": round(float(arrivals[-1] - arrivals[warmup]), 3),
+            "measured_span_s": round(span, 3),
+            "max_submit_lag_s": round(lag, 4),
             "solves": int(solves),
-            "mean_cg_iterations": round(iters / max(1, solves), 1),
+            "mean_cg_iterations": round(sum(x[4] for x in meas) / max(1, solves), 1),
             "p50_latency_ms_by_mesh": {f"L{L}-n{n}": round(float(np.percentile(v, 50)) * 1e3, 1)
                                        for (L, n), v in sorted(per.items())},
-            "workload": f"Poisson arrivals, {N} requests at {rate:g}/s over icosphere levels "
-                        f"{args.serve_levels} (30% land mask) x n in {{1,2}}, 1-32 scales each, mixed precision, "
-                        f"{args.serve_slots} slots per mesh",
+            "outputs": "spectrum only (energies)" if spectrum_only else "filtered fields to host",
         }
 
-    res = stream(args.serve_rate, args.serve_requests)
-    log(f"serving at {args.serve_rate:g}/s: {res}")
+    res = {"workload": f"icosphere levels {args.serve_levels} (30% land mask) x n in {{1,2}}, "
+                       f"{args.serve_slots} slots per mesh, mixed precision, 1-32 log-uniform scales per request",
+           "prepare_s": round(prep_s, 1), "budget_bytes": int(args.serve_budget_gib * (1 << 30))}
+    res["stream"] = stream(args.serve_rate, draw(args.serve_warmup + args.serve_requests), args.serve_warmup, True)
+    q = srv.query()
+    res["memory"] = {"tiles_bytes": q["tiles"], "peak_request_bytes": q["peak_used"],
+                     "peak_in_flight": q["peak_in_flight"]}
+    log(f"serving at {args.serve_rate:g}/s: {res['stream']}")
     if args.serve_sustained_rate > 0 and args.serve_sustained_requests > 0:
-        res["sustained"] = stream(args.serve_sustained_rate, args.serve_sustained_requests)
+        res["sustained"] = stream(args.serve_sustained_rate, draw(args.serve_sustained_requests), 0, False)
+        log(f"serving at {args.serve_sustained_rate:g}/s: {res['sustained']}")
+    # like-for-like: one request sample, served (fields returned) and plain FP64
+    cmp_reqs = draw(args.serve_compare) if args.serve_compare > 0 else []
+    if cmp_reqs:
+        t = time.perf_counter()
+        tl = [srv.submit(ids[i], pools[i][f], ks) for (i, f, ks) in cmp_reqs]
+        for (tk, _), (_, _, ks) in zip(tl, cmp_reqs):
+            srv.wait(tk, ks.size)
+        served_s = time.perf_counter() - t
     srv.close()
+    if cmp_reqs:
+        solves = sum(ks.size for (_, _, ks) in cmp_reqs)
+        t = time.perf_counter()
+        for (i, f, ks) in cmp_reqs:
+            h = handles[i]
+            h.set_options(precision=ifl.IFL_FP64, batch=1)
+            h.filter(pools[i][f], ks)
+        plain_s = time.perf_counter() - t
+        for h in handles:
+            h.set_options(precision=ifl.IFL_MIXED, batch=0)
+        res["like_for_like"] = {"requests": len(cmp_reqs), "solves": int(solves),
+                                "served_mixed_solves_per_s": round(solves / served_s, 2),
+                                "plain_fp64_single_column_solves_per_s": round(solves / plain_s, 2),
+                                "speedup": round(plain_s / served_s, 3),
+                                "what": "the same requests (fields to host) served together by the server vs "
+                                        "one ifl_filter call per request with the plain FP64 path"}
+        log(f"serving like-for-like: {res['like_for_like']}")
+    # out-of-cache SpMV rates: the level-10 mesh (n = 1) of the server
+    if 10 in levels:
+        i10 = meshes.index(next(m for m in meshes if m[0] == 10 and m[1] == 1))
+        h = handles[i10]
+        L, _, hh = meshes[i10]
+        ks = np.array([2 * math.pi / (16 * hh), 2 * math.pi / (8 * hh)])
+        f = torch.from_numpy(pools[i10][0]).to("cuda:0")
+        dst = torch.empty((1, 2, h.field_length), dtype=torch.float64, device="cuda:0")
+        sp = {"dofs": h.num_dofs}
+        for prec, name in ((ifl.IFL_FP64, "fp64_single_column"), (ifl.IFL_MIXED, "fp32_single_column")):
+            h.set_options(precision=prec, batch=1, profile=1)
+            h.filter(f, ks[:1], out=dst[:, :1])
+            h.profile_read(reset=True)
+            h.filter(f, ks, out=dst)
+            n_l, ms, b = h.profile_read(reset=True)
+            us = ms / max(n_l, 1) * 1e3
+            sp[name] = {"kernel": h.profile_kernel(), "mean_launch_us": round(us, 2), "bytes_per_launch": round(b),
+                        "GBs": round(b / (us * 1e3), 1) if n_l else None,
+                        "frac_of_hbm_peak": round(b / (us * 1e3) / HBM_PEAK_GBS, 4) if n_l else None,
+                        "launches": n_l}
+        h.set_options(precision=ifl.IFL_MIXED, batch=0, profile=0)
+        res["spmv_level10"] = sp
+        log(f"level-10 SpMV: {sp}")
     for h in handles:
         h.close()
     return res
+
+
+def _oracle_worker(task):
+    level, mask, field, ks, js, budget = task
+    import oracle as O
+    import workloads as W
+
+    s = W.icosphere(level, jitter=0.1, seed=1)
+    s = s.with_mask(W.land_mask(s, mask, n_blobs=40, seed=2))
+    op = O.scalar_operator(s, 1)
+    t0 = time.time()
+    done = 0
+    for j in js:
+        O.filter_scalar(op, field, [ks[j]])
+        done += 1
+        if time.time() - t0 > budget:
+            break
+    return done, time.time() - t0
+
+
+def cpu_parallel(level, mask, field, ks, budget_s, workers):
+    """The oracle on all host cores: one worker process per core (started
+    fresh, single-threaded), each solving its own columns of field 0 for
+    about budget_s seconds; aggregate solves/s."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    order = []
+    lo, hi = 0, len(ks) - 1
+    while lo <= hi:
+        order.append(lo)
+        if hi != lo:
+            order.append(hi)
+        lo, hi = lo + 1, hi - 1
+    tasks = [(level, mask, field, ks, order[w::workers] or order[:1], budget_s) for w in range(workers)]
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
+    try:
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            out = list(ex.map(_oracle_worker, tasks))
+    finally:
+        for k, v in env.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return sum(d / el for d, el in out if el > 0), sum(d for d, _ in out)
 
 
 def main():
@@ -356,21 +573,28 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-spmv-leg", action="store_true", help="skip the SpMV rates on the unmasked level-9 mesh")
     ap.add_argument("--no-vector-leg", action="store_true", help="skip the velocity filtering on the level-8 mesh")
-    ap.add_argument("--leg", choices=["velocity", "spmv"], default=None,
+    ap.add_argument("--leg", choices=["velocity", "spmv", "c1", "c2", "serve"], default=None,
                     help="run only this leg and print its JSON (for profiling one leg on its own)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured chunks")
-    ap.add_argument("--serve-levels", default="6,7,8,9",
+    ap.add_argument("--serve-levels", default="6,7,8,9,10",
                     help="icosphere levels of the resident meshes (each prepared for n = 1 and n = 2)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-requests", type=int, default=300, help="requests in the arrival stream")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests in the arrival stream")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="requests of the stream before the measured ones")
     ap.add_argument("--serve-slots", type=int, default=8, help="column slots per resident mesh")
-    ap.add_argument("--serve-sustained-rate", type=float, default=15.0,
-                    help="second arrival stream, below the server's capacity (requests/s; 0 = skip)")
-    ap.add_argument("--serve-sustained-requests", type=int, default=150)
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="device memory budget of the server")
+    ap.add_argument("--serve-sustained-rate", type=float, default=8.0,
+                    help="second arrival stream, below the server's capacity, fields returned (req/s; 0 = skip)")
+    ap.add_argument("--serve-sustained-requests", type=int, default=100)
+    ap.add_argument("--serve-compare", type=int, default=16,
+                    help="requests of the served vs plain FP64 comparison (0 = skip)")
+    ap.add_argument("--no-c1c2", action="store_true", help="skip the C1 and C2 legs")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="worker processes of the all-cores oracle timing (0 = min(16, host CPUs))")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="first run a plain device copy of this size (a known-traffic kernel for "
-                         "calibrating HBM byte counters)")
+                    help="first run the library's plain device copy of this size (a known-traffic kernel "
+                         "for calibrating HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the filter's independent "
@@ -385,18 +609,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     if args.leg is not None:
-        res = vector_leg(ifl) if args.leg == "velocity" else spmv_leg(ifl)
-        print(json.dumps({"leg": args.leg, **res}), flush=True)
+        fn = {"velocity": vector_leg, "spmv": spmv_leg, "c1": c1_leg, "c2": c2_leg,
+              "serve": lambda m: serve_leg(args, m)}[args.leg]
+        print(json.dumps({"leg": args.leg, **fn(ifl)}), flush=True)
         return
     if args.copy_probe_mib > 0:
-        n = args.copy_probe_mib * (1 << 20) // 8
-        a = torch.ones(n, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"copy probe: 3 x {args.copy_probe_mib} MiB device copies")
-        del a, b
+        # two dispatches of the library's copy kernel (k_stream_copy) of known size
+        ifl.stream_probe(0, args.copy_probe_mib, 1)
+        log(f"copy probe: 2 x {args.copy_probe_mib} MiB device copies (k_stream_copy)")
     mesh, fields_h, ks = make_workload(args.level, args.mask, args.fields, args.scales, dev)
     precision = ifl.IFL_MIXED if args.precision == "mixed" else ifl.IFL_FP64
     t0 = time.time()
@@ -510,22 +730,12 @@ def main():
     h.filter(fields[0:1], ks, out=out[:1])
     torch.cuda.synchronize()
     h.close()
-    # the practical streaming rate of this GPU: a plain 1 GiB device copy
-    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-    b = torch.empty_like(a)
-    a.fill_(1.0)
-    times = []
-    for _ in range(5):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1) / 1e3)
-    copy_gbs = 2 * a.numel() * 8 / float(np.median(times)) / 1e9
-    del a, b
-    res["roofline"]["copy_probe_GBs"] = round(copy_gbs, 1)
-    res["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    # the practical streaming rate of this GPU: the library's own copy probe
+    # (4 GiB, 16 bytes per thread, every resident workgroup), best of 10
+    best, med = ifl.stream_probe(0, 4096, 10)
+    res["roofline"]["copy_probe_GBs"] = round(best, 1)
+    res["roofline"]["copy_probe_median_GBs"] = round(med, 1)
+    res["roofline"]["frac_of_copy"] = round(achieved / best, 4)
     # the legs below are reported on their own: a library error in one of
     # them is recorded in its place instead of losing the whole line
     if not args.no_spmv_leg:
@@ -535,6 +745,14 @@ def main():
         except ifl.IflError as e:
             res["spmv_2.6M_vertices"] = {"error": str(e)}
         log(f"spmv: {res['spmv_2.6M_vertices']}")
+    if not args.no_c1c2:
+        for name, fn in (("c1_planar_64x64", c1_leg), ("c2_level8_biharmonic", c2_leg)):
+            log(f"{name} leg ...")
+            try:
+                res[name] = fn(ifl)
+            except ifl.IflError as e:
+                res[name] = {"error": str(e)}
+            log(f"{name}: {res[name]}")
     if not args.no_vector_leg:
         log("velocity leg on the level-8 mesh ...")
         try:
@@ -554,6 +772,18 @@ def main():
         parity, res["cpu_baseline"] = cpu_baseline(mesh, fields_h, ks, args.cpu_budget,
                                                    gpu_column=lambda j: out[0, j].cpu().numpy())
         res["parity_sample"] = parity
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        if workers > 1:
+            log(f"timing the CPU oracle on {workers} worker processes ...")
+            one = res["cpu_baseline"]
+            rate, done = cpu_parallel(args.level, args.mask, fields_h[0], ks, args.cpu_budget, workers)
+            res["cpu_baseline"] = {
+                "value": rate, "unit": "solves/s", "cores": workers, "kind": "oracle",
+                "sample": f"{done} solves of field 0 spread over {workers} single-threaded worker processes (one per "
+                          f"core, each building the oracle's operator first, not counted), ~{args.cpu_budget:g}s each, "
+                          f"same mesh and scales as the single-thread figure",
+                "single_thread": one,
+            }
     print(json.dumps(res), flush=True)
 
 

@@ -112,6 +112,7 @@ typedef struct ifl_solve_stats {
   int32_t reserved;
   double rel_residual;  /* final ||M phi - S x|| / ||M phi||, FP64 on the GPU */
   double seconds;       /* wall time of the solve (of its tile when batched) */
+  double energy;        /* filtered energy of the column, 1/2 sum M x^2 / sum M (the spectra of Sect. 4) */
 } ifl_solve_stats;
 
 typedef struct ifl_handle ifl_handle;
@@ -323,11 +324,23 @@ ifl_status ifl_profile_read(ifl_handle* h, int64_t* launches, double* total_ms,
 
 /*
  * Name of the SpMV kernel of the last timed launch, as a profiler lists it
- * (e.g. "kb_dir_spmv<float, 32>"), NUL-terminated in buf (len bytes, the
+ * (e.g. "kb_iter<float, 32, true, 6>"), NUL-terminated in buf (len bytes, the
  * name truncated to fit); "" before the first timed launch. IFL_EINVAL for
  * a NULL handle or buffer, IFL_EDEVICE for a host-only handle.
  */
 ifl_status ifl_profile_kernel(ifl_handle* h, char* buf, int32_t len);
+
+/*
+ * Measured streaming bandwidth of a device, for roofline reports: a plain
+ * copy of 'bytes' bytes (rounded down to 16-byte units; at least 16 MiB)
+ * between two device buffers the call allocates and frees, each thread
+ * moving 16 bytes per step of a grid-stride loop over all resident
+ * workgroups. Runs 'reps' timed copies (HIP events, after one untimed) and
+ * returns the best and the median rate in GB/s (read + write bytes / time).
+ * Not part of the filter; IFL_EINVAL on a bad argument, IFL_ENOMEM /
+ * IFL_EDEVICE on a device failure.
+ */
+ifl_status ifl_stream_probe(int32_t device, int64_t bytes, int32_t reps, double* best_gbs, double* median_gbs);
 
 /*
  * Autotuner of the batched engine (the multi-column CG of Sect. 2.2.2 run as
@@ -373,11 +386,16 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* h, int32_t* mesh_id);
 
 /*
  * Queue one request: field (host, L doubles) filtered at n_scales
- * wavenumbers into out (host, n_scales x L). Returns at once; the field is
- * copied, out must stay valid until ifl_wait returns for the ticket.
- * Solves are admitted into the mesh's running tile as slots and memory
- * free up; each result is the same as a standalone ifl_filter within the
- * handle's tolerance.
+ * wavenumbers into out (host, n_scales x L), or, with out = NULL, into the
+ * filtered energies only (the spectrum of Sect. 4, in the stats ifl_wait
+ * fills). Returns at once. field and out are borrowed: both must stay
+ * valid and unchanged until ifl_wait returns for the ticket (the field is
+ * read when the request is admitted). Solves are admitted into the mesh's
+ * running tile as slots and memory free up; each result is the same as a
+ * standalone ifl_filter within the handle's tolerance. A NaN or Inf at a
+ * wet entry of the field fails the request with IFL_EINVAL (reported by
+ * ifl_wait). out entries are written only for converged or ENOTCONV
+ * columns.
  */
 ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field,
                       int32_t n_scales, const double* k, double* out, ifl_ticket** ticket);

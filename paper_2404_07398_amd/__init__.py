@@ -42,4 +42,5 @@ from ._ffi import (  # noqa: F401
     ifl_spectrum,
     lib,
     prepare_mesh,
+    stream_probe,
 )

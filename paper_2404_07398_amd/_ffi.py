@@ -83,6 +83,7 @@ class ifl_solve_stats(C.Structure):
         ("reserved", C.c_int32),
         ("rel_residual", C.c_double),
         ("seconds", C.c_double),
+        ("energy", C.c_double),
     ]
 
 
@@ -145,6 +146,8 @@ _PROTOS = {
     "ifl_profile_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_int32]),
     "ifl_profile_kernel": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32]),
+    "ifl_stream_probe": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]),
     "ifl_autotune": (C.c_int32, [C.c_void_p, C.POINTER(ifl_tune)]),
     "ifl_server_create": (C.c_int32, [C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]),
     "ifl_server_add": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -449,6 +452,14 @@ def ifl_destroy(h: Handle):
     h.close()
 
 
+def stream_probe(device: int = 0, mib: int = 4096, reps: int = 10):
+    """Best and median GB/s of a plain device copy of ``mib`` MiB
+    (``ifl_stream_probe``)."""
+    best, med = C.c_double(), C.c_double()
+    _check(lib().ifl_stream_probe(int(device), int(mib) << 20, int(reps), C.byref(best), C.byref(med)))
+    return float(best.value), float(med.value)
+
+
 def ifl_last_error() -> str:
     return lib().ifl_last_error().decode(errors="replace")
 
@@ -468,19 +479,26 @@ class Server:
         self._len[int(mid.value)] = h.field_length
         return int(mid.value)
 
-    def submit(self, mesh_id: int, field: np.ndarray, ks, out: np.ndarray | None = None):
+    def submit(self, mesh_id: int, field: np.ndarray, ks, out: np.ndarray | None = None,
+               spectrum_only: bool = False):
+        """Queue a request; returns (ticket, out). With spectrum_only the
+        filtered fields are not returned (out is None) and the energies are
+        in the stats of wait(). field (and out) are kept alive here until
+        wait(), as the server reads them until then."""
         field = np.ascontiguousarray(field, dtype=np.float64)
         ks = np.ascontiguousarray(ks, dtype=np.float64)
         L = self._len.get(int(mesh_id))
         if L is not None and field.size != L:
             raise ValueError(f"field has {field.size} entries, the mesh's fields have {L}")
-        if out is None:
-            out = np.zeros((ks.size, field.size))
+        if spectrum_only:
+            out = None
+        elif out is None:
+            out = np.empty((ks.size, field.size))
         elif out.size != ks.size * field.size or out.dtype != np.float64 or not out.flags.c_contiguous:
             raise ValueError("out must be a C-contiguous float64 array of n_scales x field length")
         t = C.c_void_p()
         _check(lib().ifl_submit(self._s, int(mesh_id), C.c_void_p(field.ctypes.data), ks.size, _dptr(ks),
-                                C.c_void_p(out.ctypes.data), C.byref(t)))
+                                C.c_void_p(out.ctypes.data if out is not None else None), C.byref(t)))
         self._keep[t.value] = (field, ks, out)
         return t, out
 

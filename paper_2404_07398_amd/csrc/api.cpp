@@ -346,6 +346,13 @@ ifl_status ifl_profile_kernel(ifl_handle* h, char* buf, int32_t len) {
   return IFL_OK;
 }
 
+ifl_status ifl_stream_probe(int32_t device, int64_t bytes, int32_t reps, double* best_gbs, double* median_gbs) {
+  if (!best_gbs || !median_gbs) return fail(IFL_EINVAL, "output pointer is NULL");
+  if (bytes < (16ll << 20)) return fail(IFL_EINVAL, "the probe copies at least 16 MiB");
+  if (reps < 1 || reps > 1000) return fail(IFL_EINVAL, "reps must be in 1..1000");
+  return device_stream_probe(device, bytes, reps, best_gbs, median_gbs);
+}
+
 ifl_status ifl_autotune(ifl_handle* h, ifl_tune* out) {
   if (!h) return fail(IFL_EINVAL, "handle is NULL");
   if (!h->dev) return fail(IFL_EDEVICE, "host-only handle (device = -1)");

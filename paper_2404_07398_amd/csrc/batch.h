@@ -50,6 +50,7 @@ struct BatchMatrix {
   int64_t field_len = 0;
   int G = 1;   // blocks of the kernels that gather (SpMV, replacement, start, finish)
   int Gu = 1;  // blocks of the streaming update kernel
+  int head = 6;  // off-diagonal entries per row in the gathering kernels' pipelined head (6, 12 or 20)
 };
 
 struct BatchParams {
@@ -59,11 +60,10 @@ struct BatchParams {
   bool graphs = true;             // replay whole chunks as captured HIP graphs
 };
 
-// Algorithmic bytes of one batched SpMV launch of the recurrence form (the
-// second to fourth iteration of a chunk, the one batch_iterate times) with
-// 'live' active columns: the sliced-ELL stream, mass and diagonal, and per
-// live column the reads of z, p and the previous q (each once) and the
-// writes of p and q.
+// Algorithmic bytes of one launch of the fused iteration kernel (the second
+// to fourth iteration of a chunk, the one batch_iterate times) with 'live'
+// active columns: the sliced-ELL stream, mass and diagonal, and per live
+// column the reads of z, u and p (each once) and the writes of z, u and p.
 double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, int live);
 
 // Device work space of one tile of R slots (vectors rows x R).
@@ -72,9 +72,11 @@ struct BatchWork {
   int G = 0, Gu = 0;  // grid sizes the work space (partial-sum array) was made for
   bool mixed = false;
   // p cycles through kChunk buffers, so that the directions of a whole
-  // chunk are still there when x is updated at its last iteration
-  float *z32 = nullptr, *p32[kChunk] = {}, *q32 = nullptr;
-  double *z64 = nullptr, *p64[kChunk] = {}, *q64 = nullptr;
+  // chunk are still there when x is updated at its last iteration; z and
+  // u = diag(S)^-1 S p alternate between two buffers (an iteration gathers
+  // the previous ones while it writes the new)
+  float *z32[2] = {}, *u32[2] = {}, *p32[kChunk] = {};
+  double *z64[2] = {}, *u64[2] = {}, *p64[kChunk] = {};
   double* x = nullptr;    // FP64 solution, rows x R (updated once per chunk)
   double* phi = nullptr;  // FP64 fields, rows x R
   double* part = nullptr; // per-(quantity, column, block) partial sums

@@ -58,7 +58,7 @@ constexpr int kUnroll = 8;        // sliced-ELL entries loaded together per row
 constexpr double kU = 1.1102230246251565e-16;
 constexpr double kFloor = 8.0;
 
-enum { Q_PQ = 0, Q_RZ, Q_RR, Q_BB, Q_FL, Q_EN, Q_COUNT };
+enum { Q_PQ = 0, Q_RZ, Q_RR, Q_BB, Q_FL, Q_EN, Q_ZU, Q_UU, Q_COUNT };
 
 // Lane geometry of a tile of R columns of type T.
 template <typename T, int R>
@@ -97,9 +97,9 @@ struct BMat {
 
 template <typename T>
 struct BVec {
-  T* z;              // preconditioned residual diag(S)^-1 r
+  T* z[2];       // preconditioned residual diag(S)^-1 r (two buffers, see kb_iter)
+  T* u[2];       // diag(S)^-1 S p (two buffers)
   T* p[kChunk];  // directions of the chunk's iterations (p of iteration k in p[k])
-  T* q;
   double* x;     // FP64 solution
   double* phi;   // FP64 field per column
 };
@@ -240,7 +240,12 @@ struct Ident {
 };
 
 // ------------------------------------------------------------ iteration
-constexpr int kHead = 6;  // off-diagonal entries per row gathered in the pipelined head
+// Off-diagonal entries per row that the gathering kernels load in their
+// software-pipelined head: a class sized to the matrix (6 for the scalar
+// first-order operator on triangle meshes, 12 for the interleaved vertex
+// vectors, 20 for the biharmonic operator); rows with more entries finish
+// the rest in steps of the same width, unpipelined.
+constexpr int kHeadClasses[] = {6, 12, 20};
 
 __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
@@ -248,15 +253,27 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// p_new = z + beta p (own row and gathered neighbours), q = S p_new,
-// partial (p_new, q) per column.
+// One CG iteration per launch, with u = diag(S)^-1 S p in place of q = S p
+// (d = diag(S) = M + c diag(K_n), the Jacobi preconditioner; z = d^-1 r is
+// the residual state, r = d z is formed where it is needed):
 //
-// REC (iterations 1..3 of a chunk): q = S z + beta q_prev instead, which is
-// S p_new as well (S p_new = S z + beta S p and q_prev = S p), so only z is
-// gathered and q_prev is read on the row itself. The first iteration of
-// every chunk forms S p_new directly, so the rounding of the recurrence
-// never spans more than three iterations, and the FP64 residual
-// replacement of mixed tiles does not depend on it.
+//  FUSED (iterations 1..kChunk-1 of a chunk), given alpha_k and beta_{k+1}:
+//    z' = z - alpha_k u                 (own row and every gathered neighbour)
+//    p' = z' + beta_{k+1} p
+//    u' = z' + d^-1 c K_off z' + beta_{k+1} u   (= d^-1 S p', as S p = S z' + beta S p)
+//  so z and u are the only gathered operands, and the separate residual
+//  update of plain CG disappears: the kernel reads z, u, p and writes z', u',
+//  p' once per row.
+//  DIRECT (the first iteration of a chunk, after the FP64 residual
+//  replacement has set z): p' = z + beta p, u' = d^-1 S p' from p' of the
+//  row and its gathered neighbours, so the recurrence for u never spans more
+//  than a chunk.
+//
+// Partials per column (one grid-level reduction per iteration, finished by
+// kf_step): (p', q') = sum d p' u', sum d z' u', sum d u'^2, and (FUSED) rho =
+// (r', z') = sum d z'^2. From them, alpha = rho / (p', q') and the next rho =
+// (r - alpha q, z - alpha d^-1 q) = rho - 2 alpha (q, z) + alpha^2 (q, d^-1 q),
+// which gives beta for the next launch before the next z exists.
 //
 // The loop over a wavefront's tasks is software-pipelined so that a task
 // costs about one memory round trip instead of three. While the gathers of
@@ -265,18 +282,17 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 // values and own-row operands of task i + 1 are loaded, and they arrive
 // under the gathers of task i + 1. Vector memory operations complete in
 // issue order, so waiting for a batch of loads never waits for the loads
-// issued after it. Rows with more than kHead off-diagonal entries finish
-// the rest unpipelined (the biharmonic operator); the first-order operator
-// on triangle meshes has at most six.
-template <typename T, int R, bool REC>
-__global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                                  int k) {
+// issued after it.
+template <typename T, int R, bool FUSED, int H>
+__global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
+                                              int k) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
-  __shared__ double lds[1 * kWpb * R];
+  constexpr int NQ = FUSED ? 4 : 3;
+  __shared__ double lds[NQ * kWpb * R];
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
-  T beta[C], cc[C];
+  T alpha[C], beta[C], cc[C];
   double c64[C];
   bool on[C];
   bool any = false;
@@ -284,18 +300,26 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
   for (int c = 0; c < C; ++c) {
     const BSlot& sl = slots[j0 + c];
     on[c] = live(sl);
+    alpha[c] = on[c] ? (T)sl.alpha : (T)0;
     beta[c] = on[c] ? (T)sl.beta : (T)0;
     cc[c] = (T)sl.c;
     c64[c] = sl.c;
     any |= on[c];
   }
+  // buffers: the chunk's first iteration reads z[0] (set by the replacement)
+  // and writes u[0]; iteration k >= 1 reads z, u [(k - 1) & 1] and writes
+  // z, u [k & 1]
+  const int bin = FUSED ? ((k - 1) & 1) : 0, bout = FUSED ? (k & 1) : 0;
+  const T* __restrict__ zin = v.z[bin];
+  const T* __restrict__ uin = v.u[bin];
+  T* __restrict__ zout = v.z[bout];
+  T* __restrict__ uout = v.u[bout];
   const T* __restrict__ pin = v.p[(k + kChunk - 1) % kChunk];  // previous iteration's p
   T* __restrict__ pout = v.p[k];
-  const T* __restrict__ z = v.z;
   const T* __restrict__ val = bval<T>(m);
-  const auto dir = [&](int c, T zz, T pp) { return fma(beta[c], pp, zz); };
-  const auto zonly = [&](int, T zz, T) { return zz; };
-  double acc[1][C] = {};
+  // value of a gathered neighbour: z' (FUSED) or p' (DIRECT); g1 is u or p
+  const auto comb = [&](int c, T g0, T g1) { return FUSED ? fma(-alpha[c], g1, g0) : fma(beta[c], g1, g0); };
+  double acc[NQ][C] = {};
   if (any) {
     const Walk wk = task_walk(m.n_slices * LPR, G);
     const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
@@ -305,27 +329,27 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
     // of memory operations per iteration keeps the compiler's wait counts
     // exact), and their results are discarded
     auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
-    int32_t cu[kHead];
-    T vu[kHead];
-    Pack<T, C> zi, pi, qi;
+    int32_t cu[H];
+    T vu[H];
+    Pack<T, C> zi, ui, pi;
     double mi, kd;
     int64_t base, nb, ne;  // this task's slice base; next task's raw slice bounds
     int w;
     auto fetch_idx = [&](int64_t t, int64_t sb) {
       const int64_t l = (t * RPW + rsub) % kW;
 #pragma unroll
-      for (int u = 0; u < kHead; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
+      for (int u = 0; u < H; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
     };
     // values are loaded raw (entries past the width are masked where they
     // are used, so that no instruction consumes the loads early)
     auto fetch_rest = [&](int64_t t, int64_t sb) {
       const int64_t row = min(t * RPW + rsub, m.n_slices * kW - 1), l = row % kW;
 #pragma unroll
-      for (int u = 0; u < kHead; ++u) vu[u] = val[sb + (int64_t)u * kW + l];
+      for (int u = 0; u < H; ++u) vu[u] = val[sb + (int64_t)u * kW + l];
       const int64_t idx = row * R + j0;
-      zi = vload<T, C>(z + idx);
+      zi = vload<T, C>(zin + idx);
       pi = vload<T, C>(pin + idx);
-      if constexpr (REC) qi = vload<T, C>(v.q + idx);
+      if constexpr (FUSED) ui = vload<T, C>(uin + idx);
       mi = m.mass[row];
       kd = m.kdiag[row];
     };
@@ -344,12 +368,12 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
       const int32_t self = (int32_t)min(row, m.n - 1);
       // (a) gathers of this task; entries past the row's width (padding of
       // value 0) gather the row itself, a line that is loaded anyway
-      Pack<T, C> g0[kHead], g1[kHead];
+      Pack<T, C> g0[H], g1[H];
 #pragma unroll
-      for (int u = 0; u < kHead; ++u) {
+      for (int u = 0; u < H; ++u) {
         const int64_t off = (int64_t)(u < w ? cu[u] : self) * R + j0;
-        g0[u] = vload<T, C>(z + off);
-        if constexpr (!REC) g1[u] = vload<T, C>(pin + off);
+        g0[u] = vload<T, C>(zin + off);
+        g1[u] = vload<T, C>((FUSED ? uin : pin) + off);
       }
       const int64_t cbase = base;
       const int cw = w;
@@ -363,128 +387,92 @@ __global__ __launch_bounds__(kB) void kb_dir_spmv(BMat m, BVec<T> v, const BSlot
       nb = nb2;
       ne = ne2;
       // (d) this task's row (rows past the last dof are padding: zero mass,
-      // diagonal and entries; their p and q stay zero and are never read)
+      // diagonal and entries; their results are discarded)
       T a[C] = {};
 #pragma unroll
-      for (int u = 0; u < kHead; ++u) {
+      for (int u = 0; u < H; ++u) {
         const T vm = u < cw ? vu[u] : (T)0;
 #pragma unroll
-        for (int c = 0; c < C; ++c) a[c] = fma(vm, REC ? g0[u].v[c] : dir(c, g0[u].v[c], g1[u].v[c]), a[c]);
+        for (int c = 0; c < C; ++c) a[c] = fma(vm, comb(c, g0[u].v[c], g1[u].v[c]), a[c]);
       }
-      if (cw > kHead) {
-        if constexpr (REC)
-          row_product<T, T, R, C, false, decltype(zonly), kHead>(m, val, cbase, cw, row % kW, j0, z, z, zonly,
-                                                                          a, kHead);
-        else
-          row_product<T, T, R, C, true, decltype(dir), kHead>(m, val, cbase, cw, row % kW, j0, z, pin, dir, a,
-                                                                      kHead);
-      }
+      if (cw > H)
+        row_product<T, T, R, C, true, decltype(comb), H>(m, val, cbase, cw, row % kW, j0, zin,
+                                                         FUSED ? uin : pin, comb, a, H);
       const bool real = row < m.n;
       const int64_t idx = row * R + j0;
-      Pack<T, C> pn, qv;
+      Pack<T, C> zn, pn, un;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        pn.v[c] = fma(beta[c], pi.v[c], zi.v[c]);
-        const T d = (T)(mi + c64[c] * kd);
-        if constexpr (REC) qv.v[c] = fma(beta[c], qi.v[c], fma(d, zi.v[c], cc[c] * a[c]));
-        else qv.v[c] = fma(d, pn.v[c], cc[c] * a[c]);
-        const double pq = (double)pn.v[c] * (double)qv.v[c];
-        acc[0][c] += (on[c] && real) ? pq : 0.0;
+        const T d = real ? (T)(mi + c64[c] * kd) : (T)1;
+        zn.v[c] = FUSED ? fma(-alpha[c], ui.v[c], zi.v[c]) : zi.v[c];
+        pn.v[c] = fma(beta[c], pi.v[c], zn.v[c]);
+        const T su = zn.v[c] + (cc[c] * a[c]) / d;  // d^-1 S z' (FUSED) or d^-1 S p' - p' + z (DIRECT)
+        un.v[c] = FUSED ? fma(beta[c], ui.v[c], su) : pn.v[c] + (cc[c] * a[c]) / d;
+        const double dd = (double)d, uu = (double)un.v[c], zz = (double)zn.v[c];
+        const bool use = on[c] && real;
+        acc[0][c] += use ? dd * (double)pn.v[c] * uu : 0.0;
+        acc[1][c] += use ? dd * zz * uu : 0.0;
+        acc[2][c] += use ? dd * uu * uu : 0.0;
+        if constexpr (FUSED) acc[NQ - 1][c] += use ? dd * zz * zz : 0.0;
       }
-      vstore<T, C>(pout + idx, pn);
-      vstore<T, C>(v.q + idx, qv);
+      if (real) {
+        vstore<T, C>(pout + idx, pn);
+        vstore<T, C>(uout + idx, un);
+        if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
+      }
       // (e) values and own row of the next task
       fetch_rest(tn, base);
     }
   }
-  double tot[1];
-  col_sum<R, C, 1>(acc, lds, tot);
-  if (threadIdx.x < R) part[(Q_PQ * R + threadIdx.x) * Gp + lblock(G)] = tot[0];
+  double tot[NQ];
+  col_sum<R, C, NQ>(acc, lds, tot);
+  if (threadIdx.x < R) {
+    const int lb = lblock(G);
+    part[(Q_PQ * R + threadIdx.x) * Gp + lb] = tot[0];
+    part[(Q_ZU * R + threadIdx.x) * Gp + lb] = tot[1];
+    part[(Q_UU * R + threadIdx.x) * Gp + lb] = tot[2];
+    if constexpr (FUSED) part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[NQ - 1];
+  }
 }
 
-// z -= alpha q / diag(S) (the preconditioned residual is the stored state;
-// r = diag(S) z is formed where it is needed, so r is neither read nor
-// written); partials (r, z), (r, r) per column. At the last iteration of a
-// chunk (XUP) the chunk's x update is applied at once, in FP64 in every
-// precision, from the directions kept in p[0..3] and each column's alpha
-// history: x += sum_k alpha_k p_k. z of columns that are not iterating is
-// left unchanged. Every running column's residual is replaced right after
-// its chunk's x update, so the last iteration updates x only (no z, no
-// partials).
-template <typename T, bool XUP, int R>
-__global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                                int k) {
+// The chunk's x update, at its last iteration, in FP64 in every precision,
+// from the directions kept in p[0..3] and each column's alpha history: x +=
+// sum_k alpha_k p_k (alpha_k = 0 for a column that was not iterating).
+template <typename T, int R>
+__global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot* slots, int G) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
-  constexpr bool ZUP = !XUP;
-  __shared__ double lds[2 * kWpb * R];
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
-  T alpha[C];
-  double c64[C];
-  double ah[kChunk][C];  // alpha history (XUP)
-  bool on[C];
+  double ah[kChunk][C];
   bool any = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const BSlot& sl = slots[j0 + c];
-    on[c] = live(sl);
-    alpha[c] = on[c] ? (T)sl.alpha : (T)0;
-    c64[c] = sl.c;
-    any |= on[c];
 #pragma unroll
     for (int i = 0; i < kChunk; ++i) {
-      ah[i][c] = XUP ? sl.alpha_hist[i] : 0.0;
-      any |= XUP && ah[i][c] != 0.0;
+      ah[i][c] = sl.alpha_hist[i];
+      any |= ah[i][c] != 0.0;
     }
   }
-  double acc[2][C] = {};
-  if (any) {
-    for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
-      const int64_t row = wk.t * RPW + rsub;
-      if (row >= m.n) continue;
-      const int64_t idx = row * R + j0;
-      if constexpr (XUP) {
-        Pack<T, C> pk[kChunk];
+  if (!any) return;
+  for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
+    const int64_t row = wk.t * RPW + rsub;
+    if (row >= m.n) continue;
+    const int64_t idx = row * R + j0;
+    Pack<T, C> pk[kChunk];
 #pragma unroll
-        for (int i = 0; i < kChunk; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
-        Pack<double, C> xv = vload<double, C>(v.x + idx);
+    for (int i = 0; i < kChunk; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
+    Pack<double, C> xv = vload<double, C>(v.x + idx);
 #pragma unroll
-        for (int c = 0; c < C; ++c)
+    for (int c = 0; c < C; ++c)
 #pragma unroll
-          for (int i = 0; i < kChunk; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
-        vstore<double, C>(v.x + idx, xv);
-      }
-      if constexpr (!ZUP) continue;
-      const Pack<T, C> qv = vload<T, C>(v.q + idx);
-      Pack<T, C> zv = vload<T, C>(v.z + idx);
-      const double mi = m.mass[row], kd = m.kdiag[row];
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const T d = (T)(mi + c64[c] * kd);
-        const T zn = fma(-alpha[c], qv.v[c] / d, zv.v[c]);
-        zv.v[c] = on[c] ? zn : zv.v[c];
-        const T rr = d * zv.v[c];  // the residual r = diag(S) z
-        if (on[c]) {
-          acc[0][c] += (double)rr * (double)zv.v[c];
-          acc[1][c] += (double)rr * (double)rr;
-        }
-      }
-      vstore<T, C>(v.z + idx, zv);
-    }
-  }
-  if constexpr (ZUP) {
-    double tot[2];
-    col_sum<R, C, 2>(acc, lds, tot);
-    if (threadIdx.x < R) {
-      const int lb = lblock(G);
-      part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
-      part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
-    }
+      for (int i = 0; i < kChunk; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
+    vstore<double, C>(v.x + idx, xv);
   }
 }
 
-// FP64 residual passes, software-pipelined like kb_dir_spmv (the gathered
+// FP64 residual passes, software-pipelined like kb_iter (the gathered
 // operand is FP64: 16 B per lane and entry for FP64 tiles, 32 B for mixed).
 //
 // START (the columns in 'mask', scales cs): x = phi, p = 0 and the residual
@@ -499,7 +487,7 @@ __global__ __launch_bounds__(kB) void kb_update(BMat m, BVec<T> v, const BSlot* 
 // || |M phi| + |M x| + c |K_n| |x| ||^2. z of columns that are not running is
 // overwritten with values nothing reads (a column that enters is started
 // from scratch).
-template <typename T, int R, bool START>
+template <typename T, int R, bool START, int H>
 __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
                                                   int Gp, uint64_t mask, SlotScales cs) {
   using Gm = Geo<T, R>;
@@ -531,8 +519,8 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
     const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
     const int64_t last_slice = m.n_slices - 1;
     auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
-    int32_t cu[kHead];
-    double vu[kHead];
+    int32_t cu[H];
+    double vu[H];
     Pack<double, C> ph, xv;
     double mi, kd;
     int64_t base, nb, ne;
@@ -540,12 +528,12 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
     auto fetch_idx = [&](int64_t t, int64_t sb) {
       const int64_t l = (t * RPW + rsub) % kW;
 #pragma unroll
-      for (int u = 0; u < kHead; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
+      for (int u = 0; u < H; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
     };
     auto fetch_rest = [&](int64_t t, int64_t sb) {
       const int64_t row = min(t * RPW + rsub, m.n_slices * kW - 1), l = row % kW;
 #pragma unroll
-      for (int u = 0; u < kHead; ++u) vu[u] = m.val64[sb + (int64_t)u * kW + l];
+      for (int u = 0; u < H; ++u) vu[u] = m.val64[sb + (int64_t)u * kW + l];
       const int64_t idx = row * R + j0;
       ph = vload<double, C>(v.phi + idx);
       if constexpr (!START) xv = vload<double, C>(v.x + idx);
@@ -565,9 +553,9 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
     for (int64_t t = first; t < end; t += stride) {
       const int64_t row = t * RPW + rsub;
       const int32_t self = (int32_t)min(row, m.n - 1);
-      Pack<double, C> gx[kHead];
+      Pack<double, C> gx[H];
 #pragma unroll
-      for (int u = 0; u < kHead; ++u) gx[u] = vload<double, C>(src + (int64_t)(u < w ? cu[u] : self) * R + j0);
+      for (int u = 0; u < H; ++u) gx[u] = vload<double, C>(src + (int64_t)(u < w ? cu[u] : self) * R + j0);
       const int64_t cbase = base;
       const int cw = w;
       const int64_t tn = t + stride < end ? t + stride : t;
@@ -580,7 +568,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
       ne = ne2;
       double a[C] = {}, aa[C] = {};  // sum val x, sum |val| |x| (REPLACE)
 #pragma unroll
-      for (int u = 0; u < kHead; ++u) {
+      for (int u = 0; u < H; ++u) {
         const double vm = u < cw ? vu[u] : 0.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -588,12 +576,12 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
           if constexpr (!START) aa[c] = fma(fabs(vm), fabs(gx[u].v[c]), aa[c]);
         }
       }
-      if (cw > kHead) {
+      if (cw > H) {
         if constexpr (START)
-          row_product<double, double, R, C, false, decltype(ident), kHead>(
-              m, m.val64, cbase, cw, row % kW, j0, src, nullptr, ident, a, kHead);
+          row_product<double, double, R, C, false, decltype(ident), H>(
+              m, m.val64, cbase, cw, row % kW, j0, src, nullptr, ident, a, H);
         else
-          row_product_abs2<R, C, kHead>(m, cbase, cw, row % kW, j0, src, a, aa, kHead);
+          row_product_abs2<R, C, H>(m, cbase, cw, row % kW, j0, src, a, aa, H);
       }
       const bool real = row < m.n;
       const int64_t idx = row * R + j0;
@@ -604,7 +592,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
           Pack<T, C> zo, po = {};
           if (!all) {
             xo = vload<double, C>(v.x + idx);
-            zo = vload<T, C>(v.z + idx);
+            zo = vload<T, C>(v.z[0] + idx);
             po = vload<T, C>(pprev + idx);
           }
 #pragma unroll
@@ -621,7 +609,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
             acc[2][c] += (mi * ph.v[c]) * (mi * ph.v[c]);
           }
           vstore<double, C>(v.x + idx, xo);
-          vstore<T, C>(v.z + idx, zo);
+          vstore<T, C>(v.z[0] + idx, zo);
           vstore<T, C>(pprev + idx, po);
         }
       } else {
@@ -640,7 +628,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
             acc[2][c] += mag * mag;
           }
         }
-        if (real) vstore<T, C>(v.z + idx, zv);
+        if (real) vstore<T, C>(v.z[0] + idx, zv);
       }
       fetch_rest(tn, base);
     }
@@ -728,7 +716,7 @@ __global__ void kb_out(const double* __restrict__ x, OutPtrs out, uint64_t mask,
 
 // Columns of one tile into another of a different width (same precision), at
 // a chunk boundary: z, the chunk's last direction p[kChunk - 1] (the next
-// chunk's first SpMV forms q from it, so q is not carried), x and phi of
+// chunk's first iteration forms u from it, so u is not carried), x and phi of
 // each mapped column, one row per thread.
 struct ColMap {
   int n;
@@ -851,10 +839,15 @@ __device__ __forceinline__ double fin_sum(const double* a, int G, double* lds) {
   return t;
 }
 
-// phase 1 (after kb_dir_spmv): alpha = rho / (p, q), kept in the column's
-// alpha history at the chunk position k (0 for columns not iterating)
-__global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const double* part, int G, int Gp, int R,
-                                                         int k) {
+// After iteration k of a chunk (kb_iter): alpha_k = rho_k / (p, q), kept
+// in the column's alpha history at position k (0 for columns not
+// iterating); the next rho from the recurrence rho - 2 alpha (q, z) +
+// alpha^2 (q, d^-1 q), and beta = next rho / rho_k for the next launch. rho_k
+// is the exact (r, z) of the z the launch formed (k >= 1), or that of the
+// replacement or start (k = 0). No stopping test: a column is tested on its
+// replaced FP64 residual only, in kf_replace.
+__global__ __launch_bounds__(kFinThreads) void kf_step(BSlot* slots, const double* part, int G, int Gp, int R,
+                                                        int k) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
@@ -863,40 +856,29 @@ __global__ __launch_bounds__(kFinThreads) void kf_alpha(BSlot* slots, const doub
     return;
   }
   const double pq = fin_sum(part + (Q_PQ * R + j) * Gp, G, lds);
+  const double zu = fin_sum(part + (Q_ZU * R + j) * Gp, G, lds);
+  const double uu = fin_sum(part + (Q_UU * R + j) * Gp, G, lds);
+  const double rz = k > 0 ? fin_sum(part + (Q_RZ * R + j) * Gp, G, lds) : 0.0;
   if (threadIdx.x == 0) {
-    const double a = s.rho / pq;
+    const double rho = k > 0 ? rz : s.rho;
+    const double a = rho / pq;
+    s.iters += 1;
     if (!(pq > 0.0) || !isfinite(a)) {
       s.done = 2;
       s.alpha_hist[k] = 0.0;
     } else {
+      const double next = rho - 2.0 * a * zu + a * a * uu;
+      s.rho = rho;
       s.alpha = a;
       s.alpha_hist[k] = a;
+      s.beta = next / rho;
+      s.rr_true = 0;
     }
   }
 }
 
-// phase 2 (after kb_update, iterations 1..kChunk-1 of a chunk): rho and
-// beta; no stopping test (a column is tested on its replaced FP64 residual
-// only, in kf_replace)
-__global__ __launch_bounds__(kFinThreads) void kf_beta(BSlot* slots, const double* part, int G, int Gp, int R) {
-  __shared__ double lds[kFinThreads / kW];
-  const int j = blockIdx.x;
-  BSlot& s = slots[j];
-  if (!live(s)) return;
-  const double rz = fin_sum(part + (Q_RZ * R + j) * Gp, G, lds);
-  const double rr = fin_sum(part + (Q_RR * R + j) * Gp, G, lds);
-  if (threadIdx.x == 0) {
-    s.rho_prev = s.rho;
-    s.rho = rz;
-    s.beta = rz / s.rho_prev;
-    s.rr = rr;
-    s.iters += 1;
-    s.rr_true = 0;
-  }
-}
-
-// phase 2 of the last iteration in a chunk (after the x update and the
-// replacement pass): rho, beta from the replaced residual and the test
+// After the chunk's x update and its FP64 replacement pass: rho and beta
+// from the replaced residual, and the stopping test
 __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const double* part, int G, int Gp, int R,
                                                            int max_iter) {
   __shared__ double lds[kFinThreads / kW];
@@ -911,7 +893,6 @@ __global__ __launch_bounds__(kFinThreads) void kf_replace(BSlot* slots, const do
     s.rho = rz;
     s.beta = rz / s.rho_prev;
     s.rr = rr;
-    s.iters += 1;
     s.rr_true = 1;
     s.updates += 1;
     const double floor2 = fl * (kFloor * kU) * (kFloor * kU);
@@ -971,9 +952,9 @@ __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const dou
 template <typename T>
 BVec<T> bvec(BatchWork& w) {
   if constexpr (sizeof(T) == 4) {
-    return BVec<T>{w.z32, {w.p32[0], w.p32[1], w.p32[2], w.p32[3]}, w.q32, w.x, w.phi};
+    return BVec<T>{{w.z32[0], w.z32[1]}, {w.u32[0], w.u32[1]}, {w.p32[0], w.p32[1], w.p32[2], w.p32[3]}, w.x, w.phi};
   } else {
-    return BVec<T>{w.z64, {w.p64[0], w.p64[1], w.p64[2], w.p64[3]}, w.q64, w.x, w.phi};
+    return BVec<T>{{w.z64[0], w.z64[1]}, {w.u64[0], w.u64[1]}, {w.p64[0], w.p64[1], w.p64[2], w.p64[3]}, w.x, w.phi};
   }
 }
 
@@ -996,43 +977,56 @@ struct Grids {
   int G, Gu, Gp;
 };
 
+template <int R, int H>
+struct LaunchH {
+  template <typename T>
+  static void iter(const BMat& m, BatchWork& w, Grids g, hipStream_t s, int k) {
+    if (k == 0) kb_iter<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k);
+    else kb_iter<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k);
+  }
+  template <typename T>
+  static void replace(const BMat& m, BatchWork& w, Grids g, hipStream_t s) {
+    kb_residual<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, 0ull, SlotScales{});
+  }
+  template <typename T>
+  static void start(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs) {
+    kb_residual<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, mask, cs);
+  }
+};
+
 template <int R>
 struct Launch {
-  template <typename T>
-  static void dir_spmv(const BMat& m, BatchWork& w, Grids g, hipStream_t s, int k) {
-    if (k == 0) kb_dir_spmv<T, R, false><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k);
-    else kb_dir_spmv<T, R, true><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k);
+  template <typename T, typename F>
+  static void by_head(int head, F f) {
+    if (head <= 6) f(LaunchH<R, 6>{});
+    else if (head <= 12) f(LaunchH<R, 12>{});
+    else f(LaunchH<R, 20>{});
   }
-  // iteration k (0..kChunk-1) of a chunk; the last one applies the
-  // chunk's x update and the FP64 residual replacement of every running
-  // column, whose true residual is the only one that may stop a column (in
-  // both precisions: a recursive residual drifts from the true one when S
-  // is badly conditioned)
+  // iteration k (0..kChunk-1) of a chunk: one fused iteration kernel and its
+  // finalizer; the last one also applies the chunk's x update and the FP64
+  // residual replacement of every running column, whose true residual is
+  // the only one that may stop a column (in both precisions: a recursive
+  // residual drifts from the true one when S is badly conditioned)
   template <typename T>
-  static void update(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k) {
+  static void step(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k, int head) {
+    if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
+    by_head<T>(head, [&](auto L) { L.template iter<T>(m, w, g, s, k); });
+    if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
+    kf_step<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
     if (k == kChunk - 1) {
-      kb_update<T, true, R><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.Gu, g.Gp, k);
-      kb_residual<T, R, false><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, 0ull, SlotScales{});
+      kb_xupdate<T, R><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
+      by_head<T>(head, [&](auto L) { L.template replace<T>(m, w, g, s); });
       kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
-    } else {
-      kb_update<T, false, R><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.Gu, g.Gp, k);
-      kf_beta<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.Gu, g.Gp, R);
     }
   }
-  static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k) {
-    if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
-    if (w.mixed) dir_spmv<float>(m, w, g, s, k);
-    else dir_spmv<double>(m, w, g, s, k);
-    if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
-    kf_alpha<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
-    if (w.mixed) update<float>(m, w, g, s, prm, k);
-    else update<double>(m, w, g, s, prm, k);
+  static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k, int head) {
+    if (w.mixed) step<float>(m, w, g, s, prm, k, head);
+    else step<double>(m, w, g, s, prm, k, head);
   }
   static void init(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs,
-                   double rtol) {
-    if (w.mixed)
-      kb_residual<float, R, true><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask, cs);
-    else kb_residual<double, R, true><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask, cs);
+                   double rtol, int head) {
+    if (w.mixed) by_head<float>(head, [&](auto L) { L.template start<float>(m, w, g, s, mask, cs); });
+    else by_head<double>(head, [&](auto L) { L.template start<double>(m, w, g, s, mask, cs); });
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
   }
   static void finish(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const OutPtrs& out) {
@@ -1065,15 +1059,15 @@ void dispatch_R(int R, A&&... a) {
 
 template <int R>
 struct DoIterate {
-  static void run(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& p, int k) {
-    Launch<R>::iterate(m, w, g, s, p, k);
+  static void run(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& p, int k, int head) {
+    Launch<R>::iterate(m, w, g, s, p, k, head);
   }
 };
 template <int R>
 struct DoInit {
   static void run(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs,
-                  double rtol) {
-    Launch<R>::init(m, w, g, s, mask, cs, rtol);
+                  double rtol, int head) {
+    Launch<R>::init(m, w, g, s, mask, cs, rtol, head);
   }
 };
 template <int R>
@@ -1088,13 +1082,13 @@ int occupancy_of(int R) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (R) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 1, false>, kB, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 2, false>, kB, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 4, false>, kB, 0); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 8, false>, kB, 0); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 16, false>, kB, 0); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 32, false>, kB, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_dir_spmv<T, 64, false>, kB, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_iter<T, 1, true, 6>, kB, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_iter<T, 2, true, 6>, kB, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_iter<T, 4, true, 6>, kB, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_iter<T, 8, true, 6>, kB, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_iter<T, 16, true, 6>, kB, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_iter<T, 32, true, 6>, kB, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_iter<T, 64, true, 6>, kB, 0); break;
   }
   return e == hipSuccess ? nb : 0;
 }
@@ -1118,14 +1112,21 @@ int batch_lanes_per_row(int R, bool mixed) {
 ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   const size_t nr = (size_t)bm.n_pad * R;
   ifl_status st;
+  std::vector<void*> vecs;  // the precision's vectors, zeroed below
+  size_t es = 0;
   if (mixed) {
-    if ((st = dalloc_b(&w->z32, nr)) || (st = dalloc_b(&w->q32, nr))) return st;
-    for (float*& p : w->p32)
-      if ((st = dalloc_b(&p, nr))) return st;
+    es = sizeof(float);
+    for (float** p : {&w->z32[0], &w->z32[1], &w->u32[0], &w->u32[1], &w->p32[0], &w->p32[1], &w->p32[2], &w->p32[3]}) {
+      if ((st = dalloc_b(p, nr))) return st;
+      vecs.push_back(*p);
+    }
   } else {
-    if ((st = dalloc_b(&w->z64, nr)) || (st = dalloc_b(&w->q64, nr))) return st;
-    for (double*& p : w->p64)
-      if ((st = dalloc_b(&p, nr))) return st;
+    es = sizeof(double);
+    for (double** p :
+         {&w->z64[0], &w->z64[1], &w->u64[0], &w->u64[1], &w->p64[0], &w->p64[1], &w->p64[2], &w->p64[3]}) {
+      if ((st = dalloc_b(p, nr))) return st;
+      vecs.push_back(*p);
+    }
   }
   if ((st = dalloc_b(&w->x, nr)) || (st = dalloc_b(&w->phi, nr)) ||
       (st = dalloc_b(&w->part, (size_t)Q_COUNT * R * std::max(bm.G, bm.Gu))) || (st = dalloc_b(&w->slots, (size_t)R)) ||
@@ -1135,13 +1136,7 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   IFL_HIPB(hipMemset(w->slots, 0, sizeof(BSlot) * R));
   IFL_HIPB(hipMemset(w->x, 0, sizeof(double) * nr));
   IFL_HIPB(hipMemset(w->phi, 0, sizeof(double) * nr));
-  if (mixed) {
-    float* f32[] = {w->z32, w->p32[0], w->p32[1], w->p32[2], w->p32[3], w->q32};
-    for (float* p : f32) IFL_HIPB(hipMemset(p, 0, sizeof(float) * nr));
-  } else {
-    double* f64[] = {w->z64, w->p64[0], w->p64[1], w->p64[2], w->p64[3], w->q64};
-    for (double* p : f64) IFL_HIPB(hipMemset(p, 0, sizeof(double) * nr));
-  }
+  for (void* p : vecs) IFL_HIPB(hipMemset(p, 0, es * nr));
   // hipMemset of device memory may return before it completes, and the
   // tile's kernels run on streams that do not wait for the null stream
   IFL_HIPB(hipDeviceSynchronize());
@@ -1155,8 +1150,9 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
 
 void batch_free(BatchWork* w) {
   if (w->chunk_exec) (void)hipGraphExecDestroy(w->chunk_exec);
-  void* ptrs[] = {w->z32, w->p32[0], w->p32[1], w->p32[2], w->p32[3], w->q32, w->z64,  w->p64[0],
-                  w->p64[1], w->p64[2], w->p64[3], w->q64, w->x,     w->phi,    w->part, w->slots, w->flag};
+  void* ptrs[] = {w->z32[0], w->z32[1], w->u32[0], w->u32[1], w->p32[0], w->p32[1], w->p32[2], w->p32[3],
+                  w->z64[0], w->z64[1], w->u64[0], w->u64[1], w->p64[0], w->p64[1], w->p64[2], w->p64[3],
+                  w->x,      w->phi,    w->part,   w->slots,  w->flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w->slots_host) (void)hipHostFree(w->slots_host);
@@ -1164,7 +1160,7 @@ void batch_free(BatchWork* w) {
 }
 
 size_t batch_bytes(int64_t n_pad, int R, bool mixed) {
-  const size_t per = mixed ? (6 * 4 + 8 + 8) : (6 * 8 + 8 + 8);
+  const size_t per = mixed ? (8 * 4 + 8 + 8) : (8 * 8 + 8 + 8);
   return (size_t)n_pad * R * per;
 }
 
@@ -1233,14 +1229,14 @@ ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const 
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
   if (w.iter % kChunk != 0)
     return fail(IFL_EINVAL, "columns may only enter a tile at iterations that are multiples of kChunk");
-  dispatch_R<DoInit>(w.R, bmat(bm), w, grids(bm), s, mask, cs, rtol);
+  dispatch_R<DoInit>(w.R, bmat(bm), w, grids(bm), s, mask, cs, rtol, bm.head);
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
 }
 
 double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, int live) {
   const double vb = mixed ? 4.0 : 8.0;
-  return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 5.0 * vb * bm.n * live;
+  return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 6.0 * vb * bm.n * live;
 }
 
 // Capture one chunk (kChunk iterations, no timing events) into w.chunk_exec.
@@ -1255,7 +1251,7 @@ static ifl_status capture_chunk(const BMat& m, const BatchMatrix& bm, BatchWork&
   BatchParams p = prm;
   p.ev_begin = p.ev_end = nullptr;
   IFL_HIPB(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < kChunk; ++k) dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, p, k);
+  for (int k = 0; k < kChunk; ++k) dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, p, k, bm.head);
   hipGraph_t g = nullptr;
   const hipError_t e1 = hipStreamEndCapture(s, &g);
   const hipError_t e2 = hipGetLastError();
@@ -1300,7 +1296,7 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
       continue;
     }
     const int k = (int)(w.iter % kChunk);
-    dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, i == 1 ? prm : rest, k);
+    dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, i == 1 ? prm : rest, k, bm.head);
     ++w.iter;
     ++i;
   }
@@ -1338,10 +1334,10 @@ ifl_status batch_move_columns(const BatchMatrix& bm, BatchWork& src, BatchWork& 
   }
   const unsigned nb = (unsigned)((bm.n_pad + 255) / 256);
   if (src.mixed)
-    kb_move_cols<float><<<nb, 256, 0, s>>>(src.z32, src.p32[kChunk - 1], src.x, src.phi, src.R, dst.z32,
+    kb_move_cols<float><<<nb, 256, 0, s>>>(src.z32[0], src.p32[kChunk - 1], src.x, src.phi, src.R, dst.z32[0],
                                             dst.p32[kChunk - 1], dst.x, dst.phi, dst.R, map, bm.n_pad);
   else
-    kb_move_cols<double><<<nb, 256, 0, s>>>(src.z64, src.p64[kChunk - 1], src.x, src.phi, src.R, dst.z64,
+    kb_move_cols<double><<<nb, 256, 0, s>>>(src.z64[0], src.p64[kChunk - 1], src.x, src.phi, src.R, dst.z64[0],
                                              dst.p64[kChunk - 1], dst.x, dst.phi, dst.R, map, bm.n_pad);
   kf_move_slots<<<1, 64, 0, s>>>(src.slots, dst.slots, dst.R, map);
   IFL_HIPB(hipGetLastError());

@@ -11,13 +11,17 @@
 //    indices and values are read with fully coalesced 256 / 512 B wavefront
 //    loads; the diagonal of S = M + c diag(K_n) is formed once per solve and
 //    doubles as the Jacobi preconditioner.
-//  * One CG iteration is two kernels: (1) p = z + beta p fused into the SpMV
-//    q = S p together with the block partials of (p, q); (2) x += alpha p,
-//    r -= alpha q, z = r / diag(S) with the partials of (r, z) and (r, r).
+//  * One CG iteration is one kernel (k_cg): the residual update of the
+//    previous iteration is applied on the fly to the gathered operand
+//    (z' = z - alpha u, with u = diag(S)^-1 S p kept in place of S p), then
+//    x += alpha p, p' = z' + beta p and u' = diag(S)^-1 S p', with the block
+//    partials of the next iteration's sums: one grid-level reduction per
+//    iteration.
 //  * Reductions are deterministic two-level sums: every block writes one
-//    partial per quantity; the next kernel's blocks each finish the sum in
-//    the same fixed order, so all blocks agree bitwise on alpha / beta and
-//    on the stopping test without atomics or cross-XCD fences.
+//    partial per quantity; the next kernel's blocks each finish the sums in
+//    the same fixed order (all quantities in one pass), so all blocks agree
+//    bitwise on alpha / beta and on the stopping test without atomics or
+//    cross-XCD fences.
 //  * Logical blocks own contiguous row ranges and are mapped so that the
 //    blocks of one XCD (hardware dispatches workgroups round-robin over the
 //    8 XCDs) hold neighbouring ranges: neighbouring rows' gathers then hit
@@ -58,27 +62,24 @@ constexpr int kXcd = 8;
 constexpr int kMaxDevices = 64;
 constexpr int kUnroll = 8;                  // sliced-ELL entries loaded together per row
 
-// Per-column device scalars. Written by block 0 of a kernel, read by the
-// following kernels (kernel boundaries order them).
+// Per-column device state of the one-column path, in two copies: launch L
+// reads copy L & 1 and its block 0 writes copy (L + 1) & 1 (so no block of
+// a launch reads what that launch writes).
 struct Scalars {
   double tol2;      // rtol^2 ||M phi||^2
-  double rr_ref;    // mixed: ||r||^2 at the last FP64 residual replacement
+  double rr_ref;    // ||r||^2 of the last FP64 true residual (mixed: replacement trigger)
   double c;         // gamma / k^(2n)
   double rr_last;   // ||r||^2 seen by the last stopping test
   double res2;      // final true ||b - S x||^2 (FP64)
   double bb;        // ||b||^2
   double energy2;   // sum M x^2
-  double pad0;
+  double rho;       // (r, z) of the z a replacement superseded (beta after the replacement)
   int32_t iters;    // CG iterations performed
-  int32_t done;     // 0 running, 1 converged, 2 breakdown
-  int32_t rr_true;  // the current residual norm is an FP64 true residual (start, mixed replacement)
+  int32_t done;     // 0 running, 1 converged, 2 breakdown, 3 max_iter
   int32_t updates;  // FP64 residual replacements
-  int32_t update_now;
-  // FP64: index of the last launch of the direction kernel that replaced the
-  // residual instead of iterating (the next launch tests that true residual
-  // and restarts the directions); only ever compared with launch indices, so
-  // no kernel has to clear it
-  int32_t repl_launch;
+  int32_t mode;     // what the launch that wrote this copy did (M_INIT, M_ITER, M_REPLACE, M_DONE)
+  uint32_t fused_bits;  // bit L % 32: launch L iterated with alpha != 0 (profiling)
+  int32_t xbuf;     // after a stop: the x buffer that holds the solution
   int32_t pad1[2];
 };
 
@@ -97,17 +98,18 @@ struct DevMatrix {
   int32_t* row_of = nullptr;  // caller index -> row, -1 for entries without a dof (field_len)
   int64_t field_len = 0;
   double mass_sum = 0.0;
+  int head = 6;  // entries per row the gathering kernels load together (6, 12 or 20)
 };
 
 struct ColWork {
+  double* x[2] = {nullptr, nullptr};  // FP64 solution (both precisions)
   // FP64 path vectors
-  double *x = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *d = nullptr;
+  double *z[2] = {nullptr, nullptr}, *u[2] = {nullptr, nullptr}, *p[2] = {nullptr, nullptr}, *d = nullptr;
   // mixed path vectors
-  float *r32 = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *d32 = nullptr,
-        *xacc = nullptr;
+  float *z32[2] = {nullptr, nullptr}, *u32[2] = {nullptr, nullptr}, *p32[2] = {nullptr, nullptr}, *d32 = nullptr;
   double* phi = nullptr;   // field in internal order
   double* part = nullptr;  // partials, see offsets below
-  Scalars* sc = nullptr;
+  Scalars* sc = nullptr;       // two copies (see Scalars)
   Scalars* sc_host = nullptr;  // pinned, 2 slots
   int* flag = nullptr;         // device: non-finite input detected
   double* stage_in = nullptr;  // field staging (caller numbering)
@@ -156,8 +158,12 @@ struct DeviceState {
   double* proj_in = nullptr;      // device copy of a host cell field
 };
 
-// partial-array offsets (in units of G)
-enum { P_PQ = 0, P_RZ0 = 1, P_RZ1 = 2, P_RR0 = 3, P_RR1 = 4, P_BB = 5, P_RES = 6, P_EN = 7, P_FL = 8, P_COUNT = 9 };
+// Partial sums of a one-column launch (units of G): two parities of five
+// iteration sums, then the floor norm of a replacement, ||M phi||^2 and the
+// finish sums. Launch L writes parity L & 1 and its successor reads it.
+constexpr int kPq = 0, kZu = 1, kUu = 2, kRz = 3, kRr = 4, kPerParity = 5;
+__host__ __device__ constexpr int pidx(int parity, int q) { return parity * kPerParity + q; }
+enum { P_FL = 2 * kPerParity, P_BB, P_RES, P_EN, P_COUNT };
 
 // Work space of ifl_filter_noalloc: the one-column path's block partials
 // (P_COUNT x G doubles) followed by its Scalars, in a file-scope device
@@ -168,7 +174,7 @@ enum { P_PQ = 0, P_RZ0 = 1, P_RZ1 = 2, P_RR0 = 3, P_RR1 = 4, P_BB = 5, P_RES = 6
 constexpr size_t kNoallocScratchBytes = 64 * 1024;
 constexpr size_t kNoallocScalarsOffset = kNoallocScratchBytes - 256;  // Scalars in the last 256 bytes
 static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
-static_assert(sizeof(Scalars) <= 256, "Scalars must fit the scratch tail");
+static_assert(2 * sizeof(Scalars) <= 256, "both Scalars copies must fit the scratch tail");
 
 // Attainable accuracy of an FP64 residual r = b - S x: its rounding error is
 // bounded by a small multiple of u ||(|b| + |S| |x|)||, u = 2^-53. A true
@@ -176,6 +182,14 @@ static_assert(sizeof(Scalars) <= 256, "Scalars must fit the scratch tail");
 // further in FP64 and counts as converged.
 constexpr double kUnitRoundoff = 1.1102230246251565e-16;
 constexpr double kFloorUnits = 8.0;
+// Reliable updates: an FP64 residual replacement whenever the recursive
+// residual fell by 100x since the last true residual (delta^2 = 1e-4), in
+// both precisions, and the CG directions continue across it. Replacing only
+// when the recursive residual meets the tolerance lets it drift so far at
+// cond(S) ~ 1e6-1e7 that the continued iteration stagnates (a 10^4 fall
+// already stalls the circumcentre n = 2 system at lambda = 32h); restarting
+// instead converges, but 20-100% slower there.
+constexpr double kReplaceDelta2 = 1e-4;
 
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int logical_block(int G) {
@@ -228,14 +242,16 @@ __device__ __forceinline__ double reduce_partials(const double* a, int G, double
   return *lds_out;
 }
 
+// Vectors of a one-column solve; x, z, u = diag(S)^-1 S p and p alternate
+// between two buffers (a launch gathers the ones it reads while it writes
+// the others).
 template <typename T>
-struct Vecs {
-  T* r;
-  T* z;
-  T* p0;
-  T* p1;
-  T* q;
+struct CgVecs {
+  T* z[2];
+  T* u[2];
+  T* p[2];
   T* d;
+  double* x[2];
 };
 
 struct Mat {
@@ -259,17 +275,20 @@ __device__ __forceinline__ const float* mval<float>(const Mat& m) { return m.val
 // Only an FP64 true residual r = M phi - S x may stop a solve, in both
 // precisions: a recursive residual drifts from the true one when S is badly
 // conditioned (an FP64 solve stopped on it at cond(S) ~ 1e6 was accurate to
-// ~1e-7 only). Mixed precision replaces the residual in k_fold / k_replace;
-// FP64 replaces it in the direction kernel itself (below). Every iterating
-// launch writes the partials of the next parity, so the partials a kernel
-// reads are never stale.
+// ~1e-7 only).
+
+// Modes of a one-column launch, decided in its prologue (the same in every
+// block, from the same partials) and recorded for the next launch.
+enum { M_INIT = 0, M_ITER = 1, M_REPLACE = 2, M_DONE = 3 };
 
 // ---------------------------------------------------------------- kernels
 // Start of a solve: x0 = phi, r0 = M phi - S phi = -c K_n phi (FP64 values),
-// diag(S), z0, p = 0, and the partials of (r, z), (r, r), (b, b).
-template <typename T, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_init(Mat m, Vecs<T> v, double* x, float* xacc, const double* phi,
-                                                  double* part, Scalars* sc, double c, int G, int spb) {
+// diag(S) stored, x0 and z0 = r0 / diag(S) into buffers 0, and the sums of (r, z),
+// (r, r) (as parity 1, read by launch 0) and ||M phi||^2. Scalars copy 0 is
+// the state launch 0 reads.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init(Mat m, CgVecs<T> v, const double* phi, double* part, Scalars* sc,
+                                                  double c, int G, int spb) {
   __shared__ double lds[3][kWavesPerBlock];
   const int lb = logical_block(G);
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
@@ -291,12 +310,9 @@ __global__ __launch_bounds__(kBlock) void k_init(Mat m, Vecs<T> v, double* x, fl
     const double d64 = m.mass64[row] + c * kd;
     const T rt = (T)r64, dt = (T)d64;
     const T zt = rt / dt;
-    x[row] = ph;
-    if (MIXED) xacc[row] = 0.0f;
-    v.r[row] = rt;
-    v.z[row] = zt;
+    v.x[0][row] = ph;
+    v.z[0][row] = zt;
     v.d[row] = dt;
-    v.p0[row] = (T)0;
     acc3[0] += (double)rt * (double)zt;
     acc3[1] += r64 * r64;
     const double b = m.mass64[row] * ph;
@@ -304,307 +320,300 @@ __global__ __launch_bounds__(kBlock) void k_init(Mat m, Vecs<T> v, double* x, fl
   }
   block_sum<3>(acc3, lds);
   if (threadIdx.x == 0) {
-    part[P_RZ0 * G + lb] = acc3[0];
-    part[P_RR0 * G + lb] = acc3[1];
+    part[pidx(1, kRz) * G + lb] = acc3[0];
+    part[pidx(1, kRr) * G + lb] = acc3[1];
     part[P_BB * G + lb] = acc3[2];
     part[P_FL * G + lb] = 0.0;
-    // rho_{-1} = +inf makes beta_0 = 0
-    part[P_RZ1 * G + lb] = lb == 0 ? INFINITY : 0.0;
     if (lb == 0) {
-      sc->c = c;
-      sc->iters = 0;
-      sc->done = 0;
-      sc->rr_true = 1;
-      sc->updates = 0;
-      sc->update_now = 0;
-      sc->repl_launch = -2;
+      Scalars s0{};
+      s0.c = c;
+      s0.mode = M_INIT;
+      sc[0] = s0;
     }
   }
 }
 
-// One block: tolerance and reference norms from the init partials.
+// One block: tolerance and reference norms from the init sums.
 __global__ __launch_bounds__(kBlock) void k_setup(double* part, Scalars* sc, double rtol, int G) {
   __shared__ double lw[kWavesPerBlock];
   __shared__ double lo;
   const double bb = reduce_partials(part + P_BB * G, G, lw, &lo);
-  const double rr = reduce_partials(part + P_RR0 * G, G, lw, &lo);
   if (threadIdx.x == 0) {
-    sc->bb = bb;
-    sc->tol2 = rtol * rtol * bb;
-    sc->rr_ref = rr;
-    sc->rr_last = rr;
+    sc[0].bb = bb;
+    sc[0].tol2 = rtol * rtol * bb;
   }
 }
 
-// CG step 1: p_new = z + beta p_old (own row and gathered neighbours),
-// q = S p_new = d p_new + c K_off p_new, partial (p_new, q).
-//
-// The prologue finishes the residual sums of the previous step and takes
-// one of three decisions, the same in every block (same partials):
-//  * stop: the residual is an FP64 true one (start of the solve, the launch
-//    after a replacement, or a mixed-precision replacement) and meets
-//    max(tol, attainable-accuracy floor);
-//  * replace (FP64 only): the recursive residual meets the tolerance. x is
-//    complete at a kernel boundary, so this launch forms the true residual
-//    r = M phi - S x with FP64 values instead of iterating, with the
-//    partials of (r, z), (r, r) and the floor norm for the next launch,
-//    which tests it and, if it does not pass, restarts the directions
-//    (beta = 0) from it. The blocks of a replacing launch read only the
-//    partials of the current parity and write only those of the next one;
-//  * iterate.
-// 'launch' is the host's index of this launch (k_update of the same launch
-// does nothing after a replacement).
-template <typename T, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_dir_spmv(Mat m, Vecs<T> v, const double* x, const double* phi,
-                                                      double* part, Scalars* sc, int parity, int launch, int G,
-                                                      int spb) {
-  __shared__ double lw[kWavesPerBlock];
-  __shared__ double lo;
-  __shared__ double lds[3][kWavesPerBlock];
-  if (sc->done) return;  // finished solves cost one scalar load per launch
-  const int lb = logical_block(G);
-  const bool fresh = !MIXED && sc->repl_launch == launch - 1;  // FP64 residual replaced by the last launch
-  const bool is_true = sc->rr_true || fresh;
-  const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
-  double floor2 = 0.0;
-  if (is_true) {
-    const double f = reduce_partials(part + P_FL * G, G, lw, &lo);
-    floor2 = f * (kFloorUnits * kUnitRoundoff) * (kFloorUnits * kUnitRoundoff);
+// Sums of NQ partial arrays src[q][0..G) by the whole block in one pass
+// (fixed order); every thread returns the same values.
+template <int NQ>
+__device__ __forceinline__ void reduce_many(const double* const (&src)[NQ], int G, double (&out)[NQ],
+                                            double (*lds)[kWavesPerBlock]) {
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < G; i += kBlock) s += src[q][i];
+    v[q] = wave_sum(s);
   }
-  if (is_true && rr <= fmax(sc->tol2, floor2)) {
-    if (lb == 0 && threadIdx.x == 0) {
-      sc->done = 1;
-      sc->rr_last = rr;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[q][wid] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double t = 0.0;
+    for (int w = 0; w < kWavesPerBlock; ++w) t += lds[q][w];
+    out[q] = t;
+  }
+}
+
+// One CG iteration per launch (or, when due, the FP64 residual
+// replacement), with u = diag(S)^-1 S p in place of q = S p (d = diag(S);
+// z = d^-1 r is the residual state; r = d z is formed where needed).
+//
+// The prologue finishes the previous launch's sums and decides, in every
+// block alike:
+//  * after the start or a replacement (an FP64 true residual): stop if it
+//    meets max(tol, attainable-accuracy floor); else iterate with alpha = 0
+//    and beta = 0 after the start, beta = rho_true / rho_prev after a
+//    replacement (the directions continue: the residual is replaced, the
+//    Krylov directions are kept);
+//  * after an iteration: alpha = rho / (p, q) (breakdown if (p, q) <= 0);
+//    replace if the recursive residual meets the tolerance or fell by
+//    100x since the last true residual; else iterate
+//    with beta = rho_next / rho, rho_next = rho - 2 alpha (q, z) + alpha^2
+//    (q, d^-1 q) (the rho of z - alpha d^-1 q, known before that z exists).
+//
+// Iterate (buffers: read x, z, u, p [L & 1], write [(L + 1) & 1]):
+//    z' = z - alpha u          (own row and every gathered neighbour)
+//    x += alpha p              (FP64)
+//    p' = z' + beta p
+//    u' = z' + d^-1 c K_off z' + beta u   (= d^-1 S p')
+//  with the sums (p', q'), (q', z'), (q', d^-1 q'), (r', z'), (r', r').
+// Replace: x' = x + alpha p (own row and gathered neighbours, FP64), r =
+//  M phi - S x' with FP64 values, z = r / d, p and u carried to the other
+//  buffers, with the sums (r, z), (r, r) and the floor norm
+//  || |M phi| + |M x'| + c |K_n| |x'| ||^2.
+// Block 0 writes the state copy (L + 1) & 1, which no block of launch L
+// reads; a stopping launch records the buffer that holds the final x.
+// 'launch' is the host's index of this launch.
+template <typename T, bool MIXED, int U>
+__global__ __launch_bounds__(kBlock) void k_cg(Mat m, CgVecs<T> v, const double* phi, double* part, Scalars* sc,
+                                                int launch, int G, int spb, int max_iter) {
+  __shared__ double lds6[6][kWavesPerBlock];
+  __shared__ double lds5[5][kWavesPerBlock];
+  const int cur = launch & 1, nxt = cur ^ 1;
+  const Scalars s0 = sc[cur];
+  const int lb = logical_block(G);
+  const bool leader = lb == 0 && threadIdx.x == 0;
+  if (s0.done) {
+    if (leader) {
+      Scalars s1 = s0;
+      s1.fused_bits &= ~(1u << (launch & 31));
+      sc[nxt] = s1;
     }
+    return;
+  }
+  // previous launch's sums (parity nxt = (launch - 1) & 1)
+  double q[6];
+  {
+    const double* const src[6] = {part + pidx(nxt, kPq) * G, part + pidx(nxt, kZu) * G, part + pidx(nxt, kUu) * G,
+                                  part + pidx(nxt, kRz) * G, part + pidx(nxt, kRr) * G, part + P_FL * G};
+    reduce_many<6>(src, G, q, lds6);
+  }
+  const double pq = q[0], zu = q[1], uu = q[2], rz = q[3], rr = q[4], fl = q[5];
+  Scalars s1 = s0;
+  s1.fused_bits &= ~(1u << (launch & 31));
+  int mode;
+  double alpha = 0.0, beta = 0.0;
+  bool restart = false;
+  if (s0.mode != M_ITER) {
+    // a true residual: stop or (re)start
+    const double floor2 = fl * (kFloorUnits * kUnitRoundoff) * (kFloorUnits * kUnitRoundoff);
+    s1.rr_last = rr;
+    s1.rr_ref = rr;
+    if (rr <= fmax(s0.tol2, floor2)) {
+      s1.done = 1;
+      mode = M_DONE;
+    } else if (s0.iters >= max_iter) {
+      s1.done = 3;
+      mode = M_DONE;
+    } else {
+      mode = M_ITER;
+      restart = s0.mode == M_INIT;
+      beta = restart ? 0.0 : rz / s0.rho;
+    }
+  } else {
+    alpha = rz / pq;
+    s1.rr_last = rr;
+    if (!(pq > 0.0) || !isfinite(alpha)) {
+      s1.done = 2;
+      mode = M_DONE;
+    } else if (rr <= s0.tol2 || rr <= kReplaceDelta2 * s0.rr_ref) {
+      mode = M_REPLACE;
+      s1.rho = rz;  // rho of the z this replacement supersedes (beta after it)
+      s1.updates += 1;
+    } else if (s0.iters >= max_iter) {
+      s1.done = 3;
+      mode = M_DONE;
+    } else {
+      mode = M_ITER;
+      beta = (rz - 2.0 * alpha * zu + alpha * alpha * uu) / rz;
+    }
+  }
+  if (mode == M_DONE) s1.xbuf = cur;
+  if (mode == M_ITER) {
+    s1.iters += 1;
+    if (alpha != 0.0) s1.fused_bits |= 1u << (launch & 31);
+  }
+  s1.mode = mode;
+  if (mode == M_DONE) {
+    if (leader) sc[nxt] = s1;
     return;
   }
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
-  if (!MIXED && !is_true && rr <= sc->tol2) {
-    // FP64 residual replacement (x and the FP64 vectors r, z are T = double)
-    const double c = sc->c;
-    double acc[3] = {0.0, 0.0, 0.0};
+  const T* __restrict__ zin = v.z[cur];
+  const T* __restrict__ uin = v.u[cur];
+  const T* __restrict__ pin = v.p[cur];
+  T* __restrict__ zout = v.z[nxt];
+  T* __restrict__ uout = v.u[nxt];
+  T* __restrict__ pout = v.p[nxt];
+  const double* __restrict__ xin = v.x[cur];
+  double* __restrict__ xout = v.x[nxt];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (mode == M_REPLACE) {
+    const double c = s0.c;
     for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
       const int64_t row = s * kWave + lane;
       if (row >= m.n) continue;
       const int64_t base = m.sptr[s];
       const int w = (int)((m.sptr[s + 1] - base) / kWave);
       double a = 0.0, aa = 0.0;
-      for (int k = 0; k < w; ++k) {
-        const int64_t e = base + (int64_t)k * kWave + lane;
-        const double t = m.val64[e] * x[m.col[e]];
-        a += t;
-        aa += fabs(t);
+      for (int k0 = 0; k0 < w; k0 += U) {
+        int32_t cu[U];
+        double vu[U], xu[U];
+        T pu[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t e = base + (int64_t)(k0 + u) * kWave + lane;
+          cu[u] = m.col[e];
+          const double vv = m.val64[e];
+          vu[u] = k0 + u < w ? vv : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          xu[u] = xin[cu[u]];
+          pu[u] = pin[cu[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double xn = fma(alpha, (double)pu[u], xu[u]);
+          a = fma(vu[u], xn, a);
+          aa = fma(fabs(vu[u]), fabs(xn), aa);
+        }
       }
-      const double xi = x[row];
-      const double mi = m.mass64[row], kd = m.kdiag64[row];
-      const double r64 = mi * (phi[row] - xi) - c * (kd * xi + a);
-      const double mag = fabs(mi * phi[row]) + fabs(mi * xi) + c * (fabs(kd * xi) + aa);
-      const double zt = r64 / (double)v.d[row];
-      v.r[row] = (T)r64;
-      v.z[row] = (T)zt;
-      acc[0] += r64 * zt;
+      const T pi = pin[row], ui = uin[row];
+      const double xi = fma(alpha, (double)pi, xin[row]);
+      const double mi = m.mass64[row], kd = m.kdiag64[row], ph = phi[row];
+      const double r64 = mi * (ph - xi) - c * (kd * xi + a);
+      const double mag = fabs(mi * ph) + fabs(mi * xi) + c * (fabs(kd * xi) + aa);
+      const T rt = (T)r64;
+      const T zt = rt / v.d[row];
+      xout[row] = xi;
+      zout[row] = zt;
+      pout[row] = pi;
+      uout[row] = ui;
+      acc[0] += (double)rt * (double)zt;
       acc[1] += r64 * r64;
       acc[2] += mag * mag;
     }
-    block_sum<3>(acc, lds);
-    if (threadIdx.x == 0) {
-      part[(P_RZ0 + (parity ^ 1)) * G + lb] = acc[0];
-      part[(P_RR0 + (parity ^ 1)) * G + lb] = acc[1];
+  } else {
+    const T at = (T)alpha, bt = (T)beta, c = (T)s0.c;
+    const T* __restrict__ val = mval<T>(m);
+    const bool step = alpha != 0.0;  // z moves (and x); else z' = z, and u is not gathered
+    for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+      const int64_t row = s * kWave + lane;
+      if (row >= m.n) continue;
+      const int64_t base = m.sptr[s];
+      const int w = (int)((m.sptr[s + 1] - base) / kWave);
+      // entries U at a time: index / value loads, then the gathers, then
+      // the FMAs in entry order; loads past the row's end stay in bounds
+      // (the next slice or the zero tail) and their values are replaced by 0
+      T a = (T)0;
+      for (int k0 = 0; k0 < w; k0 += U) {
+        int32_t cu[U];
+        T vu[U], zu_[U], uu_[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t e = base + (int64_t)(k0 + u) * kWave + lane;
+          cu[u] = m.col[e];
+          const T vv = val[e];
+          vu[u] = k0 + u < w ? vv : (T)0;
+        }
+        if (step) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            zu_[u] = zin[cu[u]];
+            uu_[u] = uin[cu[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) a = fma(vu[u], fma(-at, uu_[u], zu_[u]), a);
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) zu_[u] = zin[cu[u]];
+#pragma unroll
+          for (int u = 0; u < U; ++u) a = fma(vu[u], zu_[u], a);
+        }
+      }
+      const T zi = zin[row], di = v.d[row];
+      const T ui = restart ? (T)0 : uin[row];
+      const T pi = restart ? (T)0 : pin[row];
+      const T zn = step ? fma(-at, ui, zi) : zi;
+      const double xi = xin[row];
+      xout[row] = step ? fma(alpha, (double)pi, xi) : xi;
+      const T pn = fma(bt, pi, zn);
+      const T un = fma(bt, ui, zn + (c * a) / di);
+      zout[row] = zn;
+      pout[row] = pn;
+      uout[row] = un;
+      const double dd = (double)di, zz = (double)zn, uv = (double)un;
+      acc[0] += dd * (double)pn * uv;
+      acc[1] += dd * zz * uv;
+      acc[2] += dd * uv * uv;
+      acc[3] += dd * zz * zz;
+      acc[4] += (dd * zz) * (dd * zz);
+    }
+  }
+  block_sum<5>(acc, lds5);
+  if (threadIdx.x == 0) {
+    if (mode == M_REPLACE) {
+      part[pidx(cur, kRz) * G + lb] = acc[0];
+      part[pidx(cur, kRr) * G + lb] = acc[1];
       part[P_FL * G + lb] = acc[2];
-      if (lb == 0) {
-        sc->repl_launch = launch;
-        sc->updates += 1;
-        sc->rr_last = rr;
-      }
+    } else {
+      part[pidx(cur, kPq) * G + lb] = acc[0];
+      part[pidx(cur, kZu) * G + lb] = acc[1];
+      part[pidx(cur, kUu) * G + lb] = acc[2];
+      part[pidx(cur, kRz) * G + lb] = acc[3];
+      part[pidx(cur, kRr) * G + lb] = acc[4];
     }
-    return;
-  }
-  const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
-  // after a replacement the directions restart (beta = 0)
-  const double rz_old = fresh ? INFINITY : reduce_partials(part + (P_RZ0 + (parity ^ 1)) * G, G, lw, &lo);
-  const T beta = (T)(rz / rz_old);
-  const T c = (T)sc->c;
-  const T* __restrict__ pin = parity ? v.p1 : v.p0;
-  T* __restrict__ pout = parity ? v.p0 : v.p1;
-  const T* __restrict__ z = v.z;
-  const T* __restrict__ val = mval<T>(m);
-  double pq[1] = {0.0};
-  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
-    const int64_t row = s * kWave + lane;
-    if (row >= m.n) continue;
-    const int64_t base = m.sptr[s];
-    const int w = (int)((m.sptr[s + 1] - base) / kWave);
-    // entries kUnroll at a time: index / value loads, then the gathers, then
-    // the FMAs in entry order (more loads in flight per wavefront)
-    T a = (T)0;
-    for (int k0 = 0; k0 < w; k0 += kUnroll) {
-      int32_t cu[kUnroll];
-      T vu[kUnroll], zu[kUnroll], pu[kUnroll];
-      // loads past the row's end stay in bounds (next slice or the zero
-      // tail of the arrays); their values are replaced by 0
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int64_t e = base + (int64_t)(k0 + u) * kWave + lane;
-        cu[u] = m.col[e];
-        const T vv = val[e];
-        vu[u] = k0 + u < w ? vv : (T)0;
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        zu[u] = z[cu[u]];
-        pu[u] = pin[cu[u]];
-      }
-      // entries past the row's end have value 0 and gather row 0 (finite):
-      // their FMA leaves a unchanged, so no branch keeps the gathers apart
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) a = fma(vu[u], fma(beta, pu[u], zu[u]), a);
-    }
-    const T pn = z[row] + beta * pin[row];
-    const T qv = v.d[row] * pn + c * a;
-    pout[row] = pn;
-    v.q[row] = qv;
-    pq[0] += (double)pn * (double)qv;
-  }
-  block_sum<1>(pq, lds);
-  if (threadIdx.x == 0) {
-    part[P_PQ * G + lb] = pq[0];
-    if (lb == 0) {
-      sc->iters += 1;
-      sc->rr_last = rr;
-      if (MIXED && sc->rr_true) sc->rr_ref = rr;
-    }
+    if (lb == 0) sc[nxt] = s1;
   }
 }
 
-// CG step 2: alpha = (r, z) / (p, q); x += alpha p; r -= alpha q;
-// z = r / diag(S); partials (r, z) and (r, r) for the next iteration.
-template <typename T, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_update(Mat m, Vecs<T> v, double* x, float* xacc, double* part,
-                                                    Scalars* sc, int parity, int launch, int G, int spb) {
-  __shared__ double lw[kWavesPerBlock];
-  __shared__ double lo;
-  __shared__ double lds[2][kWavesPerBlock];
-  // k_dir_spmv of this launch took the stopping decision (and set done), or
-  // replaced the residual instead of iterating
-  if (sc->done || sc->repl_launch == launch) return;
-  const double rz = reduce_partials(part + (P_RZ0 + parity) * G, G, lw, &lo);
-  const int lb = logical_block(G);
-  const double pq = reduce_partials(part + P_PQ * G, G, lw, &lo);
-  const double alpha = rz / pq;
-  if (!(pq > 0.0) || !isfinite(alpha)) {
-    if (lb == 0 && threadIdx.x == 0) sc->done = 2;
-    return;
-  }
-  const T at = (T)alpha;
-  const T* __restrict__ p = parity ? v.p0 : v.p1;
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  double acc[2] = {0.0, 0.0};
-  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
-  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
-    const int64_t row = s * kWave + lane;
-    if (row >= m.n) continue;
-    const T pv = p[row];
-    if (MIXED) xacc[row] += at * pv;
-    else x[row] += alpha * (double)pv;
-    const T rv = v.r[row] - at * v.q[row];
-    const T zv = rv / v.d[row];
-    v.r[row] = rv;
-    v.z[row] = zv;
-    acc[0] += (double)rv * (double)zv;
-    acc[1] += (double)rv * (double)rv;
-  }
-  block_sum<2>(acc, lds);
-  if (threadIdx.x == 0) {
-    part[(P_RZ0 + (parity ^ 1)) * G + lb] = acc[0];
-    part[(P_RR0 + (parity ^ 1)) * G + lb] = acc[1];
-    if (lb == 0) sc->rr_true = 0;
-  }
-}
-
-// Mixed precision, residual replacement part 1: decide (from the recursive
-// residual) whether to fold the FP32 increments into the FP64 solution now:
-// when the residual fell by a factor delta since the last replacement, or
-// when it meets the tolerance and needs an FP64 confirmation.
-__global__ __launch_bounds__(kBlock) void k_fold(Mat m, double* x, float* xacc, double* part, Scalars* sc,
-                                                 int parity, double delta2, int G, int spb) {
-  __shared__ double lw[kWavesPerBlock];
-  __shared__ double lo;
-  const int lb = logical_block(G);
-  if (sc->done || sc->rr_true) {
-    if (lb == 0 && threadIdx.x == 0) sc->update_now = 0;
-    return;
-  }
-  const double rr = reduce_partials(part + (P_RR0 + parity) * G, G, lw, &lo);
-  const bool trig = rr <= sc->tol2 || rr <= delta2 * sc->rr_ref;
-  if (lb == 0 && threadIdx.x == 0) sc->update_now = trig ? 1 : 0;
-  if (!trig) return;
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
-  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
-    const int64_t row = s * kWave + lane;
-    if (row >= m.n) continue;
-    x[row] += (double)xacc[row];
-    xacc[row] = 0.0f;
-  }
-}
-
-// Mixed precision, residual replacement part 2: r = M phi - S x in FP64
-// (FP64 values, FP64 x), stored as the FP32 recursive residual; the norm
-// partial is the FP64 one, so the next stopping test sees a true residual.
-__global__ __launch_bounds__(kBlock) void k_replace(Mat m, Vecs<float> v, const double* x, const double* phi,
-                                                    double* part, Scalars* sc, int parity, int G, int spb) {
-  __shared__ double lds[3][kWavesPerBlock];
-  if (!sc->update_now) return;
-  const int lb = logical_block(G);
-  const double c = sc->c;
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  double acc[3] = {0.0, 0.0, 0.0};
-  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
-  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
-    const int64_t row = s * kWave + lane;
-    if (row >= m.n) continue;
-    const int64_t base = m.sptr[s];
-    const int w = (int)((m.sptr[s + 1] - base) / kWave);
-    double a = 0.0, aa = 0.0;
-    for (int k = 0; k < w; ++k) {
-      const int64_t e = base + (int64_t)k * kWave + lane;
-      const double t = m.val64[e] * x[m.col[e]];
-      a += t;
-      aa += fabs(t);
-    }
-    const double xi = x[row];
-    const double mi = m.mass64[row], kd = m.kdiag64[row];
-    const double r64 = mi * (phi[row] - xi) - c * (kd * xi + a);
-    const double mag = fabs(mi * phi[row]) + fabs(mi * xi) + c * (fabs(kd * xi) + aa);
-    const float rt = (float)r64;
-    const float zt = rt / v.d[row];
-    v.r[row] = rt;
-    v.z[row] = zt;
-    acc[0] += (double)rt * (double)zt;
-    acc[1] += r64 * r64;
-    acc[2] += mag * mag;
-  }
-  block_sum<3>(acc, lds);
-  if (threadIdx.x == 0) {
-    part[(P_RZ0 + parity) * G + lb] = acc[0];
-    part[(P_RR0 + parity) * G + lb] = acc[1];
-    part[P_FL * G + lb] = acc[2];
-    if (lb == 0) {
-      sc->rr_true = 1;
-      sc->updates += 1;
-    }
-  }
-}
-
-// End of a solve: x = x (+ FP32 increments), scattered to the caller's
-// numbering; partials of the true FP64 residual and of sum M x^2.
-__global__ __launch_bounds__(kBlock) void k_finish(Mat m, const double* x, const float* xacc, const double* phi,
+// End of a solve: x (the buffer the stopping launch recorded, else the last
+// one written) scattered to the caller's numbering; partials of the true
+// FP64 residual and of sum M x^2.
+__global__ __launch_bounds__(kBlock) void k_finish(Mat m, const double* x0, const double* x1, const double* phi,
                                                    const int64_t* entity, double* out, double* part,
-                                                   Scalars* sc, int G, int spb) {
+                                                   const Scalars* sc, int last_buf, int G, int spb) {
   __shared__ double lds[2][kWavesPerBlock];
   const int lb = logical_block(G);
   const double c = sc->c;
+  const double* __restrict__ x = (sc->done ? sc->xbuf : last_buf) ? x1 : x0;
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   double acc[2] = {0.0, 0.0};
   const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
@@ -616,11 +625,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(Mat m, const double* x, const
     double a = 0.0;
     for (int k = 0; k < w; ++k) {
       const int64_t e = base + (int64_t)k * kWave + lane;
-      const int32_t j = m.col[e];
-      const double xj = xacc ? x[j] + (double)xacc[j] : x[j];
-      a += m.val64[e] * xj;
+      a += m.val64[e] * x[m.col[e]];
     }
-    const double xi = xacc ? x[row] + (double)xacc[row] : x[row];
+    const double xi = x[row];
     const double r64 = m.mass64[row] * (phi[row] - xi) - c * (m.kdiag64[row] * xi + a);
     if (out) out[entity[row]] = xi;
     acc[0] += r64 * r64;
@@ -797,6 +804,24 @@ ifl_status device_create(Handle* h) {
   }
   m.mass_sum = 0.0;
   for (double a : h->op.mass) m.mass_sum += a;
+  // the batched kernels' pipelined head: the smallest class (6, 12, 20
+  // entries) that covers 90% of the slices; wider slices finish their rows
+  // unpipelined
+  {
+    std::vector<int64_t> widths((size_t)m.n_slices);
+    for (int64_t s = 0; s < m.n_slices; ++s) widths[(size_t)s] = (sp.slice_ptr[s + 1] - sp.slice_ptr[s]) / kWave;
+    int64_t w90 = 0;
+    if (!widths.empty()) {
+      const size_t at = (widths.size() * 9) / 10;
+      std::nth_element(widths.begin(), widths.begin() + at, widths.end());
+      w90 = widths[at];
+    }
+    m.head = w90 <= 6 ? 6 : (w90 <= 12 ? 12 : 20);
+    if (const char* e = std::getenv("IFL_HEAD")) {
+      const int v = std::atoi(e);
+      if (v == 6 || v == 12 || v == 20) m.head = v;
+    }
+  }
 
   // launch geometry: logical blocks own contiguous slice ranges
   const int64_t ns = m.n_slices;
@@ -809,16 +834,15 @@ ifl_status device_create(Handle* h) {
 
   ColWork& w = d->w;
   const size_t np = (size_t)m.n_pad;
-  if ((st = dalloc(&w.x, np)) || (st = dalloc(&w.r, np)) || (st = dalloc(&w.z, np)) || (st = dalloc(&w.p[0], np)) ||
-      (st = dalloc(&w.p[1], np)) || (st = dalloc(&w.q, np)) || (st = dalloc(&w.d, np)) ||
-      (st = dalloc(&w.r32, np)) || (st = dalloc(&w.z32, np)) || (st = dalloc(&w.p32[0], np)) ||
-      (st = dalloc(&w.p32[1], np)) || (st = dalloc(&w.q32, np)) || (st = dalloc(&w.d32, np)) ||
-      (st = dalloc(&w.xacc, np)) || (st = dalloc(&w.phi, np)) || (st = dalloc(&w.part, (size_t)P_COUNT * d->G)) ||
-      (st = dalloc(&w.sc, 1)) || (st = dalloc(&w.flag, 1)))
+  for (double** v : {&w.x[0], &w.x[1], &w.z[0], &w.z[1], &w.u[0], &w.u[1], &w.p[0], &w.p[1], &w.d, &w.phi})
+    if ((st = dalloc(v, np))) return st;
+  for (float** v : {&w.z32[0], &w.z32[1], &w.u32[0], &w.u32[1], &w.p32[0], &w.p32[1], &w.d32})
+    if ((st = dalloc(v, np))) return st;
+  if ((st = dalloc(&w.part, (size_t)P_COUNT * d->G)) || (st = dalloc(&w.sc, 2)) || (st = dalloc(&w.flag, 1)))
     return st;
   IFL_HIP(hipHostMalloc((void**)&w.sc_host, 2 * sizeof(Scalars), hipHostMallocDefault));
   IFL_HIP(hipMemset(w.part, 0, sizeof(double) * P_COUNT * d->G));
-  IFL_HIP(hipMemset(w.sc, 0, sizeof(Scalars)));
+  IFL_HIP(hipMemset(w.sc, 0, 2 * sizeof(Scalars)));
   // hipMemset of device memory may return before it completes, and the
   // solves run on streams that do not wait for the null stream
   IFL_HIP(hipDeviceSynchronize());
@@ -831,9 +855,11 @@ void device_destroy(Handle* h) {
   (void)hipSetDevice(d->device);
   if (d->own_stream) (void)hipStreamSynchronize(d->own_stream);
   DevMatrix& m = d->m;
-  void* ptrs[] = {m.sptr, m.col, m.val64, m.val32, m.kdiag64, m.kdiag32, m.mass64, m.entity, m.row_of, d->w.x, d->w.r, d->w.z,
-                  d->w.p[0], d->w.p[1], d->w.q, d->w.d, d->w.r32, d->w.z32, d->w.p32[0], d->w.p32[1], d->w.q32,
-                  d->w.d32, d->w.xacc, d->w.phi, d->w.part, d->w.sc, d->w.flag, d->w.stage_in, d->w.stage_out};
+  const ColWork& w = d->w;
+  void* ptrs[] = {m.sptr,   m.col,    m.val64,  m.val32,  m.kdiag64, m.kdiag32, m.mass64,   m.entity,
+                  m.row_of, w.x[0],   w.x[1],   w.z[0],   w.z[1],    w.u[0],    w.u[1],     w.p[0],
+                  w.p[1],   w.d,      w.z32[0], w.z32[1], w.u32[0],  w.u32[1],  w.p32[0],   w.p32[1],
+                  w.d32,    w.phi,    w.part,   w.sc,     w.flag,    w.stage_in, w.stage_out};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (d->w.sc_host) (void)hipHostFree(d->w.sc_host);
@@ -897,20 +923,27 @@ ifl_status load_field(Handle* h, const double* field, bool dev_ptr, hipStream_t 
   return IFL_OK;
 }
 
-// Algorithmic bytes of one k_dir_spmv launch: the sliced-ELL stream
-// (index + value per stored entry, slice pointers), the gathered z and p
-// (each read once), own d, and the writes of p and q.
+// Algorithmic bytes of one iterating k_cg launch: the sliced-ELL stream
+// (index + value per stored entry, slice pointers), the reads of z, u, p
+// and d and the writes of z, u and p (each vector once), and the FP64
+// solution read and written.
 double spmv_bytes(const DevMatrix& m, size_t vb) {
-  return (double)m.nnz_stored * (4.0 + vb) + 8.0 * (m.n_slices + 1) + (double)m.n * vb * 5.0;
+  return (double)m.nnz_stored * (4.0 + vb) + 8.0 * (m.n_slices + 1) + (double)m.n * (vb * 7.0 + 16.0);
 }
 
 // Partials and scalars of a one-column solve: the handle's own, or the
 // no-allocation work space.
 struct ColScratch {
   double* part;
-  Scalars* sc;
+  Scalars* sc;  // two copies
   bool allow_profile;  // the handle's profiling events may be made and used
 };
+
+template <typename T, bool MIXED, int U>
+void launch_cg(const Mat& m, const CgVecs<T>& v, const double* phi, const ColScratch& cs, int launch, int G, int spb,
+               int max_iter, hipStream_t s) {
+  k_cg<T, MIXED, U><<<G, kBlock, 0, s>>>(m, v, phi, cs.part, cs.sc, launch, G, spb, max_iter);
+}
 
 template <typename T, bool MIXED>
 ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* out_dev, double* energy,
@@ -920,29 +953,32 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
   const DevMatrix& M = d->m;
   hipStream_t s = stream_of(h);
   const Mat m = mat_view(M);
-  Vecs<T> v;
+  CgVecs<T> v;
   if constexpr (MIXED) {
-    v = Vecs<T>{w.r32, w.z32, w.p32[0], w.p32[1], w.q32, w.d32};
+    v = CgVecs<T>{{w.z32[0], w.z32[1]}, {w.u32[0], w.u32[1]}, {w.p32[0], w.p32[1]}, w.d32, {w.x[0], w.x[1]}};
   } else {
-    v = Vecs<T>{w.r, w.z, w.p[0], w.p[1], w.q, w.d};
+    v = CgVecs<T>{{w.z[0], w.z[1]}, {w.u[0], w.u[1]}, {w.p[0], w.p[1]}, w.d, {w.x[0], w.x[1]}};
   }
   const int G = d->G, spb = d->spb;
   const double c = h->opt.gamma / std::pow(k, 2.0 * h->op.order);
   const auto t0 = std::chrono::steady_clock::now();
-  k_init<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, w.phi, cs.part, cs.sc, c, G, spb);
+  k_init<T><<<G, kBlock, 0, s>>>(m, v, w.phi, cs.part, cs.sc, c, G, spb);
   k_setup<<<1, kBlock, 0, s>>>(cs.part, cs.sc, h->opt.rtol, G);
   IFL_HIP(hipGetLastError());
 
-  const int chunk = 8;         // iterations between host checks
-  const int fold_every = 4;    // mixed: residual-replacement checks
-  const double delta2 = 1e-4;  // mixed: replace when ||r|| fell 100x
+  const int chunk = 8;  // launches between host checks
   const bool prof = h->opt.profile != 0 && cs.allow_profile;
   const int max_iter = h->opt.max_iter;
-  int launched = 0, chunk_id = 0;
+  // at most max_iter iterating launches, each followed by at most one
+  // replacement, and the stopping launch: the cap ends the loop in any case
+  const int64_t max_launch = 2 * (int64_t)max_iter + 16;
+  void (*cg)(const Mat&, const CgVecs<T>&, const double*, const ColScratch&, int, int, int, int, hipStream_t) =
+      M.head <= 6 ? launch_cg<T, MIXED, 6> : (M.head <= 12 ? launch_cg<T, MIXED, 12> : launch_cg<T, MIXED, 20>);
+  int64_t launched = 0;
+  int chunk_id = 0;
   bool finished = false;
   int pending = -1;  // chunk whose scalars are in flight
-  int32_t iters_seen = 0, updates_seen = 0;
-  int prof_pos[2] = {-1, -1};
+  int64_t prof_launch[2] = {-1, -1};
   if (prof) {
     ifl_status e = ensure_events(d, 4);
     if (e != IFL_OK) return e;
@@ -951,63 +987,56 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
   ifl_status result = IFL_OK;
   while (!finished) {
     const int slot = chunk_id & 1;
-    // profiling samples one SpMV launch per chunk (bracketing every launch
-    // with events would itself slow the loop down)
+    // profiling samples one launch per chunk (bracketing every launch with
+    // events would itself slow the loop down)
     const int pos = chunk_id % chunk;
-    prof_pos[slot] = -1;
-    for (int j = 0; j < chunk && launched < max_iter; ++j) {
-      const int parity = launched & 1;
+    prof_launch[slot] = -1;
+    for (int j = 0; j < chunk && launched < max_launch; ++j) {
       const bool sample = prof && j == pos;
       if (sample) IFL_HIP(hipEventRecord(d->ev[2 * slot], s));
-      k_dir_spmv<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.phi, cs.part, cs.sc, parity, launched, G, spb);
+      cg(m, v, w.phi, cs, (int)launched, G, spb, max_iter, s);
       if (sample) {
         IFL_HIP(hipEventRecord(d->ev[2 * slot + 1], s));
-        prof_pos[slot] = j;
+        prof_launch[slot] = launched;
       }
-      k_update<T, MIXED><<<G, kBlock, 0, s>>>(m, v, w.x, w.xacc, cs.part, cs.sc, parity, launched, G, spb);
       ++launched;
-      if (MIXED && (launched % fold_every == 0 || launched == max_iter)) {
-        const int par2 = launched & 1;
-        k_fold<<<G, kBlock, 0, s>>>(m, w.x, w.xacc, cs.part, cs.sc, par2, delta2, G, spb);
-        k_replace<<<G, kBlock, 0, s>>>(m, Vecs<float>{w.r32, w.z32, w.p32[0], w.p32[1], w.q32, w.d32}, w.x, w.phi,
-                                       cs.part, cs.sc, par2, G, spb);
-      }
     }
     IFL_HIP(hipGetLastError());
-    IFL_HIP(hipMemcpyAsync(&w.sc_host[slot], cs.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    // the state copy the next launch would read
+    IFL_HIP(hipMemcpyAsync(&w.sc_host[slot], cs.sc + (launched & 1), sizeof(Scalars), hipMemcpyDeviceToHost, s));
     IFL_HIP(hipEventRecord(done_ev[slot], s));
-    const bool capped = launched >= max_iter;
+    const bool capped = launched >= max_launch;
     // wait for the previous chunk (the current one keeps the GPU busy)
     int wait_chunk = capped ? chunk_id : pending;
     if (wait_chunk >= 0) {
       const int ws = wait_chunk & 1;
       IFL_HIP(hipEventSynchronize(done_ev[ws]));
       const Scalars& sh = w.sc_host[ws];
-      // count the sample only if that launch iterated (iterations within a
-      // chunk come first, finished launches after; an FP64 chunk that
-      // replaced its residual in a direction launch is not sampled)
-      const bool replaced = !MIXED && sh.updates != updates_seen;
-      if (prof && !replaced && prof_pos[ws] >= 0 && prof_pos[ws] < sh.iters - iters_seen) {
+      // count the sample only if that launch iterated with a step (the
+      // fused form the byte count describes)
+      if (prof && prof_launch[ws] >= 0 && ((sh.fused_bits >> (prof_launch[ws] & 31)) & 1u)) {
         float ms = 0.f;
         IFL_HIP(hipEventElapsedTime(&ms, d->ev[2 * ws], d->ev[2 * ws + 1]));
         d->prof_ms += ms;
         d->prof_launches += 1;
         d->prof_bytes += spmv_bytes(M, sizeof(T));
-        d->prof_kernel = MIXED ? "k_dir_spmv<float, true>" : "k_dir_spmv<double, false>";
+        d->prof_kernel = std::string("k_cg<") + (MIXED ? "float, true, " : "double, false, ") +
+                         std::to_string(M.head <= 6 ? 6 : (M.head <= 12 ? 12 : 20)) + ">";
       }
-      iters_seen = sh.iters;
-      updates_seen = sh.updates;
       if (sh.done) finished = true;
     }
     if (capped) finished = true;
     pending = chunk_id;
     ++chunk_id;
   }
-  // finish: x to caller numbering, true residual, energy
-  k_finish<<<G, kBlock, 0, s>>>(m, w.x, MIXED ? w.xacc : nullptr, w.phi, M.entity, out_dev, cs.part, cs.sc, G, spb);
-  k_finish_scalars<<<1, kBlock, 0, s>>>(cs.part, cs.sc, G);
+  // finish: x to caller numbering, true residual, energy (from the final
+  // state copy; a solve cut off by the launch cap uses the last x written)
+  Scalars* fin = cs.sc + (launched & 1);
+  k_finish<<<G, kBlock, 0, s>>>(m, w.x[0], w.x[1], w.phi, M.entity, out_dev, cs.part, fin, (int)(launched & 1), G,
+                                spb);
+  k_finish_scalars<<<1, kBlock, 0, s>>>(cs.part, fin, G);
   IFL_HIP(hipGetLastError());
-  IFL_HIP(hipMemcpyAsync(&w.sc_host[0], cs.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  IFL_HIP(hipMemcpyAsync(&w.sc_host[0], fin, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   IFL_HIP(hipStreamSynchronize(s));
   const Scalars& sh = w.sc_host[0];
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1020,6 +1049,7 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
     st_out->reserved = 0;
     st_out->rel_residual = rel;
     st_out->seconds = secs;
+    st_out->energy = 0.5 * sh.energy2 / M.mass_sum;
   }
   if (energy) *energy = 0.5 * sh.energy2 / M.mass_sum;
   if (!ok) result = fail(IFL_ENOTCONV, sh.done == 2 ? "CG breakdown ((p, Sp) <= 0 or non-finite)"
@@ -1102,6 +1132,7 @@ BatchMatrix batch_matrix(DeviceState* d, int R, bool mixed) {
   bm.entity = m.entity;
   bm.row_of = m.row_of;
   bm.field_len = m.field_len;
+  bm.head = m.head;
   // a task is one wavefront's rows: 64 / lanes-per-row consecutive rows.
   // Defaults: the gathering kernels run one block per CU, so that the rows
   // in flight on an XCD form a band narrow enough for its L2 to keep the
@@ -1264,7 +1295,8 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
       d->prof_ms += ms;
       d->prof_launches += 1;
       d->prof_bytes += batch_spmv_bytes(bm, d->m.nnz_stored, mixed, live);
-      d->prof_kernel = std::string("kb_dir_spmv<") + (mixed ? "float, " : "double, ") + std::to_string(R) + ", true>";
+      d->prof_kernel = std::string("kb_iter<") + (mixed ? "float, " : "double, ") + std::to_string(R) + ", true, " +
+                       std::to_string(bm.head) + ">";
     }
     uint64_t fin = 0;
     std::vector<double*> dst(R, nullptr);
@@ -1291,6 +1323,7 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
         so.reserved = 0;
         so.rel_residual = sl.bb > 0 ? std::sqrt(sl.res2 / sl.bb) : std::sqrt(sl.res2);
         so.seconds = std::chrono::duration<double>(now - t_in[j]).count();
+        so.energy = 0.5 * sl.energy2 / d->m.mass_sum;
       }
       if (energy) energy[col] = 0.5 * sl.energy2 / d->m.mass_sum;
       if (out && !odev)
@@ -1366,6 +1399,66 @@ ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int3
   const int R = pick_tile(h, (int64_t)n_fields * n_scales);
   if (R <= 1) return filter_single(h, n_fields, fields, n_scales, k, out, stats, energy, ColScratch{d->w.part, d->w.sc, true});
   return filter_batched(h, R, n_fields, fields, n_scales, k, out, stats, energy);
+}
+
+// Streaming probe: dst = src in 16-byte units, grid-stride (every resident
+// wavefront streams consecutive 1 KiB segments, so reads and writes are
+// fully coalesced).
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const int4* __restrict__ src, int4* __restrict__ dst,
+                                                        int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+ifl_status device_stream_probe(int device, int64_t bytes, int reps, double* best_gbs, double* median_gbs) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return fail(IFL_EDEVICE, "no such HIP device");
+  }
+  IFL_HIP(hipSetDevice(device));
+  const int64_t n = bytes / 16;
+  int4 *a = nullptr, *b = nullptr;
+  if (hipMalloc((void**)&a, n * 16) != hipSuccess || hipMalloc((void**)&b, n * 16) != hipSuccess) {
+    if (a) (void)hipFree(a);
+    (void)hipGetLastError();
+    return fail(IFL_ENOMEM, "hipMalloc of the probe buffers failed");
+  }
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stream_copy, kBlock, 0) != hipSuccess || per < 1) per = 1;
+  const int grid = per * device_cus(device);
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ifl_status st = IFL_OK;
+  std::vector<double> rates;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess || hipMemsetAsync(a, 0, n * 16, s) != hipSuccess) {
+    st = fail(IFL_EDEVICE, "probe set-up failed");
+  } else {
+    k_stream_copy<<<grid, kBlock, 0, s>>>(a, b, n);  // untimed
+    for (int r = 0; r < reps && st == IFL_OK; ++r) {
+      float ms = 0.f;
+      if (hipEventRecord(e0, s) != hipSuccess) st = fail(IFL_EDEVICE, "hipEventRecord failed");
+      k_stream_copy<<<grid, kBlock, 0, s>>>(a, b, n);
+      if (st == IFL_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = fail(IFL_EDEVICE, "timing the probe failed");
+      if (st == IFL_OK) rates.push_back(2.0 * 16.0 * (double)n / (ms * 1e-3) / 1e9);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  (void)hipFree(a);
+  (void)hipFree(b);
+  if (st != IFL_OK) return st;
+  std::sort(rates.begin(), rates.end());
+  *best_gbs = rates.back();
+  *median_gbs = rates[rates.size() / 2];
+  return IFL_OK;
 }
 
 // Zero n doubles (the start of a no-allocation call: a fill kernel rather

@@ -61,8 +61,10 @@ struct SellPack {
 
 void pack_sell(const HostOperator& op, SellPack* out);
 
-// Zero entries appended after the last slice (8 entries x 64 lanes).
-constexpr int64_t kSellTail = 8 * 64;
+// Zero entries appended after the last slice (32 entries x 64 lanes): a
+// kernel may load up to 32 entries past the end of any slice's rows without
+// a bounds check.
+constexpr int64_t kSellTail = 32 * 64;
 
 // ---------------------------------------------------------------- device side
 struct DeviceState;  // defined in device.hip
@@ -91,6 +93,7 @@ ifl_status device_project_cells(Handle* h, const double* cells, double* out);
 ifl_status device_profile_read(Handle* h, int64_t* launches, double* total_ms, double* bytes,
                                int32_t reset);
 std::string device_profile_kernel(Handle* h);
+ifl_status device_stream_probe(int device, int64_t bytes, int reps, double* best_gbs, double* median_gbs);
 ifl_status device_autotune(Handle* h, ifl_tune* out);
 
 }  // namespace ifl

@@ -37,8 +37,8 @@ struct ifl_ticket {
   int32_t mesh_id = 0;
   int32_t n_scales = 0;
   std::vector<double> k;
-  std::vector<double> field;  // host copy
-  double* out = nullptr;      // caller's host buffer, n_scales x L
+  const double* field = nullptr;  // caller's host field (borrowed until ifl_wait)
+  double* out = nullptr;          // caller's host buffer, n_scales x L (NULL: energies only)
   std::vector<ifl_solve_stats> stats;
   int remaining = 0;
   size_t footprint = 0;
@@ -164,14 +164,22 @@ ifl_status run_worker(Worker* wk) {
         t->dev_field = nullptr;
       }
       // the field goes through the staging buffer into row order (stream order
-      // keeps the staging buffer's reuse safe)
-      if (!t->dev_field ||
-          hipMemcpyAsync(wk->stage, t->field.data(), sizeof(double) * wk->L, hipMemcpyHostToDevice, wk->stream) !=
+      // keeps the staging buffer's reuse safe); the permutation raises the
+      // device flag on a NaN or Inf at a wet entry
+      bool bad = false;
+      if (!t->dev_field || batch_clear_flag(wk->w, wk->stream) != IFL_OK ||
+          hipMemcpyAsync(wk->stage, t->field, sizeof(double) * wk->L, hipMemcpyHostToDevice, wk->stream) !=
               hipSuccess ||
-          batch_permute_fields(wk->bm, wk->stage, wk->L, 1, t->dev_field, wk->w.flag, wk->stream) != IFL_OK) {
+          batch_permute_fields(wk->bm, wk->stage, wk->L, 1, t->dev_field, wk->w.flag, wk->stream) != IFL_OK ||
+          batch_check_flag(wk->w, wk->stream, &bad) != IFL_OK) {
         (void)hipGetLastError();
         release_ticket(wk, t);
-        finish_ticket(t, IFL_ENOMEM, "device allocation for the request failed");
+        finish_ticket(t, IFL_ENOMEM, "device allocation or copy for the request failed");
+        continue;
+      }
+      if (bad) {
+        release_ticket(wk, t);
+        finish_ticket(t, IFL_EINVAL, "field has a NaN or Inf at a wet entry");
         continue;
       }
       for (int j = 0; j < t->n_scales; ++j) wk->pending.push_back({t, j});
@@ -212,7 +220,7 @@ ifl_status run_worker(Worker* wk) {
     for (int j = 0; j < R; ++j) {
       if (!wk->slot[j].t || wk->w.slots_host[j].done == 0) continue;
       fin |= 1ull << j;
-      dst[j] = wk->col_out + (int64_t)j * wk->L;
+      if (wk->slot[j].t->out) dst[j] = wk->col_out + (int64_t)j * wk->L;
     }
     if (!fin) continue;
     if ((st = batch_finish(wk->bm, wk->w, fin, dst.data(), wk->stream)) != IFL_OK) return st;
@@ -223,9 +231,9 @@ ifl_status run_worker(Worker* wk) {
       const Column col = wk->slot[j];
       ifl_ticket* t = col.t;
       const BSlot& sl = wk->w.slots_host[j];
-      if (hipMemcpyAsync(t->out + (int64_t)col.scale * wk->L, dst[j], sizeof(double) * wk->L,
-                         hipMemcpyDeviceToHost, wk->stream) != hipSuccess ||
-          hipStreamSynchronize(wk->stream) != hipSuccess)
+      if (t->out && (hipMemcpyAsync(t->out + (int64_t)col.scale * wk->L, dst[j], sizeof(double) * wk->L,
+                                    hipMemcpyDeviceToHost, wk->stream) != hipSuccess ||
+                     hipStreamSynchronize(wk->stream) != hipSuccess))
         return fail(IFL_EDEVICE, "copy of a finished column failed");
       ifl_solve_stats& so = t->stats[col.scale];
       so.iterations = sl.iters;
@@ -234,6 +242,7 @@ ifl_status run_worker(Worker* wk) {
       so.reserved = 0;
       so.rel_residual = sl.bb > 0 ? std::sqrt(sl.res2 / sl.bb) : std::sqrt(sl.res2);
       so.seconds = std::chrono::duration<double>(now - wk->t_in[j]).count();
+      so.energy = 0.5 * sl.energy2 / handle_mass_sum(h);
       wk->slot[j] = Column{nullptr, 0};
       --active;
       if (--t->remaining == 0) {
@@ -346,7 +355,7 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
 
 ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field, int32_t n_scales, const double* k,
                       double* out, ifl_ticket** ticket) {
-  if (!s || !field || !k || !out || !ticket) return fail(IFL_EINVAL, "NULL argument");
+  if (!s || !field || !k || !ticket) return fail(IFL_EINVAL, "NULL argument");
   *ticket = nullptr;
   Worker* wk = nullptr;
   {
@@ -359,14 +368,11 @@ ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field, int32
   for (int32_t j = 0; j < n_scales; ++j)
     if (!(k[j] > 0) || !std::isfinite(k[j])) return fail(IFL_EINVAL, "wavenumbers must be finite and > 0");
   const HostOperator& op = wk->h->op;
-  for (int64_t i = 0; i < op.n; ++i)
-    if (!std::isfinite(field[op.entity[i]])) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");
   ifl_ticket* t = new ifl_ticket();
   t->mesh_id = mesh_id;
   t->n_scales = n_scales;
   t->k.assign(k, k + n_scales);
-  t->field.assign(field, field + op.field_len);
-  for (int64_t i = 0; i < (int64_t)n_scales * op.field_len; ++i) out[i] = 0.0;
+  t->field = field;
   t->out = out;
   t->stats.assign(n_scales, ifl_solve_stats{});
   t->remaining = n_scales;

@@ -371,8 +371,9 @@ def test_full_size_level9_certified(ifl, precision, batch):
     h = _prep(ifl, s, precision=precision, batch=batch, profile=1)
     out, stats = h.filter(phi, ks)
     t = "float" if precision else "double"
-    assert h.profile_kernel() == (f"kb_dir_spmv<{t}, {batch}, true>" if batch > 1
-                                  else f"k_dir_spmv<{t}, {str(bool(precision)).lower()}>")
+    # the fused iteration kernel with the 6-entry head of the first-order operator
+    assert h.profile_kernel() == (f"kb_iter<{t}, {batch}, true, 6>" if batch > 1
+                                  else f"k_cg<{t}, {str(bool(precision)).lower()}, 6>")
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j, k in enumerate(ks):
         cert = _oracle_certificate(op, phi, k, out[0, j])
@@ -403,7 +404,8 @@ def test_full_size_level8_vertex_vector_certified(ifl):
     for i in range(8):
         h.project_cells(cells[i], out=fields[i])
     out, stats = h.filter(fields, ks)
-    assert h.profile_kernel() == "kb_dir_spmv<float, 16, true>"
+    # interleaved vertex vectors: 12 entries a row, the 12-entry head
+    assert h.profile_kernel() == "kb_iter<float, 16, true, 12>"
     op = O.vertex_vector_operator(s, 1)
     for f in (0, 7):
         b = O.project_cells_to_vertices(op, us[f])

@@ -154,9 +154,10 @@ def test_server_errors(ifl):
     f = W.planar_k3_field(m, 1)
     bad = f.copy()
     bad[3] = np.nan
-    with pytest.raises(ifl.IflError) as e:
-        srv.submit(mid, bad, [0.5])
-    assert e.value.status == ifl.IFL_EINVAL
+    # the field is checked on the device when the request is admitted
+    t, _ = srv.submit(mid, bad, [0.5])
+    st, _, _, _ = srv.wait(t, 1)
+    assert st == ifl.IFL_EINVAL
     with pytest.raises(ValueError):
         srv.submit(mid, f[:-1], [0.5])
     with pytest.raises(ifl.IflError) as e:
@@ -215,5 +216,37 @@ def test_server_admission_by_footprint(ifl):
     assert q["admitted"] == len(fields) and q["completed"] == len(fields) and q["used"] == 0, q
     # submitted together, served one after another
     assert all(a < b for a, b in zip(lats, lats[1:])), lats
+    srv.close()
+    h.close()
+
+
+def test_spectrum_only_requests(ifl):
+    """Requests without outputs (out = NULL) return the filtered energies
+    only: bitwise the energies of the same requests with outputs, and equal
+    to 1/2 sum M u^2 / sum M of the returned fields, and to the oracle's
+    spectrum within the mixed tolerance."""
+    s = W.icosphere(5, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    op = O.scalar_operator(s, 2)
+    h = ifl.prepare_mesh(s, 0, 2, precision=ifl.IFL_MIXED)
+    fields = [W.sphere_k3_field(s, 700 + i, n_waves=64) for i in range(3)]
+    ks = W.log_scales(s.h, 5)
+    srv = ifl.Server(4 << 30, slots=8)
+    mid = srv.add(h)
+    full = [srv.submit(mid, f, ks) for f in fields]
+    spec = [srv.submit(mid, f, ks, spectrum_only=True) for f in fields]
+    for i in range(len(fields)):
+        st, stats, o, _ = srv.wait(full[i][0], len(ks))
+        st2, stats2, o2, _ = srv.wait(spec[i][0], len(ks))
+        assert st == 0 and st2 == 0 and o2 is None
+        e_full = np.array([x.energy for x in stats])
+        e_spec = np.array([x.energy for x in stats2])
+        assert np.array_equal(e_full, e_spec), i
+        A = op.A
+        e_out = np.array([0.5 * np.sum(A * O.to_dofs(op, o[j]) ** 2) / np.sum(A) for j in range(len(ks))])
+        assert np.max(np.abs(e_out - e_full) / e_out) < 1e-12, (e_out, e_full)
+        ref = O.filter_scalar(op, fields[i], ks)
+        e_ref = np.array([0.5 * np.sum(A * O.to_dofs(op, ref[j]) ** 2) / np.sum(A) for j in range(len(ks))])
+        assert np.max(np.abs(e_ref - e_full) / e_ref) < 2e-9, (e_ref, e_full)
     srv.close()
     h.close()
