@@ -291,7 +291,9 @@ def c2_leg(ifl):
     """C2: level-8 icosphere (655,362 vertices), 10% jitter, 30% land mask
     (40 caps), one k^-3 field, n = 2 (biharmonic), 20 scales (wavelengths
     32h .. 2h): the batched mixed-precision form (auto tile width) against
-    the plain FP64 path one column at a time, same GPU, same call. The
+    the plain FP64 path one column at a time, same GPU, same call; and the
+    same solves as one complex-shifted first-order system each
+    (IFL_SOLVER_SHIFTED, FP64 and mixed). The
     matrix of K_2 (~8.5 M entries) and the vectors largely fit the 256 MB
     Infinity Cache, so rates are not HBM rates."""
     import torch
@@ -306,8 +308,10 @@ def c2_leg(ifl):
     res = {"workload": f"icosphere-L8 {s.n_vertices} vertices, 30% land mask ({h.num_dofs} dofs), n=2, "
                        f"1 k^-3 field x 20 scales (wavelengths 32h..2h)"}
     out = torch.empty((1, ks.size, h.field_length), dtype=torch.float64, device="cuda:0")
-    for prec, batch, name in ((ifl.IFL_MIXED, 0, "mixed_batched"), (ifl.IFL_FP64, 1, "fp64_single_column")):
-        h.set_options(precision=prec, batch=batch)
+    for prec, batch, solver, name in ((ifl.IFL_MIXED, 0, 0, "mixed_batched"), (ifl.IFL_FP64, 1, 0, "fp64_single_column"),
+                                      (ifl.IFL_FP64, 1, 1, "shifted_fp64_single_column"),
+                                      (ifl.IFL_MIXED, 1, 1, "shifted_mixed_single_column")):
+        h.set_options(precision=prec, batch=batch, solver=solver)
         h.filter(phi, ks[:2], out=out[:, :2])
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -320,6 +324,10 @@ def c2_leg(ifl):
                      "fp64_replacements": int(sum(x.refinements for x in st))}
     res["speedup_mixed_batched_vs_plain_fp64"] = round(res["mixed_batched"]["solves_per_s"] /
                                                        res["fp64_single_column"]["solves_per_s"], 3)
+    res["speedup_shifted_fp64_vs_plain_fp64"] = round(res["shifted_fp64_single_column"]["solves_per_s"] /
+                                                      res["fp64_single_column"]["solves_per_s"], 3)
+    res["shifted"] = ("IFL_SOLVER_SHIFTED: S^-1 = Re (M + i c^(1/2) K)^-1 for n = 2, one complex-shifted "
+                      "first-order system per solve, Jacobi-COCG, one column at a time")
     h.close()
     return res
 
@@ -333,8 +341,9 @@ def serve_leg(args, ifl):
     mesh. Streams: (1) the stated one, 200 warm-up + 2,000 measured requests
     at 200 req/s, spectrum-only (the energies of the filtered fields, so that
     an overloaded queue does not hold up to 32 x 84 MB of outputs per
-    level-10 request); (2) a stream below capacity with the filtered fields
-    returned. Then a like-for-like comparison on one request sample (served,
+    level-10 request), in a bounded window: what has not finished 20 s after
+    the last arrival is cancelled and reported as such; (2) a stream below
+    capacity with the filtered fields returned. Then a like-for-like comparison on one request sample (served,
     fields returned, vs the plain FP64 path one column at a time), and the
     out-of-cache SpMV rates on the level-10 mesh."""
     import threading
@@ -375,7 +384,7 @@ def serve_leg(args, ifl):
             reqs.append((i, int(rng.integers(4)), ks))
         return reqs
 
-    def stream(rate, reqs, warmup, spectrum_only):
+    def stream(rate, reqs, warmup, spectrum_only, drain_s=None):
         # a waiter thread takes the tickets in submission order while the
         # arrivals go on, so finished outputs are dropped at once
         arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
@@ -411,25 +420,44 @@ def serve_leg(args, ifl):
             with cv:
                 box.append((t, ks.size, i, t_sub))
                 cv.notify()
+        cancelled_at = None
+        if drain_s is not None:
+            # bounded window: what has not finished drain_s after the last
+            # arrival is cancelled (its latency is only known to exceed the
+            # window)
+            th.join(timeout=max(0.0, float(arrivals[-1]) + drain_s - (time.perf_counter() - t_start)))
+            if th.is_alive():
+                cancelled_at = time.perf_counter() - t_start
+                srv.cancel()
         th.join()
         meas = [done[k] for k in range(warmup, len(reqs))]
+        ok = [x for x in meas if x[0] == 0]
         t_first = float(arrivals[warmup])
-        t_last = max(x[5] for x in meas)
-        span = t_last - t_first
-        lat = np.array([x[3] for x in meas])
+        t_last = max(x[5] for x in ok) if ok else t_first
+        span = max(1e-9, (cancelled_at if cancelled_at is not None else t_last) - t_first)
+        # latencies of cancelled requests are censored (> their time in the window)
+        lat = np.sort(np.array([x[3] if x[0] == 0 else np.inf for x in meas]))
+
+        def pct(p):
+            v = float(lat[min(len(lat) - 1, int(math.ceil(p / 100.0 * len(lat))) - 1)])
+            return round(v * 1e3, 2) if math.isfinite(v) else None
+
         per = {}
-        for x in meas:
+        for x in ok:
             per.setdefault(meshes[x[2]][:2], []).append(x[3])
-        solves = sum(x[1] for x in meas)
+        solves = sum(x[1] for x in ok)
         return {
-            "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-            "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "p50_latency_ms": pct(50),
+            "p99_latency_ms": pct(99),
             "solves_per_s": round(solves / span, 2),
             "requests": len(meas),
+            "completed_requests": len(ok),
+            "cancelled_requests": int(sum(x[0] == ifl.IFL_ECANCELED for x in meas)),
+            "window_s": round(cancelled_at - t_first, 3) if cancelled_at is not None else None,
             "warmup_requests": warmup,
-            "failed": int(sum(x[0] != 0 for x in meas)),
+            "failed": int(sum(x[0] not in (0, ifl.IFL_ECANCELED) for x in meas)),
             "offered_rate_req_s": rate,
-            "achieved_rate_req_s": round(len(meas) / span, 2),
+            "achieved_rate_req_s": round(len(ok) / span, 2),
             "arrival_window_s": round(float(arrivals[-1] - arrivals[warmup]), 3),
             "measured_span_s": round(span, 3),
             "max_submit_lag_s": round(lag, 4),
@@ -443,7 +471,8 @@ def serve_leg(args, ifl):
     res = {"workload": f"icosphere levels {args.serve_levels} (30% land mask) x n in {{1,2}}, "
                        f"{args.serve_slots} slots per mesh, mixed precision, 1-32 log-uniform scales per request",
            "prepare_s": round(prep_s, 1), "budget_bytes": int(args.serve_budget_gib * (1 << 30))}
-    res["stream"] = stream(args.serve_rate, draw(args.serve_warmup + args.serve_requests), args.serve_warmup, True)
+    res["stream"] = stream(args.serve_rate, draw(args.serve_warmup + args.serve_requests), args.serve_warmup, True,
+                           drain_s=args.serve_drain_s)
     q = srv.query()
     res["memory"] = {"tiles_bytes": q["tiles"], "peak_request_bytes": q["peak_used"],
                      "peak_in_flight": q["peak_in_flight"]}
@@ -584,6 +613,9 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200, help="requests of the stream before the measured ones")
     ap.add_argument("--serve-slots", type=int, default=8, help="column slots per resident mesh")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="device memory budget of the server")
+    ap.add_argument("--serve-drain-s", type=float, default=20.0,
+                    help="the stated stream's window: requests not finished this long after the last arrival "
+                         "are cancelled and counted as such (their latency exceeds the window)")
     ap.add_argument("--serve-sustained-rate", type=float, default=8.0,
                     help="second arrival stream, below the server's capacity, fields returned (req/s; 0 = skip)")
     ap.add_argument("--serve-sustained-requests", type=int, default=100)

@@ -54,6 +54,7 @@ typedef int32_t ifl_status;
 #define IFL_EDEVICE (-5)      /* HIP runtime error, or no usable gfx950 device */
 #define IFL_EUNSUPPORTED (-6) /* placement / order / option not implemented */
 #define IFL_EIO (-7)          /* save / load failure or bad file */
+#define IFL_ECANCELED (-8)    /* a served request cancelled by ifl_server_cancel before it finished */
 
 /* ------------------------------------------------------------------ mesh */
 #define IFL_GEOM_PLANAR 0   /* coords V x 2 (x, y) */
@@ -83,6 +84,16 @@ typedef struct ifl_mesh {
 #define IFL_MIXED 1 /* FP32 matrix values / vectors / SpMV, FP64 reductions, FP64 residual
                        replacement ("reliable updates") and FP64 solution accumulation */
 
+/* How the system S = M + c K_n of an order n >= 2 is solved. */
+#define IFL_SOLVER_KN 0      /* Jacobi-preconditioned CG on S itself (Sect. 2.2.2; default) */
+#define IFL_SOLVER_SHIFTED 1 /* the same S^-1 M phi through first-order systems only:
+                                S^-1 = (1/n) sum_j (M + s_j c^(1/n) K)^-1 with s_j = -1/w_j over the
+                                roots of w^n = -1 (partial fractions of 1/(1 + y^n) in the
+                                eigenvalues y of c^(1/n) M^-1 K); each complex-shifted system by
+                                Jacobi-preconditioned COCG (CG in the bilinear form), a real shift
+                                (odd n) by CG; conjugate shifts share one solve. Each shifted system
+                                stops on its own FP64 true residual; one column at a time. */
+
 typedef struct ifl_options {
   double gamma;      /* filter parameter (Sect. 2.1: 1/2); default 0.5 */
   double rtol;       /* stop when ||M phi - S x||_2 <= rtol * ||M phi||_2; default 1e-12 */
@@ -102,6 +113,9 @@ typedef struct ifl_options {
   int32_t profile;   /* 1 = time the SpMV launches with HIP events (ifl_profile_read) */
   int32_t graphs;    /* 1 = the batched engine replays each 4-iteration chunk of a tile as one captured
                         HIP graph (default), 0 = launches every kernel; results are bitwise equal */
+  int32_t solver;    /* IFL_SOLVER_KN (default) or IFL_SOLVER_SHIFTED (orders n >= 2; ifl_filter and
+                        ifl_spectrum then solve one column at a time whatever 'batch' says; n = 1 and
+                        the serving engine use IFL_SOLVER_KN) */
 } ifl_options;
 
 /* Per-solve statistics (one per field x scale). */
@@ -233,11 +247,13 @@ ifl_status ifl_filter(ifl_handle* h, int32_t n_fields, const double* fields,
  * fields : device, n_fields x L doubles on the handle's device.
  * out    : device, n_fields x n_scales x L doubles on the handle's device.
  * k, stats : as ifl_filter (host).
- * Limits : the handle's logical block count G must satisfy 9 G x 8 bytes
- *          <= 65,280 (G <= 906; the default is at most 512); otherwise
+ * Limits : the handle's logical block count G must satisfy 14 G x 8 bytes
+ *          <= 65,280 (G <= 582; the default is at most 512); otherwise
  *          IFL_EINVAL with a message naming both sizes. Host pointers for
  *          fields or out are IFL_EINVAL. Profiling (ifl_options.profile)
- *          is ignored.
+ *          is ignored, and orders n >= 2 are solved by Jacobi-PCG on S_n
+ *          whatever ifl_options.solver says (the shifted solves need work
+ *          space of their own).
  * All handles on one GPU share its work space, which keeps the last call's
  * contents (each call clears it first): calls that overlap on one GPU
  * (from several threads, or on several handles' streams) race; serialise
@@ -302,6 +318,14 @@ ifl_status ifl_project_cells(ifl_handle* h, const double* cells, double* out);
 int64_t ifl_operator_nnz(const ifl_handle* h);
 ifl_status ifl_export_operator(const ifl_handle* h, int64_t* row_ptr, int32_t* col,
                                double* val, double* mass, int64_t* entity);
+
+/*
+ * The first-order operator K of a handle (same rows and layout as
+ * ifl_export_operator; for order 1 it is K_n itself), which
+ * IFL_SOLVER_SHIFTED solves with. nnz = ifl_first_order_nnz(h).
+ */
+int64_t ifl_first_order_nnz(const ifl_handle* h);
+ifl_status ifl_export_first_order(const ifl_handle* h, int64_t* row_ptr, int32_t* col, double* val);
 
 /* Save / load a prepared handle (Sect. 2.2.1: the precomputed arrays can be
  * saved to disk and reused). Versioned little-endian binary. ifl_load
@@ -433,6 +457,17 @@ int32_t ifl_poll(const ifl_ticket* t);
 
 /* Latency of a finished request (seconds from submit to completion). */
 double ifl_ticket_latency(const ifl_ticket* t);
+
+/*
+ * Cancel the outstanding work of a server: requests still waiting for
+ * admission, and the columns of admitted requests that have not entered a
+ * tile slot yet, finish with IFL_ECANCELED (a request with columns already
+ * in slots completes those first; its outputs for cancelled columns are
+ * not written). Columns already in slots run to their end. Later submits
+ * are accepted as usual. For callers that stop serving with a queue
+ * (shutdown, a bounded measurement window). IFL_EINVAL on NULL.
+ */
+ifl_status ifl_server_cancel(ifl_server* s);
 
 /* Drain outstanding work and destroy the server. */
 void ifl_server_destroy(ifl_server* s);

@@ -19,6 +19,7 @@ from ._ffi import (  # noqa: F401
     IFL_EDEVICE,
     IFL_EUNSUPPORTED,
     IFL_EIO,
+    IFL_ECANCELED,
     IFL_GEOM_PLANAR,
     IFL_GEOM_PERIODIC,
     IFL_GEOM_SPHERE,
@@ -29,6 +30,8 @@ from ._ffi import (  # noqa: F401
     IFL_VERTEX_VECTOR,
     IFL_FP64,
     IFL_MIXED,
+    IFL_SOLVER_KN,
+    IFL_SOLVER_SHIFTED,
     LIB_PATH,
     default_options,
     ifl_apply,

@@ -26,10 +26,11 @@ IFL_ENOTCONV = -4
 IFL_EDEVICE = -5
 IFL_EUNSUPPORTED = -6
 IFL_EIO = -7
+IFL_ECANCELED = -8
 
 STATUS_NAMES = {
     0: "IFL_OK", -1: "IFL_EINVAL", -2: "IFL_EDEGENERATE", -3: "IFL_ENOMEM", -4: "IFL_ENOTCONV",
-    -5: "IFL_EDEVICE", -6: "IFL_EUNSUPPORTED", -7: "IFL_EIO",
+    -5: "IFL_EDEVICE", -6: "IFL_EUNSUPPORTED", -7: "IFL_EIO", -8: "IFL_ECANCELED",
 }
 
 IFL_GEOM_PLANAR = 0
@@ -44,6 +45,8 @@ IFL_VERTEX_VECTOR = 4
 
 IFL_FP64 = 0
 IFL_MIXED = 1
+IFL_SOLVER_KN = 0
+IFL_SOLVER_SHIFTED = 1
 
 
 class ifl_mesh(C.Structure):
@@ -72,6 +75,7 @@ class ifl_options(C.Structure):
         ("reorder", C.c_int32),
         ("profile", C.c_int32),
         ("graphs", C.c_int32),
+        ("solver", C.c_int32),
     ]
 
 
@@ -146,6 +150,10 @@ _PROTOS = {
     "ifl_profile_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_int32]),
     "ifl_profile_kernel": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32]),
+    "ifl_server_cancel": (C.c_int32, [C.c_void_p]),
+    "ifl_first_order_nnz": (C.c_int64, [C.c_void_p]),
+    "ifl_export_first_order": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_double)]),
     "ifl_stream_probe": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]),
     "ifl_autotune": (C.c_int32, [C.c_void_p, C.POINTER(ifl_tune)]),
@@ -381,6 +389,18 @@ class Handle:
             _dptr(val), _dptr(mass), C.cast(ent.ctypes.data, C.POINTER(C.c_int64))))
         return rp, col, val, mass, ent
 
+    def export_first_order(self):
+        """The first-order operator K (rows in the library's order)."""
+        n = self.num_dofs
+        nnz = int(lib().ifl_first_order_nnz(self._h))
+        rp = np.zeros(n + 1, np.int64)
+        col = np.zeros(nnz, np.int32)
+        val = np.zeros(nnz)
+        _check(lib().ifl_export_first_order(
+            self._h, C.cast(rp.ctypes.data, C.POINTER(C.c_int64)), C.cast(col.ctypes.data, C.POINTER(C.c_int32)),
+            _dptr(val)))
+        return rp, col, val
+
     def save(self, path: str):
         _check(lib().ifl_save(self._h, path.encode()))
 
@@ -501,6 +521,11 @@ class Server:
                                 C.c_void_p(out.ctypes.data if out is not None else None), C.byref(t)))
         self._keep[t.value] = (field, ks, out)
         return t, out
+
+    def cancel(self):
+        """Cancel the requests waiting for admission or for a slot
+        (``ifl_server_cancel``); their wait() returns IFL_ECANCELED."""
+        _check(lib().ifl_server_cancel(self._s))
 
     def query(self) -> dict:
         """Memory accounting and request counters (``ifl_server_query``)."""

@@ -26,6 +26,7 @@ static ifl_status check_options(const ifl_options& o) {
   if (o.precision != IFL_FP64 && o.precision != IFL_MIXED) return fail(IFL_EINVAL, "unknown precision");
   if (o.batch < 0 || o.batch > 64) return fail(IFL_EINVAL, "batch must be in 0..64");
   if (o.graphs != 0 && o.graphs != 1) return fail(IFL_EINVAL, "graphs must be 0 or 1");
+  if (o.solver != IFL_SOLVER_KN && o.solver != IFL_SOLVER_SHIFTED) return fail(IFL_EINVAL, "unknown solver");
   return IFL_OK;
 }
 
@@ -196,6 +197,24 @@ ifl_status ifl_project_cells(ifl_handle* h, const double* cells, double* out) {
 
 int64_t ifl_operator_nnz(const ifl_handle* h) { return h ? (int64_t)h->op.col.size() : 0; }
 
+int64_t ifl_first_order_nnz(const ifl_handle* h) {
+  if (!h) return 0;
+  return h->op.order >= 2 ? (int64_t)h->op.k1_col.size() : (int64_t)h->op.col.size();
+}
+
+ifl_status ifl_export_first_order(const ifl_handle* h, int64_t* row_ptr, int32_t* col, double* val) {
+  if (!h) return fail(IFL_EINVAL, "handle is NULL");
+  const HostOperator& op = h->op;
+  const bool own = op.order >= 2;
+  const auto& rp = own ? op.k1_row_ptr : op.row_ptr;
+  const auto& cc = own ? op.k1_col : op.col;
+  const auto& vv = own ? op.k1_val : op.val;
+  if (row_ptr) std::memcpy(row_ptr, rp.data(), sizeof(int64_t) * rp.size());
+  if (col) std::memcpy(col, cc.data(), sizeof(int32_t) * cc.size());
+  if (val) std::memcpy(val, vv.data(), sizeof(double) * vv.size());
+  return IFL_OK;
+}
+
 ifl_status ifl_export_operator(const ifl_handle* h, int64_t* row_ptr, int32_t* col, double* val, double* mass,
                                int64_t* entity) {
   if (!h) return fail(IFL_EINVAL, "handle is NULL");
@@ -208,7 +227,7 @@ ifl_status ifl_export_operator(const ifl_handle* h, int64_t* row_ptr, int32_t* c
   return IFL_OK;
 }
 
-static const char kMagic[8] = {'I', 'F', 'L', 'H', '0', '0', '0', '1'};
+static const char kMagic[8] = {'I', 'F', 'L', 'H', '0', '0', '0', '2'};
 
 ifl_status ifl_save(const ifl_handle* h, const char* path) {
   if (!h || !path) return fail(IFL_EINVAL, "handle / path is NULL");
@@ -232,6 +251,13 @@ ifl_status ifl_save(const ifl_handle* h, const char* path) {
   w(op.val.data(), sizeof(double) * op.val.size());
   w(op.mass.data(), sizeof(double) * op.mass.size());
   w(op.entity.data(), sizeof(int64_t) * op.entity.size());
+  if (op.order >= 2) {
+    const int64_t nnz1 = (int64_t)op.k1_col.size();
+    w(&nnz1, 8);
+    w(op.k1_row_ptr.data(), sizeof(int64_t) * op.k1_row_ptr.size());
+    w(op.k1_col.data(), sizeof(int32_t) * op.k1_col.size());
+    w(op.k1_val.data(), sizeof(double) * op.k1_val.size());
+  }
   if (op.placement == IFL_VERTEX_VECTOR) {
     const int64_t pn = (int64_t)op.proj_tri.size();
     w(&op.n_cells, 8);
@@ -282,6 +308,22 @@ ifl_status ifl_load(const char* path, const ifl_options* opt, ifl_handle** out) 
     r(op.val.data(), sizeof(double) * op.val.size());
     r(op.mass.data(), sizeof(double) * op.mass.size());
     r(op.entity.data(), sizeof(int64_t) * op.entity.size());
+  }
+  if (ok && op.order >= 2) {
+    int64_t nnz1 = 0;
+    r(&nnz1, 8);
+    ok = ok && nnz1 > 0 && nnz1 <= nnz;
+    if (ok) {
+      op.k1_row_ptr.resize(op.n + 1);
+      op.k1_col.resize(nnz1);
+      op.k1_val.resize(nnz1);
+      r(op.k1_row_ptr.data(), sizeof(int64_t) * op.k1_row_ptr.size());
+      r(op.k1_col.data(), sizeof(int32_t) * op.k1_col.size());
+      r(op.k1_val.data(), sizeof(double) * op.k1_val.size());
+    }
+    ok = ok && op.k1_row_ptr[0] == 0 && op.k1_row_ptr[op.n] == nnz1;
+    for (int64_t i = 0; ok && i < op.n; ++i) ok = op.k1_row_ptr[i] <= op.k1_row_ptr[i + 1];
+    for (int64_t e = 0; ok && e < nnz1; ++e) ok = op.k1_col[e] >= 0 && op.k1_col[e] < op.n;
   }
   if (ok && op.placement == IFL_VERTEX_VECTOR) {
     int64_t pn = 0;

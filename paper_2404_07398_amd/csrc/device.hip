@@ -117,6 +117,51 @@ struct ColWork {
   int64_t stage_len = 0;
 };
 
+// ---- first-order shifted solves (IFL_SOLVER_SHIFTED) ----
+// Complex vectors are interleaved (re, im) pairs of n_pad entries.
+// Partial sums of a complex launch (units of G): two parities of nine sums
+// (the complex (p, q), (q, z), (q, d^-1 q), (r, z) and the real ||r||^2),
+// then the floor norm, ||M phi||^2 and the two finish sums.
+constexpr int kCPqR = 0, kCPqI = 1, kCZuR = 2, kCZuI = 3, kCUuR = 4, kCUuI = 5, kCRzR = 6, kCRzI = 7, kCRr = 8,
+              kCPerParity = 9;
+__host__ __device__ constexpr int cidx(int parity, int q) { return parity * kCPerParity + q; }
+enum { CP_FL = 2 * kCPerParity, CP_BB, CP_RES, CP_EN, CP_COUNT };
+
+// State of one complex-shifted solve, two copies as for Scalars.
+struct CScalars {
+  double tol2, rr_ref, rr_last, bb;
+  double sr, si;          // the shift sigma = sr + i si of M + sigma K
+  double rho_r, rho_i;    // (r, z) of the z a replacement superseded
+  int32_t iters, done, updates, mode;
+  uint32_t fused_bits;
+  int32_t xbuf;
+  int32_t pad[2];
+};
+
+// The first-order operator K of a handle of order >= 2 (sliced ELL, the
+// rows of K_n).
+struct DevK1 {
+  int64_t nnz_stored = 0;
+  int64_t* sptr = nullptr;
+  int32_t* col = nullptr;
+  double* val64 = nullptr;
+  float* val32 = nullptr;
+  double* kdiag64 = nullptr;
+  float* kdiag32 = nullptr;
+  int head = 6;
+};
+
+// Work space of the shifted solves (made on first use).
+struct ShiftWork {
+  double* x[2] = {nullptr, nullptr};  // complex FP64 solution
+  double *z64[2] = {nullptr, nullptr}, *u64[2] = {nullptr, nullptr}, *p64[2] = {nullptr, nullptr}, *d64 = nullptr;
+  float *z32[2] = {nullptr, nullptr}, *u32[2] = {nullptr, nullptr}, *p32[2] = {nullptr, nullptr}, *d32 = nullptr;
+  double* acc = nullptr;   // the weighted sum of the shifted solutions (real), n_pad
+  double* part = nullptr;  // CP_COUNT x G
+  CScalars* sc = nullptr;  // two copies
+  CScalars* sc_host = nullptr;  // pinned, two slots
+};
+
 struct DeviceState {
   int device = 0;
   hipStream_t own_stream = nullptr;
@@ -134,6 +179,8 @@ struct DeviceState {
   std::string prof_kernel;  // the kernel those launches ran
   // batched engine work space (allocated on first use), and narrower tiles
   // that the last columns of a call move to
+  DevK1 k1;
+  ShiftWork sw;
   BatchWork bw;
   std::deque<BatchWork> spare;  // a deque: adding a tile leaves the others where they are
   // grid sizes picked by the autotuner, per (tile size, precision), and the
@@ -241,6 +288,11 @@ __device__ __forceinline__ double reduce_partials(const double* a, int G, double
   __syncthreads();
   return *lds_out;
 }
+
+template <typename T>
+struct alignas(2 * sizeof(T)) Pack2 {
+  T a, b;
+};
 
 // Vectors of a one-column solve; x, z, u = diag(S)^-1 S p and p alternate
 // between two buffers (a launch gathers the ones it reads while it writes
@@ -604,6 +656,398 @@ __global__ __launch_bounds__(kBlock) void k_cg(Mat m, CgVecs<T> v, const double*
   }
 }
 
+// ------------------------------------------------- complex-shifted solves
+// Complex arithmetic on (re, im) pairs; every product is written with the
+// same fma sequence wherever it is evaluated, so a value formed for a
+// gathered neighbour is bitwise the value that row's own lane stores.
+template <typename T>
+struct Cx {
+  T r, i;
+};
+template <typename T>
+__device__ __forceinline__ Cx<T> cfma(Cx<T> a, Cx<T> b, Cx<T> c) {  // a b + c
+  return Cx<T>{fma(a.r, b.r, fma(-a.i, b.i, c.r)), fma(a.r, b.i, fma(a.i, b.r, c.i))};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return Cx<T>{fma(a.r, b.r, -a.i * b.i), fma(a.r, b.i, a.i * b.r)};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cdiv(Cx<T> a, Cx<T> b) {
+  const T den = fma(b.r, b.r, b.i * b.i);
+  return Cx<T>{fma(a.r, b.r, a.i * b.i) / den, fma(a.i, b.r, -a.r * b.i) / den};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cld(const T* p, int64_t j) {
+  const Pack2<T> v = *reinterpret_cast<const Pack2<T>*>(p + 2 * j);
+  return Cx<T>{v.a, v.b};
+}
+template <typename T>
+__device__ __forceinline__ void cst(T* p, int64_t j, Cx<T> x) {
+  *reinterpret_cast<Pack2<T>*>(p + 2 * j) = Pack2<T>{x.r, x.i};
+}
+__device__ __forceinline__ Cx<double> cd(Cx<float> a) { return Cx<double>{(double)a.r, (double)a.i}; }
+__device__ __forceinline__ Cx<double> cd(Cx<double> a) { return a; }
+template <typename T>
+__device__ __forceinline__ Cx<T> ct(Cx<double> a) {
+  return Cx<T>{(T)a.r, (T)a.i};
+}
+
+template <typename T>
+struct CVecs {
+  T* z[2];
+  T* u[2];
+  T* p[2];
+  T* d;          // diag(M + sigma K), complex
+  double* x[2];  // solution, complex FP64
+};
+
+// Start of a shifted solve of (M + sigma K) y = M phi from y0 = phi: r0 =
+// -sigma K phi with FP64 values, d = m + sigma diag(K), z0 = r0 / d into
+// buffer 0, and the sums of (r, z) (complex), ||r||^2 and ||M phi||^2 (as
+// parity 1, read by launch 0).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cinit(Mat m, CVecs<T> v, const double* phi, double* part, CScalars* sc,
+                                                   double sr, double si, int G, int spb) {
+  __shared__ double lds[4][kWavesPerBlock];
+  const int lb = logical_block(G);
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const Cx<double> sig{sr, si};
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+    const int64_t row = s * kWave + lane;
+    if (row >= m.n) continue;
+    const int64_t base = m.sptr[s];
+    const int w = (int)((m.sptr[s + 1] - base) / kWave);
+    double a = 0.0;
+    for (int k = 0; k < w; ++k) {
+      const int64_t e = base + (int64_t)k * kWave + lane;
+      a += m.val64[e] * phi[m.col[e]];
+    }
+    const double ph = phi[row], kd = m.kdiag64[row], mi = m.mass64[row];
+    const double kphi = kd * ph + a;
+    const Cx<double> r64{-sr * kphi, -si * kphi};
+    const Cx<T> dt = ct<T>(Cx<double>{fma(sr, kd, mi), si * kd});
+    const Cx<T> rt = ct<T>(r64);
+    const Cx<T> zt = cdiv(rt, dt);
+    cst(v.x[0], row, Cx<double>{ph, 0.0});
+    cst(v.z[0], row, zt);
+    cst(v.d, row, dt);
+    const Cx<double> rz = cmul(cd(rt), cd(zt));
+    acc[0] += rz.r;
+    acc[1] += rz.i;
+    acc[2] += r64.r * r64.r + r64.i * r64.i;
+    acc[3] += (mi * ph) * (mi * ph);
+  }
+  block_sum<4>(acc, lds);
+  if (threadIdx.x == 0) {
+    part[cidx(1, kCRzR) * G + lb] = acc[0];
+    part[cidx(1, kCRzI) * G + lb] = acc[1];
+    part[cidx(1, kCRr) * G + lb] = acc[2];
+    part[CP_BB * G + lb] = acc[3];
+    part[CP_FL * G + lb] = 0.0;
+    if (lb == 0) {
+      CScalars s0{};
+      s0.sr = sr;
+      s0.si = si;
+      s0.mode = M_INIT;
+      sc[0] = s0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_csetup(double* part, CScalars* sc, double rtol, int G) {
+  __shared__ double lw[kWavesPerBlock];
+  __shared__ double lo;
+  const double bb = reduce_partials(part + CP_BB * G, G, lw, &lo);
+  if (threadIdx.x == 0) {
+    sc[0].bb = bb;
+    sc[0].tol2 = rtol * rtol * bb;
+  }
+}
+
+// One iteration of Jacobi-preconditioned COCG on the complex-symmetric
+// (M + sigma K) y = M phi per launch, or its FP64 residual replacement: the
+// complex counterpart of k_cg, with the bilinear form (a, b) = sum a_i b_i
+// (no conjugation) in every inner product of the recurrences, so that the
+// algebra of k_cg carries over (rho_next = rho - 2 alpha (q, z) + alpha^2
+// (q, d^-1 q)); the stopping and replacement tests use the Euclidean norm
+// ||r||^2 = sum |r_i|^2. d^-1 (M + sigma K) z' = z' + sigma d^-1 K_off z'.
+template <typename T, bool MIXED, int U>
+__global__ __launch_bounds__(kBlock) void k_ccg(Mat m, CVecs<T> v, const double* phi, double* part, CScalars* sc,
+                                                 int launch, int G, int spb, int max_iter) {
+  __shared__ double lds10[10][kWavesPerBlock];
+  __shared__ double lds9[9][kWavesPerBlock];
+  const int cur = launch & 1, nxt = cur ^ 1;
+  const CScalars s0 = sc[cur];
+  const int lb = logical_block(G);
+  const bool leader = lb == 0 && threadIdx.x == 0;
+  if (s0.done) {
+    if (leader) {
+      CScalars s1 = s0;
+      s1.fused_bits &= ~(1u << (launch & 31));
+      sc[nxt] = s1;
+    }
+    return;
+  }
+  double q[10];
+  {
+    const double* const src[10] = {
+        part + cidx(nxt, kCPqR) * G, part + cidx(nxt, kCPqI) * G, part + cidx(nxt, kCZuR) * G,
+        part + cidx(nxt, kCZuI) * G, part + cidx(nxt, kCUuR) * G, part + cidx(nxt, kCUuI) * G,
+        part + cidx(nxt, kCRzR) * G, part + cidx(nxt, kCRzI) * G, part + cidx(nxt, kCRr) * G, part + CP_FL * G};
+    reduce_many<10>(src, G, q, lds10);
+  }
+  const Cx<double> pq{q[0], q[1]}, zu{q[2], q[3]}, uu{q[4], q[5]}, rz{q[6], q[7]};
+  const double rr = q[8], fl = q[9];
+  CScalars s1 = s0;
+  s1.fused_bits &= ~(1u << (launch & 31));
+  int mode;
+  Cx<double> alpha{0.0, 0.0}, beta{0.0, 0.0};
+  bool restart = false;
+  if (s0.mode != M_ITER) {
+    const double floor2 = fl * (kFloorUnits * kUnitRoundoff) * (kFloorUnits * kUnitRoundoff);
+    s1.rr_last = rr;
+    s1.rr_ref = rr;
+    if (rr <= fmax(s0.tol2, floor2)) {
+      s1.done = 1;
+      mode = M_DONE;
+    } else if (s0.iters >= max_iter) {
+      s1.done = 3;
+      mode = M_DONE;
+    } else {
+      mode = M_ITER;
+      restart = s0.mode == M_INIT;
+      beta = restart ? Cx<double>{0.0, 0.0} : cdiv(rz, Cx<double>{s0.rho_r, s0.rho_i});
+    }
+  } else {
+    alpha = cdiv(rz, pq);
+    s1.rr_last = rr;
+    if (!(pq.r * pq.r + pq.i * pq.i > 0.0) || !isfinite(alpha.r) || !isfinite(alpha.i)) {
+      s1.done = 2;
+      mode = M_DONE;
+    } else if (rr <= s0.tol2 || rr <= kReplaceDelta2 * s0.rr_ref) {
+      mode = M_REPLACE;
+      s1.rho_r = rz.r;
+      s1.rho_i = rz.i;
+      s1.updates += 1;
+    } else if (s0.iters >= max_iter) {
+      s1.done = 3;
+      mode = M_DONE;
+    } else {
+      mode = M_ITER;
+      // (rho - 2 alpha zu + alpha^2 uu) / rho
+      const Cx<double> t1 = cmul(Cx<double>{-2.0 * alpha.r, -2.0 * alpha.i}, zu);
+      const Cx<double> t2 = cmul(cmul(alpha, alpha), uu);
+      beta = cdiv(Cx<double>{rz.r + t1.r + t2.r, rz.i + t1.i + t2.i}, rz);
+    }
+  }
+  if (mode == M_DONE) s1.xbuf = cur;
+  if (mode == M_ITER) {
+    s1.iters += 1;
+    if (alpha.r != 0.0 || alpha.i != 0.0) s1.fused_bits |= 1u << (launch & 31);
+  }
+  s1.mode = mode;
+  if (mode == M_DONE) {
+    if (leader) sc[nxt] = s1;
+    return;
+  }
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  const T* __restrict__ zin = v.z[cur];
+  const T* __restrict__ uin = v.u[cur];
+  const T* __restrict__ pin = v.p[cur];
+  T* __restrict__ zout = v.z[nxt];
+  T* __restrict__ uout = v.u[nxt];
+  T* __restrict__ pout = v.p[nxt];
+  const double* __restrict__ xin = v.x[cur];
+  double* __restrict__ xout = v.x[nxt];
+  const Cx<double> sig{s0.sr, s0.si};
+  double acc[9] = {};
+  if (mode == M_REPLACE) {
+    const double sabs = sqrt(sig.r * sig.r + sig.i * sig.i);
+    for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+      const int64_t row = s * kWave + lane;
+      if (row >= m.n) continue;
+      const int64_t base = m.sptr[s];
+      const int w = (int)((m.sptr[s + 1] - base) / kWave);
+      Cx<double> a{0.0, 0.0};
+      double aa = 0.0;
+      for (int k0 = 0; k0 < w; k0 += U) {
+        int32_t cu[U];
+        double vu[U];
+        Cx<double> xu[U];
+        Cx<T> pu[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t e = base + (int64_t)(k0 + u) * kWave + lane;
+          cu[u] = m.col[e];
+          const double vv = m.val64[e];
+          vu[u] = k0 + u < w ? vv : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          xu[u] = cld(xin, cu[u]);
+          pu[u] = cld(pin, cu[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const Cx<double> xn = cfma(alpha, cd(pu[u]), xu[u]);
+          a.r = fma(vu[u], xn.r, a.r);
+          a.i = fma(vu[u], xn.i, a.i);
+          aa = fma(fabs(vu[u]), sqrt(xn.r * xn.r + xn.i * xn.i), aa);
+        }
+      }
+      const Cx<T> pi = cld(pin, row), ui = cld(uin, row);
+      const Cx<double> xi = cfma(alpha, cd(pi), cld(xin, row));
+      const double mi = m.mass64[row], kd = m.kdiag64[row], ph = phi[row];
+      // r = M (phi - x) - sigma (kd x + K_off x)
+      const Cx<double> kx{fma(kd, xi.r, a.r), fma(kd, xi.i, a.i)};
+      const Cx<double> skx = cmul(sig, kx);
+      const Cx<double> r64{mi * (ph - xi.r) - skx.r, -mi * xi.i - skx.i};
+      const double xa = sqrt(xi.r * xi.r + xi.i * xi.i);
+      const double mag = fabs(mi * ph) + fabs(mi) * xa + sabs * (fabs(kd) * xa + aa);
+      const Cx<T> rt = ct<T>(r64);
+      const Cx<T> zt = cdiv(rt, cld(v.d, row));
+      cst(xout, row, xi);
+      cst(zout, row, zt);
+      cst(pout, row, pi);
+      cst(uout, row, ui);
+      const Cx<double> rzv = cmul(cd(rt), cd(zt));
+      acc[6] += rzv.r;
+      acc[7] += rzv.i;
+      acc[8] += r64.r * r64.r + r64.i * r64.i;
+      acc[0] += mag * mag;  // the floor norm (stored in its own slot below)
+    }
+  } else {
+    const Cx<T> at = ct<T>(alpha), bt = ct<T>(beta), nat = ct<T>(Cx<double>{-alpha.r, -alpha.i});
+    const Cx<T> st = ct<T>(sig);
+    const T* __restrict__ val = mval<T>(m);
+    const bool step = alpha.r != 0.0 || alpha.i != 0.0;
+    for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+      const int64_t row = s * kWave + lane;
+      if (row >= m.n) continue;
+      const int64_t base = m.sptr[s];
+      const int w = (int)((m.sptr[s + 1] - base) / kWave);
+      Cx<T> a{(T)0, (T)0};
+      for (int k0 = 0; k0 < w; k0 += U) {
+        int32_t cu[U];
+        T vu[U];
+        Cx<T> zu_[U], uu_[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t e = base + (int64_t)(k0 + u) * kWave + lane;
+          cu[u] = m.col[e];
+          const T vv = val[e];
+          vu[u] = k0 + u < w ? vv : (T)0;
+        }
+        if (step) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            zu_[u] = cld(zin, cu[u]);
+            uu_[u] = cld(uin, cu[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const Cx<T> zn = cfma(nat, uu_[u], zu_[u]);
+            a.r = fma(vu[u], zn.r, a.r);
+            a.i = fma(vu[u], zn.i, a.i);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) zu_[u] = cld(zin, cu[u]);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            a.r = fma(vu[u], zu_[u].r, a.r);
+            a.i = fma(vu[u], zu_[u].i, a.i);
+          }
+        }
+      }
+      const Cx<T> zi = cld(zin, row), di = cld(v.d, row);
+      const Cx<T> ui = restart ? Cx<T>{(T)0, (T)0} : cld(uin, row);
+      const Cx<T> pi = restart ? Cx<T>{(T)0, (T)0} : cld(pin, row);
+      const Cx<T> zn = step ? cfma(nat, ui, zi) : zi;
+      const Cx<double> xi = cld(xin, row);
+      cst(xout, row, step ? cfma(alpha, cd(pi), xi) : xi);
+      const Cx<T> pn = cfma(bt, pi, zn);
+      const Cx<T> sa = cdiv(cmul(st, a), di);  // sigma d^-1 K_off z'
+      const Cx<T> un = cfma(bt, ui, Cx<T>{zn.r + sa.r, zn.i + sa.i});
+      cst(zout, row, zn);
+      cst(pout, row, pn);
+      cst(uout, row, un);
+      const Cx<double> dd = cd(di), zz = cd(zn), uv = cd(un);
+      const Cx<double> du = cmul(dd, uv);
+      const Cx<double> pqv = cmul(cd(pn), du), zuv = cmul(zz, du), uuv = cmul(uv, du);
+      const Cx<double> dz = cmul(dd, zz);
+      const Cx<double> rzv = cmul(zz, dz);
+      acc[0] += pqv.r;
+      acc[1] += pqv.i;
+      acc[2] += zuv.r;
+      acc[3] += zuv.i;
+      acc[4] += uuv.r;
+      acc[5] += uuv.i;
+      acc[6] += rzv.r;
+      acc[7] += rzv.i;
+      acc[8] += dz.r * dz.r + dz.i * dz.i;
+    }
+    (void)at;
+  }
+  block_sum<9>(acc, lds9);
+  if (threadIdx.x == 0) {
+    if (mode == M_REPLACE) {
+      part[cidx(cur, kCRzR) * G + lb] = acc[6];
+      part[cidx(cur, kCRzI) * G + lb] = acc[7];
+      part[cidx(cur, kCRr) * G + lb] = acc[8];
+      part[CP_FL * G + lb] = acc[0];
+    } else {
+#pragma unroll
+      for (int q2 = 0; q2 < kCPerParity; ++q2) part[cidx(cur, q2) * G + lb] = acc[q2];
+    }
+    if (lb == 0) sc[nxt] = s1;
+  }
+}
+
+// acc += w x[stride i] over the rows (the real part of a complex solution:
+// stride 2)
+__global__ void k_accumulate(double* __restrict__ acc, const double* __restrict__ x, int stride, double w, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) acc[i] = fma(w, x[(int64_t)stride * i], acc[i]);
+}
+
+// End of a shifted solve: the summed solution to the caller's numbering,
+// with the partials of the FP64 true residual of S = M + c K_n itself (K_n
+// in m) and of sum M x^2.
+__global__ __launch_bounds__(kBlock) void k_sfinish(Mat m, const double* x, const double* phi, double c,
+                                                    const int64_t* entity, double* out, double* part, int G, int spb) {
+  __shared__ double lds[2][kWavesPerBlock];
+  const int lb = logical_block(G);
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  double acc[2] = {0.0, 0.0};
+  const int64_t s_end = min((int64_t)(lb + 1) * spb, m.n_slices);
+  for (int64_t s = (int64_t)lb * spb + wid; s < s_end; s += kWavesPerBlock) {
+    const int64_t row = s * kWave + lane;
+    if (row >= m.n) continue;
+    const int64_t base = m.sptr[s];
+    const int w = (int)((m.sptr[s + 1] - base) / kWave);
+    double a = 0.0;
+    for (int k = 0; k < w; ++k) {
+      const int64_t e = base + (int64_t)k * kWave + lane;
+      a += m.val64[e] * x[m.col[e]];
+    }
+    const double xi = x[row];
+    const double r64 = m.mass64[row] * (phi[row] - xi) - c * (m.kdiag64[row] * xi + a);
+    if (out) out[entity[row]] = xi;
+    acc[0] += r64 * r64;
+    acc[1] += m.mass64[row] * xi * xi;
+  }
+  block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    part[CP_RES * G + lb] = acc[0];
+    part[CP_EN * G + lb] = acc[1];
+  }
+}
+
 // End of a solve: x (the buffer the stopping launch recorded, else the last
 // one written) scattered to the caller's numbering; partials of the true
 // FP64 residual and of sum M x^2.
@@ -761,6 +1205,20 @@ static void* noalloc_scratch_addr(int device) {
   return g_scratch_addr[device];
 }
 
+// Entries per row the gathering kernels load together: the smallest class
+// (6, 12, 20) that covers 90% of the slices.
+static int head_class(const SellPack& sp) {
+  std::vector<int64_t> widths((size_t)sp.n_slices);
+  for (int64_t s = 0; s < sp.n_slices; ++s) widths[(size_t)s] = (sp.slice_ptr[s + 1] - sp.slice_ptr[s]) / kWave;
+  int64_t w90 = 0;
+  if (!widths.empty()) {
+    const size_t at = (widths.size() * 9) / 10;
+    std::nth_element(widths.begin(), widths.begin() + at, widths.end());
+    w90 = widths[at];
+  }
+  return w90 <= 6 ? 6 : (w90 <= 12 ? 12 : 20);
+}
+
 ifl_status device_create(Handle* h) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
@@ -807,20 +1265,23 @@ ifl_status device_create(Handle* h) {
   // the batched kernels' pipelined head: the smallest class (6, 12, 20
   // entries) that covers 90% of the slices; wider slices finish their rows
   // unpipelined
-  {
-    std::vector<int64_t> widths((size_t)m.n_slices);
-    for (int64_t s = 0; s < m.n_slices; ++s) widths[(size_t)s] = (sp.slice_ptr[s + 1] - sp.slice_ptr[s]) / kWave;
-    int64_t w90 = 0;
-    if (!widths.empty()) {
-      const size_t at = (widths.size() * 9) / 10;
-      std::nth_element(widths.begin(), widths.begin() + at, widths.end());
-      w90 = widths[at];
-    }
-    m.head = w90 <= 6 ? 6 : (w90 <= 12 ? 12 : 20);
-    if (const char* e = std::getenv("IFL_HEAD")) {
-      const int v = std::atoi(e);
-      if (v == 6 || v == 12 || v == 20) m.head = v;
-    }
+  m.head = head_class(sp);
+  if (const char* e = std::getenv("IFL_HEAD")) {
+    const int v = std::atoi(e);
+    if (v == 6 || v == 12 || v == 20) m.head = v;
+  }
+  // orders >= 2: the first-order operator for the shifted solves
+  if (h->op.order >= 2 && !h->op.k1_col.empty()) {
+    SellPack s1;
+    pack_sell_csr(h->op.n, h->op.k1_row_ptr, h->op.k1_col, h->op.k1_val, h->op.mass, &s1);
+    DevK1& k1 = d->k1;
+    k1.nnz_stored = s1.slice_ptr.back();
+    k1.head = head_class(s1);
+    std::vector<float> w32(s1.val.begin(), s1.val.end());
+    std::vector<float> kd1(s1.diag.begin(), s1.diag.end());
+    if ((st = upload(&k1.sptr, s1.slice_ptr)) || (st = upload(&k1.col, s1.col)) || (st = upload(&k1.val64, s1.val)) ||
+        (st = upload(&k1.val32, w32)) || (st = upload(&k1.kdiag64, s1.diag)) || (st = upload(&k1.kdiag32, kd1)))
+      return st;
   }
 
   // launch geometry: logical blocks own contiguous slice ranges
@@ -863,6 +1324,15 @@ void device_destroy(Handle* h) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (d->w.sc_host) (void)hipHostFree(d->w.sc_host);
+  const DevK1& k1 = d->k1;
+  const ShiftWork& sw = d->sw;
+  void* sptrs[] = {k1.sptr,    k1.col,     k1.val64,   k1.val32,   k1.kdiag64, k1.kdiag32, sw.x[0],  sw.x[1],
+                   sw.z64[0],  sw.z64[1],  sw.u64[0],  sw.u64[1],  sw.p64[0],  sw.p64[1],  sw.d64,   sw.z32[0],
+                   sw.z32[1],  sw.u32[0],  sw.u32[1],  sw.p32[0],  sw.p32[1],  sw.d32,     sw.acc,   sw.part,
+                   sw.sc};
+  for (void* p : sptrs)
+    if (p) (void)hipFree(p);
+  if (sw.sc_host) (void)hipHostFree(sw.sc_host);
   batch_free(&d->bw);
   for (BatchWork& t : d->spare) batch_free(&t);
   if (d->field_stage) (void)hipFree(d->field_stage);
@@ -937,6 +1407,7 @@ struct ColScratch {
   double* part;
   Scalars* sc;  // two copies
   bool allow_profile;  // the handle's profiling events may be made and used
+  bool allow_shifted;  // the shifted solves (their own work space) may run
 };
 
 template <typename T, bool MIXED, int U>
@@ -945,14 +1416,31 @@ void launch_cg(const Mat& m, const CgVecs<T>& v, const double* phi, const ColScr
   k_cg<T, MIXED, U><<<G, kBlock, 0, s>>>(m, v, phi, cs.part, cs.sc, launch, G, spb, max_iter);
 }
 
+// Zero n doubles (a fill kernel rather than a memset node, so that the calls
+// that use it can also be captured)
+__global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// Result of the CG loop of one column.
+struct ColRun {
+  Scalars last;          // host copy of the final state
+  int64_t launched = 0;  // launches made
+  double secs = 0.0;
+};
+
+// Jacobi-PCG on (M + c K) x = M phi (w.phi) from x0 = phi, K in m (K_n, or
+// the first-order operator of a shifted solve): start, then launches in
+// chunks of 8 until a launch stops; the solution is left in w.x[buffer of
+// the final state] (see k_finish).
 template <typename T, bool MIXED>
-ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* out_dev, double* energy,
-                        const ColScratch& cs) {
+ifl_status run_column(Handle* h, const Mat& m, int head, double c, const ColScratch& cs, bool prof_ok,
+                      ColRun* res) {
   DeviceState* d = h->dev;
   ColWork& w = d->w;
   const DevMatrix& M = d->m;
   hipStream_t s = stream_of(h);
-  const Mat m = mat_view(M);
   CgVecs<T> v;
   if constexpr (MIXED) {
     v = CgVecs<T>{{w.z32[0], w.z32[1]}, {w.u32[0], w.u32[1]}, {w.p32[0], w.p32[1]}, w.d32, {w.x[0], w.x[1]}};
@@ -960,20 +1448,19 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
     v = CgVecs<T>{{w.z[0], w.z[1]}, {w.u[0], w.u[1]}, {w.p[0], w.p[1]}, w.d, {w.x[0], w.x[1]}};
   }
   const int G = d->G, spb = d->spb;
-  const double c = h->opt.gamma / std::pow(k, 2.0 * h->op.order);
   const auto t0 = std::chrono::steady_clock::now();
   k_init<T><<<G, kBlock, 0, s>>>(m, v, w.phi, cs.part, cs.sc, c, G, spb);
   k_setup<<<1, kBlock, 0, s>>>(cs.part, cs.sc, h->opt.rtol, G);
   IFL_HIP(hipGetLastError());
 
   const int chunk = 8;  // launches between host checks
-  const bool prof = h->opt.profile != 0 && cs.allow_profile;
+  const bool prof = h->opt.profile != 0 && cs.allow_profile && prof_ok;
   const int max_iter = h->opt.max_iter;
   // at most max_iter iterating launches, each followed by at most one
   // replacement, and the stopping launch: the cap ends the loop in any case
   const int64_t max_launch = 2 * (int64_t)max_iter + 16;
   void (*cg)(const Mat&, const CgVecs<T>&, const double*, const ColScratch&, int, int, int, int, hipStream_t) =
-      M.head <= 6 ? launch_cg<T, MIXED, 6> : (M.head <= 12 ? launch_cg<T, MIXED, 12> : launch_cg<T, MIXED, 20>);
+      head <= 6 ? launch_cg<T, MIXED, 6> : (head <= 12 ? launch_cg<T, MIXED, 12> : launch_cg<T, MIXED, 20>);
   int64_t launched = 0;
   int chunk_id = 0;
   bool finished = false;
@@ -984,7 +1471,6 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
     if (e != IFL_OK) return e;
   }
   hipEvent_t* done_ev = d->done_ev;
-  ifl_status result = IFL_OK;
   while (!finished) {
     const int slot = chunk_id & 1;
     // profiling samples one launch per chunk (bracketing every launch with
@@ -1021,7 +1507,7 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
         d->prof_launches += 1;
         d->prof_bytes += spmv_bytes(M, sizeof(T));
         d->prof_kernel = std::string("k_cg<") + (MIXED ? "float, true, " : "double, false, ") +
-                         std::to_string(M.head <= 6 ? 6 : (M.head <= 12 ? 12 : 20)) + ">";
+                         std::to_string(head <= 6 ? 6 : (head <= 12 ? 12 : 20)) + ">";
       }
       if (sh.done) finished = true;
     }
@@ -1029,6 +1515,28 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
     pending = chunk_id;
     ++chunk_id;
   }
+  IFL_HIP(hipMemcpyAsync(&w.sc_host[0], cs.sc + (launched & 1), sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  IFL_HIP(hipStreamSynchronize(s));
+  res->last = w.sc_host[0];
+  res->launched = launched;
+  res->secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return IFL_OK;
+}
+
+template <typename T, bool MIXED>
+ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* out_dev, double* energy,
+                        const ColScratch& cs) {
+  DeviceState* d = h->dev;
+  ColWork& w = d->w;
+  const DevMatrix& M = d->m;
+  hipStream_t s = stream_of(h);
+  const Mat m = mat_view(M);
+  const int G = d->G, spb = d->spb;
+  const double c = h->opt.gamma / std::pow(k, 2.0 * h->op.order);
+  ColRun run;
+  ifl_status st = run_column<T, MIXED>(h, m, M.head, c, cs, true, &run);
+  if (st != IFL_OK) return st;
+  const int64_t launched = run.launched;
   // finish: x to caller numbering, true residual, energy (from the final
   // state copy; a solve cut off by the launch cap uses the last x written)
   Scalars* fin = cs.sc + (launched & 1);
@@ -1039,7 +1547,6 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
   IFL_HIP(hipMemcpyAsync(&w.sc_host[0], fin, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   IFL_HIP(hipStreamSynchronize(s));
   const Scalars& sh = w.sc_host[0];
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   const double rel = sh.bb > 0 ? std::sqrt(sh.res2 / sh.bb) : std::sqrt(sh.res2);
   const bool ok = sh.done == 1;
   if (st_out) {
@@ -1048,13 +1555,182 @@ ifl_status solve_column(Handle* h, double k, ifl_solve_stats* st_out, double* ou
     st_out->status = ok ? IFL_OK : IFL_ENOTCONV;
     st_out->reserved = 0;
     st_out->rel_residual = rel;
-    st_out->seconds = secs;
+    st_out->seconds = run.secs;
     st_out->energy = 0.5 * sh.energy2 / M.mass_sum;
   }
   if (energy) *energy = 0.5 * sh.energy2 / M.mass_sum;
-  if (!ok) result = fail(IFL_ENOTCONV, sh.done == 2 ? "CG breakdown ((p, Sp) <= 0 or non-finite)"
-                                                       : "CG reached max_iter before the tolerance");
-  return result;
+  if (!ok)
+    return fail(IFL_ENOTCONV, sh.done == 2 ? "CG breakdown ((p, Sp) <= 0 or non-finite)"
+                                           : "CG reached max_iter before the tolerance");
+  return IFL_OK;
+}
+
+// The shifted solves' work space, made on first use.
+ifl_status ensure_shift_work(DeviceState* d) {
+  ShiftWork& sw = d->sw;
+  if (sw.acc) return IFL_OK;
+  const size_t np = (size_t)d->m.n_pad;
+  ifl_status st;
+  for (double** v : {&sw.x[0], &sw.x[1], &sw.z64[0], &sw.z64[1], &sw.u64[0], &sw.u64[1], &sw.p64[0], &sw.p64[1],
+                     &sw.d64})
+    if ((st = dalloc(v, 2 * np))) return st;
+  for (float** v : {&sw.z32[0], &sw.z32[1], &sw.u32[0], &sw.u32[1], &sw.p32[0], &sw.p32[1], &sw.d32})
+    if ((st = dalloc(v, 2 * np))) return st;
+  if ((st = dalloc(&sw.part, (size_t)CP_COUNT * d->G)) || (st = dalloc(&sw.sc, 2)) || (st = dalloc(&sw.acc, np)))
+    return st;
+  IFL_HIP(hipHostMalloc((void**)&sw.sc_host, 2 * sizeof(CScalars), hipHostMallocDefault));
+  IFL_HIP(hipMemset(sw.part, 0, sizeof(double) * CP_COUNT * d->G));
+  IFL_HIP(hipMemset(sw.sc, 0, 2 * sizeof(CScalars)));
+  IFL_HIP(hipDeviceSynchronize());
+  return IFL_OK;
+}
+
+template <typename T, bool MIXED, int U>
+void launch_ccg(const Mat& m, const CVecs<T>& v, const double* phi, double* part, CScalars* sc, int launch, int G,
+                int spb, int max_iter, hipStream_t s) {
+  k_ccg<T, MIXED, U><<<G, kBlock, 0, s>>>(m, v, phi, part, sc, launch, G, spb, max_iter);
+}
+
+// Jacobi-COCG on (M + sigma K) y = M phi (w.phi) from y0 = phi, K the
+// first-order operator; the solution is left in sw.x[buffer of the final
+// state].
+template <typename T, bool MIXED>
+ifl_status run_ccolumn(Handle* h, const Mat& m, int head, double sr, double si, CScalars* last, int64_t* launched_out) {
+  DeviceState* d = h->dev;
+  ColWork& w = d->w;
+  ShiftWork& sw = d->sw;
+  hipStream_t s = stream_of(h);
+  CVecs<T> v;
+  if constexpr (MIXED) {
+    v = CVecs<T>{{sw.z32[0], sw.z32[1]}, {sw.u32[0], sw.u32[1]}, {sw.p32[0], sw.p32[1]}, sw.d32, {sw.x[0], sw.x[1]}};
+  } else {
+    v = CVecs<T>{{sw.z64[0], sw.z64[1]}, {sw.u64[0], sw.u64[1]}, {sw.p64[0], sw.p64[1]}, sw.d64, {sw.x[0], sw.x[1]}};
+  }
+  const int G = d->G, spb = d->spb;
+  k_cinit<T><<<G, kBlock, 0, s>>>(m, v, w.phi, sw.part, sw.sc, sr, si, G, spb);
+  k_csetup<<<1, kBlock, 0, s>>>(sw.part, sw.sc, h->opt.rtol, G);
+  IFL_HIP(hipGetLastError());
+  const int chunk = 8;
+  const int max_iter = h->opt.max_iter;
+  const int64_t max_launch = 2 * (int64_t)max_iter + 16;
+  void (*cg)(const Mat&, const CVecs<T>&, const double*, double*, CScalars*, int, int, int, int, hipStream_t) =
+      head <= 6 ? launch_ccg<T, MIXED, 6> : (head <= 12 ? launch_ccg<T, MIXED, 12> : launch_ccg<T, MIXED, 20>);
+  int64_t launched = 0;
+  int chunk_id = 0, pending = -1;
+  bool finished = false;
+  hipEvent_t* done_ev = d->done_ev;
+  while (!finished) {
+    const int slot = chunk_id & 1;
+    for (int j = 0; j < chunk && launched < max_launch; ++j) {
+      cg(m, v, w.phi, sw.part, sw.sc, (int)launched, G, spb, max_iter, s);
+      ++launched;
+    }
+    IFL_HIP(hipGetLastError());
+    IFL_HIP(hipMemcpyAsync(&sw.sc_host[slot], sw.sc + (launched & 1), sizeof(CScalars), hipMemcpyDeviceToHost, s));
+    IFL_HIP(hipEventRecord(done_ev[slot], s));
+    const bool capped = launched >= max_launch;
+    const int wait_chunk = capped ? chunk_id : pending;
+    if (wait_chunk >= 0) {
+      IFL_HIP(hipEventSynchronize(done_ev[wait_chunk & 1]));
+      if (sw.sc_host[wait_chunk & 1].done) finished = true;
+    }
+    if (capped) finished = true;
+    pending = chunk_id;
+    ++chunk_id;
+  }
+  IFL_HIP(hipMemcpyAsync(&sw.sc_host[0], sw.sc + (launched & 1), sizeof(CScalars), hipMemcpyDeviceToHost, s));
+  IFL_HIP(hipStreamSynchronize(s));
+  *last = sw.sc_host[0];
+  *launched_out = launched;
+  return IFL_OK;
+}
+
+// S^-1 M phi for an order n >= 2 through first-order systems only (the
+// partial fractions of 1 / (1 + y^n), y the eigenvalues of c^(1/n) M^-1 K):
+// x = (1/n) sum_j (M + s_j b K)^-1 M phi, b = c^(1/n), s_j = -1 / w_j over
+// the roots of w^n = -1. A real shift (s = 1, odd n) is solved by the real
+// CG on K, each conjugate pair of complex shifts by one COCG solve whose
+// real part counts twice. Every shifted solve stops on its own FP64 true
+// residual; the stats report the FP64 true residual of S itself.
+template <typename T, bool MIXED>
+ifl_status solve_shifted(Handle* h, double k, ifl_solve_stats* st_out, double* out_dev, double* energy) {
+  DeviceState* d = h->dev;
+  ColWork& w = d->w;
+  const DevMatrix& M = d->m;
+  const DevK1& K1 = d->k1;
+  hipStream_t s = stream_of(h);
+  if (!K1.sptr) return fail(IFL_EINVAL, "handle has no first-order operator (order 1, or an old saved file)");
+  ifl_status st = ensure_shift_work(d);
+  if (st != IFL_OK) return st;
+  const int n = h->op.order;
+  const int G = d->G, spb = d->spb;
+  const double c = h->opt.gamma / std::pow(k, 2.0 * n);
+  const double b = std::pow(c, 1.0 / n);
+  const Mat m1{M.n, M.n_slices, K1.sptr, K1.col, K1.val64, K1.val32, K1.kdiag64, K1.kdiag32, M.mass64};
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t nz = M.n_pad;
+  k_fill_zero<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(d->sw.acc, nz);
+  int iters = 0, updates = 0;
+  int bad = 0;  // 0 ok, else the done code of a failed shifted solve
+  const double pi = 3.14159265358979323846;
+  for (int j = 0; j < n; ++j) {
+    // s_j = -1 / w_j, w_j = exp(i pi (2j + 1) / n); the conjugate of
+    // s_{n-1-j}: solve the shifts with Im s >= 0 (j >= n/2 ... by symmetry)
+    const double th = pi * (2 * j + 1) / n;
+    const double sr = -std::cos(th), si = std::sin(th);  // -1/w = -conj(w) for |w| = 1
+    if (si < -1e-12) continue;
+    if (std::fabs(si) <= 1e-12) {
+      ColRun run;
+      const ColScratch cs{w.part, w.sc, false, false};
+      if ((st = run_column<T, MIXED>(h, m1, K1.head, sr * b, cs, false, &run)) != IFL_OK) return st;
+      iters += run.last.iters;
+      updates += run.last.updates;
+      if (run.last.done != 1) bad = run.last.done ? run.last.done : 3;
+      const int xb = run.last.done ? run.last.xbuf : (int)(run.launched & 1);
+      k_accumulate<<<(unsigned)((M.n + 255) / 256), 256, 0, s>>>(d->sw.acc, w.x[xb], 1, 1.0 / n, M.n);
+    } else {
+      CScalars last;
+      int64_t launched = 0;
+      if ((st = run_ccolumn<T, MIXED>(h, m1, K1.head, sr * b, si * b, &last, &launched)) != IFL_OK) return st;
+      iters += last.iters;
+      updates += last.updates;
+      if (last.done != 1) bad = last.done ? last.done : 3;
+      const int xb = last.done ? last.xbuf : (int)(launched & 1);
+      k_accumulate<<<(unsigned)((M.n + 255) / 256), 256, 0, s>>>(d->sw.acc, d->sw.x[xb], 2, 2.0 / n, M.n);
+    }
+    IFL_HIP(hipGetLastError());
+  }
+  // the summed solution to the caller, the true residual of S itself
+  const Mat mn = mat_view(M);
+  k_sfinish<<<G, kBlock, 0, s>>>(mn, d->sw.acc, w.phi, c, M.entity, out_dev, d->sw.part, G, spb);
+  IFL_HIP(hipGetLastError());
+  // the finish sums and ||M phi||^2 of the complex starts (every order >= 2
+  // has a complex shift; all shifts share the right-hand side), summed on
+  // the host in a fixed order
+  std::vector<double> part(4 * (size_t)G);
+  IFL_HIP(hipMemcpyAsync(part.data(), d->sw.part + (size_t)CP_BB * G, sizeof(double) * 3 * G,
+                         hipMemcpyDeviceToHost, s));
+  IFL_HIP(hipStreamSynchronize(s));
+  static_assert(CP_RES == CP_BB + 1 && CP_EN == CP_BB + 2, "finish sums follow ||M phi||^2");
+  double bb = 0.0, res2 = 0.0, en = 0.0;
+  for (int i = 0; i < G; ++i) bb += part[i];
+  for (int i = 0; i < G; ++i) res2 += part[G + i];
+  for (int i = 0; i < G; ++i) en += part[2 * G + i];
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st_out) {
+    st_out->iterations = iters;
+    st_out->refinements = updates;
+    st_out->status = bad ? IFL_ENOTCONV : IFL_OK;
+    st_out->reserved = 0;
+    st_out->rel_residual = bb > 0 ? std::sqrt(res2 / bb) : std::sqrt(res2);
+    st_out->seconds = secs;
+    st_out->energy = 0.5 * en / M.mass_sum;
+  }
+  if (energy) *energy = 0.5 * en / M.mass_sum;
+  if (bad)
+    return fail(IFL_ENOTCONV, bad == 2 ? "shifted CG breakdown ((p, A p) = 0 or non-finite)"
+                                       : "a shifted solve reached max_iter before the tolerance");
+  return IFL_OK;
 }
 
 }  // namespace
@@ -1085,7 +1761,10 @@ ifl_status filter_single(Handle* h, int32_t n_fields, const double* fields, int3
       }
       ifl_solve_stats* so = stats ? &stats[(int64_t)f * n_scales + j] : nullptr;
       double* eo = energy ? &energy[(int64_t)f * n_scales + j] : nullptr;
-      if (h->opt.precision == IFL_MIXED) st = solve_column<float, true>(h, k[j], so, dst, eo, cs);
+      const bool shifted = h->opt.solver == IFL_SOLVER_SHIFTED && h->op.order >= 2 && cs.allow_shifted;
+      if (shifted && h->opt.precision == IFL_MIXED) st = solve_shifted<float, true>(h, k[j], so, dst, eo);
+      else if (shifted) st = solve_shifted<double, false>(h, k[j], so, dst, eo);
+      else if (h->opt.precision == IFL_MIXED) st = solve_column<float, true>(h, k[j], so, dst, eo, cs);
       else st = solve_column<double, false>(h, k[j], so, dst, eo, cs);
       if (st == IFL_ENOTCONV) agg = st;
       else if (st != IFL_OK) return st;
@@ -1396,8 +2075,10 @@ ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int3
                          double* out, ifl_solve_stats* stats, double* energy) {
   DeviceState* d = h->dev;
   IFL_HIP(hipSetDevice(d->device));
-  const int R = pick_tile(h, (int64_t)n_fields * n_scales);
-  if (R <= 1) return filter_single(h, n_fields, fields, n_scales, k, out, stats, energy, ColScratch{d->w.part, d->w.sc, true});
+  // the shifted first-order solves run one column at a time
+  const bool shifted = h->opt.solver == IFL_SOLVER_SHIFTED && h->op.order >= 2;
+  const int R = shifted ? 1 : pick_tile(h, (int64_t)n_fields * n_scales);
+  if (R <= 1) return filter_single(h, n_fields, fields, n_scales, k, out, stats, energy, ColScratch{d->w.part, d->w.sc, true, true});
   return filter_batched(h, R, n_fields, fields, n_scales, k, out, stats, energy);
 }
 
@@ -1461,12 +2142,6 @@ ifl_status device_stream_probe(int device, int64_t bytes, int reps, double* best
   return IFL_OK;
 }
 
-// Zero n doubles (the start of a no-allocation call: a fill kernel rather
-// than a memset node, so the call can also be captured)
-__global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
-}
 
 ifl_status device_filter_noalloc(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales,
                                  const double* k, double* out, ifl_solve_stats* stats) {
@@ -1481,8 +2156,9 @@ ifl_status device_filter_noalloc(Handle* h, int32_t n_fields, const double* fiel
                                 std::to_string(kNoallocScalarsOffset));
   unsigned char* base = static_cast<unsigned char*>(noalloc_scratch_addr(d->device));
   if (!base) return fail(IFL_EDEVICE, "no-allocation work space not set up on this device");
+  // the plain path only: the shifted solves allocate their work space
   const ColScratch cs{reinterpret_cast<double*>(base), reinterpret_cast<Scalars*>(base + kNoallocScalarsOffset),
-                      false};
+                      false, false};
   hipStream_t s = stream_of(h);
   const int64_t nz = (int64_t)(kNoallocScratchBytes / sizeof(double));
   k_fill_zero<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(cs.part, nz);

@@ -27,6 +27,11 @@ struct HostOperator {
   std::vector<int32_t> col;        // nnz
   std::vector<double> val;         // nnz
   std::vector<double> mass;        // n
+  // order >= 2: the first-order operator K (same rows and layout), for the
+  // solves of S = M + c K_n as shifted first-order systems
+  std::vector<int64_t> k1_row_ptr;
+  std::vector<int32_t> k1_col;
+  std::vector<double> k1_val;
   int32_t n_components = 1;        // 1 (scalar) or 2 (vector)
   uint64_t mesh_hash = 0;
   // IFL_VERTEX_VECTOR only: the cell -> vertex projection R_vc u_c / M_v.
@@ -60,6 +65,8 @@ struct SellPack {
 };
 
 void pack_sell(const HostOperator& op, SellPack* out);
+void pack_sell_csr(int64_t n, const std::vector<int64_t>& row_ptr, const std::vector<int32_t>& col,
+                   const std::vector<double>& val, const std::vector<double>& mass, SellPack* out);
 
 // Zero entries appended after the last slice (32 entries x 64 lanes): a
 // kernel may load up to 32 entries past the end of any slice's rows without

@@ -471,6 +471,7 @@ ifl_status build_vertex_scalar(const ifl_mesh& m, int32_t order, int32_t reorder
   out->n_components = 1;
   out->field_len = m.n_vertices;
   permute_csr(n, ord, np, nc, nv, out->row_ptr, out->col, out->val);
+  if (order >= 2) permute_csr(n, ord, kp, kc, kv, out->k1_row_ptr, out->k1_col, out->k1_val);
   out->mass.resize(n);
   out->entity.resize(n);
   for (int64_t i = 0; i < n; ++i) {
@@ -602,6 +603,7 @@ ifl_status build_vertex_vector(const ifl_mesh& m, int32_t order, int32_t reorder
   out->n_components = 2;
   out->field_len = 2 * m.n_vertices;
   permute_csr(n, ord, np, ncol, nv, out->row_ptr, out->col, out->val);
+  if (order >= 2) permute_csr(n, ord, kp, kc, kv, out->k1_row_ptr, out->k1_col, out->k1_val);
   out->mass.resize(n);
   out->entity.resize(n);
   for (int64_t i = 0; i < n; ++i) {
@@ -743,6 +745,7 @@ ifl_status build_circumcenter_scalar(const ifl_mesh& m, int32_t order, int32_t r
   out->n_components = 1;
   out->field_len = m.n_triangles;
   permute_csr(n, ord, np, ncol, nv, out->row_ptr, out->col, out->val);
+  if (order >= 2) permute_csr(n, ord, kp, kc, kv, out->k1_row_ptr, out->k1_col, out->k1_val);
   out->mass.resize(n);
   out->entity.resize(n);
   for (int64_t i = 0; i < n; ++i) {
@@ -872,6 +875,7 @@ ifl_status build_cell_vector(const ifl_mesh& m, int32_t order, double A, int32_t
   out->n_components = 2;
   out->field_len = 2 * m.n_triangles;
   permute_csr(n, ord, np, ncol, nv, out->row_ptr, out->col, out->val);
+  if (order >= 2) permute_csr(n, ord, kp, kc, kv, out->k1_row_ptr, out->k1_col, out->k1_val);
   out->mass.resize(n);
   out->entity.resize(n);
   for (int64_t i = 0; i < n; ++i) {
@@ -913,8 +917,8 @@ ifl_status build_operator(const ifl_mesh& mesh, int32_t placement, int32_t order
   return IFL_OK;
 }
 
-void pack_sell(const HostOperator& op, SellPack* out) {
-  const int64_t n = op.n;
+void pack_sell_csr(int64_t n, const std::vector<int64_t>& row_ptr, const std::vector<int32_t>& col,
+                   const std::vector<double>& val, const std::vector<double>& mass, SellPack* out) {
   const int64_t ns = (n + 63) / 64;
   out->n = n;
   out->n_slices = ns;
@@ -928,7 +932,7 @@ void pack_sell(const HostOperator& op, SellPack* out) {
     int32_t w = 0;
     for (int64_t r = s * 64; r < std::min(n, s * 64 + 64); ++r) {
       int32_t len = 0;
-      for (int64_t e = op.row_ptr[r]; e < op.row_ptr[r + 1]; ++e) len += (op.col[e] != r);
+      for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) len += (col[e] != r);
       w = std::max(w, len);
       out->stored_offdiag += len;
     }
@@ -946,13 +950,13 @@ void pack_sell(const HostOperator& op, SellPack* out) {
       const int32_t self = (int32_t)std::min(r, n - 1);
       int32_t k = 0;
       if (r < n) {
-        out->mass[r] = op.mass[r];
-        for (int64_t e = op.row_ptr[r]; e < op.row_ptr[r + 1]; ++e) {
-          if (op.col[e] == r) {
-            out->diag[r] = op.val[e];
+        out->mass[r] = mass[r];
+        for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+          if (col[e] == r) {
+            out->diag[r] = val[e];
           } else {
-            out->col[out->slice_ptr[s] + 64 * k + l] = op.col[e];
-            out->val[out->slice_ptr[s] + 64 * k + l] = op.val[e];
+            out->col[out->slice_ptr[s] + 64 * k + l] = col[e];
+            out->val[out->slice_ptr[s] + 64 * k + l] = val[e];
             ++k;
           }
         }
@@ -964,5 +968,7 @@ void pack_sell(const HostOperator& op, SellPack* out) {
     }
   }
 }
+
+void pack_sell(const HostOperator& op, SellPack* out) { pack_sell_csr(op.n, op.row_ptr, op.col, op.val, op.mass, out); }
 
 }  // namespace ifl

@@ -75,6 +75,9 @@ struct Worker {
   bool dead = false;
   ifl_status exit_status = IFL_OK;
   std::string exit_msg;
+  // set by ifl_server_cancel: the worker fails its admitted columns that
+  // have not entered a slot at the top of its next loop
+  std::atomic<bool> cancel{false};
 };
 
 }  // namespace
@@ -153,6 +156,24 @@ ifl_status run_worker(Worker* wk) {
   const int chunk = 4;
   int active = 0;
   for (;;) {
+    // 0. cancellation: admitted columns still waiting for a slot end here
+    if (wk->cancel.exchange(false)) {
+      for (const Column& c : wk->pending) {
+        ifl_ticket* t = c.t;
+        t->stats[c.scale].status = IFL_ECANCELED;
+        if (--t->remaining == 0) {
+          release_ticket(wk, t);
+          finish_ticket(t, IFL_ECANCELED, "request cancelled by ifl_server_cancel");
+        } else {
+          std::lock_guard<std::mutex> lk(t->mu);
+          if (t->status == IFL_OK) {
+            t->status = IFL_ECANCELED;
+            t->error = "request cancelled by ifl_server_cancel";
+          }
+        }
+      }
+      wk->pending.clear();
+    }
     // 1. admit and stage new requests
     std::vector<ifl_ticket*> adm;
     admit(wk, &adm);
@@ -246,10 +267,14 @@ ifl_status run_worker(Worker* wk) {
       wk->slot[j] = Column{nullptr, 0};
       --active;
       if (--t->remaining == 0) {
-        bool all_ok = true;
-        for (const auto& x : t->stats) all_ok &= x.status == IFL_OK;
+        bool all_ok = true, cancelled = false;
+        for (const auto& x : t->stats) {
+          all_ok &= x.status == IFL_OK;
+          cancelled |= x.status == IFL_ECANCELED;
+        }
         release_ticket(wk, t);
-        finish_ticket(t, all_ok ? IFL_OK : IFL_ENOTCONV, all_ok ? "" : "a column did not converge");
+        if (cancelled) finish_ticket(t, IFL_ECANCELED, "request cancelled by ifl_server_cancel");
+        else finish_ticket(t, all_ok ? IFL_OK : IFL_ENOTCONV, all_ok ? "" : "a column did not converge");
       }
     }
     if ((st = batch_release(wk->w, fin, wk->stream)) != IFL_OK) return st;
@@ -390,6 +415,21 @@ ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field, int32
   }
   s->cv.notify_all();
   *ticket = t;
+  return IFL_OK;
+}
+
+ifl_status ifl_server_cancel(ifl_server* s) {
+  if (!s) return fail(IFL_EINVAL, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto& wk : s->workers) {
+      for (ifl_ticket* t : wk->queue) finish_ticket(t, IFL_ECANCELED, "request cancelled by ifl_server_cancel");
+      s->completed += (int64_t)wk->queue.size();
+      wk->queue.clear();
+      wk->cancel.store(true);
+    }
+  }
+  s->cv.notify_all();
   return IFL_OK;
 }
 

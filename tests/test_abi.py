@@ -353,3 +353,40 @@ def test_save_load_roundtrip(tmp_path, placement):
     assert e.value.status == ifl.IFL_EIO
     h.close()
     h2.close()
+
+
+@pytest.mark.parametrize("placement", ["vertex", "voronoi", "circumcenter", "cell_vector", "vertex_vector"])
+def test_first_order_operator_kept_for_shifted_solves(placement, tmp_path):
+    """A handle of order n >= 2 keeps the first-order operator K (the
+    matrix of the shifted first-order systems) in the same rows as K_n: it
+    equals the oracle's K, and it survives save / load."""
+    _lib_or_skip()
+    s = W.icosphere(3, jitter=0.1)
+    wet = np.array(W.land_mask(s, 0.3), dtype=np.uint8)
+    if placement == "vertex_vector":
+        wet[np.abs(s.coords[:, 2] / s.radius) > np.sin(np.radians(80))] = 0
+    s = s.with_mask(wet)
+    pl, op = {"vertex": (ifl.IFL_VERTEX_SCALAR, lambda: O.scalar_operator(s, 2)),
+              "voronoi": (ifl.IFL_VORONOI_SCALAR, lambda: O.voronoi_operator(s, 2)),
+              "circumcenter": (ifl.IFL_CIRCUMCENTER_SCALAR, lambda: O.circumcenter_operator(s, 2)),
+              "cell_vector": (ifl.IFL_CELL_VECTOR, lambda: O.vector_operator(s, 2)),
+              "vertex_vector": (ifl.IFL_VERTEX_VECTOR, lambda: O.vertex_vector_operator(s, 2))}[placement]
+    op = op()
+    h = _host_handle(s, pl, 2)
+
+    class _K1:  # the library's K in place of K_n for the renumbering helper
+        pass
+
+    rp, col, val = h.export_first_order()
+    _, _, _, mass, ent = h.export_operator()
+    view = _K1()
+    view.export_operator = lambda: (rp, col, val, mass, ent)
+    K, *_ = _to_oracle_numbering(view, op)
+    assert abs(K - op.K).max() <= 1e-13 * abs(op.K).max()
+    path = str(tmp_path / "h.ifl")
+    h.save(path)
+    h2 = ifl.ifl_load(path, device=-1)
+    for a, b in zip(h2.export_first_order(), (rp, col, val)):
+        assert np.array_equal(a, b)
+    h.close()
+    h2.close()

@@ -250,3 +250,31 @@ def test_spectrum_only_requests(ifl):
         assert np.max(np.abs(e_ref - e_full) / e_ref) < 2e-9, (e_ref, e_full)
     srv.close()
     h.close()
+
+
+def test_server_cancel(ifl):
+    """ifl_server_cancel ends the requests that wait for admission or for a
+    slot with IFL_ECANCELED; requests with columns in slots finish them;
+    the memory of every request is released; the server takes new requests
+    afterwards, and their results equal those of an undisturbed server."""
+    s = W.icosphere(5, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    h = ifl.prepare_mesh(s, 0, 2, precision=ifl.IFL_MIXED)
+    f = W.sphere_k3_field(s, 901, n_waves=64)
+    ks = W.log_scales(s.h, 8)
+    srv = ifl.Server(4 << 30, slots=2)
+    mid = srv.add(h)
+    ref_t, _ = srv.submit(mid, f, ks)
+    st, _, ref, _ = srv.wait(ref_t, len(ks))
+    assert st == 0
+    tl = [srv.submit(mid, f * (i + 1), ks) for i in range(12)]
+    srv.cancel()
+    codes = [srv.wait(t, len(ks))[0] for t, _ in tl]
+    assert set(codes) <= {0, ifl.IFL_ECANCELED} and codes.count(ifl.IFL_ECANCELED) >= 8, codes
+    q = srv.query()
+    assert q["used"] == 0 and q["in_flight"] == 0 and q["queued"] == 0, q
+    t, _ = srv.submit(mid, f, ks)
+    st, _, o, _ = srv.wait(t, len(ks))
+    assert st == 0 and np.array_equal(o, ref)
+    srv.close()
+    h.close()
