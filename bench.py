@@ -492,10 +492,12 @@ def serve_leg(args, ifl):
     if cmp_reqs:
         solves = sum(ks.size for (_, _, ks) in cmp_reqs)
         t = time.perf_counter()
-        for (i, f, ks) in cmp_reqs:
+        for r, (i, f, ks) in enumerate(cmp_reqs):
             h = handles[i]
             h.set_options(precision=ifl.IFL_FP64, batch=1)
             h.filter(pools[i][f], ks)
+            log(f"like-for-like: plain FP64 request {r + 1}/{len(cmp_reqs)} (L{meshes[i][0]} n={meshes[i][1]}, "
+                f"{ks.size} scales) done at {time.perf_counter() - t:.1f}s")
         plain_s = time.perf_counter() - t
         for h in handles:
             h.set_options(precision=ifl.IFL_MIXED, batch=0)
