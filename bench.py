@@ -180,6 +180,39 @@ def spmv_leg(ifl):
     return res
 
 
+def spmv10_leg(ifl):
+    """Out-of-cache cross-check of the single-column iteration rates: the
+    unmasked level-10 icosphere (10,485,762 vertices, all dofs), n = 1, FP64
+    and FP32, two scales (wavelengths 16h, 8h). Algorithmic bytes per
+    launch (1.5 GB FP64) are ~6x the 256 MB Infinity Cache, so the rate is
+    an HBM rate."""
+    import torch
+
+    import workloads as W
+
+    s = W.icosphere(10, jitter=0.1, seed=1)
+    phi = torch.from_numpy(np.asarray(W.sphere_k3_field(s, 1000, n_waves=256, device="cuda:0"))).to("cuda:0")
+    ks = np.array([2 * math.pi / (16 * s.h), 2 * math.pi / (8 * s.h)])
+    t0 = time.time()
+    h = ifl.prepare_mesh(s, ifl.IFL_VERTEX_SCALAR, 1, precision=ifl.IFL_FP64, batch=1, device=0, profile=1)
+    res = {"vertices": s.n_vertices, "dofs": h.num_dofs, "prepare_s": round(time.time() - t0, 1),
+           "scales": "wavelengths [16, 8] h"}
+    dst = torch.empty((1, 2, h.field_length), dtype=torch.float64, device="cuda:0")
+    for prec, name in ((ifl.IFL_FP64, "fp64_single_column"), (ifl.IFL_MIXED, "fp32_single_column")):
+        h.set_options(precision=prec, batch=1, profile=1)
+        h.filter(phi, ks[:1], out=dst[:, :1])
+        h.profile_read(reset=True)
+        _, st = h.filter(phi, ks, out=dst)
+        n_l, ms, b = h.profile_read(reset=True)
+        us = ms / max(n_l, 1) * 1e3
+        res[name] = {"kernel": h.profile_kernel(), "mean_launch_us": round(us, 2), "bytes_per_launch": round(b),
+                     "GBs": round(b / (us * 1e3), 1) if n_l else None,
+                     "frac_of_hbm_peak": round(b / (us * 1e3) / HBM_PEAK_GBS, 4) if n_l else None,
+                     "launches": n_l, "mean_cg_iterations": round(sum(x.iterations for x in st) / len(st), 1)}
+    h.close()
+    return res
+
+
 def vector_leg(ifl):
     """Velocity filtering on the level-8 sphere (655,362 vertices,
     1,310,720 triangles; 30% land and dry polar caps, where lon/lat
@@ -362,8 +395,9 @@ def serve_leg(args, ifl):
         pool = [np.asarray(W.sphere_k3_field(s, 3000 + 10 * L + i, n_waves=256, device="cuda:0"))
                 for i in range(4)]
         for n in (1, 2):
+            solver = ifl.IFL_SOLVER_SHIFTED if (n == 2 and args.serve_n2_solver == "shifted") else ifl.IFL_SOLVER_KN
             handles.append(ifl.prepare_mesh(s, ifl.IFL_VERTEX_SCALAR, n, precision=ifl.IFL_MIXED, device=0,
-                                            graphs=0 if args.no_graphs else 1))
+                                            graphs=0 if args.no_graphs else 1, solver=solver))
             meshes.append((L, n, s.h))
             pools.append(pool)
         log(f"serving: level {L} prepared ({time.time() - t0:.1f}s)")
@@ -469,7 +503,9 @@ def serve_leg(args, ifl):
         }
 
     res = {"workload": f"icosphere levels {args.serve_levels} (30% land mask) x n in {{1,2}}, "
-                       f"{args.serve_slots} slots per mesh, mixed precision, 1-32 log-uniform scales per request",
+                       f"{args.serve_slots} slots per mesh, mixed precision, 1-32 log-uniform scales per request; "
+                       + ("n = 2 requests by the shifted first-order solves, one column at a time"
+                          if args.serve_n2_solver == "shifted" else "n = 2 requests by Jacobi-PCG on K_2 in tiles"),
            "prepare_s": round(prep_s, 1), "budget_bytes": int(args.serve_budget_gib * (1 << 30))}
     res["stream"] = stream(args.serve_rate, draw(args.serve_warmup + args.serve_requests), args.serve_warmup, True,
                            drain_s=args.serve_drain_s)
@@ -494,13 +530,15 @@ def serve_leg(args, ifl):
         t = time.perf_counter()
         for r, (i, f, ks) in enumerate(cmp_reqs):
             h = handles[i]
-            h.set_options(precision=ifl.IFL_FP64, batch=1)
+            h.set_options(precision=ifl.IFL_FP64, batch=1, solver=ifl.IFL_SOLVER_KN)
             h.filter(pools[i][f], ks)
             log(f"like-for-like: plain FP64 request {r + 1}/{len(cmp_reqs)} (L{meshes[i][0]} n={meshes[i][1]}, "
                 f"{ks.size} scales) done at {time.perf_counter() - t:.1f}s")
         plain_s = time.perf_counter() - t
-        for h in handles:
-            h.set_options(precision=ifl.IFL_MIXED, batch=0)
+        for h, (L, n, _) in zip(handles, meshes):
+            h.set_options(precision=ifl.IFL_MIXED, batch=0,
+                          solver=ifl.IFL_SOLVER_SHIFTED if (n == 2 and args.serve_n2_solver == "shifted")
+                          else ifl.IFL_SOLVER_KN)
         res["like_for_like"] = {"requests": len(cmp_reqs), "solves": int(solves),
                                 "served_mixed_solves_per_s": round(solves / served_s, 2),
                                 "plain_fp64_single_column_solves_per_s": round(solves / plain_s, 2),
@@ -528,7 +566,7 @@ def serve_leg(args, ifl):
                         "GBs": round(b / (us * 1e3), 1) if n_l else None,
                         "frac_of_hbm_peak": round(b / (us * 1e3) / HBM_PEAK_GBS, 4) if n_l else None,
                         "launches": n_l}
-        h.set_options(precision=ifl.IFL_MIXED, batch=0, profile=0)
+        h.set_options(precision=ifl.IFL_MIXED, batch=0, profile=0, solver=ifl.IFL_SOLVER_KN)
         res["spmv_level10"] = sp
         log(f"level-10 SpMV: {sp}")
     for h in handles:
@@ -604,7 +642,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-spmv-leg", action="store_true", help="skip the SpMV rates on the unmasked level-9 mesh")
     ap.add_argument("--no-vector-leg", action="store_true", help="skip the velocity filtering on the level-8 mesh")
-    ap.add_argument("--leg", choices=["velocity", "spmv", "c1", "c2", "serve"], default=None,
+    ap.add_argument("--leg", choices=["velocity", "spmv", "spmv10", "c1", "c2", "serve"], default=None,
                     help="run only this leg and print its JSON (for profiling one leg on its own)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured chunks")
@@ -615,6 +653,9 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200, help="requests of the stream before the measured ones")
     ap.add_argument("--serve-slots", type=int, default=8, help="column slots per resident mesh")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="device memory budget of the server")
+    ap.add_argument("--serve-n2-solver", choices=["shifted", "kn"], default="shifted",
+                    help="how the served n = 2 requests are solved: the shifted first-order solves (one column at "
+                         "a time) or Jacobi-PCG on K_2 in tiles")
     ap.add_argument("--serve-drain-s", type=float, default=20.0,
                     help="the stated stream's window: requests not finished this long after the last arrival "
                          "are cancelled and counted as such (their latency exceeds the window)")
@@ -642,15 +683,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
-    if args.leg is not None:
-        fn = {"velocity": vector_leg, "spmv": spmv_leg, "c1": c1_leg, "c2": c2_leg,
-              "serve": lambda m: serve_leg(args, m)}[args.leg]
-        print(json.dumps({"leg": args.leg, **fn(ifl)}), flush=True)
-        return
     if args.copy_probe_mib > 0:
         # two dispatches of the library's copy kernel (k_stream_copy) of known size
         ifl.stream_probe(0, args.copy_probe_mib, 1)
         log(f"copy probe: 2 x {args.copy_probe_mib} MiB device copies (k_stream_copy)")
+    if args.leg is not None:
+        fn = {"velocity": vector_leg, "spmv": spmv_leg, "spmv10": spmv10_leg, "c1": c1_leg, "c2": c2_leg,
+              "serve": lambda m: serve_leg(args, m)}[args.leg]
+        print(json.dumps({"leg": args.leg, **fn(ifl)}), flush=True)
+        return
     mesh, fields_h, ks = make_workload(args.level, args.mask, args.fields, args.scales, dev)
     precision = ifl.IFL_MIXED if args.precision == "mixed" else ifl.IFL_FP64
     t0 = time.time()
@@ -765,7 +806,7 @@ def main():
     torch.cuda.synchronize()
     h.close()
     # the practical streaming rate of this GPU: the library's own copy probe
-    # (4 GiB, 16 bytes per thread, every resident workgroup), best of 10
+    # (4 GiB, 16 bytes per thread, one pass), best of 10
     best, med = ifl.stream_probe(0, 4096, 10)
     res["roofline"]["copy_probe_GBs"] = round(best, 1)
     res["roofline"]["copy_probe_median_GBs"] = round(med, 1)

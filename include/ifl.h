@@ -113,9 +113,9 @@ typedef struct ifl_options {
   int32_t profile;   /* 1 = time the SpMV launches with HIP events (ifl_profile_read) */
   int32_t graphs;    /* 1 = the batched engine replays each 4-iteration chunk of a tile as one captured
                         HIP graph (default), 0 = launches every kernel; results are bitwise equal */
-  int32_t solver;    /* IFL_SOLVER_KN (default) or IFL_SOLVER_SHIFTED (orders n >= 2; ifl_filter and
-                        ifl_spectrum then solve one column at a time whatever 'batch' says; n = 1 and
-                        the serving engine use IFL_SOLVER_KN) */
+  int32_t solver;    /* IFL_SOLVER_KN (default) or IFL_SOLVER_SHIFTED (orders n >= 2; ifl_filter,
+                        ifl_spectrum and the serving engine then solve one column at a time whatever
+                        'batch' says; n = 1 uses IFL_SOLVER_KN) */
 } ifl_options;
 
 /* Per-solve statistics (one per field x scale). */
@@ -358,8 +358,7 @@ ifl_status ifl_profile_kernel(ifl_handle* h, char* buf, int32_t len);
  * Measured streaming bandwidth of a device, for roofline reports: a plain
  * copy of 'bytes' bytes (rounded down to 16-byte units; at least 16 MiB)
  * between two device buffers the call allocates and frees, each thread
- * moving 16 bytes per step of a grid-stride loop over all resident
- * workgroups. Runs 'reps' timed copies (HIP events, after one untimed) and
+ * moving 16 bytes once (one pass of 256-thread workgroups). Runs 'reps' timed copies (HIP events, after one untimed) and
  * returns the best and the median rate in GB/s (read + write bytes / time).
  * Not part of the filter; IFL_EINVAL on a bad argument, IFL_ENOMEM /
  * IFL_EDEVICE on a device failure.
@@ -405,7 +404,12 @@ typedef struct ifl_ticket ifl_ticket;
 ifl_status ifl_server_create(size_t hbm_budget_bytes, int32_t slots, ifl_server** out);
 
 /* Register a handle (borrowed: it must outlive the server). Handles of the
- * same mesh prepared for n = 1 and n = 2 are separate entries. */
+ * same mesh prepared for n = 1 and n = 2 are separate entries. The handle's
+ * options at this call fix how its requests run: in a tile of 'slots'
+ * columns (IFL_SOLVER_KN), or, for n >= 2 with IFL_SOLVER_SHIFTED, one
+ * column at a time through the shifted first-order solves. IFL_ENOMEM when
+ * the work space (tile, or shifted-solve vectors, plus staging) does not fit
+ * the budget. */
 ifl_status ifl_server_add(ifl_server* s, ifl_handle* h, int32_t* mesh_id);
 
 /*
@@ -434,7 +438,7 @@ ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field,
  */
 typedef struct ifl_server_info {
   size_t budget;          /* hbm_budget_bytes of ifl_server_create */
-  size_t tiles;           /* work space of the registered meshes' tiles */
+  size_t tiles;           /* work space of the registered meshes (tiles or shifted solves) */
   size_t used;            /* footprint of the requests in flight now */
   size_t peak_used;       /* largest 'used' so far */
   int64_t submitted;      /* requests accepted by ifl_submit */

@@ -11,10 +11,10 @@ namespace ifl {
 
 // A batched tile advances in chunks of kChunk CG iterations: x is updated
 // and the FP64 residual replaced at the end of each chunk (where alone a
-// column may stop),
-// columns enter only at chunk boundaries, and the host advances a tile by
-// whole chunks.
-constexpr int kChunk = 4;
+// column may stop), columns enter only at chunk boundaries, and the host
+// advances a tile by whole chunks.
+constexpr int kChunk = 4;  // iterations per chunk (buffers and alpha history)
+int chunk_for_order(int order);
 
 // Per-column CG state of one slot (device memory; mirrored to pinned host
 // memory by batch_read_slots).
@@ -51,6 +51,7 @@ struct BatchMatrix {
   int G = 1;   // blocks of the kernels that gather (SpMV, replacement, start, finish)
   int Gu = 1;  // blocks of the streaming update kernel
   int head = 6;  // off-diagonal entries per row in the gathering kernels' pipelined head (6, 12 or 20)
+  int chunk = 4;  // iterations per chunk (chunk_for_order of the handle)
 };
 
 struct BatchParams {
@@ -84,6 +85,7 @@ struct BatchWork {
   BSlot* slots_host = nullptr;  // pinned
   int* flag = nullptr;
   int64_t iter = 0;       // tile iterations so far (position in the chunk)
+  int chunk = 4;          // iterations per chunk (chunk_for_order)
   // one captured chunk (kChunk iterations), rebuilt when max_iter changes
   hipGraphExec_t chunk_exec = nullptr;
   int chunk_max_iter = 0;
@@ -95,7 +97,7 @@ struct SlotScales {
   double c[64];
 };
 
-size_t batch_bytes(int64_t n_pad, int R, bool mixed);
+size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk);
 // Lanes that share one row in a tile of R columns (each lane owns 16 bytes of
 // columns: 4 FP32 or 2 FP64).
 int batch_lanes_per_row(int R, bool mixed);

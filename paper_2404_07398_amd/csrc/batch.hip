@@ -15,10 +15,10 @@
 // Per-column state (alpha, beta, rho, stopping, residual replacement) lives
 // in device memory; after each reduction phase a small kernel with one
 // workgroup per column finishes that column's sum in a fixed order. A tile
-// advances in chunks of kChunk iterations and columns enter only at
+// advances in chunks of L iterations (4 or 8) and columns enter only at
 // chunk boundaries, so all live columns share the chunk position. Inside a
 // chunk only z (the preconditioned residual) and p change; the directions
-// of the chunk are kept in kChunk buffers and x is updated once, at the
+// of the chunk are kept in L buffers and x is updated once, at the
 // chunk's last iteration (in FP64, in every precision), from them and each
 // column's alpha history. Every running column's residual is then replaced
 // by its FP64 true residual, in one pass for the whole tile, and a column
@@ -257,7 +257,7 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 // (d = diag(S) = M + c diag(K_n), the Jacobi preconditioner; z = d^-1 r is
 // the residual state, r = d z is formed where it is needed):
 //
-//  FUSED (iterations 1..kChunk-1 of a chunk), given alpha_k and beta_{k+1}:
+//  FUSED (iterations 1..L-1 of a chunk of L), given alpha_k and beta_{k+1}:
 //    z' = z - alpha_k u                 (own row and every gathered neighbour)
 //    p' = z' + beta_{k+1} p
 //    u' = z' + d^-1 c K_off z' + beta_{k+1} u   (= d^-1 S p', as S p = S z' + beta S p)
@@ -285,7 +285,7 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 // issued after it.
 template <typename T, int R, bool FUSED, int H>
 __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                              int k) {
+                                              int k, int L) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   constexpr int NQ = FUSED ? 4 : 3;
@@ -308,13 +308,13 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
   }
   // buffers: the chunk's first iteration reads z[0] (set by the replacement)
   // and writes u[0]; iteration k >= 1 reads z, u [(k - 1) & 1] and writes
-  // z, u [k & 1]
+  // z, u [k & 1] (the replacement at the chunk's end writes z[0] again)
   const int bin = FUSED ? ((k - 1) & 1) : 0, bout = FUSED ? (k & 1) : 0;
   const T* __restrict__ zin = v.z[bin];
   const T* __restrict__ uin = v.u[bin];
   T* __restrict__ zout = v.z[bout];
   T* __restrict__ uout = v.u[bout];
-  const T* __restrict__ pin = v.p[(k + kChunk - 1) % kChunk];  // previous iteration's p
+  const T* __restrict__ pin = v.p[(k + L - 1) % L];  // previous iteration's p
   T* __restrict__ pout = v.p[k];
   const T* __restrict__ val = bval<T>(m);
   // value of a gathered neighbour: z' (FUSED) or p' (DIRECT); g1 is u or p
@@ -436,21 +436,21 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
 }
 
 // The chunk's x update, at its last iteration, in FP64 in every precision,
-// from the directions kept in p[0..3] and each column's alpha history: x +=
-// sum_k alpha_k p_k (alpha_k = 0 for a column that was not iterating).
-template <typename T, int R>
+// from the directions kept in p[0..L) and each column's alpha history:
+// x += sum_k alpha_k p_k (alpha_k = 0 for a column that was not iterating).
+template <typename T, int R, int L>
 __global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot* slots, int G) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
-  double ah[kChunk][C];
+  double ah[L][C];
   bool any = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const BSlot& sl = slots[j0 + c];
 #pragma unroll
-    for (int i = 0; i < kChunk; ++i) {
+    for (int i = 0; i < L; ++i) {
       ah[i][c] = sl.alpha_hist[i];
       any |= ah[i][c] != 0.0;
     }
@@ -460,14 +460,14 @@ __global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot*
     const int64_t row = wk.t * RPW + rsub;
     if (row >= m.n) continue;
     const int64_t idx = row * R + j0;
-    Pack<T, C> pk[kChunk];
+    Pack<T, C> pk[L];
 #pragma unroll
-    for (int i = 0; i < kChunk; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
+    for (int i = 0; i < L; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
     Pack<double, C> xv = vload<double, C>(v.x + idx);
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-      for (int i = 0; i < kChunk; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
+      for (int i = 0; i < L; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
     vstore<double, C>(v.x + idx, xv);
   }
 }
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot*
 // from scratch).
 template <typename T, int R, bool START, int H>
 __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
-                                                  int Gp, uint64_t mask, SlotScales cs) {
+                                                  int Gp, uint64_t mask, SlotScales cs, int L) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   __shared__ double lds[3 * kWpb * R];
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
     all &= on[c];
   }
   const double* __restrict__ src = START ? v.phi : v.x;  // the gathered operand
-  T* __restrict__ pprev = v.p[kChunk - 1];             // the chunk's first iteration reads it as p
+  T* __restrict__ pprev = v.p[L - 1];  // the chunk's first iteration reads it as p
   const Ident ident;
   double acc[3][C] = {};
   if (any) {
@@ -715,7 +715,7 @@ __global__ void kb_out(const double* __restrict__ x, OutPtrs out, uint64_t mask,
 }
 
 // Columns of one tile into another of a different width (same precision), at
-// a chunk boundary: z, the chunk's last direction p[kChunk - 1] (the next
+// a chunk boundary: z, the chunk's last direction p[L - 1] (the next
 // chunk's first iteration forms u from it, so u is not carried), x and phi of
 // each mapped column, one row per thread.
 struct ColMap {
@@ -951,11 +951,23 @@ __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const dou
 
 template <typename T>
 BVec<T> bvec(BatchWork& w) {
+  BVec<T> v{};
   if constexpr (sizeof(T) == 4) {
-    return BVec<T>{{w.z32[0], w.z32[1]}, {w.u32[0], w.u32[1]}, {w.p32[0], w.p32[1], w.p32[2], w.p32[3]}, w.x, w.phi};
+    for (int i = 0; i < 2; ++i) {
+      v.z[i] = w.z32[i];
+      v.u[i] = w.u32[i];
+    }
+    for (int i = 0; i < kChunk; ++i) v.p[i] = w.p32[i];
   } else {
-    return BVec<T>{{w.z64[0], w.z64[1]}, {w.u64[0], w.u64[1]}, {w.p64[0], w.p64[1], w.p64[2], w.p64[3]}, w.x, w.phi};
+    for (int i = 0; i < 2; ++i) {
+      v.z[i] = w.z64[i];
+      v.u[i] = w.u64[i];
+    }
+    for (int i = 0; i < kChunk; ++i) v.p[i] = w.p64[i];
   }
+  v.x = w.x;
+  v.phi = w.phi;
+  return v;
 }
 
 template <typename T>
@@ -981,16 +993,17 @@ template <int R, int H>
 struct LaunchH {
   template <typename T>
   static void iter(const BMat& m, BatchWork& w, Grids g, hipStream_t s, int k) {
-    if (k == 0) kb_iter<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k);
-    else kb_iter<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k);
+    if (k == 0) kb_iter<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    else kb_iter<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
   }
   template <typename T>
   static void replace(const BMat& m, BatchWork& w, Grids g, hipStream_t s) {
-    kb_residual<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, 0ull, SlotScales{});
+    kb_residual<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, 0ull, SlotScales{},
+                                                    w.chunk);
   }
   template <typename T>
   static void start(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs) {
-    kb_residual<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, mask, cs);
+    kb_residual<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, mask, cs, w.chunk);
   }
 };
 
@@ -1002,7 +1015,7 @@ struct Launch {
     else if (head <= 12) f(LaunchH<R, 12>{});
     else f(LaunchH<R, 20>{});
   }
-  // iteration k (0..kChunk-1) of a chunk: one fused iteration kernel and its
+  // iteration k (0..L-1) of a chunk of L: one fused iteration kernel and its
   // finalizer; the last one also applies the chunk's x update and the FP64
   // residual replacement of every running column, whose true residual is
   // the only one that may stop a column (in both precisions: a recursive
@@ -1013,8 +1026,8 @@ struct Launch {
     by_head<T>(head, [&](auto L) { L.template iter<T>(m, w, g, s, k); });
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
     kf_step<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
-    if (k == kChunk - 1) {
-      kb_xupdate<T, R><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
+    if (k == w.chunk - 1) {
+      kb_xupdate<T, R, kChunk><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
       by_head<T>(head, [&](auto L) { L.template replace<T>(m, w, g, s); });
       kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
     }
@@ -1111,19 +1124,23 @@ int batch_lanes_per_row(int R, bool mixed) {
 
 ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   const size_t nr = (size_t)bm.n_pad * R;
+  const int chunk = bm.chunk == 8 ? 8 : 4;
   ifl_status st;
   std::vector<void*> vecs;  // the precision's vectors, zeroed below
   size_t es = 0;
   if (mixed) {
     es = sizeof(float);
-    for (float** p : {&w->z32[0], &w->z32[1], &w->u32[0], &w->u32[1], &w->p32[0], &w->p32[1], &w->p32[2], &w->p32[3]}) {
+    std::vector<float**> all = {&w->z32[0], &w->z32[1], &w->u32[0], &w->u32[1]};
+    for (int i = 0; i < chunk; ++i) all.push_back(&w->p32[i]);
+    for (float** p : all) {
       if ((st = dalloc_b(p, nr))) return st;
       vecs.push_back(*p);
     }
   } else {
     es = sizeof(double);
-    for (double** p :
-         {&w->z64[0], &w->z64[1], &w->u64[0], &w->u64[1], &w->p64[0], &w->p64[1], &w->p64[2], &w->p64[3]}) {
+    std::vector<double**> all = {&w->z64[0], &w->z64[1], &w->u64[0], &w->u64[1]};
+    for (int i = 0; i < chunk; ++i) all.push_back(&w->p64[i]);
+    for (double** p : all) {
       if ((st = dalloc_b(p, nr))) return st;
       vecs.push_back(*p);
     }
@@ -1145,22 +1162,34 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   w->Gu = bm.Gu;
   w->mixed = mixed;
   w->iter = 0;
+  w->chunk = chunk;
   return IFL_OK;
 }
 
+// Four iterations for every order. Eight were measured on first-order
+// tiles: the per-iteration cost fell (one x update and one FP64 replacement
+// per eight iterations) but the iteration count rose more (12% on the
+// level-9 sphere, 80% on the vertex vector Laplacian), since a column stops
+// only at a chunk's end and the FP32 recurrences of z and u run twice as
+// long between replacements.
+int chunk_for_order(int) { return kChunk; }
+
 void batch_free(BatchWork* w) {
   if (w->chunk_exec) (void)hipGraphExecDestroy(w->chunk_exec);
-  void* ptrs[] = {w->z32[0], w->z32[1], w->u32[0], w->u32[1], w->p32[0], w->p32[1], w->p32[2], w->p32[3],
-                  w->z64[0], w->z64[1], w->u64[0], w->u64[1], w->p64[0], w->p64[1], w->p64[2], w->p64[3],
-                  w->x,      w->phi,    w->part,   w->slots,  w->flag};
+  std::vector<void*> ptrs = {w->z32[0], w->z32[1], w->u32[0], w->u32[1], w->z64[0], w->z64[1], w->u64[0],
+                             w->u64[1], w->x,      w->phi,    w->part,   w->slots,  w->flag};
+  for (int i = 0; i < kChunk; ++i) {
+    ptrs.push_back(w->p32[i]);
+    ptrs.push_back(w->p64[i]);
+  }
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w->slots_host) (void)hipHostFree(w->slots_host);
   *w = BatchWork();
 }
 
-size_t batch_bytes(int64_t n_pad, int R, bool mixed) {
-  const size_t per = mixed ? (8 * 4 + 8 + 8) : (8 * 8 + 8 + 8);
+size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk) {
+  const size_t per = (size_t)(4 + chunk) * (mixed ? 4 : 8) + 8 + 8;  // z, u (x2), p (x chunk), x, phi
   return (size_t)n_pad * R * per;
 }
 
@@ -1227,8 +1256,8 @@ ifl_status batch_check_flag(BatchWork& w, hipStream_t s, bool* bad) {
 ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const SlotScales& cs, double rtol,
                       hipStream_t s) {
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
-  if (w.iter % kChunk != 0)
-    return fail(IFL_EINVAL, "columns may only enter a tile at iterations that are multiples of kChunk");
+  if (w.iter % w.chunk != 0)
+    return fail(IFL_EINVAL, "columns may only enter a tile at chunk boundaries");
   dispatch_R<DoInit>(w.R, bmat(bm), w, grids(bm), s, mask, cs, rtol, bm.head);
   IFL_HIPB(hipGetLastError());
   return IFL_OK;
@@ -1239,7 +1268,7 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
   return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 6.0 * vb * bm.n * live;
 }
 
-// Capture one chunk (kChunk iterations, no timing events) into w.chunk_exec.
+// Capture one chunk (w.chunk iterations, no timing events) into w.chunk_exec.
 // The kernel arguments of a tile do not change from one chunk to the next, so
 // the one graph serves every chunk until max_iter changes.
 static ifl_status capture_chunk(const BMat& m, const BatchMatrix& bm, BatchWork& w, const BatchParams& prm,
@@ -1251,7 +1280,7 @@ static ifl_status capture_chunk(const BMat& m, const BatchMatrix& bm, BatchWork&
   BatchParams p = prm;
   p.ev_begin = p.ev_end = nullptr;
   IFL_HIPB(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < kChunk; ++k) dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, p, k, bm.head);
+  for (int k = 0; k < w.chunk; ++k) dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, p, k, bm.head);
   hipGraph_t g = nullptr;
   const hipError_t e1 = hipStreamEndCapture(s, &g);
   const hipError_t e2 = hipGetLastError();
@@ -1271,7 +1300,7 @@ static ifl_status capture_chunk(const BMat& m, const BatchMatrix& bm, BatchWork&
 
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s) {
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
-  if (n_iter % kChunk != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of kChunk");
+  if (n_iter % w.chunk != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of the tile's chunk");
   const BMat m = bmat(bm);
   // the timing events (if any) go around the SpMV of the call's second
   // iteration (the recurrence form that runs three times per chunk); the
@@ -1281,7 +1310,7 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
   const bool events = prm.ev_begin || prm.ev_end;
   for (int i = 0; i < n_iter;) {
     const bool timed = events && i <= 1;
-    if (!timed && prm.graphs && !w.graphs_broken && w.iter % kChunk == 0 && n_iter - i >= kChunk) {
+    if (!timed && prm.graphs && !w.graphs_broken && w.iter % w.chunk == 0 && n_iter - i >= w.chunk) {
       if (!w.chunk_exec || w.chunk_max_iter != prm.max_iter) {
         if (capture_chunk(m, bm, w, prm, s) != IFL_OK) {
           // launch directly from now on; the stream is out of capture mode
@@ -1291,11 +1320,11 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
         }
       }
       IFL_HIPB(hipGraphLaunch(w.chunk_exec, s));
-      w.iter += kChunk;
-      i += kChunk;
+      w.iter += w.chunk;
+      i += w.chunk;
       continue;
     }
-    const int k = (int)(w.iter % kChunk);
+    const int k = (int)(w.iter % w.chunk);
     dispatch_R<DoIterate>(w.R, m, w, grids(bm), s, i == 1 ? prm : rest, k, bm.head);
     ++w.iter;
     ++i;
@@ -1322,7 +1351,8 @@ ifl_status batch_read_slots(BatchWork& w, hipStream_t s) {
 ifl_status batch_move_columns(const BatchMatrix& bm, BatchWork& src, BatchWork& dst, const int* from, const int* to,
                               int n, hipStream_t s) {
   if (src.mixed != dst.mixed) return fail(IFL_EINVAL, "tiles of different precision");
-  if (src.iter % kChunk != 0) return fail(IFL_EINVAL, "columns move only at chunk boundaries");
+  if (src.iter % src.chunk != 0 || src.chunk != dst.chunk)
+    return fail(IFL_EINVAL, "columns move only at chunk boundaries, between tiles of one chunk length");
   if (n < 0 || n > dst.R || n > src.R) return fail(IFL_EINVAL, "too many columns to move");
   ColMap map{};
   map.n = n;
@@ -1334,11 +1364,11 @@ ifl_status batch_move_columns(const BatchMatrix& bm, BatchWork& src, BatchWork& 
   }
   const unsigned nb = (unsigned)((bm.n_pad + 255) / 256);
   if (src.mixed)
-    kb_move_cols<float><<<nb, 256, 0, s>>>(src.z32[0], src.p32[kChunk - 1], src.x, src.phi, src.R, dst.z32[0],
-                                            dst.p32[kChunk - 1], dst.x, dst.phi, dst.R, map, bm.n_pad);
+    kb_move_cols<float><<<nb, 256, 0, s>>>(src.z32[0], src.p32[src.chunk - 1], src.x, src.phi, src.R, dst.z32[0],
+                                            dst.p32[dst.chunk - 1], dst.x, dst.phi, dst.R, map, bm.n_pad);
   else
-    kb_move_cols<double><<<nb, 256, 0, s>>>(src.z64[0], src.p64[kChunk - 1], src.x, src.phi, src.R, dst.z64[0],
-                                             dst.p64[kChunk - 1], dst.x, dst.phi, dst.R, map, bm.n_pad);
+    kb_move_cols<double><<<nb, 256, 0, s>>>(src.z64[0], src.p64[src.chunk - 1], src.x, src.phi, src.R, dst.z64[0],
+                                             dst.p64[dst.chunk - 1], dst.x, dst.phi, dst.R, map, bm.n_pad);
   kf_move_slots<<<1, 64, 0, s>>>(src.slots, dst.slots, dst.R, map);
   IFL_HIPB(hipGetLastError());
   dst.iter = 0;

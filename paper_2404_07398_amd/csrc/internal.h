@@ -101,6 +101,15 @@ ifl_status device_profile_read(Handle* h, int64_t* launches, double* total_ms, d
                                int32_t reset);
 std::string device_profile_kernel(Handle* h);
 ifl_status device_stream_probe(int device, int64_t bytes, int reps, double* best_gbs, double* median_gbs);
+// One column of a served request on a handle of order >= 2 with
+// IFL_SOLVER_SHIFTED: the field in row order (device, the handle's rows),
+// wavenumber k, the result to out_dev in the caller's numbering (device;
+// NULL: energy only). Runs on the handle's stream; the caller holds h->mu.
+ifl_status device_solve_shifted_rows(Handle* h, const double* phi_rows, double k, double* out_dev,
+                                     ifl_solve_stats* st);
+// Allocates (once per handle) the work space of the shifted solves and
+// returns its size in bytes; the caller holds h->mu.
+ifl_status device_shift_work(Handle* h, size_t* bytes);
 ifl_status device_autotune(Handle* h, ifl_tune* out);
 
 }  // namespace ifl

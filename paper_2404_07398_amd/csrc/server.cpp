@@ -78,6 +78,9 @@ struct Worker {
   // set by ifl_server_cancel: the worker fails its admitted columns that
   // have not entered a slot at the top of its next loop
   std::atomic<bool> cancel{false};
+  // the handle solves with IFL_SOLVER_SHIFTED (order >= 2): columns one at a
+  // time through the shifted first-order solves, no tile
+  bool shifted = false;
 };
 
 }  // namespace
@@ -146,6 +149,74 @@ void release_ticket(Worker* wk, ifl_ticket* t) {
   wk->srv->cv.notify_all();
 }
 
+// After ifl_server_cancel: the admitted columns that wait for a slot end
+// with IFL_ECANCELED (their requests finish once no column is left running).
+void cancel_pending(Worker* wk) {
+  if (!wk->cancel.exchange(false)) return;
+  for (const Column& c : wk->pending) {
+    ifl_ticket* t = c.t;
+    t->stats[c.scale].status = IFL_ECANCELED;
+    if (--t->remaining == 0) {
+      release_ticket(wk, t);
+      finish_ticket(t, IFL_ECANCELED, "request cancelled by ifl_server_cancel");
+    } else {
+      std::lock_guard<std::mutex> lk(t->mu);
+      if (t->status == IFL_OK) {
+        t->status = IFL_ECANCELED;
+        t->error = "request cancelled by ifl_server_cancel";
+      }
+    }
+  }
+  wk->pending.clear();
+}
+
+// Admit queued requests that fit the budget, stage each field on the device
+// in row order (checked for NaN / Inf there), and queue its columns.
+void stage_admitted(Worker* wk) {
+  std::vector<ifl_ticket*> adm;
+  admit(wk, &adm);
+  for (ifl_ticket* t : adm) {
+    if (!wk->field_pool.empty()) {
+      t->dev_field = wk->field_pool.back();
+      wk->field_pool.pop_back();
+    } else if (hipMalloc((void**)&t->dev_field, sizeof(double) * wk->bm.n_pad) != hipSuccess) {
+      t->dev_field = nullptr;
+    }
+    // the field goes through the staging buffer into row order (stream order
+    // keeps the staging buffer's reuse safe); the permutation raises the
+    // device flag on a NaN or Inf at a wet entry
+    bool bad = false;
+    if (!t->dev_field || batch_clear_flag(wk->w, wk->stream) != IFL_OK ||
+        hipMemcpyAsync(wk->stage, t->field, sizeof(double) * wk->L, hipMemcpyHostToDevice, wk->stream) !=
+            hipSuccess ||
+        batch_permute_fields(wk->bm, wk->stage, wk->L, 1, t->dev_field, wk->w.flag, wk->stream) != IFL_OK ||
+        batch_check_flag(wk->w, wk->stream, &bad) != IFL_OK) {
+      (void)hipGetLastError();
+      release_ticket(wk, t);
+      finish_ticket(t, IFL_ENOMEM, "device allocation or copy for the request failed");
+      continue;
+    }
+    if (bad) {
+      release_ticket(wk, t);
+      finish_ticket(t, IFL_EINVAL, "field has a NaN or Inf at a wet entry");
+      continue;
+    }
+    for (int j = 0; j < t->n_scales; ++j) wk->pending.push_back({t, j});
+  }
+}
+
+// Complete a request whose last column is done.
+void complete_ticket(Worker* wk, ifl_ticket* t) {
+  bool all_ok = true, cancelled = false;
+  for (const auto& x : t->stats) {
+    all_ok &= x.status == IFL_OK;
+    cancelled |= x.status == IFL_ECANCELED;
+  }
+  release_ticket(wk, t);
+  if (cancelled) finish_ticket(t, IFL_ECANCELED, "request cancelled by ifl_server_cancel");
+  else finish_ticket(t, all_ok ? IFL_OK : IFL_ENOTCONV, all_ok ? "" : "a column did not converge");
+}
+
 ifl_status run_worker(Worker* wk) {
   Handle* h = wk->h;
   const int R = wk->R;
@@ -153,58 +224,13 @@ ifl_status run_worker(Worker* wk) {
   BatchParams prm;
   prm.max_iter = h->opt.max_iter;
   prm.graphs = h->opt.graphs != 0;
-  const int chunk = 4;
+  const int chunk = wk->w.chunk;
   int active = 0;
   for (;;) {
     // 0. cancellation: admitted columns still waiting for a slot end here
-    if (wk->cancel.exchange(false)) {
-      for (const Column& c : wk->pending) {
-        ifl_ticket* t = c.t;
-        t->stats[c.scale].status = IFL_ECANCELED;
-        if (--t->remaining == 0) {
-          release_ticket(wk, t);
-          finish_ticket(t, IFL_ECANCELED, "request cancelled by ifl_server_cancel");
-        } else {
-          std::lock_guard<std::mutex> lk(t->mu);
-          if (t->status == IFL_OK) {
-            t->status = IFL_ECANCELED;
-            t->error = "request cancelled by ifl_server_cancel";
-          }
-        }
-      }
-      wk->pending.clear();
-    }
+    cancel_pending(wk);
     // 1. admit and stage new requests
-    std::vector<ifl_ticket*> adm;
-    admit(wk, &adm);
-    for (ifl_ticket* t : adm) {
-      if (!wk->field_pool.empty()) {
-        t->dev_field = wk->field_pool.back();
-        wk->field_pool.pop_back();
-      } else if (hipMalloc((void**)&t->dev_field, sizeof(double) * wk->bm.n_pad) != hipSuccess) {
-        t->dev_field = nullptr;
-      }
-      // the field goes through the staging buffer into row order (stream order
-      // keeps the staging buffer's reuse safe); the permutation raises the
-      // device flag on a NaN or Inf at a wet entry
-      bool bad = false;
-      if (!t->dev_field || batch_clear_flag(wk->w, wk->stream) != IFL_OK ||
-          hipMemcpyAsync(wk->stage, t->field, sizeof(double) * wk->L, hipMemcpyHostToDevice, wk->stream) !=
-              hipSuccess ||
-          batch_permute_fields(wk->bm, wk->stage, wk->L, 1, t->dev_field, wk->w.flag, wk->stream) != IFL_OK ||
-          batch_check_flag(wk->w, wk->stream, &bad) != IFL_OK) {
-        (void)hipGetLastError();
-        release_ticket(wk, t);
-        finish_ticket(t, IFL_ENOMEM, "device allocation or copy for the request failed");
-        continue;
-      }
-      if (bad) {
-        release_ticket(wk, t);
-        finish_ticket(t, IFL_EINVAL, "field has a NaN or Inf at a wet entry");
-        continue;
-      }
-      for (int j = 0; j < t->n_scales; ++j) wk->pending.push_back({t, j});
-    }
+    stage_admitted(wk);
     // 2. fill free slots
     uint64_t mask = 0;
     SlotScales cs{};
@@ -266,24 +292,55 @@ ifl_status run_worker(Worker* wk) {
       so.energy = 0.5 * sl.energy2 / handle_mass_sum(h);
       wk->slot[j] = Column{nullptr, 0};
       --active;
-      if (--t->remaining == 0) {
-        bool all_ok = true, cancelled = false;
-        for (const auto& x : t->stats) {
-          all_ok &= x.status == IFL_OK;
-          cancelled |= x.status == IFL_ECANCELED;
-        }
-        release_ticket(wk, t);
-        if (cancelled) finish_ticket(t, IFL_ECANCELED, "request cancelled by ifl_server_cancel");
-        else finish_ticket(t, all_ok ? IFL_OK : IFL_ENOTCONV, all_ok ? "" : "a column did not converge");
-      }
+      if (--t->remaining == 0) complete_ticket(wk, t);
     }
     if ((st = batch_release(wk->w, fin, wk->stream)) != IFL_OK) return st;
   }
 }
 
+// A handle of order n >= 2 with IFL_SOLVER_SHIFTED: its requests' columns
+// are solved one at a time by the shifted first-order solves (one kernel
+// per COCG iteration) on the handle's stream, under the handle's lock; the
+// other meshes' workers run concurrently on their own streams.
+ifl_status run_worker_shifted(Worker* wk) {
+  Handle* h = wk->h;
+  for (;;) {
+    cancel_pending(wk);
+    stage_admitted(wk);
+    if (wk->pending.empty()) {
+      std::unique_lock<std::mutex> lk(wk->srv->mu);
+      if (wk->srv->stop && wk->queue.empty()) return IFL_OK;
+      if (wk->queue.empty()) wk->srv->cv.wait_for(lk, std::chrono::milliseconds(50));
+      continue;
+    }
+    const Column col = wk->pending.front();
+    wk->pending.pop_front();
+    ifl_ticket* t = col.t;
+    double* dst = t->out ? wk->col_out : nullptr;
+    ifl_solve_stats so{};
+    ifl_status st;
+    {
+      std::lock_guard<std::mutex> lk(h->mu);
+      st = device_solve_shifted_rows(h, t->dev_field, t->k[col.scale], dst, &so);
+    }
+    if (st != IFL_OK && st != IFL_ENOTCONV) {
+      wk->pending.push_front(col);
+      return st;
+    }
+    if (t->out && (hipMemcpyAsync(t->out + (int64_t)col.scale * wk->L, dst, sizeof(double) * wk->L,
+                                  hipMemcpyDeviceToHost, wk->stream) != hipSuccess ||
+                   hipStreamSynchronize(wk->stream) != hipSuccess)) {
+      wk->pending.push_front(col);
+      return fail(IFL_EDEVICE, "copy of a finished column failed");
+    }
+    t->stats[col.scale] = so;
+    if (--t->remaining == 0) complete_ticket(wk, t);
+  }
+}
+
 void worker_main(Worker* wk) {
   (void)hipSetDevice(wk->srv->device);
-  ifl_status st = run_worker(wk);
+  ifl_status st = wk->shifted ? run_worker_shifted(wk) : run_worker(wk);
   if (st != IFL_OK) {
     // fail everything this worker still holds, so no waiter blocks forever;
     // admitted requests (in a slot or waiting for one) give their memory
@@ -343,19 +400,30 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
   wk->L = h->op.field_len;
   s->device = h->opt.device;
   if (hipSetDevice(h->opt.device) != hipSuccess) return fail(IFL_EDEVICE, "hipSetDevice failed");
+  wk->shifted = h->opt.solver == IFL_SOLVER_SHIFTED && h->op.order >= 2;
   wk->bm = handle_batch_matrix(h, wk->R, h->opt.precision == IFL_MIXED);
-  const size_t tile = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED) +
-                      sizeof(double) * (size_t)(wk->R + 1) * wk->L;  // + output and field staging
+  const int n_out = wk->shifted ? 1 : wk->R;  // output staging columns
+  size_t work = 0;
+  if (wk->shifted) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (ifl_status st = device_shift_work(h, &work)) return st;
+  } else {
+    work = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED, wk->bm.chunk);
+  }
+  const size_t tile = work + sizeof(double) * (size_t)(n_out + 1) * wk->L;  // + output and field staging
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->tiles + s->used + tile > s->budget)
       return fail(IFL_ENOMEM, "tile work space exceeds the server's memory budget");
     s->tiles += tile;
   }
-  ifl_status st = batch_alloc(&wk->w, wk->bm, wk->R, h->opt.precision == IFL_MIXED);
+  ifl_status st = IFL_OK;
+  if (!wk->shifted) st = batch_alloc(&wk->w, wk->bm, wk->R, h->opt.precision == IFL_MIXED);
+  else if (hipMalloc((void**)&wk->w.flag, sizeof(int)) != hipSuccess)  // only the field check's flag
+    st = fail(IFL_ENOMEM, "hipMalloc of the field check flag failed");
   if (st == IFL_OK && hipMalloc((void**)&wk->stage, sizeof(double) * (size_t)wk->L) != hipSuccess)
     st = fail(IFL_ENOMEM, "hipMalloc of the field staging failed");
-  if (st == IFL_OK && hipMalloc((void**)&wk->col_out, sizeof(double) * (size_t)wk->R * wk->L) != hipSuccess)
+  if (st == IFL_OK && hipMalloc((void**)&wk->col_out, sizeof(double) * (size_t)n_out * wk->L) != hipSuccess)
     st = fail(IFL_ENOMEM, "hipMalloc of the output staging failed");
   if (st == IFL_OK && hipStreamCreateWithFlags(&wk->stream, hipStreamNonBlocking) != hipSuccess)
     st = fail(IFL_EDEVICE, "hipStreamCreate failed");

@@ -278,3 +278,39 @@ def test_server_cancel(ifl):
     assert st == 0 and np.array_equal(o, ref)
     srv.close()
     h.close()
+
+
+def test_served_shifted_solver(ifl):
+    """A handle of order 2 with IFL_SOLVER_SHIFTED is served column by
+    column through the shifted first-order solves, beside a first-order
+    handle served in tiles: each result equals the oracle's shifted solve
+    within its precision's bar and, bitwise, the handle's own ifl_filter."""
+    s = W.icosphere(5, jitter=0.1)
+    s = s.with_mask(W.land_mask(s, 0.3))
+    op2 = O.scalar_operator(s, 2)
+    h2 = ifl.prepare_mesh(s, 0, 2, precision=ifl.IFL_MIXED, solver=ifl.IFL_SOLVER_SHIFTED)
+    h1 = ifl.prepare_mesh(s, 0, 1, precision=ifl.IFL_MIXED)
+    fields = [W.sphere_k3_field(s, 800 + i, n_waves=64) for i in range(3)]
+    ks = W.log_scales(s.h, 5)
+    alone = [h2.filter(f, ks)[0][0] for f in fields]
+    srv = ifl.Server(4 << 30, slots=4)
+    m2, m1 = srv.add(h2), srv.add(h1)
+    tl = []
+    for f in fields:
+        tl.append((srv.submit(m2, f, ks), True))
+        tl.append((srv.submit(m1, f, ks[::2]), False))
+    i2 = 0
+    for (t, _), shifted in tl:
+        n_s = ks.size if shifted else ks[::2].size
+        st, stats, o, _ = srv.wait(t, n_s)
+        assert st == 0
+        if shifted:
+            ref = O.filter_scalar(op2, fields[i2], ks, method="shifted")
+            for j in range(ks.size):
+                assert relative_l2(o[j], ref[j]) <= 1e-9
+            assert np.array_equal(o, alone[i2]), i2
+            assert all(x.iterations < 400 for x in stats)
+            i2 += 1
+    srv.close()
+    h1.close()
+    h2.close()
