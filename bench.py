@@ -213,6 +213,44 @@ def spmv10_leg(ifl):
     return res
 
 
+def reach_leg(ifl):
+    """Reach of orders 2-4 at large scales: the uniform periodic 64 x 64
+    split square (h = 1), one k^-3 field, wavelengths 8h, 11.3h, 16h, 22.6h
+    and 32h, Jacobi-PCG on K_n against the shifted first-order solves, FP64
+    and mixed, single column, max_iter 20,000. The error is against the
+    exact filter on that lattice: each Fourier mode times
+    1 / (1 + gamma (lam / k^2)^n), lam = 4 sin^2(qx/2) + 4 sin^2(qy/2)."""
+    import workloads as W
+
+    N = 64
+    m = W.split_square(N, jitter=0.0)
+    phi = W.planar_k3_field(m, 1000)
+    lams = [8.0, 8.0 * math.sqrt(2.0), 16.0, 16.0 * math.sqrt(2.0), 32.0]
+    ks = np.array([2 * math.pi / wl for wl in lams])
+    q = 2 * np.pi * np.fft.fftfreq(N)
+    QX, QY = np.meshgrid(q, q)
+    lam = 4 * np.sin(QX / 2) ** 2 + 4 * np.sin(QY / 2) ** 2
+    F = np.fft.fft2(phi.reshape(N, N))
+    res = {"mesh": "uniform periodic 64 x 64 split square", "wavelengths_h": [round(x, 1) for x in lams]}
+    for n in (2, 3, 4):
+        for solver, sname in ((ifl.IFL_SOLVER_KN, "kn"), (ifl.IFL_SOLVER_SHIFTED, "shifted")):
+            for prec, pname in ((ifl.IFL_FP64, "fp64"), (ifl.IFL_MIXED, "mixed")):
+                h = ifl.prepare_mesh(m, ifl.IFL_VERTEX_SCALAR, n, precision=prec, batch=1, device=0,
+                                     solver=solver, max_iter=20000)
+                t = time.perf_counter()
+                out, st = h.filter(phi, ks, raise_on_notconv=False)
+                el = time.perf_counter() - t
+                h.close()
+                errs = []
+                for j, k in enumerate(ks):
+                    ref = np.real(np.fft.ifft2(F / (1.0 + 0.5 * (lam / k ** 2) ** n))).ravel()
+                    errs.append(float("%.1e" % (np.linalg.norm(out[0, j] - ref) / np.linalg.norm(ref))))
+                res[f"n{n}_{sname}_{pname}"] = {
+                    "status": [int(x.status) for x in st], "iterations": [int(x.iterations) for x in st],
+                    "rel_err": errs, "solves_per_s": round(len(ks) / el, 1)}
+    return res
+
+
 def vector_leg(ifl):
     """Velocity filtering on the level-8 sphere (655,362 vertices,
     1,310,720 triangles; 30% land and dry polar caps, where lon/lat
@@ -428,6 +466,7 @@ def serve_leg(args, ifl):
 
         def waiter():
             k = 0
+            t_log = time.perf_counter()
             while k < len(reqs):
                 with cv:
                     while len(box) <= k:
@@ -437,8 +476,11 @@ def serve_leg(args, ifl):
                 done[k] = (st, ns, i, lat, sum(x.iterations for x in stats), t_sub + lat)
                 del out
                 k += 1
+                if time.perf_counter() - t_log > 10.0:
+                    t_log = time.perf_counter()
+                    log(f"  stream at {rate:g}/s: {k}/{len(reqs)} requests done, {len(box)} submitted")
 
-        th = threading.Thread(target=waiter)
+        th = threading.Thread(target=waiter, daemon=True)
         th.start()
         torch.cuda.synchronize()
         t_start = time.perf_counter()
@@ -462,8 +504,14 @@ def serve_leg(args, ifl):
             th.join(timeout=max(0.0, float(arrivals[-1]) + drain_s - (time.perf_counter() - t_start)))
             if th.is_alive():
                 cancelled_at = time.perf_counter() - t_start
+                log(f"  stream at {rate:g}/s: window over, cancelling what has not started")
                 srv.cancel()
-        th.join()
+        # columns already running finish after a cancel; a stream that still
+        # has not drained after this long is reported as stuck
+        th.join(timeout=max(120.0, 2.0 * float(arrivals[-1])) if drain_s is not None else None)
+        if th.is_alive():
+            raise RuntimeError(f"serving stream at {rate:g}/s did not drain: {len(done)}/{len(reqs)} requests "
+                               f"finished 120 s after the cancel")
         meas = [done[k] for k in range(warmup, len(reqs))]
         ok = [x for x in meas if x[0] == 0]
         t_first = float(arrivals[warmup])
@@ -481,6 +529,7 @@ def serve_leg(args, ifl):
             per.setdefault(meshes[x[2]][:2], []).append(x[3])
         solves = sum(x[1] for x in ok)
         return {
+            "drain_lag_s": round(t_last - float(arrivals[-1]), 3) if ok else None,
             "p50_latency_ms": pct(50),
             "p99_latency_ms": pct(99),
             "solves_per_s": round(solves / span, 2),
@@ -516,6 +565,31 @@ def serve_leg(args, ifl):
     if args.serve_sustained_rate > 0 and args.serve_sustained_requests > 0:
         res["sustained"] = stream(args.serve_sustained_rate, draw(args.serve_sustained_requests), 0, False)
         log(f"serving at {args.serve_sustained_rate:g}/s: {res['sustained']}")
+    if args.serve_sweep:
+        # rising offered rates (spectrum-only, bounded window); a rate is
+        # sustained when nothing is cancelled or failed and the last request
+        # finishes within serve_sweep_lag_s of the last arrival (the queue
+        # did not build up); the sweep stops at the first rate that is not
+        pts = []
+        for rate in [float(x) for x in args.serve_sweep.split(",") if x]:
+            r = stream(rate, draw(args.serve_sweep_requests), 0, True, drain_s=args.serve_sweep_drain_s)
+            ok = (r["cancelled_requests"] == 0 and r["failed"] == 0 and r["drain_lag_s"] is not None
+                  and r["drain_lag_s"] <= args.serve_sweep_lag_s)
+            pts.append({"offered_rate_req_s": rate, "achieved_rate_req_s": r["achieved_rate_req_s"],
+                        "drain_lag_s": r["drain_lag_s"],
+                        "p50_latency_ms": r["p50_latency_ms"], "p99_latency_ms": r["p99_latency_ms"],
+                        "completed_requests": r["completed_requests"], "requests": r["requests"],
+                        "solves_per_s": r["solves_per_s"], "sustained": ok})
+            log(f"serving sweep: {pts[-1]}")
+            if not ok:
+                break
+        res["rate_sweep"] = {
+            "requests_per_rate": args.serve_sweep_requests, "drain_s": args.serve_sweep_drain_s,
+            "rule": f"sustained: no request cancelled or failed, and the last one done within "
+                    f"{args.serve_sweep_lag_s:g} s of the last arrival",
+            "points": pts,
+            "highest_sustained_rate_req_s": max([x["offered_rate_req_s"] for x in pts if x["sustained"]],
+                                                default=None)}
     # like-for-like: one request sample, served (fields returned) and plain FP64
     cmp_reqs = draw(args.serve_compare) if args.serve_compare > 0 else []
     if cmp_reqs:
@@ -642,7 +716,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-spmv-leg", action="store_true", help="skip the SpMV rates on the unmasked level-9 mesh")
     ap.add_argument("--no-vector-leg", action="store_true", help="skip the velocity filtering on the level-8 mesh")
-    ap.add_argument("--leg", choices=["velocity", "spmv", "spmv10", "c1", "c2", "serve"], default=None,
+    ap.add_argument("--leg", choices=["velocity", "spmv", "spmv10", "c1", "c2", "reach", "serve"], default=None,
                     help="run only this leg and print its JSON (for profiling one leg on its own)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured chunks")
@@ -653,6 +727,11 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200, help="requests of the stream before the measured ones")
     ap.add_argument("--serve-slots", type=int, default=8, help="column slots per resident mesh")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="device memory budget of the server")
+    ap.add_argument("--serve-sweep-lag-s", type=float, default=3.0)
+    ap.add_argument("--serve-sweep", default="2,4,6,8,12",
+                    help="offered rates (req/s) of the serving rate sweep, comma-separated; empty = no sweep")
+    ap.add_argument("--serve-sweep-requests", type=int, default=40)
+    ap.add_argument("--serve-sweep-drain-s", type=float, default=8.0)
     ap.add_argument("--serve-n2-solver", choices=["shifted", "kn"], default="shifted",
                     help="how the served n = 2 requests are solved: the shifted first-order solves (one column at "
                          "a time) or Jacobi-PCG on K_2 in tiles")
@@ -689,6 +768,7 @@ def main():
         log(f"copy probe: 2 x {args.copy_probe_mib} MiB device copies (k_stream_copy)")
     if args.leg is not None:
         fn = {"velocity": vector_leg, "spmv": spmv_leg, "spmv10": spmv10_leg, "c1": c1_leg, "c2": c2_leg,
+              "reach": reach_leg,
               "serve": lambda m: serve_leg(args, m)}[args.leg]
         print(json.dumps({"leg": args.leg, **fn(ifl)}), flush=True)
         return
@@ -821,7 +901,8 @@ def main():
             res["spmv_2.6M_vertices"] = {"error": str(e)}
         log(f"spmv: {res['spmv_2.6M_vertices']}")
     if not args.no_c1c2:
-        for name, fn in (("c1_planar_64x64", c1_leg), ("c2_level8_biharmonic", c2_leg)):
+        for name, fn in (("c1_planar_64x64", c1_leg), ("c2_level8_biharmonic", c2_leg),
+                         ("orders_reach_64x64", reach_leg)):
             log(f"{name} leg ...")
             try:
                 res[name] = fn(ifl)
@@ -839,7 +920,7 @@ def main():
         log("serving leg ...")
         try:
             res["serving"] = serve_leg(args, ifl)
-        except ifl.IflError as e:
+        except (ifl.IflError, RuntimeError) as e:
             res["serving"] = {"error": str(e)}
         log(f"serving: {res['serving']}")
     if not args.no_cpu_baseline:

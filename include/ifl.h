@@ -434,7 +434,9 @@ ifl_status ifl_submit(ifl_server* s, int32_t mesh_id, const double* field,
  * its field copy on the device: 8 bytes per dof row, the dofs rounded up to
  * a multiple of 64 (its columns run in the mesh's tile, whose work space is
  * charged once, at ifl_server_add). A request is admitted when
- * tiles + used + its footprint <= budget, or when nothing is in flight.
+ * tiles + used + its footprint <= budget, or when nothing is in flight, and
+ * while fewer than 2 x slots of its mesh's admitted columns wait for a slot
+ * (requests of a mesh are admitted in submission order).
  */
 typedef struct ifl_server_info {
   size_t budget;          /* hbm_budget_bytes of ifl_server_create */

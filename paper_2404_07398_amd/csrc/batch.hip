@@ -1124,7 +1124,9 @@ int batch_lanes_per_row(int R, bool mixed) {
 
 ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
   const size_t nr = (size_t)bm.n_pad * R;
-  const int chunk = bm.chunk == 8 ? 8 : 4;
+  // the x update (kb_xupdate<T, R, kChunk>) reads kChunk direction buffers
+  if (bm.chunk != kChunk) return fail(IFL_EINVAL, "tile chunk length differs from the kernels' kChunk");
+  const int chunk = bm.chunk;
   ifl_status st;
   std::vector<void*> vecs;  // the precision's vectors, zeroed below
   size_t es = 0;

@@ -116,11 +116,14 @@ void finish_ticket(ifl_ticket* t, ifl_status st, const std::string& msg) {
 
 // Admit queued requests of this worker whose footprint fits the budget
 // (oldest first; a request that does not fit blocks the ones behind it so
-// that large requests are not starved).
+// that large requests are not starved), while fewer than 2 R of the
+// worker's admitted columns wait for a slot: a mesh whose columns run slowly
+// does not take the whole budget for requests it cannot start yet.
 void admit(Worker* wk, std::vector<ifl_ticket*>* admitted) {
   ifl_server* s = wk->srv;
   std::lock_guard<std::mutex> lk(s->mu);
-  while (!wk->queue.empty()) {
+  size_t waiting = wk->pending.size();
+  while (!wk->queue.empty() && waiting < 2 * (size_t)wk->R) {
     ifl_ticket* t = wk->queue.front();
     // one request is always admitted when none is in flight, so a request
     // larger than the budget still runs (alone)
@@ -132,6 +135,7 @@ void admit(Worker* wk, std::vector<ifl_ticket*>* admitted) {
     s->peak_in_flight = std::max(s->peak_in_flight, s->in_flight);
     wk->queue.pop_front();
     admitted->push_back(t);
+    waiting += (size_t)t->n_scales;
   }
 }
 
@@ -252,9 +256,11 @@ ifl_status run_worker(Worker* wk) {
       if (st != IFL_OK) return st;
     }
     if (active == 0) {
+      // nothing to run: wait for a submit, a release of memory elsewhere or
+      // a cancel (a queued request that does not fit yet must not spin)
       std::unique_lock<std::mutex> lk(wk->srv->mu);
       if (wk->srv->stop && wk->queue.empty()) return IFL_OK;
-      if (wk->queue.empty()) wk->srv->cv.wait_for(lk, std::chrono::milliseconds(50));
+      wk->srv->cv.wait_for(lk, std::chrono::milliseconds(50));
       continue;
     }
     // 3. iterate
@@ -310,7 +316,7 @@ ifl_status run_worker_shifted(Worker* wk) {
     if (wk->pending.empty()) {
       std::unique_lock<std::mutex> lk(wk->srv->mu);
       if (wk->srv->stop && wk->queue.empty()) return IFL_OK;
-      if (wk->queue.empty()) wk->srv->cv.wait_for(lk, std::chrono::milliseconds(50));
+      wk->srv->cv.wait_for(lk, std::chrono::milliseconds(50));
       continue;
     }
     const Column col = wk->pending.front();

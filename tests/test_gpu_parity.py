@@ -436,18 +436,20 @@ def _level8_biharmonic():
     return _L8_N2
 
 
-@pytest.mark.parametrize("precision,batch", [(0, 1), (1, 0)])
-def test_full_size_level8_biharmonic_certified(ifl, precision, batch):
+@pytest.mark.parametrize("precision,batch,shifted", [(0, 1, False), (1, 0, False), (0, 1, True), (1, 1, True)])
+def test_full_size_level8_biharmonic_certified(ifl, precision, batch, shifted):
     """Level-8 icosphere (655,362 vertices), 30% land mask, n = 2 (the
     biharmonic filter, 20 scales from 32h to 2h), each precision against
-    its own bar at three sampled scales. At the largest scale (32h, cond(S)
-    ~ 1e5) the residual certificate ||r|| / (min(A) ||x||) is too loose to
-    prove 1e-11, so that column is compared element by element with the
-    oracle's direct solve of the same system; the other two are certified
-    with the oracle's own K_2 = K M^-1 K."""
+    its own bar at three sampled scales, by Jacobi-PCG on K_2 and by the
+    shifted first-order solves. At the largest scale (32h, cond(S) ~ 1e5)
+    the residual certificate ||r|| / (min(A) ||x||) is too loose to prove
+    1e-11, so that column is compared element by element with the oracle's
+    direct solve of the same system; the other two are certified with the
+    oracle's own K_2 = K M^-1 K."""
     d = _level8_biharmonic()
     s, phi, ks, op = d["s"], d["phi"], d["ks"], d["op"]
-    h = _prep(ifl, s, n=2, precision=precision, batch=batch)
+    solver = ifl.IFL_SOLVER_SHIFTED if shifted else ifl.IFL_SOLVER_KN
+    h = _prep(ifl, s, n=2, precision=precision, batch=batch, solver=solver)
     out, stats = h.filter(phi, ks)
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j, k in enumerate(ks):
@@ -457,7 +459,7 @@ def test_full_size_level8_biharmonic_certified(ifl, precision, batch):
         else:
             err = _oracle_certificate(op, phi, k, out[0, j])
             what = "certified_err<="
-        print(f"L8 n=2 precision={precision} batch={batch} k={k:.3e} {what} {err:.2e} "
+        print(f"L8 n=2 precision={precision} batch={batch} shifted={shifted} k={k:.3e} {what} {err:.2e} "
               f"it={stats[j].iterations} upd={stats[j].refinements} t={stats[j].seconds:.3f}s")
         assert stats[j].status == 0
         assert err <= tol
