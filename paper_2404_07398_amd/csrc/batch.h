@@ -50,7 +50,17 @@ struct BatchMatrix {
   int64_t field_len = 0;
   int G = 1;   // blocks of the kernels that gather (SpMV, replacement, start, finish)
   int Gu = 1;  // blocks of the streaming update kernel
-  int head = 6;  // off-diagonal entries per row in the gathering kernels' pipelined head (6, 12 or 20)
+  int head = 6;  // off-diagonal entries per row in the gathering kernels' pipelined head (6, 12 or 20;
+                 // with pairs: blocks per block row, 3, 6 or 12)
+  // two-component operators: the gathering kernels run on 2 x 2 blocks
+  // (each lane handles both component rows of a block row and gathers a
+  // neighbour's two components together); the vectors keep their layout
+  bool pairs = false;
+  int64_t nb = 0, nb_slices = 0, pnnz = 0;  // block rows, slices of 64 of them, stored block entries
+  const int64_t* psptr = nullptr;
+  const int32_t* pcol = nullptr;
+  const double* pval64 = nullptr;  // 4 per entry
+  const float* pval32 = nullptr;
   int chunk = 4;  // iterations per chunk (chunk_for_order of the handle)
 };
 

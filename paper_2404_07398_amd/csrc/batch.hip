@@ -93,6 +93,12 @@ struct BMat {
   const double* kdiag;
   const double* mass;
   const int64_t* entity;
+  // 2 x 2-block sliced ELL of a two-component operator (pair kernels)
+  int64_t nb, nb_slices;
+  const int64_t* psptr;
+  const int32_t* pcol;
+  const double* pval64;
+  const float* pval32;
 };
 
 template <typename T>
@@ -118,6 +124,13 @@ template <>
 __device__ __forceinline__ const double* bval<double>(const BMat& m) { return m.val64; }
 template <>
 __device__ __forceinline__ const float* bval<float>(const BMat& m) { return m.val32; }
+
+template <typename T>
+__device__ __forceinline__ const T* pval(const BMat& m);
+template <>
+__device__ __forceinline__ const double* pval<double>(const BMat& m) { return m.pval64; }
+template <>
+__device__ __forceinline__ const float* pval<float>(const BMat& m) { return m.pval32; }
 
 // partial-sum slot of this block
 __device__ __forceinline__ int lblock(int) { return blockIdx.x; }
@@ -643,6 +656,437 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
   }
 }
 
+// ------------------------------------------------------------ 2 x 2 blocks
+// Pair forms of kb_iter and kb_residual for two-component operators (rows
+// 2b and 2b + 1 are the two components of block row b). A task is RPW block
+// rows; a lane handles its C columns of both rows of a block row, and a
+// neighbour block's two rows are gathered together: two 16-byte loads per
+// gathered vector and neighbour for the pair of rows, where the row forms
+// make four (each row gathers both components of every neighbour). The
+// per-row arithmetic is that of the row forms; a block row's sums run over
+// its blocks in increasing block column, component 2j before 2j + 1, the
+// order of the row forms' sorted entries. The vectors keep their row
+// layout, so the streaming kernels are shared.
+
+// Blocks k_begin .. w - 1 of a block row in steps of U (past the pipelined
+// head): a[r][c] += sum_blocks v[2r] comb(x(2j)) + v[2r + 1] comb(x(2j + 1)).
+// Entries past the row's end are in bounds (next slice, or the zero tail)
+// and their values are replaced by 0.
+template <typename V, typename T, int R, int C, bool TWO, typename Comb, int U>
+__device__ __forceinline__ void pair_product(const BMat& m, const V* __restrict__ val, int64_t base, int w,
+                                             int64_t l, int j0, const T* __restrict__ x0,
+                                             const T* __restrict__ x1, Comb comb, T (&a)[2][C], int k_begin) {
+  for (int k0 = k_begin; k0 < w; k0 += U) {
+    int32_t cu[U];
+    Pack<V, 4> vu[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = base + (int64_t)(k0 + u) * kW + l;
+      cu[u] = m.pcol[e];
+      vu[u] = vload<V, 4>(val + 4 * e);
+    }
+    Pack<T, C> g0[U][2], g1[U][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t off = (int64_t)cu[u] * (2 * R) + j0;
+      g0[u][0] = vload<T, C>(x0 + off);
+      g0[u][1] = vload<T, C>(x0 + off + R);
+      if constexpr (TWO) {
+        g1[u][0] = vload<T, C>(x1 + off);
+        g1[u][1] = vload<T, C>(x1 + off + R);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = k0 + u < w;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const T xu = comb(c, g0[u][0].v[c], TWO ? g1[u][0].v[c] : (T)0);
+        const T xv = comb(c, g0[u][1].v[c], TWO ? g1[u][1].v[c] : (T)0);
+        a[0][c] = fma(in ? (T)vu[u].v[0] : (T)0, xu, a[0][c]);
+        a[0][c] = fma(in ? (T)vu[u].v[1] : (T)0, xv, a[0][c]);
+        a[1][c] = fma(in ? (T)vu[u].v[2] : (T)0, xu, a[1][c]);
+        a[1][c] = fma(in ? (T)vu[u].v[3] : (T)0, xv, a[1][c]);
+      }
+    }
+  }
+}
+
+// The FP64 residual's two sums over blocks k_begin .. w - 1: a += v x,
+// aa += |v| |x| (pair form of row_product_abs2).
+template <int R, int C, int U>
+__device__ __forceinline__ void pair_product_abs2(const BMat& m, int64_t base, int w, int64_t l, int j0,
+                                                  const double* __restrict__ x, double (&a)[2][C],
+                                                  double (&aa)[2][C], int k_begin) {
+  for (int k0 = k_begin; k0 < w; k0 += U) {
+    int32_t cu[U];
+    Pack<double, 4> vu[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = base + (int64_t)(k0 + u) * kW + l;
+      cu[u] = m.pcol[e];
+      vu[u] = vload<double, 4>(m.pval64 + 4 * e);
+    }
+    Pack<double, C> g[U][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t off = (int64_t)cu[u] * (2 * R) + j0;
+      g[u][0] = vload<double, C>(x + off);
+      g[u][1] = vload<double, C>(x + off + R);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = k0 + u < w;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const double v0 = in ? vu[u].v[2 * r] : 0.0, v1 = in ? vu[u].v[2 * r + 1] : 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          a[r][c] = fma(v0, g[u][0].v[c], a[r][c]);
+          a[r][c] = fma(v1, g[u][1].v[c], a[r][c]);
+          aa[r][c] = fma(fabs(v0), fabs(g[u][0].v[c]), aa[r][c]);
+          aa[r][c] = fma(fabs(v1), fabs(g[u][1].v[c]), aa[r][c]);
+        }
+      }
+    }
+  }
+}
+
+// kb_iter on 2 x 2 blocks (same forms, buffers and partials).
+template <typename T, int R, bool FUSED, int H>
+__global__ __launch_bounds__(kB) void kb_iter2(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
+                                               int k, int L) {
+  using Gm = Geo<T, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
+  constexpr int NQ = FUSED ? 4 : 3;
+  __shared__ double lds[NQ * kWpb * R];
+  const int lane = threadIdx.x % kW;
+  const int j0 = (lane % LPR) * C, bsub = lane / LPR;
+  T alpha[C], beta[C], cc[C];
+  double c64[C];
+  bool on[C];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const BSlot& sl = slots[j0 + c];
+    on[c] = live(sl);
+    alpha[c] = on[c] ? (T)sl.alpha : (T)0;
+    beta[c] = on[c] ? (T)sl.beta : (T)0;
+    cc[c] = (T)sl.c;
+    c64[c] = sl.c;
+    any |= on[c];
+  }
+  const int bin = FUSED ? ((k - 1) & 1) : 0, bout = FUSED ? (k & 1) : 0;
+  const T* __restrict__ zin = v.z[bin];
+  const T* __restrict__ uin = v.u[bin];
+  T* __restrict__ zout = v.z[bout];
+  T* __restrict__ uout = v.u[bout];
+  const T* __restrict__ pin = v.p[(k + L - 1) % L];
+  T* __restrict__ pout = v.p[k];
+  const T* __restrict__ g1src = FUSED ? uin : pin;
+  const T* __restrict__ val = pval<T>(m);
+  const auto comb = [&](int c, T g0, T g1) { return FUSED ? fma(-alpha[c], g1, g0) : fma(beta[c], g1, g0); };
+  double acc[NQ][C] = {};
+  if (any) {
+    const Walk wk = task_walk(m.nb_slices * LPR, G);
+    const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
+    const int64_t last_slice = m.nb_slices - 1;
+    const int64_t last_row = m.n_slices * kW - 1;  // vectors, mass and diagonal hold n_slices * 64 rows
+    auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
+    int32_t cu[H];
+    Pack<T, 4> vu[H];
+    Pack<T, C> zi[2], ui[2], pi[2];
+    double mi[2], kd[2];
+    int64_t base, nb, ne;
+    int w;
+    auto fetch_idx = [&](int64_t t, int64_t sb) {
+      const int64_t l = (t * RPW + bsub) % kW;
+#pragma unroll
+      for (int u = 0; u < H; ++u) cu[u] = m.pcol[sb + (int64_t)u * kW + l];
+    };
+    auto fetch_rest = [&](int64_t t, int64_t sb) {
+      const int64_t brow = min(t * RPW + bsub, m.nb_slices * kW - 1), l = brow % kW;
+#pragma unroll
+      for (int u = 0; u < H; ++u) vu[u] = vload<T, 4>(val + 4 * (sb + (int64_t)u * kW + l));
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int64_t row = min(2 * brow + r, last_row), idx = row * R + j0;
+        zi[r] = vload<T, C>(zin + idx);
+        pi[r] = vload<T, C>(pin + idx);
+        if constexpr (FUSED) ui[r] = vload<T, C>(uin + idx);
+        mi[r] = m.mass[row];
+        kd[r] = m.kdiag[row];
+      }
+    };
+    {
+      const int64_t s0 = slice_of(first);
+      base = wave_uniform(m.psptr[s0]);
+      w = (int)((wave_uniform(m.psptr[s0 + 1]) - base) / kW);
+      fetch_idx(first, base);
+      fetch_rest(first, base);
+      const int64_t s1 = slice_of(first + stride);
+      nb = m.psptr[s1];
+      ne = m.psptr[s1 + 1];
+    }
+    for (int64_t t = first; t < end; t += stride) {
+      const int64_t brow = t * RPW + bsub;
+      const int64_t self = min(brow, m.nb - 1);
+      // (a) gathers of this task: both rows of every neighbour block
+      Pack<T, C> g0[H][2], g1[H][2];
+#pragma unroll
+      for (int u = 0; u < H; ++u) {
+        const int64_t off = (u < w ? (int64_t)cu[u] : self) * (2 * R) + j0;
+        g0[u][0] = vload<T, C>(zin + off);
+        g0[u][1] = vload<T, C>(zin + off + R);
+        g1[u][0] = vload<T, C>(g1src + off);
+        g1[u][1] = vload<T, C>(g1src + off + R);
+      }
+      const int64_t cbase = base;
+      const int cw = w;
+      // (b) slice bounds two tasks ahead, (c) indices of the next task
+      const int64_t tn = t + stride < end ? t + stride : t;
+      const int64_t s2 = slice_of(t + 2 * stride);
+      const int64_t nb2 = m.psptr[s2], ne2 = m.psptr[s2 + 1];
+      base = wave_uniform(nb);
+      w = (int)((wave_uniform(ne) - base) / kW);
+      fetch_idx(tn, base);
+      nb = nb2;
+      ne = ne2;
+      // (d) the two rows of this block row
+      T a[2][C] = {};
+#pragma unroll
+      for (int u = 0; u < H; ++u) {
+        const bool in = u < cw;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const T xu = comb(c, g0[u][0].v[c], g1[u][0].v[c]);
+          const T xv = comb(c, g0[u][1].v[c], g1[u][1].v[c]);
+          a[0][c] = fma(in ? vu[u].v[0] : (T)0, xu, a[0][c]);
+          a[0][c] = fma(in ? vu[u].v[1] : (T)0, xv, a[0][c]);
+          a[1][c] = fma(in ? vu[u].v[2] : (T)0, xu, a[1][c]);
+          a[1][c] = fma(in ? vu[u].v[3] : (T)0, xv, a[1][c]);
+        }
+      }
+      if (cw > H)
+        pair_product<T, T, R, C, true, decltype(comb), H>(m, val, cbase, cw, brow % kW, j0, zin, g1src, comb, a,
+                                                           H);
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int64_t row = 2 * brow + r;
+        const bool real = row < m.n;
+        const int64_t idx = row * R + j0;
+        Pack<T, C> zn, pn, un;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const T d = real ? (T)(mi[r] + c64[c] * kd[r]) : (T)1;
+          zn.v[c] = FUSED ? fma(-alpha[c], ui[r].v[c], zi[r].v[c]) : zi[r].v[c];
+          pn.v[c] = fma(beta[c], pi[r].v[c], zn.v[c]);
+          const T su = zn.v[c] + (cc[c] * a[r][c]) / d;
+          un.v[c] = FUSED ? fma(beta[c], ui[r].v[c], su) : pn.v[c] + (cc[c] * a[r][c]) / d;
+          const double dd = (double)d, uu = (double)un.v[c], zz = (double)zn.v[c];
+          const bool use = on[c] && real;
+          acc[0][c] += use ? dd * (double)pn.v[c] * uu : 0.0;
+          acc[1][c] += use ? dd * zz * uu : 0.0;
+          acc[2][c] += use ? dd * uu * uu : 0.0;
+          if constexpr (FUSED) acc[NQ - 1][c] += use ? dd * zz * zz : 0.0;
+        }
+        if (real) {
+          vstore<T, C>(pout + idx, pn);
+          vstore<T, C>(uout + idx, un);
+          if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
+        }
+      }
+      // (e) values and own rows of the next task
+      fetch_rest(tn, base);
+    }
+  }
+  double tot[NQ];
+  col_sum<R, C, NQ>(acc, lds, tot);
+  if (threadIdx.x < R) {
+    const int lb = lblock(G);
+    part[(Q_PQ * R + threadIdx.x) * Gp + lb] = tot[0];
+    part[(Q_ZU * R + threadIdx.x) * Gp + lb] = tot[1];
+    part[(Q_UU * R + threadIdx.x) * Gp + lb] = tot[2];
+    if constexpr (FUSED) part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[NQ - 1];
+  }
+}
+
+// kb_residual on 2 x 2 blocks (same START / REPLACE forms and partials).
+template <typename T, int R, bool START, int H>
+__global__ __launch_bounds__(kB) void kb_residual2(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+                                                   int Gp, uint64_t mask, SlotScales cs, int L) {
+  using Gm = Geo<T, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
+  __shared__ double lds[3 * kWpb * R];
+  const int lane = threadIdx.x % kW;
+  const int j0 = (lane % LPR) * C, bsub = lane / LPR;
+  bool on[C];
+  double cc[C];
+  bool any = false, all = true;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    if constexpr (START) {
+      on[c] = ((mask >> (j0 + c)) & 1ull) != 0;
+      cc[c] = cs.c[j0 + c];
+    } else {
+      on[c] = live(slots[j0 + c]);
+      cc[c] = slots[j0 + c].c;
+    }
+    any |= on[c];
+    all &= on[c];
+  }
+  const double* __restrict__ src = START ? v.phi : v.x;
+  T* __restrict__ pprev = v.p[L - 1];
+  const Ident ident;
+  double acc[3][C] = {};
+  if (any) {
+    const Walk wk = task_walk(m.nb_slices * LPR, G);
+    const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
+    const int64_t last_slice = m.nb_slices - 1;
+    const int64_t last_row = m.n_slices * kW - 1;
+    auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
+    int32_t cu[H];
+    Pack<double, 4> vu[H];
+    Pack<double, C> ph[2], xv[2];
+    double mi[2], kd[2];
+    int64_t base, nb, ne;
+    int w;
+    auto fetch_idx = [&](int64_t t, int64_t sb) {
+      const int64_t l = (t * RPW + bsub) % kW;
+#pragma unroll
+      for (int u = 0; u < H; ++u) cu[u] = m.pcol[sb + (int64_t)u * kW + l];
+    };
+    auto fetch_rest = [&](int64_t t, int64_t sb) {
+      const int64_t brow = min(t * RPW + bsub, m.nb_slices * kW - 1), l = brow % kW;
+#pragma unroll
+      for (int u = 0; u < H; ++u) vu[u] = vload<double, 4>(m.pval64 + 4 * (sb + (int64_t)u * kW + l));
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int64_t row = min(2 * brow + r, last_row), idx = row * R + j0;
+        ph[r] = vload<double, C>(v.phi + idx);
+        if constexpr (!START) xv[r] = vload<double, C>(v.x + idx);
+        mi[r] = m.mass[row];
+        kd[r] = m.kdiag[row];
+      }
+    };
+    {
+      const int64_t s0 = slice_of(first);
+      base = wave_uniform(m.psptr[s0]);
+      w = (int)((wave_uniform(m.psptr[s0 + 1]) - base) / kW);
+      fetch_idx(first, base);
+      fetch_rest(first, base);
+      const int64_t s1 = slice_of(first + stride);
+      nb = m.psptr[s1];
+      ne = m.psptr[s1 + 1];
+    }
+    for (int64_t t = first; t < end; t += stride) {
+      const int64_t brow = t * RPW + bsub;
+      const int64_t self = min(brow, m.nb - 1);
+      Pack<double, C> gx[H][2];
+#pragma unroll
+      for (int u = 0; u < H; ++u) {
+        const int64_t off = (u < w ? (int64_t)cu[u] : self) * (2 * R) + j0;
+        gx[u][0] = vload<double, C>(src + off);
+        gx[u][1] = vload<double, C>(src + off + R);
+      }
+      const int64_t cbase = base;
+      const int cw = w;
+      const int64_t tn = t + stride < end ? t + stride : t;
+      const int64_t s2 = slice_of(t + 2 * stride);
+      const int64_t nb2 = m.psptr[s2], ne2 = m.psptr[s2 + 1];
+      base = wave_uniform(nb);
+      w = (int)((wave_uniform(ne) - base) / kW);
+      fetch_idx(tn, base);
+      nb = nb2;
+      ne = ne2;
+      double a[2][C] = {}, aa[2][C] = {};  // sum val x, sum |val| |x| (REPLACE)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+          const bool in = u < cw;
+          const double v0 = in ? vu[u].v[2 * r] : 0.0, v1 = in ? vu[u].v[2 * r + 1] : 0.0;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            a[r][c] = fma(v0, gx[u][0].v[c], a[r][c]);
+            a[r][c] = fma(v1, gx[u][1].v[c], a[r][c]);
+            if constexpr (!START) {
+              aa[r][c] = fma(fabs(v0), fabs(gx[u][0].v[c]), aa[r][c]);
+              aa[r][c] = fma(fabs(v1), fabs(gx[u][1].v[c]), aa[r][c]);
+            }
+          }
+        }
+      if (cw > H) {
+        if constexpr (START)
+          pair_product<double, double, R, C, false, decltype(ident), H>(m, m.pval64, cbase, cw, brow % kW, j0, src,
+                                                                         nullptr, ident, a, H);
+        else
+          pair_product_abs2<R, C, H>(m, cbase, cw, brow % kW, j0, src, a, aa, H);
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int64_t row = 2 * brow + r;
+        const bool real = row < m.n;
+        const int64_t idx = row * R + j0;
+        if constexpr (START) {
+          if (real) {
+            Pack<double, C> xo = ph[r];
+            Pack<T, C> zo, po = {};
+            if (!all) {
+              xo = vload<double, C>(v.x + idx);
+              zo = vload<T, C>(v.z[0] + idx);
+              po = vload<T, C>(pprev + idx);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+              if (!on[c]) continue;
+              const double r64 = -cc[c] * (kd[r] * ph[r].v[c] + a[r][c]);
+              const T rt = (T)r64;
+              const T d = (T)(mi[r] + cc[c] * kd[r]);
+              xo.v[c] = ph[r].v[c];
+              zo.v[c] = rt / d;
+              po.v[c] = (T)0;
+              acc[0][c] += (double)rt * (double)zo.v[c];
+              acc[1][c] += r64 * r64;
+              acc[2][c] += (mi[r] * ph[r].v[c]) * (mi[r] * ph[r].v[c]);
+            }
+            vstore<double, C>(v.x + idx, xo);
+            vstore<T, C>(v.z[0] + idx, zo);
+            vstore<T, C>(pprev + idx, po);
+          }
+        } else {
+          Pack<T, C> zv;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const double xf = xv[r].v[c];
+            const double r64 = mi[r] * (ph[r].v[c] - xf) - cc[c] * (kd[r] * xf + a[r][c]);
+            const T rt = (T)r64;
+            const T d = (T)(mi[r] + cc[c] * kd[r]);
+            zv.v[c] = rt / d;
+            if (on[c] && real) {
+              const double mag =
+                  fabs(mi[r] * ph[r].v[c]) + fabs(mi[r] * xf) + cc[c] * (fabs(kd[r] * xf) + aa[r][c]);
+              acc[0][c] += (double)rt * (double)zv.v[c];
+              acc[1][c] += r64 * r64;
+              acc[2][c] += mag * mag;
+            }
+          }
+          if (real) vstore<T, C>(v.z[0] + idx, zv);
+        }
+      }
+      fetch_rest(tn, base);
+    }
+  }
+  double tot[3];
+  col_sum<R, C, 3>(acc, lds, tot);
+  if (threadIdx.x < R) {
+    const int lb = lblock(G);
+    part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
+    part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
+    part[((START ? Q_BB : Q_FL) * R + threadIdx.x) * Gp + lb] = tot[2];
+  }
+}
+
 // End of a column: partials of sum M x^2 (kb_out writes x out). A column
 // stops right after a replacement, whose FP64 true residual is that of this
 // very x, so no residual is formed here.
@@ -1007,13 +1451,39 @@ struct LaunchH {
   }
 };
 
+// the pair kernels of a two-component operator, head of H blocks
+template <int R, int H>
+struct LaunchP {
+  template <typename T>
+  static void iter(const BMat& m, BatchWork& w, Grids g, hipStream_t s, int k) {
+    if (k == 0) kb_iter2<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    else kb_iter2<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+  }
+  template <typename T>
+  static void replace(const BMat& m, BatchWork& w, Grids g, hipStream_t s) {
+    kb_residual2<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, 0ull, SlotScales{},
+                                                     w.chunk);
+  }
+  template <typename T>
+  static void start(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs) {
+    kb_residual2<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, mask, cs, w.chunk);
+  }
+};
+
 template <int R>
 struct Launch {
+  // the gathering kernels for the matrix's form and head class
   template <typename T, typename F>
-  static void by_head(int head, F f) {
-    if (head <= 6) f(LaunchH<R, 6>{});
-    else if (head <= 12) f(LaunchH<R, 12>{});
-    else f(LaunchH<R, 20>{});
+  static void by_head(const BMat& m, int head, F f) {
+    if (m.psptr) {
+      f(LaunchP<R, 6>{});
+    } else if (head <= 6) {
+      f(LaunchH<R, 6>{});
+    } else if (head <= 12) {
+      f(LaunchH<R, 12>{});
+    } else {
+      f(LaunchH<R, 20>{});
+    }
   }
   // iteration k (0..L-1) of a chunk of L: one fused iteration kernel and its
   // finalizer; the last one also applies the chunk's x update and the FP64
@@ -1023,12 +1493,12 @@ struct Launch {
   template <typename T>
   static void step(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k, int head) {
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
-    by_head<T>(head, [&](auto L) { L.template iter<T>(m, w, g, s, k); });
+    by_head<T>(m, head, [&](auto L) { L.template iter<T>(m, w, g, s, k); });
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
     kf_step<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
     if (k == w.chunk - 1) {
       kb_xupdate<T, R, kChunk><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
-      by_head<T>(head, [&](auto L) { L.template replace<T>(m, w, g, s); });
+      by_head<T>(m, head, [&](auto L) { L.template replace<T>(m, w, g, s); });
       kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
     }
   }
@@ -1038,8 +1508,8 @@ struct Launch {
   }
   static void init(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs,
                    double rtol, int head) {
-    if (w.mixed) by_head<float>(head, [&](auto L) { L.template start<float>(m, w, g, s, mask, cs); });
-    else by_head<double>(head, [&](auto L) { L.template start<double>(m, w, g, s, mask, cs); });
+    if (w.mixed) by_head<float>(m, head, [&](auto L) { L.template start<float>(m, w, g, s, mask, cs); });
+    else by_head<double>(m, head, [&](auto L) { L.template start<double>(m, w, g, s, mask, cs); });
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
   }
   static void finish(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const OutPtrs& out) {
@@ -1200,8 +1670,9 @@ static Grids grids(const BatchMatrix& bm) { return Grids{bm.G, bm.Gu, std::max(b
 static bool same_grids(const BatchMatrix& bm, const BatchWork& w) { return bm.G == w.G && bm.Gu == w.Gu; }
 
 static BMat bmat(const BatchMatrix& bm) {
-  return BMat{bm.n, bm.n_slices, bm.row_of, bm.field_len, bm.sptr, bm.col, bm.val64, bm.val32, bm.kdiag, bm.mass,
-              bm.entity};
+  return BMat{bm.n,     bm.n_slices,  bm.row_of, bm.field_len, bm.sptr, bm.col,    bm.val64,
+              bm.val32, bm.kdiag,     bm.mass,   bm.entity,    bm.nb,   bm.nb_slices, bm.psptr,
+              bm.pcol,  bm.pval64,    bm.pval32};
 }
 
 ifl_status batch_clear_flag(BatchWork& w, hipStream_t s) {
@@ -1267,6 +1738,9 @@ ifl_status batch_init(const BatchMatrix& bm, BatchWork& w, uint64_t mask, const 
 
 double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, int live) {
   const double vb = mixed ? 4.0 : 8.0;
+  // pair kernels: block entries (index + four values) over slices of block rows
+  if (bm.pairs)
+    return (double)bm.pnnz * (4.0 + 4.0 * vb) + 8.0 * (bm.nb_slices + 1) + 16.0 * bm.n + 6.0 * vb * bm.n * live;
   return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 6.0 * vb * bm.n * live;
 }
 

@@ -99,6 +99,14 @@ struct DevMatrix {
   int64_t field_len = 0;
   double mass_sum = 0.0;
   int head = 6;  // entries per row the gathering kernels load together (6, 12 or 20)
+  // two-component operators: the 2 x 2-block sliced ELL of the batched
+  // gathering kernels (PairPack); psptr == nullptr otherwise
+  int64_t nb = 0, nb_slices = 0, pnnz = 0;
+  int64_t* psptr = nullptr;
+  int32_t* pcol = nullptr;
+  double* pval64 = nullptr;
+  float* pval32 = nullptr;
+  int phead = 6;  // blocks per block row in the pipelined head
 };
 
 struct ColWork {
@@ -1272,6 +1280,36 @@ ifl_status device_create(Handle* h) {
     const int v = std::atoi(e);
     if (v == 6 || v == 12 || v == 20) m.head = v;
   }
+  // two-component operators with wide rows: 2 x 2 blocks for the batched
+  // gathering kernels, a head of 6 blocks (wider rows finish in unpipelined
+  // steps of 6; a head of 12 blocks would spill registers). Measured on the
+  // level-8 sphere: the vertex vectors (6 neighbour blocks a block row)
+  // iterate 3-4% faster in blocks than in rows; the cell vectors (3
+  // neighbour blocks) 2-5% slower, so operators whose rows hold at most 3
+  // blocks in 90% of the slices keep the row kernels.
+  {
+    PairPack pp;
+    if (pack_pairs(h->op, &pp)) {
+      std::vector<int64_t> widths((size_t)pp.n_slices);
+      for (int64_t q = 0; q < pp.n_slices; ++q) widths[(size_t)q] = (pp.slice_ptr[q + 1] - pp.slice_ptr[q]) / kWave;
+      int64_t w90 = 0;
+      if (!widths.empty()) {
+        const size_t at = (widths.size() * 9) / 10;
+        std::nth_element(widths.begin(), widths.begin() + at, widths.end());
+        w90 = widths[at];
+      }
+      if (w90 > 3) {
+        m.nb = pp.nb;
+        m.nb_slices = pp.n_slices;
+        m.pnnz = pp.slice_ptr.back();
+        m.phead = 6;
+        std::vector<float> p32(pp.val.begin(), pp.val.end());
+        if ((st = upload(&m.psptr, pp.slice_ptr)) || (st = upload(&m.pcol, pp.col)) ||
+            (st = upload(&m.pval64, pp.val)) || (st = upload(&m.pval32, p32)))
+          return st;
+      }
+    }
+  }
   // orders >= 2: the first-order operator for the shifted solves
   if (h->op.order >= 2 && !h->op.k1_col.empty()) {
     SellPack s1;
@@ -1319,6 +1357,9 @@ void device_destroy(Handle* h) {
   if (d->own_stream) (void)hipStreamSynchronize(d->own_stream);
   DevMatrix& m = d->m;
   const ColWork& w = d->w;
+  void* pptrs[] = {m.psptr, m.pcol, m.pval64, m.pval32};
+  for (void* p : pptrs)
+    if (p) (void)hipFree(p);
   void* ptrs[] = {m.sptr,   m.col,    m.val64,  m.val32,  m.kdiag64, m.kdiag32, m.mass64,   m.entity,
                   m.row_of, w.x[0],   w.x[1],   w.z[0],   w.z[1],    w.u[0],    w.u[1],     w.p[0],
                   w.p[1],   w.d,      w.z32[0], w.z32[1], w.u32[0],  w.u32[1],  w.p32[0],   w.p32[1],
@@ -1815,6 +1856,17 @@ BatchMatrix batch_matrix(DeviceState* d, int R, bool mixed) {
   bm.field_len = m.field_len;
   bm.head = m.head;
   bm.chunk = chunk_for_order(d->order);
+  if (m.psptr) {
+    bm.pairs = true;
+    bm.nb = m.nb;
+    bm.nb_slices = m.nb_slices;
+    bm.pnnz = m.pnnz;
+    bm.psptr = m.psptr;
+    bm.pcol = m.pcol;
+    bm.pval64 = m.pval64;
+    bm.pval32 = m.pval32;
+    bm.head = m.phead;
+  }
   // a task is one wavefront's rows: 64 / lanes-per-row consecutive rows.
   // Defaults: the gathering kernels run one block per CU, so that the rows
   // in flight on an XCD form a band narrow enough for its L2 to keep the
@@ -1977,7 +2029,8 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
       d->prof_ms += ms;
       d->prof_launches += 1;
       d->prof_bytes += batch_spmv_bytes(bm, d->m.nnz_stored, mixed, live);
-      d->prof_kernel = std::string("kb_iter<") + (mixed ? "float, " : "double, ") + std::to_string(R) + ", true, " +
+      d->prof_kernel = std::string(bm.pairs ? "kb_iter2<" : "kb_iter<") + (mixed ? "float, " : "double, ") +
+                       std::to_string(R) + ", true, " +
                        std::to_string(bm.head) + ">";
     }
     uint64_t fin = 0;

@@ -68,6 +68,29 @@ void pack_sell(const HostOperator& op, SellPack* out);
 void pack_sell_csr(int64_t n, const std::vector<int64_t>& row_ptr, const std::vector<int32_t>& col,
                    const std::vector<double>& val, const std::vector<double>& mass, SellPack* out);
 
+// 2 x 2-block sliced ELL of a two-component operator (rows 2b and 2b + 1
+// are the two components of block row b, as the vector placements number
+// them): slices of 64 block rows; entry k of block row 64 s + l, at
+// slice_ptr[s] + 64 k + l, holds a block column j and the four couplings
+// (row 2b to 2j, row 2b to 2j + 1, row 2b + 1 to 2j, row 2b + 1 to 2j + 1)
+// at val[4 (slice_ptr[s] + 64 k + l) ..]. Block columns increase along a
+// block row; the diagonal of K_n is not stored (a block on the diagonal
+// keeps only the coupling of the two components, and exists only if that
+// coupling does); rows are padded to the slice's width with (block row,
+// zeros), and kSellTail zero entries follow the last slice.
+struct PairPack {
+  int64_t nb = 0;        // block rows
+  int64_t n_slices = 0;  // slices of 64 block rows
+  std::vector<int64_t> slice_ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;  // 4 per entry
+  int64_t stored_blocks = 0;  // blocks with a coupling (no padding)
+};
+
+// Packs op as 2 x 2 blocks; false (and out untouched) unless op has two
+// components.
+bool pack_pairs(const HostOperator& op, PairPack* out);
+
 // Zero entries appended after the last slice (32 entries x 64 lanes): a
 // kernel may load up to 32 entries past the end of any slice's rows without
 // a bounds check.

@@ -971,4 +971,67 @@ void pack_sell_csr(int64_t n, const std::vector<int64_t>& row_ptr, const std::ve
 
 void pack_sell(const HostOperator& op, SellPack* out) { pack_sell_csr(op.n, op.row_ptr, op.col, op.val, op.mass, out); }
 
+bool pack_pairs(const HostOperator& op, PairPack* out) {
+  if (op.n_components != 2 || op.n % 2 != 0) return false;
+  const int64_t nb = op.n / 2, ns = (nb + 63) / 64;
+  // the blocks of block row b in increasing block column: the CSR rows 2b
+  // and 2b + 1 (sorted columns) merged; emit(j, v) for every block with at
+  // least one off-diagonal entry
+  auto blocks = [&](int64_t b, auto&& emit) {
+    int64_t e0 = op.row_ptr[2 * b], e0e = op.row_ptr[2 * b + 1];
+    int64_t e1 = op.row_ptr[2 * b + 1], e1e = op.row_ptr[2 * b + 2];
+    while (e0 < e0e || e1 < e1e) {
+      const int64_t j0 = e0 < e0e ? op.col[e0] / 2 : INT64_MAX, j1 = e1 < e1e ? op.col[e1] / 2 : INT64_MAX;
+      const int64_t j = std::min(j0, j1);
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+      bool any = false;
+      for (; e0 < e0e && op.col[e0] / 2 == j; ++e0)
+        if (op.col[e0] != 2 * b) {
+          v[op.col[e0] % 2] = op.val[e0];
+          any = true;
+        }
+      for (; e1 < e1e && op.col[e1] / 2 == j; ++e1)
+        if (op.col[e1] != 2 * b + 1) {
+          v[2 + op.col[e1] % 2] = op.val[e1];
+          any = true;
+        }
+      if (any) emit((int32_t)j, v);
+    }
+  };
+  out->nb = nb;
+  out->n_slices = ns;
+  out->slice_ptr.assign(ns + 1, 0);
+  out->stored_blocks = 0;
+  std::vector<int32_t> width(ns, 0);
+  for (int64_t s = 0; s < ns; ++s) {
+    int32_t w = 0;
+    for (int64_t b = s * 64; b < std::min(nb, s * 64 + 64); ++b) {
+      int32_t len = 0;
+      blocks(b, [&](int32_t, const double*) { ++len; });
+      w = std::max(w, len);
+      out->stored_blocks += len;
+    }
+    width[s] = w;
+    out->slice_ptr[s + 1] = out->slice_ptr[s] + 64 * (int64_t)w;
+  }
+  out->col.assign(out->slice_ptr[ns] + kSellTail, 0);
+  out->val.assign(4 * (out->slice_ptr[ns] + kSellTail), 0.0);
+  for (int64_t s = 0; s < ns; ++s) {
+    for (int64_t l = 0; l < 64; ++l) {
+      const int64_t b = s * 64 + l;
+      const int32_t self = (int32_t)std::min(b, nb - 1);
+      int32_t k = 0;
+      if (b < nb)
+        blocks(b, [&](int32_t j, const double* v) {
+          const int64_t e = out->slice_ptr[s] + 64 * (int64_t)k + l;
+          out->col[e] = j;
+          for (int q = 0; q < 4; ++q) out->val[4 * e + q] = v[q];
+          ++k;
+        });
+      for (; k < width[s]; ++k) out->col[out->slice_ptr[s] + 64 * (int64_t)k + l] = self;
+    }
+  }
+  return true;
+}
+
 }  // namespace ifl

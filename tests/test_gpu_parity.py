@@ -404,8 +404,8 @@ def test_full_size_level8_vertex_vector_certified(ifl):
     for i in range(8):
         h.project_cells(cells[i], out=fields[i])
     out, stats = h.filter(fields, ks)
-    # interleaved vertex vectors: 12 entries a row, the 12-entry head
-    assert h.profile_kernel() == "kb_iter<float, 16, true, 12>"
+    # vertex vectors: the 2 x 2-block kernels, 6 neighbour blocks a block row
+    assert h.profile_kernel() == "kb_iter2<float, 16, true, 6>"
     op = O.vertex_vector_operator(s, 1)
     for f in (0, 7):
         b = O.project_cells_to_vertices(op, us[f])
@@ -567,6 +567,46 @@ def test_batched_cell_vector(ifl, precision):
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j in range(len(ks)):
         assert relative_l2(out[0, j], ref[j].reshape(-1)) <= tol
+    h.close()
+
+
+@pytest.mark.parametrize("placement", ["vertex_vector", "cell_vector"])
+def test_pair_kernels_match_single_column(ifl, placement):
+    """Vertex vectors run the 2 x 2-block gathering kernels in tiles
+    (kb_iter2 / kb_residual2; cell vectors, with 3 neighbour blocks, the row
+    kernels) and the row kernels in the single-column path: in FP64 both
+    converge to the same solutions (within the FP64 bar of each other), and
+    both to the oracle's."""
+    if placement == "vertex_vector":
+        s = _polar_dry_sphere(5)
+        pl = ifl.IFL_VERTEX_VECTOR
+        op = O.vertex_vector_operator(s, 1)
+        u = W.sphere_k3_velocity(s, 11, 12, n_waves=64)
+        ks = W.log_scales(s.h, 5)
+        ref = O.filter_vertex_vector(op, u, ks)
+    else:
+        s, _ = _sphere(5, 0.3)
+        pl = ifl.IFL_CELL_VECTOR
+        op = O.vector_operator(s, 1)
+        u = W.sphere_k3_velocity(s, 11, 12, n_waves=64)
+        ks = W.log_scales(s.h, 5)
+        ref = O.filter_vector(op, u, ks)
+    h = _prep(ifl, s, placement=pl, n=1, precision=ifl.IFL_FP64, batch=8, profile=1)
+    field = h.project_cells(u) if pl == ifl.IFL_VERTEX_VECTOR else u.reshape(-1)
+    tiles, st_t = h.filter(np.stack([field, field]), ks)
+    tile_kernel = "kb_iter2<double, 8, true, 6>" if pl == ifl.IFL_VERTEX_VECTOR else "kb_iter<double, 8, true, 6>"
+    assert h.profile_kernel() == tile_kernel
+    h.set_options(batch=1)
+    single, st_s = h.filter(field, ks)
+    assert h.profile_kernel().startswith("k_cg<double, false, ")
+    for j in range(len(ks)):
+        ref_j = np.asarray(ref[j]).reshape(-1)
+        for f in range(2):
+            d = relative_l2(tiles[f, j], single[0, j])
+            e = relative_l2(tiles[f, j], ref_j)
+            print(f"{placement} j={j} field={f} tiles-vs-single={d:.2e} tiles-vs-oracle={e:.2e} "
+                  f"it={st_t[f * len(ks) + j].iterations}/{st_s[j].iterations}")
+            assert d <= TOL_FP64 and e <= TOL_FP64
     h.close()
 
 
