@@ -83,6 +83,34 @@ struct Scalars {
   int32_t pad1[2];
 };
 
+// The fields of Scalars that a k_cg launch changes; the others pass through
+// from the copy it read. Keeping only these live (and re-reading the rest
+// when the copy is written) keeps the whole struct out of scratch memory.
+struct ScalarsMut {
+  double rr_ref, rr_last, rho;
+  int32_t iters, done, updates, mode, xbuf;
+  uint32_t fused_bits;
+};
+
+__device__ __forceinline__ ScalarsMut mut_of(const Scalars& s) {
+  return ScalarsMut{s.rr_ref, s.rr_last, s.rho, s.iters, s.done, s.updates, s.mode, s.xbuf, s.fused_bits};
+}
+
+// *dst = *src with the changed fields of m (one thread).
+__device__ __forceinline__ void put_scalars(Scalars* dst, const Scalars* src, const ScalarsMut& m) {
+  Scalars t = *src;
+  t.rr_ref = m.rr_ref;
+  t.rr_last = m.rr_last;
+  t.rho = m.rho;
+  t.iters = m.iters;
+  t.done = m.done;
+  t.updates = m.updates;
+  t.mode = m.mode;
+  t.xbuf = m.xbuf;
+  t.fused_bits = m.fused_bits;
+  *dst = t;
+}
+
 struct DevMatrix {
   int64_t n = 0, n_slices = 0, n_pad = 0;
   int64_t nnz_stored = 0;   // padded sliced-ELL entries
@@ -471,9 +499,9 @@ __global__ __launch_bounds__(kBlock) void k_cg(Mat m, CgVecs<T> v, const double*
   const bool leader = lb == 0 && threadIdx.x == 0;
   if (s0.done) {
     if (leader) {
-      Scalars s1 = s0;
+      ScalarsMut s1 = mut_of(s0);
       s1.fused_bits &= ~(1u << (launch & 31));
-      sc[nxt] = s1;
+      put_scalars(&sc[nxt], &sc[cur], s1);
     }
     return;
   }
@@ -485,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_cg(Mat m, CgVecs<T> v, const double*
     reduce_many<6>(src, G, q, lds6);
   }
   const double pq = q[0], zu = q[1], uu = q[2], rz = q[3], rr = q[4], fl = q[5];
-  Scalars s1 = s0;
+  ScalarsMut s1 = mut_of(s0);
   s1.fused_bits &= ~(1u << (launch & 31));
   int mode;
   double alpha = 0.0, beta = 0.0;
@@ -531,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_cg(Mat m, CgVecs<T> v, const double*
   }
   s1.mode = mode;
   if (mode == M_DONE) {
-    if (leader) sc[nxt] = s1;
+    if (leader) put_scalars(&sc[nxt], &sc[cur], s1);
     return;
   }
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
@@ -661,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void k_cg(Mat m, CgVecs<T> v, const double*
       part[pidx(cur, kRz) * G + lb] = acc[3];
       part[pidx(cur, kRr) * G + lb] = acc[4];
     }
-    if (lb == 0) sc[nxt] = s1;
+    if (lb == 0) put_scalars(&sc[nxt], &sc[cur], s1);
   }
 }
 
