@@ -381,7 +381,9 @@ def c2_leg(ifl):
     out = torch.empty((1, ks.size, h.field_length), dtype=torch.float64, device="cuda:0")
     for prec, batch, solver, name in ((ifl.IFL_MIXED, 0, 0, "mixed_batched"), (ifl.IFL_FP64, 1, 0, "fp64_single_column"),
                                       (ifl.IFL_FP64, 1, 1, "shifted_fp64_single_column"),
-                                      (ifl.IFL_MIXED, 1, 1, "shifted_mixed_single_column")):
+                                      (ifl.IFL_MIXED, 1, 1, "shifted_mixed_single_column"),
+                                      (ifl.IFL_FP64, 0, 1, "shifted_fp64_complex_tiles"),
+                                      (ifl.IFL_MIXED, 0, 1, "shifted_mixed_complex_tiles")):
         h.set_options(precision=prec, batch=batch, solver=solver)
         h.filter(phi, ks[:2], out=out[:, :2])
         torch.cuda.synchronize()
@@ -397,8 +399,11 @@ def c2_leg(ifl):
                                                        res["fp64_single_column"]["solves_per_s"], 3)
     res["speedup_shifted_fp64_vs_plain_fp64"] = round(res["shifted_fp64_single_column"]["solves_per_s"] /
                                                       res["fp64_single_column"]["solves_per_s"], 3)
+    res["speedup_shifted_mixed_tiles_vs_plain_fp64"] = round(res["shifted_mixed_complex_tiles"]["solves_per_s"] /
+                                                            res["fp64_single_column"]["solves_per_s"], 3)
     res["shifted"] = ("IFL_SOLVER_SHIFTED: S^-1 = Re (M + i c^(1/2) K)^-1 for n = 2, one complex-shifted "
-                      "first-order system per solve, Jacobi-COCG, one column at a time")
+                      "first-order system per solve, Jacobi-COCG, one column at a time (batch 1) or in complex "
+                      "tiles (auto width)")
     h.close()
     return res
 

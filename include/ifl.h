@@ -113,9 +113,12 @@ typedef struct ifl_options {
   int32_t profile;   /* 1 = time the SpMV launches with HIP events (ifl_profile_read) */
   int32_t graphs;    /* 1 = the batched engine replays each 4-iteration chunk of a tile as one captured
                         HIP graph (default), 0 = launches every kernel; results are bitwise equal */
-  int32_t solver;    /* IFL_SOLVER_KN (default) or IFL_SOLVER_SHIFTED (orders n >= 2; ifl_filter,
-                        ifl_spectrum and the serving engine then solve one column at a time whatever
-                        'batch' says; n = 1 uses IFL_SOLVER_KN) */
+  int32_t solver;    /* IFL_SOLVER_KN (default) or IFL_SOLVER_SHIFTED (orders n >= 2; n = 1 uses
+                        IFL_SOLVER_KN). With SHIFTED, ifl_filter and ifl_spectrum run n = 2 in complex
+                        tiles of 'batch' / 2 columns (batch 0: the library's width; scalar operators
+                        with first-order rows of at most 6 entries 90% of the time), other orders and
+                        batch = 1 one column at a time; the serving engine one column at a time.
+                        Tiles report the shifted system's FP64 true residual in rel_residual */
 } ifl_options;
 
 /* Per-solve statistics (one per field x scale). */

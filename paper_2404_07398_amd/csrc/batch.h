@@ -82,6 +82,10 @@ struct BatchWork {
   int R = 0;
   int G = 0, Gu = 0;  // grid sizes the work space (partial-sum array) was made for
   bool mixed = false;
+  // complex tile: columns 2j, 2j + 1 are the real and imaginary parts of
+  // one complex-shifted first-order system (Jacobi-COCG); slot 2j + 1
+  // carries the imaginary parts of the scalars, sigma in its c
+  bool cx = false;
   // p cycles through kChunk buffers, so that the directions of a whole
   // chunk are still there when x is updated at its last iteration; z and
   // u = diag(S)^-1 S p alternate between two buffers (an iteration gathers

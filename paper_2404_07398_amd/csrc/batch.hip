@@ -1087,6 +1087,470 @@ __global__ __launch_bounds__(kB) void kb_residual2(BMat m, BVec<T> v, const BSlo
   }
 }
 
+// ------------------------------------------------------- complex tiles
+// A complex tile (BatchWork::cx) runs Jacobi-COCG on complex-shifted
+// first-order systems (M + sigma K) y = M phi, one per column pair: real
+// columns 2j and 2j + 1 hold the real and imaginary parts of complex column
+// j (vectors, alpha, beta, rho and sigma alike: sigma_re in slot 2j's c,
+// sigma_im in slot 2j + 1's). K is real, so the gathered products are those
+// of the real kernels, column by column; the per-row arithmetic is complex,
+// with the symmetric bilinear form (no conjugation) in place of the inner
+// product and the Hermitian norm |r|^2 for the stopping test. A lane owns
+// an even number of columns, so both parts of a complex value are in one
+// lane. The order-2 filter is the real part of one such solve per column.
+
+// (r, i) += (ar + i ai)(br + i bi)
+__device__ __forceinline__ void cmul_acc(double ar, double ai, double br, double bi, double& r, double& i) {
+  r += ar * br - ai * bi;
+  i += ar * bi + ai * br;
+}
+
+// the complex value of a gathered neighbour for the column pair at lane
+// elements 2q, 2q + 1: z - alpha u (FUSED) or z + beta p (DIRECT)
+template <typename T, int C, bool FUSED>
+__device__ __forceinline__ void comb_cx(const T (&alpha)[C], const T (&beta)[C], int q, const Pack<T, C>& g0,
+                                        const Pack<T, C>& g1, T& cr, T& ci) {
+  const T xr = g1.v[2 * q], xi = g1.v[2 * q + 1], zr = g0.v[2 * q], zi = g0.v[2 * q + 1];
+  if constexpr (FUSED) {
+    const T ar = alpha[2 * q], ai = alpha[2 * q + 1];
+    cr = fma(-ar, xr, fma(ai, xi, zr));
+    ci = fma(-ar, xi, fma(-ai, xr, zi));
+  } else {
+    const T br = beta[2 * q], bi = beta[2 * q + 1];
+    cr = fma(br, xr, fma(-bi, xi, zr));
+    ci = fma(br, xi, fma(bi, xr, zi));
+  }
+}
+
+// Entries k_begin .. w - 1 of a row (past the pipelined head), complex
+// combiner (the row form's row_product).
+template <typename T, int R, int C, bool FUSED, int U>
+__device__ __forceinline__ void row_product_cx(const BMat& m, const T* __restrict__ val, int64_t base, int w,
+                                               int64_t l, int j0, const T* __restrict__ x0,
+                                               const T* __restrict__ x1, const T (&alpha)[C], const T (&beta)[C],
+                                               T (&a)[C], int k_begin) {
+  for (int k0 = k_begin; k0 < w; k0 += U) {
+    int32_t cu[U];
+    T vu[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = base + (int64_t)(k0 + u) * kW + l;
+      cu[u] = m.col[e];
+      const T vv = val[e];
+      vu[u] = k0 + u < w ? vv : (T)0;
+    }
+    Pack<T, C> g0[U], g1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t off = (int64_t)cu[u] * R + j0;
+      g0[u] = vload<T, C>(x0 + off);
+      g1[u] = vload<T, C>(x1 + off);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < C / 2; ++q) {
+        T cr, ci;
+        comb_cx<T, C, FUSED>(alpha, beta, q, g0[u], g1[u], cr, ci);
+        a[2 * q] = fma(vu[u], cr, a[2 * q]);
+        a[2 * q + 1] = fma(vu[u], ci, a[2 * q + 1]);
+      }
+  }
+}
+
+// kb_iter for complex tiles (same forms, buffers, pipelining and partials;
+// the partials are the real and imaginary parts of the complex sums).
+template <typename T, int R, bool FUSED, int H>
+__global__ __launch_bounds__(kB) void kbc_iter(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
+                                               int k, int L) {
+  using Gm = Geo<T, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
+  static_assert(C % 2 == 0, "a lane holds whole complex values");
+  constexpr int NQ = FUSED ? 4 : 3;
+  __shared__ double lds[NQ * kWpb * R];
+  const int lane = threadIdx.x % kW;
+  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
+  T alpha[C], beta[C], cc[C];
+  double c64[C];
+  bool on[C];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const BSlot& sl = slots[j0 + c];
+    on[c] = live(sl);
+    alpha[c] = on[c] ? (T)sl.alpha : (T)0;
+    beta[c] = on[c] ? (T)sl.beta : (T)0;
+    cc[c] = (T)sl.c;
+    c64[c] = sl.c;
+    any |= on[c];
+  }
+  const int bin = FUSED ? ((k - 1) & 1) : 0, bout = FUSED ? (k & 1) : 0;
+  const T* __restrict__ zin = v.z[bin];
+  const T* __restrict__ uin = v.u[bin];
+  T* __restrict__ zout = v.z[bout];
+  T* __restrict__ uout = v.u[bout];
+  const T* __restrict__ pin = v.p[(k + L - 1) % L];
+  T* __restrict__ pout = v.p[k];
+  const T* __restrict__ g1src = FUSED ? uin : pin;
+  const T* __restrict__ val = bval<T>(m);
+  double acc[NQ][C] = {};
+  if (any) {
+    const Walk wk = task_walk(m.n_slices * LPR, G);
+    const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
+    const int64_t last_slice = m.n_slices - 1;
+    auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
+    int32_t cu[H];
+    T vu[H];
+    Pack<T, C> zi, ui, pi;
+    double mi, kd;
+    int64_t base, nb, ne;
+    int w;
+    auto fetch_idx = [&](int64_t t, int64_t sb) {
+      const int64_t l = (t * RPW + rsub) % kW;
+#pragma unroll
+      for (int u = 0; u < H; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
+    };
+    auto fetch_rest = [&](int64_t t, int64_t sb) {
+      const int64_t row = min(t * RPW + rsub, m.n_slices * kW - 1), l = row % kW;
+#pragma unroll
+      for (int u = 0; u < H; ++u) vu[u] = val[sb + (int64_t)u * kW + l];
+      const int64_t idx = row * R + j0;
+      zi = vload<T, C>(zin + idx);
+      pi = vload<T, C>(pin + idx);
+      if constexpr (FUSED) ui = vload<T, C>(uin + idx);
+      mi = m.mass[row];
+      kd = m.kdiag[row];
+    };
+    {
+      const int64_t s0 = slice_of(first);
+      base = wave_uniform(m.sptr[s0]);
+      w = (int)((wave_uniform(m.sptr[s0 + 1]) - base) / kW);
+      fetch_idx(first, base);
+      fetch_rest(first, base);
+      const int64_t s1 = slice_of(first + stride);
+      nb = m.sptr[s1];
+      ne = m.sptr[s1 + 1];
+    }
+    for (int64_t t = first; t < end; t += stride) {
+      const int64_t row = t * RPW + rsub;
+      const int32_t self = (int32_t)min(row, m.n - 1);
+      Pack<T, C> g0[H], g1[H];
+#pragma unroll
+      for (int u = 0; u < H; ++u) {
+        const int64_t off = (int64_t)(u < w ? cu[u] : self) * R + j0;
+        g0[u] = vload<T, C>(zin + off);
+        g1[u] = vload<T, C>(g1src + off);
+      }
+      const int64_t cbase = base;
+      const int cw = w;
+      const int64_t tn = t + stride < end ? t + stride : t;
+      const int64_t s2 = slice_of(t + 2 * stride);
+      const int64_t nb2 = m.sptr[s2], ne2 = m.sptr[s2 + 1];
+      base = wave_uniform(nb);
+      w = (int)((wave_uniform(ne) - base) / kW);
+      fetch_idx(tn, base);
+      nb = nb2;
+      ne = ne2;
+      T a[C] = {};
+#pragma unroll
+      for (int u = 0; u < H; ++u) {
+        const T vm = u < cw ? vu[u] : (T)0;
+#pragma unroll
+        for (int q = 0; q < C / 2; ++q) {
+          T cr, ci;
+          comb_cx<T, C, FUSED>(alpha, beta, q, g0[u], g1[u], cr, ci);
+          a[2 * q] = fma(vm, cr, a[2 * q]);
+          a[2 * q + 1] = fma(vm, ci, a[2 * q + 1]);
+        }
+      }
+      if (cw > H)
+        row_product_cx<T, R, C, FUSED, H>(m, val, cbase, cw, row % kW, j0, zin, g1src, alpha, beta, a, H);
+      const bool real = row < m.n;
+      const int64_t idx = row * R + j0;
+      Pack<T, C> zn, pn, un;
+#pragma unroll
+      for (int q = 0; q < C / 2; ++q) {
+        const int e0 = 2 * q, e1 = 2 * q + 1;
+        // d = diag(S) = M + sigma diag(K) (complex), padding rows 1
+        const T dr = real ? (T)(mi + c64[e0] * kd) : (T)1, di = real ? (T)(c64[e1] * kd) : (T)0;
+        T zr, zim;
+        if constexpr (FUSED) {
+          zr = fma(-alpha[e0], ui.v[e0], fma(alpha[e1], ui.v[e1], zi.v[e0]));
+          zim = fma(-alpha[e0], ui.v[e1], fma(-alpha[e1], ui.v[e0], zi.v[e1]));
+        } else {
+          zr = zi.v[e0];
+          zim = zi.v[e1];
+        }
+        const T pr = fma(beta[e0], pi.v[e0], fma(-beta[e1], pi.v[e1], zr));
+        const T pim = fma(beta[e0], pi.v[e1], fma(beta[e1], pi.v[e0], zim));
+        // d^-1 sigma K_off x (x = z' when FUSED, p' when DIRECT)
+        const T sr = cc[e0] * a[e0] - cc[e1] * a[e1], si = cc[e0] * a[e1] + cc[e1] * a[e0];
+        const T den = dr * dr + di * di;
+        const T wr = (sr * dr + si * di) / den, wi = (si * dr - sr * di) / den;
+        T ur, uim;
+        if constexpr (FUSED) {
+          ur = fma(beta[e0], ui.v[e0], fma(-beta[e1], ui.v[e1], zr + wr));
+          uim = fma(beta[e0], ui.v[e1], fma(beta[e1], ui.v[e0], zim + wi));
+        } else {
+          ur = pr + wr;
+          uim = pim + wi;
+        }
+        zn.v[e0] = zr;
+        zn.v[e1] = zim;
+        pn.v[e0] = pr;
+        pn.v[e1] = pim;
+        un.v[e0] = ur;
+        un.v[e1] = uim;
+        if (on[e0] && real) {
+          double dur = 0.0, dui = 0.0;  // d u
+          cmul_acc((double)dr, (double)di, (double)ur, (double)uim, dur, dui);
+          cmul_acc((double)pr, (double)pim, dur, dui, acc[0][e0], acc[0][e1]);
+          cmul_acc((double)zr, (double)zim, dur, dui, acc[1][e0], acc[1][e1]);
+          cmul_acc((double)ur, (double)uim, dur, dui, acc[2][e0], acc[2][e1]);
+          if constexpr (FUSED) {
+            double dzr = 0.0, dzi = 0.0;
+            cmul_acc((double)dr, (double)di, (double)zr, (double)zim, dzr, dzi);
+            cmul_acc((double)zr, (double)zim, dzr, dzi, acc[NQ - 1][e0], acc[NQ - 1][e1]);
+          }
+        }
+      }
+      if (real) {
+        vstore<T, C>(pout + idx, pn);
+        vstore<T, C>(uout + idx, un);
+        if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
+      }
+      fetch_rest(tn, base);
+    }
+  }
+  double tot[NQ];
+  col_sum<R, C, NQ>(acc, lds, tot);
+  if (threadIdx.x < R) {
+    const int lb = lblock(G);
+    part[(Q_PQ * R + threadIdx.x) * Gp + lb] = tot[0];
+    part[(Q_ZU * R + threadIdx.x) * Gp + lb] = tot[1];
+    part[(Q_UU * R + threadIdx.x) * Gp + lb] = tot[2];
+    if constexpr (FUSED) part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[NQ - 1];
+  }
+}
+
+// x += sum_k alpha_k p_k (complex, FP64) at the chunk's end.
+template <typename T, int R, int L>
+__global__ __launch_bounds__(kB) void kbc_xupdate(BMat m, BVec<T> v, const BSlot* slots, int G) {
+  using Gm = Geo<T, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
+  const int lane = threadIdx.x % kW;
+  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
+  double ah[L][C];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const BSlot& sl = slots[j0 + c];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      ah[i][c] = sl.alpha_hist[i];
+      any |= ah[i][c] != 0.0;
+    }
+  }
+  if (!any) return;
+  for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
+    const int64_t row = wk.t * RPW + rsub;
+    if (row >= m.n) continue;
+    const int64_t idx = row * R + j0;
+    Pack<T, C> pk[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
+    Pack<double, C> xv = vload<double, C>(v.x + idx);
+#pragma unroll
+    for (int q = 0; q < C / 2; ++q)
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const double ar = ah[i][2 * q], ai = ah[i][2 * q + 1];
+        const double pr = (double)pk[i].v[2 * q], pim = (double)pk[i].v[2 * q + 1];
+        xv.v[2 * q] = fma(ar, pr, fma(-ai, pim, xv.v[2 * q]));
+        xv.v[2 * q + 1] = fma(ar, pim, fma(ai, pr, xv.v[2 * q + 1]));
+      }
+    vstore<double, C>(v.x + idx, xv);
+  }
+}
+
+// kb_residual for complex tiles: START (x = phi, p = 0, r0 = M phi - S phi =
+// -sigma K phi) and REPLACE (r = M phi - S x in FP64), z = r / diag(S), with
+// the partials of (r, z) (complex), |r|^2 and ||M phi||^2 or the
+// attainable-accuracy norm (both parts of a column pair add up).
+template <typename T, int R, bool START, int H>
+__global__ __launch_bounds__(kB) void kbc_residual(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+                                                   int Gp, uint64_t mask, SlotScales cs, int L) {
+  using Gm = Geo<T, R>;
+  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
+  static_assert(C % 2 == 0, "a lane holds whole complex values");
+  __shared__ double lds[3 * kWpb * R];
+  const int lane = threadIdx.x % kW;
+  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
+  bool on[C];
+  double cc[C];
+  bool any = false, all = true;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    if constexpr (START) {
+      on[c] = ((mask >> (j0 + c)) & 1ull) != 0;
+      cc[c] = cs.c[j0 + c];
+    } else {
+      on[c] = live(slots[j0 + c]);
+      cc[c] = slots[j0 + c].c;
+    }
+    any |= on[c];
+    all &= on[c];
+  }
+  const double* __restrict__ src = START ? v.phi : v.x;
+  T* __restrict__ pprev = v.p[L - 1];
+  const Ident ident;
+  double acc[3][C] = {};
+  if (any) {
+    const Walk wk = task_walk(m.n_slices * LPR, G);
+    const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
+    const int64_t last_slice = m.n_slices - 1;
+    auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
+    int32_t cu[H];
+    double vu[H];
+    Pack<double, C> ph, xv;
+    double mi, kd;
+    int64_t base, nb, ne;
+    int w;
+    auto fetch_idx = [&](int64_t t, int64_t sb) {
+      const int64_t l = (t * RPW + rsub) % kW;
+#pragma unroll
+      for (int u = 0; u < H; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
+    };
+    auto fetch_rest = [&](int64_t t, int64_t sb) {
+      const int64_t row = min(t * RPW + rsub, m.n_slices * kW - 1), l = row % kW;
+#pragma unroll
+      for (int u = 0; u < H; ++u) vu[u] = m.val64[sb + (int64_t)u * kW + l];
+      const int64_t idx = row * R + j0;
+      ph = vload<double, C>(v.phi + idx);
+      if constexpr (!START) xv = vload<double, C>(v.x + idx);
+      mi = m.mass[row];
+      kd = m.kdiag[row];
+    };
+    {
+      const int64_t s0 = slice_of(first);
+      base = wave_uniform(m.sptr[s0]);
+      w = (int)((wave_uniform(m.sptr[s0 + 1]) - base) / kW);
+      fetch_idx(first, base);
+      fetch_rest(first, base);
+      const int64_t s1 = slice_of(first + stride);
+      nb = m.sptr[s1];
+      ne = m.sptr[s1 + 1];
+    }
+    for (int64_t t = first; t < end; t += stride) {
+      const int64_t row = t * RPW + rsub;
+      const int32_t self = (int32_t)min(row, m.n - 1);
+      Pack<double, C> gx[H];
+#pragma unroll
+      for (int u = 0; u < H; ++u) gx[u] = vload<double, C>(src + (int64_t)(u < w ? cu[u] : self) * R + j0);
+      const int64_t cbase = base;
+      const int cw = w;
+      const int64_t tn = t + stride < end ? t + stride : t;
+      const int64_t s2 = slice_of(t + 2 * stride);
+      const int64_t nb2 = m.sptr[s2], ne2 = m.sptr[s2 + 1];
+      base = wave_uniform(nb);
+      w = (int)((wave_uniform(ne) - base) / kW);
+      fetch_idx(tn, base);
+      nb = nb2;
+      ne = ne2;
+      double a[C] = {}, aa[C] = {};
+#pragma unroll
+      for (int u = 0; u < H; ++u) {
+        const double vm = u < cw ? vu[u] : 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          a[c] = fma(vm, gx[u].v[c], a[c]);
+          if constexpr (!START) aa[c] = fma(fabs(vm), fabs(gx[u].v[c]), aa[c]);
+        }
+      }
+      if (cw > H) {
+        if constexpr (START)
+          row_product<double, double, R, C, false, decltype(ident), H>(m, m.val64, cbase, cw, row % kW, j0, src,
+                                                                        nullptr, ident, a, H);
+        else
+          row_product_abs2<R, C, H>(m, cbase, cw, row % kW, j0, src, a, aa, H);
+      }
+      const bool real = row < m.n;
+      const int64_t idx = row * R + j0;
+      if constexpr (START) {
+        if (real) {
+          Pack<double, C> xo = ph;
+          Pack<T, C> zo, po = {};
+          if (!all) {
+            xo = vload<double, C>(v.x + idx);
+            zo = vload<T, C>(v.z[0] + idx);
+            po = vload<T, C>(pprev + idx);
+          }
+#pragma unroll
+          for (int q = 0; q < C / 2; ++q) {
+            const int e0 = 2 * q, e1 = 2 * q + 1;
+            if (!on[e0]) continue;
+            const double tr = kd * ph.v[e0] + a[e0], ti = kd * ph.v[e1] + a[e1];
+            const double rr64 = -(cc[e0] * tr - cc[e1] * ti), ri64 = -(cc[e0] * ti + cc[e1] * tr);
+            const T rtr = (T)rr64, rti = (T)ri64;
+            const T dr = (T)(mi + cc[e0] * kd), di = (T)(cc[e1] * kd);
+            const T den = dr * dr + di * di;
+            const T zr = (rtr * dr + rti * di) / den, zim = (rti * dr - rtr * di) / den;
+            xo.v[e0] = ph.v[e0];
+            xo.v[e1] = ph.v[e1];
+            zo.v[e0] = zr;
+            zo.v[e1] = zim;
+            po.v[e0] = (T)0;
+            po.v[e1] = (T)0;
+            cmul_acc((double)rtr, (double)rti, (double)zr, (double)zim, acc[0][e0], acc[0][e1]);
+            acc[1][e0] += rr64 * rr64;
+            acc[1][e1] += ri64 * ri64;
+            acc[2][e0] += (mi * ph.v[e0]) * (mi * ph.v[e0]);
+            acc[2][e1] += (mi * ph.v[e1]) * (mi * ph.v[e1]);
+          }
+          vstore<double, C>(v.x + idx, xo);
+          vstore<T, C>(v.z[0] + idx, zo);
+          vstore<T, C>(pprev + idx, po);
+        }
+      } else {
+        Pack<T, C> zv;
+#pragma unroll
+        for (int q = 0; q < C / 2; ++q) {
+          const int e0 = 2 * q, e1 = 2 * q + 1;
+          const double xr = xv.v[e0], xim = xv.v[e1];
+          const double tr = kd * xr + a[e0], ti = kd * xim + a[e1];
+          const double rr64 = mi * (ph.v[e0] - xr) - (cc[e0] * tr - cc[e1] * ti);
+          const double ri64 = mi * (ph.v[e1] - xim) - (cc[e0] * ti + cc[e1] * tr);
+          const T rtr = (T)rr64, rti = (T)ri64;
+          const T dr = (T)(mi + cc[e0] * kd), di = (T)(cc[e1] * kd);
+          const T den = dr * dr + di * di;
+          zv.v[e0] = (rtr * dr + rti * di) / den;
+          zv.v[e1] = (rti * dr - rtr * di) / den;
+          if (on[e0] && real) {
+            const double sabs = sqrt(cc[e0] * cc[e0] + cc[e1] * cc[e1]);
+            const double m0 = fabs(mi * ph.v[e0]) + fabs(mi * xr) + sabs * (fabs(kd * xr) + aa[e0]);
+            const double m1 = fabs(mi * ph.v[e1]) + fabs(mi * xim) + sabs * (fabs(kd * xim) + aa[e1]);
+            cmul_acc((double)rtr, (double)rti, (double)zv.v[e0], (double)zv.v[e1], acc[0][e0], acc[0][e1]);
+            acc[1][e0] += rr64 * rr64;
+            acc[1][e1] += ri64 * ri64;
+            acc[2][e0] += m0 * m0;
+            acc[2][e1] += m1 * m1;
+          }
+        }
+        if (real) vstore<T, C>(v.z[0] + idx, zv);
+      }
+      fetch_rest(tn, base);
+    }
+  }
+  double tot[3];
+  col_sum<R, C, 3>(acc, lds, tot);
+  if (threadIdx.x < R) {
+    const int lb = lblock(G);
+    part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[0];
+    part[(Q_RR * R + threadIdx.x) * Gp + lb] = tot[1];
+    part[((START ? Q_BB : Q_FL) * R + threadIdx.x) * Gp + lb] = tot[2];
+  }
+}
+
 // End of a column: partials of sum M x^2 (kb_out writes x out). A column
 // stops right after a replacement, whose FP64 true residual is that of this
 // very x, so no residual is formed here.
@@ -1393,6 +1857,116 @@ __global__ __launch_bounds__(kFinThreads) void kf_finish(BSlot* slots, const dou
   }
 }
 
+// Finalizers of complex tiles: block q handles the column pair (2q, 2q + 1)
+// and keeps both slots' counters and flags equal.
+__device__ __forceinline__ void cdiv(double ar, double ai, double br, double bi, double& r, double& i) {
+  const double den = br * br + bi * bi;
+  r = (ar * br + ai * bi) / den;
+  i = (ai * br - ar * bi) / den;
+}
+
+__global__ __launch_bounds__(kFinThreads) void kfc_step(BSlot* slots, const double* part, int G, int Gp, int R,
+                                                         int k) {
+  __shared__ double lds[kFinThreads / kW];
+  const int j = 2 * blockIdx.x;
+  BSlot& s = slots[j];
+  BSlot& t = slots[j + 1];
+  if (!live(s)) {
+    if (threadIdx.x == 0) s.alpha_hist[k] = t.alpha_hist[k] = 0.0;
+    return;
+  }
+  const double pqr = fin_sum(part + (Q_PQ * R + j) * Gp, G, lds), pqi = fin_sum(part + (Q_PQ * R + j + 1) * Gp, G, lds);
+  const double zur = fin_sum(part + (Q_ZU * R + j) * Gp, G, lds), zui = fin_sum(part + (Q_ZU * R + j + 1) * Gp, G, lds);
+  const double uur = fin_sum(part + (Q_UU * R + j) * Gp, G, lds), uui = fin_sum(part + (Q_UU * R + j + 1) * Gp, G, lds);
+  const double rzr = k > 0 ? fin_sum(part + (Q_RZ * R + j) * Gp, G, lds) : 0.0;
+  const double rzi = k > 0 ? fin_sum(part + (Q_RZ * R + j + 1) * Gp, G, lds) : 0.0;
+  if (threadIdx.x == 0) {
+    const double rr = k > 0 ? rzr : s.rho, ri = k > 0 ? rzi : t.rho;
+    double ar, ai;
+    cdiv(rr, ri, pqr, pqi, ar, ai);
+    s.iters += 1;
+    t.iters += 1;
+    if (!(pqr * pqr + pqi * pqi > 0.0) || !isfinite(ar) || !isfinite(ai)) {
+      s.done = t.done = 2;
+      s.alpha_hist[k] = t.alpha_hist[k] = 0.0;
+    } else {
+      // next rho = rho - 2 alpha (q, z) + alpha^2 (q, d^-1 q)
+      const double a2r = ar * ar - ai * ai, a2i = 2.0 * ar * ai;
+      const double nr = rr - 2.0 * (ar * zur - ai * zui) + (a2r * uur - a2i * uui);
+      const double ni = ri - 2.0 * (ar * zui + ai * zur) + (a2r * uui + a2i * uur);
+      double br, bi;
+      cdiv(nr, ni, rr, ri, br, bi);
+      s.rho = rr;
+      t.rho = ri;
+      s.alpha = ar;
+      t.alpha = ai;
+      s.alpha_hist[k] = ar;
+      t.alpha_hist[k] = ai;
+      s.beta = br;
+      t.beta = bi;
+      s.rr_true = t.rr_true = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFinThreads) void kfc_replace(BSlot* slots, const double* part, int G, int Gp, int R,
+                                                            int max_iter) {
+  __shared__ double lds[kFinThreads / kW];
+  const int j = 2 * blockIdx.x;
+  BSlot& s = slots[j];
+  BSlot& t = slots[j + 1];
+  if (!live(s)) return;
+  const double rzr = fin_sum(part + (Q_RZ * R + j) * Gp, G, lds), rzi = fin_sum(part + (Q_RZ * R + j + 1) * Gp, G, lds);
+  const double rr = fin_sum(part + (Q_RR * R + j) * Gp, G, lds) + fin_sum(part + (Q_RR * R + j + 1) * Gp, G, lds);
+  const double fl = fin_sum(part + (Q_FL * R + j) * Gp, G, lds) + fin_sum(part + (Q_FL * R + j + 1) * Gp, G, lds);
+  if (threadIdx.x == 0) {
+    s.rho_prev = s.rho;
+    t.rho_prev = t.rho;
+    double br, bi;
+    cdiv(rzr, rzi, s.rho_prev, t.rho_prev, br, bi);
+    s.rho = rzr;
+    t.rho = rzi;
+    s.beta = br;
+    t.beta = bi;
+    s.rr = t.rr = rr;
+    s.rr_true = t.rr_true = 1;
+    s.updates += 1;
+    t.updates += 1;
+    const double floor2 = fl * (kFloor * kU) * (kFloor * kU);
+    if (rr <= fmax(s.tol2, floor2)) s.done = t.done = 1;
+    else if (s.iters >= max_iter) s.done = t.done = 3;
+  }
+}
+
+__global__ __launch_bounds__(kFinThreads) void kfc_init(BSlot* slots, const double* part, int G, int Gp, int R,
+                                                         uint64_t mask, double rtol, SlotScales cs) {
+  __shared__ double lds[kFinThreads / kW];
+  const int j = 2 * blockIdx.x;
+  if (!((mask >> j) & 1ull)) return;
+  BSlot& s = slots[j];
+  BSlot& t = slots[j + 1];
+  const double rzr = fin_sum(part + (Q_RZ * R + j) * Gp, G, lds), rzi = fin_sum(part + (Q_RZ * R + j + 1) * Gp, G, lds);
+  const double rr = fin_sum(part + (Q_RR * R + j) * Gp, G, lds) + fin_sum(part + (Q_RR * R + j + 1) * Gp, G, lds);
+  const double bb = fin_sum(part + (Q_BB * R + j) * Gp, G, lds) + fin_sum(part + (Q_BB * R + j + 1) * Gp, G, lds);
+  if (threadIdx.x == 0) {
+    s.c = cs.c[j];
+    t.c = cs.c[j + 1];
+    s.rho = rzr;
+    t.rho = rzi;
+    s.rho_prev = t.rho_prev = INFINITY;
+    s.beta = t.beta = 0.0;
+    s.alpha = t.alpha = 0.0;
+    s.rr = t.rr = rr;
+    s.bb = t.bb = bb;
+    s.tol2 = t.tol2 = rtol * rtol * bb;
+    s.iters = t.iters = 0;
+    s.updates = t.updates = 0;
+    s.rr_true = t.rr_true = 1;
+    s.active = t.active = 1;
+    s.done = t.done = rr <= s.tol2 ? 1 : 0;
+  }
+}
+
 template <typename T>
 BVec<T> bvec(BatchWork& w) {
   BVec<T> v{};
@@ -1492,6 +2066,12 @@ struct Launch {
   // residual drifts from the true one when S is badly conditioned)
   template <typename T>
   static void step(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k, int head) {
+    if constexpr (R >= 2) {
+      if (w.cx) {
+        step_cx<T>(m, w, g, s, prm, k);
+        return;
+      }
+    }
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
     by_head<T>(m, head, [&](auto L) { L.template iter<T>(m, w, g, s, k); });
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
@@ -1502,12 +2082,39 @@ struct Launch {
       kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
     }
   }
+  // complex tiles (the first-order operator, head of 6 entries)
+  template <typename T>
+  static void step_cx(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k) {
+    if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
+    if (k == 0) kbc_iter<T, R, false, 6><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    else kbc_iter<T, R, true, 6><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
+    kfc_step<<<R / 2, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
+    if (k == w.chunk - 1) {
+      kbc_xupdate<T, R, kChunk><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
+      kbc_residual<T, R, false, 6><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, 0ull,
+                                                       SlotScales{}, w.chunk);
+      kfc_replace<<<R / 2, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
+    }
+  }
   static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k, int head) {
     if (w.mixed) step<float>(m, w, g, s, prm, k, head);
     else step<double>(m, w, g, s, prm, k, head);
   }
   static void init(const BMat& m, BatchWork& w, Grids g, hipStream_t s, uint64_t mask, const SlotScales& cs,
                    double rtol, int head) {
+    if constexpr (R >= 2) {
+      if (w.cx) {
+        if (w.mixed)
+          kbc_residual<float, R, true, 6><<<g.G, kB, 0, s>>>(m, bvec<float>(w), w.slots, w.part, g.G, g.Gp, mask, cs,
+                                                             w.chunk);
+        else
+          kbc_residual<double, R, true, 6><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask,
+                                                              cs, w.chunk);
+        kfc_init<<<R / 2, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
+        return;
+      }
+    }
     if (w.mixed) by_head<float>(m, head, [&](auto L) { L.template start<float>(m, w, g, s, mask, cs); });
     else by_head<double>(m, head, [&](auto L) { L.template start<double>(m, w, g, s, mask, cs); });
     kf_init<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);

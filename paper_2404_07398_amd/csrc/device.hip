@@ -220,6 +220,8 @@ struct DeviceState {
   ShiftWork sw;
   BatchWork bw;
   std::deque<BatchWork> spare;  // a deque: adding a tile leaves the others where they are
+  BatchWork bwc;                 // complex tile of the shifted solves (order 2)
+  double* zero_rows = nullptr;   // n_pad zeros: the imaginary part of a field
   // grid sizes picked by the autotuner, per (tile size, precision), and the
   // tile size it found best per precision (0 = not tuned)
   struct TunedGrid {
@@ -1405,6 +1407,8 @@ void device_destroy(Handle* h) {
     if (p) (void)hipFree(p);
   if (sw.sc_host) (void)hipHostFree(sw.sc_host);
   batch_free(&d->bw);
+  batch_free(&d->bwc);
+  if (d->zero_rows) (void)hipFree(d->zero_rows);
   for (BatchWork& t : d->spare) batch_free(&t);
   if (d->field_stage) (void)hipFree(d->field_stage);
   if (d->field_rows) (void)hipFree(d->field_rows);
@@ -1912,6 +1916,25 @@ BatchMatrix batch_matrix(DeviceState* d, int R, bool mixed) {
   return bm;
 }
 
+// The first-order operator K of an order >= 2 handle (same rows, mass and
+// numbering as K_n) for the complex tiles of the shifted solves.
+static BatchMatrix batch_matrix_k1(DeviceState* d, int R, bool mixed) {
+  BatchMatrix bm = batch_matrix(d, R, mixed);
+  const DevK1& k1 = d->k1;
+  bm.sptr = k1.sptr;
+  bm.col = k1.col;
+  bm.val64 = k1.val64;
+  bm.val32 = k1.val32;
+  bm.kdiag = k1.kdiag64;
+  bm.head = k1.head;
+  bm.pairs = false;
+  bm.psptr = nullptr;
+  bm.pcol = nullptr;
+  bm.pval64 = nullptr;
+  bm.pval32 = nullptr;
+  return bm;
+}
+
 BatchMatrix handle_batch_matrix(Handle* h, int R, bool mixed) { return batch_matrix(h->dev, R, mixed); }
 double handle_mass_sum(const Handle* h) { return h->dev->m.mass_sum; }
 
@@ -1950,20 +1973,15 @@ ifl_status spare_tile(DeviceState* d, int R, bool mixed, hipStream_t s, BatchWor
 
 // Many columns at once: slots of a tile of R columns are filled from the
 // (field, scale) list, iterated together, and refilled as columns finish.
-ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fields, int32_t n_scales,
-                          const double* k, double* out, ifl_solve_stats* stats, double* energy) {
+// A batched call's staging: the fields on the device, then in row order in
+// d->field_rows (once per call; each is loaded once per scale) with the
+// non-finite check of every wet entry (through w's flag), and host-output
+// staging for out_cols columns.
+ifl_status stage_call(Handle* h, const BatchMatrix& bm, BatchWork& w, int32_t n_fields, const double* fields,
+                      int out_cols, hipStream_t s) {
   DeviceState* d = h->dev;
-  hipStream_t s = stream_of(h);
   const int64_t L = h->op.field_len;
-  const bool mixed = h->opt.precision == IFL_MIXED;
-  ifl_status st = ensure_batch(d, R, mixed);
-  if (st != IFL_OK) return st;
-  BatchWork* wp = &d->bw;
-  BatchMatrix bm = batch_matrix(d, R, mixed);
-  const int R0 = R;
-  // slots left active by an earlier call that stopped on an error
-  if ((st = batch_release(*wp, ~0ull, s)) != IFL_OK) return st;
-  // fields on the device
+  ifl_status st;
   const double* fdev = fields;
   if (!is_device_ptr(fields)) {
     const int64_t need = (int64_t)n_fields * L;
@@ -1977,31 +1995,44 @@ ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fiel
     IFL_HIP(hipMemcpyAsync(d->field_stage, fields, sizeof(double) * need, hipMemcpyHostToDevice, s));
     fdev = d->field_stage;
   }
-  const bool odev = out ? is_device_ptr(out) : false;
-  if (out && !odev && d->col_stage_len < (int64_t)R * L) {
+  if (out_cols > 0 && d->col_stage_len < (int64_t)out_cols * L) {
     if (d->col_stage) (void)hipFree(d->col_stage);
     d->col_stage = nullptr;
     d->col_stage_len = 0;
-    if ((st = dalloc(&d->col_stage, (size_t)R * L)) != IFL_OK) return st;
-    d->col_stage_len = (int64_t)R * L;
+    if ((st = dalloc(&d->col_stage, (size_t)out_cols * L)) != IFL_OK) return st;
+    d->col_stage_len = (int64_t)out_cols * L;
   }
-  // the fields in row order, once per call (each is loaded once per scale),
-  // with the non-finite check of every wet entry
-  {
-    const int64_t need = (int64_t)n_fields * bm.n_pad;
-    if (d->field_rows_len < need) {
-      if (d->field_rows) (void)hipFree(d->field_rows);
-      d->field_rows = nullptr;
-      d->field_rows_len = 0;
-      if ((st = dalloc(&d->field_rows, (size_t)need)) != IFL_OK) return st;
-      d->field_rows_len = need;
-    }
-    bool bad = false;
-    if ((st = batch_clear_flag(*wp, s)) != IFL_OK) return st;
-    if ((st = batch_permute_fields(bm, fdev, L, n_fields, d->field_rows, wp->flag, s)) != IFL_OK) return st;
-    if ((st = batch_check_flag(*wp, s, &bad)) != IFL_OK) return st;
-    if (bad) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");
+  const int64_t need = (int64_t)n_fields * bm.n_pad;
+  if (d->field_rows_len < need) {
+    if (d->field_rows) (void)hipFree(d->field_rows);
+    d->field_rows = nullptr;
+    d->field_rows_len = 0;
+    if ((st = dalloc(&d->field_rows, (size_t)need)) != IFL_OK) return st;
+    d->field_rows_len = need;
   }
+  bool bad = false;
+  if ((st = batch_clear_flag(w, s)) != IFL_OK) return st;
+  if ((st = batch_permute_fields(bm, fdev, L, n_fields, d->field_rows, w.flag, s)) != IFL_OK) return st;
+  if ((st = batch_check_flag(w, s, &bad)) != IFL_OK) return st;
+  if (bad) return fail(IFL_EINVAL, "field has a NaN or Inf at a wet entry");
+  return IFL_OK;
+}
+
+ifl_status filter_batched(Handle* h, int R, int32_t n_fields, const double* fields, int32_t n_scales,
+                          const double* k, double* out, ifl_solve_stats* stats, double* energy) {
+  DeviceState* d = h->dev;
+  hipStream_t s = stream_of(h);
+  const int64_t L = h->op.field_len;
+  const bool mixed = h->opt.precision == IFL_MIXED;
+  ifl_status st = ensure_batch(d, R, mixed);
+  if (st != IFL_OK) return st;
+  BatchWork* wp = &d->bw;
+  BatchMatrix bm = batch_matrix(d, R, mixed);
+  const int R0 = R;
+  // slots left active by an earlier call that stopped on an error
+  if ((st = batch_release(*wp, ~0ull, s)) != IFL_OK) return st;
+  const bool odev = out ? is_device_ptr(out) : false;
+  if ((st = stage_call(h, bm, *wp, n_fields, fields, out && !odev ? R : 0, s)) != IFL_OK) return st;
   // columns: larger scales (more iterations) first, fields in order
   const int64_t ncols = (int64_t)n_fields * n_scales;
   std::vector<int64_t> order(ncols);
@@ -2155,12 +2186,135 @@ int pick_tile(const Handle* h, int64_t ncols) {
 
 }  // namespace
 
+// Order 2 with IFL_SOLVER_SHIFTED in tiles: S_2^-1 M phi is the real part of
+// (M + sigma K)^-1 M phi, sigma = -b / w_0 (w_0 = exp(i pi / 2), b = c^(1/2)),
+// one complex column per (field, scale) in a complex tile of 2 Rc real
+// columns over the first-order operator (Jacobi-COCG, FP64 replacements at
+// every chunk end, stop on the shifted system's FP64 true residual, as the
+// one-column shifted solves). Columns enter at chunk boundaries, larger
+// scales first; the tile keeps its width.
+ifl_status filter_batched_cx(Handle* h, int Rc, int32_t n_fields, const double* fields, int32_t n_scales,
+                             const double* k, double* out, ifl_solve_stats* stats, double* energy) {
+  DeviceState* d = h->dev;
+  hipStream_t s = stream_of(h);
+  const int64_t L = h->op.field_len;
+  const bool mixed = h->opt.precision == IFL_MIXED;
+  const int R = 2 * Rc;
+  ifl_status st;
+  if (!d->k1.sptr) return fail(IFL_EINVAL, "handle has no first-order operator (an old saved file)");
+  BatchMatrix bm = batch_matrix_k1(d, R, mixed);
+  BatchWork& w = d->bwc;
+  if (!w.slots || w.R != R || w.mixed != mixed || w.G != bm.G || w.Gu != bm.Gu) {
+    batch_free(&w);
+    w = BatchWork();
+    if ((st = batch_alloc(&w, bm, R, mixed)) != IFL_OK) return st;
+    w.cx = true;
+  }
+  if (!d->zero_rows) {
+    if ((st = dalloc(&d->zero_rows, (size_t)bm.n_pad)) != IFL_OK) return st;
+    k_fill_zero<<<(unsigned)((bm.n_pad + 255) / 256), 256, 0, s>>>(d->zero_rows, bm.n_pad);
+    IFL_HIP(hipGetLastError());
+  }
+  if ((st = batch_release(w, ~0ull, s)) != IFL_OK) return st;
+  const bool odev = out ? is_device_ptr(out) : false;
+  if ((st = stage_call(h, bm, w, n_fields, fields, out && !odev ? R : 0, s)) != IFL_OK) return st;
+  const int64_t ncols = (int64_t)n_fields * n_scales;
+  std::vector<int64_t> order(ncols);
+  for (int64_t i = 0; i < ncols; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return k[a % n_scales] < k[b % n_scales]; });
+  BatchParams prm;
+  prm.max_iter = h->opt.max_iter;
+  prm.graphs = h->opt.graphs != 0;
+  // the shift of the pair with Im >= 0 (the same one the one-column solves take)
+  const double pi = 3.14159265358979323846, th = pi / 2;
+  const double sr = -std::cos(th), si = std::sin(th);
+  std::vector<int64_t> slot_col(Rc, -1);
+  std::vector<std::chrono::steady_clock::time_point> t_in(Rc);
+  int64_t next = 0, finished = 0;
+  bool any_notconv = false;
+  while (finished < ncols) {
+    uint64_t mask = 0;
+    SlotScales cs{};
+    const double* src[64] = {};
+    for (int q = 0; q < Rc && next < ncols; ++q) {
+      if (slot_col[q] >= 0) continue;
+      const int64_t col = order[next++];
+      const int64_t f = col / n_scales, sc = col % n_scales;
+      const double b = std::sqrt(h->opt.gamma / std::pow(k[sc], 4.0));
+      src[2 * q] = d->field_rows + f * bm.n_pad;
+      src[2 * q + 1] = d->zero_rows;
+      cs.c[2 * q] = sr * b;
+      cs.c[2 * q + 1] = si * b;
+      slot_col[q] = col;
+      t_in[q] = std::chrono::steady_clock::now();
+      mask |= 3ull << (2 * q);
+    }
+    if (mask) {
+      if ((st = batch_load_columns(bm, w, mask, src, true, s)) != IFL_OK) return st;
+      if ((st = batch_init(bm, w, mask, cs, h->opt.rtol, s)) != IFL_OK) return st;
+    }
+    if ((st = batch_iterate(bm, w, w.chunk, prm, s)) != IFL_OK) return st;
+    if ((st = batch_read_slots(w, s)) != IFL_OK) return st;
+    uint64_t fin = 0;
+    std::vector<double*> dst(R, nullptr);
+    for (int q = 0; q < Rc; ++q) {
+      if (slot_col[q] < 0 || w.slots_host[2 * q].done == 0) continue;
+      fin |= 3ull << (2 * q);
+      if (out) dst[2 * q] = odev ? out + slot_col[q] * L : d->col_stage + (int64_t)(2 * q) * L;
+    }
+    if (!fin) continue;
+    if ((st = batch_finish(bm, w, fin, dst.data(), s)) != IFL_OK) return st;
+    if ((st = batch_read_slots(w, s)) != IFL_OK) return st;
+    const auto now = std::chrono::steady_clock::now();
+    for (int q = 0; q < Rc; ++q) {
+      if (!((fin >> (2 * q)) & 1ull)) continue;
+      const BSlot& sl = w.slots_host[2 * q];
+      const int64_t col = slot_col[q];
+      const bool ok = sl.done == 1;
+      any_notconv |= !ok;
+      if (stats) {
+        ifl_solve_stats& so = stats[col];
+        so.iterations = sl.iters;
+        so.refinements = sl.updates;
+        so.status = ok ? IFL_OK : IFL_ENOTCONV;
+        so.reserved = 0;
+        so.rel_residual = sl.bb > 0 ? std::sqrt(sl.res2 / sl.bb) : std::sqrt(sl.res2);
+        so.seconds = std::chrono::duration<double>(now - t_in[q]).count();
+        so.energy = 0.5 * sl.energy2 / d->m.mass_sum;
+      }
+      if (energy) energy[col] = 0.5 * sl.energy2 / d->m.mass_sum;
+      if (out && !odev)
+        IFL_HIP(hipMemcpyAsync(out + col * L, dst[2 * q], sizeof(double) * L, hipMemcpyDeviceToHost, s));
+      slot_col[q] = -1;
+      ++finished;
+    }
+    if ((st = batch_release(w, fin, s)) != IFL_OK) return st;
+  }
+  IFL_HIP(hipStreamSynchronize(s));
+  if (any_notconv) return fail(IFL_ENOTCONV, "a shifted solve did not converge within max_iter");
+  return IFL_OK;
+}
+
 ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int32_t n_scales, const double* k,
                          double* out, ifl_solve_stats* stats, double* energy) {
   DeviceState* d = h->dev;
   IFL_HIP(hipSetDevice(d->device));
-  // the shifted first-order solves run one column at a time
   const bool shifted = h->opt.solver == IFL_SOLVER_SHIFTED && h->op.order >= 2;
+  // order 2 (one complex shift) in complex tiles of first-order operators
+  // with narrow rows; other orders, and batch = 1, one column at a time
+  if (shifted && h->op.order == 2 && d->k1.head <= 6 && h->opt.batch != 1) {
+    const int64_t ncols = (int64_t)n_fields * n_scales;
+    int Rc = 1;
+    if (h->opt.batch >= 2) {
+      Rc = std::min(32, std::max(1, h->opt.batch / 2));
+    } else {
+      while (Rc * 2 <= std::min<int64_t>(16, std::max<int64_t>(1, ncols / 2))) Rc *= 2;
+    }
+    int Rp = 1;  // tiles come in powers of two
+    while (Rp * 2 <= Rc) Rp *= 2;
+    return filter_batched_cx(h, Rp, n_fields, fields, n_scales, k, out, stats, energy);
+  }
   const int R = shifted ? 1 : pick_tile(h, (int64_t)n_fields * n_scales);
   if (R <= 1) return filter_single(h, n_fields, fields, n_scales, k, out, stats, energy, ColScratch{d->w.part, d->w.sc, true, true});
   return filter_batched(h, R, n_fields, fields, n_scales, k, out, stats, energy);

@@ -436,7 +436,8 @@ def _level8_biharmonic():
     return _L8_N2
 
 
-@pytest.mark.parametrize("precision,batch,shifted", [(0, 1, False), (1, 0, False), (0, 1, True), (1, 1, True)])
+@pytest.mark.parametrize("precision,batch,shifted", [(0, 1, False), (1, 0, False), (0, 1, True), (1, 1, True),
+                                                     (0, 0, True), (1, 0, True)])
 def test_full_size_level8_biharmonic_certified(ifl, precision, batch, shifted):
     """Level-8 icosphere (655,362 vertices), 30% land mask, n = 2 (the
     biharmonic filter, 20 scales from 32h to 2h), each precision against
@@ -567,6 +568,37 @@ def test_batched_cell_vector(ifl, precision):
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     for j in range(len(ks)):
         assert relative_l2(out[0, j], ref[j].reshape(-1)) <= tol
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("batch", [2, 4, 16, 0])
+def test_shifted_complex_tiles(ifl, precision, batch):
+    """Order 2 with IFL_SOLVER_SHIFTED in complex tiles (real and imaginary
+    parts in adjacent columns, Jacobi-COCG on M + sigma K): 3 fields x 5
+    scales 32h .. 2h through tiles of 1, 2, 8 complex columns (and the
+    library's width), so columns enter and leave at chunk boundaries; each
+    column against the oracle's shifted solve and against the one-column
+    shifted path."""
+    tol = TOL_FP64 if precision == 0 else TOL_MIXED
+    s, _ = _sphere(5, 0.3)
+    fields = np.stack([W.sphere_k3_field(s, 700 + i, n_waves=64) for i in range(3)])
+    ks = W.log_scales(s.h, 5)
+    op = O.scalar_operator(s, 2)
+    h = _prep(ifl, s, n=2, precision=precision, batch=batch, solver=ifl.IFL_SOLVER_SHIFTED)
+    out, st = h.filter(fields, ks)
+    h.set_options(batch=1)
+    single, st1 = h.filter(fields, ks)
+    for f in range(3):
+        ref = O.filter_scalar(op, fields[f], ks, method="shifted")
+        for j in range(len(ks)):
+            e = relative_l2(out[f, j], ref[j])
+            d = relative_l2(out[f, j], single[f, j])
+            x = st[f * len(ks) + j]
+            print(f"complex tiles batch={batch} precision={precision} f={f} j={j} err={e:.2e} vs-single={d:.2e} "
+                  f"it={x.iterations}/{st1[f * len(ks) + j].iterations} repl={x.refinements}")
+            assert x.status == 0 and e <= tol and d <= 2 * tol
+            assert abs(x.energy - st1[f * len(ks) + j].energy) <= 1e-8 * abs(st1[f * len(ks) + j].energy)
     h.close()
 
 
