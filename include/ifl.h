@@ -117,8 +117,9 @@ typedef struct ifl_options {
                         IFL_SOLVER_KN). With SHIFTED, ifl_filter and ifl_spectrum run n = 2 in complex
                         tiles of 'batch' / 2 columns (batch 0: the library's width; scalar operators
                         with first-order rows of at most 6 entries 90% of the time), other orders and
-                        batch = 1 one column at a time; the serving engine one column at a time.
-                        Tiles report the shifted system's FP64 true residual in rel_residual */
+                        batch = 1 one column at a time; the serving engine serves n = 2 in a complex
+                        tile of 2 x slots real columns (slots <= 32), other orders one column at a
+                        time. Tiles report the shifted system's FP64 true residual in rel_residual */
 } ifl_options;
 
 /* Per-solve statistics (one per field x scale). */

@@ -26,14 +26,14 @@ struct BSlot {
   double bb;        // ||M phi||^2
   double res2;      // final true ||M phi - S x||^2 (that of the last replacement)
   double energy2;   // final sum M x^2
-  double pad0;
+  double rr_best;   // complex tiles: the smallest true ||r||^2 so far (stall detection)
   double alpha_hist[kChunk];  // alpha of each iteration of the current chunk (0 if not iterating)
   int32_t active;   // slot holds a column
   int32_t done;     // 0 running, 1 converged, 2 breakdown, 3 max_iter
   int32_t iters;    // CG iterations of this column
   int32_t updates;  // FP64 residual replacements
   int32_t rr_true;  // rr is an FP64 true residual
-  int32_t pad1;
+  int32_t stall;    // complex tiles: chunk ends since rr_best last fell by 10%
 };
 
 // The handle's matrix as the batched kernels see it (device pointers).
@@ -86,6 +86,10 @@ struct BatchWork {
   // one complex-shifted first-order system (Jacobi-COCG); slot 2j + 1
   // carries the imaginary parts of the scalars, sigma in its c
   bool cx = false;
+  // complex tiles: a column pair stops when |r|^2 <= (rtol / (1 + |sigma| g))^2
+  // ||M phi||^2, g >= ||K M^-1||_2 (the handle's bound), so that the residual
+  // of S_2 itself, Re r + b K M^-1 Im r, meets rtol
+  double cx_g = 0.0;
   // p cycles through kChunk buffers, so that the directions of a whole
   // chunk are still there when x is updated at its last iteration; z and
   // u = diag(S)^-1 S p alternate between two buffers (an iteration gathers
@@ -154,6 +158,15 @@ ifl_status batch_release(BatchWork& w, uint64_t mask, hipStream_t s);
 // The handle's matrix for tiles of R columns, and the sum of its mass
 // (both need a device handle; defined with the device state).
 BatchMatrix handle_batch_matrix(Handle* h, int R, bool mixed);
+// Complex tiles of the order-2 shifted solves: whether the handle runs them
+// (IFL_SOLVER_SHIFTED, order 2, a first-order operator with narrow rows),
+// their matrix (the first-order operator), and the shift of a column at
+// wavenumber k (slot 2j's and 2j + 1's c).
+bool handle_cx_tiles(const Handle* h);
+BatchMatrix handle_batch_matrix_k1(Handle* h, int R, bool mixed);
+void cx_shift(const Handle* h, double k, double* sigma_re, double* sigma_im);
+// g >= ||K M^-1||_2 for the first-order operator K of an order >= 2 handle
+double handle_cx_gnorm(const Handle* h);
 double handle_mass_sum(const Handle* h);
 
 }  // namespace ifl

@@ -1909,8 +1909,14 @@ __global__ __launch_bounds__(kFinThreads) void kfc_step(BSlot* slots, const doub
   }
 }
 
+// A column pair whose FP64 true residual stops falling (mixed precision at
+// the tightened tolerance can stall near it) restarts its directions once
+// (beta = 0) after two chunk ends without a 10% fall, stops as converged
+// after four if it meets the plain rtol on the shifted system (the
+// attainable accuracy; the tightened target is then out of reach), and as
+// not converged after 32.
 __global__ __launch_bounds__(kFinThreads) void kfc_replace(BSlot* slots, const double* part, int G, int Gp, int R,
-                                                            int max_iter) {
+                                                            int max_iter, double g) {
   __shared__ double lds[kFinThreads / kW];
   const int j = 2 * blockIdx.x;
   BSlot& s = slots[j];
@@ -1933,13 +1939,27 @@ __global__ __launch_bounds__(kFinThreads) void kfc_replace(BSlot* slots, const d
     s.updates += 1;
     t.updates += 1;
     const double floor2 = fl * (kFloor * kU) * (kFloor * kU);
-    if (rr <= fmax(s.tol2, floor2)) s.done = t.done = 1;
-    else if (s.iters >= max_iter) s.done = t.done = 3;
+    if (rr < 0.9 * s.rr_best) {
+      s.rr_best = t.rr_best = rr;
+      s.stall = t.stall = 0;
+    } else {
+      s.stall = t.stall = s.stall + 1;
+    }
+    const double f = 1.0 + sqrt(s.c * s.c + t.c * t.c) * g;  // tol2 = (rtol / f)^2 bb
+    if (rr <= fmax(s.tol2, floor2)) {
+      s.done = t.done = 1;
+    } else if (s.stall >= 4 && rr <= s.tol2 * f * f) {
+      s.done = t.done = 1;
+    } else if (s.iters >= max_iter || s.stall >= 32) {
+      s.done = t.done = 3;
+    } else if (s.stall == 2) {
+      s.beta = t.beta = 0.0;
+    }
   }
 }
 
 __global__ __launch_bounds__(kFinThreads) void kfc_init(BSlot* slots, const double* part, int G, int Gp, int R,
-                                                         uint64_t mask, double rtol, SlotScales cs) {
+                                                         uint64_t mask, double rtol, SlotScales cs, double g) {
   __shared__ double lds[kFinThreads / kW];
   const int j = 2 * blockIdx.x;
   if (!((mask >> j) & 1ull)) return;
@@ -1958,10 +1978,13 @@ __global__ __launch_bounds__(kFinThreads) void kfc_init(BSlot* slots, const doub
     s.alpha = t.alpha = 0.0;
     s.rr = t.rr = rr;
     s.bb = t.bb = bb;
-    s.tol2 = t.tol2 = rtol * rtol * bb;
+    const double tol = rtol / (1.0 + sqrt(cs.c[j] * cs.c[j] + cs.c[j + 1] * cs.c[j + 1]) * g);
+    s.tol2 = t.tol2 = tol * tol * bb;
     s.iters = t.iters = 0;
     s.updates = t.updates = 0;
     s.rr_true = t.rr_true = 1;
+    s.rr_best = t.rr_best = rr;
+    s.stall = t.stall = 0;
     s.active = t.active = 1;
     s.done = t.done = rr <= s.tol2 ? 1 : 0;
   }
@@ -2094,7 +2117,7 @@ struct Launch {
       kbc_xupdate<T, R, kChunk><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
       kbc_residual<T, R, false, 6><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, 0ull,
                                                        SlotScales{}, w.chunk);
-      kfc_replace<<<R / 2, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
+      kfc_replace<<<R / 2, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter, w.cx_g);
     }
   }
   static void iterate(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k, int head) {
@@ -2111,7 +2134,7 @@ struct Launch {
         else
           kbc_residual<double, R, true, 6><<<g.G, kB, 0, s>>>(m, bvec<double>(w), w.slots, w.part, g.G, g.Gp, mask,
                                                               cs, w.chunk);
-        kfc_init<<<R / 2, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs);
+        kfc_init<<<R / 2, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, mask, rtol, cs, w.cx_g);
         return;
       }
     }

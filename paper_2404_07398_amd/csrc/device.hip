@@ -221,6 +221,7 @@ struct DeviceState {
   BatchWork bw;
   std::deque<BatchWork> spare;  // a deque: adding a tile leaves the others where they are
   BatchWork bwc;                 // complex tile of the shifted solves (order 2)
+  double k1_gnorm = 0.0;         // g >= ||K M^-1||_2 of the first-order operator (order >= 2)
   double* zero_rows = nullptr;   // n_pad zeros: the imaginary part of a field
   // grid sizes picked by the autotuner, per (tile size, precision), and the
   // tile size it found best per precision (0 = not tuned)
@@ -1352,6 +1353,15 @@ ifl_status device_create(Handle* h) {
     if ((st = upload(&k1.sptr, s1.slice_ptr)) || (st = upload(&k1.col, s1.col)) || (st = upload(&k1.val64, s1.val)) ||
         (st = upload(&k1.val32, w32)) || (st = upload(&k1.kdiag64, s1.diag)) || (st = upload(&k1.kdiag32, kd1)))
       return st;
+    // ||K M^-1||_2 <= ||K||_2 / min M, ||K||_2 <= the largest absolute row sum (K symmetric)
+    double rowmax = 0.0, mmin = INFINITY;
+    for (int64_t r = 0; r < h->op.n; ++r) {
+      double a = 0.0;
+      for (int64_t e = h->op.k1_row_ptr[r]; e < h->op.k1_row_ptr[r + 1]; ++e) a += std::fabs(h->op.k1_val[e]);
+      rowmax = std::max(rowmax, a);
+      if (h->op.mass[r] > 0.0) mmin = std::min(mmin, h->op.mass[r]);
+    }
+    d->k1_gnorm = std::isfinite(mmin) ? rowmax / mmin : 0.0;
   }
 
   // launch geometry: logical blocks own contiguous slice ranges
@@ -1683,7 +1693,11 @@ ifl_status run_ccolumn(Handle* h, const Mat& m, int head, double sr, double si, 
   }
   const int G = d->G, spb = d->spb;
   k_cinit<T><<<G, kBlock, 0, s>>>(m, v, w.phi, sw.part, sw.sc, sr, si, G, spb);
-  k_csetup<<<1, kBlock, 0, s>>>(sw.part, sw.sc, h->opt.rtol, G);
+  // order 2: the tolerance that makes the residual of S_2 itself meet rtol
+  // (the complex tiles' rule); other orders stop each shifted system at rtol
+  const double rtol = h->op.order == 2 ? h->opt.rtol / (1.0 + std::sqrt(sr * sr + si * si) * d->k1_gnorm)
+                                       : h->opt.rtol;
+  k_csetup<<<1, kBlock, 0, s>>>(sw.part, sw.sc, rtol, G);
   IFL_HIP(hipGetLastError());
   const int chunk = 8;
   const int max_iter = h->opt.max_iter;
@@ -1936,6 +1950,23 @@ static BatchMatrix batch_matrix_k1(DeviceState* d, int R, bool mixed) {
 }
 
 BatchMatrix handle_batch_matrix(Handle* h, int R, bool mixed) { return batch_matrix(h->dev, R, mixed); }
+BatchMatrix handle_batch_matrix_k1(Handle* h, int R, bool mixed) { return batch_matrix_k1(h->dev, R, mixed); }
+
+double handle_cx_gnorm(const Handle* h) { return h->dev ? h->dev->k1_gnorm : 0.0; }
+
+bool handle_cx_tiles(const Handle* h) {
+  return h->opt.solver == IFL_SOLVER_SHIFTED && h->op.order == 2 && h->dev && h->dev->k1.sptr &&
+         h->dev->k1.head <= 6;
+}
+
+// sigma = -b / w_0 for the shift pair with Im >= 0 (w_0 = exp(i pi / 2),
+// b = c^(1/2), c = gamma / k^4), as the one-column shifted solves take it
+void cx_shift(const Handle* h, double k, double* sigma_re, double* sigma_im) {
+  const double pi = 3.14159265358979323846, th = pi / 2;
+  const double b = std::sqrt(h->opt.gamma / std::pow(k, 4.0));
+  *sigma_re = -std::cos(th) * b;
+  *sigma_im = std::sin(th) * b;
+}
 double handle_mass_sum(const Handle* h) { return h->dev->m.mass_sum; }
 
 namespace {
@@ -2210,6 +2241,7 @@ ifl_status filter_batched_cx(Handle* h, int Rc, int32_t n_fields, const double* 
     if ((st = batch_alloc(&w, bm, R, mixed)) != IFL_OK) return st;
     w.cx = true;
   }
+  w.cx_g = d->k1_gnorm;
   if (!d->zero_rows) {
     if ((st = dalloc(&d->zero_rows, (size_t)bm.n_pad)) != IFL_OK) return st;
     k_fill_zero<<<(unsigned)((bm.n_pad + 255) / 256), 256, 0, s>>>(d->zero_rows, bm.n_pad);
@@ -2226,9 +2258,6 @@ ifl_status filter_batched_cx(Handle* h, int Rc, int32_t n_fields, const double* 
   BatchParams prm;
   prm.max_iter = h->opt.max_iter;
   prm.graphs = h->opt.graphs != 0;
-  // the shift of the pair with Im >= 0 (the same one the one-column solves take)
-  const double pi = 3.14159265358979323846, th = pi / 2;
-  const double sr = -std::cos(th), si = std::sin(th);
   std::vector<int64_t> slot_col(Rc, -1);
   std::vector<std::chrono::steady_clock::time_point> t_in(Rc);
   int64_t next = 0, finished = 0;
@@ -2241,11 +2270,9 @@ ifl_status filter_batched_cx(Handle* h, int Rc, int32_t n_fields, const double* 
       if (slot_col[q] >= 0) continue;
       const int64_t col = order[next++];
       const int64_t f = col / n_scales, sc = col % n_scales;
-      const double b = std::sqrt(h->opt.gamma / std::pow(k[sc], 4.0));
       src[2 * q] = d->field_rows + f * bm.n_pad;
       src[2 * q + 1] = d->zero_rows;
-      cs.c[2 * q] = sr * b;
-      cs.c[2 * q + 1] = si * b;
+      cx_shift(h, k[sc], &cs.c[2 * q], &cs.c[2 * q + 1]);
       slot_col[q] = col;
       t_in[q] = std::chrono::steady_clock::now();
       mask |= 3ull << (2 * q);
@@ -2303,7 +2330,7 @@ ifl_status device_filter(Handle* h, int32_t n_fields, const double* fields, int3
   const bool shifted = h->opt.solver == IFL_SOLVER_SHIFTED && h->op.order >= 2;
   // order 2 (one complex shift) in complex tiles of first-order operators
   // with narrow rows; other orders, and batch = 1, one column at a time
-  if (shifted && h->op.order == 2 && d->k1.head <= 6 && h->opt.batch != 1) {
+  if (handle_cx_tiles(h) && h->opt.batch != 1) {
     const int64_t ncols = (int64_t)n_fields * n_scales;
     int Rc = 1;
     if (h->opt.batch >= 2) {

@@ -81,6 +81,10 @@ struct Worker {
   // the handle solves with IFL_SOLVER_SHIFTED (order >= 2): columns one at a
   // time through the shifted first-order solves, no tile
   bool shifted = false;
+  // order 2 with IFL_SOLVER_SHIFTED in a complex tile (2 real slots per
+  // column: real and imaginary parts) over the first-order operator
+  bool cx = false;
+  double* zero_rows = nullptr;  // n_pad zeros: the imaginary part of a field
 };
 
 }  // namespace
@@ -239,15 +243,23 @@ ifl_status run_worker(Worker* wk) {
     uint64_t mask = 0;
     SlotScales cs{};
     const double* src[64] = {};
-    for (int j = 0; j < R && !wk->pending.empty(); ++j) {
+    // a column takes one slot, or in a complex tile the pair (j, j + 1)
+    const int step = wk->cx ? 2 : 1;
+    for (int j = 0; j < R && !wk->pending.empty(); j += step) {
       if (wk->slot[j].t) continue;
       const Column col = wk->pending.front();
       wk->pending.pop_front();
       src[j] = col.t->dev_field;
-      cs.c[j] = h->opt.gamma / std::pow(col.t->k[col.scale], 2.0 * h->op.order);
+      if (wk->cx) {
+        src[j + 1] = wk->zero_rows;
+        cx_shift(h, col.t->k[col.scale], &cs.c[j], &cs.c[j + 1]);
+        mask |= 3ull << j;
+      } else {
+        cs.c[j] = h->opt.gamma / std::pow(col.t->k[col.scale], 2.0 * h->op.order);
+        mask |= 1ull << j;
+      }
       wk->slot[j] = col;
       wk->t_in[j] = Clock::now();
-      mask |= 1ull << j;
       ++active;
     }
     if (mask) {
@@ -270,16 +282,16 @@ ifl_status run_worker(Worker* wk) {
     // 4. retire finished columns
     uint64_t fin = 0;
     std::vector<double*> dst(R, nullptr);
-    for (int j = 0; j < R; ++j) {
+    for (int j = 0; j < R; j += step) {
       if (!wk->slot[j].t || wk->w.slots_host[j].done == 0) continue;
-      fin |= 1ull << j;
+      fin |= (wk->cx ? 3ull : 1ull) << j;
       if (wk->slot[j].t->out) dst[j] = wk->col_out + (int64_t)j * wk->L;
     }
     if (!fin) continue;
     if ((st = batch_finish(wk->bm, wk->w, fin, dst.data(), wk->stream)) != IFL_OK) return st;
     if ((st = batch_read_slots(wk->w, wk->stream)) != IFL_OK) return st;
     const auto now = Clock::now();
-    for (int j = 0; j < R; ++j) {
+    for (int j = 0; j < R; j += step) {
       if (!((fin >> j) & 1ull)) continue;
       const Column col = wk->slot[j];
       ifl_ticket* t = col.t;
@@ -406,8 +418,15 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
   wk->L = h->op.field_len;
   s->device = h->opt.device;
   if (hipSetDevice(h->opt.device) != hipSuccess) return fail(IFL_EDEVICE, "hipSetDevice failed");
-  wk->shifted = h->opt.solver == IFL_SOLVER_SHIFTED && h->op.order >= 2;
-  wk->bm = handle_batch_matrix(h, wk->R, h->opt.precision == IFL_MIXED);
+  wk->cx = handle_cx_tiles(h);
+  wk->shifted = h->opt.solver == IFL_SOLVER_SHIFTED && h->op.order >= 2 && !wk->cx;
+  if (wk->cx) {
+    if (s->slots > 32) return fail(IFL_EINVAL, "complex tiles of order-2 shifted handles hold at most 32 slots");
+    wk->R = 2 * s->slots;
+    wk->bm = handle_batch_matrix_k1(h, wk->R, h->opt.precision == IFL_MIXED);
+  } else {
+    wk->bm = handle_batch_matrix(h, wk->R, h->opt.precision == IFL_MIXED);
+  }
   const int n_out = wk->shifted ? 1 : wk->R;  // output staging columns
   size_t work = 0;
   if (wk->shifted) {
@@ -415,6 +434,7 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
     if (ifl_status st = device_shift_work(h, &work)) return st;
   } else {
     work = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED, wk->bm.chunk);
+    if (wk->cx) work += sizeof(double) * (size_t)wk->bm.n_pad;  // zero imaginary parts
   }
   const size_t tile = work + sizeof(double) * (size_t)(n_out + 1) * wk->L;  // + output and field staging
   {
@@ -427,6 +447,14 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
   if (!wk->shifted) st = batch_alloc(&wk->w, wk->bm, wk->R, h->opt.precision == IFL_MIXED);
   else if (hipMalloc((void**)&wk->w.flag, sizeof(int)) != hipSuccess)  // only the field check's flag
     st = fail(IFL_ENOMEM, "hipMalloc of the field check flag failed");
+  if (st == IFL_OK && wk->cx) {
+    wk->w.cx = true;
+    wk->w.cx_g = handle_cx_gnorm(h);
+    if (hipMalloc((void**)&wk->zero_rows, sizeof(double) * (size_t)wk->bm.n_pad) != hipSuccess ||
+        hipMemset(wk->zero_rows, 0, sizeof(double) * (size_t)wk->bm.n_pad) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+      st = fail(IFL_ENOMEM, "allocation of the zero imaginary parts failed");
+  }
   if (st == IFL_OK && hipMalloc((void**)&wk->stage, sizeof(double) * (size_t)wk->L) != hipSuccess)
     st = fail(IFL_ENOMEM, "hipMalloc of the field staging failed");
   if (st == IFL_OK && hipMalloc((void**)&wk->col_out, sizeof(double) * (size_t)n_out * wk->L) != hipSuccess)
@@ -437,6 +465,7 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
     batch_free(&wk->w);
     if (wk->col_out) (void)hipFree(wk->col_out);
     if (wk->stage) (void)hipFree(wk->stage);
+    if (wk->zero_rows) (void)hipFree(wk->zero_rows);
     std::lock_guard<std::mutex> lk(s->mu);
     s->tiles -= tile;
     return st;
@@ -569,6 +598,7 @@ void ifl_server_destroy(ifl_server* s) {
     batch_free(&wk->w);
     if (wk->col_out) (void)hipFree(wk->col_out);
     if (wk->stage) (void)hipFree(wk->stage);
+    if (wk->zero_rows) (void)hipFree(wk->zero_rows);
     for (double* f : wk->field_pool) (void)hipFree(f);
     if (wk->stream) (void)hipStreamDestroy(wk->stream);
   }

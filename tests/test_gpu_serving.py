@@ -281,10 +281,11 @@ def test_server_cancel(ifl):
 
 
 def test_served_shifted_solver(ifl):
-    """A handle of order 2 with IFL_SOLVER_SHIFTED is served column by
-    column through the shifted first-order solves, beside a first-order
-    handle served in tiles: each result equals the oracle's shifted solve
-    within its precision's bar and, bitwise, the handle's own ifl_filter."""
+    """A handle of order 2 with IFL_SOLVER_SHIFTED is served in a complex
+    tile (two real slots per column) over its first-order operator, beside
+    a first-order handle served in a real tile: each result equals the
+    oracle's shifted solve within its precision's bar and, bitwise, the
+    handle's own ifl_filter in complex tiles of the same width."""
     s = W.icosphere(5, jitter=0.1)
     s = s.with_mask(W.land_mask(s, 0.3))
     op2 = O.scalar_operator(s, 2)
@@ -292,6 +293,7 @@ def test_served_shifted_solver(ifl):
     h1 = ifl.prepare_mesh(s, 0, 1, precision=ifl.IFL_MIXED)
     fields = [W.sphere_k3_field(s, 800 + i, n_waves=64) for i in range(3)]
     ks = W.log_scales(s.h, 5)
+    h2.set_options(batch=8)  # complex tiles of 4 columns, as the server's 4 slots
     alone = [h2.filter(f, ks)[0][0] for f in fields]
     srv = ifl.Server(4 << 30, slots=4)
     m2, m1 = srv.add(h2), srv.add(h1)
