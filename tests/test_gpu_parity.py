@@ -602,6 +602,27 @@ def test_shifted_complex_tiles(ifl, precision, batch):
     h.close()
 
 
+def test_complex_tiles_stall_safeguard_level9(ifl):
+    """A mixed-precision complex-tile column that stalled near the tightened
+    order-2 tolerance (level-9 sphere, 30% land, wavelength 26.6h, 8-column
+    complex tiles) ran to max_iter before the stall rule; it now stops at
+    the attainable accuracy, within the mixed bar of the one-column solve."""
+    s = W.icosphere(9, jitter=0.1, seed=1)
+    s = s.with_mask(W.land_mask(s, 0.3, n_blobs=40, seed=2))
+    f = np.asarray(W.sphere_k3_field(s, 3090, n_waves=256, device="cuda"))
+    ks = np.array([2 * np.pi / (w * s.h) for w in (26.62, 16.0, 8.0)])
+    h = _prep(ifl, s, n=2, precision=ifl.IFL_MIXED, batch=16, solver=ifl.IFL_SOLVER_SHIFTED, max_iter=4000)
+    tiles, st = h.filter(f, ks)
+    h.set_options(batch=1)
+    single, st1 = h.filter(f, ks)
+    for j in range(len(ks)):
+        d = relative_l2(tiles[0, j], single[0, j])
+        print(f"L9 stall case j={j} it={st[j].iterations}/{st1[j].iterations} relres={st[j].rel_residual:.1e} "
+              f"tiles-vs-single={d:.2e}")
+        assert st[j].status == 0 and st[j].iterations < 1000 and d <= TOL_MIXED
+    h.close()
+
+
 @pytest.mark.parametrize("placement", ["vertex_vector", "cell_vector"])
 def test_pair_kernels_match_single_column(ifl, placement):
     """Vertex vectors run the 2 x 2-block gathering kernels in tiles
