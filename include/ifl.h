@@ -119,10 +119,11 @@ typedef struct ifl_options {
                         with first-order rows of at most 6 entries 90% of the time), other orders and
                         batch = 1 one column at a time; the serving engine serves n = 2 in a complex
                         tile of 2 x slots real columns (slots <= 32), other orders one column at a
-                        time. n = 2 stops each shifted system at rtol / (1 + |sigma| g), g >=
-                        ||K M^-1||, so that the residual of S_2 meets rtol (a tile column whose
-                        residual stalls above that stops at rtol on the shifted system). Tiles report
-                        the shifted system's FP64 true residual in rel_residual */
+                        time. Each shifted system stops on its own FP64 true residual: at rtol one
+                        column at a time; in n = 2 tiles at rtol / (1 + |sigma| g), g >= ||K M^-1||,
+                        so that the residual of S_2 meets rtol (a tile column whose residual stalls
+                        above that stops at rtol). Tiles report the shifted system's FP64 true
+                        residual in rel_residual, one column at a time that of S_n */
 } ifl_options;
 
 /* Per-solve statistics (one per field x scale). */
