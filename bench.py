@@ -563,7 +563,7 @@ def serve_leg(args, ifl):
 
     res = {"workload": f"icosphere levels {args.serve_levels} (30% land mask) x n in {{1,2}}, "
                        f"{args.serve_slots} slots per mesh, mixed precision, 1-32 log-uniform scales per request; "
-                       + ("n = 2 requests by the shifted first-order solves, one column at a time"
+                       + ("n = 2 requests by the shifted first-order solves in complex tiles"
                           if args.serve_n2_solver == "shifted" else "n = 2 requests by Jacobi-PCG on K_2 in tiles"),
            "prepare_s": round(prep_s, 1), "budget_bytes": int(args.serve_budget_gib * (1 << 30))}
     res["stream"] = stream(args.serve_rate, draw(args.serve_warmup + args.serve_requests), args.serve_warmup, True,
