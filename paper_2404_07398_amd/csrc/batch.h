@@ -28,6 +28,8 @@ struct BSlot {
   double energy2;   // final sum M x^2
   double rr_best;   // complex tiles: the smallest true ||r||^2 so far (stall detection)
   double alpha_hist[kChunk];  // alpha of each iteration of the current chunk (0 if not iterating)
+  double beta_hist[kChunk];   // beta of each iteration of the current chunk (p_k = z_k + beta_k p_k-1)
+  double pq;                  // (p, S p) of the last iteration
   int32_t active;   // slot holds a column
   int32_t done;     // 0 running, 1 converged, 2 breakdown, 3 max_iter
   int32_t iters;    // CG iterations of this column
@@ -90,12 +92,16 @@ struct BatchWork {
   // ||M phi||^2, g >= ||K M^-1||_2 (the handle's bound), so that the residual
   // of S_2 itself, Re r + b K M^-1 Im r, meets rtol
   double cx_g = 0.0;
-  // p cycles through kChunk buffers, so that the directions of a whole
-  // chunk are still there when x is updated at its last iteration; z and
-  // u = diag(S)^-1 S p alternate between two buffers (an iteration gathers
-  // the previous ones while it writes the new)
-  float *z32[2] = {}, *u32[2] = {}, *p32[kChunk] = {};
-  double *z64[2] = {}, *u64[2] = {}, *p64[kChunk] = {};
+  // Vectors of a chunk. u = diag(S)^-1 S p alternates between two buffers
+  // (an iteration gathers the previous one while it writes the new).
+  // zrec (scalar tiles): z_k of iteration k stays in z[k] for the whole
+  // chunk, the carried direction in p[kChunk - 1], and the x update rebuilds
+  // the chunk's directions from them. Otherwise (2 x 2-block and complex
+  // tiles) z alternates between z[0] and z[1] and p cycles through kChunk
+  // buffers, so that the chunk's directions are there at its x update.
+  bool zrec = false;
+  float *z32[kChunk] = {}, *u32[2] = {}, *p32[kChunk] = {};
+  double *z64[kChunk] = {}, *u64[2] = {}, *p64[kChunk] = {};
   double* x = nullptr;    // FP64 solution, rows x R (updated once per chunk)
   double* phi = nullptr;  // FP64 fields, rows x R
   double* part = nullptr; // per-(quantity, column, block) partial sums
@@ -115,13 +121,18 @@ struct SlotScales {
   double c[64];
 };
 
-size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk);
+// Device bytes of a tile's work space (zrec: the scalar tiles' vector set,
+// see BatchWork).
+size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk, bool zrec);
 // Lanes that share one row in a tile of R columns (each lane owns 16 bytes of
 // columns: 4 FP32 or 2 FP64).
 int batch_lanes_per_row(int R, bool mixed);
 // Blocks of the batched SpMV kernel that are resident on the device at once.
 int batch_resident_blocks(int R, bool mixed, int device);
-ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed);
+// Allocate a tile of R columns; cx: a complex tile (of the first-order
+// operator). Scalar tiles (neither complex nor of 2 x 2 blocks) take the
+// zrec vector set.
+ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed, bool cx = false);
 void batch_free(BatchWork* w);
 
 ifl_status batch_clear_flag(BatchWork& w, hipStream_t s);

@@ -103,7 +103,7 @@ struct BMat {
 
 template <typename T>
 struct BVec {
-  T* z[2];       // preconditioned residual diag(S)^-1 r (two buffers, see kb_iter)
+  T* z[kChunk];  // preconditioned residual diag(S)^-1 r (per iteration of a chunk, or two buffers)
   T* u[2];       // diag(S)^-1 S p (two buffers)
   T* p[kChunk];  // directions of the chunk's iterations (p of iteration k in p[k])
   double* x;     // FP64 solution
@@ -270,23 +270,30 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 // (d = diag(S) = M + c diag(K_n), the Jacobi preconditioner; z = d^-1 r is
 // the residual state, r = d z is formed where it is needed):
 //
-//  FUSED (iterations 1..L-1 of a chunk of L), given alpha_k and beta_{k+1}:
-//    z' = z - alpha_k u                 (own row and every gathered neighbour)
-//    p' = z' + beta_{k+1} p
-//    u' = z' + d^-1 c K_off z' + beta_{k+1} u   (= d^-1 S p', as S p = S z' + beta S p)
-//  so z and u are the only gathered operands, and the separate residual
-//  update of plain CG disappears: the kernel reads z, u, p and writes z', u',
-//  p' once per row.
+//  FUSED (iterations 1..L-1 of a chunk of L), given alpha_k-1 and beta_k:
+//    z_k = z_k-1 - alpha_k-1 u_k-1        (own row and every gathered neighbour)
+//    u_k = z_k + d^-1 c K_off z_k + beta_k u_k-1   (= d^-1 S p_k, as
+//          S p_k = S z_k + beta_k S p_k-1 with p_k = z_k + beta_k p_k-1)
+//  so z and u are the only gathered operands and the only vectors a row
+//  reads and writes: the kernel reads z_k-1, u_k-1 and writes z_k (kept in
+//  z[k] for the x update) and u_k (not at the chunk's last iteration, whose
+//  u nothing reads). The directions p_k are never formed here; the chunk's x
+//  update rebuilds them from z_0..z_L-1 and the carried p_-1.
 //  DIRECT (the first iteration of a chunk, after the FP64 residual
-//  replacement has set z): p' = z + beta p, u' = d^-1 S p' from p' of the
-//  row and its gathered neighbours, so the recurrence for u never spans more
-//  than a chunk.
+//  replacement has set z_0): p_0 = z_0 + beta_0 p_-1 from the carried
+//  direction, u_0 = d^-1 S p_0 from p_0 of the row and its gathered
+//  neighbours, so the recurrence for u never spans more than a chunk.
 //
 // Partials per column (one grid-level reduction per iteration, finished by
-// kf_step): (p', q') = sum d p' u', sum d z' u', sum d u'^2, and (FUSED) rho =
-// (r', z') = sum d z'^2. From them, alpha = rho / (p', q') and the next rho =
-// (r - alpha q, z - alpha d^-1 q) = rho - 2 alpha (q, z) + alpha^2 (q, d^-1 q),
-// which gives beta for the next launch before the next z exists.
+// kf_step): sum d z_k u_k = (z_k, q_k), sum d u_k^2 = (q_k, d^-1 q_k), and
+//   DIRECT: sum d p_0 u_0 = (p_0, q_0);
+//   FUSED:  sum d u_k-1 z_k = (q_k-1, z_k) and rho_k = (r_k, z_k) = sum d z_k^2.
+// With S symmetric, (p_k, q_k) = (z_k, q_k) + beta_k (p_k-1, q_k) and
+// (p_k-1, q_k) = (q_k-1, p_k) = (q_k-1, z_k) + beta_k (p_k-1, q_k-1), which
+// gives (p_k, q_k) from the partials and the last iteration's (p, q) with
+// no conjugacy assumed. Then alpha_k = rho_k / (p_k, q_k) and the next rho =
+// (r - alpha q, z - alpha d^-1 q) = rho - 2 alpha (q, z) + alpha^2 (q, d^-1 q)
+// gives beta for the next launch before the next z exists.
 //
 // The loop over a wavefront's tasks is software-pipelined so that a task
 // costs about one memory round trip instead of three. While the gathers of
@@ -319,18 +326,17 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
     c64[c] = sl.c;
     any |= on[c];
   }
-  // buffers: the chunk's first iteration reads z[0] (set by the replacement)
-  // and writes u[0]; iteration k >= 1 reads z, u [(k - 1) & 1] and writes
-  // z, u [k & 1] (the replacement at the chunk's end writes z[0] again)
-  const int bin = FUSED ? ((k - 1) & 1) : 0, bout = FUSED ? (k & 1) : 0;
-  const T* __restrict__ zin = v.z[bin];
-  const T* __restrict__ uin = v.u[bin];
-  T* __restrict__ zout = v.z[bout];
-  T* __restrict__ uout = v.u[bout];
-  const T* __restrict__ pin = v.p[(k + L - 1) % L];  // previous iteration's p
-  T* __restrict__ pout = v.p[k];
+  // buffers: iteration k reads z[k - 1] (DIRECT: z[0], set by the
+  // replacement) and writes z[k]; u alternates, u_k in u[k & 1]; DIRECT
+  // reads the carried direction p_-1 in p[L - 1]
+  const T* __restrict__ zin = v.z[FUSED ? k - 1 : 0];
+  T* __restrict__ zout = v.z[k];
+  const T* __restrict__ uin = v.u[(k + 1) & 1];
+  T* __restrict__ uout = v.u[k & 1];
+  const T* __restrict__ pin = v.p[L - 1];
+  const bool keep_u = k < L - 1;
   const T* __restrict__ val = bval<T>(m);
-  // value of a gathered neighbour: z' (FUSED) or p' (DIRECT); g1 is u or p
+  // value of a gathered neighbour: z_k (FUSED) or p_0 (DIRECT); g1 is u or p
   const auto comb = [&](int c, T g0, T g1) { return FUSED ? fma(-alpha[c], g1, g0) : fma(beta[c], g1, g0); };
   double acc[NQ][C] = {};
   if (any) {
@@ -344,7 +350,7 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
     auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
     int32_t cu[H];
     T vu[H];
-    Pack<T, C> zi, ui, pi;
+    Pack<T, C> zi, gi;  // own row: z and (FUSED) u or (DIRECT) p
     double mi, kd;
     int64_t base, nb, ne;  // this task's slice base; next task's raw slice bounds
     int w;
@@ -361,8 +367,7 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
       for (int u = 0; u < H; ++u) vu[u] = val[sb + (int64_t)u * kW + l];
       const int64_t idx = row * R + j0;
       zi = vload<T, C>(zin + idx);
-      pi = vload<T, C>(pin + idx);
-      if constexpr (FUSED) ui = vload<T, C>(uin + idx);
+      gi = vload<T, C>((FUSED ? uin : pin) + idx);
       mi = m.mass[row];
       kd = m.kdiag[row];
     };
@@ -413,24 +418,29 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
                                                          FUSED ? uin : pin, comb, a, H);
       const bool real = row < m.n;
       const int64_t idx = row * R + j0;
-      Pack<T, C> zn, pn, un;
+      Pack<T, C> zn, un;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const T d = real ? (T)(mi + c64[c] * kd) : (T)1;
-        zn.v[c] = FUSED ? fma(-alpha[c], ui.v[c], zi.v[c]) : zi.v[c];
-        pn.v[c] = fma(beta[c], pi.v[c], zn.v[c]);
-        const T su = zn.v[c] + (cc[c] * a[c]) / d;  // d^-1 S z' (FUSED) or d^-1 S p' - p' + z (DIRECT)
-        un.v[c] = FUSED ? fma(beta[c], ui.v[c], su) : pn.v[c] + (cc[c] * a[c]) / d;
-        const double dd = (double)d, uu = (double)un.v[c], zz = (double)zn.v[c];
+        const double dd = (double)d;
         const bool use = on[c] && real;
-        acc[0][c] += use ? dd * (double)pn.v[c] * uu : 0.0;
-        acc[1][c] += use ? dd * zz * uu : 0.0;
+        if constexpr (FUSED) {
+          zn.v[c] = fma(-alpha[c], gi.v[c], zi.v[c]);
+          un.v[c] = fma(beta[c], gi.v[c], zn.v[c] + (cc[c] * a[c]) / d);
+          acc[0][c] += use ? dd * (double)gi.v[c] * (double)zn.v[c] : 0.0;
+          acc[NQ - 1][c] += use ? dd * (double)zn.v[c] * (double)zn.v[c] : 0.0;
+        } else {
+          zn.v[c] = zi.v[c];
+          const T pn = fma(beta[c], gi.v[c], zi.v[c]);
+          un.v[c] = pn + (cc[c] * a[c]) / d;
+          acc[0][c] += use ? dd * (double)pn * (double)un.v[c] : 0.0;
+        }
+        const double uu = (double)un.v[c];
+        acc[1][c] += use ? dd * (double)zn.v[c] * uu : 0.0;
         acc[2][c] += use ? dd * uu * uu : 0.0;
-        if constexpr (FUSED) acc[NQ - 1][c] += use ? dd * zz * zz : 0.0;
       }
       if (real) {
-        vstore<T, C>(pout + idx, pn);
-        vstore<T, C>(uout + idx, un);
+        if (keep_u) vstore<T, C>(uout + idx, un);
         if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
       }
       // (e) values and own row of the next task
@@ -449,24 +459,31 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
 }
 
 // The chunk's x update, at its last iteration, in FP64 in every precision,
-// from the directions kept in p[0..L) and each column's alpha history:
 // x += sum_k alpha_k p_k (alpha_k = 0 for a column that was not iterating).
-template <typename T, int R, int L>
+// ZREC: the directions are rebuilt from the chunk's z_k and the carried
+// p_-1, p_k = z_k + beta_k p_k-1 (in FP64), and p_L-1 is carried to the
+// next chunk in place of p_-1 (columns that did not iterate keep theirs);
+// otherwise they are read from p[0..L).
+template <typename T, int R, int L, bool ZREC>
 __global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot* slots, int G) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
-  double ah[L][C];
+  double ah[L][C], bh[L][C];
+  bool moved[C];
   bool any = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const BSlot& sl = slots[j0 + c];
+    moved[c] = false;
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       ah[i][c] = sl.alpha_hist[i];
-      any |= ah[i][c] != 0.0;
+      bh[i][c] = sl.beta_hist[i];
+      moved[c] |= ah[i][c] != 0.0;
     }
+    any |= moved[c];
   }
   if (!any) return;
   for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
@@ -475,12 +492,27 @@ __global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot*
     const int64_t idx = row * R + j0;
     Pack<T, C> pk[L];
 #pragma unroll
-    for (int i = 0; i < L; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
+    for (int i = 0; i < L; ++i) pk[i] = vload<T, C>((ZREC ? v.z[i] : v.p[i]) + idx);
     Pack<double, C> xv = vload<double, C>(v.x + idx);
+    if constexpr (ZREC) {
+      Pack<T, C> pc = vload<T, C>(v.p[L - 1] + idx);
 #pragma unroll
-    for (int c = 0; c < C; ++c)
+      for (int c = 0; c < C; ++c) {
+        double pd = (double)pc.v[c];
 #pragma unroll
-      for (int i = 0; i < L; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
+        for (int i = 0; i < L; ++i) {
+          pd = fma(bh[i][c], pd, (double)pk[i].v[c]);
+          xv.v[c] = fma(ah[i][c], pd, xv.v[c]);
+        }
+        if (moved[c]) pc.v[c] = (T)pd;
+      }
+      vstore<T, C>(v.p[L - 1] + idx, pc);
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int i = 0; i < L; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
+    }
     vstore<double, C>(v.x + idx, xv);
   }
 }
@@ -1747,36 +1779,46 @@ __device__ __forceinline__ double fin_sum(const double* a, int G, double* lds) {
   return t;
 }
 
-// After iteration k of a chunk (kb_iter): alpha_k = rho_k / (p, q), kept
-// in the column's alpha history at position k (0 for columns not
-// iterating); the next rho from the recurrence rho - 2 alpha (q, z) +
-// alpha^2 (q, d^-1 q), and beta = next rho / rho_k for the next launch. rho_k
-// is the exact (r, z) of the z the launch formed (k >= 1), or that of the
-// replacement or start (k = 0). No stopping test: a column is tested on its
-// replaced FP64 residual only, in kf_replace.
+// After iteration k of a chunk (kb_iter, kb_iter2): alpha_k = rho_k / (p,
+// q), kept in the column's alpha history at position k (0 for columns not
+// iterating) beside the beta the launch used; the next rho from the
+// recurrence rho - 2 alpha (q, z) + alpha^2 (q, d^-1 q), and beta = next rho
+// / rho_k for the next launch. rho_k is the exact (r, z) of the z the launch
+// formed (k >= 1), or that of the replacement or start (k = 0). (p, q) is
+// the launch's partial, or (zrec, k >= 1) (z, q) + beta ((q_prev, z) + beta
+// (p, q)_prev) from the partials of kb_iter's z-recurrence form. No stopping
+// test: a column is tested on its replaced FP64 residual only, in
+// kf_replace.
 __global__ __launch_bounds__(kFinThreads) void kf_step(BSlot* slots, const double* part, int G, int Gp, int R,
-                                                        int k) {
+                                                        int k, bool zrec) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
   if (!live(s)) {
-    if (threadIdx.x == 0) s.alpha_hist[k] = 0.0;
+    if (threadIdx.x == 0) {
+      s.alpha_hist[k] = 0.0;
+      s.beta_hist[k] = 0.0;
+    }
     return;
   }
-  const double pq = fin_sum(part + (Q_PQ * R + j) * Gp, G, lds);
+  const double p0 = fin_sum(part + (Q_PQ * R + j) * Gp, G, lds);
   const double zu = fin_sum(part + (Q_ZU * R + j) * Gp, G, lds);
   const double uu = fin_sum(part + (Q_UU * R + j) * Gp, G, lds);
   const double rz = k > 0 ? fin_sum(part + (Q_RZ * R + j) * Gp, G, lds) : 0.0;
   if (threadIdx.x == 0) {
+    const double b = s.beta;
+    const double pq = zrec && k > 0 ? zu + b * (p0 + b * s.pq) : p0;
     const double rho = k > 0 ? rz : s.rho;
     const double a = rho / pq;
     s.iters += 1;
+    s.beta_hist[k] = b;
     if (!(pq > 0.0) || !isfinite(a)) {
       s.done = 2;
       s.alpha_hist[k] = 0.0;
     } else {
       const double next = rho - 2.0 * a * zu + a * a * uu;
       s.rho = rho;
+      s.pq = pq;
       s.alpha = a;
       s.alpha_hist[k] = a;
       s.beta = next / rho;
@@ -1994,17 +2036,17 @@ template <typename T>
 BVec<T> bvec(BatchWork& w) {
   BVec<T> v{};
   if constexpr (sizeof(T) == 4) {
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 2; ++i) v.u[i] = w.u32[i];
+    for (int i = 0; i < kChunk; ++i) {
       v.z[i] = w.z32[i];
-      v.u[i] = w.u32[i];
+      v.p[i] = w.p32[i];
     }
-    for (int i = 0; i < kChunk; ++i) v.p[i] = w.p32[i];
   } else {
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 2; ++i) v.u[i] = w.u64[i];
+    for (int i = 0; i < kChunk; ++i) {
       v.z[i] = w.z64[i];
-      v.u[i] = w.u64[i];
+      v.p[i] = w.p64[i];
     }
-    for (int i = 0; i < kChunk; ++i) v.p[i] = w.p64[i];
   }
   v.x = w.x;
   v.phi = w.phi;
@@ -2098,9 +2140,10 @@ struct Launch {
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
     by_head<T>(m, head, [&](auto L) { L.template iter<T>(m, w, g, s, k); });
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
-    kf_step<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
+    kf_step<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k, w.zrec);
     if (k == w.chunk - 1) {
-      kb_xupdate<T, R, kChunk><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
+      if (w.zrec) kb_xupdate<T, R, kChunk, true><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
+      else kb_xupdate<T, R, kChunk, false><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
       by_head<T>(m, head, [&](auto L) { L.template replace<T>(m, w, g, s); });
       kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
     }
@@ -2222,31 +2265,39 @@ int batch_lanes_per_row(int R, bool mixed) {
   return R / C;
 }
 
-ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed) {
+ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed, bool cx) {
   const size_t nr = (size_t)bm.n_pad * R;
-  // the x update (kb_xupdate<T, R, kChunk>) reads kChunk direction buffers
+  // the x update (kb_xupdate<T, R, kChunk, .>) reads kChunk z or p buffers
   if (bm.chunk != kChunk) return fail(IFL_EINVAL, "tile chunk length differs from the kernels' kChunk");
   const int chunk = bm.chunk;
+  const bool zrec = !bm.pairs && !cx;
   ifl_status st;
   std::vector<void*> vecs;  // the precision's vectors, zeroed below
   size_t es = 0;
+  // zrec: z[0..chunk), u[0..2), p[chunk - 1]; otherwise z[0..2), u[0..2), p[0..chunk)
+  auto pick = [&](auto& z, auto& u, auto& dir) {
+    std::vector<std::remove_reference_t<decltype(z[0])>*> all = {&u[0], &u[1], &z[0], &z[1], &dir[chunk - 1]};
+    if (zrec)
+      for (int i = 2; i < chunk; ++i) all.push_back(&z[i]);
+    else
+      for (int i = 0; i < chunk - 1; ++i) all.push_back(&dir[i]);
+    return all;
+  };
   if (mixed) {
     es = sizeof(float);
-    std::vector<float**> all = {&w->z32[0], &w->z32[1], &w->u32[0], &w->u32[1]};
-    for (int i = 0; i < chunk; ++i) all.push_back(&w->p32[i]);
-    for (float** p : all) {
+    for (float** p : pick(w->z32, w->u32, w->p32)) {
       if ((st = dalloc_b(p, nr))) return st;
       vecs.push_back(*p);
     }
   } else {
     es = sizeof(double);
-    std::vector<double**> all = {&w->z64[0], &w->z64[1], &w->u64[0], &w->u64[1]};
-    for (int i = 0; i < chunk; ++i) all.push_back(&w->p64[i]);
-    for (double** p : all) {
+    for (double** p : pick(w->z64, w->u64, w->p64)) {
       if ((st = dalloc_b(p, nr))) return st;
       vecs.push_back(*p);
     }
   }
+  w->zrec = zrec;
+  w->cx = cx;
   if ((st = dalloc_b(&w->x, nr)) || (st = dalloc_b(&w->phi, nr)) ||
       (st = dalloc_b(&w->part, (size_t)Q_COUNT * R * std::max(bm.G, bm.Gu))) || (st = dalloc_b(&w->slots, (size_t)R)) ||
       (st = dalloc_b(&w->flag, 1)))
@@ -2278,9 +2329,11 @@ int chunk_for_order(int) { return kChunk; }
 
 void batch_free(BatchWork* w) {
   if (w->chunk_exec) (void)hipGraphExecDestroy(w->chunk_exec);
-  std::vector<void*> ptrs = {w->z32[0], w->z32[1], w->u32[0], w->u32[1], w->z64[0], w->z64[1], w->u64[0],
-                             w->u64[1], w->x,      w->phi,    w->part,   w->slots,  w->flag};
+  std::vector<void*> ptrs = {w->u32[0], w->u32[1], w->u64[0], w->u64[1], w->x,
+                             w->phi,    w->part,   w->slots,  w->flag};
   for (int i = 0; i < kChunk; ++i) {
+    ptrs.push_back(w->z32[i]);
+    ptrs.push_back(w->z64[i]);
     ptrs.push_back(w->p32[i]);
     ptrs.push_back(w->p64[i]);
   }
@@ -2290,8 +2343,9 @@ void batch_free(BatchWork* w) {
   *w = BatchWork();
 }
 
-size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk) {
-  const size_t per = (size_t)(4 + chunk) * (mixed ? 4 : 8) + 8 + 8;  // z, u (x2), p (x chunk), x, phi
+size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk, bool zrec) {
+  // zrec: z (x chunk), u (x2), p; otherwise z, u (x2), p (x chunk); and x, phi
+  const size_t per = (size_t)(zrec ? chunk + 3 : chunk + 4) * (mixed ? 4 : 8) + 8 + 8;
   return (size_t)n_pad * R * per;
 }
 
@@ -2371,7 +2425,8 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
   // pair kernels: block entries (index + four values) over slices of block rows
   if (bm.pairs)
     return (double)bm.pnnz * (4.0 + 4.0 * vb) + 8.0 * (bm.nb_slices + 1) + 16.0 * bm.n + 6.0 * vb * bm.n * live;
-  return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 6.0 * vb * bm.n * live;
+  // scalar tiles (z-recurrence form): z and u read, z and u written per column
+  return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 4.0 * vb * bm.n * live;
 }
 
 // Capture one chunk (w.chunk iterations, no timing events) into w.chunk_exec.
@@ -2406,6 +2461,7 @@ static ifl_status capture_chunk(const BMat& m, const BatchMatrix& bm, BatchWork&
 
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s) {
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
+  if (w.zrec == (bm.pairs || w.cx)) return fail(IFL_EINVAL, "tile vectors were allocated for another matrix form");
   if (n_iter % w.chunk != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of the tile's chunk");
   const BMat m = bmat(bm);
   // the timing events (if any) go around the SpMV of the call's second

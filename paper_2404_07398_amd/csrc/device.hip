@@ -2237,8 +2237,7 @@ ifl_status filter_batched_cx(Handle* h, int Rc, int32_t n_fields, const double* 
   if (!w.slots || w.R != R || w.mixed != mixed || w.G != bm.G || w.Gu != bm.Gu) {
     batch_free(&w);
     w = BatchWork();
-    if ((st = batch_alloc(&w, bm, R, mixed)) != IFL_OK) return st;
-    w.cx = true;
+    if ((st = batch_alloc(&w, bm, R, mixed, true)) != IFL_OK) return st;
   }
   w.cx_g = d->k1_gnorm;
   if (!d->zero_rows) {

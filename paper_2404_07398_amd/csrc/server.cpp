@@ -433,7 +433,8 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
     std::lock_guard<std::mutex> lk(h->mu);
     if (ifl_status st = device_shift_work(h, &work)) return st;
   } else {
-    work = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED, wk->bm.chunk);
+    work = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED, wk->bm.chunk,
+                       !wk->cx && !wk->bm.pairs);
     if (wk->cx) work += sizeof(double) * (size_t)wk->bm.n_pad;  // zero imaginary parts
   }
   const size_t tile = work + sizeof(double) * (size_t)(n_out + 1) * wk->L;  // + output and field staging
@@ -444,11 +445,10 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
     s->tiles += tile;
   }
   ifl_status st = IFL_OK;
-  if (!wk->shifted) st = batch_alloc(&wk->w, wk->bm, wk->R, h->opt.precision == IFL_MIXED);
+  if (!wk->shifted) st = batch_alloc(&wk->w, wk->bm, wk->R, h->opt.precision == IFL_MIXED, wk->cx);
   else if (hipMalloc((void**)&wk->w.flag, sizeof(int)) != hipSuccess)  // only the field check's flag
     st = fail(IFL_ENOMEM, "hipMalloc of the field check flag failed");
   if (st == IFL_OK && wk->cx) {
-    wk->w.cx = true;
     wk->w.cx_g = handle_cx_gnorm(h);
     if (hipMalloc((void**)&wk->zero_rows, sizeof(double) * (size_t)wk->bm.n_pad) != hipSuccess ||
         hipMemset(wk->zero_rows, 0, sizeof(double) * (size_t)wk->bm.n_pad) != hipSuccess ||
