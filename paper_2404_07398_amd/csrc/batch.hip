@@ -260,6 +260,12 @@ struct Ident {
 // the rest in steps of the same width, unpipelined.
 constexpr int kHeadClasses[] = {6, 12, 20};
 
+// a / d in the iteration kernels: FP32 tiles multiply by the hardware
+// reciprocal (1 ulp), a rounding of the kind their recurrences already
+// carry; FP64 tiles divide
+__device__ __forceinline__ float over(float a, float d) { return a * __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double over(double a, double d) { return a / d; }
+
 __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
@@ -422,22 +428,28 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const T d = real ? (T)(mi + c64[c] * kd) : (T)1;
-        const double dd = (double)d;
-        const bool use = on[c] && real;
+        // the row's weight in the column's partials (0 where the row or the
+        // column does not count); each product below is the weight times a
+        // vector in T, i.e. r = d z or d u, so no new range is needed, and
+        // it is summed in FP64
+        const T dw = on[c] && real ? d : (T)0;
+        const T su = over(cc[c] * a[c], d);  // d^-1 c K_off applied to the gathered operand
         if constexpr (FUSED) {
           zn.v[c] = fma(-alpha[c], gi.v[c], zi.v[c]);
-          un.v[c] = fma(beta[c], gi.v[c], zn.v[c] + (cc[c] * a[c]) / d);
-          acc[0][c] += use ? dd * (double)gi.v[c] * (double)zn.v[c] : 0.0;
-          acc[NQ - 1][c] += use ? dd * (double)zn.v[c] * (double)zn.v[c] : 0.0;
+          un.v[c] = fma(beta[c], gi.v[c], zn.v[c] + su);
         } else {
           zn.v[c] = zi.v[c];
-          const T pn = fma(beta[c], gi.v[c], zi.v[c]);
-          un.v[c] = pn + (cc[c] * a[c]) / d;
-          acc[0][c] += use ? dd * (double)pn * (double)un.v[c] : 0.0;
+          un.v[c] = fma(beta[c], gi.v[c], zi.v[c]) + su;
         }
-        const double uu = (double)un.v[c];
-        acc[1][c] += use ? dd * (double)zn.v[c] * uu : 0.0;
-        acc[2][c] += use ? dd * uu * uu : 0.0;
+        const double rz = (double)(dw * zn.v[c]), ru = (double)(dw * un.v[c]), uu = (double)un.v[c];
+        if constexpr (FUSED) {
+          acc[0][c] = fma(rz, (double)gi.v[c], acc[0][c]);
+          acc[NQ - 1][c] = fma(rz, (double)zn.v[c], acc[NQ - 1][c]);
+        } else {
+          acc[0][c] = fma(ru, (double)fma(beta[c], gi.v[c], zi.v[c]), acc[0][c]);
+        }
+        acc[1][c] = fma(rz, uu, acc[1][c]);
+        acc[2][c] = fma(ru, uu, acc[2][c]);
       }
       if (real) {
         if (keep_u) vstore<T, C>(uout + idx, un);
