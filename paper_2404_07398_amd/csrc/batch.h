@@ -94,9 +94,9 @@ struct BatchWork {
   double cx_g = 0.0;
   // Vectors of a chunk. u = diag(S)^-1 S p alternates between two buffers
   // (an iteration gathers the previous one while it writes the new).
-  // zrec (scalar tiles): z_k of iteration k stays in z[k] for the whole
-  // chunk, the carried direction in p[kChunk - 1], and the x update rebuilds
-  // the chunk's directions from them. Otherwise (2 x 2-block and complex
+  // zrec (scalar tiles): z_k of iteration k < kChunk - 1 stays in z[k] for
+  // the whole chunk, the carried direction in p[kChunk - 1], and the x
+  // update rebuilds the chunk's directions from them. Otherwise (2 x 2-block and complex
   // tiles) z alternates between z[0] and z[1] and p cycles through kChunk
   // buffers, so that the chunk's directions are there at its x update.
   bool zrec = false;

@@ -282,9 +282,10 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 //          S p_k = S z_k + beta_k S p_k-1 with p_k = z_k + beta_k p_k-1)
 //  so z and u are the only gathered operands and the only vectors a row
 //  reads and writes: the kernel reads z_k-1, u_k-1 and writes z_k (kept in
-//  z[k] for the x update) and u_k (not at the chunk's last iteration, whose
-//  u nothing reads). The directions p_k are never formed here; the chunk's x
-//  update rebuilds them from z_0..z_L-1 and the carried p_-1.
+//  z[k] for the x update) and u_k. The chunk's last iteration stores
+//  nothing: its u is never read, and the x update forms its z from z_L-2 and
+//  u_L-2. The directions p_k are never formed here; the chunk's x update
+//  rebuilds them from z_0..z_L-1 and the carried p_-1.
 //  DIRECT (the first iteration of a chunk, after the FP64 residual
 //  replacement has set z_0): p_0 = z_0 + beta_0 p_-1 from the carried
 //  direction, u_0 = d^-1 S p_0 from p_0 of the row and its gathered
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
   const T* __restrict__ uin = v.u[(k + 1) & 1];
   T* __restrict__ uout = v.u[k & 1];
   const T* __restrict__ pin = v.p[L - 1];
-  const bool keep_u = k < L - 1;
+  const bool keep = k < L - 1;  // the chunk's last z and u are never stored
   const T* __restrict__ val = bval<T>(m);
   // value of a gathered neighbour: z_k (FUSED) or p_0 (DIRECT); g1 is u or p
   const auto comb = [&](int c, T g0, T g1) { return FUSED ? fma(-alpha[c], g1, g0) : fma(beta[c], g1, g0); };
@@ -451,8 +452,8 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
         acc[1][c] = fma(rz, uu, acc[1][c]);
         acc[2][c] = fma(ru, uu, acc[2][c]);
       }
-      if (real) {
-        if (keep_u) vstore<T, C>(uout + idx, un);
+      if (real && keep) {
+        vstore<T, C>(uout + idx, un);
         if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
       }
       // (e) values and own row of the next task
@@ -472,10 +473,10 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
 
 // The chunk's x update, at its last iteration, in FP64 in every precision,
 // x += sum_k alpha_k p_k (alpha_k = 0 for a column that was not iterating).
-// ZREC: the directions are rebuilt from the chunk's z_k and the carried
-// p_-1, p_k = z_k + beta_k p_k-1 (in FP64), and p_L-1 is carried to the
-// next chunk in place of p_-1 (columns that did not iterate keep theirs);
-// otherwise they are read from p[0..L).
+// ZREC: the directions are rebuilt from the chunk's z_k (z_L-1 from z_L-2
+// and u_L-2) and the carried p_-1, p_k = z_k + beta_k p_k-1 (in FP64), and
+// p_L-1 is carried to the next chunk in place of p_-1 (columns that did not
+// iterate keep theirs); otherwise they are read from p[0..L).
 template <typename T, int R, int L, bool ZREC>
 __global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot* slots, int G) {
   using Gm = Geo<T, R>;
@@ -504,9 +505,13 @@ __global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot*
     const int64_t idx = row * R + j0;
     Pack<T, C> pk[L];
 #pragma unroll
-    for (int i = 0; i < L; ++i) pk[i] = vload<T, C>((ZREC ? v.z[i] : v.p[i]) + idx);
+    for (int i = 0; i < L - 1; ++i) pk[i] = vload<T, C>((ZREC ? v.z[i] : v.p[i]) + idx);
+    pk[L - 1] = vload<T, C>((ZREC ? v.u[(L - 2) & 1] : v.p[L - 1]) + idx);
     Pack<double, C> xv = vload<double, C>(v.x + idx);
     if constexpr (ZREC) {
+      // z_L-1 = z_L-2 - alpha_L-2 u_L-2, as the last iteration formed it
+#pragma unroll
+      for (int c = 0; c < C; ++c) pk[L - 1].v[c] = fma(-(T)ah[L - 2][c], pk[L - 1].v[c], pk[L - 2].v[c]);
       Pack<T, C> pc = vload<T, C>(v.p[L - 1] + idx);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -923,16 +928,16 @@ __global__ __launch_bounds__(kB) void kb_iter2(BMat m, BVec<T> v, const BSlot* s
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const T d = real ? (T)(mi[r] + c64[c] * kd[r]) : (T)1;
+          const T dw = on[c] && real ? d : (T)0;  // the row's weight in the partials (as kb_iter)
+          const T su = over(cc[c] * a[r][c], d);
           zn.v[c] = FUSED ? fma(-alpha[c], ui[r].v[c], zi[r].v[c]) : zi[r].v[c];
           pn.v[c] = fma(beta[c], pi[r].v[c], zn.v[c]);
-          const T su = zn.v[c] + (cc[c] * a[r][c]) / d;
-          un.v[c] = FUSED ? fma(beta[c], ui[r].v[c], su) : pn.v[c] + (cc[c] * a[r][c]) / d;
-          const double dd = (double)d, uu = (double)un.v[c], zz = (double)zn.v[c];
-          const bool use = on[c] && real;
-          acc[0][c] += use ? dd * (double)pn.v[c] * uu : 0.0;
-          acc[1][c] += use ? dd * zz * uu : 0.0;
-          acc[2][c] += use ? dd * uu * uu : 0.0;
-          if constexpr (FUSED) acc[NQ - 1][c] += use ? dd * zz * zz : 0.0;
+          un.v[c] = FUSED ? fma(beta[c], ui[r].v[c], zn.v[c] + su) : pn.v[c] + su;
+          const double rz = (double)(dw * zn.v[c]), ru = (double)(dw * un.v[c]), uu = (double)un.v[c];
+          acc[0][c] = fma(ru, (double)pn.v[c], acc[0][c]);
+          acc[1][c] = fma(rz, uu, acc[1][c]);
+          acc[2][c] = fma(ru, uu, acc[2][c]);
+          if constexpr (FUSED) acc[NQ - 1][c] = fma(rz, (double)zn.v[c], acc[NQ - 1][c]);
         }
         if (real) {
           vstore<T, C>(pout + idx, pn);
@@ -2286,11 +2291,11 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed, b
   ifl_status st;
   std::vector<void*> vecs;  // the precision's vectors, zeroed below
   size_t es = 0;
-  // zrec: z[0..chunk), u[0..2), p[chunk - 1]; otherwise z[0..2), u[0..2), p[0..chunk)
+  // zrec: z[0..chunk - 1), u[0..2), p[chunk - 1]; otherwise z[0..2), u[0..2), p[0..chunk)
   auto pick = [&](auto& z, auto& u, auto& dir) {
     std::vector<std::remove_reference_t<decltype(z[0])>*> all = {&u[0], &u[1], &z[0], &z[1], &dir[chunk - 1]};
     if (zrec)
-      for (int i = 2; i < chunk; ++i) all.push_back(&z[i]);
+      for (int i = 2; i < chunk - 1; ++i) all.push_back(&z[i]);
     else
       for (int i = 0; i < chunk - 1; ++i) all.push_back(&dir[i]);
     return all;
@@ -2356,8 +2361,8 @@ void batch_free(BatchWork* w) {
 }
 
 size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk, bool zrec) {
-  // zrec: z (x chunk), u (x2), p; otherwise z, u (x2), p (x chunk); and x, phi
-  const size_t per = (size_t)(zrec ? chunk + 3 : chunk + 4) * (mixed ? 4 : 8) + 8 + 8;
+  // zrec: z (x chunk - 1), u (x2), p; otherwise z, u (x2), p (x chunk); and x, phi
+  const size_t per = (size_t)(zrec ? chunk + 2 : chunk + 4) * (mixed ? 4 : 8) + 8 + 8;
   return (size_t)n_pad * R * per;
 }
 
