@@ -310,9 +310,9 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 // under the gathers of task i + 1. Vector memory operations complete in
 // issue order, so waiting for a batch of loads never waits for the loads
 // issued after it.
-template <typename T, int R, bool FUSED, int H>
-__global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                              int k, int L) {
+template <typename T, int R, bool FUSED, int H, bool KEEP>
+__device__ __forceinline__ void iter_body(const BMat& m, const BVec<T>& v, const BSlot* slots, double* part, int G,
+                                          int Gp, int k, int L) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   constexpr int NQ = FUSED ? 4 : 3;
@@ -341,7 +341,6 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
   const T* __restrict__ uin = v.u[(k + 1) & 1];
   T* __restrict__ uout = v.u[k & 1];
   const T* __restrict__ pin = v.p[L - 1];
-  const bool keep = k < L - 1;  // the chunk's last z and u are never stored
   const T* __restrict__ val = bval<T>(m);
   // value of a gathered neighbour: z_k (FUSED) or p_0 (DIRECT); g1 is u or p
   const auto comb = [&](int c, T g0, T g1) { return FUSED ? fma(-alpha[c], g1, g0) : fma(beta[c], g1, g0); };
@@ -452,9 +451,11 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
         acc[1][c] = fma(rz, uu, acc[1][c]);
         acc[2][c] = fma(ru, uu, acc[2][c]);
       }
-      if (real && keep) {
-        vstore<T, C>(uout + idx, un);
-        if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
+      if constexpr (KEEP) {
+        if (real) {
+          vstore<T, C>(uout + idx, un);
+          if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
+        }
       }
       // (e) values and own row of the next task
       fetch_rest(tn, base);
@@ -469,6 +470,20 @@ __global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* sl
     part[(Q_UU * R + threadIdx.x) * Gp + lb] = tot[2];
     if constexpr (FUSED) part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[NQ - 1];
   }
+}
+
+// iterations 0..L-2 of a chunk (FUSED: 1..L-2)
+template <typename T, int R, bool FUSED, int H>
+__global__ __launch_bounds__(kB) void kb_iter(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
+                                              int k, int L) {
+  iter_body<T, R, FUSED, H, true>(m, v, slots, part, G, Gp, k, L);
+}
+
+// the chunk's last iteration (k = L - 1): partials only, nothing stored
+template <typename T, int R, int H>
+__global__ __launch_bounds__(kB) void kb_iter_last(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+                                                   int Gp, int k, int L) {
+  iter_body<T, R, true, H, false>(m, v, slots, part, G, Gp, k, L);
 }
 
 // The chunk's x update, at its last iteration, in FP64 in every precision,
@@ -2094,7 +2109,9 @@ struct LaunchH {
   template <typename T>
   static void iter(const BMat& m, BatchWork& w, Grids g, hipStream_t s, int k) {
     if (k == 0) kb_iter<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
-    else kb_iter<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    else if (k < w.chunk - 1)
+      kb_iter<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    else kb_iter_last<T, R, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
   }
   template <typename T>
   static void replace(const BMat& m, BatchWork& w, Grids g, hipStream_t s) {
@@ -2482,7 +2499,7 @@ ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const 
   if (n_iter % w.chunk != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of the tile's chunk");
   const BMat m = bmat(bm);
   // the timing events (if any) go around the SpMV of the call's second
-  // iteration (the recurrence form that runs three times per chunk); the
+  // iteration (the recurrence form that stores z and u, twice per chunk); the
   // chunk holding it is launched directly
   BatchParams rest = prm;
   rest.ev_begin = rest.ev_end = nullptr;
