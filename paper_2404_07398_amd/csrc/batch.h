@@ -94,11 +94,12 @@ struct BatchWork {
   double cx_g = 0.0;
   // Vectors of a chunk. u = diag(S)^-1 S p alternates between two buffers
   // (an iteration gathers the previous one while it writes the new).
-  // zrec (scalar tiles): z_k of iteration k < kChunk - 1 stays in z[k] for
-  // the whole chunk, the carried direction in p[kChunk - 1], and the x
-  // update rebuilds the chunk's directions from them. Otherwise (2 x 2-block and complex
-  // tiles) z alternates between z[0] and z[1] and p cycles through kChunk
-  // buffers, so that the chunk's directions are there at its x update.
+  // zrec (scalar and complex tiles): z_k of iteration k < kChunk - 1 stays
+  // in z[k] for the whole chunk, the carried direction in p[kChunk - 1], and
+  // the x update rebuilds the chunk's directions from them. Otherwise
+  // (2 x 2-block tiles) z alternates between z[0] and z[1] and p cycles
+  // through kChunk buffers, so that the chunk's directions are there at its
+  // x update.
   bool zrec = false;
   float *z32[kChunk] = {}, *u32[2] = {}, *p32[kChunk] = {};
   double *z64[kChunk] = {}, *u64[2] = {}, *p64[kChunk] = {};
@@ -121,7 +122,7 @@ struct SlotScales {
   double c[64];
 };
 
-// Device bytes of a tile's work space (zrec: the scalar tiles' vector set,
+// Device bytes of a tile's work space (zrec: the vector set of scalar and complex tiles,
 // see BatchWork).
 size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk, bool zrec);
 // Lanes that share one row in a tile of R columns (each lane owns 16 bytes of
@@ -130,8 +131,7 @@ int batch_lanes_per_row(int R, bool mixed);
 // Blocks of the batched SpMV kernel that are resident on the device at once.
 int batch_resident_blocks(int R, bool mixed, int device);
 // Allocate a tile of R columns; cx: a complex tile (of the first-order
-// operator). Scalar tiles (neither complex nor of 2 x 2 blocks) take the
-// zrec vector set.
+// operator). Tiles that are not of 2 x 2 blocks take the zrec vector set.
 ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed, bool cx = false);
 void batch_free(BatchWork* w);
 

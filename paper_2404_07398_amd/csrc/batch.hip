@@ -1222,11 +1222,18 @@ __device__ __forceinline__ void row_product_cx(const BMat& m, const T* __restric
   }
 }
 
-// kb_iter for complex tiles (same forms, buffers, pipelining and partials;
-// the partials are the real and imaginary parts of the complex sums).
-template <typename T, int R, bool FUSED, int H>
-__global__ __launch_bounds__(kB) void kbc_iter(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                               int k, int L) {
+// kb_iter for complex tiles (same forms, buffers, pipelining and partials,
+// the z-and-u form of the scalar tiles; the partials are the real and
+// imaginary parts of the complex sums, in the bilinear form x^T y that COCG
+// uses, for which S is symmetric).
+__device__ __forceinline__ void cfma(double ar, double ai, double br, double bi, double& r, double& i) {
+  r = fma(ar, br, fma(-ai, bi, r));
+  i = fma(ar, bi, fma(ai, br, i));
+}
+
+template <typename T, int R, bool FUSED, int H, bool KEEP>
+__device__ __forceinline__ void cx_body(const BMat& m, const BVec<T>& v, const BSlot* slots, double* part, int G,
+                                        int Gp, int k, int L) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   static_assert(C % 2 == 0, "a lane holds whole complex values");
@@ -1248,13 +1255,13 @@ __global__ __launch_bounds__(kB) void kbc_iter(BMat m, BVec<T> v, const BSlot* s
     c64[c] = sl.c;
     any |= on[c];
   }
-  const int bin = FUSED ? ((k - 1) & 1) : 0, bout = FUSED ? (k & 1) : 0;
-  const T* __restrict__ zin = v.z[bin];
-  const T* __restrict__ uin = v.u[bin];
-  T* __restrict__ zout = v.z[bout];
-  T* __restrict__ uout = v.u[bout];
-  const T* __restrict__ pin = v.p[(k + L - 1) % L];
-  T* __restrict__ pout = v.p[k];
+  // buffers as in kb_iter: iteration k reads z[k - 1] (DIRECT: z[0]) and
+  // writes z[k]; u_k in u[k & 1]; DIRECT reads the carried p_-1 in p[L - 1]
+  const T* __restrict__ zin = v.z[FUSED ? k - 1 : 0];
+  T* __restrict__ zout = v.z[k];
+  const T* __restrict__ uin = v.u[(k + 1) & 1];
+  T* __restrict__ uout = v.u[k & 1];
+  const T* __restrict__ pin = v.p[L - 1];
   const T* __restrict__ g1src = FUSED ? uin : pin;
   const T* __restrict__ val = bval<T>(m);
   double acc[NQ][C] = {};
@@ -1265,7 +1272,7 @@ __global__ __launch_bounds__(kB) void kbc_iter(BMat m, BVec<T> v, const BSlot* s
     auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
     int32_t cu[H];
     T vu[H];
-    Pack<T, C> zi, ui, pi;
+    Pack<T, C> zi, gi;  // own row: z and (FUSED) u or (DIRECT) p
     double mi, kd;
     int64_t base, nb, ne;
     int w;
@@ -1280,8 +1287,7 @@ __global__ __launch_bounds__(kB) void kbc_iter(BMat m, BVec<T> v, const BSlot* s
       for (int u = 0; u < H; ++u) vu[u] = val[sb + (int64_t)u * kW + l];
       const int64_t idx = row * R + j0;
       zi = vload<T, C>(zin + idx);
-      pi = vload<T, C>(pin + idx);
-      if constexpr (FUSED) ui = vload<T, C>(uin + idx);
+      gi = vload<T, C>(g1src + idx);
       mi = m.mass[row];
       kd = m.kdiag[row];
     };
@@ -1331,57 +1337,63 @@ __global__ __launch_bounds__(kB) void kbc_iter(BMat m, BVec<T> v, const BSlot* s
         row_product_cx<T, R, C, FUSED, H>(m, val, cbase, cw, row % kW, j0, zin, g1src, alpha, beta, a, H);
       const bool real = row < m.n;
       const int64_t idx = row * R + j0;
-      Pack<T, C> zn, pn, un;
+      Pack<T, C> zn, un;
 #pragma unroll
       for (int q = 0; q < C / 2; ++q) {
         const int e0 = 2 * q, e1 = 2 * q + 1;
         // d = diag(S) = M + sigma diag(K) (complex), padding rows 1
         const T dr = real ? (T)(mi + c64[e0] * kd) : (T)1, di = real ? (T)(c64[e1] * kd) : (T)0;
+        const T gr = gi.v[e0], gim = gi.v[e1];
         T zr, zim;
         if constexpr (FUSED) {
-          zr = fma(-alpha[e0], ui.v[e0], fma(alpha[e1], ui.v[e1], zi.v[e0]));
-          zim = fma(-alpha[e0], ui.v[e1], fma(-alpha[e1], ui.v[e0], zi.v[e1]));
+          zr = fma(-alpha[e0], gr, fma(alpha[e1], gim, zi.v[e0]));
+          zim = fma(-alpha[e0], gim, fma(-alpha[e1], gr, zi.v[e1]));
         } else {
           zr = zi.v[e0];
           zim = zi.v[e1];
         }
-        const T pr = fma(beta[e0], pi.v[e0], fma(-beta[e1], pi.v[e1], zr));
-        const T pim = fma(beta[e0], pi.v[e1], fma(beta[e1], pi.v[e0], zim));
         // d^-1 sigma K_off x (x = z' when FUSED, p' when DIRECT)
         const T sr = cc[e0] * a[e0] - cc[e1] * a[e1], si = cc[e0] * a[e1] + cc[e1] * a[e0];
-        const T den = dr * dr + di * di;
-        const T wr = (sr * dr + si * di) / den, wi = (si * dr - sr * di) / den;
-        T ur, uim;
+        const T rden = over((T)1, dr * dr + di * di);
+        const T wr = (sr * dr + si * di) * rden, wi = (si * dr - sr * di) * rden;
+        T ur, uim, pr = 0, pim = 0;
         if constexpr (FUSED) {
-          ur = fma(beta[e0], ui.v[e0], fma(-beta[e1], ui.v[e1], zr + wr));
-          uim = fma(beta[e0], ui.v[e1], fma(beta[e1], ui.v[e0], zim + wi));
+          ur = fma(beta[e0], gr, fma(-beta[e1], gim, zr + wr));
+          uim = fma(beta[e0], gim, fma(beta[e1], gr, zim + wi));
         } else {
+          pr = fma(beta[e0], gr, fma(-beta[e1], gim, zr));
+          pim = fma(beta[e0], gim, fma(beta[e1], gr, zim));
           ur = pr + wr;
           uim = pim + wi;
         }
         zn.v[e0] = zr;
         zn.v[e1] = zim;
-        pn.v[e0] = pr;
-        pn.v[e1] = pim;
         un.v[e0] = ur;
         un.v[e1] = uim;
-        if (on[e0] && real) {
-          double dur = 0.0, dui = 0.0;  // d u
-          cmul_acc((double)dr, (double)di, (double)ur, (double)uim, dur, dui);
-          cmul_acc((double)pr, (double)pim, dur, dui, acc[0][e0], acc[0][e1]);
-          cmul_acc((double)zr, (double)zim, dur, dui, acc[1][e0], acc[1][e1]);
-          cmul_acc((double)ur, (double)uim, dur, dui, acc[2][e0], acc[2][e1]);
-          if constexpr (FUSED) {
-            double dzr = 0.0, dzi = 0.0;
-            cmul_acc((double)dr, (double)di, (double)zr, (double)zim, dzr, dzi);
-            cmul_acc((double)zr, (double)zim, dzr, dzi, acc[NQ - 1][e0], acc[NQ - 1][e1]);
-          }
+        // the row's weight d (0 where the row or the column pair does not
+        // count); d u and d z are formed in T (they are r-sized) and each
+        // complex product is summed in FP64 with FMAs
+        const bool use = on[e0] && real;
+        const T wr0 = use ? dr : (T)0, wi0 = use ? di : (T)0;
+        const double dur = (double)(wr0 * ur - wi0 * uim), dui = (double)(wr0 * uim + wi0 * ur);
+        const double zr64 = (double)zr, zi64 = (double)zim, ur64 = (double)ur, ui64 = (double)uim;
+        if constexpr (FUSED) {
+          // (q_k-1, z_k) = sum (d u_k-1) z_k
+          const double qr = (double)(wr0 * gr - wi0 * gim), qi = (double)(wr0 * gim + wi0 * gr);
+          cfma(qr, qi, zr64, zi64, acc[0][e0], acc[0][e1]);
+          const double dzr = (double)(wr0 * zr - wi0 * zim), dzi = (double)(wr0 * zim + wi0 * zr);
+          cfma(dzr, dzi, zr64, zi64, acc[NQ - 1][e0], acc[NQ - 1][e1]);
+        } else {
+          cfma(dur, dui, (double)pr, (double)pim, acc[0][e0], acc[0][e1]);
         }
+        cfma(dur, dui, zr64, zi64, acc[1][e0], acc[1][e1]);
+        cfma(dur, dui, ur64, ui64, acc[2][e0], acc[2][e1]);
       }
-      if (real) {
-        vstore<T, C>(pout + idx, pn);
-        vstore<T, C>(uout + idx, un);
-        if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
+      if constexpr (KEEP) {
+        if (real) {
+          vstore<T, C>(uout + idx, un);
+          if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
+        }
       }
       fetch_rest(tn, base);
     }
@@ -1397,42 +1409,85 @@ __global__ __launch_bounds__(kB) void kbc_iter(BMat m, BVec<T> v, const BSlot* s
   }
 }
 
-// x += sum_k alpha_k p_k (complex, FP64) at the chunk's end.
+template <typename T, int R, bool FUSED, int H>
+__global__ __launch_bounds__(kB) void kbc_iter(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
+                                               int k, int L) {
+  cx_body<T, R, FUSED, H, true>(m, v, slots, part, G, Gp, k, L);
+}
+
+// the chunk's last iteration of a complex tile: partials only
+template <typename T, int R, int H>
+__global__ __launch_bounds__(kB) void kbc_iter_last(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+                                                    int Gp, int k, int L) {
+  cx_body<T, R, true, H, false>(m, v, slots, part, G, Gp, k, L);
+}
+
+// The complex tile's x update at the chunk's end, as kb_xupdate's ZREC
+// form in complex FP64: z_L-1 = z_L-2 - alpha_L-2 u_L-2 (as the last
+// iteration formed it), p_k = z_k + beta_k p_k-1 from the carried p_-1, x
+// += sum_k alpha_k p_k, and p_L-1 carried (pairs that did not iterate keep
+// theirs).
 template <typename T, int R, int L>
 __global__ __launch_bounds__(kB) void kbc_xupdate(BMat m, BVec<T> v, const BSlot* slots, int G) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   const int lane = threadIdx.x % kW;
   const int j0 = (lane % LPR) * C, rsub = lane / LPR;
-  double ah[L][C];
+  double ah[L][C], bh[L][C];
+  bool moved[C];
   bool any = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const BSlot& sl = slots[j0 + c];
+    moved[c] = false;
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       ah[i][c] = sl.alpha_hist[i];
-      any |= ah[i][c] != 0.0;
+      bh[i][c] = sl.beta_hist[i];
+      moved[c] |= ah[i][c] != 0.0;
     }
+  }
+#pragma unroll
+  for (int q = 0; q < C / 2; ++q) {
+    moved[2 * q] = moved[2 * q + 1] = moved[2 * q] || moved[2 * q + 1];
+    any |= moved[2 * q];
   }
   if (!any) return;
   for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
     const int64_t row = wk.t * RPW + rsub;
     if (row >= m.n) continue;
     const int64_t idx = row * R + j0;
-    Pack<T, C> pk[L];
+    Pack<T, C> zk[L];
 #pragma unroll
-    for (int i = 0; i < L; ++i) pk[i] = vload<T, C>(v.p[i] + idx);
+    for (int i = 0; i < L - 1; ++i) zk[i] = vload<T, C>(v.z[i] + idx);
+    zk[L - 1] = vload<T, C>(v.u[(L - 2) & 1] + idx);
     Pack<double, C> xv = vload<double, C>(v.x + idx);
+    Pack<T, C> pc = vload<T, C>(v.p[L - 1] + idx);
 #pragma unroll
-    for (int q = 0; q < C / 2; ++q)
+    for (int q = 0; q < C / 2; ++q) {
+      const int e0 = 2 * q, e1 = 2 * q + 1;
+      {
+        const T ar = (T)ah[L - 2][e0], ai = (T)ah[L - 2][e1];
+        const T ur = zk[L - 1].v[e0], ui = zk[L - 1].v[e1];
+        zk[L - 1].v[e0] = fma(-ar, ur, fma(ai, ui, zk[L - 2].v[e0]));
+        zk[L - 1].v[e1] = fma(-ar, ui, fma(-ai, ur, zk[L - 2].v[e1]));
+      }
+      double pr = (double)pc.v[e0], pi = (double)pc.v[e1];
 #pragma unroll
       for (int i = 0; i < L; ++i) {
-        const double ar = ah[i][2 * q], ai = ah[i][2 * q + 1];
-        const double pr = (double)pk[i].v[2 * q], pim = (double)pk[i].v[2 * q + 1];
-        xv.v[2 * q] = fma(ar, pr, fma(-ai, pim, xv.v[2 * q]));
-        xv.v[2 * q + 1] = fma(ar, pim, fma(ai, pr, xv.v[2 * q + 1]));
+        const double br = bh[i][e0], bi = bh[i][e1];
+        const double nr = fma(br, pr, fma(-bi, pi, (double)zk[i].v[e0]));
+        const double ni = fma(br, pi, fma(bi, pr, (double)zk[i].v[e1]));
+        pr = nr;
+        pi = ni;
+        cfma(ah[i][e0], ah[i][e1], pr, pi, xv.v[e0], xv.v[e1]);
       }
+      if (moved[e0]) {
+        pc.v[e0] = (T)pr;
+        pc.v[e1] = (T)pi;
+      }
+    }
+    vstore<T, C>(v.p[L - 1] + idx, pc);
     vstore<double, C>(v.x + idx, xv);
   }
 }
@@ -1946,15 +2001,25 @@ __global__ __launch_bounds__(kFinThreads) void kfc_step(BSlot* slots, const doub
   BSlot& s = slots[j];
   BSlot& t = slots[j + 1];
   if (!live(s)) {
-    if (threadIdx.x == 0) s.alpha_hist[k] = t.alpha_hist[k] = 0.0;
+    if (threadIdx.x == 0) s.alpha_hist[k] = t.alpha_hist[k] = s.beta_hist[k] = t.beta_hist[k] = 0.0;
     return;
   }
-  const double pqr = fin_sum(part + (Q_PQ * R + j) * Gp, G, lds), pqi = fin_sum(part + (Q_PQ * R + j + 1) * Gp, G, lds);
+  const double p0r = fin_sum(part + (Q_PQ * R + j) * Gp, G, lds), p0i = fin_sum(part + (Q_PQ * R + j + 1) * Gp, G, lds);
   const double zur = fin_sum(part + (Q_ZU * R + j) * Gp, G, lds), zui = fin_sum(part + (Q_ZU * R + j + 1) * Gp, G, lds);
   const double uur = fin_sum(part + (Q_UU * R + j) * Gp, G, lds), uui = fin_sum(part + (Q_UU * R + j + 1) * Gp, G, lds);
   const double rzr = k > 0 ? fin_sum(part + (Q_RZ * R + j) * Gp, G, lds) : 0.0;
   const double rzi = k > 0 ? fin_sum(part + (Q_RZ * R + j + 1) * Gp, G, lds) : 0.0;
   if (threadIdx.x == 0) {
+    // (p, q) = (z, q) + beta ((q_prev, z) + beta (p, q)_prev) for k >= 1 (as kf_step)
+    const double b0r = s.beta, b0i = t.beta;
+    double pqr = p0r, pqi = p0i;
+    if (k > 0) {
+      const double hr = p0r + (b0r * s.pq - b0i * t.pq), hi = p0i + (b0r * t.pq + b0i * s.pq);
+      pqr = zur + (b0r * hr - b0i * hi);
+      pqi = zui + (b0r * hi + b0i * hr);
+    }
+    s.beta_hist[k] = b0r;
+    t.beta_hist[k] = b0i;
     const double rr = k > 0 ? rzr : s.rho, ri = k > 0 ? rzi : t.rho;
     double ar, ai;
     cdiv(rr, ri, pqr, pqi, ar, ai);
@@ -1972,6 +2037,8 @@ __global__ __launch_bounds__(kFinThreads) void kfc_step(BSlot* slots, const doub
       cdiv(nr, ni, rr, ri, br, bi);
       s.rho = rr;
       t.rho = ri;
+      s.pq = pqr;
+      t.pq = pqi;
       s.alpha = ar;
       t.alpha = ai;
       s.alpha_hist[k] = ar;
@@ -2187,7 +2254,9 @@ struct Launch {
   static void step_cx(const BMat& m, BatchWork& w, Grids g, hipStream_t s, const BatchParams& prm, int k) {
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
     if (k == 0) kbc_iter<T, R, false, 6><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
-    else kbc_iter<T, R, true, 6><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    else if (k < w.chunk - 1)
+      kbc_iter<T, R, true, 6><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    else kbc_iter_last<T, R, 6><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
     kfc_step<<<R / 2, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
     if (k == w.chunk - 1) {
@@ -2304,7 +2373,7 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed, b
   // the x update (kb_xupdate<T, R, kChunk, .>) reads kChunk z or p buffers
   if (bm.chunk != kChunk) return fail(IFL_EINVAL, "tile chunk length differs from the kernels' kChunk");
   const int chunk = bm.chunk;
-  const bool zrec = !bm.pairs && !cx;
+  const bool zrec = !bm.pairs;
   ifl_status st;
   std::vector<void*> vecs;  // the precision's vectors, zeroed below
   size_t es = 0;
@@ -2495,7 +2564,7 @@ static ifl_status capture_chunk(const BMat& m, const BatchMatrix& bm, BatchWork&
 
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s) {
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
-  if (w.zrec == (bm.pairs || w.cx)) return fail(IFL_EINVAL, "tile vectors were allocated for another matrix form");
+  if (w.zrec == bm.pairs) return fail(IFL_EINVAL, "tile vectors were allocated for another matrix form");
   if (n_iter % w.chunk != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of the tile's chunk");
   const BMat m = bmat(bm);
   // the timing events (if any) go around the SpMV of the call's second
