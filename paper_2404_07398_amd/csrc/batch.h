@@ -92,15 +92,12 @@ struct BatchWork {
   // ||M phi||^2, g >= ||K M^-1||_2 (the handle's bound), so that the residual
   // of S_2 itself, Re r + b K M^-1 Im r, meets rtol
   double cx_g = 0.0;
-  // Vectors of a chunk. u = diag(S)^-1 S p alternates between two buffers
-  // (an iteration gathers the previous one while it writes the new).
-  // zrec (scalar and complex tiles): z_k of iteration k < kChunk - 1 stays
-  // in z[k] for the whole chunk, the carried direction in p[kChunk - 1], and
-  // the x update rebuilds the chunk's directions from them. Otherwise
-  // (2 x 2-block tiles) z alternates between z[0] and z[1] and p cycles
-  // through kChunk buffers, so that the chunk's directions are there at its
-  // x update.
-  bool zrec = false;
+  // Vectors of a chunk: z_k of iteration k < kChunk - 1 stays in z[k] for
+  // the whole chunk (z[0] from the FP64 replacement), u = diag(S)^-1 S p
+  // alternates between two buffers (an iteration gathers the previous one
+  // while it writes the new), and p[kChunk - 1] holds the carried direction;
+  // the x update rebuilds the chunk's directions from them (p[0..kChunk - 1)
+  // stay unallocated).
   float *z32[kChunk] = {}, *u32[2] = {}, *p32[kChunk] = {};
   double *z64[kChunk] = {}, *u64[2] = {}, *p64[kChunk] = {};
   double* x = nullptr;    // FP64 solution, rows x R (updated once per chunk)
@@ -122,16 +119,15 @@ struct SlotScales {
   double c[64];
 };
 
-// Device bytes of a tile's work space (zrec: the vector set of scalar and complex tiles,
-// see BatchWork).
-size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk, bool zrec);
+// Device bytes of a tile's work space (the vectors of BatchWork).
+size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk);
 // Lanes that share one row in a tile of R columns (each lane owns 16 bytes of
 // columns: 4 FP32 or 2 FP64).
 int batch_lanes_per_row(int R, bool mixed);
 // Blocks of the batched SpMV kernel that are resident on the device at once.
 int batch_resident_blocks(int R, bool mixed, int device);
 // Allocate a tile of R columns; cx: a complex tile (of the first-order
-// operator). Tiles that are not of 2 x 2 blocks take the zrec vector set.
+// operator).
 ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed, bool cx = false);
 void batch_free(BatchWork* w);
 

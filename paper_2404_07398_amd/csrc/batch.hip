@@ -103,9 +103,9 @@ struct BMat {
 
 template <typename T>
 struct BVec {
-  T* z[kChunk];  // preconditioned residual diag(S)^-1 r (per iteration of a chunk, or two buffers)
+  T* z[kChunk];  // preconditioned residual diag(S)^-1 r of each iteration of a chunk but the last
   T* u[2];       // diag(S)^-1 S p (two buffers)
-  T* p[kChunk];  // directions of the chunk's iterations (p of iteration k in p[k])
+  T* p[kChunk];  // p[kChunk - 1]: the direction carried from one chunk to the next
   double* x;     // FP64 solution
   double* phi;   // FP64 field per column
 };
@@ -486,13 +486,13 @@ __global__ __launch_bounds__(kB) void kb_iter_last(BMat m, BVec<T> v, const BSlo
   iter_body<T, R, true, H, false>(m, v, slots, part, G, Gp, k, L);
 }
 
-// The chunk's x update, at its last iteration, in FP64 in every precision,
-// x += sum_k alpha_k p_k (alpha_k = 0 for a column that was not iterating).
-// ZREC: the directions are rebuilt from the chunk's z_k (z_L-1 from z_L-2
-// and u_L-2) and the carried p_-1, p_k = z_k + beta_k p_k-1 (in FP64), and
-// p_L-1 is carried to the next chunk in place of p_-1 (columns that did not
-// iterate keep theirs); otherwise they are read from p[0..L).
-template <typename T, int R, int L, bool ZREC>
+// The chunk's x update, at its last iteration, in FP64 in every precision:
+// the directions are rebuilt from the chunk's z_k (z_L-1 from z_L-2 and
+// u_L-2, the FP32 update the last iteration applied) and the carried p_-1,
+// p_k = z_k + beta_k p_k-1 (in FP64), x += sum_k alpha_k p_k (alpha_k = 0
+// for a column that was not iterating), and p_L-1 is carried to the next
+// chunk in place of p_-1 (columns that did not iterate keep theirs).
+template <typename T, int R, int L>
 __global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot* slots, int G) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
@@ -518,33 +518,24 @@ __global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot*
     const int64_t row = wk.t * RPW + rsub;
     if (row >= m.n) continue;
     const int64_t idx = row * R + j0;
-    Pack<T, C> pk[L];
+    Pack<T, C> zk[L];
 #pragma unroll
-    for (int i = 0; i < L - 1; ++i) pk[i] = vload<T, C>((ZREC ? v.z[i] : v.p[i]) + idx);
-    pk[L - 1] = vload<T, C>((ZREC ? v.u[(L - 2) & 1] : v.p[L - 1]) + idx);
+    for (int i = 0; i < L - 1; ++i) zk[i] = vload<T, C>(v.z[i] + idx);
+    zk[L - 1] = vload<T, C>(v.u[(L - 2) & 1] + idx);
     Pack<double, C> xv = vload<double, C>(v.x + idx);
-    if constexpr (ZREC) {
-      // z_L-1 = z_L-2 - alpha_L-2 u_L-2, as the last iteration formed it
+    Pack<T, C> pc = vload<T, C>(v.p[L - 1] + idx);
 #pragma unroll
-      for (int c = 0; c < C; ++c) pk[L - 1].v[c] = fma(-(T)ah[L - 2][c], pk[L - 1].v[c], pk[L - 2].v[c]);
-      Pack<T, C> pc = vload<T, C>(v.p[L - 1] + idx);
+    for (int c = 0; c < C; ++c) {
+      zk[L - 1].v[c] = fma(-(T)ah[L - 2][c], zk[L - 1].v[c], zk[L - 2].v[c]);
+      double pd = (double)pc.v[c];
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        double pd = (double)pc.v[c];
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-          pd = fma(bh[i][c], pd, (double)pk[i].v[c]);
-          xv.v[c] = fma(ah[i][c], pd, xv.v[c]);
-        }
-        if (moved[c]) pc.v[c] = (T)pd;
+      for (int i = 0; i < L; ++i) {
+        pd = fma(bh[i][c], pd, (double)zk[i].v[c]);
+        xv.v[c] = fma(ah[i][c], pd, xv.v[c]);
       }
-      vstore<T, C>(v.p[L - 1] + idx, pc);
-    } else {
-#pragma unroll
-      for (int c = 0; c < C; ++c)
-#pragma unroll
-        for (int i = 0; i < L; ++i) xv.v[c] = fma(ah[i][c], (double)pk[i].v[c], xv.v[c]);
+      if (moved[c]) pc.v[c] = (T)pd;
     }
+    vstore<T, C>(v.p[L - 1] + idx, pc);
     vstore<double, C>(v.x + idx, xv);
   }
 }
@@ -817,9 +808,9 @@ __device__ __forceinline__ void pair_product_abs2(const BMat& m, int64_t base, i
 }
 
 // kb_iter on 2 x 2 blocks (same forms, buffers and partials).
-template <typename T, int R, bool FUSED, int H>
-__global__ __launch_bounds__(kB) void kb_iter2(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
-                                               int k, int L) {
+template <typename T, int R, bool FUSED, int H, bool KEEP>
+__device__ __forceinline__ void pair_body(const BMat& m, const BVec<T>& v, const BSlot* slots, double* part, int G,
+                                          int Gp, int k, int L) {
   using Gm = Geo<T, R>;
   constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
   constexpr int NQ = FUSED ? 4 : 3;
@@ -840,13 +831,12 @@ __global__ __launch_bounds__(kB) void kb_iter2(BMat m, BVec<T> v, const BSlot* s
     c64[c] = sl.c;
     any |= on[c];
   }
-  const int bin = FUSED ? ((k - 1) & 1) : 0, bout = FUSED ? (k & 1) : 0;
-  const T* __restrict__ zin = v.z[bin];
-  const T* __restrict__ uin = v.u[bin];
-  T* __restrict__ zout = v.z[bout];
-  T* __restrict__ uout = v.u[bout];
-  const T* __restrict__ pin = v.p[(k + L - 1) % L];
-  T* __restrict__ pout = v.p[k];
+  // buffers as in kb_iter (z-and-u form)
+  const T* __restrict__ zin = v.z[FUSED ? k - 1 : 0];
+  T* __restrict__ zout = v.z[k];
+  const T* __restrict__ uin = v.u[(k + 1) & 1];
+  T* __restrict__ uout = v.u[k & 1];
+  const T* __restrict__ pin = v.p[L - 1];
   const T* __restrict__ g1src = FUSED ? uin : pin;
   const T* __restrict__ val = pval<T>(m);
   const auto comb = [&](int c, T g0, T g1) { return FUSED ? fma(-alpha[c], g1, g0) : fma(beta[c], g1, g0); };
@@ -859,7 +849,7 @@ __global__ __launch_bounds__(kB) void kb_iter2(BMat m, BVec<T> v, const BSlot* s
     auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
     int32_t cu[H];
     Pack<T, 4> vu[H];
-    Pack<T, C> zi[2], ui[2], pi[2];
+    Pack<T, C> zi[2], gi[2];  // own rows: z and (FUSED) u or (DIRECT) p
     double mi[2], kd[2];
     int64_t base, nb, ne;
     int w;
@@ -876,8 +866,7 @@ __global__ __launch_bounds__(kB) void kb_iter2(BMat m, BVec<T> v, const BSlot* s
       for (int r = 0; r < 2; ++r) {
         const int64_t row = min(2 * brow + r, last_row), idx = row * R + j0;
         zi[r] = vload<T, C>(zin + idx);
-        pi[r] = vload<T, C>(pin + idx);
-        if constexpr (FUSED) ui[r] = vload<T, C>(uin + idx);
+        gi[r] = vload<T, C>(g1src + idx);
         mi[r] = m.mass[row];
         kd[r] = m.kdiag[row];
       }
@@ -939,25 +928,36 @@ __global__ __launch_bounds__(kB) void kb_iter2(BMat m, BVec<T> v, const BSlot* s
         const int64_t row = 2 * brow + r;
         const bool real = row < m.n;
         const int64_t idx = row * R + j0;
-        Pack<T, C> zn, pn, un;
+        Pack<T, C> zn, un;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const T d = real ? (T)(mi[r] + c64[c] * kd[r]) : (T)1;
           const T dw = on[c] && real ? d : (T)0;  // the row's weight in the partials (as kb_iter)
           const T su = over(cc[c] * a[r][c], d);
-          zn.v[c] = FUSED ? fma(-alpha[c], ui[r].v[c], zi[r].v[c]) : zi[r].v[c];
-          pn.v[c] = fma(beta[c], pi[r].v[c], zn.v[c]);
-          un.v[c] = FUSED ? fma(beta[c], ui[r].v[c], zn.v[c] + su) : pn.v[c] + su;
+          T pn = 0;
+          if constexpr (FUSED) {
+            zn.v[c] = fma(-alpha[c], gi[r].v[c], zi[r].v[c]);
+            un.v[c] = fma(beta[c], gi[r].v[c], zn.v[c] + su);
+          } else {
+            zn.v[c] = zi[r].v[c];
+            pn = fma(beta[c], gi[r].v[c], zi[r].v[c]);
+            un.v[c] = pn + su;
+          }
           const double rz = (double)(dw * zn.v[c]), ru = (double)(dw * un.v[c]), uu = (double)un.v[c];
-          acc[0][c] = fma(ru, (double)pn.v[c], acc[0][c]);
+          if constexpr (FUSED) {
+            acc[0][c] = fma(rz, (double)gi[r].v[c], acc[0][c]);
+            acc[NQ - 1][c] = fma(rz, (double)zn.v[c], acc[NQ - 1][c]);
+          } else {
+            acc[0][c] = fma(ru, (double)pn, acc[0][c]);
+          }
           acc[1][c] = fma(rz, uu, acc[1][c]);
           acc[2][c] = fma(ru, uu, acc[2][c]);
-          if constexpr (FUSED) acc[NQ - 1][c] = fma(rz, (double)zn.v[c], acc[NQ - 1][c]);
         }
-        if (real) {
-          vstore<T, C>(pout + idx, pn);
-          vstore<T, C>(uout + idx, un);
-          if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
+        if constexpr (KEEP) {
+          if (real) {
+            vstore<T, C>(uout + idx, un);
+            if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
+          }
         }
       }
       // (e) values and own rows of the next task
@@ -973,6 +973,19 @@ __global__ __launch_bounds__(kB) void kb_iter2(BMat m, BVec<T> v, const BSlot* s
     part[(Q_UU * R + threadIdx.x) * Gp + lb] = tot[2];
     if constexpr (FUSED) part[(Q_RZ * R + threadIdx.x) * Gp + lb] = tot[NQ - 1];
   }
+}
+
+template <typename T, int R, bool FUSED, int H>
+__global__ __launch_bounds__(kB) void kb_iter2(BMat m, BVec<T> v, const BSlot* slots, double* part, int G, int Gp,
+                                               int k, int L) {
+  pair_body<T, R, FUSED, H, true>(m, v, slots, part, G, Gp, k, L);
+}
+
+// the chunk's last iteration on 2 x 2 blocks: partials only
+template <typename T, int R, int H>
+__global__ __launch_bounds__(kB) void kb_iter2_last(BMat m, BVec<T> v, const BSlot* slots, double* part, int G,
+                                                    int Gp, int k, int L) {
+  pair_body<T, R, true, H, false>(m, v, slots, part, G, Gp, k, L);
 }
 
 // kb_residual on 2 x 2 blocks (same START / REPLACE forms and partials).
@@ -1422,7 +1435,7 @@ __global__ __launch_bounds__(kB) void kbc_iter_last(BMat m, BVec<T> v, const BSl
   cx_body<T, R, true, H, false>(m, v, slots, part, G, Gp, k, L);
 }
 
-// The complex tile's x update at the chunk's end, as kb_xupdate's ZREC
+// The complex tile's x update at the chunk's end, as kb_xupdate's
 // form in complex FP64: z_L-1 = z_L-2 - alpha_L-2 u_L-2 (as the last
 // iteration formed it), p_k = z_k + beta_k p_k-1 from the carried p_-1, x
 // += sum_k alpha_k p_k, and p_L-1 carried (pairs that did not iterate keep
@@ -1872,12 +1885,12 @@ __device__ __forceinline__ double fin_sum(const double* a, int G, double* lds) {
 // recurrence rho - 2 alpha (q, z) + alpha^2 (q, d^-1 q), and beta = next rho
 // / rho_k for the next launch. rho_k is the exact (r, z) of the z the launch
 // formed (k >= 1), or that of the replacement or start (k = 0). (p, q) is
-// the launch's partial, or (zrec, k >= 1) (z, q) + beta ((q_prev, z) + beta
-// (p, q)_prev) from the partials of kb_iter's z-recurrence form. No stopping
+// the launch's partial (k = 0), or (z, q) + beta ((q_prev, z) + beta (p,
+// q)_prev) from the partials of the z-and-u form (k >= 1). No stopping
 // test: a column is tested on its replaced FP64 residual only, in
 // kf_replace.
 __global__ __launch_bounds__(kFinThreads) void kf_step(BSlot* slots, const double* part, int G, int Gp, int R,
-                                                        int k, bool zrec) {
+                                                        int k) {
   __shared__ double lds[kFinThreads / kW];
   const int j = blockIdx.x;
   BSlot& s = slots[j];
@@ -1894,7 +1907,7 @@ __global__ __launch_bounds__(kFinThreads) void kf_step(BSlot* slots, const doubl
   const double rz = k > 0 ? fin_sum(part + (Q_RZ * R + j) * Gp, G, lds) : 0.0;
   if (threadIdx.x == 0) {
     const double b = s.beta;
-    const double pq = zrec && k > 0 ? zu + b * (p0 + b * s.pq) : p0;
+    const double pq = k > 0 ? zu + b * (p0 + b * s.pq) : p0;
     const double rho = k > 0 ? rz : s.rho;
     const double a = rho / pq;
     s.iters += 1;
@@ -2197,7 +2210,9 @@ struct LaunchP {
   template <typename T>
   static void iter(const BMat& m, BatchWork& w, Grids g, hipStream_t s, int k) {
     if (k == 0) kb_iter2<T, R, false, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
-    else kb_iter2<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    else if (k < w.chunk - 1)
+      kb_iter2<T, R, true, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
+    else kb_iter2_last<T, R, H><<<g.G, kB, 0, s>>>(m, bvec<T>(w), w.slots, w.part, g.G, g.Gp, k, w.chunk);
   }
   template <typename T>
   static void replace(const BMat& m, BatchWork& w, Grids g, hipStream_t s) {
@@ -2241,10 +2256,9 @@ struct Launch {
     if (prm.ev_begin) (void)hipEventRecord(prm.ev_begin, s);
     by_head<T>(m, head, [&](auto L) { L.template iter<T>(m, w, g, s, k); });
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
-    kf_step<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k, w.zrec);
+    kf_step<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
     if (k == w.chunk - 1) {
-      if (w.zrec) kb_xupdate<T, R, kChunk, true><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
-      else kb_xupdate<T, R, kChunk, false><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
+      kb_xupdate<T, R, kChunk><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
       by_head<T>(m, head, [&](auto L) { L.template replace<T>(m, w, g, s); });
       kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
     }
@@ -2370,20 +2384,16 @@ int batch_lanes_per_row(int R, bool mixed) {
 
 ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed, bool cx) {
   const size_t nr = (size_t)bm.n_pad * R;
-  // the x update (kb_xupdate<T, R, kChunk, .>) reads kChunk z or p buffers
+  // the x update (kb_xupdate<T, R, kChunk>) reads the chunk's z buffers
   if (bm.chunk != kChunk) return fail(IFL_EINVAL, "tile chunk length differs from the kernels' kChunk");
   const int chunk = bm.chunk;
-  const bool zrec = !bm.pairs;
   ifl_status st;
   std::vector<void*> vecs;  // the precision's vectors, zeroed below
   size_t es = 0;
-  // zrec: z[0..chunk - 1), u[0..2), p[chunk - 1]; otherwise z[0..2), u[0..2), p[0..chunk)
+  // z[0..chunk - 1), u[0..2), the carried direction p[chunk - 1]
   auto pick = [&](auto& z, auto& u, auto& dir) {
-    std::vector<std::remove_reference_t<decltype(z[0])>*> all = {&u[0], &u[1], &z[0], &z[1], &dir[chunk - 1]};
-    if (zrec)
-      for (int i = 2; i < chunk - 1; ++i) all.push_back(&z[i]);
-    else
-      for (int i = 0; i < chunk - 1; ++i) all.push_back(&dir[i]);
+    std::vector<std::remove_reference_t<decltype(z[0])>*> all = {&u[0], &u[1], &dir[chunk - 1]};
+    for (int i = 0; i < chunk - 1; ++i) all.push_back(&z[i]);
     return all;
   };
   if (mixed) {
@@ -2399,7 +2409,6 @@ ifl_status batch_alloc(BatchWork* w, const BatchMatrix& bm, int R, bool mixed, b
       vecs.push_back(*p);
     }
   }
-  w->zrec = zrec;
   w->cx = cx;
   if ((st = dalloc_b(&w->x, nr)) || (st = dalloc_b(&w->phi, nr)) ||
       (st = dalloc_b(&w->part, (size_t)Q_COUNT * R * std::max(bm.G, bm.Gu))) || (st = dalloc_b(&w->slots, (size_t)R)) ||
@@ -2446,9 +2455,9 @@ void batch_free(BatchWork* w) {
   *w = BatchWork();
 }
 
-size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk, bool zrec) {
-  // zrec: z (x chunk - 1), u (x2), p; otherwise z, u (x2), p (x chunk); and x, phi
-  const size_t per = (size_t)(zrec ? chunk + 2 : chunk + 4) * (mixed ? 4 : 8) + 8 + 8;
+size_t batch_bytes(int64_t n_pad, int R, bool mixed, int chunk) {
+  // z (x chunk - 1), u (x2), p, and x, phi
+  const size_t per = (size_t)(chunk + 2) * (mixed ? 4 : 8) + 8 + 8;
   return (size_t)n_pad * R * per;
 }
 
@@ -2527,8 +2536,8 @@ double batch_spmv_bytes(const BatchMatrix& bm, int64_t nnz_stored, bool mixed, i
   const double vb = mixed ? 4.0 : 8.0;
   // pair kernels: block entries (index + four values) over slices of block rows
   if (bm.pairs)
-    return (double)bm.pnnz * (4.0 + 4.0 * vb) + 8.0 * (bm.nb_slices + 1) + 16.0 * bm.n + 6.0 * vb * bm.n * live;
-  // scalar tiles (z-recurrence form): z and u read, z and u written per column
+    return (double)bm.pnnz * (4.0 + 4.0 * vb) + 8.0 * (bm.nb_slices + 1) + 16.0 * bm.n + 4.0 * vb * bm.n * live;
+  // z and u read, z and u written per column
   return (double)nnz_stored * (4.0 + vb) + 8.0 * (bm.n_slices + 1) + 16.0 * bm.n + 4.0 * vb * bm.n * live;
 }
 
@@ -2564,7 +2573,6 @@ static ifl_status capture_chunk(const BMat& m, const BatchMatrix& bm, BatchWork&
 
 ifl_status batch_iterate(const BatchMatrix& bm, BatchWork& w, int n_iter, const BatchParams& prm, hipStream_t s) {
   if (!same_grids(bm, w)) return fail(IFL_EINVAL, "tile work space was sized for other grid sizes");
-  if (w.zrec == bm.pairs) return fail(IFL_EINVAL, "tile vectors were allocated for another matrix form");
   if (n_iter % w.chunk != 0) return fail(IFL_EINVAL, "batched iterations come in multiples of the tile's chunk");
   const BMat m = bmat(bm);
   // the timing events (if any) go around the SpMV of the call's second

@@ -433,7 +433,7 @@ ifl_status ifl_server_add(ifl_server* s, ifl_handle* hh, int32_t* mesh_id) {
     std::lock_guard<std::mutex> lk(h->mu);
     if (ifl_status st = device_shift_work(h, &work)) return st;
   } else {
-    work = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED, wk->bm.chunk, !wk->bm.pairs);
+    work = batch_bytes(wk->bm.n_pad, wk->R, h->opt.precision == IFL_MIXED, wk->bm.chunk);
     if (wk->cx) work += sizeof(double) * (size_t)wk->bm.n_pad;  // zero imaginary parts
   }
   const size_t tile = work + sizeof(double) * (size_t)(n_out + 1) * wk->L;  // + output and field staging
