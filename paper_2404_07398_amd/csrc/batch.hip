@@ -35,6 +35,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "batch.h"
@@ -266,6 +267,36 @@ constexpr int kHeadClasses[] = {6, 12, 20};
 __device__ __forceinline__ float over(float a, float d) { return a * __builtin_amdgcn_rcpf(d); }
 __device__ __forceinline__ double over(double a, double d) { return a / d; }
 
+// Lanes of a row share the row's matrix entries: each of the LPR lanes of a
+// row (consecutive lanes, LPR dividing 32) loads every LPR-th entry, and
+// ds_swizzle (bit mode, within 32 lanes) hands lane SRC's copy to the others
+// of its row. The swizzle runs on the LDS crossbar, not the vector memory
+// path, which the gathers keep busy.
+template <int LPR, int SRC>
+__device__ __forceinline__ int row_share(int x) {
+  constexpr int kPattern = (0x1F & ~(LPR - 1)) | (SRC << 5);
+  return __builtin_amdgcn_ds_swizzle(x, kPattern);
+}
+template <int LPR, int SRC>
+__device__ __forceinline__ float row_share(float x) {
+  return __int_as_float(row_share<LPR, SRC>(__float_as_int(x)));
+}
+template <int LPR, int SRC>
+__device__ __forceinline__ double row_share(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = row_share<LPR, SRC>((int)(b & 0xffffffffll)), hi = row_share<LPR, SRC>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <typename F, int... I>
+__device__ __forceinline__ void unroll_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// f(std::integral_constant<int, i>) for i = 0..N-1 (i usable as a template argument)
+template <int N, typename F>
+__device__ __forceinline__ void unroll(F&& f) {
+  unroll_seq(f, std::make_integer_sequence<int, N>{});
+}
+
 __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
@@ -345,7 +376,11 @@ __device__ __forceinline__ void iter_body(const BMat& m, const BVec<T>& v, const
   // value of a gathered neighbour: z_k (FUSED) or p_0 (DIRECT); g1 is u or p
   const auto comb = [&](int c, T g0, T g1) { return FUSED ? fma(-alpha[c], g1, g0) : fma(beta[c], g1, g0); };
   double acc[NQ][C] = {};
-  if (any) {
+  // the whole wave walks the tasks if any of its lanes has a live column
+  // (the lanes of a row share the row's entries); lanes whose columns have
+  // all stopped rewrite those columns' vectors, which nothing reads, and add
+  // nothing to the partials
+  if (__any(any)) {
     const Walk wk = task_walk(m.n_slices * LPR, G);
     const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
     const int64_t last_slice = m.n_slices - 1;
@@ -354,8 +389,12 @@ __device__ __forceinline__ void iter_body(const BMat& m, const BVec<T>& v, const
     // of memory operations per iteration keeps the compiler's wait counts
     // exact), and their results are discarded
     auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
-    int32_t cu[H];
-    T vu[H];
+    // entries of the head: lane lc of a row loads entries lc, lc + LPR, ...
+    // (the last entry again past H), shared across the row by row_share
+    constexpr int NL = (H + LPR - 1) / LPR;
+    const int lc = lane % LPR;
+    int32_t cu[H], cl[NL];
+    T vu[H], vl[NL];
     Pack<T, C> zi, gi;  // own row: z and (FUSED) u or (DIRECT) p
     double mi, kd;
     int64_t base, nb, ne;  // this task's slice base; next task's raw slice bounds
@@ -363,14 +402,28 @@ __device__ __forceinline__ void iter_body(const BMat& m, const BVec<T>& v, const
     auto fetch_idx = [&](int64_t t, int64_t sb) {
       const int64_t l = (t * RPW + rsub) % kW;
 #pragma unroll
-      for (int u = 0; u < H; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
+      for (int i = 0; i < NL; ++i) cl[i] = m.col[sb + (int64_t)min(lc + i * LPR, H - 1) * kW + l];
+    };
+    auto share_idx = [&]() {
+      unroll<H>([&](auto U) {
+        constexpr int u = decltype(U)::value;
+        if constexpr (LPR == 1) cu[u] = cl[u];
+        else cu[u] = row_share<LPR, u % LPR>(cl[u / LPR]);
+      });
+    };
+    auto share_val = [&]() {
+      unroll<H>([&](auto U) {
+        constexpr int u = decltype(U)::value;
+        if constexpr (LPR == 1) vu[u] = vl[u];
+        else vu[u] = row_share<LPR, u % LPR>(vl[u / LPR]);
+      });
     };
     // values are loaded raw (entries past the width are masked where they
     // are used, so that no instruction consumes the loads early)
     auto fetch_rest = [&](int64_t t, int64_t sb) {
       const int64_t row = min(t * RPW + rsub, m.n_slices * kW - 1), l = row % kW;
 #pragma unroll
-      for (int u = 0; u < H; ++u) vu[u] = val[sb + (int64_t)u * kW + l];
+      for (int i = 0; i < NL; ++i) vl[i] = val[sb + (int64_t)min(lc + i * LPR, H - 1) * kW + l];
       const int64_t idx = row * R + j0;
       zi = vload<T, C>(zin + idx);
       gi = vload<T, C>((FUSED ? uin : pin) + idx);
@@ -383,6 +436,7 @@ __device__ __forceinline__ void iter_body(const BMat& m, const BVec<T>& v, const
       w = (int)((wave_uniform(m.sptr[s0 + 1]) - base) / kW);
       fetch_idx(first, base);
       fetch_rest(first, base);
+      share_idx();
       const int64_t s1 = slice_of(first + stride);
       nb = m.sptr[s1];
       ne = m.sptr[s1 + 1];
@@ -412,6 +466,7 @@ __device__ __forceinline__ void iter_body(const BMat& m, const BVec<T>& v, const
       ne = ne2;
       // (d) this task's row (rows past the last dof are padding: zero mass,
       // diagonal and entries; their results are discarded)
+      share_val();
       T a[C] = {};
 #pragma unroll
       for (int u = 0; u < H; ++u) {
@@ -457,8 +512,9 @@ __device__ __forceinline__ void iter_body(const BMat& m, const BVec<T>& v, const
           if constexpr (FUSED) vstore<T, C>(zout + idx, zn);
         }
       }
-      // (e) values and own row of the next task
+      // (e) values and own row of the next task; its indices to every lane
       fetch_rest(tn, base);
+      share_idx();
     }
   }
   double tot[NQ];
