@@ -638,13 +638,23 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
   T* __restrict__ pprev = v.p[L - 1];  // the chunk's first iteration reads it as p
   const Ident ident;
   double acc[3][C] = {};
-  if (any) {
+  // REPLACE: the whole wave walks the tasks if any of its lanes has a live
+  // column, and the lanes of a row share the row's entries (as kb_iter);
+  // START: only lanes with an entering column, each loading its entries
+  constexpr bool SHARE = !START && LPR > 1;
+  bool run;
+  if constexpr (START) run = any;
+  else run = __any(any);
+  if (run) {
     const Walk wk = task_walk(m.n_slices * LPR, G);
     const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
     const int64_t last_slice = m.n_slices - 1;
     auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
-    int32_t cu[H];
-    double vu[H];
+    constexpr int LS = SHARE ? LPR : 1;  // lanes that split a row's entries
+    constexpr int NL = (H + LS - 1) / LS;
+    const int lc = SHARE ? lane % LPR : 0;
+    int32_t cu[H], cl[NL];
+    double vu[H], vl[NL];
     Pack<double, C> ph, xv;
     double mi, kd;
     int64_t base, nb, ne;
@@ -652,12 +662,26 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
     auto fetch_idx = [&](int64_t t, int64_t sb) {
       const int64_t l = (t * RPW + rsub) % kW;
 #pragma unroll
-      for (int u = 0; u < H; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
+      for (int i = 0; i < NL; ++i) cl[i] = m.col[sb + (int64_t)min(lc + i * LS, H - 1) * kW + l];
+    };
+    auto share_idx = [&]() {
+      unroll<H>([&](auto U) {
+        constexpr int u = decltype(U)::value;
+        if constexpr (LS == 1) cu[u] = cl[u];
+        else cu[u] = row_share<LS, u % LS>(cl[u / LS]);
+      });
+    };
+    auto share_val = [&]() {
+      unroll<H>([&](auto U) {
+        constexpr int u = decltype(U)::value;
+        if constexpr (LS == 1) vu[u] = vl[u];
+        else vu[u] = row_share<LS, u % LS>(vl[u / LS]);
+      });
     };
     auto fetch_rest = [&](int64_t t, int64_t sb) {
       const int64_t row = min(t * RPW + rsub, m.n_slices * kW - 1), l = row % kW;
 #pragma unroll
-      for (int u = 0; u < H; ++u) vu[u] = m.val64[sb + (int64_t)u * kW + l];
+      for (int i = 0; i < NL; ++i) vl[i] = m.val64[sb + (int64_t)min(lc + i * LS, H - 1) * kW + l];
       const int64_t idx = row * R + j0;
       ph = vload<double, C>(v.phi + idx);
       if constexpr (!START) xv = vload<double, C>(v.x + idx);
@@ -670,6 +694,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
       w = (int)((wave_uniform(m.sptr[s0 + 1]) - base) / kW);
       fetch_idx(first, base);
       fetch_rest(first, base);
+      share_idx();
       const int64_t s1 = slice_of(first + stride);
       nb = m.sptr[s1];
       ne = m.sptr[s1 + 1];
@@ -690,6 +715,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
       fetch_idx(tn, base);
       nb = nb2;
       ne = ne2;
+      share_val();
       double a[C] = {}, aa[C] = {};  // sum val x, sum |val| |x| (REPLACE)
 #pragma unroll
       for (int u = 0; u < H; ++u) {
@@ -755,6 +781,7 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
         if (real) vstore<T, C>(v.z[0] + idx, zv);
       }
       fetch_rest(tn, base);
+      share_idx();
     }
   }
   double tot[3];
