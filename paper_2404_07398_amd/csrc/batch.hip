@@ -638,13 +638,15 @@ __global__ __launch_bounds__(kB) void kb_residual(BMat m, BVec<T> v, const BSlot
   T* __restrict__ pprev = v.p[L - 1];  // the chunk's first iteration reads it as p
   const Ident ident;
   double acc[3][C] = {};
-  // REPLACE: the whole wave walks the tasks if any of its lanes has a live
-  // column, and the lanes of a row share the row's entries (as kb_iter);
-  // START: only lanes with an entering column, each loading its entries
-  constexpr bool SHARE = !START && LPR > 1;
+  // REPLACE with the first-order head: the whole wave walks the tasks if any
+  // of its lanes has a live column, and the lanes of a row share the row's
+  // entries (as kb_iter; with the wider heads the shared copies push the
+  // FP64 pass past the register file); START: only lanes with an entering
+  // column, each loading its entries
+  constexpr bool SHARE = !START && LPR > 1 && H <= 6;
   bool run;
-  if constexpr (START) run = any;
-  else run = __any(any);
+  if constexpr (SHARE) run = __any(any);
+  else run = any;
   if (run) {
     const Walk wk = task_walk(m.n_slices * LPR, G);
     const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
@@ -1361,13 +1363,15 @@ __device__ __forceinline__ void cx_body(const BMat& m, const BVec<T>& v, const B
   const T* __restrict__ g1src = FUSED ? uin : pin;
   const T* __restrict__ val = bval<T>(m);
   double acc[NQ][C] = {};
-  if (any) {
+  if (__any(any)) {  // as kb_iter: the whole wave, the row's lanes share its entries
     const Walk wk = task_walk(m.n_slices * LPR, G);
     const int64_t first = wave_uniform(wk.t), end = wk.end, stride = wk.stride;
     const int64_t last_slice = m.n_slices - 1;
     auto slice_of = [&](int64_t t) { return min((t * RPW) / kW, last_slice); };
-    int32_t cu[H];
-    T vu[H];
+    constexpr int NL = (H + LPR - 1) / LPR;
+    const int lc = lane % LPR;
+    int32_t cu[H], cl[NL];
+    T vu[H], vl[NL];
     Pack<T, C> zi, gi;  // own row: z and (FUSED) u or (DIRECT) p
     double mi, kd;
     int64_t base, nb, ne;
@@ -1375,12 +1379,26 @@ __device__ __forceinline__ void cx_body(const BMat& m, const BVec<T>& v, const B
     auto fetch_idx = [&](int64_t t, int64_t sb) {
       const int64_t l = (t * RPW + rsub) % kW;
 #pragma unroll
-      for (int u = 0; u < H; ++u) cu[u] = m.col[sb + (int64_t)u * kW + l];
+      for (int i = 0; i < NL; ++i) cl[i] = m.col[sb + (int64_t)min(lc + i * LPR, H - 1) * kW + l];
+    };
+    auto share_idx = [&]() {
+      unroll<H>([&](auto U) {
+        constexpr int u = decltype(U)::value;
+        if constexpr (LPR == 1) cu[u] = cl[u];
+        else cu[u] = row_share<LPR, u % LPR>(cl[u / LPR]);
+      });
+    };
+    auto share_val = [&]() {
+      unroll<H>([&](auto U) {
+        constexpr int u = decltype(U)::value;
+        if constexpr (LPR == 1) vu[u] = vl[u];
+        else vu[u] = row_share<LPR, u % LPR>(vl[u / LPR]);
+      });
     };
     auto fetch_rest = [&](int64_t t, int64_t sb) {
       const int64_t row = min(t * RPW + rsub, m.n_slices * kW - 1), l = row % kW;
 #pragma unroll
-      for (int u = 0; u < H; ++u) vu[u] = val[sb + (int64_t)u * kW + l];
+      for (int i = 0; i < NL; ++i) vl[i] = val[sb + (int64_t)min(lc + i * LPR, H - 1) * kW + l];
       const int64_t idx = row * R + j0;
       zi = vload<T, C>(zin + idx);
       gi = vload<T, C>(g1src + idx);
@@ -1393,6 +1411,7 @@ __device__ __forceinline__ void cx_body(const BMat& m, const BVec<T>& v, const B
       w = (int)((wave_uniform(m.sptr[s0 + 1]) - base) / kW);
       fetch_idx(first, base);
       fetch_rest(first, base);
+      share_idx();
       const int64_t s1 = slice_of(first + stride);
       nb = m.sptr[s1];
       ne = m.sptr[s1 + 1];
@@ -1417,6 +1436,7 @@ __device__ __forceinline__ void cx_body(const BMat& m, const BVec<T>& v, const B
       fetch_idx(tn, base);
       nb = nb2;
       ne = ne2;
+      share_val();
       T a[C] = {};
 #pragma unroll
       for (int u = 0; u < H; ++u) {
@@ -1492,6 +1512,7 @@ __device__ __forceinline__ void cx_body(const BMat& m, const BVec<T>& v, const B
         }
       }
       fetch_rest(tn, base);
+      share_idx();
     }
   }
   double tot[NQ];
