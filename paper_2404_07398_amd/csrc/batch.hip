@@ -548,52 +548,60 @@ __global__ __launch_bounds__(kB) void kb_iter_last(BMat m, BVec<T> v, const BSlo
 // p_k = z_k + beta_k p_k-1 (in FP64), x += sum_k alpha_k p_k (alpha_k = 0
 // for a column that was not iterating), and p_L-1 is carried to the next
 // chunk in place of p_-1 (columns that did not iterate keep theirs).
+// A one-pass launch: one thread per row and lane (a streaming pass runs
+// faster with a thread per element than walking the rows with the resident
+// workgroups), the columns' alpha and beta histories staged in LDS once per
+// block of kXB threads.
+constexpr int kXB = 1024;
 template <typename T, int R, int L>
-__global__ __launch_bounds__(kB) void kb_xupdate(BMat m, BVec<T> v, const BSlot* slots, int G) {
+__global__ __launch_bounds__(kXB) void kb_xupdate(BMat m, BVec<T> v, const BSlot* slots) {
   using Gm = Geo<T, R>;
-  constexpr int C = Gm::C, LPR = Gm::LPR, RPW = Gm::RPW;
-  const int lane = threadIdx.x % kW;
-  const int j0 = (lane % LPR) * C, rsub = lane / LPR;
+  constexpr int C = Gm::C, LPR = Gm::LPR;
+  __shared__ double hist[2 * L * R];  // alpha_hist[k] of column j at k R + j, beta_hist after them
+  for (int i = threadIdx.x; i < 2 * L * R; i += kXB) {
+    const int j = i % R, k = (i / R) % L;
+    hist[i] = i < L * R ? slots[j].alpha_hist[k] : slots[j].beta_hist[k];
+  }
+  __syncthreads();
+  const int64_t g = (int64_t)blockIdx.x * kXB + threadIdx.x;
+  const int64_t row = g / LPR;
+  if (row >= m.n) return;
+  const int j0 = (int)(g % LPR) * C;
   double ah[L][C], bh[L][C];
   bool moved[C];
   bool any = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const BSlot& sl = slots[j0 + c];
     moved[c] = false;
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      ah[i][c] = sl.alpha_hist[i];
-      bh[i][c] = sl.beta_hist[i];
+      ah[i][c] = hist[i * R + j0 + c];
+      bh[i][c] = hist[(L + i) * R + j0 + c];
       moved[c] |= ah[i][c] != 0.0;
     }
     any |= moved[c];
   }
   if (!any) return;
-  for (Walk wk = task_walk(m.n_slices * LPR, G); wk.t < wk.end; wk.t += wk.stride) {
-    const int64_t row = wk.t * RPW + rsub;
-    if (row >= m.n) continue;
-    const int64_t idx = row * R + j0;
-    Pack<T, C> zk[L];
+  const int64_t idx = row * R + j0;
+  Pack<T, C> zk[L];
 #pragma unroll
-    for (int i = 0; i < L - 1; ++i) zk[i] = vload<T, C>(v.z[i] + idx);
-    zk[L - 1] = vload<T, C>(v.u[(L - 2) & 1] + idx);
-    Pack<double, C> xv = vload<double, C>(v.x + idx);
-    Pack<T, C> pc = vload<T, C>(v.p[L - 1] + idx);
+  for (int i = 0; i < L - 1; ++i) zk[i] = vload<T, C>(v.z[i] + idx);
+  zk[L - 1] = vload<T, C>(v.u[(L - 2) & 1] + idx);
+  Pack<double, C> xv = vload<double, C>(v.x + idx);
+  Pack<T, C> pc = vload<T, C>(v.p[L - 1] + idx);
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      zk[L - 1].v[c] = fma(-(T)ah[L - 2][c], zk[L - 1].v[c], zk[L - 2].v[c]);
-      double pd = (double)pc.v[c];
+  for (int c = 0; c < C; ++c) {
+    zk[L - 1].v[c] = fma(-(T)ah[L - 2][c], zk[L - 1].v[c], zk[L - 2].v[c]);
+    double pd = (double)pc.v[c];
 #pragma unroll
-      for (int i = 0; i < L; ++i) {
-        pd = fma(bh[i][c], pd, (double)zk[i].v[c]);
-        xv.v[c] = fma(ah[i][c], pd, xv.v[c]);
-      }
-      if (moved[c]) pc.v[c] = (T)pd;
+    for (int i = 0; i < L; ++i) {
+      pd = fma(bh[i][c], pd, (double)zk[i].v[c]);
+      xv.v[c] = fma(ah[i][c], pd, xv.v[c]);
     }
-    vstore<T, C>(v.p[L - 1] + idx, pc);
-    vstore<double, C>(v.x + idx, xv);
+    if (moved[c]) pc.v[c] = (T)pd;
   }
+  vstore<T, C>(v.p[L - 1] + idx, pc);
+  vstore<double, C>(v.x + idx, xv);
 }
 
 // FP64 residual passes, software-pipelined like kb_iter (the gathered
@@ -2362,7 +2370,9 @@ struct Launch {
     if (prm.ev_end) (void)hipEventRecord(prm.ev_end, s);
     kf_step<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, k);
     if (k == w.chunk - 1) {
-      kb_xupdate<T, R, kChunk><<<g.Gu, kB, 0, s>>>(m, bvec<T>(w), w.slots, g.Gu);
+      const int64_t xthreads = m.n * Geo<T, R>::LPR;
+      if (xthreads > 0)
+        kb_xupdate<T, R, kChunk><<<(unsigned)((xthreads + kXB - 1) / kXB), kXB, 0, s>>>(m, bvec<T>(w), w.slots);
       by_head<T>(m, head, [&](auto L) { L.template replace<T>(m, w, g, s); });
       kf_replace<<<R, kFinThreads, 0, s>>>(w.slots, w.part, g.G, g.Gp, R, prm.max_iter);
     }
