@@ -390,7 +390,8 @@ ifl_status ifl_stream_probe(int32_t device, int64_t bytes, int32_t reps, double*
 typedef struct ifl_tune {
   int32_t batch;                   /* fastest tile size (columns per tile) */
   int32_t blocks_gather;           /* its blocks of the SpMV / replacement / start / finish kernels */
-  int32_t blocks_update;           /* its blocks of the streaming update kernel */
+  int32_t blocks_update;           /* its blocks of the complex tiles' x update (the real tiles'
+                                      x update is a one-pass launch, one thread per row and lane) */
   int32_t candidates;              /* configurations timed */
   double us_per_column_iteration;  /* measured cost of the fastest configuration */
 } ifl_tune;

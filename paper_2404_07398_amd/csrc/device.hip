@@ -2493,8 +2493,10 @@ ifl_status device_autotune(Handle* h, ifl_tune* out) {
   for (int R : {16, 32, 64}) {
     Best b;
     std::vector<std::pair<int, int>> seen;
+    // the update grid only sizes the complex tiles' x update (the real
+    // tiles' x update is a one-pass launch): one value
     for (int gm : {1, 2, 4})
-      for (int gu : {2, 4}) {
+      for (int gu : {2}) {
         const int G = fit_grid(d, R, mixed, cus * gm / 2), Gu = fit_grid(d, R, mixed, cus * gu / 2);
         if (std::find(seen.begin(), seen.end(), std::make_pair(G, Gu)) != seen.end()) continue;
         seen.emplace_back(G, Gu);
