@@ -51,7 +51,7 @@ struct BatchMatrix {
   const int32_t* row_of = nullptr;  // caller index -> row (-1: no dof), field_len entries
   int64_t field_len = 0;
   int G = 1;   // blocks of the kernels that gather (SpMV, replacement, start, finish)
-  int Gu = 1;  // blocks of the streaming update kernel
+  int Gu = 1;  // blocks of the complex tiles' x update (the real tiles' x update is one-pass)
   int head = 6;  // off-diagonal entries per row in the gathering kernels' pipelined head (6, 12 or 20;
                  // with pairs: blocks per block row, 3, 6 or 12)
   // two-component operators: the gathering kernels run on 2 x 2 blocks

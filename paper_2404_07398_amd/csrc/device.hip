@@ -1915,8 +1915,9 @@ BatchMatrix batch_matrix(DeviceState* d, int R, bool mixed) {
   // a task is one wavefront's rows: 64 / lanes-per-row consecutive rows.
   // Defaults: the gathering kernels run one block per CU, so that the rows
   // in flight on an XCD form a band narrow enough for its L2 to keep the
-  // gathered neighbours; the streaming update runs all resident blocks. The
-  // autotuner may have picked others for this tile size.
+  // gathered neighbours; the complex tiles' x update runs all resident
+  // blocks (the real tiles' x update is a one-pass launch). The autotuner
+  // may have picked others for this tile size.
   int G = device_cus(d->device), Gu = batch_resident_blocks(R, mixed, d->device);
   for (const auto& t : d->tuned)
     if (t.R == R && t.mixed == mixed) {
